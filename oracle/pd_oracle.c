@@ -1,0 +1,913 @@
+/*
+ * pd_oracle.c -- plain FP64 CPU oracle of the r-z PIC-DSMC step
+ * (arXiv 2109.00214, Sections 2.1-2.3).  TEST INFRASTRUCTURE ONLY: it is
+ * loaded by the tests, the smoke check and the benchmark's CPU-baseline leg,
+ * never by the product path.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fPIC -shared (no fast-math).  Every
+ * floating-point value is one binary64 expression evaluated left to right
+ * as parenthesised; round-to-nearest-even; no fused multiply-add.
+ *
+ * Step order (the paper only says the PIC and DSMC parts are coupled):
+ *   sort -> collide (decide, claim, apply, create) -> deposit -> Poisson ->
+ *   field -> gather+push -> compact + inject -> step counter.
+ *
+ * Parity pins for every function are in tests/test_oracle_*.py.  Two
+ * pieces are pinned only by conservation identities ("parity unpinned"
+ * beyond them): the scattering law of the e-e stage of the double
+ * ionization (Eq. 14 says only "similar to Coulomb scattering") and the
+ * energy sharing of the single-ionization events (the paper calls their
+ * schemes mature and gives none).
+ */
+#include "pd_oracle.h"
+
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* CODATA 2018 */
+#define Q_E 1.602176634e-19
+#define EPS0 8.8541878128e-12
+#define PI_D 3.14159265358979323846
+
+static char g_err[256];
+static int fail(const char* msg) {
+  snprintf(g_err, sizeof g_err, "%s", msg);
+  return -1;
+}
+const char* or_last_error(void) { return g_err; }
+
+struct or_sim {
+  int nr, nz;
+  int64_t ncell; /* nr*nz */
+  double R, L, V, dt, W;
+  uint64_t seed;
+  int enable_di, deposit_off, collisions_off;
+
+  int Z[OR_NSPECIES];
+  double m[OR_NSPECIES];
+  int species_set;
+
+  int xs_set[OR_NCHANNELS];
+  int xs_n[OR_NCHANNELS];
+  double xs_thr[OR_NCHANNELS], xs_dsq[OR_NCHANNELS];
+  double* xs_tab[OR_NCHANNELS];
+
+  /* host tables */
+  double dr, dz, qunit;
+  double qmdt[OR_NSPECIES];
+  double *Vnode, *Vcell;  /* [nr+1], [nr] (radial factor times dz) */
+  double *ra, *rb, *rc;   /* radial FV coefficients [nr+1] */
+  double *S;              /* sine table [(nz+1)*(nz+1)], S[k*(nz+1)+j] */
+  double *mu;             /* z eigenvalues [nz+1] */
+  double mr[OR_NCHANNELS], f1[OR_NCHANNELS], f2[OR_NCHANNELS], ck[OR_NCHANNELS];
+  double two_dE_mr[OR_NCHANNELS];
+  double edges[65];
+
+  /* particles */
+  int64_t n, cap;
+  double *r, *z, *vr, *vt, *vz;
+  uint8_t* sp;
+  uint32_t *id, *key;
+  uint8_t* alive;
+  int64_t n_sorted; /* particles present at the sort (before creation) */
+
+  /* collide stage record (sorted positions) */
+  uint8_t* choice;
+  uint32_t* target;
+  uint8_t* win;
+  uint32_t* claim;
+  int64_t coll_cap;
+
+  /* grids: node-major, r fastest, (nz+1) rows of (nr+1) */
+  int64_t* Q;
+  double *phi, *Er, *Ez;
+  int64_t* off; /* CSR offsets [6*ncell+1] */
+
+  /* injection schedule */
+  int sched_n, sched_pos;
+  int64_t* sched_off;
+  double *s_r, *s_z, *s_vr, *s_vt, *s_vz;
+  uint8_t* s_sp;
+
+  int64_t step, next_id;
+  int64_t events[OR_NCHANNELS], conflicts, created;
+  int64_t absorbed[3][OR_NSPECIES], injected[OR_NSPECIES];
+  int64_t charge_absorbed, charge_injected;
+};
+
+/* ------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+ * 32x32->64 multiplications with a Weyl-sequence key schedule.          */
+void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+    uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+    uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    uint32_t n1 = (uint32_t)p1;
+    uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    uint32_t n3 = (uint32_t)p0;
+    c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* counter = (particle id, 0, step, purpose<<24 | draw); key = seed */
+static void draw4(const or_sim* s, uint32_t id, uint32_t purpose, uint32_t d,
+                  uint32_t w[4]) {
+  uint32_t ctr[4] = {id, 0u, (uint32_t)s->step, (purpose << 24) | d};
+  uint32_t key[2] = {(uint32_t)s->seed, (uint32_t)(s->seed >> 32)};
+  or_philox4x32_10(ctr, key, w);
+}
+
+/* uniform double in [0,1) from two words: top 53 bits of (hi:lo) */
+static double u53(uint32_t hi, uint32_t lo) {
+  uint64_t b = (((uint64_t)hi << 32) | (uint64_t)lo) >> 11;
+  return (double)b * 0x1p-53;
+}
+
+/* ------------------------------------------------------------------ */
+static void* xalloc(size_t n) {
+  void* p = calloc(n ? n : 1, 1);
+  if (!p) { fprintf(stderr, "oracle: out of memory\n"); abort(); }
+  return p;
+}
+
+or_sim* or_create(int nr, int nz, double R, double L, double V, double dt,
+                  double weight, uint64_t seed, int enable_di,
+                  int deposit_off, int collisions_off) {
+  if (nr < 2 || nz < 2 || !(R > 0) || !(L > 0) || !(dt > 0) || !(weight > 0) ||
+      !isfinite(V)) {
+    fail("or_create: invalid domain");
+    return NULL;
+  }
+  or_sim* s = (or_sim*)xalloc(sizeof(or_sim));
+  s->nr = nr; s->nz = nz; s->ncell = (int64_t)nr * nz;
+  s->R = R; s->L = L; s->V = V; s->dt = dt; s->W = weight; s->seed = seed;
+  s->enable_di = enable_di; s->deposit_off = deposit_off;
+  s->collisions_off = collisions_off;
+  s->dr = R / (double)nr;
+  s->dz = L / (double)nz;
+  s->qunit = (Q_E * weight) * 0x1p-40;
+  const double dr = s->dr, dz = s->dz;
+
+  /* node volumes (linear weighting in r, Verboncoeur) and cell volumes */
+  s->Vnode = (double*)xalloc(sizeof(double) * (nr + 1));
+  s->Vcell = (double*)xalloc(sizeof(double) * nr);
+  s->Vnode[0] = ((PI_D * (dr * dr)) * dz) / 3.0;
+  for (int i = 1; i < nr; ++i) s->Vnode[i] = (((2.0 * PI_D) * ((double)i * dr)) * dr) * dz;
+  s->Vnode[nr] = (PI_D * dz) * ((R * dr) - ((dr * dr) / 3.0));
+  for (int i = 0; i < nr; ++i) {
+    double ri = (double)i * dr, ri1 = (double)(i + 1) * dr;
+    s->Vcell[i] = (PI_D * ((ri1 * ri1) - (ri * ri))) * dz;
+  }
+
+  /* finite-volume radial operator: control interval [r_{i-1/2}, r_{i+1/2}]
+   * clipped to [0, R]; zero flux through r = 0 and r = R.               */
+  s->ra = (double*)xalloc(sizeof(double) * (nr + 1));
+  s->rb = (double*)xalloc(sizeof(double) * (nr + 1));
+  s->rc = (double*)xalloc(sizeof(double) * (nr + 1));
+  for (int i = 0; i <= nr; ++i) {
+    double A;
+    if (i == 0) A = (dr * dr) / 8.0;
+    else if (i == nr) A = ((R * dr) / 2.0) - ((dr * dr) / 8.0);
+    else A = ((double)i * dr) * dr;
+    double rm = (i == 0) ? 0.0 : ((double)i - 0.5) * dr;
+    double rp = (i == nr) ? 0.0 : ((double)i + 0.5) * dr;
+    s->ra[i] = rm / (dr * A);
+    s->rc[i] = rp / (dr * A);
+    s->rb[i] = -(s->ra[i] + s->rc[i]);
+  }
+
+  /* DST-I table over the z nodes and the eigenvalues of the 3-point d2/dz2 */
+  s->S = (double*)xalloc(sizeof(double) * (size_t)(nz + 1) * (nz + 1));
+  for (int k = 0; k <= nz; ++k)
+    for (int j = 0; j <= nz; ++j) {
+      int64_t m = ((int64_t)k * j) % (2 * (int64_t)nz);
+      int neg = 0;
+      if (m >= nz) { m -= nz; neg = 1; }
+      if (2 * m > nz) m = nz - m;
+      double v = (m == 0) ? 0.0 : sin((PI_D * (double)m) / (double)nz);
+      s->S[(size_t)k * (nz + 1) + j] = neg ? -v : v;
+    }
+  s->mu = (double*)xalloc(sizeof(double) * (nz + 1));
+  for (int k = 0; k <= nz; ++k) {
+    double h = sin((PI_D * (double)k) / (2.0 * (double)nz));
+    s->mu[k] = -(4.0 * (h * h)) / (dz * dz);
+  }
+
+  for (int b = 0; b <= 64; ++b) s->edges[b] = pow(10.0, (3.0 * (double)b) / 64.0);
+
+  int64_t nn = (int64_t)(nr + 1) * (nz + 1);
+  s->Q = (int64_t*)xalloc(sizeof(int64_t) * nn);
+  s->phi = (double*)xalloc(sizeof(double) * nn);
+  s->Er = (double*)xalloc(sizeof(double) * nn);
+  s->Ez = (double*)xalloc(sizeof(double) * nn);
+  s->off = (int64_t*)xalloc(sizeof(int64_t) * (6 * s->ncell + 1));
+  /* vacuum potential before the first solve */
+  for (int j = 0; j <= nz; ++j)
+    for (int i = 0; i <= nr; ++i)
+      s->phi[(int64_t)j * (nr + 1) + i] = (-V) + (V * ((double)j / (double)nz));
+  /* default charge numbers */
+  const int Zd[OR_NSPECIES] = {-1, 0, 1, 2, 2, 2};
+  for (int k = 0; k < OR_NSPECIES; ++k) s->Z[k] = Zd[k];
+  return s;
+}
+
+void or_destroy(or_sim* s) {
+  if (!s) return;
+  for (int k = 0; k < OR_NCHANNELS; ++k) free(s->xs_tab[k]);
+  free(s->Vnode); free(s->Vcell); free(s->ra); free(s->rb); free(s->rc);
+  free(s->S); free(s->mu);
+  free(s->r); free(s->z); free(s->vr); free(s->vt); free(s->vz);
+  free(s->sp); free(s->id); free(s->key); free(s->alive);
+  free(s->choice); free(s->target); free(s->win); free(s->claim);
+  free(s->Q); free(s->phi); free(s->Er); free(s->Ez); free(s->off);
+  free(s->sched_off); free(s->s_r); free(s->s_z); free(s->s_vr); free(s->s_vt);
+  free(s->s_vz); free(s->s_sp);
+  free(s);
+}
+
+static void derive_pairs(or_sim* s) {
+  /* projectile = electron, target = Cu (EL, SI, DI) or Cu+ (SI2) */
+  const int tgt[OR_NCHANNELS] = {OR_CU, OR_CU, OR_CU, OR_CU1};
+  for (int k = 0; k < OR_NCHANNELS; ++k) {
+    double m1 = s->m[OR_E], m2 = s->m[tgt[k]];
+    s->mr[k] = (m1 * m2) / (m1 + m2);
+    s->f1[k] = s->mr[k] / m1;
+    s->f2[k] = s->mr[k] / m2;
+    s->ck[k] = sqrt(s->mr[k] / (2.0 * Q_E));
+    s->two_dE_mr[k] = (k == OR_EL) ? 0.0 : (2.0 * (-(s->xs_thr[k] * Q_E))) / s->mr[k];
+  }
+}
+
+int or_set_species(or_sim* s, int n, const int* Z, const double* mass) {
+  if (n != OR_NSPECIES) return fail("or_set_species: need 6 species");
+  for (int k = 0; k < n; ++k)
+    if (!(mass[k] > 0) || !isfinite(mass[k])) return fail("or_set_species: bad mass");
+  for (int k = 0; k < n; ++k) { s->Z[k] = Z[k]; s->m[k] = mass[k]; }
+  for (int k = 0; k < n; ++k) s->qmdt[k] = (((double)s->Z[k] * Q_E) / s->m[k]) * s->dt;
+  s->species_set = 1;
+  derive_pairs(s);
+  return 0;
+}
+
+int or_set_cross_section(or_sim* s, int ch, double thr, int n, double dsq,
+                         const double* sigma) {
+  if (ch < 0 || ch >= OR_NCHANNELS) return fail("or_set_cross_section: channel");
+  if (n < 2 || !(dsq > 0) || !(thr >= 0)) return fail("or_set_cross_section: table");
+  int ex;
+  double mant = frexp(dsq, &ex);
+  if (mant != 0.5) return fail("or_set_cross_section: dsqrtE must be a power of 2");
+  for (int i = 0; i < n; ++i)
+    if (!(sigma[i] >= 0) || !isfinite(sigma[i])) return fail("or_set_cross_section: sigma");
+  free(s->xs_tab[ch]);
+  s->xs_tab[ch] = (double*)xalloc(sizeof(double) * n);
+  memcpy(s->xs_tab[ch], sigma, sizeof(double) * n);
+  s->xs_n[ch] = n; s->xs_thr[ch] = thr; s->xs_dsq[ch] = dsq; s->xs_set[ch] = 1;
+  if (s->species_set) derive_pairs(s);
+  return 0;
+}
+
+/* ------------------------------------------------------------------ */
+static void reserve(or_sim* s, int64_t need) {
+  if (need <= s->cap) return;
+  int64_t c = s->cap ? s->cap : 1024;
+  while (c < need) c *= 2;
+  s->r = (double*)realloc(s->r, sizeof(double) * c);
+  s->z = (double*)realloc(s->z, sizeof(double) * c);
+  s->vr = (double*)realloc(s->vr, sizeof(double) * c);
+  s->vt = (double*)realloc(s->vt, sizeof(double) * c);
+  s->vz = (double*)realloc(s->vz, sizeof(double) * c);
+  s->sp = (uint8_t*)realloc(s->sp, c);
+  s->id = (uint32_t*)realloc(s->id, sizeof(uint32_t) * c);
+  s->key = (uint32_t*)realloc(s->key, sizeof(uint32_t) * c);
+  s->alive = (uint8_t*)realloc(s->alive, c);
+  if (!s->r || !s->z || !s->vr || !s->vt || !s->vz || !s->sp || !s->id ||
+      !s->key || !s->alive) { fprintf(stderr, "oracle: out of memory\n"); abort(); }
+  s->cap = c;
+}
+
+/* cell of a position: i = min((int)(r/dr), nr-1), j likewise in z */
+static void cell_of(const or_sim* s, double r, double z, int* ci, int* cj,
+                    double* fr, double* fz) {
+  double xr = r / s->dr, xz = z / s->dz;
+  int i = (int)xr, j = (int)xz;
+  if (i > s->nr - 1) i = s->nr - 1;
+  if (j > s->nz - 1) j = s->nz - 1;
+  *ci = i; *cj = j;
+  *fr = xr - (double)i;
+  *fz = xz - (double)j;
+}
+
+/* sort key: species-major, then cell = j*nr + i */
+static uint32_t key_of(const or_sim* s, double r, double z, int sp) {
+  int i, j; double fr, fz;
+  cell_of(s, r, z, &i, &j, &fr, &fz);
+  return (uint32_t)((int64_t)sp * s->ncell + (int64_t)j * s->nr + i);
+}
+
+static int check_particles(const or_sim* s, int64_t n, const double* r,
+                           const double* z, const double* vr, const double* vt,
+                           const double* vz, const uint8_t* sp) {
+  for (int64_t p = 0; p < n; ++p) {
+    if (!isfinite(r[p]) || !isfinite(z[p]) || !isfinite(vr[p]) ||
+        !isfinite(vt[p]) || !isfinite(vz[p]))
+      return fail("inject: non-finite value");
+    if (!(r[p] >= 0.0) || !(r[p] < s->R) || !(z[p] >= 0.0) || !(z[p] < s->L))
+      return fail("inject: position outside the domain");
+    if (sp[p] >= OR_NSPECIES) return fail("inject: species out of range");
+  }
+  return 0;
+}
+
+static void append(or_sim* s, int64_t n, const double* r, const double* z,
+                   const double* vr, const double* vt, const double* vz,
+                   const uint8_t* sp) {
+  reserve(s, s->n + n);
+  for (int64_t p = 0; p < n; ++p) {
+    int64_t q = s->n + p;
+    s->r[q] = r[p]; s->z[q] = z[p]; s->vr[q] = vr[p]; s->vt[q] = vt[p];
+    s->vz[q] = vz[p]; s->sp[q] = sp[p];
+    s->id[q] = (uint32_t)(s->next_id + p);
+    s->key[q] = key_of(s, r[p], z[p], sp[p]);
+    s->alive[q] = 1;
+    s->injected[sp[p]] += 1;
+    s->charge_injected += s->Z[sp[p]];
+  }
+  s->n += n;
+  s->next_id += n;
+}
+
+int or_inject(or_sim* s, int64_t n, const double* r, const double* z,
+              const double* vr, const double* vt, const double* vz,
+              const uint8_t* sp) {
+  if (n < 0) return fail("inject: n < 0");
+  if (s->next_id + n > (int64_t)UINT32_MAX) return fail("inject: id overflow");
+  if (check_particles(s, n, r, z, vr, vt, vz, sp)) return -1;
+  append(s, n, r, z, vr, vt, vz, sp);
+  return 0;
+}
+
+int or_schedule_injection(or_sim* s, int nsteps, const int64_t* offs,
+                          const double* r, const double* z, const double* vr,
+                          const double* vt, const double* vz, const uint8_t* sp) {
+  if (nsteps < 0 || offs[0] != 0) return fail("schedule: bad offsets");
+  for (int k = 0; k < nsteps; ++k)
+    if (offs[k + 1] < offs[k]) return fail("schedule: offsets decrease");
+  int64_t tot = offs[nsteps];
+  if (check_particles(s, tot, r, z, vr, vt, vz, sp)) return -1;
+  free(s->sched_off); free(s->s_r); free(s->s_z); free(s->s_vr); free(s->s_vt);
+  free(s->s_vz); free(s->s_sp);
+  s->sched_off = (int64_t*)xalloc(sizeof(int64_t) * (nsteps + 1));
+  memcpy(s->sched_off, offs, sizeof(int64_t) * (nsteps + 1));
+  s->s_r = (double*)xalloc(sizeof(double) * tot);
+  s->s_z = (double*)xalloc(sizeof(double) * tot);
+  s->s_vr = (double*)xalloc(sizeof(double) * tot);
+  s->s_vt = (double*)xalloc(sizeof(double) * tot);
+  s->s_vz = (double*)xalloc(sizeof(double) * tot);
+  s->s_sp = (uint8_t*)xalloc(tot);
+  memcpy(s->s_r, r, sizeof(double) * tot); memcpy(s->s_z, z, sizeof(double) * tot);
+  memcpy(s->s_vr, vr, sizeof(double) * tot); memcpy(s->s_vt, vt, sizeof(double) * tot);
+  memcpy(s->s_vz, vz, sizeof(double) * tot); memcpy(s->s_sp, sp, tot);
+  s->sched_n = nsteps; s->sched_pos = 0;
+  return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* 1. sort: stable by key (ties keep the input order)                   */
+static int cmp_u64(const void* a, const void* b) {
+  uint64_t x = *(const uint64_t*)a, y = *(const uint64_t*)b;
+  return (x > y) - (x < y);
+}
+
+void or_stage_sort(or_sim* s) {
+  int64_t n = s->n;
+  uint64_t* kv = (uint64_t*)xalloc(sizeof(uint64_t) * (n ? n : 1));
+  for (int64_t p = 0; p < n; ++p) {
+    s->key[p] = key_of(s, s->r[p], s->z[p], s->sp[p]);
+    kv[p] = ((uint64_t)s->key[p] << 32) | (uint64_t)p; /* index breaks ties */
+  }
+  qsort(kv, (size_t)n, sizeof(uint64_t), cmp_u64);
+  double* tmp = (double*)xalloc(sizeof(double) * (n ? n : 1));
+  double* arrs[5] = {s->r, s->z, s->vr, s->vt, s->vz};
+  for (int a = 0; a < 5; ++a) {
+    for (int64_t p = 0; p < n; ++p) tmp[p] = arrs[a][kv[p] & 0xffffffffu];
+    memcpy(arrs[a], tmp, sizeof(double) * n);
+  }
+  uint32_t* t32 = (uint32_t*)tmp;
+  for (int64_t p = 0; p < n; ++p) t32[p] = s->id[kv[p] & 0xffffffffu];
+  memcpy(s->id, t32, sizeof(uint32_t) * n);
+  for (int64_t p = 0; p < n; ++p) t32[p] = (uint32_t)(kv[p] >> 32);
+  memcpy(s->key, t32, sizeof(uint32_t) * n);
+  uint8_t* t8 = (uint8_t*)tmp;
+  for (int64_t p = 0; p < n; ++p) t8[p] = s->sp[kv[p] & 0xffffffffu];
+  memcpy(s->sp, t8, n);
+  free(tmp);
+  free(kv);
+  /* CSR offsets over the flattened (species, cell) key space */
+  int64_t nk = 6 * s->ncell;
+  memset(s->off, 0, sizeof(int64_t) * (nk + 1));
+  for (int64_t p = 0; p < n; ++p) s->off[s->key[p] + 1] += 1;
+  for (int64_t k = 0; k < nk; ++k) s->off[k + 1] += s->off[k];
+  s->n_sorted = n;
+}
+
+/* ------------------------------------------------------------------ */
+/* 2-5. DSMC collisions (Eqs. 4-7 and the four stages of Eqs. 12-15)   */
+
+/* integrated cross section at relative speed g: tables are uniform in
+ * sqrt(energy in eV), linear interpolation, zero below threshold,
+ * clamped at the last entry                                            */
+static double sigma_of(const or_sim* s, int k, double g) {
+  double sq = g * s->ck[k];
+  double eps = sq * sq;
+  if (eps < s->xs_thr[k]) return 0.0;
+  int n = s->xs_n[k];
+  const double* t = s->xs_tab[k];
+  double x = sq / s->xs_dsq[k];
+  if (x >= (double)(n - 1)) return t[n - 1];
+  int i = (int)x;
+  return t[i] + ((x - (double)i) * (t[i + 1] - t[i]));
+}
+
+double or_cross_section(const or_sim* s, int channel, double g) {
+  return sigma_of(s, channel, g);
+}
+
+/* isotropic unit vector by Marsaglia's (1972) rejection method; each
+ * purpose has its own draw counter; the cap is never reached in practice */
+void or_isotropic(const or_sim* s, uint32_t id, uint32_t purpose, double n[3]) {
+  for (uint32_t d = 0; d < 64; ++d) {
+    uint32_t w[4];
+    draw4(s, id, purpose, d, w);
+    double u1 = (2.0 * u53(w[0], w[1])) - 1.0;
+    double u2 = (2.0 * u53(w[2], w[3])) - 1.0;
+    double q = (u1 * u1) + (u2 * u2);
+    if (q < 1.0 && q > 0.0) {
+      double t = sqrt(1.0 - q);
+      n[0] = (2.0 * u1) * t;
+      n[1] = (2.0 * u2) * t;
+      n[2] = 1.0 - (2.0 * q);
+      return;
+    }
+  }
+  n[0] = 0.0; n[1] = 0.0; n[2] = 1.0;
+}
+
+/* binary collision, Eqs. 5-6: u = v1 - v2, |u'|^2 = |u|^2 + 2 dE / m_r
+ * (clamped at 0), u' = |u'| n, v1 += (u'-u) m_r/m1, v2 -= (u'-u) m_r/m2  */
+static void binary(double v1[3], double v2[3], double two_dE_mr, double f1,
+                   double f2, const double n[3]) {
+  double u[3] = {v1[0] - v2[0], v1[1] - v2[1], v1[2] - v2[2]};
+  double g2 = ((u[0] * u[0]) + (u[1] * u[1])) + (u[2] * u[2]);
+  double gp2 = g2 + two_dE_mr;
+  if (gp2 < 0.0) gp2 = 0.0;
+  double gp = sqrt(gp2);
+  for (int c = 0; c < 3; ++c) {
+    double du = (gp * n[c]) - u[c];
+    v1[c] = v1[c] + (du * f1);
+    v2[c] = v2[c] - (du * f2);
+  }
+}
+
+static void coll_reserve(or_sim* s, int64_t n) {
+  if (n <= s->coll_cap) return;
+  free(s->choice); free(s->target); free(s->win); free(s->claim);
+  s->choice = (uint8_t*)xalloc(n);
+  s->target = (uint32_t*)xalloc(sizeof(uint32_t) * n);
+  s->win = (uint8_t*)xalloc(n);
+  s->claim = (uint32_t*)xalloc(sizeof(uint32_t) * n);
+  s->coll_cap = n;
+}
+
+void or_stage_collide(or_sim* s) {
+  int64_t n = s->n;
+  coll_reserve(s, n ? n : 1);
+  memset(s->choice, 0, n);
+  memset(s->win, 0, n);
+  if (s->collisions_off) return;
+  const int64_t C = s->ncell;
+  const int64_t n_e = s->off[C]; /* electrons occupy [0, off[C]) */
+
+  /* decide: reads the pre-collision state only (Eq. 4) */
+  for (int64_t p = 0; p < n_e; ++p) {
+    int64_t cell = s->key[p]; /* species 0 */
+    int ci = (int)(cell % s->nr);
+    int64_t b_cu = s->off[1 * C + cell], n_cu = s->off[1 * C + cell + 1] - b_cu;
+    int64_t b_c1 = s->off[2 * C + cell], n_c1 = s->off[2 * C + cell + 1] - b_c1;
+    uint32_t w[4], t[4];
+    draw4(s, s->id[p], 0, 0, w);
+    draw4(s, s->id[p], 1, 0, t);
+    double R1 = u53(w[0], w[1]);
+    double R2 = u53(w[2], w[3]);
+    int64_t tc = b_cu + (int64_t)(((uint64_t)t[0] * (uint64_t)n_cu) >> 32);
+    int64_t t1 = b_c1 + (int64_t)(((uint64_t)t[1] * (uint64_t)n_c1) >> 32);
+    double x[OR_NCHANNELS] = {0.0, 0.0, 0.0, 0.0};
+    for (int k = 0; k < OR_NCHANNELS; ++k) {
+      int64_t nt = (k == OR_SI2) ? n_c1 : n_cu;
+      int64_t tp = (k == OR_SI2) ? t1 : tc;
+      if (nt == 0) continue;
+      if (k == OR_DI && !s->enable_di) continue;
+      double dvr = s->vr[p] - s->vr[tp];
+      double dvt = s->vt[p] - s->vt[tp];
+      double dvz = s->vz[p] - s->vz[tp];
+      double g = sqrt(((dvr * dvr) + (dvt * dvt)) + (dvz * dvz));
+      double sig = sigma_of(s, k, g);
+      double dens = ((double)nt * s->W) / s->Vcell[ci];
+      x[k] = ((s->dt * g) * dens) * sig;
+    }
+    double X = ((x[0] + x[1]) + x[2]) + x[3];
+    double pc = 1.0 - exp(-X);
+    if (!(R1 < pc)) continue;
+    double u = R2 * X, c = 0.0;
+    int ch = -1;
+    for (int k = 0; k < OR_NCHANNELS; ++k) {
+      c = c + x[k];
+      if (u < c) { ch = k; break; }
+    }
+    if (ch < 0)
+      for (int k = OR_NCHANNELS - 1; k >= 0; --k)
+        if (x[k] > 0.0) { ch = k; break; }
+    s->choice[p] = (uint8_t)(ch + 1);
+    s->target[p] = (uint32_t)((ch == OR_SI2) ? t1 : tc);
+  }
+
+  /* claim: a target takes part in at most one event; the electron with
+   * the lowest sorted position wins                                    */
+  for (int64_t p = 0; p < n; ++p) s->claim[p] = UINT32_MAX;
+  for (int64_t p = 0; p < n_e; ++p)
+    if (s->choice[p] && s->claim[s->target[p]] == UINT32_MAX)
+      s->claim[s->target[p]] = (uint32_t)p;
+  for (int64_t p = 0; p < n_e; ++p)
+    if (s->choice[p]) {
+      if (s->claim[s->target[p]] == (uint32_t)p) s->win[p] = 1;
+      else s->conflicts += 1;
+    }
+
+  /* apply + create, winners in sorted order; new electrons appended with
+   * ids next_id++ (the stage-2 electron first, then the stage-4 one)   */
+  int64_t n_new = 0;
+  for (int64_t p = 0; p < n_e; ++p)
+    if (s->win[p]) n_new += (s->choice[p] == OR_EL + 1) ? 0 : (s->choice[p] == OR_DI + 1 ? 2 : 1);
+  reserve(s, n + n_new);
+  for (int64_t p = 0; p < n_e; ++p) {
+    if (!s->win[p]) continue;
+    int ch = s->choice[p] - 1;
+    uint32_t tp = s->target[p];
+    double e1[3] = {s->vr[p], s->vt[p], s->vz[p]};
+    double A[3] = {s->vr[tp], s->vt[tp], s->vz[tp]};
+    double nh[3];
+    s->events[ch] += 1;
+    /* stage 1: elastic (dE = 0) or inelastic with the channel threshold */
+    or_isotropic(s, s->id[p], 2, nh);
+    binary(e1, A, s->two_dE_mr[ch], s->f1[ch], s->f2[ch], nh);
+    s->vr[tp] = A[0]; s->vt[tp] = A[1]; s->vz[tp] = A[2];
+    if (ch == OR_EL) {
+      s->vr[p] = e1[0]; s->vt[p] = e1[1]; s->vz[p] = e1[2];
+      continue;
+    }
+    /* stage 2: the excited target emits e2, which inherits its position
+     * and post-stage-1 velocity; the target keeps its slot and id        */
+    s->sp[tp] = (uint8_t)(ch == OR_SI ? OR_CU1 : (ch == OR_DI ? OR_CU2_DOUBLE : OR_CU2_STEP));
+    double e2[3] = {A[0], A[1], A[2]};
+    /* stage 3: e1-e2 elastic, equal masses (m_r/m = 1/2), isotropic    */
+    or_isotropic(s, s->id[p], 3, nh);
+    binary(e1, e2, 0.0, 0.5, 0.5, nh);
+    int64_t q = s->n;
+    s->r[q] = s->r[tp]; s->z[q] = s->z[tp];
+    s->vr[q] = e2[0]; s->vt[q] = e2[1]; s->vz[q] = e2[2];
+    s->sp[q] = OR_E; s->id[q] = (uint32_t)s->next_id; s->alive[q] = 1;
+    s->key[q] = key_of(s, s->r[q], s->z[q], OR_E);
+    s->n += 1; s->next_id += 1; s->created += 1;
+    if (ch == OR_DI) {
+      /* stage 4: e3 splits into two orthogonal edges of the rectangle
+       * whose diagonal is v3: v5 = (v3.n)n stays, v6 = v3 - v5 is new  */
+      or_isotropic(s, s->id[p], 4, nh);
+      double d = ((e1[0] * nh[0]) + (e1[1] * nh[1])) + (e1[2] * nh[2]);
+      double v5[3] = {d * nh[0], d * nh[1], d * nh[2]};
+      double v6[3] = {e1[0] - v5[0], e1[1] - v5[1], e1[2] - v5[2]};
+      e1[0] = v5[0]; e1[1] = v5[1]; e1[2] = v5[2];
+      q = s->n;
+      s->r[q] = s->r[p]; s->z[q] = s->z[p];
+      s->vr[q] = v6[0]; s->vt[q] = v6[1]; s->vz[q] = v6[2];
+      s->sp[q] = OR_E; s->id[q] = (uint32_t)s->next_id; s->alive[q] = 1;
+      s->key[q] = key_of(s, s->r[q], s->z[q], OR_E);
+      s->n += 1; s->next_id += 1; s->created += 1;
+    }
+    s->vr[p] = e1[0]; s->vt[p] = e1[1]; s->vz[p] = e1[2];
+  }
+}
+
+/* ------------------------------------------------------------------ */
+/* 6. deposit, Eqs. 9-10: bilinear (cloud-in-cell) weights rounded to
+ *    2^-20 per dimension; complementary weights make each particle
+ *    contribute exactly Z * 2^40                                         */
+void or_stage_deposit(or_sim* s) {
+  const int nr = s->nr;
+  int64_t nn = (int64_t)(nr + 1) * (s->nz + 1);
+  memset(s->Q, 0, sizeof(int64_t) * nn);
+  if (s->deposit_off) return;
+  for (int64_t p = 0; p < s->n; ++p) {
+    int i, j; double fr, fz;
+    cell_of(s, s->r[p], s->z[p], &i, &j, &fr, &fz);
+    int64_t ar = (int64_t)floor((fr * 1048576.0) + 0.5), br = 1048576 - ar;
+    int64_t az = (int64_t)floor((fz * 1048576.0) + 0.5), bz = 1048576 - az;
+    int64_t Zp = s->Z[s->sp[p]];
+    int64_t b = (int64_t)j * (nr + 1) + i;
+    s->Q[b] += Zp * (br * bz);
+    s->Q[b + 1] += Zp * (ar * bz);
+    s->Q[b + nr + 1] += Zp * (br * az);
+    s->Q[b + nr + 2] += Zp * (ar * az);
+  }
+}
+
+void or_set_charge(or_sim* s, const int64_t* Q) {
+  memcpy(s->Q, Q, sizeof(int64_t) * (size_t)(s->nr + 1) * (s->nz + 1));
+}
+
+/* ------------------------------------------------------------------ */
+/* 7. Poisson, Eq. 8 read as lap(phi) = -rho/eps0 in r-z, finite volume:
+ *    Dirichlet at z = 0, L; zero flux at r = 0 and r = R.
+ *    phi = phi_vac + phi_p; phi_p by a sine transform in z (DST-I over
+ *    the interior z nodes), a tridiagonal (Thomas) solve per mode in r,
+ *    and the inverse transform.                                         */
+int or_poisson_solve(const or_sim* s, const double* f, double* phi_p) {
+  const int nr = s->nr, nz = s->nz, W = nr + 1;
+  double* fh = (double*)xalloc(sizeof(double) * (size_t)(nz + 1) * W);
+  double* g = (double*)xalloc(sizeof(double) * (size_t)(nz + 1) * W);
+  double* cp = (double*)xalloc(sizeof(double) * W);
+  double* dp = (double*)xalloc(sizeof(double) * W);
+  for (int k = 1; k < nz; ++k)
+    for (int i = 0; i <= nr; ++i) {
+      double acc = 0.0;
+      for (int j = 1; j < nz; ++j)
+        acc = acc + (f[(size_t)j * W + i] * s->S[(size_t)k * (nz + 1) + j]);
+      fh[(size_t)k * W + i] = acc;
+    }
+  for (int k = 1; k < nz; ++k) {
+    const double* rhs = fh + (size_t)k * W;
+    double inv = 1.0 / (s->rb[0] + s->mu[k]);
+    cp[0] = s->rc[0] * inv;
+    dp[0] = rhs[0] * inv;
+    for (int i = 1; i <= nr; ++i) {
+      double den = (s->rb[i] + s->mu[k]) - (s->ra[i] * cp[i - 1]);
+      inv = 1.0 / den;
+      cp[i] = s->rc[i] * inv;
+      dp[i] = (rhs[i] - (s->ra[i] * dp[i - 1])) * inv;
+    }
+    double* x = g + (size_t)k * W;
+    x[nr] = dp[nr];
+    for (int i = nr - 1; i >= 0; --i) x[i] = dp[i] - (cp[i] * x[i + 1]);
+  }
+  const double scale = 2.0 / (double)nz;
+  for (int j = 0; j <= nz; ++j)
+    for (int i = 0; i <= nr; ++i) {
+      if (j == 0 || j == nz) { phi_p[(size_t)j * W + i] = 0.0; continue; }
+      double acc = 0.0;
+      for (int k = 1; k < nz; ++k)
+        acc = acc + (g[(size_t)k * W + i] * s->S[(size_t)k * (nz + 1) + j]);
+      phi_p[(size_t)j * W + i] = acc * scale;
+    }
+  free(fh); free(g); free(cp); free(dp);
+  return 0;
+}
+
+void or_stage_poisson(or_sim* s) {
+  const int nr = s->nr, nz = s->nz, W = nr + 1;
+  size_t nn = (size_t)(nz + 1) * W;
+  double* f = (double*)xalloc(sizeof(double) * nn);
+  double* pp = (double*)xalloc(sizeof(double) * nn);
+  for (int j = 1; j < nz; ++j)
+    for (int i = 0; i <= nr; ++i) {
+      double rho = ((double)s->Q[(size_t)j * W + i] * s->qunit) / s->Vnode[i];
+      f[(size_t)j * W + i] = -(rho / EPS0);
+    }
+  or_poisson_solve(s, f, pp);
+  for (int j = 0; j <= nz; ++j) {
+    double vac = (-s->V) + (s->V * ((double)j / (double)nz));
+    for (int i = 0; i <= nr; ++i) s->phi[(size_t)j * W + i] = vac + pp[(size_t)j * W + i];
+  }
+  free(f); free(pp);
+}
+
+/* 8. E = -grad(phi): central differences; second-order one-sided at the
+ *    electrodes; E_r = 0 on the axis and at r = R (zero-flux wall)      */
+void or_stage_field(or_sim* s) {
+  const int nr = s->nr, nz = s->nz, W = nr + 1;
+  const double tdz = 2.0 * s->dz, tdr = 2.0 * s->dr;
+  const double* P = s->phi;
+  for (int j = 0; j <= nz; ++j)
+    for (int i = 0; i <= nr; ++i) {
+      size_t b = (size_t)j * W + i;
+      double ez;
+      if (j == 0) ez = (((3.0 * P[b]) - (4.0 * P[b + W])) + P[b + 2 * W]) / tdz;
+      else if (j == nz) ez = (((4.0 * P[b - W]) - (3.0 * P[b])) - P[b - 2 * W]) / tdz;
+      else ez = (P[b - W] - P[b + W]) / tdz;
+      double er = (i == 0 || i == nr) ? 0.0 : (P[b - 1] - P[b + 1]) / tdr;
+      s->Ez[b] = ez;
+      s->Er[b] = er;
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* 9. gather (the deposit's bilinear weights, unrounded) and leapfrog push
+ *    in 2D3V: v += (q/m) E dt; straight move in the particle's local
+ *    Cartesian frame; rotate back to the r-z plane                        */
+void or_stage_push(or_sim* s) {
+  const int nr = s->nr, W = nr + 1;
+  const double dt = s->dt;
+  for (int64_t p = 0; p < s->n; ++p) {
+    int i, j; double fr, fz;
+    cell_of(s, s->r[p], s->z[p], &i, &j, &fr, &fz);
+    size_t b = (size_t)j * W + i;
+    double gr = 1.0 - fr, gz = 1.0 - fz;
+    double w00 = gr * gz, w10 = fr * gz, w01 = gr * fz, w11 = fr * fz;
+    double Er = (((w00 * s->Er[b]) + (w10 * s->Er[b + 1])) + (w01 * s->Er[b + W])) + (w11 * s->Er[b + W + 1]);
+    double Ez = (((w00 * s->Ez[b]) + (w10 * s->Ez[b + 1])) + (w01 * s->Ez[b + W])) + (w11 * s->Ez[b + W + 1]);
+    double qm = s->qmdt[s->sp[p]];
+    double vr = s->vr[p] + (qm * Er);
+    double vz = s->vz[p] + (qm * Ez);
+    double vt = s->vt[p];
+    double x = s->r[p] + (vr * dt);
+    double y = vt * dt;
+    double z = s->z[p] + (vz * dt);
+    double rn = sqrt((x * x) + (y * y));
+    if (rn > 0.0) {
+      double c = x / rn, sn = y / rn;
+      double vr2 = (c * vr) + (sn * vt);
+      double vt2 = (c * vt) - (sn * vr);
+      vr = vr2; vt = vt2;
+    }
+    s->r[p] = rn; s->z[p] = z;
+    s->vr[p] = vr; s->vt[p] = vt; s->vz[p] = vz;
+    int bnd = -1;
+    if (z < 0.0) bnd = OR_CATHODE;
+    else if (!(z < s->L)) bnd = OR_ANODE;
+    else if (!(rn < s->R)) bnd = OR_OUTER;
+    if (bnd >= 0) {
+      s->alive[p] = 0;
+      s->absorbed[bnd][s->sp[p]] += 1;
+      s->charge_absorbed += s->Z[s->sp[p]];
+    } else {
+      s->alive[p] = 1;
+      s->key[p] = key_of(s, rn, z, s->sp[p]);
+    }
+  }
+}
+
+/* 10. stable compaction of the absorbed particles, then this step's
+ *     injected particles in the order given                              */
+void or_stage_compact_inject(or_sim* s) {
+  int64_t w = 0;
+  for (int64_t p = 0; p < s->n; ++p) {
+    if (!s->alive[p]) continue;
+    s->r[w] = s->r[p]; s->z[w] = s->z[p]; s->vr[w] = s->vr[p];
+    s->vt[w] = s->vt[p]; s->vz[w] = s->vz[p]; s->sp[w] = s->sp[p];
+    s->id[w] = s->id[p]; s->key[w] = s->key[p]; s->alive[w] = 1;
+    ++w;
+  }
+  s->n = w;
+  if (s->sched_pos < s->sched_n) {
+    int64_t a = s->sched_off[s->sched_pos], b = s->sched_off[s->sched_pos + 1];
+    append(s, b - a, s->s_r + a, s->s_z + a, s->s_vr + a, s->s_vt + a, s->s_vz + a,
+           s->s_sp + a);
+    s->sched_pos += 1;
+  }
+}
+
+void or_stage_end(or_sim* s) { s->step += 1; }
+
+int or_step(or_sim* s, int nsteps) {
+  if (!s->species_set) return fail("or_step: species not set");
+  if (!s->collisions_off)
+    for (int k = 0; k < OR_NCHANNELS; ++k)
+      if (!s->xs_set[k]) return fail("or_step: cross section missing");
+  for (int t = 0; t < nsteps; ++t) {
+    if (s->next_id + 2 * s->n > (int64_t)UINT32_MAX) return fail("or_step: id overflow");
+    or_stage_sort(s);
+    or_stage_collide(s);
+    or_stage_deposit(s);
+    or_stage_poisson(s);
+    or_stage_field(s);
+    or_stage_push(s);
+    or_stage_compact_inject(s);
+    or_stage_end(s);
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------ */
+int64_t or_count(const or_sim* s) { return s->n; }
+
+void or_get_particles(const or_sim* s, double* r, double* z, double* vr,
+                      double* vt, double* vz, uint8_t* sp, uint32_t* id,
+                      uint32_t* key) {
+  int64_t n = s->n;
+  memcpy(r, s->r, sizeof(double) * n); memcpy(z, s->z, sizeof(double) * n);
+  memcpy(vr, s->vr, sizeof(double) * n); memcpy(vt, s->vt, sizeof(double) * n);
+  memcpy(vz, s->vz, sizeof(double) * n); memcpy(sp, s->sp, n);
+  memcpy(id, s->id, sizeof(uint32_t) * n); memcpy(key, s->key, sizeof(uint32_t) * n);
+}
+
+void or_set_velocities(or_sim* s, const double* vr, const double* vt, const double* vz) {
+  memcpy(s->vr, vr, sizeof(double) * s->n);
+  memcpy(s->vt, vt, sizeof(double) * s->n);
+  memcpy(s->vz, vz, sizeof(double) * s->n);
+}
+
+void or_get_field(const or_sim* s, double* phi, double* Er, double* Ez, int64_t* Q) {
+  size_t nn = (size_t)(s->nr + 1) * (s->nz + 1);
+  if (phi) memcpy(phi, s->phi, sizeof(double) * nn);
+  if (Er) memcpy(Er, s->Er, sizeof(double) * nn);
+  if (Ez) memcpy(Ez, s->Ez, sizeof(double) * nn);
+  if (Q) memcpy(Q, s->Q, sizeof(int64_t) * nn);
+}
+
+void or_get_offsets(const or_sim* s, int64_t* offsets) {
+  memcpy(offsets, s->off, sizeof(int64_t) * (6 * s->ncell + 1));
+}
+
+void or_get_collisions(const or_sim* s, uint8_t* choice, uint32_t* target, uint8_t* winner) {
+  int64_t n = s->n_sorted;
+  if (s->coll_cap < n) n = s->coll_cap;
+  memcpy(choice, s->choice, n);
+  memcpy(target, s->target, sizeof(uint32_t) * n);
+  memcpy(winner, s->win, n);
+}
+
+void or_node_volumes(const or_sim* s, double* Vnode, double* Vcell) {
+  memcpy(Vnode, s->Vnode, sizeof(double) * (s->nr + 1));
+  memcpy(Vcell, s->Vcell, sizeof(double) * s->nr);
+}
+
+void or_get_diag(const or_sim* s, or_diag* d) {
+  memset(d, 0, sizeof *d);
+  d->step = s->step; d->n_alive = s->n; d->next_id = s->next_id;
+  for (int k = 0; k < OR_NCHANNELS; ++k) d->events[k] = s->events[k];
+  d->conflicts = s->conflicts; d->created = s->created;
+  memcpy(d->absorbed, s->absorbed, sizeof d->absorbed);
+  memcpy(d->injected, s->injected, sizeof d->injected);
+  d->charge_absorbed = s->charge_absorbed;
+  d->charge_injected = s->charge_injected;
+  for (int64_t p = 0; p < s->n; ++p) {
+    int sp = s->sp[p];
+    d->count[sp] += 1;
+    d->charge_alive += s->Z[sp];
+    double v2 = ((s->vr[p] * s->vr[p]) + (s->vt[p] * s->vt[p])) + (s->vz[p] * s->vz[p]);
+    d->ke_J[sp] += (0.5 * s->m[sp]) * v2;
+    if (sp >= OR_CU2_STEP) {
+      double ke = ((0.5 * s->m[sp]) * v2) / Q_E;
+      int bin;
+      if (ke < s->edges[0]) bin = 64;
+      else if (!(ke < s->edges[64])) bin = 65;
+      else { bin = 0; while (!(ke < s->edges[bin + 1])) ++bin; }
+      d->spectrum[sp - OR_CU2_STEP][bin] += 1;
+    }
+  }
+  /* Eq. 21 over charge states 0..2 */
+  double N0 = (double)d->count[OR_CU], N1 = (double)d->count[OR_CU1];
+  double N2 = (double)(d->count[OR_CU2_STEP] + d->count[OR_CU2_DOUBLE] + d->count[OR_CU2_INIT]);
+  d->gamma = (N0 + N1 + N2) > 0 ? (N1 + N2) / ((N0 + N1) + N2) : 0.0;
+  d->qbar = (N1 + N2) > 0 ? (N1 + (2.0 * N2)) / (N1 + N2) : 0.0;
+}
+
+/* ------------------------------------------------------------------ */
+/* The literal splitting construction of Eqs. 16-20, used only to check
+ * the projection form against it: shorten v by cos(chi), rotate into the
+ * frame where v lies on +z, scatter by (chi, psi), rotate back.         */
+void or_rotation(double theta, double phi, double Rm[9]) {
+  double ct = cos(theta), st = sin(theta), cf = cos(phi), sf = sin(phi);
+  Rm[0] = ct * cf; Rm[1] = ct * sf; Rm[2] = -st;
+  Rm[3] = -sf;     Rm[4] = cf;      Rm[5] = 0.0;
+  Rm[6] = st * cf; Rm[7] = st * sf; Rm[8] = ct;
+}
+
+static void matvec(const double M[9], const double x[3], double y[3]) {
+  for (int a = 0; a < 3; ++a) y[a] = ((M[3 * a] * x[0]) + (M[3 * a + 1] * x[1])) + (M[3 * a + 2] * x[2]);
+}
+static void matTvec(const double M[9], const double x[3], double y[3]) {
+  for (int a = 0; a < 3; ++a) y[a] = ((M[a] * x[0]) + (M[3 + a] * x[1])) + (M[6 + a] * x[2]);
+}
+
+void or_split_literal(const double v[3], double chi, double psi, double v5[3]) {
+  double vm = sqrt(((v[0] * v[0]) + (v[1] * v[1])) + (v[2] * v[2]));
+  double theta = (vm > 0.0) ? acos(v[2] / vm) : 0.0;
+  double vp = sqrt((v[0] * v[0]) + (v[1] * v[1]));
+  double phi = (vp > 0.0) ? atan2(v[1], v[0]) : 0.0; /* v along z: phi = 0 */
+  double a = cos(chi);
+  double sv[3] = {a * v[0], a * v[1], a * v[2]};
+  double Rt[9], Rc[9], t1[3], t2[3];
+  or_rotation(theta, phi, Rt);
+  or_rotation(chi, psi, Rc);
+  matvec(Rt, sv, t1);   /* Eq. 17: into the local frame */
+  matTvec(Rc, t1, t2);  /* Eq. 18: scatter (R^-1 = R^T) */
+  matTvec(Rt, t2, v5);  /* Eq. 19: back to the laboratory frame */
+}

@@ -1,0 +1,104 @@
+/*
+ * pd_oracle.h -- plain, slow FP64 CPU oracle for one r-z electrostatic
+ * PIC-DSMC step with the four electron-impact channels of Yang et al.,
+ * "The role of double ionization on the generation of doubly charged ions
+ * in copper vacuum arcs" (arXiv 2109.00214).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this library.  It shares no
+ * code, header, table or constant generator with the GPU library; the two
+ * agree only through the written arithmetic contract (one IEEE binary64
+ * expression per quantity, evaluated left to right as parenthesised, no
+ * contraction into fused multiply-add).
+ *
+ * All functions are single-threaded.  Errors return a negative int and set
+ * a message readable with or_last_error().
+ */
+#ifndef PD_ORACLE_H
+#define PD_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* species enum (fixed order); the three Cu2+ tags are separate species */
+enum { OR_E = 0, OR_CU = 1, OR_CU1 = 2, OR_CU2_STEP = 3, OR_CU2_DOUBLE = 4,
+       OR_CU2_INIT = 5, OR_NSPECIES = 6 };
+/* collision channels in cumulative-sum order */
+enum { OR_EL = 0, OR_SI = 1, OR_DI = 2, OR_SI2 = 3, OR_NCHANNELS = 4 };
+/* absorbing boundaries */
+enum { OR_CATHODE = 0, OR_ANODE = 1, OR_OUTER = 2 };
+
+typedef struct or_sim or_sim;
+
+typedef struct {
+  int64_t step, n_alive, next_id;
+  int64_t count[OR_NSPECIES];
+  int64_t events[OR_NCHANNELS];     /* cumulative */
+  int64_t conflicts;                /* cumulative */
+  int64_t created;                  /* cumulative electrons made by collisions */
+  int64_t absorbed[3][OR_NSPECIES]; /* cumulative, per boundary */
+  int64_t injected[OR_NSPECIES];    /* cumulative, incl. initial population */
+  int64_t charge_alive, charge_absorbed, charge_injected; /* sum of Z */
+  double ke_J[OR_NSPECIES];
+  double gamma, qbar;
+  int64_t spectrum[3][66]; /* Cu2+ tags STEP, DOUBLE, INIT: 64 bins, <1 eV, >=1000 eV */
+} or_diag;
+
+or_sim* or_create(int nr, int nz, double R, double L, double V, double dt,
+                  double weight, uint64_t seed, int enable_di,
+                  int deposit_off, int collisions_off);
+void or_destroy(or_sim* s);
+const char* or_last_error(void);
+
+int or_set_species(or_sim* s, int n, const int* Z, const double* mass);
+int or_set_cross_section(or_sim* s, int channel, double threshold_eV, int n,
+                         double dsqrtE, const double* sigma);
+int or_inject(or_sim* s, int64_t n, const double* r, const double* z,
+              const double* vr, const double* vt, const double* vz,
+              const uint8_t* sp);
+int or_schedule_injection(or_sim* s, int nsteps, const int64_t* offsets,
+                          const double* r, const double* z, const double* vr,
+                          const double* vt, const double* vz, const uint8_t* sp);
+int or_step(or_sim* s, int nsteps);
+
+/* stage-level entry points (a full step is these in this order) */
+void or_stage_sort(or_sim* s);
+void or_stage_collide(or_sim* s);
+void or_stage_deposit(or_sim* s);
+void or_stage_poisson(or_sim* s);
+void or_stage_field(or_sim* s);
+void or_stage_push(or_sim* s);
+void or_stage_compact_inject(or_sim* s);
+void or_stage_end(or_sim* s); /* step counter += 1 */
+
+int64_t or_count(const or_sim* s);
+void or_get_particles(const or_sim* s, double* r, double* z, double* vr,
+                      double* vt, double* vz, uint8_t* sp, uint32_t* id,
+                      uint32_t* key);
+void or_set_velocities(or_sim* s, const double* vr, const double* vt,
+                       const double* vz);
+void or_get_field(const or_sim* s, double* phi, double* Er, double* Ez,
+                  int64_t* Q);
+/* set the node charge directly (tests of the Poisson stage) */
+void or_set_charge(or_sim* s, const int64_t* Q);
+void or_get_offsets(const or_sim* s, int64_t* offsets); /* 6*nr*nz + 2 */
+/* per-electron decisions of the last collide stage, in sorted order */
+void or_get_collisions(const or_sim* s, uint8_t* choice, uint32_t* target,
+                       uint8_t* winner);
+void or_get_diag(const or_sim* s, or_diag* d);
+
+/* pure building blocks, exposed for the pin tests */
+void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+int or_poisson_solve(const or_sim* s, const double* f, double* phi_p);
+void or_isotropic(const or_sim* s, uint32_t id, uint32_t purpose, double n[3]);
+void or_rotation(double theta, double phi, double Rm[9]);
+void or_split_literal(const double v[3], double chi, double psi, double v5[3]);
+void or_node_volumes(const or_sim* s, double* Vnode, double* Vcell);
+double or_cross_section(const or_sim* s, int channel, double g);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

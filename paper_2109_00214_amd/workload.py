@@ -1,0 +1,194 @@
+"""Seeded synthetic inputs shaped like the paper's cathode-spot workload.
+
+This module holds none of the method's arithmetic: it only draws particles
+and builds the cross-section tables that both the GPU library and the CPU
+oracle receive as inputs (positions, velocities at the half step before
+their first push, species, and sigma tables uniform in sqrt(E)).
+
+Workload recipe (paper Sec. 2.3, rescaled to the benchmark domains):
+  * domain: r in [0, R), z in [0, L), gap L = 2 um, R = L * nr / nz;
+    cathode at z = 0 held at -V, grounded anode at z = L, V = 2.9 kV
+    (the source voltage of the paper's circuit);
+  * initial population: 40 % e, 40 % Cu, 18 % Cu+, 2 % Cu2+ (tag INIT);
+    density falls off as exp(-d / 0.25 um) with d the distance to the
+    cathode spot disk (r <= 0.5 um, z = 0); electrons 95 % Maxwellian at
+    5 eV plus a 5 % 100 eV beam along +z; heavy particles Maxwellian 2000 K;
+  * injection every step at the spot: electrons (field emission at a
+    constant rate) and neutral Cu at 3 % of the electron rate (the paper's
+    neutral-to-electron flux ratio), both flux-Maxwellian at 2000 K,
+    spread over the first step of flight;
+  * cross sections: synthetic Lotz-form ionization tables with the
+    thresholds 7.73 eV (Cu -> Cu+), 20.29 eV (Cu+ -> Cu2+), 28.0 eV
+    (Cu -> Cu2+, direct double ionization) and a synthetic elastic
+    table; the paper's own data (its Fig. 1) are not available.
+"""
+from dataclasses import dataclass, replace
+
+import numpy as np
+
+# CODATA 2018
+QE = 1.602176634e-19
+ME = 9.1093837015e-31
+AMU = 1.66053906660e-27
+KB = 1.380649e-23
+EPS0 = 8.8541878128e-12
+M_CU = 63.546 * AMU
+
+# species enum: E, CU, CU1, CU2_STEP, CU2_DOUBLE, CU2_INIT
+E, CU, CU1, CU2_STEP, CU2_DOUBLE, CU2_INIT = range(6)
+SPECIES_NAMES = ("e", "Cu", "Cu+", "Cu2+(step)", "Cu2+(double)", "Cu2+(init)")
+# channels in cumulative order
+EL, SI, DI, SI2 = range(4)
+CHANNEL_NAMES = ("elastic", "Cu->Cu+", "Cu->Cu2+ (double)", "Cu+->Cu2+")
+THRESHOLDS_EV = (0.0, 7.73, 28.0, 20.29)
+
+
+def species_table():
+    """Charge numbers and masses, enum order (every Cu state has M_Cu)."""
+    Z = np.array([-1, 0, 1, 2, 2, 2], dtype=np.int32)
+    m = np.array([ME, M_CU, M_CU, M_CU, M_CU, M_CU], dtype=np.float64)
+    return Z, m
+
+
+def lotz(E, P, q, a_cm2=4.5e-14):
+    """Simplified Lotz form sigma = a q ln(E/P) / (E P) in m^2 (E, P in eV)."""
+    E = np.asarray(E, dtype=np.float64)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        s = a_cm2 * q * np.log(np.where(E > P, E / P, 1.0)) / (np.where(E > 0, E, 1.0) * P)
+    return np.where(E >= P, s, 0.0) * 1e-4
+
+
+def cross_section_tables(dsqrtE=2.0 ** -4, n=1025):
+    """(channel, threshold_eV, dsqrtE, sigma[n]) for EL, SI, DI, SI2.
+
+    Tables are uniform in sqrt(E/eV) with spacing dsqrtE (a power of 2).
+    """
+    sq = np.arange(n, dtype=np.float64) * dsqrtE
+    En = sq * sq
+    el = 1e-19 / (1.0 + En / 20.0)
+    si = lotz(En, 7.73, 1.0)
+    di = lotz(En, 28.0, 1.0)
+    si2 = lotz(En, 20.29, 10.0)
+    return [(EL, 0.0, dsqrtE, el), (SI, 7.73, dsqrtE, si), (DI, 28.0, dsqrtE, di),
+            (SI2, 20.29, dsqrtE, si2)]
+
+
+def constant_tables(sig, dsqrtE=2.0 ** -4, n=64, thresholds=(0.0, 0.0, 0.0, 0.0)):
+    """Constant-sigma tables (rate tests); sig = 4 values, one per channel."""
+    return [(k, float(thresholds[k]), dsqrtE, np.full(n, float(sig[k]))) for k in range(4)]
+
+
+@dataclass(frozen=True)
+class Config:
+    name: str
+    nr: int
+    nz: int
+    L: float = 2e-6
+    V: float = 2900.0
+    dt: float = 1e-14
+    weight: float = 100.0
+    seed: int = 1
+    n_init: int = 50_000
+    inj_e: int = 100
+    inj_cu: int = 3
+    steps: int = 200
+    spot: float = 0.5e-6
+    lam: float = 0.25e-6
+    enable_di: bool = True
+
+    @property
+    def R(self):
+        return self.L * self.nr / self.nz
+
+
+CONFIGS = {
+    # plain FP64, 32x64 cells, 50k particles, W = 100, 200 steps, seed 1
+    "tiny": Config("tiny", 32, 64),
+    # paper-shaped: 256x512 cells, 5M particles, W = 1, 2000 steps
+    "paper": Config("paper", 256, 512, weight=1.0, n_init=5_000_000, inj_e=10_000,
+                    inj_cu=300, steps=2000),
+}
+
+
+def config(name, **kw):
+    return replace(CONFIGS[name], **kw)
+
+
+def _rng(seed, tag):
+    return np.random.Generator(np.random.Philox(key=[int(seed), int(tag)]))
+
+
+def _positions(rng, n, cfg):
+    """n positions with density ~ exp(-d/lam), d = distance to the spot disk."""
+    R, L, lam, rs = cfg.R, cfg.L, cfg.lam, cfg.spot
+    out_r = np.empty(0)
+    out_z = np.empty(0)
+    while out_r.size < n:
+        m = max(1024, int((n - out_r.size) * 2.6))
+        # z from an exponential truncated to [0, L); r uniform in area
+        u = rng.random(m)
+        z = -lam * np.log1p(-u * (1.0 - np.exp(-L / lam)))
+        r = R * np.sqrt(rng.random(m))
+        d = np.where(r <= rs, z, np.sqrt((r - rs) ** 2 + z ** 2))
+        acc = rng.random(m) < np.exp(-(d - z) / lam)
+        ok = acc & (r < R) & (z < L) & (z >= 0)
+        out_r = np.concatenate([out_r, r[ok]])
+        out_z = np.concatenate([out_z, z[ok]])
+    return out_r[:n], out_z[:n]
+
+
+def initial_population(cfg, n=None, mix=(0.40, 0.40, 0.18, 0.02)):
+    """Initial super-particles (v at the half step before the first push)."""
+    n = cfg.n_init if n is None else n
+    rng = _rng(cfg.seed, 0x1A17)  # stream INIT
+    counts = [int(round(n * f)) for f in mix]
+    counts[0] += n - sum(counts)
+    sp = np.concatenate([np.full(c, s, np.uint8)
+                         for c, s in zip(counts, (E, CU, CU1, CU2_INIT))])
+    r, z = _positions(rng, n, cfg)
+    v = np.zeros((3, n))
+    ne = counts[0]
+    s_e = np.sqrt(5.0 * QE / ME)
+    s_h = np.sqrt(KB * 2000.0 / M_CU)
+    v[:, :ne] = rng.normal(0.0, s_e, (3, ne))
+    beam = rng.random(ne) < 0.05
+    v[:, :ne][:, beam] = 0.0
+    v[2, :ne][beam] = np.sqrt(2.0 * 100.0 * QE / ME)
+    v[:, ne:] = rng.normal(0.0, s_h, (3, n - ne))
+    return {"r": r, "z": z, "vr": v[0].copy(), "vt": v[1].copy(), "vz": v[2].copy(),
+            "sp": sp}
+
+
+def _emit(rng, n, mass, cfg):
+    s = np.sqrt(KB * 2000.0 / mass)
+    r = cfg.spot * np.sqrt(rng.random(n))
+    vz = s * np.sqrt(-2.0 * np.log1p(-rng.random(n)))  # flux-weighted normal component
+    vr = rng.normal(0.0, s, n)
+    vt = rng.normal(0.0, s, n)
+    z = rng.random(n) * vz * cfg.dt
+    return r, z, vr, vt, vz
+
+
+def injection_schedule(cfg, nsteps, first_step=0):
+    """Per-step injection lists for steps first_step .. first_step+nsteps-1.
+
+    Returns (offsets[nsteps+1], particle dict) in injection order: per step
+    the electrons, then the neutrals.
+    """
+    parts = {k: [] for k in ("r", "z", "vr", "vt", "vz", "sp")}
+    offs = [0]
+    for s in range(first_step, first_step + nsteps):
+        rng = _rng(cfg.seed, 0x10000000 + s)  # stream INJ, one per step
+        for cnt, spc, mass in ((cfg.inj_e, E, ME), (cfg.inj_cu, CU, M_CU)):
+            r, z, vr, vt, vz = _emit(rng, cnt, mass, cfg)
+            for k, a in zip(("r", "z", "vr", "vt", "vz"), (r, z, vr, vt, vz)):
+                parts[k].append(a)
+            parts["sp"].append(np.full(cnt, spc, np.uint8))
+        offs.append(offs[-1] + cfg.inj_e + cfg.inj_cu)
+    out = {k: (np.concatenate(v) if v else np.zeros(0)) for k, v in parts.items()}
+    out["sp"] = out["sp"].astype(np.uint8)
+    return np.array(offs, dtype=np.int64), out
+
+
+def subset(parts, idx):
+    return {k: np.ascontiguousarray(v[idx]) for k, v in parts.items()}

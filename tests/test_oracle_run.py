@@ -1,0 +1,124 @@
+"""Whole-step pins of the oracle: exact conservation of charge and particle
+bookkeeping (the four-stage scheme conserves charge overall, Sec. 2.2),
+Eq. 21, the Cu2+ energy spectra per channel label, input validation and
+determinism."""
+import numpy as np
+import pytest
+
+from conftest import make_oracle
+from paper_2109_00214_amd import workload as W
+
+
+def _tiny_run(steps, **kw):
+    cfg = W.config("tiny", **kw)
+    o = make_oracle(cfg)
+    o.inject(W.initial_population(cfg))
+    off, inj = W.injection_schedule(cfg, steps)
+    o.schedule_injection(off, inj)
+    return cfg, o
+
+
+def _bookkeeping(d):
+    ev = d["events"]
+    alive = d["count"]
+    ab = d["absorbed"].sum(axis=0)
+    inj = d["injected"]
+    # every particle ever present is alive, absorbed, or (heavy) converted
+    assert alive[W.CU2_DOUBLE] + ab[W.CU2_DOUBLE] == ev[W.DI]
+    assert alive[W.CU2_STEP] + ab[W.CU2_STEP] == ev[W.SI2]
+    assert alive[W.CU2_INIT] + ab[W.CU2_INIT] == inj[W.CU2_INIT]
+    assert alive[W.CU1] + ab[W.CU1] == inj[W.CU1] + ev[W.SI] - ev[W.SI2]
+    assert alive[W.CU] + ab[W.CU] == inj[W.CU] - ev[W.SI] - ev[W.DI]
+    assert d["created"] == ev[W.SI] + ev[W.SI2] + 2 * ev[W.DI]
+    assert alive[W.E] + ab[W.E] == inj[W.E] + d["created"]
+    assert d["charge_alive"] + d["charge_absorbed"] == d["charge_injected"]
+    assert d["n_alive"] == alive.sum()
+
+
+def test_tiny_run_conserves_charge_and_counts():
+    cfg, o = _tiny_run(60)
+    for s in range(60):
+        o.step(1)
+        d = o.diag()
+        _bookkeeping(d)
+        assert d["step"] == s + 1
+    assert d["events"].sum() > 50 and d["events"][W.DI] > 0
+    assert d["next_id"] == d["injected"].sum() + d["created"]
+    p = o.particles()
+    assert len(np.unique(p["id"])) == len(p["id"])
+
+
+def test_di_switch():
+    cfg, o = _tiny_run(30, enable_di=False)
+    o.step(30)
+    d = o.diag()
+    assert d["events"][W.DI] == 0 and d["count"][W.CU2_DOUBLE] == 0
+    _bookkeeping(d)
+
+
+def test_run_is_deterministic():
+    a = _tiny_run(15)[1]
+    b = _tiny_run(15)[1]
+    a.step(15)
+    b.step(15)
+    pa, pb = a.particles(), b.particles()
+    for k in pa:
+        assert np.array_equal(pa[k], pb[k])
+    assert np.array_equal(a.field()["phi"], b.field()["phi"])
+
+
+def test_split_steps_equal_one_call():
+    a = _tiny_run(10)[1]
+    b = _tiny_run(10)[1]
+    a.step(10)
+    for _ in range(10):
+        b.step(1)
+    assert np.array_equal(a.particles()["vz"], b.particles()["vz"])
+
+
+def test_eq21_and_spectrum_on_built_population():
+    cfg = W.config("tiny")
+    o = make_oracle(cfg)
+    counts = {W.CU: 30, W.CU1: 12, W.CU2_STEP: 5, W.CU2_DOUBLE: 2, W.CU2_INIT: 1, W.E: 7}
+    sp = np.concatenate([np.full(c, s, np.uint8) for s, c in counts.items()])
+    n = sp.size
+    # Cu2+ energies chosen in the middle of known log bins (1..1000 eV, 64 bins)
+    bins = np.arange(n) % 66
+    ke_eV = np.where(bins < 64, 10 ** (3 * (bins + 0.5) / 64), np.where(bins == 64, 0.3, 2000.0))
+    m = np.where(sp == W.E, W.ME, W.M_CU)
+    v = np.sqrt(2 * ke_eV * W.QE / m)
+    o.inject({"r": np.full(n, 0.5e-6), "z": np.full(n, 1e-6), "vr": np.zeros(n),
+              "vt": np.zeros(n), "vz": v, "sp": sp})
+    d = o.diag()
+    N0, N1, N2 = 30, 12, 8
+    assert d["gamma"] == pytest.approx((N1 + N2) / (N0 + N1 + N2), rel=1e-15)
+    assert d["qbar"] == pytest.approx((N1 + 2 * N2) / (N1 + N2), rel=1e-15)
+    for t, s in enumerate((W.CU2_STEP, W.CU2_DOUBLE, W.CU2_INIT)):
+        ref = np.bincount(bins[sp == s], minlength=66)
+        assert np.array_equal(d["spectrum"][t], ref)
+    ke_J = 0.5 * m * v * v
+    for s in range(6):
+        assert d["ke_J"][s] == pytest.approx(ke_J[sp == s].sum(), rel=1e-12)
+
+
+@pytest.mark.parametrize("bad", ["nan", "r_neg", "r_big", "z_neg", "z_big", "species"])
+def test_injection_validation(bad):
+    cfg = W.config("tiny")
+    o = make_oracle(cfg)
+    p = {"r": np.array([0.1e-6]), "z": np.array([0.1e-6]), "vr": np.zeros(1),
+         "vt": np.zeros(1), "vz": np.zeros(1), "sp": np.zeros(1, np.uint8)}
+    if bad == "nan":
+        p["vz"][0] = np.nan
+    elif bad == "r_neg":
+        p["r"][0] = -1e-9
+    elif bad == "r_big":
+        p["r"][0] = cfg.R
+    elif bad == "z_neg":
+        p["z"][0] = -1e-9
+    elif bad == "z_big":
+        p["z"][0] = cfg.L
+    else:
+        p["sp"][0] = 6
+    with pytest.raises(ValueError):
+        o.inject(p)
+    assert o.count() == 0
