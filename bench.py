@@ -1,0 +1,167 @@
+"""Benchmark of the r-z PIC-DSMC step on one MI355X.
+
+Workload (default): the paper-shaped configuration -- 256 x 512 r-z cells,
+5,000,000 super-particles (40 % e, 40 % Cu, 18 % Cu+, 2 % Cu2+) at W = 1,
+10,300 particles injected per step, FP64 deterministic mode, seed 1.  All
+inputs (initial population and the whole injection schedule) are resident
+in HBM before the timed region.  A "step" is the full hot path: sort ->
+collisions -> deposit -> Poisson -> field -> gather+push -> absorb ->
+inject.  The metric is particle-steps per second including DSMC: the sum
+over the timed steps of the particles pushed, divided by the wall time of
+those steps (HIP events on the library's stream, bracketed by
+synchronisation).
+
+Prints one JSON line.  --gpus N > 1 is not supported (one GPU only).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per particle and launch (FP64 record: r, z, vr, vt, vz = 40 B,
+# species 1 B, id 4 B, key 4 B)
+ALGO_BYTES = {
+    "push": 41 + 40 + 4,          # read state + species, write state + key
+    "permute": 4 + 4 + 45 + 49,   # read key + perm + record, write record + key
+    "deposit": 8 + 8 + 1,         # read r, z, species
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1980)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--config", default="paper")
+    ap.add_argument("--n-init", type=int, default=None)
+    ap.add_argument("--cpu-steps", type=int, default=1,
+                    help="oracle steps timed for the CPU baseline (0: skip)")
+    ap.add_argument("--traffic", default=None,
+                    help="JSON file with rocprofv3 FETCH/WRITE bytes per launch of the kernel")
+    return ap.parse_args()
+
+
+def cpu_baseline(cfg, parts, off, inj, nsteps):
+    """The oracle, single-threaded, on a bounded sample of the same workload."""
+    import oracle
+    from paper_2109_00214_amd import workload as W
+    o = oracle.Oracle(cfg.nr, cfg.nz, cfg.R, cfg.L, cfg.V, cfg.dt, cfg.weight, cfg.seed,
+                      enable_di=cfg.enable_di)
+    Z, m = W.species_table()
+    o.set_species(Z, m)
+    for ch, thr, dsq, sig in W.cross_section_tables():
+        o.set_cross_section(ch, thr, dsq, sig)
+    o.inject(parts)
+    o.schedule_injection(off[: nsteps + 1], {k: v[: off[nsteps]] for k, v in inj.items()})
+    tot = 0
+    t0 = time.perf_counter()
+    for _ in range(nsteps):
+        o.stage("sort")
+        o.stage("collide")
+        tot += o.count()
+        for st in ("deposit", "poisson", "field", "push", "compact_inject", "end"):
+            o.stage(st)
+    dt = time.perf_counter() - t0
+    return {"value": tot / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": "%d step(s) of the %s workload from its initial state (%d particles), "
+                      "single-threaded FP64 C oracle" % (nsteps, cfg.name, len(parts["r"])),
+            "seconds": dt}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py: this build runs on one GPU only (--gpus %d requested)" % a.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2109_00214_amd import workload as W
+    from paper_2109_00214_amd.pd import Simulation
+
+    kw = {} if a.n_init is None else {"n_init": a.n_init}
+    cfg = W.config(a.config, **kw)
+    nsteps = a.warmup + a.steps
+    t0 = time.time()
+    parts = W.initial_population(cfg)
+    off, inj = W.injection_schedule(cfg, nsteps)
+    print("inputs ready in %.1f s: %d initial, %d scheduled" % (time.time() - t0, len(parts["r"]),
+                                                                  off[-1]), file=sys.stderr)
+    torch.cuda.init()
+    stream = torch.cuda.current_stream()
+    cap = int(1.25 * cfg.n_init + cfg.inj_cu * nsteps + 40 * cfg.inj_e + 1_000_000)
+    sim = Simulation(cfg, cap, W.cross_section_tables(), W.species_table(), timing=True,
+                     stream=stream.cuda_stream)
+    sim.inject(parts)
+    sim.schedule_injection(off, inj)
+    sim.step(a.warmup)
+    sim.synchronize()
+    d0 = sim.diag()
+    sim.timing(reset=True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    sim.step(a.steps)
+    e1.record(stream)
+    sim.synchronize()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    d1 = sim.diag()
+    stages, tsteps = sim.timing()
+    pst = d1["particle_steps"] - d0["particle_steps"]
+    value = pst / (ms / 1e3)
+    per_step = {k: v / max(tsteps, 1) for k, v in stages.items()}
+    print("stage ms/step: " + ", ".join("%s %.4f" % kv for kv in per_step.items()), file=sys.stderr)
+    # roofline of the dominant single-kernel stage
+    cand = {k: per_step[k] for k in ALGO_BYTES}
+    dom = max(cand, key=cand.get)
+    units = pst / a.steps
+    achieved = ALGO_BYTES[dom] * units / (per_step[dom] / 1e3) / 1e9
+    traffic = None
+    if a.traffic and os.path.exists(a.traffic):
+        tr = json.load(open(a.traffic))
+        traffic = tr.get(dom)
+    roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "bytes_per_particle": ALGO_BYTES[dom], "particles_per_launch": round(units)}
+    out = {
+        "metric": "particle-steps/s incl. DSMC",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "%s: %dx%d r-z cells, %d initial super-particles, W=%g, "
+                               "%d injected/step, FP64 deterministic" %
+                               (cfg.name, cfg.nr, cfg.nz, cfg.n_init, cfg.weight,
+                                cfg.inj_e + cfg.inj_cu),
+                   "poisson": "direct FP64 (sine transform + tridiagonal)",
+                   "poisson_s_per_step": per_step["poisson"] / 1e3,
+                   "mean_particles_per_step": round(units),
+                   "final_particles": int(d1["n_alive"])},
+        "roofline": roof,
+        "stages_ms_per_step": {k: round(v, 5) for k, v in per_step.items()},
+        "cpu_baseline": None,
+    }
+    sim.close()
+    if a.cpu_steps > 0:
+        out["cpu_baseline"] = cpu_baseline(cfg, parts, off, inj, a.cpu_steps)
+    del np
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

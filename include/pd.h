@@ -1,0 +1,197 @@
+/*
+ * pd.h -- C ABI of the MI355X (gfx950) r-z electrostatic PIC-DSMC library.
+ *
+ * The library advances one 2D3V axisymmetric plasma in a planar diode
+ * (cathode at z = 0, anode at z = L, symmetry axis r = 0, wall at r = R)
+ * with the particle-in-cell / direct-simulation-Monte-Carlo step of
+ * Yang et al., arXiv 2109.00214, Sec. 2:
+ *   - per-cell particle lists (stable sort by species and cell),
+ *   - DSMC electron-impact collisions (Sec. 2.1, Eqs. 4-7): elastic,
+ *     Cu -> Cu+, Cu+ -> Cu2+ and the paper's direct Cu -> Cu2+ double
+ *     ionization done as four binary stages (Sec. 2.2, Eqs. 11-15); Cu2+
+ *     super-particles carry the label of the channel that made them,
+ *   - cloud-in-cell charge deposit (Eqs. 9-10) in int64 fixed point,
+ *   - the cylindrical Poisson equation (Eq. 8) and E = -grad(phi),
+ *   - field gather and leapfrog push in 2D3V (Sec. 2.1, Newton's law),
+ *   - absorption at the electrodes and the wall, and injection.
+ *
+ * Conventions (all entry points):
+ *   - Units are SI, except thresholds and spectra in eV.
+ *   - Every pointer argument is a HOST pointer.  Input arrays are owned by
+ *     the caller and copied during the call; output arrays are
+ *     caller-allocated.  The library owns all device memory of a context.
+ *   - Node arrays are node-major with r fastest: index j*(nr+1) + i for the
+ *     node at r = i*R/nr, z = j*L/nz, j = 0..nz, i = 0..nr.
+ *   - Particle arrays are structure-of-arrays of length n.
+ *   - A non-zero return leaves the context unchanged unless stated
+ *     otherwise; pd_last_error() gives a message.  No C++ exception
+ *     crosses the ABI.
+ *   - Calls on one context must not overlap; separate contexts are
+ *     independent.  Work runs on the context's HIP stream; entry points
+ *     that return data synchronise that stream first.
+ *   - Results depend only on the inputs and the seed, never on the launch
+ *     geometry: in the FP64 deterministic mode every integer result and
+ *     every particle and node value is bit-identical to the reference
+ *     arithmetic (one IEEE binary64 expression per quantity, no fused
+ *     multiply-add).
+ */
+#ifndef PD_H
+#define PD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pd_ctx pd_ctx;
+
+typedef enum {
+  PD_OK = 0,
+  PD_EINVAL = -1,     /* bad argument (NaN, out of the domain, wrong size) */
+  PD_ENOMEM = -2,     /* device allocation failed */
+  PD_EDEVICE = -3,    /* HIP runtime error */
+  PD_ESTATE = -4,     /* call not valid in the current state */
+  PD_ENOCONV = -5,    /* iterative Poisson solve did not converge */
+  PD_ECAPACITY = -6   /* particle capacity or 32-bit id space exhausted */
+} pd_status;
+
+/* species (fixed order); the three Cu2+ labels are separate species */
+enum { PD_E = 0, PD_CU = 1, PD_CU1 = 2, PD_CU2_STEP = 3, PD_CU2_DOUBLE = 4,
+       PD_CU2_INIT = 5, PD_NSPECIES = 6 };
+/* collision channels, in the order their probabilities are summed */
+enum { PD_EL = 0, PD_SI = 1, PD_DI = 2, PD_SI2 = 3, PD_NCHANNELS = 4 };
+/* absorbing boundaries */
+enum { PD_CATHODE = 0, PD_ANODE = 1, PD_OUTER = 2 };
+/* precision forms */
+enum { PD_FP64_DET = 0 };
+/* Poisson solvers */
+enum { PD_POISSON_DIRECT64 = 0 };
+/* stages timed by pd_get_timing: radix passes of the sort, payload
+ * permutation, CSR offsets, collisions, deposit, Poisson, field, push,
+ * injection + counter roll */
+enum { PD_T_RADIX = 0, PD_T_PERMUTE = 1, PD_T_OFFSETS = 2, PD_T_COLLIDE = 3,
+       PD_T_DEPOSIT = 4, PD_T_POISSON = 5, PD_T_FIELD = 6, PD_T_PUSH = 7,
+       PD_T_INJECT = 8, PD_NTIMERS = 9 };
+
+typedef struct {
+  int32_t nr, nz;      /* cells in r and z (nr >= 2, nz >= 2) */
+  double R, L;         /* wall radius and gap length, m */
+  double V_cathode;    /* phi(z = 0) = -V_cathode, phi(z = L) = 0, V */
+  double dt;           /* time step, s (one step for every species) */
+  double weight;       /* real particles per super-particle */
+  uint64_t seed;       /* Philox4x32-10 key of the collision draws */
+  int64_t capacity;    /* maximum number of particles held at once */
+} pd_domain;
+
+typedef struct {
+  int32_t precision;      /* PD_FP64_DET */
+  int32_t poisson;        /* PD_POISSON_DIRECT64 */
+  int32_t enable_di;      /* 1: include the direct Cu -> Cu2+ channel */
+  int32_t deposit_off;    /* 1: skip the deposit (vacuum field), tests */
+  int32_t collisions_off; /* 1: skip the DSMC stage, tests */
+  int32_t timing;         /* 1: record HIP events around every stage */
+  void* stream;           /* hipStream_t to run on, or NULL for a new one */
+} pd_opts;
+
+typedef struct {
+  int64_t step, n_alive, next_id;
+  int64_t count[PD_NSPECIES];
+  int64_t events[PD_NCHANNELS];  /* cumulative events per channel */
+  int64_t conflicts;             /* cumulative trials that lost their target */
+  int64_t created;               /* cumulative electrons made by collisions */
+  int64_t absorbed[3][PD_NSPECIES];
+  int64_t injected[PD_NSPECIES]; /* cumulative, initial population included */
+  int64_t charge_alive, charge_absorbed, charge_injected; /* sums of Z, exact */
+  double ke_J[PD_NSPECIES];      /* kinetic energy per species at v(n+1/2) */
+  double gamma, qbar;            /* Eq. 21 over charge states 0..2 */
+  int64_t particle_steps;        /* sum over steps of the particles pushed */
+} pd_diag;
+
+/* Create a context on the current HIP device.  dom and opts are copied.
+ * Device memory for dom->capacity particles is allocated here.
+ * Errors: PD_EINVAL (sizes, NaN), PD_ENOMEM, PD_EDEVICE.            */
+pd_status pd_create(const pd_domain* dom, const pd_opts* opts, pd_ctx** out);
+
+/* Charge numbers Z[n] and masses mass[n] (kg) in the species order above;
+ * n must be PD_NSPECIES.  Must be called before the first step.       */
+pd_status pd_set_species(pd_ctx* ctx, int n, const int32_t* Z, const double* mass);
+
+/* Integrated cross section of one channel (Eq. 4's sigma) as a table
+ * uniform in sqrt(E / eV): sigma[k] at sqrt(E) = k * dsqrtE, n >= 2,
+ * dsqrtE a power of two, linear interpolation, sigma = 0 below
+ * threshold_eV, clamped at the last entry.  E is the energy of relative
+ * motion m_r g^2 / 2.  threshold_eV is also the energy lost in the first
+ * stage of an ionizing event (Sec. 2.2, Eq. 12).                     */
+pd_status pd_set_cross_section(pd_ctx* ctx, int channel, double threshold_eV, int n,
+                               double dsqrtE, const double* sigma);
+
+/* Append n particles now: positions r, z (0 <= r < R, 0 <= z < L),
+ * velocities vr, vt, vz at the half step before their first push
+ * (leapfrog), species sp[n].  They receive ids next_id, next_id+1, ...
+ * Errors: PD_EINVAL (non-finite, outside the domain, species >= 6) and
+ * PD_ECAPACITY; the context is unchanged on error.                   */
+pd_status pd_inject(pd_ctx* ctx, int64_t n, const double* r, const double* z,
+                    const double* vr, const double* vt, const double* vz,
+                    const uint8_t* sp);
+
+/* Upload an injection schedule for the next nsteps steps: step k appends
+ * particles offsets[k] .. offsets[k+1]-1 (offsets[0] = 0) at the end of
+ * the step, after absorption, in the order given, with fresh ids.  The
+ * whole schedule is copied to device memory now.  Replaces any earlier
+ * schedule; steps past its end inject nothing.                        */
+pd_status pd_schedule_injection(pd_ctx* ctx, int nsteps, const int64_t* offsets,
+                                const double* r, const double* z, const double* vr,
+                                const double* vt, const double* vz, const uint8_t* sp);
+
+/* Enqueue nsteps full steps on the context's stream and return.  Step n:
+ * sort -> collide -> deposit -> Poisson -> field -> gather+push ->
+ * absorb -> inject.  Capacity overflow found on the device is reported
+ * by the next call that synchronises (PD_ECAPACITY); the context is then
+ * unusable (PD_ESTATE).                                               */
+pd_status pd_step(pd_ctx* ctx, int nsteps);
+
+/* Wait for all enqueued work; reports device-side errors.            */
+pd_status pd_synchronize(pd_ctx* ctx);
+
+/* Counts, cumulative events and the snapshot reductions.            */
+pd_status pd_get_diagnostics(pd_ctx* ctx, pd_diag* out);
+
+/* Kinetic-energy spectrum of one Cu2+ label (tag 0 = step-wise, 1 =
+ * direct double ionization, 2 = initial): out[0..63] count particles
+ * with 10^(3b/64) <= E/eV < 10^(3(b+1)/64); out[64] counts E < 1 eV,
+ * out[65] counts E >= 1000 eV.  E = M |v|^2 / 2 at v(n+1/2).          */
+pd_status pd_get_spectrum(pd_ctx* ctx, int tag, int64_t out[66]);
+
+/* Number of particles alive.                                          */
+pd_status pd_get_count(pd_ctx* ctx, int64_t* n);
+
+/* Copy the alive particles, in the order the next sort receives them,
+ * into caller arrays of length >= cap (cap >= count, else PD_EINVAL).
+ * key = species * nr * nz + j * nr + i of the particle's cell.  Any
+ * pointer may be NULL.                                                */
+pd_status pd_get_particles(pd_ctx* ctx, int64_t cap, double* r, double* z, double* vr,
+                           double* vt, double* vz, uint8_t* sp, uint32_t* id,
+                           uint32_t* key);
+
+/* Potential, field and integer node charge of the last step ((nr+1) *
+ * (nz+1) nodes each; Q in units of e * weight * 2^-40).  Any pointer may
+ * be NULL.                                                            */
+pd_status pd_get_field(pd_ctx* ctx, double* phi, double* Er, double* Ez, int64_t* Q);
+
+/* Accumulated device time per stage (ms, PD_NTIMERS entries) and the
+ * number of steps timed, since creation or the last reset (requires
+ * opts.timing).  reset != 0 clears the accumulators after reading.    */
+pd_status pd_get_timing(pd_ctx* ctx, double* ms, int64_t* steps, int reset);
+
+/* Message of the last failed call on this context (never NULL).      */
+const char* pd_last_error(const pd_ctx* ctx);
+
+/* Free the context and its device memory.  NULL is ignored.          */
+void pd_destroy(pd_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,313 @@
+// k_collide.hip -- DSMC electron-impact collisions (paper Sec. 2.1-2.2).
+//
+// One trial per electron per step (Eq. 4 with the exact exponential over
+// the summed channels).  Four launches:
+//   decide  -- one lane per electron (electrons occupy sorted positions
+//              [0, off[C]) because keys are species-major): counter-based
+//              Philox draws keyed by particle id, one uniform Cu and one
+//              Cu+ target in the electron's cell, relative speed, sigma
+//              from the sqrt(E) tables, x_k = dt g n_t sigma_k, the test
+//              R1 < 1 - exp(-X) and the channel; successful trials claim
+//              their target with atomicMin of the sorted position;
+//   resolve -- the lowest position wins each target; counts per channel
+//              and the number of electrons each winner creates (0/1/2);
+//   scan    -- exclusive scan of those counts in sorted order: slots and
+//              ids of new electrons are therefore independent of timing;
+//   apply   -- Eqs. 5-6 (binary update) with isotropic directions
+//              (Eq. 7 with I = 1/(4 pi), Marsaglia's method); ionizing
+//              events run the stages of Eqs. 12-15.
+// All floating-point expressions are evaluated exactly as written (the
+// library is compiled without contraction), so the results are identical
+// to any other evaluation of the same binary64 expressions.
+#include "pd_internal.h"
+
+namespace pd {
+
+static inline int grid_for(int64_t n, int block = 256) {
+  int64_t g = (n + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > 8192) g = 8192;
+  return (int)g;
+}
+
+// Philox4x32-10 (Salmon et al., SC'11)
+__device__ inline void philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                              uint32_t k1, uint32_t out[4]) {
+#pragma unroll
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+  }
+  out[0] = c0;
+  out[1] = c1;
+  out[2] = c2;
+  out[3] = c3;
+}
+
+// uniform in [0,1): the top 53 bits of (hi:lo) times 2^-53
+__device__ inline double u53(uint32_t hi, uint32_t lo) {
+  const uint64_t b = (((uint64_t)hi << 32) | (uint64_t)lo) >> 11;
+  return (double)b * 0x1p-53;
+}
+
+__device__ inline double sigma_of(const CollideParams& cp, int k, double g) {
+  const double sq = g * cp.ck[k];
+  const double eps = sq * sq;
+  if (eps < cp.thr[k]) return 0.0;
+  const int n = cp.tabn[k];
+  const double* t = cp.tab[k];
+  const double x = sq / cp.dsq[k];
+  if (x >= (double)(n - 1)) return t[n - 1];
+  const int i = (int)x;
+  return t[i] + ((x - (double)i) * (t[i + 1] - t[i]));
+}
+
+// isotropic unit vector (Marsaglia 1972); counter (id, 0, step, purpose<<24 | d)
+__device__ inline void isotropic(const CollideParams& cp, uint32_t id, uint32_t step,
+                                 uint32_t purpose, double n[3]) {
+  for (uint32_t d = 0; d < 64; ++d) {
+    uint32_t w[4];
+    philox(id, 0u, step, (purpose << 24) | d, cp.seed_lo, cp.seed_hi, w);
+    const double u1 = (2.0 * u53(w[0], w[1])) - 1.0;
+    const double u2 = (2.0 * u53(w[2], w[3])) - 1.0;
+    const double q = (u1 * u1) + (u2 * u2);
+    if (q < 1.0 && q > 0.0) {
+      const double t = sqrt(1.0 - q);
+      n[0] = (2.0 * u1) * t;
+      n[1] = (2.0 * u2) * t;
+      n[2] = 1.0 - (2.0 * q);
+      return;
+    }
+  }
+  n[0] = 0.0;
+  n[1] = 0.0;
+  n[2] = 1.0;
+}
+
+// binary collision, Eqs. 5-6
+__device__ inline void binary(double v1[3], double v2[3], double two_dE_mr, double f1, double f2,
+                              const double n[3]) {
+  const double u0 = v1[0] - v2[0], u1 = v1[1] - v2[1], u2 = v1[2] - v2[2];
+  const double g2 = ((u0 * u0) + (u1 * u1)) + (u2 * u2);
+  double gp2 = g2 + two_dE_mr;
+  if (gp2 < 0.0) gp2 = 0.0;
+  const double gp = sqrt(gp2);
+  const double u[3] = {u0, u1, u2};
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double du = (gp * n[c]) - u[c];
+    v1[c] = v1[c] + (du * f1);
+    v2[c] = v2[c] - (du * f2);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_decide(Parts P, const uint32_t* off, const DevState* st,
+                                                Grid g, CollideParams cp, uint8_t* choice,
+                                                uint32_t* target, uint32_t* claim,
+                                                uint32_t* scan_len) {
+  const uint32_t C = g.C;
+  const uint32_t n_e = off[C];
+  const uint32_t step = st->step;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *scan_len = n_e;
+  for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < n_e; e += gridDim.x * blockDim.x) {
+    const uint32_t cell = P.key[e];
+    const int ci = (int)(cell % (uint32_t)g.nr);
+    const uint32_t b_cu = off[C + cell], n_cu = off[C + cell + 1] - b_cu;
+    const uint32_t b_c1 = off[2 * C + cell], n_c1 = off[2 * C + cell + 1] - b_c1;
+    const uint32_t id = P.id[e];
+    uint32_t w[4], t[4];
+    philox(id, 0u, step, 0u, cp.seed_lo, cp.seed_hi, w);
+    philox(id, 0u, step, 1u << 24, cp.seed_lo, cp.seed_hi, t);
+    const double R1 = u53(w[0], w[1]);
+    const double R2 = u53(w[2], w[3]);
+    const uint32_t tc = b_cu + __umulhi(t[0], n_cu);
+    const uint32_t t1 = b_c1 + __umulhi(t[1], n_c1);
+    const double evr = P.vr[e], evt = P.vt[e], evz = P.vz[e];
+    double x[kNC] = {0.0, 0.0, 0.0, 0.0};
+    const double Vc = cp.Vcell[ci];
+    // Cu target: EL, SI, DI share the pick and the relative speed
+    if (n_cu > 0) {
+      const double dvr = evr - P.vr[tc], dvt = evt - P.vt[tc], dvz = evz - P.vz[tc];
+      const double gg = sqrt(((dvr * dvr) + (dvt * dvt)) + (dvz * dvz));
+      const double dens = ((double)n_cu * cp.W) / Vc;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        if (k == 2 && !cp.enable_di) continue;
+        x[k] = ((cp.dt * gg) * dens) * sigma_of(cp, k, gg);
+      }
+    }
+    if (n_c1 > 0) {
+      const double dvr = evr - P.vr[t1], dvt = evt - P.vt[t1], dvz = evz - P.vz[t1];
+      const double gg = sqrt(((dvr * dvr) + (dvt * dvt)) + (dvz * dvz));
+      const double dens = ((double)n_c1 * cp.W) / Vc;
+      x[3] = ((cp.dt * gg) * dens) * sigma_of(cp, 3, gg);
+    }
+    const double X = ((x[0] + x[1]) + x[2]) + x[3];
+    const double pc = 1.0 - exp(-X);
+    int ch = -1;
+    if (R1 < pc) {
+      const double u = R2 * X;
+      double c = 0.0;
+#pragma unroll
+      for (int k = 0; k < kNC; ++k) {
+        c = c + x[k];
+        if (ch < 0 && u < c) ch = k;
+      }
+      if (ch < 0) {
+        for (int k = kNC - 1; k >= 0; --k)
+          if (x[k] > 0.0) {
+            ch = k;
+            break;
+          }
+      }
+    }
+    if (ch >= 0) {
+      const uint32_t tp = (ch == 3) ? t1 : tc;
+      choice[e] = (uint8_t)(ch + 1);
+      target[e] = tp;
+      atomicMin(&claim[tp], e);
+    } else {
+      choice[e] = 0;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_resolve(const uint32_t* off, DevState* st, Grid g,
+                                                 uint8_t* choice, const uint32_t* target,
+                                                 const uint32_t* claim, uint32_t* ccount) {
+  const uint32_t n_e = off[g.C];
+  const int lane = threadIdx.x & 63;
+  // grid-stride over whole waves so that every lane of a wave takes part in the ballots
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t e0 = blockIdx.x * blockDim.x; e0 < n_e; e0 += stride) {
+    const uint32_t e = e0 + threadIdx.x;
+    int ch = -1;
+    bool lost = false;
+    uint32_t cnt = 0;
+    if (e < n_e) {
+      const uint32_t c = choice[e];
+      if (c) {
+        if (claim[target[e]] == e) {
+          ch = (int)c - 1;
+          cnt = (ch == 0) ? 0u : (ch == 2 ? 2u : 1u);
+        } else {
+          lost = true;
+          choice[e] = 0;
+        }
+      }
+      ccount[e] = cnt;
+    }
+    const uint64_t ml = __ballot(lost);
+    if (lane == 0 && ml) atomicAdd(&st->conflicts, (unsigned long long)__popcll(ml));
+#pragma unroll
+    for (int k = 0; k < kNC; ++k) {
+      const uint64_t m = __ballot(ch == k);
+      if (lane == 0 && m) atomicAdd(&st->events[k], (unsigned long long)__popcll(m));
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_apply(Parts P, const uint32_t* off, DevState* st, Grid g,
+                                               CollideParams cp, const uint8_t* choice,
+                                               const uint32_t* target, const uint32_t* cbase,
+                                               uint32_t* claim, uint32_t cap) {
+  const uint32_t n_e = off[g.C];
+  const uint32_t n_alive = st->n_alive;
+  const uint32_t next_id = st->next_id;
+  const uint32_t step = st->step;
+  if (st->err) return;  // the guard found no room for the new electrons
+  for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < n_e; e += gridDim.x * blockDim.x) {
+    const uint32_t c = choice[e];
+    if (!c) continue;
+    const int ch = (int)c - 1;
+    const uint32_t tp = target[e];
+    const uint32_t id = P.id[e];
+    double e1[3] = {P.vr[e], P.vt[e], P.vz[e]};
+    double A[3] = {P.vr[tp], P.vt[tp], P.vz[tp]};
+    double nh[3];
+    claim[tp] = 0xFFFFFFFFu;
+    // stage 1: elastic, or inelastic losing the channel threshold (Eq. 12)
+    isotropic(cp, id, step, 2u, nh);
+    binary(e1, A, cp.two_dE_mr[ch], cp.f1[ch], cp.f2[ch], nh);
+    P.vr[tp] = A[0];
+    P.vt[tp] = A[1];
+    P.vz[tp] = A[2];
+    if (ch == 0) {
+      P.vr[e] = e1[0];
+      P.vt[e] = e1[1];
+      P.vz[e] = e1[2];
+      continue;
+    }
+    // stage 2 (Eq. 13): the target keeps its slot and id, changes label;
+    // the new electron e2 takes the target's position and velocity
+    P.sp[tp] = (uint8_t)(ch == 1 ? 2 : (ch == 2 ? 4 : 3));
+    double e2[3] = {A[0], A[1], A[2]};
+    // stage 3 (Eq. 14): e1-e2 elastic, equal masses
+    isotropic(cp, id, step, 3u, nh);
+    binary(e1, e2, 0.0, 0.5, 0.5, nh);
+    const uint32_t slot = n_alive + cbase[e];
+    const uint32_t nid = next_id + cbase[e];
+    P.r[slot] = P.r[tp];
+    P.z[slot] = P.z[tp];
+    P.vr[slot] = e2[0];
+    P.vt[slot] = e2[1];
+    P.vz[slot] = e2[2];
+    P.sp[slot] = 0;
+    P.id[slot] = nid;
+    if (ch == 2) {
+      // stage 4 (Eq. 15): e3 splits into the two orthogonal edges of the
+      // rectangle whose diagonal is v3
+      isotropic(cp, id, step, 4u, nh);
+      const double d = ((e1[0] * nh[0]) + (e1[1] * nh[1])) + (e1[2] * nh[2]);
+      const double v5[3] = {d * nh[0], d * nh[1], d * nh[2]};
+      const uint32_t s6 = slot + 1;
+      P.r[s6] = P.r[e];
+      P.z[s6] = P.z[e];
+      P.vr[s6] = e1[0] - v5[0];
+      P.vt[s6] = e1[1] - v5[1];
+      P.vz[s6] = e1[2] - v5[2];
+      P.sp[s6] = 0;
+      P.id[s6] = nid + 1;
+      e1[0] = v5[0];
+      e1[1] = v5[1];
+      e1[2] = v5[2];
+    }
+    P.vr[e] = e1[0];
+    P.vt[e] = e1[1];
+    P.vz[e] = e1[2];
+  }
+}
+
+// No room for the new electrons (capacity or 32-bit ids), or an earlier
+// error: flag it and create nothing, so that every later launch of the step
+// touches only the live particles [0, n_alive).
+__global__ void k_created_guard(DevState* st, uint32_t cap) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const uint64_t n = (uint64_t)st->n_alive + st->n_created;
+  if (st->err || n > cap || (uint64_t)st->next_id + st->n_created > 0xFFFFFFFFull) {
+    st->err |= 1u;
+    st->n_created = 0;
+  }
+}
+
+void collide(const Parts& P, const uint32_t* off, DevState* st, const Grid& g,
+             const CollideParams& cp, CollideWork& w, uint32_t* bsum, int64_t cap, hipStream_t s) {
+  const int gr = grid_for(cap);
+  k_decide<<<gr, 256, 0, s>>>(P, off, st, g, cp, w.choice, w.target, w.claim, w.scan_len);
+  k_resolve<<<gr, 256, 0, s>>>(off, st, g, w.choice, w.target, w.claim, w.ccount);
+  scan_exclusive(w.ccount, w.cbase, w.scan_len, &st->n_created, bsum, cap, s);
+  k_created_guard<<<1, 64, 0, s>>>(st, (uint32_t)cap);
+  k_apply<<<gr, 256, 0, s>>>(P, off, st, g, cp, w.choice, w.target, w.cbase, w.claim,
+                             (uint32_t)cap);
+}
+
+}  // namespace pd

@@ -1,0 +1,400 @@
+// k_pic.hip -- particle-in-cell part of the step (paper Sec. 2.1):
+// fixed-point cloud-in-cell deposit (Eqs. 9-10), the cylindrical Poisson
+// solve (Eq. 8) by a sine transform in z and tridiagonal solves in r, the
+// nodal field E = -grad(phi), gather + leapfrog push in 2D3V, absorption,
+// injection, and the snapshot reductions.
+#include "pd_internal.h"
+
+namespace pd {
+
+static inline int grid_for(int64_t n, int block = 256) {
+  int64_t g = (n + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > 8192) g = 8192;
+  return (int)g;
+}
+
+// cell and in-cell fractions: i = min((int)(r/dr), nr-1), fr = r/dr - i
+__device__ inline void cell_of(const Grid& g, double r, double z, int& i, int& j, double& fr,
+                               double& fz) {
+  const double xr = r / g.dr, xz = z / g.dz;
+  i = (int)xr;
+  j = (int)xz;
+  if (i > g.nr - 1) i = g.nr - 1;
+  if (j > g.nz - 1) j = g.nz - 1;
+  fr = xr - (double)i;
+  fz = xz - (double)j;
+}
+
+// ---------------------------------------------------------------------------
+// deposit: weights rounded to 2^-20 per dimension, complementary, so each
+// particle adds exactly Z * 2^40 to the four nodes of its cell
+__global__ void __launch_bounds__(256) k_deposit(Parts P, const DevState* st, Grid g,
+                                                 SpeciesParams spp, unsigned long long* Q) {
+  const uint32_t n = st->n_alive + st->n_created;
+  const int W = g.nr + 1;
+  for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
+    int i, j;
+    double fr, fz;
+    cell_of(g, P.r[p], P.z[p], i, j, fr, fz);
+    const int64_t ar = (int64_t)floor((fr * 1048576.0) + 0.5), br = 1048576 - ar;
+    const int64_t az = (int64_t)floor((fz * 1048576.0) + 0.5), bz = 1048576 - az;
+    const int64_t Zp = spp.Z[P.sp[p]];
+    if (Zp == 0) continue;
+    const int b = j * W + i;
+    atomicAdd(&Q[b], (unsigned long long)(Zp * (br * bz)));
+    atomicAdd(&Q[b + 1], (unsigned long long)(Zp * (ar * bz)));
+    atomicAdd(&Q[b + W], (unsigned long long)(Zp * (br * az)));
+    atomicAdd(&Q[b + W + 1], (unsigned long long)(Zp * (ar * az)));
+  }
+}
+
+__global__ void k_fill_i64(int64_t* p, int64_t v, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+void fill_i64(int64_t* p, int64_t v, int64_t n, hipStream_t s) {
+  k_fill_i64<<<grid_for(n), 256, 0, s>>>(p, v, n);
+}
+void fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
+  k_fill_u32<<<grid_for(n), 256, 0, s>>>(p, v, n);
+}
+
+void deposit(const Parts& P, const DevState* st, const Grid& g, const SpeciesParams& sp,
+             int64_t* Q, int64_t cap, hipStream_t s) {
+  const int64_t nn = (int64_t)(g.nr + 1) * (g.nz + 1);
+  fill_i64(Q, 0, nn, s);
+  k_deposit<<<grid_for(cap), 256, 0, s>>>(P, st, g, sp, (unsigned long long*)Q);
+}
+
+// ---------------------------------------------------------------------------
+// Poisson: f = -rho/eps0 on the interior rows, rho = Q qunit / V_node
+__global__ void __launch_bounds__(256) k_rhs(const int64_t* Q, const double* Vnode, double qunit,
+                                             int nr, int nz, double* f) {
+  const int W = nr + 1;
+  const int n = (nz - 1) * W;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+    const int i = t % W;
+    const double rho = ((double)Q[t + W] * qunit) / Vnode[i];
+    f[t] = -(rho / kEPS0);
+  }
+}
+
+// forward DST-I over the interior z nodes: fh[i][k] = sum_j f[j][i] S[k][j]
+__global__ void __launch_bounds__(256) k_dst_fwd(const double* f, const double* S, int nr, int nz,
+                                                 double* fh) {
+  const int M = nz - 1, W = nr + 1;
+  const int n = W * M;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+    const int k = t % M, i = t / M;
+    double acc = 0.0;
+    for (int j = 0; j < M; ++j) acc = acc + (f[j * W + i] * S[j * M + k]);
+    fh[t] = acc;
+  }
+}
+
+// Thomas per mode with the host-factored reciprocals: in place on fh
+__global__ void __launch_bounds__(256) k_thomas(double* fh, const double* tinv, const double* tcp,
+                                                const double* ra, int nr, int nz) {
+  const int M = nz - 1;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= M) return;
+  double dp = fh[k] * tinv[k];
+  fh[k] = dp;
+  for (int i = 1; i <= nr; ++i) {
+    const int q = i * M + k;
+    dp = (fh[q] - (ra[i] * dp)) * tinv[q];
+    fh[q] = dp;
+  }
+  double x = dp;
+  for (int i = nr - 1; i >= 0; --i) {
+    const int q = i * M + k;
+    x = fh[q] - (tcp[q] * x);
+    fh[q] = x;
+  }
+}
+
+// inverse DST-I and the vacuum potential
+__global__ void __launch_bounds__(256) k_dst_inv(const double* gh, const double* S, int nr, int nz,
+                                                 double V, double* phi) {
+  const int M = nz - 1, W = nr + 1;
+  const int n = (nz + 1) * W;
+  const double scale = 2.0 / (double)nz;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+    const int j = t % (nz + 1), i = t / (nz + 1);
+    const double vac = (-V) + (V * ((double)j / (double)nz));
+    double pp = 0.0;
+    if (j > 0 && j < nz) {
+      double acc = 0.0;
+      const double* grow = gh + (size_t)i * M;
+      for (int k = 0; k < M; ++k) acc = acc + (grow[k] * S[k * M + (j - 1)]);
+      pp = acc * scale;
+    }
+    phi[j * W + i] = vac + pp;
+  }
+}
+
+void poisson_direct(const Grid& g, FieldWork& fw, hipStream_t s) {
+  const int nr = g.nr, nz = g.nz, M = nz - 1, W = nr + 1;
+  k_rhs<<<grid_for((int64_t)M * W), 256, 0, s>>>(fw.Q, fw.Vnode, fw.qunit, nr, nz, fw.f);
+  k_dst_fwd<<<grid_for((int64_t)M * W), 256, 0, s>>>(fw.f, fw.S, nr, nz, fw.fh);
+  k_thomas<<<(M + 255) / 256, 256, 0, s>>>(fw.fh, fw.tinv, fw.tcp, fw.ra, nr, nz);
+  k_dst_inv<<<grid_for((int64_t)(nz + 1) * W), 256, 0, s>>>(fw.fh, fw.S, nr, nz, g.V, fw.phi);
+}
+
+// E = -grad(phi): central differences, second-order one-sided at the
+// electrodes, E_r = 0 on the axis and at the wall
+__global__ void __launch_bounds__(256) k_field(const double* phi, int nr, int nz, double dr,
+                                               double dz, double* Er, double* Ez) {
+  const int W = nr + 1;
+  const int n = (nz + 1) * W;
+  const double tdz = 2.0 * dz, tdr = 2.0 * dr;
+  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < n; b += gridDim.x * blockDim.x) {
+    const int j = b / W, i = b % W;
+    double ez;
+    if (j == 0) ez = (((3.0 * phi[b]) - (4.0 * phi[b + W])) + phi[b + 2 * W]) / tdz;
+    else if (j == nz) ez = (((4.0 * phi[b - W]) - (3.0 * phi[b])) - phi[b - 2 * W]) / tdz;
+    else ez = (phi[b - W] - phi[b + W]) / tdz;
+    const double er = (i == 0 || i == nr) ? 0.0 : (phi[b - 1] - phi[b + 1]) / tdr;
+    Ez[b] = ez;
+    Er[b] = er;
+  }
+}
+
+void field(const Grid& g, FieldWork& fw, hipStream_t s) {
+  const int64_t n = (int64_t)(g.nr + 1) * (g.nz + 1);
+  k_field<<<grid_for(n), 256, 0, s>>>(fw.phi, g.nr, g.nz, g.dr, g.dz, fw.Er, fw.Ez);
+}
+
+// ---------------------------------------------------------------------------
+// wave-aggregated absorbed counters: one atomic per (boundary, species) per wave
+__device__ inline void count_codes(int code, unsigned long long* ctr) {
+  const int lane = threadIdx.x & 63;
+  uint64_t pending = __ballot(code >= 0);
+  while (pending) {
+    const int leader = __ffsll((long long)pending) - 1;
+    const int c = __shfl(code, leader, 64);
+    const uint64_t m = __ballot(code == c);
+    if (lane == leader) atomicAdd(&ctr[c], (unsigned long long)__popcll(m));
+    pending &= ~m;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_push(Parts P, DevState* st, Grid g, SpeciesParams spp,
+                                              const double* Er, const double* Ez) {
+  const uint32_t n = st->n_alive + st->n_created;
+  const int W = g.nr + 1;
+  const double dt = g.dt;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t p0 = blockIdx.x * blockDim.x; p0 < n; p0 += stride) {
+    const uint32_t p = p0 + threadIdx.x;
+    int code = -1;
+    if (p < n) {
+      int i, j;
+      double fr, fz;
+      const double r = P.r[p], z0 = P.z[p];
+      cell_of(g, r, z0, i, j, fr, fz);
+      const int b = j * W + i;
+      const double gr = 1.0 - fr, gz = 1.0 - fz;
+      const double w00 = gr * gz, w10 = fr * gz, w01 = gr * fz, w11 = fr * fz;
+      const double er = (((w00 * Er[b]) + (w10 * Er[b + 1])) + (w01 * Er[b + W])) + (w11 * Er[b + W + 1]);
+      const double ez = (((w00 * Ez[b]) + (w10 * Ez[b + 1])) + (w01 * Ez[b + W])) + (w11 * Ez[b + W + 1]);
+      const int s = P.sp[p];
+      const double qm = spp.qmdt[s];
+      double vr = P.vr[p] + (qm * er);
+      double vz = P.vz[p] + (qm * ez);
+      double vt = P.vt[p];
+      const double x = r + (vr * dt);
+      const double y = vt * dt;
+      const double z = z0 + (vz * dt);
+      const double rn = sqrt((x * x) + (y * y));
+      if (rn > 0.0) {
+        const double c = x / rn, sn = y / rn;
+        const double vr2 = (c * vr) + (sn * vt);
+        const double vt2 = (c * vt) - (sn * vr);
+        vr = vr2;
+        vt = vt2;
+      }
+      P.r[p] = rn;
+      P.z[p] = z;
+      P.vr[p] = vr;
+      P.vt[p] = vt;
+      P.vz[p] = vz;
+      int bnd = -1;
+      if (z < 0.0) bnd = 0;
+      else if (!(z < g.L)) bnd = 1;
+      else if (!(rn < g.R)) bnd = 2;
+      if (bnd >= 0) {
+        code = bnd * kNS + s;
+        P.key[p] = g.sentinel;
+      } else {
+        int i2, j2;
+        double a, c;
+        cell_of(g, rn, z, i2, j2, a, c);
+        P.key[p] = (uint32_t)s * g.C + (uint32_t)(j2 * g.nr + i2);
+      }
+    }
+    count_codes(code, st->absorbed);
+  }
+}
+
+void push(const Parts& P, DevState* st, const Grid& g, const SpeciesParams& sp, const FieldWork& fw,
+          int64_t cap, hipStream_t s) {
+  k_push<<<grid_for(cap), 256, 0, s>>>(P, st, g, sp, fw.Er, fw.Ez);
+}
+
+// ---------------------------------------------------------------------------
+// this step's scheduled particles, appended after the pushed ones
+__global__ void __launch_bounds__(256) k_inject(Parts P, DevState* st, Grid g, Schedule sc,
+                                                uint32_t cap) {
+  const uint32_t pos = st->sched_pos;
+  if (pos >= st->sched_n) return;
+  const int64_t a = sc.off[pos];
+  const uint32_t cnt = (uint32_t)(sc.off[pos + 1] - a);
+  const uint32_t base = st->n_alive + st->n_created;
+  const uint32_t id0 = st->next_id + st->n_created;
+  if ((uint64_t)base + cnt > cap || (uint64_t)id0 + cnt > 0xFFFFFFFFull) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&st->err, 1u);
+    return;
+  }
+  for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < cnt; q += gridDim.x * blockDim.x) {
+    const int64_t src = a + q;
+    const uint32_t d = base + q;
+    const double r = sc.r[src], z = sc.z[src];
+    const uint32_t s = sc.sp[src];
+    P.r[d] = r;
+    P.z[d] = z;
+    P.vr[d] = sc.vr[src];
+    P.vt[d] = sc.vt[src];
+    P.vz[d] = sc.vz[src];
+    P.sp[d] = (uint8_t)s;
+    P.id[d] = id0 + q;
+    int i, j;
+    double fr, fz;
+    cell_of(g, r, z, i, j, fr, fz);
+    P.key[d] = s * g.C + (uint32_t)(j * g.nr + i);
+  }
+}
+
+void inject_scheduled(const Parts& P, DevState* st, const Grid& g, const Schedule& sc, int64_t cap,
+                      hipStream_t s) {
+  if (!sc.off) return;
+  k_inject<<<grid_for(sc.max_count), 256, 0, s>>>(P, st, g, sc, (uint32_t)cap);
+}
+
+// roll the counters: the arrays now hold alive + created + injected
+__global__ void k_step_end(DevState* st, const int64_t* soff) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  uint32_t inj = 0;
+  if (soff && st->sched_pos < st->sched_n) {
+    inj = (uint32_t)(soff[st->sched_pos + 1] - soff[st->sched_pos]);
+    st->sched_pos += 1;
+  }
+  if (st->err) inj = 0;
+  st->created += st->n_created;
+  st->pushed += st->n_alive + st->n_created;
+  st->n_total = st->n_alive + st->n_created + inj;
+  st->next_id += st->n_created + inj;
+  st->n_created = 0;
+  st->step += 1;
+}
+
+void step_end(DevState* st, const Schedule& sc, hipStream_t s) {
+  k_step_end<<<1, 64, 0, s>>>(st, sc.off);
+}
+
+// host-initiated append of n particles already copied to src
+__global__ void __launch_bounds__(256) k_append(Parts P, const DevState* st, Grid g, Parts src,
+                                                uint32_t n) {
+  const uint32_t base = st->n_total;
+  const uint32_t id0 = st->next_id;
+  for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
+    const uint32_t d = base + q;
+    const double r = src.r[q], z = src.z[q];
+    const uint32_t s = src.sp[q];
+    P.r[d] = r;
+    P.z[d] = z;
+    P.vr[d] = src.vr[q];
+    P.vt[d] = src.vt[q];
+    P.vz[d] = src.vz[q];
+    P.sp[d] = (uint8_t)s;
+    P.id[d] = id0 + q;
+    int i, j;
+    double fr, fz;
+    cell_of(g, r, z, i, j, fr, fz);
+    P.key[d] = s * g.C + (uint32_t)(j * g.nr + i);
+  }
+}
+__global__ void k_append_end(DevState* st, uint32_t n) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    st->n_total += n;
+    st->next_id += n;
+  }
+}
+
+void append(const Parts& P, DevState* st, const Grid& g, const Parts& src, uint32_t n,
+            hipStream_t s) {
+  if (n == 0) return;
+  k_append<<<grid_for(n), 256, 0, s>>>(P, st, g, src, n);
+  k_append_end<<<1, 64, 0, s>>>(st, n);
+}
+
+// ---------------------------------------------------------------------------
+// snapshot: counts and kinetic energy per species (per-block partials, summed
+// on the host in block order), Cu2+ spectra by comparison with the edges
+__global__ void __launch_bounds__(256) k_diag(Parts P, const DevState* st, Grid g,
+                                              SpeciesParams spp, const double* edges,
+                                              unsigned long long* counts, double* ke,
+                                              unsigned long long* spec) {
+  __shared__ unsigned long long sc[kNS];
+  __shared__ double sk[256][kNS];
+  const uint32_t n = st->n_total;
+  if (threadIdx.x < kNS) sc[threadIdx.x] = 0;
+  double acc[kNS] = {0, 0, 0, 0, 0, 0};
+  __syncthreads();
+  for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
+    if (P.key[p] == g.sentinel) continue;
+    const int s = P.sp[p];
+    atomicAdd(&sc[s], 1ull);
+    const double v2 = ((P.vr[p] * P.vr[p]) + (P.vt[p] * P.vt[p])) + (P.vz[p] * P.vz[p]);
+    acc[s] += (0.5 * spp.m[s]) * v2;
+    if (s >= 3) {
+      const double e = ((0.5 * spp.m[s]) * v2) / kQE;
+      int bin;
+      if (e < edges[0]) bin = 64;
+      else if (!(e < edges[64])) bin = 65;
+      else {
+        int lo = 0, hi = 64;  // edges[lo] <= e < edges[hi]
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (e < edges[mid]) hi = mid;
+          else lo = mid;
+        }
+        bin = lo;
+      }
+      atomicAdd(&spec[(s - 3) * 66 + bin], 1ull);
+    }
+  }
+  for (int s = 0; s < kNS; ++s) sk[threadIdx.x][s] = acc[s];
+  __syncthreads();
+  if (threadIdx.x < kNS) {
+    double t = 0.0;
+    for (int q = 0; q < 256; ++q) t += sk[q][threadIdx.x];
+    ke[blockIdx.x * kNS + threadIdx.x] = t;
+    counts[blockIdx.x * kNS + threadIdx.x] = sc[threadIdx.x];
+  }
+}
+
+void diag_snapshot(const Parts& P, const DevState* st, const Grid& g, const SpeciesParams& sp,
+                   const double* edges, unsigned long long* counts, double* ke,
+                   unsigned long long* spec, hipStream_t s) {
+  k_diag<<<kDiagBlocks, 256, 0, s>>>(P, st, g, sp, edges, counts, ke, spec);
+}
+
+}  // namespace pd

@@ -1,0 +1,749 @@
+// pd_capi.hip -- host engine and C ABI (include/pd.h) of the gfx950
+// PIC-DSMC library.  Owns the device memory of a context, builds the host
+// tables of the method (node and cell volumes, the finite-volume radial
+// operator, the sine table and the per-mode tridiagonal factors), and
+// enqueues the kernels of one step on the context's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstddef>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/pd.h"
+#include "pd_internal.h"
+
+using namespace pd;
+
+struct pd_ctx {
+  pd_domain dom;
+  pd_opts opts;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+  bool poisoned = false;
+
+  Grid g{};
+  SpeciesParams spp{};
+  CollideParams cpar{};
+  bool species_set = false;
+  bool xs_set[kNC] = {false, false, false, false};
+  double xs_thr[kNC] = {0, 0, 0, 0};
+  double qunit = 0;
+  int key_bits = 0;
+  int64_t cap = 0;
+
+  // device memory
+  std::vector<void*> allocs;
+  Parts A{}, B{};
+  SortWork sw{};
+  CollideWork cw{};
+  FieldWork fw{};
+  DevState* st = nullptr;
+  uint32_t* off = nullptr;
+  double* d_xs[kNC] = {nullptr, nullptr, nullptr, nullptr};
+  double* d_edges = nullptr;
+  unsigned long long* d_dcount = nullptr;
+  double* d_dke = nullptr;
+  unsigned long long* d_spec = nullptr;
+
+  // injection schedule
+  Schedule sched{};
+  std::vector<void*> sched_allocs;
+  std::vector<std::array<int64_t, kNS>> sched_species;
+  int64_t sched_n = 0, host_sched_pos = 0;
+
+  // host-side bookkeeping
+  int64_t host_step = 0;
+  int64_t injected[kNS] = {0, 0, 0, 0, 0, 0};
+
+  // timing
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::vector<hipEvent_t>> ev_pending;
+  double t_ms[PD_NTIMERS] = {0};
+  int64_t t_steps = 0;
+};
+
+namespace {
+
+thread_local std::string g_create_err;
+
+pd_status set_err(pd_ctx* c, pd_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return s;
+}
+
+#define HIPCHK(ctx, call)                                                                 \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return set_err(ctx, PD_EDEVICE, "%s: %s", #call, hipGetErrorString(e_));           \
+  } while (0)
+
+template <class T>
+pd_status dalloc(pd_ctx* c, T** p, size_t n) {
+  void* q = nullptr;
+  size_t bytes = n * sizeof(T);
+  if (bytes == 0) bytes = 16;
+  hipError_t e = hipMalloc(&q, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return set_err(c, PD_ENOMEM, "hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
+  }
+  c->allocs.push_back(q);
+  *p = (T*)q;
+  return PD_OK;
+}
+
+pd_status alloc_parts(pd_ctx* c, Parts& P, int64_t n) {
+  pd_status s;
+  if ((s = dalloc(c, &P.r, n)) || (s = dalloc(c, &P.z, n)) || (s = dalloc(c, &P.vr, n)) ||
+      (s = dalloc(c, &P.vt, n)) || (s = dalloc(c, &P.vz, n)) || (s = dalloc(c, &P.sp, n)) ||
+      (s = dalloc(c, &P.id, n)) || (s = dalloc(c, &P.key, n)))
+    return s;
+  return PD_OK;
+}
+
+bool finite_all(int64_t n, const double* a) {
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(a[i])) return false;
+  return true;
+}
+
+pd_status check_particles(pd_ctx* c, int64_t n, const double* r, const double* z, const double* vr,
+                          const double* vt, const double* vz, const uint8_t* sp) {
+  if (n > 0 && (!r || !z || !vr || !vt || !vz || !sp))
+    return set_err(c, PD_EINVAL, "null particle array");
+  if (!finite_all(n, r) || !finite_all(n, z) || !finite_all(n, vr) || !finite_all(n, vt) ||
+      !finite_all(n, vz))
+    return set_err(c, PD_EINVAL, "non-finite particle value");
+  for (int64_t p = 0; p < n; ++p) {
+    if (!(r[p] >= 0.0) || !(r[p] < c->dom.R) || !(z[p] >= 0.0) || !(z[p] < c->dom.L))
+      return set_err(c, PD_EINVAL, "particle %lld outside the domain", (long long)p);
+    if (sp[p] >= kNS) return set_err(c, PD_EINVAL, "particle %lld: species %d", (long long)p, sp[p]);
+  }
+  return PD_OK;
+}
+
+// Host tables of the method.  Every expression is the binary64 value of the
+// formula as parenthesised (compiled without contraction).
+void build_tables(pd_ctx* c, std::vector<double>& Vnode, std::vector<double>& Vcell,
+                  std::vector<double>& ra, std::vector<double>& S, std::vector<double>& tinv,
+                  std::vector<double>& tcp, std::vector<double>& edges) {
+  const int nr = c->dom.nr, nz = c->dom.nz, M = nz - 1;
+  const double R = c->dom.R, dr = c->g.dr, dz = c->g.dz;
+  Vnode.assign(nr + 1, 0.0);
+  Vcell.assign(nr, 0.0);
+  // node volumes of linear weighting in r (the hat function's volume
+  // integral) and the cell volumes
+  Vnode[0] = ((kPI * (dr * dr)) * dz) / 3.0;
+  for (int i = 1; i < nr; ++i) Vnode[i] = (((2.0 * kPI) * ((double)i * dr)) * dr) * dz;
+  Vnode[nr] = (kPI * dz) * ((R * dr) - ((dr * dr) / 3.0));
+  for (int i = 0; i < nr; ++i) {
+    const double a = (double)i * dr, b = (double)(i + 1) * dr;
+    Vcell[i] = (kPI * ((b * b) - (a * a))) * dz;
+  }
+  // radial finite-volume operator: flux r dphi/dr through the faces of
+  // [r_{i-1/2}, r_{i+1/2}] clipped to [0, R], none through r = 0 and r = R
+  std::vector<double> rb(nr + 1), rc(nr + 1);
+  ra.assign(nr + 1, 0.0);
+  for (int i = 0; i <= nr; ++i) {
+    double area;
+    if (i == 0) area = (dr * dr) / 8.0;
+    else if (i == nr) area = ((R * dr) / 2.0) - ((dr * dr) / 8.0);
+    else area = ((double)i * dr) * dr;
+    const double lo = (i == 0) ? 0.0 : ((double)i - 0.5) * dr;
+    const double hi = (i == nr) ? 0.0 : ((double)i + 0.5) * dr;
+    ra[i] = lo / (dr * area);
+    rc[i] = hi / (dr * area);
+    rb[i] = -(ra[i] + rc[i]);
+  }
+  // DST-I table over the interior z nodes, argument reduced exactly
+  S.assign((size_t)M * M, 0.0);
+  for (int k = 1; k <= M; ++k)
+    for (int j = 1; j <= M; ++j) {
+      long long m = ((long long)k * j) % (2LL * nz);
+      bool neg = false;
+      if (m >= nz) {
+        m -= nz;
+        neg = true;
+      }
+      if (2 * m > nz) m = nz - m;
+      const double v = (m == 0) ? 0.0 : std::sin((kPI * (double)m) / (double)nz);
+      S[(size_t)(k - 1) * M + (j - 1)] = neg ? -v : v;
+    }
+  // per-mode tridiagonal factors of (D_r + mu_k), mu_k the eigenvalue of
+  // the 3-point d2/dz2 on sin(pi k j / nz)
+  tinv.assign((size_t)(nr + 1) * M, 0.0);
+  tcp.assign((size_t)(nr + 1) * M, 0.0);
+  for (int k = 1; k <= M; ++k) {
+    const double h = std::sin((kPI * (double)k) / (2.0 * (double)nz));
+    const double mu = -(4.0 * (h * h)) / (dz * dz);
+    double inv = 1.0 / (rb[0] + mu);
+    double cp = rc[0] * inv;
+    tinv[(size_t)0 * M + (k - 1)] = inv;
+    tcp[(size_t)0 * M + (k - 1)] = cp;
+    for (int i = 1; i <= nr; ++i) {
+      const double den = (rb[i] + mu) - (ra[i] * cp);
+      inv = 1.0 / den;
+      cp = rc[i] * inv;
+      tinv[(size_t)i * M + (k - 1)] = inv;
+      tcp[(size_t)i * M + (k - 1)] = cp;
+    }
+  }
+  edges.assign(65, 0.0);
+  for (int b = 0; b <= 64; ++b) edges[b] = std::pow(10.0, (3.0 * (double)b) / 64.0);
+}
+
+void derive_pairs(pd_ctx* c) {
+  // projectile: electron; target: Cu (EL, SI, DI) or Cu+ (SI2)
+  const int tgt[kNC] = {PD_CU, PD_CU, PD_CU, PD_CU1};
+  for (int k = 0; k < kNC; ++k) {
+    const double m1 = c->spp.m[PD_E], m2 = c->spp.m[tgt[k]];
+    const double mr = (m1 * m2) / (m1 + m2);
+    c->cpar.f1[k] = mr / m1;
+    c->cpar.f2[k] = mr / m2;
+    c->cpar.ck[k] = std::sqrt(mr / (2.0 * kQE));
+    c->cpar.two_dE_mr[k] = (k == PD_EL) ? 0.0 : (2.0 * (-(c->xs_thr[k] * kQE))) / mr;
+  }
+}
+
+pd_status sync(pd_ctx* c) {
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    c->poisoned = true;
+    return set_err(c, PD_EDEVICE, "stream: %s", hipGetErrorString(e));
+  }
+  return PD_OK;
+}
+
+pd_status read_state(pd_ctx* c, DevState* h) {
+  pd_status s = sync(c);
+  if (s) return s;
+  HIPCHK(c, hipMemcpy(h, c->st, sizeof(DevState), hipMemcpyDeviceToHost));
+  if (h->err) {
+    c->poisoned = true;
+    return set_err(c, PD_ECAPACITY, "particle capacity (%lld) or id space exhausted on the device",
+                   (long long)c->cap);
+  }
+  return PD_OK;
+}
+
+hipEvent_t get_event(pd_ctx* c) {
+  if (!c->ev_pool.empty()) {
+    hipEvent_t e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+
+void harvest_timing(pd_ctx* c) {
+  for (auto& set : c->ev_pending) {
+    for (int k = 0; k < PD_NTIMERS; ++k) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, set[k], set[k + 1]) == hipSuccess) c->t_ms[k] += ms;
+    }
+    c->t_steps += 1;
+    for (auto e : set) c->ev_pool.push_back(e);
+  }
+  c->ev_pending.clear();
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+extern "C" {
+
+pd_status pd_create(const pd_domain* dom, const pd_opts* opts, pd_ctx** out) {
+  if (!dom || !opts || !out) return PD_EINVAL;
+  *out = nullptr;
+  pd_ctx* c = new (std::nothrow) pd_ctx();
+  if (!c) return PD_ENOMEM;
+  c->dom = *dom;
+  c->opts = *opts;
+  auto fail = [&](pd_status s) {
+    g_create_err = c->err;
+    pd_destroy(c);
+    return s;
+  };
+  if (dom->nr < 2 || dom->nz < 2 || dom->nr > 8192 || dom->nz > 8192 ||
+      (int64_t)dom->nr * dom->nz * 6 >= (1LL << 31) || !(dom->R > 0) || !(dom->L > 0) ||
+      !(dom->dt > 0) || !(dom->weight > 0) || !std::isfinite(dom->V_cathode) ||
+      !std::isfinite(dom->R) || !std::isfinite(dom->L) || dom->capacity < 1 ||
+      dom->capacity > (int64_t)kScanChunk * kScanMaxBlocks)
+    return fail(set_err(c, PD_EINVAL, "invalid domain"));
+  if (opts->precision != PD_FP64_DET || opts->poisson != PD_POISSON_DIRECT64)
+    return fail(set_err(c, PD_EINVAL, "unsupported precision or Poisson mode"));
+  if (opts->stream) {
+    c->stream = (hipStream_t)opts->stream;
+  } else {
+    if (hipStreamCreate(&c->stream) != hipSuccess) return fail(set_err(c, PD_EDEVICE, "stream"));
+    c->own_stream = true;
+  }
+  const int nr = dom->nr, nz = dom->nz;
+  c->cap = dom->capacity;
+  c->g.nr = nr;
+  c->g.nz = nz;
+  c->g.C = (uint32_t)(nr * nz);
+  c->g.sentinel = 6u * c->g.C;
+  c->g.dr = dom->R / (double)nr;
+  c->g.dz = dom->L / (double)nz;
+  c->g.R = dom->R;
+  c->g.L = dom->L;
+  c->g.V = dom->V_cathode;
+  c->g.dt = dom->dt;
+  c->qunit = (kQE * dom->weight) * 0x1p-40;
+  {
+    int b = 0;
+    while ((1u << b) <= c->g.sentinel) ++b;
+    c->key_bits = b;
+  }
+  const int Zd[kNS] = {-1, 0, 1, 2, 2, 2};
+  for (int k = 0; k < kNS; ++k) c->spp.Z[k] = Zd[k];
+  c->cpar.W = dom->weight;
+  c->cpar.dt = dom->dt;
+  c->cpar.seed_lo = (uint32_t)dom->seed;
+  c->cpar.seed_hi = (uint32_t)(dom->seed >> 32);
+  c->cpar.enable_di = opts->enable_di ? 1 : 0;
+
+  const int64_t cap = c->cap;
+  const int64_t nn = (int64_t)(nr + 1) * (nz + 1);
+  const int M = nz - 1;
+  const int64_t tiles = (cap + kSortTile - 1) / kSortTile;
+  pd_status s;
+  if ((s = alloc_parts(c, c->A, cap)) || (s = alloc_parts(c, c->B, cap)) ||
+      (s = dalloc(c, &c->sw.k0, cap)) || (s = dalloc(c, &c->sw.k1, cap)) ||
+      (s = dalloc(c, &c->sw.v0, cap)) || (s = dalloc(c, &c->sw.v1, cap)) ||
+      (s = dalloc(c, &c->sw.hist, (size_t)kRadix * (tiles < 1 ? 1 : tiles))) ||
+      (s = dalloc(c, &c->sw.bsum, kScanMaxBlocks)) || (s = dalloc(c, &c->sw.scan_len, 4)) ||
+      (s = dalloc(c, &c->cw.choice, cap)) || (s = dalloc(c, &c->cw.target, cap)) ||
+      (s = dalloc(c, &c->cw.claim, cap)) || (s = dalloc(c, &c->cw.ccount, cap)) ||
+      (s = dalloc(c, &c->cw.cbase, cap)) || (s = dalloc(c, &c->cw.scan_len, 4)) ||
+      (s = dalloc(c, &c->fw.Q, nn)) || (s = dalloc(c, &c->fw.phi, nn)) ||
+      (s = dalloc(c, &c->fw.Er, nn)) || (s = dalloc(c, &c->fw.Ez, nn)) ||
+      (s = dalloc(c, &c->fw.f, (size_t)M * (nr + 1))) ||
+      (s = dalloc(c, &c->fw.fh, (size_t)M * (nr + 1))) || (s = dalloc(c, &c->st, 1)) ||
+      (s = dalloc(c, &c->off, (size_t)c->g.sentinel + 1)) || (s = dalloc(c, &c->d_edges, 65)) ||
+      (s = dalloc(c, &c->d_dcount, (size_t)kDiagBlocks * kNS)) ||
+      (s = dalloc(c, &c->d_dke, (size_t)kDiagBlocks * kNS)) ||
+      (s = dalloc(c, &c->d_spec, 3 * 66)))
+    return fail(s);
+  c->sw.cap = cap;
+  c->cw.cap = cap;
+
+  std::vector<double> Vnode, Vcell, ra, S, tinv, tcp, edges;
+  build_tables(c, Vnode, Vcell, ra, S, tinv, tcp, edges);
+  double *dVn, *dVc, *dra, *dS, *dti, *dtc;
+  if ((s = dalloc(c, &dVn, Vnode.size())) || (s = dalloc(c, &dVc, Vcell.size())) ||
+      (s = dalloc(c, &dra, ra.size())) || (s = dalloc(c, &dS, S.size())) ||
+      (s = dalloc(c, &dti, tinv.size())) || (s = dalloc(c, &dtc, tcp.size())))
+    return fail(s);
+  auto up = [&](void* d, const void* h, size_t b) {
+    return hipMemcpy(d, h, b, hipMemcpyHostToDevice) == hipSuccess;
+  };
+  if (!up(dVn, Vnode.data(), Vnode.size() * 8) || !up(dVc, Vcell.data(), Vcell.size() * 8) ||
+      !up(dra, ra.data(), ra.size() * 8) || !up(dS, S.data(), S.size() * 8) ||
+      !up(dti, tinv.data(), tinv.size() * 8) || !up(dtc, tcp.data(), tcp.size() * 8) ||
+      !up(c->d_edges, edges.data(), 65 * 8))
+    return fail(set_err(c, PD_EDEVICE, "table upload failed"));
+  c->fw.Vnode = dVn;
+  c->fw.ra = dra;
+  c->fw.S = dS;
+  c->fw.tinv = dti;
+  c->fw.tcp = dtc;
+  c->fw.qunit = c->qunit;
+  c->cpar.Vcell = dVc;
+
+  DevState h{};
+  if (hipMemcpy(c->st, &h, sizeof h, hipMemcpyHostToDevice) != hipSuccess)
+    return fail(set_err(c, PD_EDEVICE, "state upload failed"));
+  fill_u32(c->cw.claim, 0xFFFFFFFFu, cap, c->stream);
+  fill_i64(c->fw.Q, 0, nn, c->stream);
+  // vacuum potential and field until the first solve
+  {
+    std::vector<double> phi(nn), er(nn, 0.0), ez(nn);
+    for (int j = 0; j <= nz; ++j) {
+      const double vac = (-dom->V_cathode) + (dom->V_cathode * ((double)j / (double)nz));
+      for (int i = 0; i <= nr; ++i) phi[(size_t)j * (nr + 1) + i] = vac;
+    }
+    if (!up(c->fw.phi, phi.data(), nn * 8)) return fail(set_err(c, PD_EDEVICE, "upload"));
+    field(c->g, c->fw, c->stream);
+  }
+  if (hipStreamSynchronize(c->stream) != hipSuccess)
+    return fail(set_err(c, PD_EDEVICE, "initialisation failed"));
+  *out = c;
+  return PD_OK;
+}
+
+pd_status pd_set_species(pd_ctx* c, int n, const int32_t* Z, const double* mass) {
+  if (!c) return PD_EINVAL;
+  if (n != kNS || !Z || !mass) return set_err(c, PD_EINVAL, "need %d species", kNS);
+  for (int k = 0; k < n; ++k)
+    if (!(mass[k] > 0) || !std::isfinite(mass[k]) || Z[k] < -8 || Z[k] > 8)
+      return set_err(c, PD_EINVAL, "species %d: bad charge or mass", k);
+  for (int k = 0; k < n; ++k) {
+    c->spp.Z[k] = Z[k];
+    c->spp.m[k] = mass[k];
+    c->spp.qmdt[k] = (((double)Z[k] * kQE) / mass[k]) * c->dom.dt;
+  }
+  c->species_set = true;
+  derive_pairs(c);
+  return PD_OK;
+}
+
+pd_status pd_set_cross_section(pd_ctx* c, int ch, double thr, int n, double dsq, const double* sig) {
+  if (!c) return PD_EINVAL;
+  if (ch < 0 || ch >= kNC) return set_err(c, PD_EINVAL, "channel %d", ch);
+  if (n < 2 || !sig || !(dsq > 0) || !std::isfinite(dsq) || !(thr >= 0) || !std::isfinite(thr))
+    return set_err(c, PD_EINVAL, "bad cross-section table");
+  int ex;
+  if (std::frexp(dsq, &ex) != 0.5) return set_err(c, PD_EINVAL, "dsqrtE must be a power of 2");
+  for (int i = 0; i < n; ++i)
+    if (!(sig[i] >= 0) || !std::isfinite(sig[i])) return set_err(c, PD_EINVAL, "sigma[%d]", i);
+  pd_status s = sync(c);
+  if (s) return s;
+  double* d = nullptr;
+  if ((s = dalloc(c, &d, (size_t)n))) return s;
+  HIPCHK(c, hipMemcpy(d, sig, sizeof(double) * n, hipMemcpyHostToDevice));
+  c->d_xs[ch] = d;
+  c->cpar.tab[ch] = d;
+  c->cpar.tabn[ch] = n;
+  c->cpar.thr[ch] = thr;
+  c->cpar.dsq[ch] = dsq;
+  c->xs_thr[ch] = thr;
+  c->xs_set[ch] = true;
+  if (c->species_set) derive_pairs(c);
+  return PD_OK;
+}
+
+pd_status pd_inject(pd_ctx* c, int64_t n, const double* r, const double* z, const double* vr,
+                    const double* vt, const double* vz, const uint8_t* sp) {
+  if (!c) return PD_EINVAL;
+  if (c->poisoned) return set_err(c, PD_ESTATE, "context unusable after an earlier error");
+  if (n < 0) return set_err(c, PD_EINVAL, "n < 0");
+  pd_status s = check_particles(c, n, r, z, vr, vt, vz, sp);
+  if (s) return s;
+  if (n == 0) return PD_OK;
+  DevState h;
+  if ((s = read_state(c, &h))) return s;
+  if ((int64_t)h.n_total + n > c->cap) return set_err(c, PD_ECAPACITY, "capacity %lld", (long long)c->cap);
+  if ((int64_t)h.next_id + n > (int64_t)0xFFFFFFFFLL) return set_err(c, PD_ECAPACITY, "id space");
+  // stage through B's tail-free buffers: B is scratch between steps
+  Parts src = c->B;
+  HIPCHK(c, hipMemcpyAsync(src.r, r, 8 * n, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(src.z, z, 8 * n, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(src.vr, vr, 8 * n, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(src.vt, vt, 8 * n, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(src.vz, vz, 8 * n, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(src.sp, sp, n, hipMemcpyHostToDevice, c->stream));
+  append(c->A, c->st, c->g, src, (uint32_t)n, c->stream);
+  HIPCHK(c, hipGetLastError());
+  if ((s = sync(c))) return s;
+  for (int64_t p = 0; p < n; ++p) c->injected[sp[p]] += 1;
+  return PD_OK;
+}
+
+pd_status pd_schedule_injection(pd_ctx* c, int nsteps, const int64_t* offs, const double* r,
+                                const double* z, const double* vr, const double* vt,
+                                const double* vz, const uint8_t* sp) {
+  if (!c) return PD_EINVAL;
+  if (c->poisoned) return set_err(c, PD_ESTATE, "context unusable after an earlier error");
+  if (nsteps < 0 || (nsteps > 0 && !offs) || (nsteps > 0 && offs[0] != 0))
+    return set_err(c, PD_EINVAL, "bad schedule offsets");
+  int64_t maxc = 0;
+  for (int k = 0; k < nsteps; ++k) {
+    if (offs[k + 1] < offs[k]) return set_err(c, PD_EINVAL, "schedule offsets decrease");
+    maxc = std::max<int64_t>(maxc, offs[k + 1] - offs[k]);
+  }
+  const int64_t tot = nsteps ? offs[nsteps] : 0;
+  pd_status s = check_particles(c, tot, r, z, vr, vt, vz, sp);
+  if (s) return s;
+  if ((s = sync(c))) return s;
+  for (void* p : c->sched_allocs) (void)hipFree(p);
+  c->sched_allocs.clear();
+  c->sched = Schedule{};
+  c->sched_species.clear();
+  auto dup = [&](const void* h, size_t bytes) -> void* {
+    void* d = nullptr;
+    if (hipMalloc(&d, bytes ? bytes : 16) != hipSuccess) return nullptr;
+    c->sched_allocs.push_back(d);
+    if (bytes && hipMemcpy(d, h, bytes, hipMemcpyHostToDevice) != hipSuccess) return nullptr;
+    return d;
+  };
+  if (nsteps > 0) {
+    Schedule sc{};
+    sc.off = (const int64_t*)dup(offs, sizeof(int64_t) * (nsteps + 1));
+    sc.r = (const double*)dup(r, 8 * tot);
+    sc.z = (const double*)dup(z, 8 * tot);
+    sc.vr = (const double*)dup(vr, 8 * tot);
+    sc.vt = (const double*)dup(vt, 8 * tot);
+    sc.vz = (const double*)dup(vz, 8 * tot);
+    sc.sp = (const uint8_t*)dup(sp, tot);
+    sc.max_count = maxc;
+    if (!sc.off || !sc.r || !sc.z || !sc.vr || !sc.vt || !sc.vz || !sc.sp)
+      return set_err(c, PD_ENOMEM, "schedule upload failed");
+    c->sched = sc;
+    c->sched_species.resize(nsteps);
+    for (int k = 0; k < nsteps; ++k) {
+      std::array<int64_t, kNS> a{};
+      for (int64_t p = offs[k]; p < offs[k + 1]; ++p) a[sp[p]] += 1;
+      c->sched_species[k] = a;
+    }
+  }
+  c->sched_n = nsteps;
+  c->host_sched_pos = 0;
+  uint32_t v[2] = {0u, (uint32_t)nsteps};
+  HIPCHK(c, hipMemcpy((char*)c->st + offsetof(DevState, sched_pos), v, sizeof v,
+                      hipMemcpyHostToDevice));
+  return PD_OK;
+}
+
+pd_status pd_step(pd_ctx* c, int nsteps) {
+  if (!c) return PD_EINVAL;
+  if (c->poisoned) return set_err(c, PD_ESTATE, "context unusable after an earlier error");
+  if (nsteps < 0) return set_err(c, PD_EINVAL, "nsteps < 0");
+  if (!c->species_set) return set_err(c, PD_ESTATE, "species not set");
+  if (!c->opts.collisions_off)
+    for (int k = 0; k < kNC; ++k)
+      if (!c->xs_set[k]) return set_err(c, PD_ESTATE, "cross section %d not set", k);
+  hipStream_t s = c->stream;
+  const int64_t nn = (int64_t)(c->g.nr + 1) * (c->g.nz + 1);
+  for (int t = 0; t < nsteps; ++t) {
+    std::vector<hipEvent_t> ev;
+    auto mark = [&]() {
+      if (c->opts.timing) {
+        hipEvent_t e = get_event(c);
+        (void)hipEventRecord(e, s);
+        ev.push_back(e);
+      }
+    };
+    mark();
+    uint32_t *skeys, *perm;
+    sort_keys(c->A.key, c->key_bits, c->sw, c->st, &skeys, &perm, s);
+    mark();
+    gather_sorted(c->A, c->B, skeys, perm, c->st, c->g.sentinel, c->cap, s);
+    std::swap(c->A, c->B);
+    mark();
+    // the radix output holds every key, the absorbed ones (sentinel) included;
+    // the permuted payload skips those, so its key tail is not defined
+    build_offsets(skeys, c->st, c->off, c->g.sentinel + 1, s);
+    mark();
+    if (!c->opts.collisions_off)
+      collide(c->A, c->off, c->st, c->g, c->cpar, c->cw, c->sw.bsum, c->cap, s);
+    mark();
+    if (c->opts.deposit_off) fill_i64(c->fw.Q, 0, nn, s);
+    else deposit(c->A, c->st, c->g, c->spp, c->fw.Q, c->cap, s);
+    mark();
+    poisson_direct(c->g, c->fw, s);
+    mark();
+    field(c->g, c->fw, s);
+    mark();
+    push(c->A, c->st, c->g, c->spp, c->fw, c->cap, s);
+    mark();
+    inject_scheduled(c->A, c->st, c->g, c->sched, c->cap, s);
+    step_end(c->st, c->sched, s);
+    mark();
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+      c->poisoned = true;
+      return set_err(c, PD_EDEVICE, "launch failed: %s", hipGetErrorString(e));
+    }
+    if (c->host_sched_pos < c->sched_n) {
+      for (int k = 0; k < kNS; ++k) c->injected[k] += c->sched_species[c->host_sched_pos][k];
+      c->host_sched_pos += 1;
+    }
+    c->host_step += 1;
+    if (c->opts.timing) {
+      c->ev_pending.push_back(ev);
+      if (c->ev_pending.size() >= 512) {
+        pd_status st = sync(c);
+        if (st) return st;
+        harvest_timing(c);
+      }
+    }
+  }
+  return PD_OK;
+}
+
+pd_status pd_synchronize(pd_ctx* c) {
+  if (!c) return PD_EINVAL;
+  DevState h;
+  return read_state(c, &h);
+}
+
+static pd_status snapshot(pd_ctx* c, DevState& h, int64_t counts[kNS], double ke[kNS],
+                          int64_t spec[3][66]) {
+  pd_status s = read_state(c, &h);
+  if (s) return s;
+  HIPCHK(c, hipMemsetAsync(c->d_spec, 0, sizeof(unsigned long long) * 3 * 66, c->stream));
+  diag_snapshot(c->A, c->st, c->g, c->spp, c->d_edges, c->d_dcount, c->d_dke, c->d_spec, c->stream);
+  HIPCHK(c, hipGetLastError());
+  if ((s = sync(c))) return s;
+  std::vector<unsigned long long> hc((size_t)kDiagBlocks * kNS), hs(3 * 66);
+  std::vector<double> hk((size_t)kDiagBlocks * kNS);
+  HIPCHK(c, hipMemcpy(hc.data(), c->d_dcount, hc.size() * 8, hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(hk.data(), c->d_dke, hk.size() * 8, hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(hs.data(), c->d_spec, hs.size() * 8, hipMemcpyDeviceToHost));
+  for (int k = 0; k < kNS; ++k) {
+    counts[k] = 0;
+    ke[k] = 0.0;
+  }
+  for (int b = 0; b < kDiagBlocks; ++b)
+    for (int k = 0; k < kNS; ++k) {
+      counts[k] += (int64_t)hc[(size_t)b * kNS + k];
+      ke[k] += hk[(size_t)b * kNS + k];
+    }
+  for (int t = 0; t < 3; ++t)
+    for (int b = 0; b < 66; ++b) spec[t][b] = (int64_t)hs[t * 66 + b];
+  return PD_OK;
+}
+
+pd_status pd_get_diagnostics(pd_ctx* c, pd_diag* out) {
+  if (!c || !out) return PD_EINVAL;
+  DevState h;
+  int64_t counts[kNS];
+  double ke[kNS];
+  int64_t spec[3][66];
+  pd_status s = snapshot(c, h, counts, ke, spec);
+  if (s) return s;
+  std::memset(out, 0, sizeof *out);
+  out->step = c->host_step;
+  out->next_id = h.next_id;
+  int64_t n = 0;
+  for (int k = 0; k < kNS; ++k) {
+    out->count[k] = counts[k];
+    out->ke_J[k] = ke[k];
+    n += counts[k];
+    out->injected[k] = c->injected[k];
+    out->charge_alive += counts[k] * c->spp.Z[k];
+    out->charge_injected += c->injected[k] * c->spp.Z[k];
+  }
+  out->n_alive = n;
+  for (int k = 0; k < kNC; ++k) out->events[k] = (int64_t)h.events[k];
+  out->conflicts = (int64_t)h.conflicts;
+  out->particle_steps = (int64_t)h.pushed;
+  out->created = (int64_t)h.created;
+  for (int b = 0; b < 3; ++b)
+    for (int k = 0; k < kNS; ++k) {
+      out->absorbed[b][k] = (int64_t)h.absorbed[b * kNS + k];
+      out->charge_absorbed += out->absorbed[b][k] * c->spp.Z[k];
+    }
+  const double N0 = (double)counts[PD_CU], N1 = (double)counts[PD_CU1];
+  const double N2 = (double)(counts[PD_CU2_STEP] + counts[PD_CU2_DOUBLE] + counts[PD_CU2_INIT]);
+  out->gamma = (N0 + N1 + N2) > 0 ? (N1 + N2) / ((N0 + N1) + N2) : 0.0;
+  out->qbar = (N1 + N2) > 0 ? (N1 + (2.0 * N2)) / (N1 + N2) : 0.0;
+  return PD_OK;
+}
+
+pd_status pd_get_spectrum(pd_ctx* c, int tag, int64_t out[66]) {
+  if (!c || !out) return PD_EINVAL;
+  if (tag < 0 || tag > 2) return set_err(c, PD_EINVAL, "tag %d", tag);
+  DevState h;
+  int64_t counts[kNS];
+  double ke[kNS];
+  int64_t spec[3][66];
+  pd_status s = snapshot(c, h, counts, ke, spec);
+  if (s) return s;
+  for (int b = 0; b < 66; ++b) out[b] = spec[tag][b];
+  return PD_OK;
+}
+
+pd_status pd_get_count(pd_ctx* c, int64_t* n) {
+  if (!c || !n) return PD_EINVAL;
+  DevState h;
+  pd_status s = read_state(c, &h);
+  if (s) return s;
+  int64_t a = 0;
+  for (int k = 0; k < 3 * kNS; ++k) a += (int64_t)h.absorbed[k];
+  int64_t inj = 0;
+  for (int k = 0; k < kNS; ++k) inj += c->injected[k];
+  *n = inj + (int64_t)h.created - a;
+  return PD_OK;
+}
+
+pd_status pd_get_particles(pd_ctx* c, int64_t cap, double* r, double* z, double* vr, double* vt,
+                           double* vz, uint8_t* sp, uint32_t* id, uint32_t* key) {
+  if (!c) return PD_EINVAL;
+  DevState h;
+  pd_status s = read_state(c, &h);
+  if (s) return s;
+  const int64_t n = h.n_total;
+  std::vector<uint32_t> k(n);
+  HIPCHK(c, hipMemcpy(k.data(), c->A.key, 4 * n, hipMemcpyDeviceToHost));
+  int64_t alive = 0;
+  for (int64_t p = 0; p < n; ++p) alive += (k[p] != c->g.sentinel);
+  if (cap < alive) return set_err(c, PD_EINVAL, "cap %lld < %lld particles", (long long)cap,
+                                  (long long)alive);
+  auto pull = [&](auto* dst, const auto* src, size_t esz) -> pd_status {
+    if (!dst) return PD_OK;
+    std::vector<unsigned char> buf(esz * n);
+    HIPCHK(c, hipMemcpy(buf.data(), src, esz * n, hipMemcpyDeviceToHost));
+    int64_t w = 0;
+    for (int64_t p = 0; p < n; ++p)
+      if (k[p] != c->g.sentinel) std::memcpy((unsigned char*)dst + esz * (w++), &buf[esz * p], esz);
+    return PD_OK;
+  };
+  if ((s = pull(r, c->A.r, 8)) || (s = pull(z, c->A.z, 8)) || (s = pull(vr, c->A.vr, 8)) ||
+      (s = pull(vt, c->A.vt, 8)) || (s = pull(vz, c->A.vz, 8)) || (s = pull(sp, c->A.sp, 1)) ||
+      (s = pull(id, c->A.id, 4)) || (s = pull(key, c->A.key, 4)))
+    return s;
+  return PD_OK;
+}
+
+pd_status pd_get_field(pd_ctx* c, double* phi, double* Er, double* Ez, int64_t* Q) {
+  if (!c) return PD_EINVAL;
+  pd_status s = sync(c);
+  if (s) return s;
+  const size_t nn = (size_t)(c->g.nr + 1) * (c->g.nz + 1);
+  if (phi) HIPCHK(c, hipMemcpy(phi, c->fw.phi, 8 * nn, hipMemcpyDeviceToHost));
+  if (Er) HIPCHK(c, hipMemcpy(Er, c->fw.Er, 8 * nn, hipMemcpyDeviceToHost));
+  if (Ez) HIPCHK(c, hipMemcpy(Ez, c->fw.Ez, 8 * nn, hipMemcpyDeviceToHost));
+  if (Q) HIPCHK(c, hipMemcpy(Q, c->fw.Q, 8 * nn, hipMemcpyDeviceToHost));
+  return PD_OK;
+}
+
+pd_status pd_get_timing(pd_ctx* c, double* ms, int64_t* steps, int reset) {
+  if (!c) return PD_EINVAL;
+  if (!c->opts.timing) return set_err(c, PD_ESTATE, "timing was not enabled");
+  pd_status s = sync(c);
+  if (s) return s;
+  harvest_timing(c);
+  if (ms)
+    for (int k = 0; k < PD_NTIMERS; ++k) ms[k] = c->t_ms[k];
+  if (steps) *steps = c->t_steps;
+  if (reset) {
+    for (int k = 0; k < PD_NTIMERS; ++k) c->t_ms[k] = 0.0;
+    c->t_steps = 0;
+  }
+  return PD_OK;
+}
+
+const char* pd_last_error(const pd_ctx* c) { return c ? c->err.c_str() : g_create_err.c_str(); }
+
+void pd_destroy(pd_ctx* c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (auto& set : c->ev_pending)
+    for (auto e : set) (void)hipEventDestroy(e);
+  for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+  for (void* p : c->sched_allocs) (void)hipFree(p);
+  for (void* p : c->allocs) (void)hipFree(p);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+}  // extern "C"

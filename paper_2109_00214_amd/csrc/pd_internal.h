@@ -1,0 +1,148 @@
+// pd_internal.h -- device data layout and kernel launchers of the gfx950
+// PIC-DSMC library (internal; the public boundary is include/pd.h).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace pd {
+
+constexpr double kQE = 1.602176634e-19;    // elementary charge, C (CODATA 2018)
+constexpr double kEPS0 = 8.8541878128e-12; // vacuum permittivity, F/m
+constexpr double kPI = 3.14159265358979323846;
+constexpr int kNS = 6;                     // species
+constexpr int kNC = 4;                     // collision channels
+
+// Device-resident counters: every launch reads the particle counts from
+// here, so a step needs no host round trip and can be replayed as a graph.
+struct DevState {
+  uint32_t n_total;    // particles in the arrays at step start (dead ones included)
+  uint32_t n_alive;    // after the sort: particles with a live key
+  uint32_t n_created;  // electrons made by this step's collisions
+  uint32_t next_id;    // first unused id at step start
+  uint32_t step;       // step counter, the Philox counter word 2
+  uint32_t sched_pos;  // next injection-schedule slot
+  uint32_t sched_n;    // schedule length (steps)
+  uint32_t err;        // bit 0: capacity overflow
+  unsigned long long events[kNC];
+  unsigned long long conflicts;
+  unsigned long long created;
+  unsigned long long pushed;   // sum over steps of the particles pushed
+  unsigned long long absorbed[3 * kNS];
+};
+
+// Structure-of-arrays particle store (FP64 deterministic form).
+struct Parts {
+  double *r, *z, *vr, *vt, *vz;
+  uint8_t* sp;
+  uint32_t *id, *key;
+};
+
+struct Grid {
+  int nr, nz;
+  uint32_t C;         // cells nr*nz
+  uint32_t sentinel;  // key of an absorbed particle (= 6*C)
+  double dr, dz, R, L, V, dt;
+};
+
+struct SpeciesParams {
+  int Z[kNS];
+  double qmdt[kNS];   // ((Z e) / m) dt
+  double m[kNS];
+};
+
+struct CollideParams {
+  double W, dt;
+  uint32_t seed_lo, seed_hi;
+  int enable_di;
+  double ck[kNC];        // sqrt(m_r / (2 e)): relative speed -> sqrt(E/eV)
+  double thr[kNC];       // thresholds, eV
+  double dsq[kNC];       // table spacing in sqrt(E/eV), a power of two
+  double f1[kNC], f2[kNC];
+  double two_dE_mr[kNC]; // 2 (-E_th e) / m_r
+  const double* tab[kNC];
+  int tabn[kNC];
+  const double* Vcell;   // cell volumes [nr]
+};
+
+struct Schedule {
+  const int64_t* off;    // [n+1]
+  int64_t max_count;     // largest per-step count (launch size)
+  const double *r, *z, *vr, *vt, *vz;
+  const uint8_t* sp;
+};
+
+// ---- sort (k_sort.hip) ----
+constexpr int kSortBlock = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortBlock * kSortItems;  // 4096 keys per tile
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;
+constexpr int kScanChunk = 8192;                    // elements per scan block
+constexpr int kScanMaxBlocks = 16384;
+
+struct SortWork {
+  uint32_t *k0, *k1, *v0, *v1;  // key/value ping-pong [cap]
+  uint32_t* hist;               // [kRadix * tiles_cap]
+  uint32_t* bsum;               // [kScanMaxBlocks]
+  uint32_t* scan_len;           // device scalar
+  int64_t cap;
+};
+
+// Stable LSD radix sort of st->n_total keys; returns the buffer holding
+// the sorted keys (*skeys) and the permutation (*perm: sorted -> source).
+void sort_keys(const uint32_t* keys, int key_bits, SortWork& w, DevState* st,
+               uint32_t** skeys, uint32_t** perm, hipStream_t s);
+// Exclusive scan of *len u32 values (device length), total to *total.
+void scan_exclusive(const uint32_t* in, uint32_t* out, const uint32_t* len,
+                    uint32_t* total, uint32_t* bsum, int64_t max_len, hipStream_t s);
+void gather_sorted(const Parts& src, const Parts& dst, const uint32_t* skeys,
+                   const uint32_t* perm, const DevState* st, uint32_t sentinel,
+                   int64_t cap, hipStream_t s);
+void build_offsets(const uint32_t* skeys, DevState* st, uint32_t* off, uint32_t nkeys,
+                   hipStream_t s);
+
+// ---- collisions (k_collide.hip) ----
+struct CollideWork {
+  uint8_t* choice;
+  uint32_t *target, *claim, *ccount, *cbase, *scan_len;
+  int64_t cap;
+};
+void collide(const Parts& P, const uint32_t* off, DevState* st, const Grid& g,
+             const CollideParams& cp, CollideWork& w, uint32_t* bsum, int64_t cap,
+             hipStream_t s);
+
+// ---- particle-in-cell (k_pic.hip) ----
+struct FieldWork {
+  int64_t* Q;           // nodes
+  double *phi, *Er, *Ez;
+  double* f;            // [(nz-1) * (nr+1)] interior right-hand side
+  double* fh;           // [(nr+1) * (nz-1)] transformed, k fastest
+  const double* S;      // [(nz-1)^2] DST-I table, symmetric
+  const double* tinv;   // [(nr+1) * (nz-1)] Thomas reciprocals
+  const double* tcp;    // [(nr+1) * (nz-1)] Thomas upper factors
+  const double* ra;     // [nr+1] radial lower coefficients
+  const double* Vnode;  // [nr+1]
+  double qunit;
+};
+void deposit(const Parts& P, const DevState* st, const Grid& g, const SpeciesParams& sp,
+             int64_t* Q, int64_t cap, hipStream_t s);
+void poisson_direct(const Grid& g, FieldWork& fw, hipStream_t s);
+void field(const Grid& g, FieldWork& fw, hipStream_t s);
+void push(const Parts& P, DevState* st, const Grid& g, const SpeciesParams& sp,
+          const FieldWork& fw, int64_t cap, hipStream_t s);
+void inject_scheduled(const Parts& P, DevState* st, const Grid& g, const Schedule& sc,
+                      int64_t cap, hipStream_t s);
+void step_end(DevState* st, const Schedule& sc, hipStream_t s);
+void append(const Parts& P, DevState* st, const Grid& g, const Parts& src, uint32_t n,
+            hipStream_t s);
+// snapshot reductions: per-block partial counts, KE sums, spectrum bins
+constexpr int kDiagBlocks = 512;
+void diag_snapshot(const Parts& P, const DevState* st, const Grid& g, const SpeciesParams& sp,
+                   const double* edges, unsigned long long* counts /*[kDiagBlocks*6]*/,
+                   double* ke /*[kDiagBlocks*6]*/, unsigned long long* spec /*[3*66]*/,
+                   hipStream_t s);
+void fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
+void fill_i64(int64_t* p, int64_t v, int64_t n, hipStream_t s);
+
+}  // namespace pd

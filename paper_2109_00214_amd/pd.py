@@ -1,0 +1,262 @@
+"""Thin ctypes binding of the gfx950 PIC-DSMC library (include/pd.h).
+
+Argument marshalling only: the functions below carry the C names and pass
+host numpy arrays straight through; every step of the method runs in the
+library's HIP kernels.  There is no CPU fallback: if ``libpd.so`` is missing
+or no GPU is present, the calls raise.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpd.so")
+
+PD_OK, PD_EINVAL, PD_ENOMEM, PD_EDEVICE, PD_ESTATE, PD_ENOCONV, PD_ECAPACITY = 0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "PD_OK", -1: "PD_EINVAL", -2: "PD_ENOMEM", -3: "PD_EDEVICE", -4: "PD_ESTATE",
+                -5: "PD_ENOCONV", -6: "PD_ECAPACITY"}
+PD_FP64_DET = 0
+PD_POISSON_DIRECT64 = 0
+TIMER_NAMES = ("radix", "permute", "offsets", "collide", "deposit", "poisson", "field", "push",
+               "inject")
+EXPORTED = ("pd_create", "pd_set_species", "pd_set_cross_section", "pd_inject",
+            "pd_schedule_injection", "pd_step", "pd_synchronize", "pd_get_diagnostics",
+            "pd_get_spectrum", "pd_get_count", "pd_get_particles", "pd_get_field",
+            "pd_get_timing", "pd_last_error", "pd_destroy")
+
+
+class PdError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+class pd_domain(C.Structure):
+    _fields_ = [("nr", C.c_int32), ("nz", C.c_int32), ("R", C.c_double), ("L", C.c_double),
+                ("V_cathode", C.c_double), ("dt", C.c_double), ("weight", C.c_double),
+                ("seed", C.c_uint64), ("capacity", C.c_int64)]
+
+
+class pd_opts(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("poisson", C.c_int32), ("enable_di", C.c_int32),
+                ("deposit_off", C.c_int32), ("collisions_off", C.c_int32), ("timing", C.c_int32),
+                ("stream", C.c_void_p)]
+
+
+class pd_diag(C.Structure):
+    _fields_ = [("step", C.c_int64), ("n_alive", C.c_int64), ("next_id", C.c_int64),
+                ("count", C.c_int64 * 6), ("events", C.c_int64 * 4), ("conflicts", C.c_int64),
+                ("created", C.c_int64), ("absorbed", (C.c_int64 * 6) * 3),
+                ("injected", C.c_int64 * 6), ("charge_alive", C.c_int64),
+                ("charge_absorbed", C.c_int64), ("charge_injected", C.c_int64),
+                ("ke_J", C.c_double * 6), ("gamma", C.c_double), ("qbar", C.c_double),
+                ("particle_steps", C.c_int64)]
+
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load libpd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError("libpd.so not built (run __graft_entry__.build()): %s" % path)
+    lib = C.CDLL(path)
+    P = C.c_void_p
+    lib.pd_create.argtypes = [C.POINTER(pd_domain), C.POINTER(pd_opts), C.POINTER(C.c_void_p)]
+    lib.pd_set_species.argtypes = [P, C.c_int, P, P]
+    lib.pd_set_cross_section.argtypes = [P, C.c_int, C.c_double, C.c_int, C.c_double, P]
+    lib.pd_inject.argtypes = [P, C.c_int64] + [P] * 6
+    lib.pd_schedule_injection.argtypes = [P, C.c_int, P] + [P] * 6
+    lib.pd_step.argtypes = [P, C.c_int]
+    lib.pd_synchronize.argtypes = [P]
+    lib.pd_get_diagnostics.argtypes = [P, C.POINTER(pd_diag)]
+    lib.pd_get_spectrum.argtypes = [P, C.c_int, P]
+    lib.pd_get_count.argtypes = [P, C.POINTER(C.c_int64)]
+    lib.pd_get_particles.argtypes = [P, C.c_int64] + [P] * 8
+    lib.pd_get_field.argtypes = [P, P, P, P, P]
+    lib.pd_get_timing.argtypes = [P, P, C.POINTER(C.c_int64), C.c_int]
+    lib.pd_last_error.argtypes = [P]
+    lib.pd_last_error.restype = C.c_char_p
+    lib.pd_destroy.argtypes = [P]
+    lib.pd_destroy.restype = None
+    for name in EXPORTED:
+        if name not in ("pd_last_error", "pd_destroy"):
+            getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _check(ctx, status):
+    if status != PD_OK:
+        msg = load_library().pd_last_error(ctx)
+        raise PdError(status, msg.decode() if msg else "")
+
+
+# ---- functions with the C names (marshalling only) -------------------------
+def pd_create(dom, opts):
+    lib = load_library()
+    h = C.c_void_p()
+    _check(None, lib.pd_create(C.byref(dom), C.byref(opts), C.byref(h)))
+    return h
+
+
+def pd_set_species(ctx, Z, mass):
+    Z = np.ascontiguousarray(Z, np.int32)
+    m = np.ascontiguousarray(mass, np.float64)
+    _check(ctx, load_library().pd_set_species(ctx, len(Z), _ptr(Z), _ptr(m)))
+
+
+def pd_set_cross_section(ctx, channel, threshold_eV, dsqrtE, sigma):
+    s = np.ascontiguousarray(sigma, np.float64)
+    _check(ctx, load_library().pd_set_cross_section(ctx, channel, threshold_eV, len(s), dsqrtE,
+                                                    _ptr(s)))
+
+
+def _parts(p):
+    return [np.ascontiguousarray(p[k], np.float64) for k in ("r", "z", "vr", "vt", "vz")] + [
+        np.ascontiguousarray(p["sp"], np.uint8)]
+
+
+def pd_inject(ctx, parts):
+    a = _parts(parts)
+    _check(ctx, load_library().pd_inject(ctx, len(a[0]), *[_ptr(x) for x in a]))
+
+
+def pd_schedule_injection(ctx, offsets, parts):
+    off = np.ascontiguousarray(offsets, np.int64)
+    a = _parts(parts)
+    _check(ctx, load_library().pd_schedule_injection(ctx, len(off) - 1, _ptr(off),
+                                                     *[_ptr(x) for x in a]))
+
+
+def pd_step(ctx, nsteps=1):
+    _check(ctx, load_library().pd_step(ctx, nsteps))
+
+
+def pd_synchronize(ctx):
+    _check(ctx, load_library().pd_synchronize(ctx))
+
+
+def pd_get_diagnostics(ctx):
+    d = pd_diag()
+    _check(ctx, load_library().pd_get_diagnostics(ctx, C.byref(d)))
+    out = {}
+    for name, _ in pd_diag._fields_:
+        v = getattr(d, name)
+        out[name] = v if isinstance(v, (int, float)) else np.array(
+            [list(x) if not isinstance(x, (int, float)) else x for x in v])
+    return out
+
+
+def pd_get_spectrum(ctx, tag):
+    out = np.zeros(66, np.int64)
+    _check(ctx, load_library().pd_get_spectrum(ctx, tag, _ptr(out)))
+    return out
+
+
+def pd_get_count(ctx):
+    n = C.c_int64()
+    _check(ctx, load_library().pd_get_count(ctx, C.byref(n)))
+    return n.value
+
+
+def pd_get_particles(ctx):
+    n = pd_get_count(ctx)
+    out = {k: np.zeros(n, np.float64) for k in ("r", "z", "vr", "vt", "vz")}
+    out["sp"] = np.zeros(n, np.uint8)
+    out["id"] = np.zeros(n, np.uint32)
+    out["key"] = np.zeros(n, np.uint32)
+    _check(ctx, load_library().pd_get_particles(
+        ctx, n, *[_ptr(out[k]) for k in ("r", "z", "vr", "vt", "vz", "sp", "id", "key")]))
+    return out
+
+
+def pd_get_field(ctx, nr, nz):
+    nn = (nr + 1) * (nz + 1)
+    phi, Er, Ez = (np.zeros(nn) for _ in range(3))
+    Q = np.zeros(nn, np.int64)
+    _check(ctx, load_library().pd_get_field(ctx, _ptr(phi), _ptr(Er), _ptr(Ez), _ptr(Q)))
+    shp = (nz + 1, nr + 1)
+    return {"phi": phi.reshape(shp), "Er": Er.reshape(shp), "Ez": Ez.reshape(shp),
+            "Q": Q.reshape(shp)}
+
+
+def pd_get_timing(ctx, reset=False):
+    ms = np.zeros(len(TIMER_NAMES))
+    steps = C.c_int64()
+    _check(ctx, load_library().pd_get_timing(ctx, _ptr(ms), C.byref(steps), int(reset)))
+    return dict(zip(TIMER_NAMES, ms.tolist())), steps.value
+
+
+def pd_last_error(ctx):
+    msg = load_library().pd_last_error(ctx)
+    return msg.decode() if msg else ""
+
+
+def pd_destroy(ctx):
+    if ctx:
+        load_library().pd_destroy(ctx)
+
+
+# ---- convenience wrapper ----------------------------------------------------
+class Simulation:
+    """One context: the domain of a workload config plus species and tables."""
+
+    def __init__(self, cfg, capacity, tables, species, enable_di=None, deposit_off=False,
+                 collisions_off=False, timing=False, stream=None):
+        dom = pd_domain(cfg.nr, cfg.nz, cfg.R, cfg.L, cfg.V, cfg.dt, cfg.weight, cfg.seed,
+                        int(capacity))
+        di = cfg.enable_di if enable_di is None else enable_di
+        opts = pd_opts(PD_FP64_DET, PD_POISSON_DIRECT64, int(di), int(deposit_off),
+                       int(collisions_off), int(timing), stream)
+        self.cfg = cfg
+        self.h = pd_create(dom, opts)
+        pd_set_species(self.h, *species)
+        for ch, thr, dsq, sig in tables:
+            pd_set_cross_section(self.h, ch, thr, dsq, sig)
+
+    def inject(self, parts):
+        pd_inject(self.h, parts)
+
+    def schedule_injection(self, offsets, parts):
+        pd_schedule_injection(self.h, offsets, parts)
+
+    def step(self, n=1):
+        pd_step(self.h, n)
+
+    def synchronize(self):
+        pd_synchronize(self.h)
+
+    def diag(self):
+        return pd_get_diagnostics(self.h)
+
+    def spectrum(self, tag):
+        return pd_get_spectrum(self.h, tag)
+
+    def count(self):
+        return pd_get_count(self.h)
+
+    def particles(self):
+        return pd_get_particles(self.h)
+
+    def field(self):
+        return pd_get_field(self.h, self.cfg.nr, self.cfg.nz)
+
+    def timing(self, reset=False):
+        return pd_get_timing(self.h, reset)
+
+    def close(self):
+        if getattr(self, "h", None):
+            pd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()

@@ -1,0 +1,152 @@
+"""GPU parity: the HIP library (through the C-ABI) against the CPU oracle on
+the same seeded inputs.  FP64 deterministic mode: every particle value,
+key, id, node charge, potential and field value and every integer count
+must be bit-identical (kinetic-energy sums, whose summation order is free,
+to 1e-12 relative)."""
+import numpy as np
+import pytest
+
+from gpu_common import assert_same_state, gpu_sim, log, pair
+from paper_2109_00214_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _one(sp, r, z, vr, vt, vz):
+    return {"r": np.array([r]), "z": np.array([z]), "vr": np.array([vr]), "vt": np.array([vt]),
+            "vz": np.array([vz]), "sp": np.array([sp], np.uint8)}
+
+
+def test_single_electron_uniform_field():
+    log("case: single electron, vacuum field, tiny grid")
+    cfg = W.config("tiny")
+    a = (-W.QE) * (-cfg.V / cfg.L) / W.ME
+    p = _one(W.E, 0.3e-6, 0.05e-6, 0.0, 0.0, -a * cfg.dt / 2)
+    g, o = pair(cfg, parts=p, capacity=64, deposit_off=True, collisions_off=True, sched=False)
+    for s in range(1, 15):
+        g.step(1)
+        o.step(1)
+        assert_same_state(g, o, "step %d" % s)
+
+
+def test_empty_domain_steps():
+    log("case: empty domain")
+    cfg = W.config("tiny")
+    g = gpu_sim(cfg, 1024)
+    g.step(3)
+    d = g.diag()
+    assert d["n_alive"] == 0 and d["step"] == 3 and d["events"].sum() == 0
+    f = g.field()
+    j = np.arange(cfg.nz + 1)
+    assert np.array_equal(f["phi"][:, 0], (-cfg.V) + cfg.V * (j / cfg.nz))
+
+
+@pytest.mark.parametrize("n", [1, 63, 4095, 4097, 12289])
+def test_ragged_sizes_short_run(n):
+    log("case: ragged population n=%d" % n)
+    cfg = W.config("tiny", n_init=n)
+    g, o = pair(cfg, n_init=n, steps=4)
+    for s in range(1, 5):
+        g.step(1)
+        o.step(1)
+        assert_same_state(g, o, "n=%d step %d" % (n, s))
+
+
+def test_tiny_config_200_steps_bit_exact():
+    """32x64 cells, 50k particles, W = 100, seed 1, 200 steps."""
+    cfg = W.config("tiny")
+    log("case: tiny config, 200 steps")
+    g, o = pair(cfg, steps=cfg.steps)
+    done = 0
+    for target in (1, 2, 5, 20, 60, 120, 200):
+        g.step(target - done)
+        o.step(target - done)
+        done = target
+        p = assert_same_state(g, o, "step %d" % done)
+        log("  step %d ok: %d particles" % (done, len(p["r"])))
+    d = g.diag()
+    assert d["events"][W.DI] > 0 and d["events"][W.SI2] > 0
+    assert d["particle_steps"] > 200 * 30000
+
+
+def test_di_disabled_and_seed_dependence():
+    log("case: DI off, seed 7")
+    cfg = W.config("tiny", seed=7, enable_di=False)
+    g, o = pair(cfg, steps=30)
+    g.step(30)
+    o.step(30)
+    assert_same_state(g, o, "no-DI step 30")
+    assert g.diag()["events"][W.DI] == 0
+
+
+def test_dense_collisions_many_conflicts():
+    """Few targets per cell and many electrons: most trials collide and many
+    lose their target; ids and slots of new electrons must still match."""
+    log("case: dense constant-sigma collisions")
+    cfg = W.config("tiny", nr=8, nz=16, weight=1e6, V=500.0)
+    tables = W.constant_tables((3e-19, 2e-19, 1e-19, 2e-19), thresholds=(0, 7.73, 28.0, 20.29),
+                               n=2048)
+    g, o = pair(cfg, n_init=20000, steps=10, tables=tables)
+    for s in range(1, 11):
+        g.step(1)
+        o.step(1)
+        assert_same_state(g, o, "dense step %d" % s)
+    d = g.diag()
+    assert d["conflicts"] > 100 and d["events"].min() > 10
+
+
+def test_gpu_runs_are_deterministic():
+    log("case: determinism")
+    cfg = W.config("tiny")
+    runs = []
+    for _ in range(2):
+        g = gpu_sim(cfg, 200_000)
+        g.inject(W.initial_population(cfg))
+        off, inj = W.injection_schedule(cfg, 40)
+        g.schedule_injection(off, inj)
+        g.step(40)
+        runs.append(g.particles())
+        g.close()
+    for k in runs[0]:
+        assert np.array_equal(runs[0][k], runs[1][k]), k
+
+
+def test_errors_leave_state_unchanged():
+    from paper_2109_00214_amd.pd import PdError, PD_EINVAL, PD_ECAPACITY
+    log("case: error paths")
+    cfg = W.config("tiny")
+    g = gpu_sim(cfg, 100)
+    p = _one(W.E, 0.1e-6, 0.1e-6, 0.0, 0.0, 0.0)
+    bad = dict(p)
+    bad["vz"] = np.array([np.nan])
+    with pytest.raises(PdError) as e:
+        g.inject(bad)
+    assert e.value.status == PD_EINVAL
+    far = dict(p)
+    far["z"] = np.array([cfg.L])
+    with pytest.raises(PdError):
+        g.inject(far)
+    assert g.count() == 0
+    many = {k: np.repeat(v, 101) for k, v in p.items()}
+    with pytest.raises(PdError) as e:
+        g.inject(many)
+    assert e.value.status == PD_ECAPACITY
+    assert g.count() == 0
+    g.inject(p)
+    assert g.count() == 1
+
+
+def test_capacity_overflow_on_device_is_reported():
+    """Injection beyond capacity inside pd_step: the device sets the error
+    flag, the kernels write nothing out of bounds, and the next
+    synchronising call reports PD_ECAPACITY."""
+    from paper_2109_00214_amd.pd import PdError, PD_ECAPACITY
+    log("case: device capacity overflow")
+    cfg = W.config("tiny", inj_e=50, inj_cu=0)
+    g = gpu_sim(cfg, 120, collisions_off=True)
+    off, inj = W.injection_schedule(cfg, 5)
+    g.schedule_injection(off, inj)
+    g.step(5)
+    with pytest.raises(PdError) as e:
+        g.synchronize()
+    assert e.value.status == PD_ECAPACITY
