@@ -29,23 +29,59 @@ __device__ inline void cell_of(const Grid& g, double r, double z, int& i, int& j
 // ---------------------------------------------------------------------------
 // deposit: weights rounded to 2^-20 per dimension, complementary, so each
 // particle adds exactly Z * 2^40 to the four nodes of its cell
+// The particles are sorted by (species, cell), so neighbouring lanes mostly
+// share a cell: each wave sums the contributions of every run of equal cells
+// (a segmented suffix sum over the lanes) and only the first lane of a run
+// issues the four int64 atomics.  Integer addition is associative, so the
+// node charges do not depend on this grouping.  Waves holding only neutral
+// particles (the long Cu run of the species-major order) read the species
+// byte and nothing else.  (The Cu run cannot be skipped by offsets alone:
+// collisions ionize targets inside it in place.)
 __global__ void __launch_bounds__(256) k_deposit(Parts P, const DevState* st, Grid g,
                                                  SpeciesParams spp, unsigned long long* Q) {
   const uint32_t n = st->n_alive + st->n_created;
   const int W = g.nr + 1;
-  for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
-    int i, j;
-    double fr, fz;
-    cell_of(g, P.r[p], P.z[p], i, j, fr, fz);
-    const int64_t ar = (int64_t)floor((fr * 1048576.0) + 0.5), br = 1048576 - ar;
-    const int64_t az = (int64_t)floor((fz * 1048576.0) + 0.5), bz = 1048576 - az;
-    const int64_t Zp = spp.Z[P.sp[p]];
-    if (Zp == 0) continue;
-    const int b = j * W + i;
-    atomicAdd(&Q[b], (unsigned long long)(Zp * (br * bz)));
-    atomicAdd(&Q[b + 1], (unsigned long long)(Zp * (ar * bz)));
-    atomicAdd(&Q[b + W], (unsigned long long)(Zp * (br * az)));
-    atomicAdd(&Q[b + W + 1], (unsigned long long)(Zp * (ar * az)));
+  const int lane = threadIdx.x & 63;
+  const uint64_t upto = (lane == 63) ? 0ull : (~0ull << (lane + 1));  // lanes above this one
+  for (uint32_t q0 = blockIdx.x * blockDim.x; q0 < n; q0 += gridDim.x * blockDim.x) {
+    const uint32_t p = q0 + threadIdx.x;
+    const long long Zp = (p < n) ? spp.Z[P.sp[p]] : 0;
+    if (!__ballot(Zp != 0)) continue;
+    int b = -1;
+    long long v0 = 0, v1 = 0, v2 = 0, v3 = 0;
+    if (Zp != 0) {
+      int i, j;
+      double fr, fz;
+      cell_of(g, P.r[p], P.z[p], i, j, fr, fz);
+      const long long ar = (long long)floor((fr * 1048576.0) + 0.5), br = 1048576 - ar;
+      const long long az = (long long)floor((fz * 1048576.0) + 0.5), bz = 1048576 - az;
+      b = j * W + i;
+      v0 = Zp * (br * bz);
+      v1 = Zp * (ar * bz);
+      v2 = Zp * (br * az);
+      v3 = Zp * (ar * az);
+    }
+    const int bprev = __shfl_up(b, 1, 64);
+    const bool head = (lane == 0) || (b != bprev);
+    const uint64_t later = __ballot(head) & upto;
+    const int end = later ? (__ffsll((long long)later) - 1) : 64;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const long long t0 = __shfl_down(v0, o, 64), t1 = __shfl_down(v1, o, 64);
+      const long long t2 = __shfl_down(v2, o, 64), t3 = __shfl_down(v3, o, 64);
+      if (lane + o < end) {
+        v0 += t0;
+        v1 += t1;
+        v2 += t2;
+        v3 += t3;
+      }
+    }
+    if (head && b >= 0) {
+      if (v0) atomicAdd(&Q[b], (unsigned long long)v0);
+      if (v1) atomicAdd(&Q[b + 1], (unsigned long long)v1);
+      if (v2) atomicAdd(&Q[b + W], (unsigned long long)v2);
+      if (v3) atomicAdd(&Q[b + W + 1], (unsigned long long)v3);
+    }
   }
 }
 
@@ -66,86 +102,12 @@ void fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
   k_fill_u32<<<grid_for(n), 256, 0, s>>>(p, v, n);
 }
 
-void deposit(const Parts& P, const DevState* st, const Grid& g, const SpeciesParams& sp,
-             int64_t* Q, int64_t cap, hipStream_t s) {
+void deposit(const Parts& P, const DevState* st, const uint32_t* off, const Grid& g,
+             const SpeciesParams& sp, int64_t* Q, int64_t cap, hipStream_t s) {
   const int64_t nn = (int64_t)(g.nr + 1) * (g.nz + 1);
   fill_i64(Q, 0, nn, s);
+  (void)off;
   k_deposit<<<grid_for(cap), 256, 0, s>>>(P, st, g, sp, (unsigned long long*)Q);
-}
-
-// ---------------------------------------------------------------------------
-// Poisson: f = -rho/eps0 on the interior rows, rho = Q qunit / V_node
-__global__ void __launch_bounds__(256) k_rhs(const int64_t* Q, const double* Vnode, double qunit,
-                                             int nr, int nz, double* f) {
-  const int W = nr + 1;
-  const int n = (nz - 1) * W;
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
-    const int i = t % W;
-    const double rho = ((double)Q[t + W] * qunit) / Vnode[i];
-    f[t] = -(rho / kEPS0);
-  }
-}
-
-// forward DST-I over the interior z nodes: fh[i][k] = sum_j f[j][i] S[k][j]
-__global__ void __launch_bounds__(256) k_dst_fwd(const double* f, const double* S, int nr, int nz,
-                                                 double* fh) {
-  const int M = nz - 1, W = nr + 1;
-  const int n = W * M;
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
-    const int k = t % M, i = t / M;
-    double acc = 0.0;
-    for (int j = 0; j < M; ++j) acc = acc + (f[j * W + i] * S[j * M + k]);
-    fh[t] = acc;
-  }
-}
-
-// Thomas per mode with the host-factored reciprocals: in place on fh
-__global__ void __launch_bounds__(256) k_thomas(double* fh, const double* tinv, const double* tcp,
-                                                const double* ra, int nr, int nz) {
-  const int M = nz - 1;
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= M) return;
-  double dp = fh[k] * tinv[k];
-  fh[k] = dp;
-  for (int i = 1; i <= nr; ++i) {
-    const int q = i * M + k;
-    dp = (fh[q] - (ra[i] * dp)) * tinv[q];
-    fh[q] = dp;
-  }
-  double x = dp;
-  for (int i = nr - 1; i >= 0; --i) {
-    const int q = i * M + k;
-    x = fh[q] - (tcp[q] * x);
-    fh[q] = x;
-  }
-}
-
-// inverse DST-I and the vacuum potential
-__global__ void __launch_bounds__(256) k_dst_inv(const double* gh, const double* S, int nr, int nz,
-                                                 double V, double* phi) {
-  const int M = nz - 1, W = nr + 1;
-  const int n = (nz + 1) * W;
-  const double scale = 2.0 / (double)nz;
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
-    const int j = t % (nz + 1), i = t / (nz + 1);
-    const double vac = (-V) + (V * ((double)j / (double)nz));
-    double pp = 0.0;
-    if (j > 0 && j < nz) {
-      double acc = 0.0;
-      const double* grow = gh + (size_t)i * M;
-      for (int k = 0; k < M; ++k) acc = acc + (grow[k] * S[k * M + (j - 1)]);
-      pp = acc * scale;
-    }
-    phi[j * W + i] = vac + pp;
-  }
-}
-
-void poisson_direct(const Grid& g, FieldWork& fw, hipStream_t s) {
-  const int nr = g.nr, nz = g.nz, M = nz - 1, W = nr + 1;
-  k_rhs<<<grid_for((int64_t)M * W), 256, 0, s>>>(fw.Q, fw.Vnode, fw.qunit, nr, nz, fw.f);
-  k_dst_fwd<<<grid_for((int64_t)M * W), 256, 0, s>>>(fw.f, fw.S, nr, nz, fw.fh);
-  k_thomas<<<(M + 255) / 256, 256, 0, s>>>(fw.fh, fw.tinv, fw.tcp, fw.ra, nr, nz);
-  k_dst_inv<<<grid_for((int64_t)(nz + 1) * W), 256, 0, s>>>(fw.fh, fw.S, nr, nz, g.V, fw.phi);
 }
 
 // E = -grad(phi): central differences, second-order one-sided at the

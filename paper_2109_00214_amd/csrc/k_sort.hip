@@ -1,19 +1,25 @@
 // k_sort.hip -- per-cell particle lists: stable LSD radix sort of the
-// (species, cell) keys, CSR offsets, and the payload permutation.
+// (species, cell) keys, the payload permutation and the CSR offsets.
 //
 // The pairing of DSMC collisions needs the particles of every cell (paper
 // Sec. 2.1: a projectile and a target are chosen in the same cell each
 // step).  Keys are species-major: key = species * nr * nz + j * nr + i; an
 // absorbed particle carries the sentinel 6 * nr * nz and sorts last.
 //
-// Radix pass = upsweep (per-tile digit histogram, LDS atomics) -> exclusive
-// scan of the digit-major histogram -> downsweep.  The downsweep ranks keys
-// stably with wave ballots: the lanes holding equal digits are found with
-// one ballot per digit bit, the rank inside the wave is a popcount under
-// the lane mask, and a per-wave LDS counter per digit carries the rank
-// across the 16 iterations of a wave's contiguous 1024-key chunk; a
-// cross-wave prefix per digit then fixes the order between the four waves.
-// No spin waits anywhere: every kernel finishes for any input.
+// A pass over a digit of D <= 11 bits:
+//   up   -- per-tile digit histogram (LDS atomics), digit-major in memory;
+//   scan -- exclusive scan of that histogram: global start of every
+//           (digit, tile) run;
+//   down -- stable ranking inside the tile: each wave walks its contiguous
+//           1024 keys 64 at a time, finds the lanes holding the same digit
+//           with one ballot per digit bit, ranks by popcount under the lane
+//           mask and carries a per-wave count per digit in LDS; a prefix
+//           over waves and digits then places every key at its tile-local
+//           sorted position in LDS, and the tile is written out in that
+//           order, so the stores of one digit run are contiguous.
+// The particle records then move once, gathered by the source index with
+// contiguous stores.  No kernel waits on another block: every launch
+// finishes for any input.
 #include "pd_internal.h"
 
 namespace pd {
@@ -31,7 +37,7 @@ __device__ inline uint32_t block_scan256(uint32_t v, uint32_t* total, uint32_t* 
   uint32_t x = v;
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
-    uint32_t y = __shfl_up(x, o, 64);
+    const uint32_t y = __shfl_up(x, o, 64);
     if (lane >= o) x += y;
   }
   if (lane == 63) sh[wid] = x;
@@ -39,7 +45,7 @@ __device__ inline uint32_t block_scan256(uint32_t v, uint32_t* total, uint32_t* 
   uint32_t wbase = 0, tot = 0;
 #pragma unroll
   for (int w = 0; w < 4; ++w) {
-    uint32_t t = sh[w];
+    const uint32_t t = sh[w];
     wbase += (w < wid) ? t : 0u;
     tot += t;
   }
@@ -48,42 +54,41 @@ __device__ inline uint32_t block_scan256(uint32_t v, uint32_t* total, uint32_t* 
   return wbase + x - v;
 }
 
-__global__ void __launch_bounds__(256) k_scan_reduce(const uint32_t* in, const uint32_t* len_p,
-                                                     uint32_t* bsum) {
+// ---------------------------------------------------------------------------
+// exclusive scan of *len_p u32 values; chunks of kScanChunk = 256 x 8
+constexpr int kScanPer = kScanChunk / 256;
+
+__global__ void __launch_bounds__(256) k_scan_reduce(const uint32_t* __restrict__ in,
+                                                     const uint32_t* len_p,
+                                                     uint32_t* __restrict__ bsum) {
   __shared__ uint32_t sh[4];
   const uint32_t len = *len_p;
   const uint32_t nb = (len + kScanChunk - 1) / kScanChunk;
   if (blockIdx.x >= nb) return;
-  const uint32_t base = blockIdx.x * kScanChunk;
+  const uint32_t base = blockIdx.x * kScanChunk + threadIdx.x * kScanPer;
   uint32_t acc = 0;
-  for (int it = 0; it < kScanChunk / 256; ++it) {
-    uint32_t idx = base + it * 256 + threadIdx.x;
-    acc += (idx < len) ? in[idx] : 0u;
-  }
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) acc += (base + k < len) ? in[base + k] : 0u;
   uint32_t tot;
   block_scan256(acc, &tot, sh);
   if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
 }
 
-// exclusive scan of the block sums (<= 16384 of them) by one 1024-thread block
+// exclusive scan of the block sums by one 1024-thread block (<= 65536 sums)
 __global__ void __launch_bounds__(1024) k_scan_bsums(uint32_t* bsum, const uint32_t* len_p,
                                                      uint32_t* total) {
   __shared__ uint32_t sh[16];
   const uint32_t len = *len_p;
   const uint32_t nb = (len + kScanChunk - 1) / kScanChunk;
   const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
-  uint32_t v[16];
+  const uint32_t per = (nb + 1023) / 1024;
+  const uint32_t b0 = t * per;
   uint32_t s = 0;
-#pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    uint32_t idx = t * 16 + k;
-    v[k] = (idx < nb) ? bsum[idx] : 0u;
-    s += v[k];
-  }
+  for (uint32_t k = 0; k < per; ++k) s += (b0 + k < nb) ? bsum[b0 + k] : 0u;
   uint32_t x = s;
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
-    uint32_t y = __shfl_up(x, o, 64);
+    const uint32_t y = __shfl_up(x, o, 64);
     if (lane >= o) x += y;
   }
   if (lane == 63) sh[wid] = x;
@@ -94,30 +99,37 @@ __global__ void __launch_bounds__(1024) k_scan_bsums(uint32_t* bsum, const uint3
     tot += sh[w];
   }
   uint32_t run = wbase + x - s;
-#pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    uint32_t idx = t * 16 + k;
-    if (idx < nb) bsum[idx] = run;
-    run += v[k];
+  for (uint32_t k = 0; k < per; ++k) {
+    if (b0 + k < nb) {
+      const uint32_t v = bsum[b0 + k];
+      bsum[b0 + k] = run;
+      run += v;
+    }
   }
   if (t == 0 && total) *total = tot;
 }
 
 __global__ void __launch_bounds__(256) k_scan_down(const uint32_t* in, uint32_t* out,
-                                                   const uint32_t* len_p, const uint32_t* bsum) {
+                                                   const uint32_t* len_p,
+                                                   const uint32_t* __restrict__ bsum) {
   __shared__ uint32_t sh[4];
   const uint32_t len = *len_p;
   const uint32_t nb = (len + kScanChunk - 1) / kScanChunk;
   if (blockIdx.x >= nb) return;
-  uint32_t run = bsum[blockIdx.x];
-  const uint32_t base = blockIdx.x * kScanChunk;
-  for (int it = 0; it < kScanChunk / 256; ++it) {
-    uint32_t idx = base + it * 256 + threadIdx.x;
-    uint32_t v = (idx < len) ? in[idx] : 0u;
-    uint32_t tot;
-    uint32_t ex = block_scan256(v, &tot, sh);
-    if (idx < len) out[idx] = run + ex;
-    run += tot;
+  const uint32_t base = blockIdx.x * kScanChunk + threadIdx.x * kScanPer;
+  uint32_t v[kScanPer];
+  uint32_t acc = 0;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    v[k] = (base + k < len) ? in[base + k] : 0u;
+    acc += v[k];
+  }
+  uint32_t tot;
+  uint32_t run = bsum[blockIdx.x] + block_scan256(acc, &tot, sh);
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    if (base + k < len) out[base + k] = run;
+    run += v[k];
   }
 }
 
@@ -131,139 +143,235 @@ void scan_exclusive(const uint32_t* in, uint32_t* out, const uint32_t* len, uint
 }
 
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_radix_up(const uint32_t* keys, const DevState* st,
-                                                  int shift, uint32_t* hist, uint32_t* scan_len) {
-  __shared__ uint32_t h[kRadix];
-  const uint32_t n = st->n_total;
-  const uint32_t ntiles = (n + kSortTile - 1) / kSortTile;
-  if (blockIdx.x == 0 && threadIdx.x == 0) *scan_len = kRadix * ntiles;
-  if (blockIdx.x >= ntiles) return;
-  h[threadIdx.x] = 0;
-  __syncthreads();
-  const uint32_t base = blockIdx.x * kSortTile;
-#pragma unroll 4
-  for (int it = 0; it < kSortItems; ++it) {
-    uint32_t idx = base + it * kSortBlock + threadIdx.x;
-    if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & (kRadix - 1)], 1u);
+// Stable digit ranking of 64 keys held one per lane: the lanes with the same
+// digit are found with one ballot per digit bit; returns the rank of this
+// lane among them and their number.
+__device__ inline uint32_t match_rank(uint32_t d, bool valid, int dbits, uint64_t lt,
+                                      uint32_t* cnt) {
+  uint64_t peers = __ballot(valid);
+  for (int b = 0; b < dbits; ++b) {
+    const bool bit = (d >> b) & 1u;
+    const uint64_t m = __ballot(bit);
+    peers &= bit ? m : ~m;
   }
-  __syncthreads();
-  hist[threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+  *cnt = (uint32_t)__popcll(peers);
+  return (uint32_t)__popcll(peers & lt);
 }
 
-__global__ void __launch_bounds__(256) k_radix_down(const uint32_t* kin, const uint32_t* vin,
-                                                    uint32_t* kout, uint32_t* vout,
-                                                    const DevState* st, int shift,
-                                                    const uint32_t* hist) {
-  __shared__ uint32_t wh[4][kRadix];
+// per-tile digit histogram: each wave counts its contiguous 1024 keys with
+// one LDS update per distinct digit of every 64 keys (no atomics)
+template <int RB>
+__global__ void __launch_bounds__(256) k_radix_up(const uint32_t* __restrict__ keys,
+                                                  const DevState* st, int shift, int dbits,
+                                                  uint32_t* __restrict__ hist,
+                                                  uint32_t* __restrict__ scan_len) {
+  constexpr int R = 1 << RB;
+  __shared__ uint32_t wh[4][R];
+  const uint32_t n = st->n_total;
+  const uint32_t ntiles = (n + kSortTile - 1) / kSortTile;
+  const int nbins = 1 << dbits;
+  const uint32_t mask = (uint32_t)nbins - 1u;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *scan_len = (uint32_t)nbins * ntiles;
+  if (blockIdx.x >= ntiles) return;
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  for (int d = t; d < nbins; d += 256) wh[0][d] = wh[1][d] = wh[2][d] = wh[3][d] = 0;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const uint32_t base = blockIdx.x * kSortTile + w * (kSortTile / 4);
+  uint32_t kk[kSortItems];
+#pragma unroll
+  for (int it = 0; it < kSortItems; ++it) {
+    const uint32_t idx = base + it * 64 + lane;
+    kk[it] = (idx < n) ? keys[idx] : 0u;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < kSortItems; ++it) {
+    const bool valid = base + it * 64 + lane < n;
+    const uint32_t d = (kk[it] >> shift) & mask;
+    uint32_t c;
+    const uint32_t r = match_rank(d, valid, dbits, lt, &c);
+    if (valid && r == 0) wh[w][d] += c;
+  }
+  __syncthreads();
+  for (int d = t; d < nbins; d += 256)
+    hist[(size_t)d * ntiles + blockIdx.x] = wh[0][d] + wh[1][d] + wh[2][d] + wh[3][d];
+}
+
+template <int RB>
+__global__ void __launch_bounds__(256) k_radix_down(const uint32_t* __restrict__ kin,
+                                                    const uint32_t* __restrict__ vin,
+                                                    uint32_t* __restrict__ kout,
+                                                    uint32_t* __restrict__ vout,
+                                                    const DevState* st, int shift, int dbits,
+                                                    const uint32_t* __restrict__ hist) {
+  constexpr int R = 1 << RB;
+  __shared__ uint32_t wh[4][R];
+  __shared__ uint32_t gofs[R];
+  __shared__ uint32_t tkey[kSortTile];
+  __shared__ uint32_t tval[kSortTile];
+  __shared__ uint32_t sh[4];
   const uint32_t n = st->n_total;
   const uint32_t ntiles = (n + kSortTile - 1) / kSortTile;
   if (blockIdx.x >= ntiles) return;
+  const int nbins = 1 << dbits;
+  const uint32_t mask = (uint32_t)nbins - 1u;
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
-  const uint32_t gb = hist[t * ntiles + blockIdx.x];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) wh[q][t] = 0;
-  __syncthreads();
+  for (int d = t; d < nbins; d += 256) wh[0][d] = wh[1][d] = wh[2][d] = wh[3][d] = 0;
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const uint32_t base = blockIdx.x * kSortTile + w * (kSortTile / 4);
+  const uint32_t tile0 = blockIdx.x * kSortTile;
+  const uint32_t base = tile0 + w * (kSortTile / 4);
   uint32_t kk[kSortItems], vv[kSortItems], rk[kSortItems];
 #pragma unroll
   for (int it = 0; it < kSortItems; ++it) {
     const uint32_t idx = base + it * 64 + lane;
     const bool valid = idx < n;
-    const uint32_t k = valid ? kin[idx] : 0u;
-    const uint32_t v = valid ? (vin ? vin[idx] : idx) : 0u;
-    const uint32_t d = (k >> shift) & (kRadix - 1);
-    uint64_t peers = __ballot(valid);
+    kk[it] = valid ? kin[idx] : 0u;
+    vv[it] = valid ? (vin ? vin[idx] : idx) : 0u;
+  }
+  __syncthreads();
 #pragma unroll
-    for (int b = 0; b < kRadixBits; ++b) {
-      const bool bit = (d >> b) & 1u;
-      const uint64_t m = __ballot(bit);
-      peers &= bit ? m : ~m;
-    }
-    const uint32_t r = (uint32_t)__popcll(peers & lt);
+  for (int it = 0; it < kSortItems; ++it) {
+    const bool valid = base + it * 64 + lane < n;
+    const uint32_t d = (kk[it] >> shift) & mask;
+    uint32_t c;
+    const uint32_t r = match_rank(d, valid, dbits, lt, &c);
     const uint32_t old = wh[w][d];
-    if (valid && r == 0) wh[w][d] = old + (uint32_t)__popcll(peers);
-    kk[it] = k;
-    vv[it] = v;
+    if (valid && r == 0) wh[w][d] = old + c;
     rk[it] = old + r;
   }
   __syncthreads();
+  // tile-local start of every digit (prefix over digits of the tile counts),
+  // the start of each wave's share, and global minus local start
   {
-    const uint32_t a0 = wh[0][t], a1 = wh[1][t], a2 = wh[2][t];
-    wh[0][t] = gb;
-    wh[1][t] = gb + a0;
-    wh[2][t] = gb + a0 + a1;
-    wh[3][t] = gb + a0 + a1 + a2;
+    constexpr int PER = (R + 255) / 256;
+    uint32_t cnt[PER];
+    uint32_t s = 0;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int d = t * PER + q;
+      cnt[q] = (d < nbins) ? (wh[0][d] + wh[1][d] + wh[2][d] + wh[3][d]) : 0u;
+      s += cnt[q];
+    }
+    uint32_t tot;
+    uint32_t run = block_scan256(s, &tot, sh);
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int d = t * PER + q;
+      if (d < nbins) {
+        const uint32_t a0 = wh[0][d], a1 = wh[1][d], a2 = wh[2][d];
+        gofs[d] = hist[(size_t)d * ntiles + blockIdx.x] - run;
+        wh[0][d] = run;
+        wh[1][d] = run + a0;
+        wh[2][d] = run + a0 + a1;
+        wh[3][d] = run + a0 + a1 + a2;
+      }
+      run += cnt[q];
+    }
   }
   __syncthreads();
 #pragma unroll
   for (int it = 0; it < kSortItems; ++it) {
     const uint32_t idx = base + it * 64 + lane;
     if (idx < n) {
-      const uint32_t d = (kk[it] >> shift) & (kRadix - 1);
-      const uint32_t dst = wh[w][d] + rk[it];
-      kout[dst] = kk[it];
-      vout[dst] = vv[it];
+      const uint32_t lp = wh[w][(kk[it] >> shift) & mask] + rk[it];
+      tkey[lp] = kk[it];
+      tval[lp] = vv[it];
+    }
+  }
+  __syncthreads();
+  const uint32_t cnt = (n - tile0 < (uint32_t)kSortTile) ? (n - tile0) : (uint32_t)kSortTile;
+#pragma unroll 4
+  for (uint32_t q = t; q < cnt; q += 256) {
+    const uint32_t k = tkey[q];
+    const uint32_t p = gofs[(k >> shift) & mask] + q;
+    kout[p] = k;
+    vout[p] = tval[q];
+  }
+}
+
+// payload permutation: dst[p] = src[perm[p]] for the live particles; every
+// sorted key (the sentinel ones included) goes to dst.key
+constexpr int kGatherPer = 4;
+__global__ void __launch_bounds__(256) k_gather(Parts src, Parts dst,
+                                                const uint32_t* __restrict__ skeys,
+                                                const uint32_t* __restrict__ perm,
+                                                const DevState* st, uint32_t sentinel) {
+  const uint32_t n = st->n_total;
+  const uint32_t stride = gridDim.x * blockDim.x * kGatherPer;
+  for (uint32_t p0 = blockIdx.x * blockDim.x * kGatherPer + threadIdx.x; p0 < n; p0 += stride) {
+    uint32_t k[kGatherPer], q[kGatherPer];
+#pragma unroll
+    for (int u = 0; u < kGatherPer; ++u) {
+      const uint32_t p = p0 + u * blockDim.x;
+      k[u] = (p < n) ? skeys[p] : sentinel;
+      q[u] = (p < n) ? perm[p] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < kGatherPer; ++u) {
+      const uint32_t p = p0 + u * blockDim.x;
+      if (p >= n) continue;
+      dst.key[p] = k[u];
+      if (k[u] == sentinel) continue;
+      const uint32_t s = q[u];
+      dst.r[p] = src.r[s];
+      dst.z[p] = src.z[s];
+      dst.vr[p] = src.vr[s];
+      dst.vt[p] = src.vt[s];
+      dst.vz[p] = src.vz[s];
+      dst.sp[p] = src.sp[s];
+      dst.id[p] = src.id[s];
     }
   }
 }
 
-void sort_keys(const uint32_t* keys, int key_bits, SortWork& w, DevState* st, uint32_t** skeys,
-               uint32_t** perm, hipStream_t s) {
+template <int RB>
+static void radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
+                       int shift, int dbits, SortWork& w, DevState* st, int g, hipStream_t s) {
+  k_radix_up<RB><<<g, 256, 0, s>>>(kin, st, shift, dbits, w.hist, w.scan_len);
+  scan_exclusive(w.hist, w.hist, w.scan_len, nullptr, w.bsum, (int64_t)(1 << dbits) * g, s);
+  k_radix_down<RB><<<g, 256, 0, s>>>(kin, vin, kout, vout, st, shift, dbits, w.hist);
+}
+
+void sort_particles(const Parts& src, const Parts& dst, int key_bits, SortWork& w, DevState* st,
+                    uint32_t sentinel, int part, hipStream_t s) {
   const int tiles_cap = (int)((w.cap + kSortTile - 1) / kSortTile);
   const int g = tiles_cap < 1 ? 1 : tiles_cap;
-  const uint32_t* kin = keys;
-  const uint32_t* vin = nullptr;
-  int passes = (key_bits + kRadixBits - 1) / kRadixBits;
+  int passes = (key_bits + kRadixMaxBits - 1) / kRadixMaxBits;
   if (passes < 1) passes = 1;
-  for (int p = 0; p < passes; ++p) {
-    const int shift = p * kRadixBits;
-    uint32_t* kout = (p & 1) ? w.k1 : w.k0;
-    uint32_t* vout = (p & 1) ? w.v1 : w.v0;
-    k_radix_up<<<g, 256, 0, s>>>(kin, st, shift, w.hist, w.scan_len);
-    scan_exclusive(w.hist, w.hist, w.scan_len, nullptr, w.bsum, (int64_t)kRadix * g, s);
-    k_radix_down<<<g, 256, 0, s>>>(kin, vin, kout, vout, st, shift, w.hist);
-    kin = kout;
-    vin = vout;
+  const int dbits = (key_bits + passes - 1) / passes;
+  if (part == 0) {
+    const uint32_t* kin = src.key;
+    const uint32_t* vin = nullptr;
+    for (int p = 0; p < passes; ++p) {
+      uint32_t* kout = (p & 1) ? w.k1 : w.k0;
+      uint32_t* vout = (p & 1) ? w.v1 : w.v0;
+      const int shift = p * dbits;
+      const int db = (key_bits - shift < dbits) ? key_bits - shift : dbits;
+      if (db <= 8) radix_pass<8>(kin, vin, kout, vout, shift, db, w, st, g, s);
+      else radix_pass<10>(kin, vin, kout, vout, shift, db, w, st, g, s);
+      kin = kout;
+      vin = vout;
+    }
+  } else {
+    const uint32_t* skeys = ((passes - 1) & 1) ? w.k1 : w.k0;
+    const uint32_t* perm = ((passes - 1) & 1) ? w.v1 : w.v0;
+    int64_t gb = (w.cap + 256 * kGatherPer - 1) / (256 * kGatherPer);
+    if (gb < 1) gb = 1;
+    if (gb > 4096) gb = 4096;
+    k_gather<<<(int)gb, 256, 0, s>>>(src, dst, skeys, perm, st, sentinel);
   }
-  *skeys = const_cast<uint32_t*>(kin);
-  *perm = const_cast<uint32_t*>(vin);
 }
 
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_gather(Parts src, Parts dst, const uint32_t* skeys,
-                                                const uint32_t* perm, const DevState* st,
-                                                uint32_t sentinel) {
-  const uint32_t n = st->n_total;
-  for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
-    const uint32_t k = skeys[p];
-    if (k == sentinel) continue;
-    const uint32_t q = perm[p];
-    dst.r[p] = src.r[q];
-    dst.z[p] = src.z[q];
-    dst.vr[p] = src.vr[q];
-    dst.vt[p] = src.vt[q];
-    dst.vz[p] = src.vz[q];
-    dst.sp[p] = src.sp[q];
-    dst.id[p] = src.id[q];
-    dst.key[p] = k;
-  }
-}
-
-void gather_sorted(const Parts& src, const Parts& dst, const uint32_t* skeys, const uint32_t* perm,
-                   const DevState* st, uint32_t sentinel, int64_t cap, hipStream_t s) {
-  k_gather<<<grid_for(cap), 256, 0, s>>>(src, dst, skeys, perm, st, sentinel);
-}
-
 // off[k] = first sorted position whose key >= k, for k = 0 .. nkeys-1;
 // off[sentinel] is the number of live particles.
-__global__ void __launch_bounds__(256) k_offsets(const uint32_t* skeys, DevState* st,
-                                                 uint32_t* off, uint32_t nkeys) {
+__global__ void __launch_bounds__(256) k_offsets(const uint32_t* __restrict__ skeys, DevState* st,
+                                                 uint32_t* __restrict__ off, uint32_t nkeys) {
   const uint32_t n = st->n_total;
   for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < nkeys; k += gridDim.x * blockDim.x) {
     uint32_t lo = 0, hi = n;
     while (lo < hi) {
-      uint32_t mid = lo + ((hi - lo) >> 1);
+      const uint32_t mid = lo + ((hi - lo) >> 1);
       if (skeys[mid] < k) lo = mid + 1;
       else hi = mid;
     }

@@ -280,7 +280,7 @@ pd_status pd_create(const pd_domain* dom, const pd_opts* opts, pd_ctx** out) {
     pd_destroy(c);
     return s;
   };
-  if (dom->nr < 2 || dom->nz < 2 || dom->nr > 8192 || dom->nz > 8192 ||
+  if (dom->nr < 2 || dom->nz < 2 || poisson_lds_bytes(dom->nr) > 65536 || dom->nz > 8192 ||
       (int64_t)dom->nr * dom->nz * 6 >= (1LL << 31) || !(dom->R > 0) || !(dom->L > 0) ||
       !(dom->dt > 0) || !(dom->weight > 0) || !std::isfinite(dom->V_cathode) ||
       !std::isfinite(dom->R) || !std::isfinite(dom->L) || dom->capacity < 1 ||
@@ -335,8 +335,9 @@ pd_status pd_create(const pd_domain* dom, const pd_opts* opts, pd_ctx** out) {
       (s = dalloc(c, &c->cw.cbase, cap)) || (s = dalloc(c, &c->cw.scan_len, 4)) ||
       (s = dalloc(c, &c->fw.Q, nn)) || (s = dalloc(c, &c->fw.phi, nn)) ||
       (s = dalloc(c, &c->fw.Er, nn)) || (s = dalloc(c, &c->fw.Ez, nn)) ||
+      (s = dalloc(c, &c->fw.fh, (size_t)M * (nr + 1))) ||
       (s = dalloc(c, &c->fw.f, (size_t)M * (nr + 1))) ||
-      (s = dalloc(c, &c->fw.fh, (size_t)M * (nr + 1))) || (s = dalloc(c, &c->st, 1)) ||
+      (s = dalloc(c, &c->fw.g, (size_t)M * (nr + 1))) || (s = dalloc(c, &c->st, 1)) ||
       (s = dalloc(c, &c->off, (size_t)c->g.sentinel + 1)) || (s = dalloc(c, &c->d_edges, 65)) ||
       (s = dalloc(c, &c->d_dcount, (size_t)kDiagBlocks * kNS)) ||
       (s = dalloc(c, &c->d_dke, (size_t)kDiagBlocks * kNS)) ||
@@ -532,21 +533,18 @@ pd_status pd_step(pd_ctx* c, int nsteps) {
       }
     };
     mark();
-    uint32_t *skeys, *perm;
-    sort_keys(c->A.key, c->key_bits, c->sw, c->st, &skeys, &perm, s);
+    sort_particles(c->A, c->B, c->key_bits, c->sw, c->st, c->g.sentinel, 0, s);
     mark();
-    gather_sorted(c->A, c->B, skeys, perm, c->st, c->g.sentinel, c->cap, s);
+    sort_particles(c->A, c->B, c->key_bits, c->sw, c->st, c->g.sentinel, 1, s);
     std::swap(c->A, c->B);
     mark();
-    // the radix output holds every key, the absorbed ones (sentinel) included;
-    // the permuted payload skips those, so its key tail is not defined
-    build_offsets(skeys, c->st, c->off, c->g.sentinel + 1, s);
+    build_offsets(c->A.key, c->st, c->off, c->g.sentinel + 1, s);
     mark();
     if (!c->opts.collisions_off)
       collide(c->A, c->off, c->st, c->g, c->cpar, c->cw, c->sw.bsum, c->cap, s);
     mark();
     if (c->opts.deposit_off) fill_i64(c->fw.Q, 0, nn, s);
-    else deposit(c->A, c->st, c->g, c->spp, c->fw.Q, c->cap, s);
+    else deposit(c->A, c->st, c->off, c->g, c->spp, c->fw.Q, c->cap, s);
     mark();
     poisson_direct(c->g, c->fw, s);
     mark();

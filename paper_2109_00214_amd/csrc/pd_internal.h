@@ -76,10 +76,10 @@ struct Schedule {
 constexpr int kSortBlock = 256;
 constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortBlock * kSortItems;  // 4096 keys per tile
-constexpr int kRadixBits = 8;
-constexpr int kRadix = 1 << kRadixBits;
-constexpr int kScanChunk = 8192;                    // elements per scan block
-constexpr int kScanMaxBlocks = 16384;
+constexpr int kRadixMaxBits = 10;                  // digit width of a pass
+constexpr int kRadix = 1 << kRadixMaxBits;
+constexpr int kScanChunk = 2048;                    // elements per scan block
+constexpr int kScanMaxBlocks = 65536;
 
 struct SortWork {
   uint32_t *k0, *k1, *v0, *v1;  // key/value ping-pong [cap]
@@ -89,16 +89,14 @@ struct SortWork {
   int64_t cap;
 };
 
-// Stable LSD radix sort of st->n_total keys; returns the buffer holding
-// the sorted keys (*skeys) and the permutation (*perm: sorted -> source).
-void sort_keys(const uint32_t* keys, int key_bits, SortWork& w, DevState* st,
-               uint32_t** skeys, uint32_t** perm, hipStream_t s);
+// Stable LSD radix sort of the st->n_total keys of src; the last pass moves
+// the records into dst (every key, the sentinel ones included, lands in
+// dst.key).  part = 0: every pass but the last; part = 1: the last pass.
+void sort_particles(const Parts& src, const Parts& dst, int key_bits, SortWork& w, DevState* st,
+                    uint32_t sentinel, int part, hipStream_t s);
 // Exclusive scan of *len u32 values (device length), total to *total.
 void scan_exclusive(const uint32_t* in, uint32_t* out, const uint32_t* len,
                     uint32_t* total, uint32_t* bsum, int64_t max_len, hipStream_t s);
-void gather_sorted(const Parts& src, const Parts& dst, const uint32_t* skeys,
-                   const uint32_t* perm, const DevState* st, uint32_t sentinel,
-                   int64_t cap, hipStream_t s);
 void build_offsets(const uint32_t* skeys, DevState* st, uint32_t* off, uint32_t nkeys,
                    hipStream_t s);
 
@@ -116,8 +114,9 @@ void collide(const Parts& P, const uint32_t* off, DevState* st, const Grid& g,
 struct FieldWork {
   int64_t* Q;           // nodes
   double *phi, *Er, *Ez;
-  double* f;            // [(nz-1) * (nr+1)] interior right-hand side
-  double* fh;           // [(nr+1) * (nz-1)] transformed, k fastest
+  double* f;            // [(nz-1) * (nr+1)] right-hand side, interior rows
+  double* fh;           // [(nr+1) * (nz-1)] transformed, mode fastest
+  double* g;            // [(nz-1) * (nr+1)] per-mode solutions, r fastest
   const double* S;      // [(nz-1)^2] DST-I table, symmetric
   const double* tinv;   // [(nr+1) * (nz-1)] Thomas reciprocals
   const double* tcp;    // [(nr+1) * (nz-1)] Thomas upper factors
@@ -125,9 +124,10 @@ struct FieldWork {
   const double* Vnode;  // [nr+1]
   double qunit;
 };
-void deposit(const Parts& P, const DevState* st, const Grid& g, const SpeciesParams& sp,
-             int64_t* Q, int64_t cap, hipStream_t s);
+void deposit(const Parts& P, const DevState* st, const uint32_t* off, const Grid& g,
+             const SpeciesParams& sp, int64_t* Q, int64_t cap, hipStream_t s);
 void poisson_direct(const Grid& g, FieldWork& fw, hipStream_t s);
+size_t poisson_lds_bytes(int nr);
 void field(const Grid& g, FieldWork& fw, hipStream_t s);
 void push(const Parts& P, DevState* st, const Grid& g, const SpeciesParams& sp,
           const FieldWork& fw, int64_t cap, hipStream_t s);
