@@ -287,25 +287,15 @@ __global__ void __launch_bounds__(256) k_apply(Parts P, const uint32_t* off, Dev
   }
 }
 
-// No room for the new electrons (capacity or 32-bit ids), or an earlier
-// error: flag it and create nothing, so that every later launch of the step
-// touches only the live particles [0, n_alive).
-__global__ void k_created_guard(DevState* st, uint32_t cap) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const uint64_t n = (uint64_t)st->n_alive + st->n_created;
-  if (st->err || n > cap || (uint64_t)st->next_id + st->n_created > 0xFFFFFFFFull) {
-    st->err |= 1u;
-    st->n_created = 0;
-  }
-}
-
 void collide(const Parts& P, const uint32_t* off, DevState* st, const Grid& g,
              const CollideParams& cp, CollideWork& w, uint32_t* bsum, int64_t cap, hipStream_t s) {
   const int gr = grid_for(cap);
   k_decide<<<gr, 256, 0, s>>>(P, off, st, g, cp, w.choice, w.target, w.claim, w.scan_len);
   k_resolve<<<gr, 256, 0, s>>>(off, st, g, w.choice, w.target, w.claim, w.ccount);
-  scan_exclusive(w.ccount, w.cbase, w.scan_len, &st->n_created, bsum, cap, s);
-  k_created_guard<<<1, 64, 0, s>>>(st, (uint32_t)cap);
+  // created-electron slots; the scan's guard flags an overflow and then
+  // creates nothing, so every later launch touches only [0, n_alive)
+  scan_exclusive(w.ccount, w.cbase, w.scan_len, &st->n_created, bsum, cap, s, st,
+                 (uint32_t)cap);
   k_apply<<<gr, 256, 0, s>>>(P, off, st, g, cp, w.choice, w.target, w.cbase, w.claim,
                              (uint32_t)cap);
 }

@@ -104,9 +104,7 @@ void fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
 
 void deposit(const Parts& P, const DevState* st, const uint32_t* off, const Grid& g,
              const SpeciesParams& sp, int64_t* Q, int64_t cap, hipStream_t s) {
-  const int64_t nn = (int64_t)(g.nr + 1) * (g.nz + 1);
-  fill_i64(Q, 0, nn, s);
-  (void)off;
+  (void)off;  // Q was cleared by the offsets launch
   k_deposit<<<grid_for(cap), 256, 0, s>>>(P, st, g, sp, (unsigned long long*)Q);
 }
 
@@ -213,18 +211,19 @@ void push(const Parts& P, DevState* st, const Grid& g, const SpeciesParams& sp, 
 
 // ---------------------------------------------------------------------------
 // this step's scheduled particles, appended after the pushed ones
+// The last block to finish (a ticket counter, no waiting) then rolls the
+// counters: the arrays now hold alive + created + injected.
 __global__ void __launch_bounds__(256) k_inject(Parts P, DevState* st, Grid g, Schedule sc,
                                                 uint32_t cap) {
+  __shared__ uint32_t last;
   const uint32_t pos = st->sched_pos;
-  if (pos >= st->sched_n) return;
-  const int64_t a = sc.off[pos];
-  const uint32_t cnt = (uint32_t)(sc.off[pos + 1] - a);
+  const bool have = sc.off && pos < st->sched_n;
+  const int64_t a = have ? sc.off[pos] : 0;
+  uint32_t cnt = have ? (uint32_t)(sc.off[pos + 1] - a) : 0u;
   const uint32_t base = st->n_alive + st->n_created;
   const uint32_t id0 = st->next_id + st->n_created;
-  if ((uint64_t)base + cnt > cap || (uint64_t)id0 + cnt > 0xFFFFFFFFull) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&st->err, 1u);
-    return;
-  }
+  const bool fits = (uint64_t)base + cnt <= cap && (uint64_t)id0 + cnt <= 0xFFFFFFFFull;
+  if (!fits) cnt = 0;
   for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < cnt; q += gridDim.x * blockDim.x) {
     const int64_t src = a + q;
     const uint32_t d = base + q;
@@ -242,33 +241,28 @@ __global__ void __launch_bounds__(256) k_inject(Parts P, DevState* st, Grid g, S
     cell_of(g, r, z, i, j, fr, fz);
     P.key[d] = s * g.C + (uint32_t)(j * g.nr + i);
   }
-}
-
-void inject_scheduled(const Parts& P, DevState* st, const Grid& g, const Schedule& sc, int64_t cap,
-                      hipStream_t s) {
-  if (!sc.off) return;
-  k_inject<<<grid_for(sc.max_count), 256, 0, s>>>(P, st, g, sc, (uint32_t)cap);
-}
-
-// roll the counters: the arrays now hold alive + created + injected
-__global__ void k_step_end(DevState* st, const int64_t* soff) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  uint32_t inj = 0;
-  if (soff && st->sched_pos < st->sched_n) {
-    inj = (uint32_t)(soff[st->sched_pos + 1] - soff[st->sched_pos]);
-    st->sched_pos += 1;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    last = (atomicAdd(&st->ticket, 1u) == gridDim.x - 1) ? 1u : 0u;
   }
-  if (st->err) inj = 0;
+  __syncthreads();
+  if (!last || threadIdx.x != 0) return;
+  __threadfence();
+  if (!fits) atomicOr(&st->err, 1u);
+  if (have) st->sched_pos = pos + 1;
   st->created += st->n_created;
   st->pushed += st->n_alive + st->n_created;
-  st->n_total = st->n_alive + st->n_created + inj;
-  st->next_id += st->n_created + inj;
+  st->n_total = base + cnt;
+  st->next_id = id0 + cnt;
   st->n_created = 0;
   st->step += 1;
+  st->ticket = 0;
 }
 
-void step_end(DevState* st, const Schedule& sc, hipStream_t s) {
-  k_step_end<<<1, 64, 0, s>>>(st, sc.off);
+void inject_and_roll(const Parts& P, DevState* st, const Grid& g, const Schedule& sc, int64_t cap,
+                     hipStream_t s) {
+  k_inject<<<grid_for(sc.off ? sc.max_count : 1), 256, 0, s>>>(P, st, g, sc, (uint32_t)cap);
 }
 
 // host-initiated append of n particles already copied to src

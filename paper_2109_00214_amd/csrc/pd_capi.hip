@@ -169,20 +169,20 @@ void build_tables(pd_ctx* c, std::vector<double>& Vnode, std::vector<double>& Vc
     rc[i] = hi / (dr * area);
     rb[i] = -(ra[i] + rc[i]);
   }
-  // DST-I table over the interior z nodes, argument reduced exactly
-  S.assign((size_t)M * M, 0.0);
-  for (int k = 1; k <= M; ++k)
-    for (int j = 1; j <= M; ++j) {
-      long long m = ((long long)k * j) % (2LL * nz);
-      bool neg = false;
-      if (m >= nz) {
-        m -= nz;
-        neg = true;
-      }
-      if (2 * m > nz) m = nz - m;
-      const double v = (m == 0) ? 0.0 : std::sin((kPI * (double)m) / (double)nz);
-      S[(size_t)(k - 1) * M + (j - 1)] = neg ? -v : v;
+  // DST-I entries sin(pi k j / nz): they depend only on m = (k j) mod 2 nz,
+  // reduced exactly to [0, nz/2] by the symmetries of sin (sign restored)
+  S.assign((size_t)2 * nz, 0.0);
+  for (int m0 = 0; m0 < 2 * nz; ++m0) {
+    long long m = m0;
+    bool neg = false;
+    if (m >= nz) {
+      m -= nz;
+      neg = true;
     }
+    if (2 * m > nz) m = nz - m;
+    const double v = (m == 0) ? 0.0 : std::sin((kPI * (double)m) / (double)nz);
+    S[m0] = neg ? -v : v;
+  }
   // per-mode tridiagonal factors of (D_r + mu_k), mu_k the eigenvalue of
   // the 3-point d2/dz2 on sin(pi k j / nz)
   tinv.assign((size_t)(nr + 1) * M, 0.0);
@@ -280,7 +280,7 @@ pd_status pd_create(const pd_domain* dom, const pd_opts* opts, pd_ctx** out) {
     pd_destroy(c);
     return s;
   };
-  if (dom->nr < 2 || dom->nz < 2 || poisson_lds_bytes(dom->nr) > 65536 || dom->nz > 8192 ||
+  if (dom->nr < 2 || dom->nz < 2 || poisson_lds_bytes(dom->nr, dom->nz) > 65536 || dom->nz > 8192 ||
       (int64_t)dom->nr * dom->nz * 6 >= (1LL << 31) || !(dom->R > 0) || !(dom->L > 0) ||
       !(dom->dt > 0) || !(dom->weight > 0) || !std::isfinite(dom->V_cathode) ||
       !std::isfinite(dom->R) || !std::isfinite(dom->L) || dom->capacity < 1 ||
@@ -363,7 +363,7 @@ pd_status pd_create(const pd_domain* dom, const pd_opts* opts, pd_ctx** out) {
     return fail(set_err(c, PD_EDEVICE, "table upload failed"));
   c->fw.Vnode = dVn;
   c->fw.ra = dra;
-  c->fw.S = dS;
+  c->fw.T = dS;
   c->fw.tinv = dti;
   c->fw.tcp = dtc;
   c->fw.qunit = c->qunit;
@@ -538,13 +538,12 @@ pd_status pd_step(pd_ctx* c, int nsteps) {
     sort_particles(c->A, c->B, c->key_bits, c->sw, c->st, c->g.sentinel, 1, s);
     std::swap(c->A, c->B);
     mark();
-    build_offsets(c->A.key, c->st, c->off, c->g.sentinel + 1, s);
+    build_offsets(c->A.key, c->st, c->off, c->g.sentinel + 1, c->fw.Q, (uint32_t)nn, s);
     mark();
     if (!c->opts.collisions_off)
       collide(c->A, c->off, c->st, c->g, c->cpar, c->cw, c->sw.bsum, c->cap, s);
     mark();
-    if (c->opts.deposit_off) fill_i64(c->fw.Q, 0, nn, s);
-    else deposit(c->A, c->st, c->off, c->g, c->spp, c->fw.Q, c->cap, s);
+    if (!c->opts.deposit_off) deposit(c->A, c->st, c->off, c->g, c->spp, c->fw.Q, c->cap, s);
     mark();
     poisson_direct(c->g, c->fw, s);
     mark();
@@ -552,8 +551,7 @@ pd_status pd_step(pd_ctx* c, int nsteps) {
     mark();
     push(c->A, c->st, c->g, c->spp, c->fw, c->cap, s);
     mark();
-    inject_scheduled(c->A, c->st, c->g, c->sched, c->cap, s);
-    step_end(c->st, c->sched, s);
+    inject_and_roll(c->A, c->st, c->g, c->sched, c->cap, s);
     mark();
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {

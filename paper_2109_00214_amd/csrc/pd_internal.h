@@ -24,6 +24,8 @@ struct DevState {
   uint32_t sched_pos;  // next injection-schedule slot
   uint32_t sched_n;    // schedule length (steps)
   uint32_t err;        // bit 0: capacity overflow
+  uint32_t ticket;     // finished blocks of the injection launch (last one rolls)
+  uint32_t pad_;
   unsigned long long events[kNC];
   unsigned long long conflicts;
   unsigned long long created;
@@ -94,11 +96,15 @@ struct SortWork {
 // dst.key).  part = 0: every pass but the last; part = 1: the last pass.
 void sort_particles(const Parts& src, const Parts& dst, int key_bits, SortWork& w, DevState* st,
                     uint32_t sentinel, int part, hipStream_t s);
-// Exclusive scan of *len u32 values (device length), total to *total.
+// Exclusive scan of *len u32 values (device length), total to *total.  With
+// a guard state the total counts new particles: it is forced to 0 and the
+// error flagged when they would not fit in cap (or the ids would wrap).
 void scan_exclusive(const uint32_t* in, uint32_t* out, const uint32_t* len,
-                    uint32_t* total, uint32_t* bsum, int64_t max_len, hipStream_t s);
+                    uint32_t* total, uint32_t* bsum, int64_t max_len, hipStream_t s,
+                    DevState* guard, uint32_t cap);
+// CSR offsets of the sorted keys; the same launch clears the node charge Q.
 void build_offsets(const uint32_t* skeys, DevState* st, uint32_t* off, uint32_t nkeys,
-                   hipStream_t s);
+                   int64_t* Q, uint32_t nnodes, hipStream_t s);
 
 // ---- collisions (k_collide.hip) ----
 struct CollideWork {
@@ -117,7 +123,7 @@ struct FieldWork {
   double* f;            // [(nz-1) * (nr+1)] right-hand side, interior rows
   double* fh;           // [(nr+1) * (nz-1)] transformed, mode fastest
   double* g;            // [(nz-1) * (nr+1)] per-mode solutions, r fastest
-  const double* S;      // [(nz-1)^2] DST-I table, symmetric
+  const double* T;      // [2 nz] DST-I entries by (k j) mod 2 nz
   const double* tinv;   // [(nr+1) * (nz-1)] Thomas reciprocals
   const double* tcp;    // [(nr+1) * (nz-1)] Thomas upper factors
   const double* ra;     // [nr+1] radial lower coefficients
@@ -127,13 +133,13 @@ struct FieldWork {
 void deposit(const Parts& P, const DevState* st, const uint32_t* off, const Grid& g,
              const SpeciesParams& sp, int64_t* Q, int64_t cap, hipStream_t s);
 void poisson_direct(const Grid& g, FieldWork& fw, hipStream_t s);
-size_t poisson_lds_bytes(int nr);
+size_t poisson_lds_bytes(int nr, int nz);
 void field(const Grid& g, FieldWork& fw, hipStream_t s);
 void push(const Parts& P, DevState* st, const Grid& g, const SpeciesParams& sp,
           const FieldWork& fw, int64_t cap, hipStream_t s);
-void inject_scheduled(const Parts& P, DevState* st, const Grid& g, const Schedule& sc,
-                      int64_t cap, hipStream_t s);
-void step_end(DevState* st, const Schedule& sc, hipStream_t s);
+// append this step's scheduled particles and roll the step counters
+void inject_and_roll(const Parts& P, DevState* st, const Grid& g, const Schedule& sc,
+                     int64_t cap, hipStream_t s);
 void append(const Parts& P, DevState* st, const Grid& g, const Parts& src, uint32_t n,
             hipStream_t s);
 // snapshot reductions: per-block partial counts, KE sums, spectrum bins
