@@ -39,10 +39,12 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--config", default="paper")
     ap.add_argument("--n-init", type=int, default=None)
-    ap.add_argument("--cpu-steps", type=int, default=1,
+    ap.add_argument("--cpu-steps", type=int, default=40,
                     help="oracle steps timed for the CPU baseline (0: skip)")
-    ap.add_argument("--traffic", default=None,
-                    help="JSON file with rocprofv3 FETCH/WRITE bytes per launch of the kernel")
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles",
+                                                      "hbm_traffic_paper_256x512.txt"),
+                    help="rocprofv3 FETCH/WRITE summary written by "
+                         "paper_2109_00214_amd.profiling traffic")
     return ap.parse_args()
 
 
@@ -124,10 +126,11 @@ def main():
     dom = max(cand, key=cand.get)
     units = pst / a.steps
     achieved = ALGO_BYTES[dom] * units / (per_step[dom] / 1e3) / 1e9
-    traffic = None
-    if a.traffic and os.path.exists(a.traffic):
-        tr = json.load(open(a.traffic))
-        traffic = tr.get(dom)
+    # HBM bytes per launch from the counters, if taken on this workload and
+    # on the kernel as it is now
+    from paper_2109_00214_amd.profiling import read_traffic
+    traffic = read_traffic(a.traffic).get(dom) if cfg.name == "paper" and a.n_init is None \
+        else None
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "bytes_per_particle": ALGO_BYTES[dom], "particles_per_launch": round(units)}
