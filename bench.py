@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--config", default="paper")
     ap.add_argument("--n-init", type=int, default=None)
+    ap.add_argument("--poisson", choices=("direct", "mgpcg"), default="direct",
+                    help="direct FP64 solve, or FP32 multigrid CG with FP64 refinement")
     ap.add_argument("--cpu-steps", type=int, default=40,
                     help="oracle steps timed for the CPU baseline (0: skip)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles",
@@ -85,7 +87,7 @@ def main():
     import torch
 
     from paper_2109_00214_amd import workload as W
-    from paper_2109_00214_amd.pd import Simulation
+    from paper_2109_00214_amd.pd import PD_POISSON_DIRECT64, PD_POISSON_MGPCG, Simulation
 
     kw = {} if a.n_init is None else {"n_init": a.n_init}
     cfg = W.config(a.config, **kw)
@@ -99,7 +101,8 @@ def main():
     stream = torch.cuda.current_stream()
     cap = int(1.25 * cfg.n_init + cfg.inj_cu * nsteps + 40 * cfg.inj_e + 1_000_000)
     sim = Simulation(cfg, cap, W.cross_section_tables(), W.species_table(), timing=True,
-                     stream=stream.cuda_stream)
+                     stream=stream.cuda_stream,
+                     poisson=PD_POISSON_MGPCG if a.poisson == "mgpcg" else PD_POISSON_DIRECT64)
     sim.inject(parts)
     sim.schedule_injection(off, inj)
     sim.step(a.warmup)
@@ -151,8 +154,15 @@ def main():
                                "%d injected/step, FP64 deterministic" %
                                (cfg.name, cfg.nr, cfg.nz, cfg.n_init, cfg.weight,
                                 cfg.inj_e + cfg.inj_cu),
-                   "poisson": "direct FP64 (sine transform + tridiagonal)",
+                   "poisson": ("direct FP64 (sine transform + tridiagonal)"
+                               if a.poisson == "direct" else
+                               "FP32 multigrid-preconditioned CG, FP64 refinement, rtol 1e-8"),
                    "poisson_s_per_step": per_step["poisson"] / 1e3,
+                   "poisson_rel_res_final": d1["poisson_rel_res"],
+                   "poisson_cg_iters_per_step": (d1["poisson_iters"] - d0["poisson_iters"]) / a.steps,
+                   "poisson_refinements_per_step":
+                       (d1["poisson_refinements"] - d0["poisson_refinements"]) / a.steps,
+                   "poisson_fallbacks": d1["poisson_fallbacks"],
                    "mean_particles_per_step": round(units),
                    "final_particles": int(d1["n_alive"])},
         "roofline": roof,

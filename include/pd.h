@@ -66,8 +66,12 @@ enum { PD_EL = 0, PD_SI = 1, PD_DI = 2, PD_SI2 = 3, PD_NCHANNELS = 4 };
 enum { PD_CATHODE = 0, PD_ANODE = 1, PD_OUTER = 2 };
 /* precision forms */
 enum { PD_FP64_DET = 0 };
-/* Poisson solvers */
-enum { PD_POISSON_DIRECT64 = 0 };
+/* Poisson solvers: the direct FP64 solve (sine transform in z, tridiagonal
+ * in r), or conjugate gradients in FP32 preconditioned by a geometric
+ * multigrid V-cycle inside FP64 iterative refinement, started from the
+ * previous step's potential and stopped at the relative residual
+ * poisson_rtol (falls back to the direct solve if it does not get there) */
+enum { PD_POISSON_DIRECT64 = 0, PD_POISSON_MGPCG = 1 };
 /* stages timed by pd_get_timing: radix passes of the sort, payload
  * permutation, CSR offsets, collisions, deposit, Poisson, field, push,
  * injection + counter roll */
@@ -93,6 +97,9 @@ typedef struct {
   int32_t collisions_off; /* 1: skip the DSMC stage, tests */
   int32_t timing;         /* 1: record HIP events around every stage */
   void* stream;           /* hipStream_t to run on, or NULL for a new one */
+  double poisson_rtol;    /* iterative solves: target relative residual
+                           * ||b - A phi|| / ||b|| of the volume-weighted
+                           * system, electrode values in b (0: 1e-8) */
 } pd_opts;
 
 typedef struct {
@@ -107,6 +114,11 @@ typedef struct {
   double ke_J[PD_NSPECIES];      /* kinetic energy per species at v(n+1/2) */
   double gamma, qbar;            /* Eq. 21 over charge states 0..2 */
   int64_t particle_steps;        /* sum over steps of the particles pushed */
+  double poisson_rel_res;        /* relative residual of the current phi (FP64) */
+  int64_t poisson_solves;        /* cumulative Poisson solves */
+  int64_t poisson_iters;         /* cumulative CG iterations (iterative solver) */
+  int64_t poisson_refinements;   /* cumulative FP64 refinement steps */
+  int64_t poisson_fallbacks;     /* solves that fell back to the direct solve */
 } pd_diag;
 
 /* Create a context on the current HIP device.  dom and opts are copied.
@@ -179,6 +191,17 @@ pd_status pd_get_particles(pd_ctx* ctx, int64_t cap, double* r, double* z, doubl
  * (nz+1) nodes each; Q in units of e * weight * 2^-40).  Any pointer may
  * be NULL.                                                            */
 pd_status pd_get_field(pd_ctx* ctx, double* phi, double* Er, double* Ez, int64_t* Q);
+
+/* Solve the field equation for the node charge Q ((nr+1)*(nz+1) values,
+ * units of e * weight * 2^-40) with the context's Poisson solver, starting
+ * from the context's current potential; the context keeps Q, phi and E as
+ * if a step had deposited Q.  phi (may be NULL) receives the potential,
+ * iters (may be NULL) the CG iterations of this solve (0 for the direct
+ * solve), rel_res (may be NULL) the relative residual reached.
+ * Errors: PD_EINVAL (NULL Q), PD_ENOCONV never (the direct solve is the
+ * fallback), PD_EDEVICE.                                                */
+pd_status pd_poisson(pd_ctx* ctx, const int64_t* Q, double* phi, int32_t* iters,
+                     double* rel_res);
 
 /* Accumulated device time per stage (ms, PD_NTIMERS entries) and the
  * number of steps timed, since creation or the last reset (requires

@@ -73,6 +73,8 @@ def oracle_lib():
         lib.or_get_diag.argtypes = [P, C.POINTER(_Diag)]
         lib.or_philox4x32_10.argtypes = [P, P, P]
         lib.or_poisson_solve.argtypes = [P, P, P]
+        lib.or_poisson_residual.argtypes = [P, P, P, dp, dp]
+        lib.or_poisson_residual.restype = None
         lib.or_isotropic.argtypes = [P, C.c_uint32, C.c_uint32, P]
         lib.or_rotation.argtypes = [C.c_double, C.c_double, P]
         lib.or_split_literal.argtypes = [P, C.c_double, C.c_double, P]
@@ -216,6 +218,15 @@ class Oracle:
         out = np.zeros_like(f)
         self.lib.or_poisson_solve(self.h, _p(f), _p(out))
         return out.reshape(self.nz + 1, self.nr + 1)
+
+    def poisson_residual(self, Q, phi):
+        """(||b - A phi||, ||b||) of the volume-weighted Poisson system."""
+        q = np.ascontiguousarray(Q, dtype=np.int64).reshape(-1)
+        f = np.ascontiguousarray(phi, dtype=np.float64).reshape(-1)
+        assert q.size == f.size == (self.nr + 1) * (self.nz + 1)
+        rn, bn = C.c_double(), C.c_double()
+        self.lib.or_poisson_residual(self.h, _p(q), _p(f), C.byref(rn), C.byref(bn))
+        return rn.value, bn.value
 
     def isotropic(self, pid, purpose):
         n = np.zeros(3)

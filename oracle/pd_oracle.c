@@ -680,6 +680,41 @@ int or_poisson_solve(const or_sim* s, const double* f, double* phi_p) {
   return 0;
 }
 
+/* Residual of a potential for the node charge Q.  Each node row of the
+ * finite-volume equation lap(phi) = -rho/eps0 (rho = Q qunit / V_node) is
+ * multiplied by the node's control volume w_i = A_i dz, A_i the integral of
+ * r dr over its radial control interval.  With phi holding the electrode
+ * values on rows 0 and nz, w (rho/eps0 + lap phi) is b - A phi, and b is
+ * w rho/eps0 plus w phi_electrode/dz^2 on the rows next to the electrodes. */
+void or_poisson_residual(const or_sim* s, const int64_t* Q, const double* phi,
+                         double* rnorm, double* bnorm) {
+  const int nr = s->nr, nz = s->nz, W = nr + 1;
+  const double dr = s->dr, dz = s->dz, dz2 = dz * dz;
+  double rr = 0.0, bb = 0.0;
+  for (int j = 1; j < nz; ++j)
+    for (int i = 0; i <= nr; ++i) {
+      double A;
+      if (i == 0) A = (dr * dr) / 8.0;
+      else if (i == nr) A = ((s->R * dr) / 2.0) - ((dr * dr) / 8.0);
+      else A = ((double)i * dr) * dr;
+      const double w = A * dz;
+      const size_t q = (size_t)j * W + i;
+      const double rho = ((double)Q[q] * s->qunit) / s->Vnode[i];
+      double lap = s->rb[i] * phi[q];
+      if (i > 0) lap = lap + (s->ra[i] * phi[q - 1]);
+      if (i < nr) lap = lap + (s->rc[i] * phi[q + 1]);
+      lap = lap + (((phi[q - W] - (2.0 * phi[q])) + phi[q + W]) / dz2);
+      const double r = w * ((rho / EPS0) + lap);
+      double b = w * (rho / EPS0);
+      if (j == 1) b = b + ((w * phi[i]) / dz2);
+      if (j == nz - 1) b = b + ((w * phi[(size_t)nz * W + i]) / dz2);
+      rr = rr + (r * r);
+      bb = bb + (b * b);
+    }
+  *rnorm = sqrt(rr);
+  *bnorm = sqrt(bb);
+}
+
 void or_stage_poisson(or_sim* s) {
   const int nr = s->nr, nz = s->nz, W = nr + 1;
   size_t nn = (size_t)(nz + 1) * W;

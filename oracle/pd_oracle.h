@@ -92,6 +92,11 @@ void or_get_diag(const or_sim* s, or_diag* d);
 /* pure building blocks, exposed for the pin tests */
 void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 int or_poisson_solve(const or_sim* s, const double* f, double* phi_p);
+/* ||b - A phi||_2 and ||b||_2 of the Poisson system written over the
+ * interior z rows with every node row multiplied by its control volume
+ * (which makes A symmetric), the electrode values of phi moved into b */
+void or_poisson_residual(const or_sim* s, const int64_t* Q, const double* phi,
+                         double* rnorm, double* bnorm);
 void or_isotropic(const or_sim* s, uint32_t id, uint32_t purpose, double n[3]);
 void or_rotation(double theta, double phi, double Rm[9]);
 void or_split_literal(const double v[3], double chi, double psi, double v5[3]);

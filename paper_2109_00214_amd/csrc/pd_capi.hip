@@ -63,6 +63,13 @@ struct pd_ctx {
   int64_t host_step = 0;
   int64_t injected[kNS] = {0, 0, 0, 0, 0, 0};
 
+  // Poisson: FP64 residual operator (every solver) and the multigrid-CG work
+  MGWork mg{};
+  MGScal* h_sc = nullptr;  // pinned host copy of the solve scalars
+  bool mg_on = false;
+  int mg_inner = 8, mg_outer_max = 8;
+  int64_t p_solves = 0, p_fallbacks = 0;
+
   // timing
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::vector<hipEvent_t>> ev_pending;
@@ -206,6 +213,151 @@ void build_tables(pd_ctx* c, std::vector<double>& Vnode, std::vector<double>& Vc
   for (int b = 0; b <= 64; ++b) edges[b] = std::pow(10.0, (3.0 * (double)b) / 64.0);
 }
 
+// Coefficients of the volume-weighted symmetric operator on a grid of
+// nr x nz cells: ew_i = r_{i-1/2} dz/dr, ee_i = r_{i+1/2} dz/dr,
+// ez_i = A_i/dz, w_i = A_i dz, A_i = integral of r dr over the node's radial
+// control interval clipped to [0, R].
+void weighted_operator(int nr, int nz, double R, double L, std::vector<double>& ew,
+                       std::vector<double>& ee, std::vector<double>& ez, std::vector<double>& w) {
+  const double dr = R / (double)nr, dz = L / (double)nz;
+  ew.assign(nr + 1, 0.0);
+  ee.assign(nr + 1, 0.0);
+  ez.assign(nr + 1, 0.0);
+  w.assign(nr + 1, 0.0);
+  for (int i = 0; i <= nr; ++i) {
+    double area;
+    if (i == 0) area = (dr * dr) / 8.0;
+    else if (i == nr) area = ((R * dr) / 2.0) - ((dr * dr) / 8.0);
+    else area = ((double)i * dr) * dr;
+    const double lo = (i == 0) ? 0.0 : ((double)i - 0.5) * dr;
+    const double hi = (i == nr) ? 0.0 : ((double)i + 0.5) * dr;
+    ew[i] = (lo * dz) / dr;
+    ee[i] = (hi * dz) / dr;
+    ez[i] = area / dz;
+    w[i] = area * dz;
+  }
+}
+
+// FP64 residual operator, solve scalars and, for the iterative solver, the
+// multigrid hierarchy (levels halve nr and nz while both stay even and >= 4;
+// the coarsest levels that fit kMGCoarseLds run in one workgroup).
+pd_status build_mg(pd_ctx* c, const double* dVnode) {
+  const int nr = c->dom.nr, nz = c->dom.nz;
+  MGWork& w = c->mg;
+  pd_status s;
+  std::vector<double> ew, ee, ez, wt;
+  weighted_operator(nr, nz, c->dom.R, c->dom.L, ew, ee, ez, wt);
+  std::vector<double> dg(nr + 1);
+  for (int i = 0; i <= nr; ++i) dg[i] = (ew[i] + ee[i]) + (2.0 * ez[i]);
+  double *d[5];
+  const std::vector<double>* h[5] = {&ew, &ee, &ez, &dg, &wt};
+  for (int k = 0; k < 5; ++k) {
+    if ((s = dalloc(c, &d[k], nr + 1))) return s;
+    if (hipMemcpy(d[k], h[k]->data(), 8 * (nr + 1), hipMemcpyHostToDevice) != hipSuccess)
+      return set_err(c, PD_EDEVICE, "upload");
+  }
+  w.op = MGOp64{nr, nz, d[0], d[1], d[2], d[3], d[4], dVnode, c->qunit};
+  if ((s = dalloc(c, &w.sc, 1)) || (s = dalloc(c, &w.part, (size_t)kMGParts * 4)) ||
+      (s = dalloc(c, &w.part64, (size_t)kMGParts * 2)))
+    return s;
+  if (hipHostMalloc((void**)&c->h_sc, sizeof(MGScal), 0) != hipSuccess)
+    return set_err(c, PD_ENOMEM, "pinned host memory");
+  MGScal h0{};
+  h0.rtol = c->opts.poisson_rtol > 0 ? c->opts.poisson_rtol : 1e-8;
+  h0.tol2 = 1e-8f;  // inner solve: ||r||/||r0|| <= 1e-4
+  h0.inner_max = c->mg_inner;
+  h0.done = 1;
+  if (hipMemcpy(w.sc, &h0, sizeof h0, hipMemcpyHostToDevice) != hipSuccess)
+    return set_err(c, PD_EDEVICE, "upload");
+  if (!c->mg_on) return PD_OK;
+
+  int nl = 1;
+  while (nl < kMGMaxLevels && ((nr >> (nl - 1)) % 2 == 0) && ((nz >> (nl - 1)) % 2 == 0) &&
+         (nr >> (nl - 1)) >= 4 && (nz >> (nl - 1)) >= 4)
+    ++nl;
+  w.nlev = nl;
+  w.coarse_sweeps = 8;
+  w.lc = -1;
+  for (int l = 0; l < nl && w.lc < 0; ++l) {
+    size_t b = 0;
+    for (int k = l; k < nl; ++k) b += 2 * sizeof(float) * (size_t)((nr >> k) + 1) * ((nz >> k) + 1);
+    if (b <= kMGCoarseLds) w.lc = l;
+  }
+  if (w.lc < 0)
+    return set_err(c, PD_EINVAL, "multigrid: grid %dx%d cannot be coarsened into LDS", nr, nz);
+  for (int l = 0; l < nl; ++l) {
+    const int a = nr >> l, b = nz >> l;
+    const size_t nn = (size_t)(a + 1) * (b + 1);
+    MGLevel& m = w.lev[l];
+    m.nr = a;
+    m.nz = b;
+    std::vector<double> lew, lee, lez, lw;
+    weighted_operator(a, b, c->dom.R, c->dom.L, lew, lee, lez, lw);
+    std::vector<float> tab(4 * (size_t)(a + 1));
+    for (int i = 0; i <= a; ++i) {
+      tab[i] = (float)lew[i];
+      tab[(a + 1) + i] = (float)lee[i];
+      tab[2 * (a + 1) + i] = (float)lez[i];
+      tab[3 * (a + 1) + i] = (float)(1.0 / ((lew[i] + lee[i]) + (2.0 * lez[i])));
+    }
+    float *dt, *x, *bb;
+    if ((s = dalloc(c, &dt, tab.size())) || (s = dalloc(c, &x, nn)) || (s = dalloc(c, &bb, nn)))
+      return s;
+    if (hipMemcpy(dt, tab.data(), 4 * tab.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(x, 0, 4 * nn) != hipSuccess || hipMemset(bb, 0, 4 * nn) != hipSuccess)
+      return set_err(c, PD_EDEVICE, "upload");
+    m.x = x;
+    m.b = bb;
+    m.ew = dt;
+    m.ee = dt + (a + 1);
+    m.ez = dt + 2 * (a + 1);
+    m.dinv = dt + 3 * (a + 1);
+  }
+  const size_t n0 = (size_t)(nr + 1) * (nz + 1);
+  float** v[4] = {&w.xc, &w.s, &w.p, &w.q};
+  for (int k = 0; k < 4; ++k) {
+    if ((s = dalloc(c, v[k], n0))) return s;
+    if (hipMemset(*v[k], 0, 4 * n0) != hipSuccess) return set_err(c, PD_EDEVICE, "memset");
+  }
+  mg_configure(w);
+  return PD_OK;
+}
+
+pd_status read_mg(pd_ctx* c) {
+  if (hipMemcpyAsync(c->h_sc, c->mg.sc, sizeof(MGScal), hipMemcpyDeviceToHost, c->stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess) {
+    c->poisoned = true;
+    return set_err(c, PD_EDEVICE, "Poisson scalars");
+  }
+  return PD_OK;
+}
+
+// The step's Poisson solve: direct, or multigrid CG from the current phi
+// with FP64 refinement until the relative residual reaches rtol (the direct
+// solve takes over if it does not within mg_outer_max refinements).
+pd_status solve_poisson(pd_ctx* c) {
+  hipStream_t s = c->stream;
+  c->p_solves += 1;
+  if (!c->mg_on) {
+    poisson_direct(c->g, c->fw, s);
+    return PD_OK;
+  }
+  mg_residual(c->mg, c->fw.phi, c->fw.Q, s);
+  for (int o = 0;; ++o) {
+    pd_status st = read_mg(c);
+    if (st) return st;
+    if (c->h_sc->conv) break;
+    if (o == c->mg_outer_max) {
+      poisson_direct(c->g, c->fw, s);
+      c->p_fallbacks += 1;
+      break;
+    }
+    mg_outer(c->mg, c->fw.phi, c->fw.Q, c->mg_inner, s);
+  }
+  return PD_OK;
+}
+
 void derive_pairs(pd_ctx* c) {
   // projectile: electron; target: Cu (EL, SI, DI) or Cu+ (SI2)
   const int tgt[kNC] = {PD_CU, PD_CU, PD_CU, PD_CU1};
@@ -286,8 +438,11 @@ pd_status pd_create(const pd_domain* dom, const pd_opts* opts, pd_ctx** out) {
       !std::isfinite(dom->R) || !std::isfinite(dom->L) || dom->capacity < 1 ||
       dom->capacity > (int64_t)kScanChunk * kScanMaxBlocks)
     return fail(set_err(c, PD_EINVAL, "invalid domain"));
-  if (opts->precision != PD_FP64_DET || opts->poisson != PD_POISSON_DIRECT64)
+  if (opts->precision != PD_FP64_DET ||
+      (opts->poisson != PD_POISSON_DIRECT64 && opts->poisson != PD_POISSON_MGPCG) ||
+      !(opts->poisson_rtol >= 0.0) || !std::isfinite(opts->poisson_rtol))
     return fail(set_err(c, PD_EINVAL, "unsupported precision or Poisson mode"));
+  c->mg_on = opts->poisson == PD_POISSON_MGPCG;
   if (opts->stream) {
     c->stream = (hipStream_t)opts->stream;
   } else {
@@ -368,6 +523,7 @@ pd_status pd_create(const pd_domain* dom, const pd_opts* opts, pd_ctx** out) {
   c->fw.tcp = dtc;
   c->fw.qunit = c->qunit;
   c->cpar.Vcell = dVc;
+  if ((s = build_mg(c, dVn))) return fail(s);
 
   DevState h{};
   if (hipMemcpy(c->st, &h, sizeof h, hipMemcpyHostToDevice) != hipSuccess)
@@ -545,7 +701,10 @@ pd_status pd_step(pd_ctx* c, int nsteps) {
     mark();
     if (!c->opts.deposit_off) deposit(c->A, c->st, c->off, c->g, c->spp, c->fw.Q, c->cap, s);
     mark();
-    poisson_direct(c->g, c->fw, s);
+    {
+      pd_status ps = solve_poisson(c);
+      if (ps) return ps;
+    }
     mark();
     field(c->g, c->fw, s);
     mark();
@@ -638,6 +797,13 @@ pd_status pd_get_diagnostics(pd_ctx* c, pd_diag* out) {
       out->absorbed[b][k] = (int64_t)h.absorbed[b * kNS + k];
       out->charge_absorbed += out->absorbed[b][k] * c->spp.Z[k];
     }
+  mg_residual(c->mg, c->fw.phi, c->fw.Q, c->stream);
+  if ((s = read_mg(c))) return s;
+  out->poisson_rel_res = c->h_sc->rel;
+  out->poisson_solves = c->p_solves;
+  out->poisson_iters = c->h_sc->iters;
+  out->poisson_refinements = c->h_sc->outer;
+  out->poisson_fallbacks = c->p_fallbacks;
   const double N0 = (double)counts[PD_CU], N1 = (double)counts[PD_CU1];
   const double N2 = (double)(counts[PD_CU2_STEP] + counts[PD_CU2_DOUBLE] + counts[PD_CU2_INIT]);
   out->gamma = (N0 + N1 + N2) > 0 ? (N1 + N2) / ((N0 + N1) + N2) : 0.0;
@@ -712,6 +878,27 @@ pd_status pd_get_field(pd_ctx* c, double* phi, double* Er, double* Ez, int64_t* 
   return PD_OK;
 }
 
+pd_status pd_poisson(pd_ctx* c, const int64_t* Q, double* phi, int32_t* iters, double* rel_res) {
+  if (!c) return PD_EINVAL;
+  if (c->poisoned) return set_err(c, PD_ESTATE, "context unusable after an earlier error");
+  if (!Q) return set_err(c, PD_EINVAL, "Q is NULL");
+  pd_status s = sync(c);
+  if (s) return s;
+  const size_t nn = (size_t)(c->g.nr + 1) * (c->g.nz + 1);
+  HIPCHK(c, hipMemcpy(c->fw.Q, Q, 8 * nn, hipMemcpyHostToDevice));
+  if ((s = read_mg(c))) return s;
+  const int it0 = c->h_sc->iters;
+  if ((s = solve_poisson(c))) return s;
+  field(c->g, c->fw, c->stream);
+  mg_residual(c->mg, c->fw.phi, c->fw.Q, c->stream);
+  HIPCHK(c, hipGetLastError());
+  if ((s = read_mg(c))) return s;
+  if (iters) *iters = c->h_sc->iters - it0;
+  if (rel_res) *rel_res = c->h_sc->rel;
+  if (phi) HIPCHK(c, hipMemcpy(phi, c->fw.phi, 8 * nn, hipMemcpyDeviceToHost));
+  return PD_OK;
+}
+
 pd_status pd_get_timing(pd_ctx* c, double* ms, int64_t* steps, int reset) {
   if (!c) return PD_EINVAL;
   if (!c->opts.timing) return set_err(c, PD_ESTATE, "timing was not enabled");
@@ -738,6 +925,7 @@ void pd_destroy(pd_ctx* c) {
   for (auto e : c->ev_pool) (void)hipEventDestroy(e);
   for (void* p : c->sched_allocs) (void)hipFree(p);
   for (void* p : c->allocs) (void)hipFree(p);
+  if (c->h_sc) (void)hipHostFree(c->h_sc);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }

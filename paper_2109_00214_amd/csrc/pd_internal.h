@@ -134,6 +134,51 @@ void deposit(const Parts& P, const DevState* st, const uint32_t* off, const Grid
              const SpeciesParams& sp, int64_t* Q, int64_t cap, hipStream_t s);
 void poisson_direct(const Grid& g, FieldWork& fw, hipStream_t s);
 size_t poisson_lds_bytes(int nr, int nz);
+
+// ---- multigrid-preconditioned CG with FP64 refinement (k_mgpcg.hip) ----
+constexpr int kMGBlock = 256;
+constexpr int kMGParts = 1024;          // most blocks of a reducing launch
+constexpr int kMGMaxLevels = 12;
+constexpr size_t kMGCoarseLds = 96 * 1024;  // LDS of the one-workgroup coarse cycle
+
+// one grid level: nodes (nr+1) x (nz+1), rows 0 and nz are the (zero)
+// Dirichlet rows; operator coefficients per radial node
+struct MGLevel {
+  int nr, nz;
+  float* x;              // V-cycle result (level 0: the preconditioned residual z)
+  const float* b;        // right-hand side (level 0: the CG residual r)
+  const float *ew, *ee, *ez, *dinv;
+};
+// level-0 operator in FP64 for the refinement residual
+struct MGOp64 {
+  int nr, nz;
+  const double *ew, *ee, *ez, *dg, *w, *Vnode;
+  double qunit;
+};
+// device scalars of a solve
+struct MGScal {
+  double rnorm, rel, rtol;
+  float rz_old, alpha, beta, tol2;
+  int it, inner_max, done, conv;
+  int iters, outer;      // cumulative CG iterations and refinements
+  unsigned ticket[4];
+};
+struct MGWork {
+  int nlev, lc, coarse_sweeps;
+  MGLevel lev[kMGMaxLevels];
+  MGOp64 op;
+  float *xc, *s, *p, *q;  // CG solution, A z, search direction, A p
+  float* part;            // [kMGParts * 4]
+  double* part64;         // [kMGParts * 2]
+  MGScal* sc;
+};
+size_t mg_coarse_lds_bytes(const MGWork& w);
+void mg_configure(MGWork& w);
+// sc->rnorm, rel, conv of phi for the node charge Q
+void mg_residual(const MGWork& w, const double* phi, const int64_t* Q, hipStream_t s);
+// one refinement: FP32 PCG (at most `inner` iterations) on the scaled FP64
+// residual, phi += correction, new residual
+void mg_outer(MGWork& w, double* phi, const int64_t* Q, int inner, hipStream_t s);
 void field(const Grid& g, FieldWork& fw, hipStream_t s);
 void push(const Parts& P, DevState* st, const Grid& g, const SpeciesParams& sp,
           const FieldWork& fw, int64_t cap, hipStream_t s);

@@ -17,13 +17,13 @@ PD_OK, PD_EINVAL, PD_ENOMEM, PD_EDEVICE, PD_ESTATE, PD_ENOCONV, PD_ECAPACITY = 0
 STATUS_NAMES = {0: "PD_OK", -1: "PD_EINVAL", -2: "PD_ENOMEM", -3: "PD_EDEVICE", -4: "PD_ESTATE",
                 -5: "PD_ENOCONV", -6: "PD_ECAPACITY"}
 PD_FP64_DET = 0
-PD_POISSON_DIRECT64 = 0
+PD_POISSON_DIRECT64, PD_POISSON_MGPCG = 0, 1
 TIMER_NAMES = ("radix", "permute", "offsets", "collide", "deposit", "poisson", "field", "push",
                "inject")
 EXPORTED = ("pd_create", "pd_set_species", "pd_set_cross_section", "pd_inject",
             "pd_schedule_injection", "pd_step", "pd_synchronize", "pd_get_diagnostics",
             "pd_get_spectrum", "pd_get_count", "pd_get_particles", "pd_get_field",
-            "pd_get_timing", "pd_last_error", "pd_destroy")
+            "pd_poisson", "pd_get_timing", "pd_last_error", "pd_destroy")
 
 
 class PdError(RuntimeError):
@@ -41,7 +41,7 @@ class pd_domain(C.Structure):
 class pd_opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("poisson", C.c_int32), ("enable_di", C.c_int32),
                 ("deposit_off", C.c_int32), ("collisions_off", C.c_int32), ("timing", C.c_int32),
-                ("stream", C.c_void_p)]
+                ("stream", C.c_void_p), ("poisson_rtol", C.c_double)]
 
 
 class pd_diag(C.Structure):
@@ -51,7 +51,9 @@ class pd_diag(C.Structure):
                 ("injected", C.c_int64 * 6), ("charge_alive", C.c_int64),
                 ("charge_absorbed", C.c_int64), ("charge_injected", C.c_int64),
                 ("ke_J", C.c_double * 6), ("gamma", C.c_double), ("qbar", C.c_double),
-                ("particle_steps", C.c_int64)]
+                ("particle_steps", C.c_int64), ("poisson_rel_res", C.c_double),
+                ("poisson_solves", C.c_int64), ("poisson_iters", C.c_int64),
+                ("poisson_refinements", C.c_int64), ("poisson_fallbacks", C.c_int64)]
 
 
 _lib = None
@@ -78,6 +80,7 @@ def load_library(path=LIB_PATH):
     lib.pd_get_count.argtypes = [P, C.POINTER(C.c_int64)]
     lib.pd_get_particles.argtypes = [P, C.c_int64] + [P] * 8
     lib.pd_get_field.argtypes = [P, P, P, P, P]
+    lib.pd_poisson.argtypes = [P, P, P, C.POINTER(C.c_int32), C.POINTER(C.c_double)]
     lib.pd_get_timing.argtypes = [P, P, C.POINTER(C.c_int64), C.c_int]
     lib.pd_last_error.argtypes = [P]
     lib.pd_last_error.restype = C.c_char_p
@@ -189,6 +192,18 @@ def pd_get_field(ctx, nr, nz):
             "Q": Q.reshape(shp)}
 
 
+def pd_poisson(ctx, Q, nr, nz):
+    """Solve for node charges Q; returns (phi, CG iterations, relative residual)."""
+    q = np.ascontiguousarray(Q, np.int64).reshape(-1)
+    if q.size != (nr + 1) * (nz + 1):
+        raise ValueError("Q has %d values, the grid %d nodes" % (q.size, (nr + 1) * (nz + 1)))
+    phi = np.zeros(q.size)
+    it = C.c_int32()
+    rel = C.c_double()
+    _check(ctx, load_library().pd_poisson(ctx, _ptr(q), _ptr(phi), C.byref(it), C.byref(rel)))
+    return phi.reshape(nz + 1, nr + 1), it.value, rel.value
+
+
 def pd_get_timing(ctx, reset=False):
     ms = np.zeros(len(TIMER_NAMES))
     steps = C.c_int64()
@@ -211,12 +226,13 @@ class Simulation:
     """One context: the domain of a workload config plus species and tables."""
 
     def __init__(self, cfg, capacity, tables, species, enable_di=None, deposit_off=False,
-                 collisions_off=False, timing=False, stream=None):
+                 collisions_off=False, timing=False, stream=None, poisson=PD_POISSON_DIRECT64,
+                 poisson_rtol=0.0):
         dom = pd_domain(cfg.nr, cfg.nz, cfg.R, cfg.L, cfg.V, cfg.dt, cfg.weight, cfg.seed,
                         int(capacity))
         di = cfg.enable_di if enable_di is None else enable_di
-        opts = pd_opts(PD_FP64_DET, PD_POISSON_DIRECT64, int(di), int(deposit_off),
-                       int(collisions_off), int(timing), stream)
+        opts = pd_opts(PD_FP64_DET, poisson, int(di), int(deposit_off), int(collisions_off),
+                       int(timing), stream, float(poisson_rtol))
         self.cfg = cfg
         self.h = pd_create(dom, opts)
         pd_set_species(self.h, *species)
@@ -249,6 +265,9 @@ class Simulation:
 
     def field(self):
         return pd_get_field(self.h, self.cfg.nr, self.cfg.nz)
+
+    def poisson(self, Q):
+        return pd_poisson(self.h, Q, self.cfg.nr, self.cfg.nz)
 
     def timing(self, reset=False):
         return pd_get_timing(self.h, reset)

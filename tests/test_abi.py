@@ -47,8 +47,9 @@ def test_struct_layouts_match_header():
 #include <stdio.h>
 #include <stddef.h>
 #include "pd.h"
-int main(void){ printf("%zu %zu %zu %zu\n", sizeof(pd_domain), sizeof(pd_opts), sizeof(pd_diag),
-  offsetof(pd_diag, particle_steps)); return 0; }
+int main(void){ printf("%zu %zu %zu %zu %zu %zu\n", sizeof(pd_domain), sizeof(pd_opts), sizeof(pd_diag),
+  offsetof(pd_diag, particle_steps), offsetof(pd_opts, poisson_rtol),
+  offsetof(pd_diag, poisson_fallbacks)); return 0; }
 '''
     with tempfile.TemporaryDirectory() as d:
         c = os.path.join(d, "t.c")
@@ -60,6 +61,8 @@ int main(void){ printf("%zu %zu %zu %zu\n", sizeof(pd_domain), sizeof(pd_opts), 
     assert int(out[1]) == ctypes.sizeof(pd.pd_opts)
     assert int(out[2]) == ctypes.sizeof(pd.pd_diag)
     assert int(out[3]) == pd.pd_diag.particle_steps.offset
+    assert int(out[4]) == pd.pd_opts.poisson_rtol.offset
+    assert int(out[5]) == pd.pd_diag.poisson_fallbacks.offset
 
 
 def test_missing_library_fails_loudly(tmp_path):

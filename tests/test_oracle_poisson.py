@@ -149,3 +149,86 @@ def test_point_charge_field_direction():
     assert phi[16, 8] == phi.max() and phi[16, 8] > 0
     assert f["Ez"][18, 8] > 0 and f["Ez"][14, 8] < 0
     assert f["Er"][16, 10] > 0 and f["Er"][16, 6] < 0
+
+
+def _areas(nr, R):
+    """Integral of r dr over each node's radial control interval."""
+    dr = R / nr
+    lo = np.maximum(np.arange(nr + 1) - 0.5, 0.0) * dr
+    hi = np.minimum(np.arange(nr + 1) + 0.5, nr) * dr
+    return (hi * hi - lo * lo) / 2.0
+
+
+def test_residual_matches_dense_brute_force():
+    """||b - A phi|| and ||b|| against the dense control-volume matrix,
+    with the rows weighted by the node volumes and the electrode values
+    moved to the right-hand side."""
+    nr, nz = 6, 10
+    cfg = W.config("tiny", nr=nr, nz=nz, V=500.0)
+    o = make_oracle(cfg, collisions_off=True)
+    dr, dz = cfg.R / nr, cfg.L / nz
+    rng = np.random.default_rng(3)
+    Q = rng.integers(-2 ** 45, 2 ** 45, size=(nz + 1, nr + 1))
+    phi = rng.normal(size=(nz + 1, nr + 1)) * 100.0
+    Vn, _ = o.node_volumes()
+    rho = Q * (1.602176634e-19 * cfg.weight * 2.0 ** -40) / Vn[None, :]
+    A = _dense_operator(nr, nz, cfg.R, cfg.L)
+    lap = (A @ phi[1:nz].reshape(-1)).reshape(nz - 1, nr + 1)
+    lap[0] += phi[0] / dz ** 2
+    lap[-1] += phi[nz] / dz ** 2
+    w = _areas(nr, cfg.R) * dz
+    r = w[None, :] * (rho[1:nz] / 8.8541878128e-12 + lap)
+    b = w[None, :] * rho[1:nz] / 8.8541878128e-12
+    b[0] += w * phi[0] / dz ** 2
+    b[-1] += w * phi[nz] / dz ** 2
+    rn, bn = o.poisson_residual(Q, phi)
+    assert rn == pytest.approx(np.linalg.norm(r), rel=1e-10)
+    assert bn == pytest.approx(np.linalg.norm(b), rel=1e-12)
+
+
+def test_residual_of_direct_solve_and_vacuum():
+    """The direct solve leaves a residual at rounding level; the vacuum
+    potential with no charge leaves (almost) none, and then ||b|| is the
+    cathode lift alone: V w_i / dz^2 on the first interior row."""
+    for nr, nz in ((8, 16), (32, 64)):
+        cfg = W.config("tiny", nr=nr, nz=nz)
+        o = make_oracle(cfg, collisions_off=True)
+        dz = cfg.L / nz
+        Q0 = np.zeros((nz + 1, nr + 1), np.int64)
+        j = np.arange(nz + 1)
+        vac = np.repeat(((-cfg.V) + cfg.V * (j / nz))[:, None], nr + 1, axis=1)
+        rn, bn = o.poisson_residual(Q0, vac)
+        w = _areas(nr, cfg.R) * dz
+        assert bn == pytest.approx(cfg.V * np.linalg.norm(w) / dz ** 2, rel=1e-12)
+        assert rn <= 1e-13 * bn
+        rng = np.random.default_rng(nr)
+        Q = rng.integers(0, 2 ** 50, size=(nz + 1, nr + 1))
+        o.set_charge(Q)
+        o.stage("poisson")
+        rn, bn = o.poisson_residual(Q, o.field()["phi"])
+        assert rn <= 1e-12 * bn
+
+
+def test_residual_detects_a_perturbed_potential():
+    """Moving one interior node of the exact solution by d changes the
+    residual by exactly the column of A: |r| = d * sqrt(dg^2 + sum of
+    the squared couplings) with the volume weights."""
+    nr, nz = 8, 16
+    cfg = W.config("tiny", nr=nr, nz=nz)
+    o = make_oracle(cfg, collisions_off=True)
+    rng = np.random.default_rng(1)
+    Q = rng.integers(0, 2 ** 50, size=(nz + 1, nr + 1))
+    o.set_charge(Q)
+    o.stage("poisson")
+    phi = o.field()["phi"].copy()
+    dr, dz = cfg.R / nr, cfg.L / nz
+    i, j, d = 3, 7, 1e-3
+    phi[j, i] += d
+    rn, _ = o.poisson_residual(Q, phi)
+    w = _areas(nr, cfg.R) * dz
+    ew = lambda k: (k - 0.5) * dr * dz / dr  # noqa: E731
+    ee = lambda k: (k + 0.5) * dr * dz / dr  # noqa: E731
+    ez = lambda k: w[k] / dz ** 2  # noqa: E731
+    dg = ew(i) + ee(i) + 2 * ez(i)
+    col = [dg, ee(i - 1), ew(i + 1), ez(i), ez(i)]
+    assert rn == pytest.approx(d * np.sqrt(np.sum(np.square(col))), rel=1e-6)
