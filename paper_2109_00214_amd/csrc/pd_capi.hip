@@ -67,7 +67,7 @@ struct pd_ctx {
   MGWork mg{};
   MGScal* h_sc = nullptr;  // pinned host copy of the solve scalars
   bool mg_on = false;
-  int mg_inner = 8, mg_outer_max = 8;
+  int mg_inner = 8, mg_inner_max = 16, mg_outer_max = 8;
   int64_t p_solves = 0, p_fallbacks = 0;
 
   // timing
@@ -257,15 +257,14 @@ pd_status build_mg(pd_ctx* c, const double* dVnode) {
       return set_err(c, PD_EDEVICE, "upload");
   }
   w.op = MGOp64{nr, nz, d[0], d[1], d[2], d[3], d[4], dVnode, c->qunit};
-  if ((s = dalloc(c, &w.sc, 1)) || (s = dalloc(c, &w.part, (size_t)kMGParts * 4)) ||
+  if ((s = dalloc(c, &w.sc, 1)) || (s = dalloc(c, &w.part, (size_t)kMGParts * 5)) ||
       (s = dalloc(c, &w.part64, (size_t)kMGParts * 2)))
     return s;
   if (hipHostMalloc((void**)&c->h_sc, sizeof(MGScal), 0) != hipSuccess)
     return set_err(c, PD_ENOMEM, "pinned host memory");
   MGScal h0{};
   h0.rtol = c->opts.poisson_rtol > 0 ? c->opts.poisson_rtol : 1e-8;
-  h0.tol2 = 1e-8f;  // inner solve: ||r||/||r0|| <= 1e-4
-  h0.inner_max = c->mg_inner;
+  h0.tol2 = 1e-10f;  // inner solve: ||r|| / ||r0|| <= 1e-5 (||r0|| = 1)
   h0.done = 1;
   if (hipMemcpy(w.sc, &h0, sizeof h0, hipMemcpyHostToDevice) != hipSuccess)
     return set_err(c, PD_EDEVICE, "upload");
@@ -276,15 +275,16 @@ pd_status build_mg(pd_ctx* c, const double* dVnode) {
          (nr >> (nl - 1)) >= 4 && (nz >> (nl - 1)) >= 4)
     ++nl;
   w.nlev = nl;
-  w.coarse_sweeps = 8;
+  w.coarse_sweeps = 4;
   w.lc = -1;
   for (int l = 0; l < nl && w.lc < 0; ++l) {
     size_t b = 0;
-    for (int k = l; k < nl; ++k) b += 2 * sizeof(float) * (size_t)((nr >> k) + 1) * ((nz >> k) + 1);
-    if (b <= kMGCoarseLds) w.lc = l;
+    for (int k = l; k < nl; ++k) b += (size_t)((nr >> k) + 1) * ((nz >> k) + 1);
+    if (b <= (size_t)kMGCoarseNodes) w.lc = l;
   }
   if (w.lc < 0)
-    return set_err(c, PD_EINVAL, "multigrid: grid %dx%d cannot be coarsened into LDS", nr, nz);
+    return set_err(c, PD_EINVAL, "multigrid: grid %dx%d does not coarsen to %d nodes", nr, nz,
+                   kMGCoarseNodes);
   for (int l = 0; l < nl; ++l) {
     const int a = nr >> l, b = nz >> l;
     const size_t nn = (size_t)(a + 1) * (b + 1);
@@ -312,6 +312,56 @@ pd_status build_mg(pd_ctx* c, const double* dVnode) {
     m.ee = dt + (a + 1);
     m.ez = dt + 2 * (a + 1);
     m.dinv = dt + 3 * (a + 1);
+  }
+  // exact coarsest solve: the inverse of the coarsest operator (FP64
+  // Gauss-Jordan with partial pivoting, stored in FP32)
+  w.coarsest_inv = nullptr;
+  {
+    const int a = nr >> (nl - 1), b = nz >> (nl - 1), W = a + 1, n = W * (b - 1);
+    if (n <= kMGCoarsestDense) {
+      std::vector<double> lew, lee, lez, lw, A((size_t)n * n, 0.0), I((size_t)n * n, 0.0);
+      weighted_operator(a, b, c->dom.R, c->dom.L, lew, lee, lez, lw);
+      for (int j = 1; j < b; ++j)
+        for (int i = 0; i <= a; ++i) {
+          const int k = (j - 1) * W + i;
+          A[(size_t)k * n + k] = (lew[i] + lee[i]) + (2.0 * lez[i]);
+          if (i > 0) A[(size_t)k * n + k - 1] = -lew[i];
+          if (i < a) A[(size_t)k * n + k + 1] = -lee[i];
+          if (j > 1) A[(size_t)k * n + k - W] = -lez[i];
+          if (j < b - 1) A[(size_t)k * n + k + W] = -lez[i];
+          I[(size_t)k * n + k] = 1.0;
+        }
+      for (int col = 0; col < n; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < n; ++r)
+          if (std::fabs(A[(size_t)r * n + col]) > std::fabs(A[(size_t)piv * n + col])) piv = r;
+        for (int k = 0; k < n; ++k) {
+          std::swap(A[(size_t)col * n + k], A[(size_t)piv * n + k]);
+          std::swap(I[(size_t)col * n + k], I[(size_t)piv * n + k]);
+        }
+        const double d = A[(size_t)col * n + col];
+        for (int k = 0; k < n; ++k) {
+          A[(size_t)col * n + k] /= d;
+          I[(size_t)col * n + k] /= d;
+        }
+        for (int r = 0; r < n; ++r) {
+          if (r == col) continue;
+          const double f = A[(size_t)r * n + col];
+          if (f == 0.0) continue;
+          for (int k = 0; k < n; ++k) {
+            A[(size_t)r * n + k] -= f * A[(size_t)col * n + k];
+            I[(size_t)r * n + k] -= f * I[(size_t)col * n + k];
+          }
+        }
+      }
+      std::vector<float> inv((size_t)n * n);
+      for (size_t k = 0; k < inv.size(); ++k) inv[k] = (float)I[k];
+      float* d;
+      if ((s = dalloc(c, &d, inv.size()))) return s;
+      if (hipMemcpy(d, inv.data(), 4 * inv.size(), hipMemcpyHostToDevice) != hipSuccess)
+        return set_err(c, PD_EDEVICE, "upload");
+      w.coarsest_inv = d;
+    }
   }
   const size_t n0 = (size_t)(nr + 1) * (nz + 1);
   float** v[4] = {&w.xc, &w.s, &w.p, &w.q};
@@ -343,17 +393,22 @@ pd_status solve_poisson(pd_ctx* c) {
     poisson_direct(c->g, c->fw, s);
     return PD_OK;
   }
+  // the first refinement is enqueued without waiting: a warm start that
+  // already meets the tolerance turns it into no-ops on the device
   mg_residual(c->mg, c->fw.phi, c->fw.Q, s);
   for (int o = 0;; ++o) {
+    mg_outer(c->mg, c->fw.phi, c->fw.Q, c->mg_inner, s);
     pd_status st = read_mg(c);
     if (st) return st;
+    // CG iterations for the next refinement: one more than the last took
+    const int used = c->h_sc->it_last;
+    c->mg_inner = std::min(c->mg_inner_max, std::max(2, used + (used >= c->mg_inner ? 2 : 1)));
     if (c->h_sc->conv) break;
-    if (o == c->mg_outer_max) {
+    if (o + 1 == c->mg_outer_max) {
       poisson_direct(c->g, c->fw, s);
       c->p_fallbacks += 1;
       break;
     }
-    mg_outer(c->mg, c->fw.phi, c->fw.Q, c->mg_inner, s);
   }
   return PD_OK;
 }

@@ -139,7 +139,7 @@ size_t poisson_lds_bytes(int nr, int nz);
 constexpr int kMGBlock = 256;
 constexpr int kMGParts = 1024;          // most blocks of a reducing launch
 constexpr int kMGMaxLevels = 12;
-constexpr size_t kMGCoarseLds = 96 * 1024;  // LDS of the one-workgroup coarse cycle
+constexpr int kMGCoarseNodes = 3072;    // nodes of the levels the one-workgroup cycle takes
 
 // one grid level: nodes (nr+1) x (nz+1), rows 0 and nz are the (zero)
 // Dirichlet rows; operator coefficients per radial node
@@ -157,18 +157,21 @@ struct MGOp64 {
 };
 // device scalars of a solve
 struct MGScal {
-  double rnorm, rel, rtol;
-  float rz_old, alpha, beta, tol2;
-  int it, inner_max, done, conv;
-  int iters, outer;      // cumulative CG iterations and refinements
-  unsigned ticket[4];
+  double rnorm, rel, rtol;  // ||b - A phi||, its ratio to ||b||, target ratio
+  float tol2;               // inner stop: ||r||^2 of the scaled correction solve
+  float rz[2];              // r.z of the last two CG iterations (slot it & 1)
+  int done, conv;           // CG stopped; refinement converged
+  int iters, outer;         // cumulative CG iterations and refinements
+  int it_last;              // CG iterations of the latest refinement
 };
+constexpr int kMGCoarsestDense = 64;    // coarsest unknowns solved by a dense inverse
 struct MGWork {
   int nlev, lc, coarse_sweeps;
+  const float* coarsest_inv;  // [n x n] or NULL (then coarse_sweeps sweeps)
   MGLevel lev[kMGMaxLevels];
   MGOp64 op;
   float *xc, *s, *p, *q;  // CG solution, A z, search direction, A p
-  float* part;            // [kMGParts * 4]
+  float* part;            // [kMGParts * 5]: CG partials (4 dots, then r.r)
   double* part64;         // [kMGParts * 2]
   MGScal* sc;
 };

@@ -63,7 +63,7 @@ def kernel_stats_text(d, cmd):
            "%-56s %7s %10s %10s %6s" % ("kernel", "calls", "avg_us", "total_ms", "pct")]
     for r in rows:
         out.append("%-56s %7s %10.2f %10.2f %6.2f" % (
-            r["Name"].split("(")[0][:56], r["Calls"], float(r["AverageNs"]) / 1e3,
+            r["Name"].replace("(anonymous namespace)::", "").split("(")[0][:56], r["Calls"], float(r["AverageNs"]) / 1e3,
             float(r["TotalDurationNs"]) / 1e6, float(r["Percentage"])))
     return "\n".join(out)
 
@@ -71,7 +71,7 @@ def kernel_stats_text(d, cmd):
 def _per_kernel(d):
     vals = defaultdict(list)
     for r in csv.DictReader(open(_csv(d, "counter_collection.csv"))):
-        vals[r["Kernel_Name"].split("(")[0]].append(float(r["Counter_Value"]))
+        vals[r["Kernel_Name"].replace("(anonymous namespace)::", "").split("(")[0]].append(float(r["Counter_Value"]))
     return vals
 
 
