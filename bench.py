@@ -23,13 +23,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes per particle and launch (FP64 record: r, z, vr, vt, vz = 40 B,
-# species 1 B, id 4 B, key 4 B)
-ALGO_BYTES = {
-    "push": 41 + 40 + 4,          # read state + species, write state + key
-    "permute": 4 + 4 + 45 + 49,   # read key + perm + record, write record + key
-    "deposit": 8 + 8 + 1,         # read r, z, species
-}
+# algorithmic bytes per particle and launch, by the real type's size F (the
+# record: r, z, vr, vt, vz = 5F, species 1 B, id 4 B, key 4 B)
+def algo_bytes(F):
+    return {
+        "push": (5 * F + 1) + 5 * F + 4,              # read state + species, write state + key
+        "permute": 4 + 4 + (5 * F + 5) + (5 * F + 9),  # read key + perm + record, write record + key
+        "deposit": 2 * F + 1,                          # read r, z, species
+    }
 
 
 def parse():
@@ -41,6 +42,8 @@ def parse():
     ap.add_argument("--n-init", type=int, default=None)
     ap.add_argument("--poisson", choices=("direct", "mgpcg"), default="direct",
                     help="direct FP64 solve, or FP32 multigrid CG with FP64 refinement")
+    ap.add_argument("--precision", choices=("fp64", "fp32"), default="fp64",
+                    help="FP64 deterministic, or the FP32 particle record (FP32 gather/push)")
     ap.add_argument("--cpu-steps", type=int, default=40,
                     help="oracle steps timed for the CPU baseline (0: skip)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles",
@@ -87,7 +90,8 @@ def main():
     import torch
 
     from paper_2109_00214_amd import workload as W
-    from paper_2109_00214_amd.pd import PD_POISSON_DIRECT64, PD_POISSON_MGPCG, Simulation
+    from paper_2109_00214_amd.pd import (PD_FP32_MIXED, PD_FP64_DET, PD_POISSON_DIRECT64,
+                                         PD_POISSON_MGPCG, Simulation)
 
     kw = {} if a.n_init is None else {"n_init": a.n_init}
     cfg = W.config(a.config, **kw)
@@ -102,7 +106,8 @@ def main():
     cap = int(1.25 * cfg.n_init + cfg.inj_cu * nsteps + 40 * cfg.inj_e + 1_000_000)
     sim = Simulation(cfg, cap, W.cross_section_tables(), W.species_table(), timing=True,
                      stream=stream.cuda_stream,
-                     poisson=PD_POISSON_MGPCG if a.poisson == "mgpcg" else PD_POISSON_DIRECT64)
+                     poisson=PD_POISSON_MGPCG if a.poisson == "mgpcg" else PD_POISSON_DIRECT64,
+                     precision=PD_FP32_MIXED if a.precision == "fp32" else PD_FP64_DET)
     sim.inject(parts)
     sim.schedule_injection(off, inj)
     sim.step(a.warmup)
@@ -125,6 +130,7 @@ def main():
     per_step = {k: v / max(tsteps, 1) for k, v in stages.items()}
     print("stage ms/step: " + ", ".join("%s %.4f" % kv for kv in per_step.items()), file=sys.stderr)
     # roofline of the dominant single-kernel stage
+    ALGO_BYTES = algo_bytes(4 if a.precision == "fp32" else 8)
     cand = {k: per_step[k] for k in ALGO_BYTES}
     dom = max(cand, key=cand.get)
     units = pst / a.steps
@@ -132,8 +138,8 @@ def main():
     # HBM bytes per launch from the counters, if taken on this workload and
     # on the kernel as it is now
     from paper_2109_00214_amd.profiling import read_traffic
-    traffic = read_traffic(a.traffic).get(dom) if cfg.name == "paper" and a.n_init is None \
-        else None
+    traffic = read_traffic(a.traffic).get(dom) if (cfg.name == "paper" and a.n_init is None and
+                                                    a.precision == "fp64") else None
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "bytes_per_particle": ALGO_BYTES[dom], "particles_per_launch": round(units)}
@@ -148,12 +154,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32" if a.precision == "fp32" else "f64",
         "data": "synthetic",
         "config": {"workload": "%s: %dx%d r-z cells, %d initial super-particles, W=%g, "
-                               "%d injected/step, FP64 deterministic" %
+                               "%d injected/step, %s" %
                                (cfg.name, cfg.nr, cfg.nz, cfg.n_init, cfg.weight,
-                                cfg.inj_e + cfg.inj_cu),
+                                cfg.inj_e + cfg.inj_cu,
+                                "FP32 record/gather/push, FP64 collisions" if a.precision == "fp32"
+                                else "FP64 deterministic"),
                    "poisson": ("direct FP64 (sine transform + tridiagonal)"
                                if a.poisson == "direct" else
                                "FP32 multigrid-preconditioned CG, FP64 refinement, rtol 1e-8"),

@@ -110,7 +110,9 @@ __device__ inline void binary(double v1[3], double v2[3], double two_dE_mr, doub
   }
 }
 
-__global__ void __launch_bounds__(256) k_decide(Parts P, const uint32_t* off, const DevState* st,
+// (T: precision of the particle record; the collision arithmetic is FP64)
+template <typename T>
+__global__ void __launch_bounds__(256) k_decide(PartsT<T> P, const uint32_t* off, const DevState* st,
                                                 Grid g, CollideParams cp, uint8_t* choice,
                                                 uint32_t* target, uint32_t* claim,
                                                 uint32_t* scan_len) {
@@ -136,7 +138,8 @@ __global__ void __launch_bounds__(256) k_decide(Parts P, const uint32_t* off, co
     const double Vc = cp.Vcell[ci];
     // Cu target: EL, SI, DI share the pick and the relative speed
     if (n_cu > 0) {
-      const double dvr = evr - P.vr[tc], dvt = evt - P.vt[tc], dvz = evz - P.vz[tc];
+      const double dvr = evr - (double)P.vr[tc], dvt = evt - (double)P.vt[tc],
+                   dvz = evz - (double)P.vz[tc];
       const double gg = sqrt(((dvr * dvr) + (dvt * dvt)) + (dvz * dvz));
       const double dens = ((double)n_cu * cp.W) / Vc;
 #pragma unroll
@@ -146,7 +149,8 @@ __global__ void __launch_bounds__(256) k_decide(Parts P, const uint32_t* off, co
       }
     }
     if (n_c1 > 0) {
-      const double dvr = evr - P.vr[t1], dvt = evt - P.vt[t1], dvz = evz - P.vz[t1];
+      const double dvr = evr - (double)P.vr[t1], dvt = evt - (double)P.vt[t1],
+                   dvz = evz - (double)P.vz[t1];
       const double gg = sqrt(((dvr * dvr) + (dvt * dvt)) + (dvz * dvz));
       const double dens = ((double)n_c1 * cp.W) / Vc;
       x[3] = ((cp.dt * gg) * dens) * sigma_of(cp, 3, gg);
@@ -216,7 +220,8 @@ __global__ void __launch_bounds__(256) k_resolve(const uint32_t* off, DevState* 
   }
 }
 
-__global__ void __launch_bounds__(256) k_apply(Parts P, const uint32_t* off, DevState* st, Grid g,
+template <typename T>
+__global__ void __launch_bounds__(256) k_apply(PartsT<T> P, const uint32_t* off, DevState* st, Grid g,
                                                CollideParams cp, const uint8_t* choice,
                                                const uint32_t* target, const uint32_t* cbase,
                                                uint32_t* claim, uint32_t cap) {
@@ -238,13 +243,13 @@ __global__ void __launch_bounds__(256) k_apply(Parts P, const uint32_t* off, Dev
     // stage 1: elastic, or inelastic losing the channel threshold (Eq. 12)
     isotropic(cp, id, step, 2u, nh);
     binary(e1, A, cp.two_dE_mr[ch], cp.f1[ch], cp.f2[ch], nh);
-    P.vr[tp] = A[0];
-    P.vt[tp] = A[1];
-    P.vz[tp] = A[2];
+    P.vr[tp] = (T)A[0];
+    P.vt[tp] = (T)A[1];
+    P.vz[tp] = (T)A[2];
     if (ch == 0) {
-      P.vr[e] = e1[0];
-      P.vt[e] = e1[1];
-      P.vz[e] = e1[2];
+      P.vr[e] = (T)e1[0];
+      P.vt[e] = (T)e1[1];
+      P.vz[e] = (T)e1[2];
       continue;
     }
     // stage 2 (Eq. 13): the target keeps its slot and id, changes label;
@@ -258,9 +263,9 @@ __global__ void __launch_bounds__(256) k_apply(Parts P, const uint32_t* off, Dev
     const uint32_t nid = next_id + cbase[e];
     P.r[slot] = P.r[tp];
     P.z[slot] = P.z[tp];
-    P.vr[slot] = e2[0];
-    P.vt[slot] = e2[1];
-    P.vz[slot] = e2[2];
+    P.vr[slot] = (T)e2[0];
+    P.vt[slot] = (T)e2[1];
+    P.vz[slot] = (T)e2[2];
     P.sp[slot] = 0;
     P.id[slot] = nid;
     if (ch == 2) {
@@ -272,32 +277,37 @@ __global__ void __launch_bounds__(256) k_apply(Parts P, const uint32_t* off, Dev
       const uint32_t s6 = slot + 1;
       P.r[s6] = P.r[e];
       P.z[s6] = P.z[e];
-      P.vr[s6] = e1[0] - v5[0];
-      P.vt[s6] = e1[1] - v5[1];
-      P.vz[s6] = e1[2] - v5[2];
+      P.vr[s6] = (T)(e1[0] - v5[0]);
+      P.vt[s6] = (T)(e1[1] - v5[1]);
+      P.vz[s6] = (T)(e1[2] - v5[2]);
       P.sp[s6] = 0;
       P.id[s6] = nid + 1;
       e1[0] = v5[0];
       e1[1] = v5[1];
       e1[2] = v5[2];
     }
-    P.vr[e] = e1[0];
-    P.vt[e] = e1[1];
-    P.vz[e] = e1[2];
+    P.vr[e] = (T)e1[0];
+    P.vt[e] = (T)e1[1];
+    P.vz[e] = (T)e1[2];
   }
 }
 
-void collide(const Parts& P, const uint32_t* off, DevState* st, const Grid& g,
+template <typename T>
+void collide(const PartsT<T>& P, const uint32_t* off, DevState* st, const Grid& g,
              const CollideParams& cp, CollideWork& w, uint32_t* bsum, int64_t cap, hipStream_t s) {
   const int gr = grid_for(cap);
-  k_decide<<<gr, 256, 0, s>>>(P, off, st, g, cp, w.choice, w.target, w.claim, w.scan_len);
+  k_decide<T><<<gr, 256, 0, s>>>(P, off, st, g, cp, w.choice, w.target, w.claim, w.scan_len);
   k_resolve<<<gr, 256, 0, s>>>(off, st, g, w.choice, w.target, w.claim, w.ccount);
   // created-electron slots; the scan's guard flags an overflow and then
   // creates nothing, so every later launch touches only [0, n_alive)
   scan_exclusive(w.ccount, w.cbase, w.scan_len, &st->n_created, bsum, cap, s, st,
                  (uint32_t)cap);
-  k_apply<<<gr, 256, 0, s>>>(P, off, st, g, cp, w.choice, w.target, w.cbase, w.claim,
-                             (uint32_t)cap);
+  k_apply<T><<<gr, 256, 0, s>>>(P, off, st, g, cp, w.choice, w.target, w.cbase, w.claim,
+                                (uint32_t)cap);
 }
+template void collide<double>(const Parts&, const uint32_t*, DevState*, const Grid&,
+                              const CollideParams&, CollideWork&, uint32_t*, int64_t, hipStream_t);
+template void collide<float>(const PartsF&, const uint32_t*, DevState*, const Grid&,
+                             const CollideParams&, CollideWork&, uint32_t*, int64_t, hipStream_t);
 
 }  // namespace pd

@@ -14,16 +14,17 @@ static inline int grid_for(int64_t n, int block = 256) {
   return (int)g;
 }
 
-// cell and in-cell fractions: i = min((int)(r/dr), nr-1), fr = r/dr - i
-__device__ inline void cell_of(const Grid& g, double r, double z, int& i, int& j, double& fr,
-                               double& fz) {
-  const double xr = r / g.dr, xz = z / g.dz;
+// cell and in-cell fractions: i = min((int)(r/dr), nr-1), fr = r/dr - i,
+// in the precision T of the particle record
+template <typename T>
+__device__ inline void cell_of(const Grid& g, T r, T z, int& i, int& j, T& fr, T& fz) {
+  const T xr = r / (T)g.dr, xz = z / (T)g.dz;
   i = (int)xr;
   j = (int)xz;
   if (i > g.nr - 1) i = g.nr - 1;
   if (j > g.nz - 1) j = g.nz - 1;
-  fr = xr - (double)i;
-  fz = xz - (double)j;
+  fr = xr - (T)i;
+  fz = xz - (T)j;
 }
 
 // ---------------------------------------------------------------------------
@@ -36,8 +37,11 @@ __device__ inline void cell_of(const Grid& g, double r, double z, int& i, int& j
 // node charges do not depend on this grouping.  Waves holding only neutral
 // particles (the long Cu run of the species-major order) read the species
 // byte and nothing else.  (The Cu run cannot be skipped by offsets alone:
-// collisions ionize targets inside it in place.)
-__global__ void __launch_bounds__(256) k_deposit(Parts P, const DevState* st, Grid g,
+// collisions ionize targets inside it in place.)  In the FP32 form the
+// fractions come from the FP32 positions; the rounding to 2^-20 is the
+// same, so the node charges stay exact integers.
+template <typename T>
+__global__ void __launch_bounds__(256) k_deposit(PartsT<T> P, const DevState* st, Grid g,
                                                  SpeciesParams spp, unsigned long long* Q) {
   const uint32_t n = st->n_alive + st->n_created;
   const int W = g.nr + 1;
@@ -51,10 +55,10 @@ __global__ void __launch_bounds__(256) k_deposit(Parts P, const DevState* st, Gr
     long long v0 = 0, v1 = 0, v2 = 0, v3 = 0;
     if (Zp != 0) {
       int i, j;
-      double fr, fz;
-      cell_of(g, P.r[p], P.z[p], i, j, fr, fz);
-      const long long ar = (long long)floor((fr * 1048576.0) + 0.5), br = 1048576 - ar;
-      const long long az = (long long)floor((fz * 1048576.0) + 0.5), bz = 1048576 - az;
+      T fr, fz;
+      cell_of<T>(g, P.r[p], P.z[p], i, j, fr, fz);
+      const long long ar = (long long)floor((fr * (T)1048576) + (T)0.5), br = 1048576 - ar;
+      const long long az = (long long)floor((fz * (T)1048576) + (T)0.5), bz = 1048576 - az;
       b = j * W + i;
       v0 = Zp * (br * bz);
       v1 = Zp * (ar * bz);
@@ -102,16 +106,23 @@ void fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
   k_fill_u32<<<grid_for(n), 256, 0, s>>>(p, v, n);
 }
 
-void deposit(const Parts& P, const DevState* st, const uint32_t* off, const Grid& g,
+template <typename T>
+void deposit(const PartsT<T>& P, const DevState* st, const uint32_t* off, const Grid& g,
              const SpeciesParams& sp, int64_t* Q, int64_t cap, hipStream_t s) {
   (void)off;  // Q was cleared by the offsets launch
-  k_deposit<<<grid_for(cap), 256, 0, s>>>(P, st, g, sp, (unsigned long long*)Q);
+  k_deposit<T><<<grid_for(cap), 256, 0, s>>>(P, st, g, sp, (unsigned long long*)Q);
 }
+template void deposit<double>(const Parts&, const DevState*, const uint32_t*, const Grid&,
+                              const SpeciesParams&, int64_t*, int64_t, hipStream_t);
+template void deposit<float>(const PartsF&, const DevState*, const uint32_t*, const Grid&,
+                             const SpeciesParams&, int64_t*, int64_t, hipStream_t);
 
 // E = -grad(phi): central differences, second-order one-sided at the
-// electrodes, E_r = 0 on the axis and at the wall
+// electrodes, E_r = 0 on the axis and at the wall; FP32 copies for the FP32
+// push when Erf is not NULL
 __global__ void __launch_bounds__(256) k_field(const double* phi, int nr, int nz, double dr,
-                                               double dz, double* Er, double* Ez) {
+                                               double dz, double* Er, double* Ez, float* Erf,
+                                               float* Ezf) {
   const int W = nr + 1;
   const int n = (nz + 1) * W;
   const double tdz = 2.0 * dz, tdr = 2.0 * dr;
@@ -124,12 +135,17 @@ __global__ void __launch_bounds__(256) k_field(const double* phi, int nr, int nz
     const double er = (i == 0 || i == nr) ? 0.0 : (phi[b - 1] - phi[b + 1]) / tdr;
     Ez[b] = ez;
     Er[b] = er;
+    if (Erf) {
+      Ezf[b] = (float)ez;
+      Erf[b] = (float)er;
+    }
   }
 }
 
 void field(const Grid& g, FieldWork& fw, hipStream_t s) {
   const int64_t n = (int64_t)(g.nr + 1) * (g.nz + 1);
-  k_field<<<grid_for(n), 256, 0, s>>>(fw.phi, g.nr, g.nz, g.dr, g.dz, fw.Er, fw.Ez);
+  k_field<<<grid_for(n), 256, 0, s>>>(fw.phi, g.nr, g.nz, g.dr, g.dz, fw.Er, fw.Ez, fw.Erf,
+                                      fw.Ezf);
 }
 
 // ---------------------------------------------------------------------------
@@ -146,38 +162,42 @@ __device__ inline void count_codes(int code, unsigned long long* ctr) {
   }
 }
 
-__global__ void __launch_bounds__(256) k_push(Parts P, DevState* st, Grid g, SpeciesParams spp,
-                                              const double* Er, const double* Ez) {
+// gather (bilinear, the deposit's weights) and leapfrog push in the record's
+// precision T: v += (q/m) E dt, Cartesian move, rotation back to the r-z
+// plane; absorbed particles get the sentinel key, the others their new key
+template <typename T>
+__global__ void __launch_bounds__(256) k_push(PartsT<T> P, DevState* st, Grid g, SpeciesParams spp,
+                                              const T* Er, const T* Ez) {
   const uint32_t n = st->n_alive + st->n_created;
   const int W = g.nr + 1;
-  const double dt = g.dt;
+  const T dt = (T)g.dt;
   const uint32_t stride = gridDim.x * blockDim.x;
   for (uint32_t p0 = blockIdx.x * blockDim.x; p0 < n; p0 += stride) {
     const uint32_t p = p0 + threadIdx.x;
     int code = -1;
     if (p < n) {
       int i, j;
-      double fr, fz;
-      const double r = P.r[p], z0 = P.z[p];
-      cell_of(g, r, z0, i, j, fr, fz);
+      T fr, fz;
+      const T r = P.r[p], z0 = P.z[p];
+      cell_of<T>(g, r, z0, i, j, fr, fz);
       const int b = j * W + i;
-      const double gr = 1.0 - fr, gz = 1.0 - fz;
-      const double w00 = gr * gz, w10 = fr * gz, w01 = gr * fz, w11 = fr * fz;
-      const double er = (((w00 * Er[b]) + (w10 * Er[b + 1])) + (w01 * Er[b + W])) + (w11 * Er[b + W + 1]);
-      const double ez = (((w00 * Ez[b]) + (w10 * Ez[b + 1])) + (w01 * Ez[b + W])) + (w11 * Ez[b + W + 1]);
+      const T gr = (T)1 - fr, gz = (T)1 - fz;
+      const T w00 = gr * gz, w10 = fr * gz, w01 = gr * fz, w11 = fr * fz;
+      const T er = (((w00 * Er[b]) + (w10 * Er[b + 1])) + (w01 * Er[b + W])) + (w11 * Er[b + W + 1]);
+      const T ez = (((w00 * Ez[b]) + (w10 * Ez[b + 1])) + (w01 * Ez[b + W])) + (w11 * Ez[b + W + 1]);
       const int s = P.sp[p];
-      const double qm = spp.qmdt[s];
-      double vr = P.vr[p] + (qm * er);
-      double vz = P.vz[p] + (qm * ez);
-      double vt = P.vt[p];
-      const double x = r + (vr * dt);
-      const double y = vt * dt;
-      const double z = z0 + (vz * dt);
-      const double rn = sqrt((x * x) + (y * y));
-      if (rn > 0.0) {
-        const double c = x / rn, sn = y / rn;
-        const double vr2 = (c * vr) + (sn * vt);
-        const double vt2 = (c * vt) - (sn * vr);
+      const T qm = (T)spp.qmdt[s];
+      T vr = P.vr[p] + (qm * er);
+      T vz = P.vz[p] + (qm * ez);
+      T vt = P.vt[p];
+      const T x = r + (vr * dt);
+      const T y = vt * dt;
+      const T z = z0 + (vz * dt);
+      const T rn = sqrt((x * x) + (y * y));
+      if (rn > (T)0) {
+        const T c = x / rn, sn = y / rn;
+        const T vr2 = (c * vr) + (sn * vt);
+        const T vt2 = (c * vt) - (sn * vr);
         vr = vr2;
         vt = vt2;
       }
@@ -187,16 +207,16 @@ __global__ void __launch_bounds__(256) k_push(Parts P, DevState* st, Grid g, Spe
       P.vt[p] = vt;
       P.vz[p] = vz;
       int bnd = -1;
-      if (z < 0.0) bnd = 0;
-      else if (!(z < g.L)) bnd = 1;
-      else if (!(rn < g.R)) bnd = 2;
+      if (z < (T)0) bnd = 0;
+      else if (!(z < (T)g.L)) bnd = 1;
+      else if (!(rn < (T)g.R)) bnd = 2;
       if (bnd >= 0) {
         code = bnd * kNS + s;
         P.key[p] = g.sentinel;
       } else {
         int i2, j2;
-        double a, c;
-        cell_of(g, rn, z, i2, j2, a, c);
+        T a, c;
+        cell_of<T>(g, rn, z, i2, j2, a, c);
         P.key[p] = (uint32_t)s * g.C + (uint32_t)(j2 * g.nr + i2);
       }
     }
@@ -204,16 +224,23 @@ __global__ void __launch_bounds__(256) k_push(Parts P, DevState* st, Grid g, Spe
   }
 }
 
-void push(const Parts& P, DevState* st, const Grid& g, const SpeciesParams& sp, const FieldWork& fw,
-          int64_t cap, hipStream_t s) {
-  k_push<<<grid_for(cap), 256, 0, s>>>(P, st, g, sp, fw.Er, fw.Ez);
+template <>
+void push<double>(const Parts& P, DevState* st, const Grid& g, const SpeciesParams& sp,
+                  const FieldWork& fw, int64_t cap, hipStream_t s) {
+  k_push<double><<<grid_for(cap), 256, 0, s>>>(P, st, g, sp, fw.Er, fw.Ez);
+}
+template <>
+void push<float>(const PartsF& P, DevState* st, const Grid& g, const SpeciesParams& sp,
+                 const FieldWork& fw, int64_t cap, hipStream_t s) {
+  k_push<float><<<grid_for(cap), 256, 0, s>>>(P, st, g, sp, fw.Erf, fw.Ezf);
 }
 
 // ---------------------------------------------------------------------------
 // this step's scheduled particles, appended after the pushed ones
 // The last block to finish (a ticket counter, no waiting) then rolls the
 // counters: the arrays now hold alive + created + injected.
-__global__ void __launch_bounds__(256) k_inject(Parts P, DevState* st, Grid g, Schedule sc,
+template <typename T>
+__global__ void __launch_bounds__(256) k_inject(PartsT<T> P, DevState* st, Grid g, Schedule sc,
                                                 uint32_t cap) {
   __shared__ uint32_t last;
   const uint32_t pos = st->sched_pos;
@@ -227,18 +254,18 @@ __global__ void __launch_bounds__(256) k_inject(Parts P, DevState* st, Grid g, S
   for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < cnt; q += gridDim.x * blockDim.x) {
     const int64_t src = a + q;
     const uint32_t d = base + q;
-    const double r = sc.r[src], z = sc.z[src];
+    const T r = (T)sc.r[src], z = (T)sc.z[src];
     const uint32_t s = sc.sp[src];
     P.r[d] = r;
     P.z[d] = z;
-    P.vr[d] = sc.vr[src];
-    P.vt[d] = sc.vt[src];
-    P.vz[d] = sc.vz[src];
+    P.vr[d] = (T)sc.vr[src];
+    P.vt[d] = (T)sc.vt[src];
+    P.vz[d] = (T)sc.vz[src];
     P.sp[d] = (uint8_t)s;
     P.id[d] = id0 + q;
     int i, j;
-    double fr, fz;
-    cell_of(g, r, z, i, j, fr, fz);
+    T fr, fz;
+    cell_of<T>(g, r, z, i, j, fr, fz);
     P.key[d] = s * g.C + (uint32_t)(j * g.nr + i);
   }
   __syncthreads();
@@ -260,19 +287,25 @@ __global__ void __launch_bounds__(256) k_inject(Parts P, DevState* st, Grid g, S
   st->ticket = 0;
 }
 
-void inject_and_roll(const Parts& P, DevState* st, const Grid& g, const Schedule& sc, int64_t cap,
-                     hipStream_t s) {
-  k_inject<<<grid_for(sc.off ? sc.max_count : 1), 256, 0, s>>>(P, st, g, sc, (uint32_t)cap);
+template <typename T>
+void inject_and_roll(const PartsT<T>& P, DevState* st, const Grid& g, const Schedule& sc,
+                     int64_t cap, hipStream_t s) {
+  k_inject<T><<<grid_for(sc.off ? sc.max_count : 1), 256, 0, s>>>(P, st, g, sc, (uint32_t)cap);
 }
+template void inject_and_roll<double>(const Parts&, DevState*, const Grid&, const Schedule&,
+                                      int64_t, hipStream_t);
+template void inject_and_roll<float>(const PartsF&, DevState*, const Grid&, const Schedule&,
+                                     int64_t, hipStream_t);
 
 // host-initiated append of n particles already copied to src
-__global__ void __launch_bounds__(256) k_append(Parts P, const DevState* st, Grid g, Parts src,
-                                                uint32_t n) {
+template <typename T>
+__global__ void __launch_bounds__(256) k_append(PartsT<T> P, const DevState* st, Grid g,
+                                                PartsT<T> src, uint32_t n) {
   const uint32_t base = st->n_total;
   const uint32_t id0 = st->next_id;
   for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
     const uint32_t d = base + q;
-    const double r = src.r[q], z = src.z[q];
+    const T r = src.r[q], z = src.z[q];
     const uint32_t s = src.sp[q];
     P.r[d] = r;
     P.z[d] = z;
@@ -282,8 +315,8 @@ __global__ void __launch_bounds__(256) k_append(Parts P, const DevState* st, Gri
     P.sp[d] = (uint8_t)s;
     P.id[d] = id0 + q;
     int i, j;
-    double fr, fz;
-    cell_of(g, r, z, i, j, fr, fz);
+    T fr, fz;
+    cell_of<T>(g, r, z, i, j, fr, fz);
     P.key[d] = s * g.C + (uint32_t)(j * g.nr + i);
   }
 }
@@ -294,17 +327,23 @@ __global__ void k_append_end(DevState* st, uint32_t n) {
   }
 }
 
-void append(const Parts& P, DevState* st, const Grid& g, const Parts& src, uint32_t n,
+template <typename T>
+void append(const PartsT<T>& P, DevState* st, const Grid& g, const PartsT<T>& src, uint32_t n,
             hipStream_t s) {
   if (n == 0) return;
-  k_append<<<grid_for(n), 256, 0, s>>>(P, st, g, src, n);
+  k_append<T><<<grid_for(n), 256, 0, s>>>(P, st, g, src, n);
   k_append_end<<<1, 64, 0, s>>>(st, n);
 }
+template void append<double>(const Parts&, DevState*, const Grid&, const Parts&, uint32_t,
+                             hipStream_t);
+template void append<float>(const PartsF&, DevState*, const Grid&, const PartsF&, uint32_t,
+                            hipStream_t);
 
 // ---------------------------------------------------------------------------
 // snapshot: counts and kinetic energy per species (per-block partials, summed
 // on the host in block order), Cu2+ spectra by comparison with the edges
-__global__ void __launch_bounds__(256) k_diag(Parts P, const DevState* st, Grid g,
+template <typename T>
+__global__ void __launch_bounds__(256) k_diag(PartsT<T> P, const DevState* st, Grid g,
                                               SpeciesParams spp, const double* edges,
                                               unsigned long long* counts, double* ke,
                                               unsigned long long* spec) {
@@ -318,7 +357,8 @@ __global__ void __launch_bounds__(256) k_diag(Parts P, const DevState* st, Grid 
     if (P.key[p] == g.sentinel) continue;
     const int s = P.sp[p];
     atomicAdd(&sc[s], 1ull);
-    const double v2 = ((P.vr[p] * P.vr[p]) + (P.vt[p] * P.vt[p])) + (P.vz[p] * P.vz[p]);
+    const double vr = P.vr[p], vt = P.vt[p], vz = P.vz[p];
+    const double v2 = ((vr * vr) + (vt * vt)) + (vz * vz);
     acc[s] += (0.5 * spp.m[s]) * v2;
     if (s >= 3) {
       const double e = ((0.5 * spp.m[s]) * v2) / kQE;
@@ -347,10 +387,17 @@ __global__ void __launch_bounds__(256) k_diag(Parts P, const DevState* st, Grid 
   }
 }
 
-void diag_snapshot(const Parts& P, const DevState* st, const Grid& g, const SpeciesParams& sp,
+template <typename T>
+void diag_snapshot(const PartsT<T>& P, const DevState* st, const Grid& g, const SpeciesParams& sp,
                    const double* edges, unsigned long long* counts, double* ke,
                    unsigned long long* spec, hipStream_t s) {
-  k_diag<<<kDiagBlocks, 256, 0, s>>>(P, st, g, sp, edges, counts, ke, spec);
+  k_diag<T><<<kDiagBlocks, 256, 0, s>>>(P, st, g, sp, edges, counts, ke, spec);
 }
+template void diag_snapshot<double>(const Parts&, const DevState*, const Grid&,
+                                    const SpeciesParams&, const double*, unsigned long long*,
+                                    double*, unsigned long long*, hipStream_t);
+template void diag_snapshot<float>(const PartsF&, const DevState*, const Grid&,
+                                   const SpeciesParams&, const double*, unsigned long long*,
+                                   double*, unsigned long long*, hipStream_t);
 
 }  // namespace pd

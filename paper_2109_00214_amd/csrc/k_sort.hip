@@ -323,7 +323,8 @@ __global__ void __launch_bounds__(256) k_radix_down(const uint32_t* __restrict__
 // payload permutation: dst[p] = src[perm[p]] for the live particles; every
 // sorted key (the sentinel ones included) goes to dst.key
 constexpr int kGatherPer = 4;
-__global__ void __launch_bounds__(256) k_gather(Parts src, Parts dst,
+template <typename T>
+__global__ void __launch_bounds__(256) k_gather(PartsT<T> src, PartsT<T> dst,
                                                 const uint32_t* __restrict__ skeys,
                                                 const uint32_t* __restrict__ perm,
                                                 const DevState* st, uint32_t sentinel) {
@@ -341,7 +342,7 @@ __global__ void __launch_bounds__(256) k_gather(Parts src, Parts dst,
       k[u] = skeys[pc];
       q[u] = perm[pc];
     }
-    double r[kGatherPer], z[kGatherPer], vr[kGatherPer], vt[kGatherPer], vz[kGatherPer];
+    T r[kGatherPer], z[kGatherPer], vr[kGatherPer], vt[kGatherPer], vz[kGatherPer];
     uint32_t id[kGatherPer];
     uint8_t sp[kGatherPer];
 #pragma unroll
@@ -389,8 +390,9 @@ static void radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout,
 
 // key_bits <= 20: two passes of ceil(key_bits/2) bits (at most 10);
 // wider keys: passes of 10 bits
-void sort_particles(const Parts& src, const Parts& dst, int key_bits, SortWork& w, DevState* st,
-                    uint32_t sentinel, int part, hipStream_t s) {
+template <typename T>
+void sort_particles(const PartsT<T>& src, const PartsT<T>& dst, int key_bits, SortWork& w,
+                    DevState* st, uint32_t sentinel, int part, hipStream_t s) {
   int passes = (key_bits + kRadixMaxBits - 1) / kRadixMaxBits;
   if (passes < 2) passes = 2;
   const int dbits = (key_bits + passes - 1) / passes;
@@ -412,9 +414,13 @@ void sort_particles(const Parts& src, const Parts& dst, int key_bits, SortWork& 
     int64_t gb = (w.cap + 256 * kGatherPer - 1) / (256 * kGatherPer);
     if (gb < 1) gb = 1;
     if (gb > 2048) gb = 2048;
-    k_gather<<<(int)gb, 256, 0, s>>>(src, dst, skeys, perm, st, sentinel);
+    k_gather<T><<<(int)gb, 256, 0, s>>>(src, dst, skeys, perm, st, sentinel);
   }
 }
+template void sort_particles<double>(const Parts&, const Parts&, int, SortWork&, DevState*,
+                                     uint32_t, int, hipStream_t);
+template void sort_particles<float>(const PartsF&, const PartsF&, int, SortWork&, DevState*,
+                                    uint32_t, int, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // off[k] = first sorted position whose key >= k, for k = 0 .. nkeys-1;

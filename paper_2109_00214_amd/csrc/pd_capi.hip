@@ -41,7 +41,9 @@ struct pd_ctx {
 
   // device memory
   std::vector<void*> allocs;
-  Parts A{}, B{};
+  Parts A{}, B{};    // FP64 form: the particles (A) and the sort's destination
+  PartsF Af{}, Bf{};  // FP32 form
+  bool fp32 = false;
   SortWork sw{};
   CollideWork cw{};
   FieldWork fw{};
@@ -113,7 +115,8 @@ pd_status dalloc(pd_ctx* c, T** p, size_t n) {
   return PD_OK;
 }
 
-pd_status alloc_parts(pd_ctx* c, Parts& P, int64_t n) {
+template <class T>
+pd_status alloc_parts(pd_ctx* c, PartsT<T>& P, int64_t n) {
   pd_status s;
   if ((s = dalloc(c, &P.r, n)) || (s = dalloc(c, &P.z, n)) || (s = dalloc(c, &P.vr, n)) ||
       (s = dalloc(c, &P.vt, n)) || (s = dalloc(c, &P.vz, n)) || (s = dalloc(c, &P.sp, n)) ||
@@ -470,6 +473,54 @@ void harvest_timing(pd_ctx* c) {
   c->ev_pending.clear();
 }
 
+// host arrays -> staging buffers (converted to the record's precision) ->
+// appended after the particles held now
+template <class T>
+pd_status stage_append(pd_ctx* c, const PartsT<T>& A, const PartsT<T>& B, int64_t n,
+                              const double* r, const double* z, const double* vr,
+                              const double* vt, const double* vz, const uint8_t* sp) {
+  const double* h[5] = {r, z, vr, vt, vz};
+  T* d[5] = {B.r, B.z, B.vr, B.vt, B.vz};
+  std::vector<T> buf((size_t)n);
+  for (int k = 0; k < 5; ++k) {
+    for (int64_t p = 0; p < n; ++p) buf[p] = (T)h[k][p];
+    HIPCHK(c, hipMemcpy(d[k], buf.data(), sizeof(T) * n, hipMemcpyHostToDevice));
+  }
+  HIPCHK(c, hipMemcpy(B.sp, sp, n, hipMemcpyHostToDevice));
+  append(A, c->st, c->g, B, (uint32_t)n, c->stream);
+  HIPCHK(c, hipGetLastError());
+  return PD_OK;
+}
+
+// one step on the context's stream: sort -> collide -> deposit -> Poisson
+// -> field -> push -> inject (mark() records the stage boundaries)
+template <class T, class Mark>
+pd_status enqueue_step(pd_ctx* c, PartsT<T>& A, PartsT<T>& B, int64_t nn, Mark& mark) {
+  hipStream_t s = c->stream;
+  mark();
+  sort_particles(A, B, c->key_bits, c->sw, c->st, c->g.sentinel, 0, s);
+  mark();
+  sort_particles(A, B, c->key_bits, c->sw, c->st, c->g.sentinel, 1, s);
+  std::swap(A, B);
+  mark();
+  build_offsets(A.key, c->st, c->off, c->g.sentinel + 1, c->fw.Q, (uint32_t)nn, s);
+  mark();
+  if (!c->opts.collisions_off) collide(A, c->off, c->st, c->g, c->cpar, c->cw, c->sw.bsum, c->cap, s);
+  mark();
+  if (!c->opts.deposit_off) deposit(A, c->st, c->off, c->g, c->spp, c->fw.Q, c->cap, s);
+  mark();
+  pd_status ps = solve_poisson(c);
+  if (ps) return ps;
+  mark();
+  field(c->g, c->fw, s);
+  mark();
+  push(A, c->st, c->g, c->spp, c->fw, c->cap, s);
+  mark();
+  inject_and_roll(A, c->st, c->g, c->sched, c->cap, s);
+  mark();
+  return PD_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -493,11 +544,12 @@ pd_status pd_create(const pd_domain* dom, const pd_opts* opts, pd_ctx** out) {
       !std::isfinite(dom->R) || !std::isfinite(dom->L) || dom->capacity < 1 ||
       dom->capacity > (int64_t)kScanChunk * kScanMaxBlocks)
     return fail(set_err(c, PD_EINVAL, "invalid domain"));
-  if (opts->precision != PD_FP64_DET ||
+  if ((opts->precision != PD_FP64_DET && opts->precision != PD_FP32_MIXED) ||
       (opts->poisson != PD_POISSON_DIRECT64 && opts->poisson != PD_POISSON_MGPCG) ||
       !(opts->poisson_rtol >= 0.0) || !std::isfinite(opts->poisson_rtol))
     return fail(set_err(c, PD_EINVAL, "unsupported precision or Poisson mode"));
   c->mg_on = opts->poisson == PD_POISSON_MGPCG;
+  c->fp32 = opts->precision == PD_FP32_MIXED;
   if (opts->stream) {
     c->stream = (hipStream_t)opts->stream;
   } else {
@@ -535,7 +587,9 @@ pd_status pd_create(const pd_domain* dom, const pd_opts* opts, pd_ctx** out) {
   const int M = nz - 1;
   const int64_t tiles = (cap + kSortTile - 1) / kSortTile;
   pd_status s;
-  if ((s = alloc_parts(c, c->A, cap)) || (s = alloc_parts(c, c->B, cap)) ||
+  if ((c->fp32 ? ((s = alloc_parts(c, c->Af, cap)) || (s = alloc_parts(c, c->Bf, cap)) ||
+                  (s = dalloc(c, &c->fw.Erf, nn)) || (s = dalloc(c, &c->fw.Ezf, nn)))
+               : ((s = alloc_parts(c, c->A, cap)) || (s = alloc_parts(c, c->B, cap)))) ||
       (s = dalloc(c, &c->sw.k0, cap)) || (s = dalloc(c, &c->sw.k1, cap)) ||
       (s = dalloc(c, &c->sw.v0, cap)) || (s = dalloc(c, &c->sw.v1, cap)) ||
       (s = dalloc(c, &c->sw.hist, (size_t)kRadix * (tiles < 1 ? 1 : tiles))) ||
@@ -654,16 +708,10 @@ pd_status pd_inject(pd_ctx* c, int64_t n, const double* r, const double* z, cons
   if ((s = read_state(c, &h))) return s;
   if ((int64_t)h.n_total + n > c->cap) return set_err(c, PD_ECAPACITY, "capacity %lld", (long long)c->cap);
   if ((int64_t)h.next_id + n > (int64_t)0xFFFFFFFFLL) return set_err(c, PD_ECAPACITY, "id space");
-  // stage through B's tail-free buffers: B is scratch between steps
-  Parts src = c->B;
-  HIPCHK(c, hipMemcpyAsync(src.r, r, 8 * n, hipMemcpyHostToDevice, c->stream));
-  HIPCHK(c, hipMemcpyAsync(src.z, z, 8 * n, hipMemcpyHostToDevice, c->stream));
-  HIPCHK(c, hipMemcpyAsync(src.vr, vr, 8 * n, hipMemcpyHostToDevice, c->stream));
-  HIPCHK(c, hipMemcpyAsync(src.vt, vt, 8 * n, hipMemcpyHostToDevice, c->stream));
-  HIPCHK(c, hipMemcpyAsync(src.vz, vz, 8 * n, hipMemcpyHostToDevice, c->stream));
-  HIPCHK(c, hipMemcpyAsync(src.sp, sp, n, hipMemcpyHostToDevice, c->stream));
-  append(c->A, c->st, c->g, src, (uint32_t)n, c->stream);
-  HIPCHK(c, hipGetLastError());
+  // stage through the sort's destination buffers (scratch between steps)
+  if (c->fp32) s = stage_append(c, c->Af, c->Bf, n, r, z, vr, vt, vz, sp);
+  else s = stage_append(c, c->A, c->B, n, r, z, vr, vt, vz, sp);
+  if (s) return s;
   if ((s = sync(c))) return s;
   for (int64_t p = 0; p < n; ++p) c->injected[sp[p]] += 1;
   return PD_OK;
@@ -743,30 +791,9 @@ pd_status pd_step(pd_ctx* c, int nsteps) {
         ev.push_back(e);
       }
     };
-    mark();
-    sort_particles(c->A, c->B, c->key_bits, c->sw, c->st, c->g.sentinel, 0, s);
-    mark();
-    sort_particles(c->A, c->B, c->key_bits, c->sw, c->st, c->g.sentinel, 1, s);
-    std::swap(c->A, c->B);
-    mark();
-    build_offsets(c->A.key, c->st, c->off, c->g.sentinel + 1, c->fw.Q, (uint32_t)nn, s);
-    mark();
-    if (!c->opts.collisions_off)
-      collide(c->A, c->off, c->st, c->g, c->cpar, c->cw, c->sw.bsum, c->cap, s);
-    mark();
-    if (!c->opts.deposit_off) deposit(c->A, c->st, c->off, c->g, c->spp, c->fw.Q, c->cap, s);
-    mark();
-    {
-      pd_status ps = solve_poisson(c);
-      if (ps) return ps;
-    }
-    mark();
-    field(c->g, c->fw, s);
-    mark();
-    push(c->A, c->st, c->g, c->spp, c->fw, c->cap, s);
-    mark();
-    inject_and_roll(c->A, c->st, c->g, c->sched, c->cap, s);
-    mark();
+    pd_status ps = c->fp32 ? enqueue_step(c, c->Af, c->Bf, nn, mark)
+                           : enqueue_step(c, c->A, c->B, nn, mark);
+    if (ps) return ps;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
       c->poisoned = true;
@@ -800,7 +827,12 @@ static pd_status snapshot(pd_ctx* c, DevState& h, int64_t counts[kNS], double ke
   pd_status s = read_state(c, &h);
   if (s) return s;
   HIPCHK(c, hipMemsetAsync(c->d_spec, 0, sizeof(unsigned long long) * 3 * 66, c->stream));
-  diag_snapshot(c->A, c->st, c->g, c->spp, c->d_edges, c->d_dcount, c->d_dke, c->d_spec, c->stream);
+  if (c->fp32)
+    diag_snapshot(c->Af, c->st, c->g, c->spp, c->d_edges, c->d_dcount, c->d_dke, c->d_spec,
+                  c->stream);
+  else
+    diag_snapshot(c->A, c->st, c->g, c->spp, c->d_edges, c->d_dcount, c->d_dke, c->d_spec,
+                  c->stream);
   HIPCHK(c, hipGetLastError());
   if ((s = sync(c))) return s;
   std::vector<unsigned long long> hc((size_t)kDiagBlocks * kNS), hs(3 * 66);
@@ -900,7 +932,7 @@ pd_status pd_get_particles(pd_ctx* c, int64_t cap, double* r, double* z, double*
   if (s) return s;
   const int64_t n = h.n_total;
   std::vector<uint32_t> k(n);
-  HIPCHK(c, hipMemcpy(k.data(), c->A.key, 4 * n, hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(k.data(), c->fp32 ? c->Af.key : c->A.key, 4 * n, hipMemcpyDeviceToHost));
   int64_t alive = 0;
   for (int64_t p = 0; p < n; ++p) alive += (k[p] != c->g.sentinel);
   if (cap < alive) return set_err(c, PD_EINVAL, "cap %lld < %lld particles", (long long)cap,
@@ -914,6 +946,23 @@ pd_status pd_get_particles(pd_ctx* c, int64_t cap, double* r, double* z, double*
       if (k[p] != c->g.sentinel) std::memcpy((unsigned char*)dst + esz * (w++), &buf[esz * p], esz);
     return PD_OK;
   };
+  // FP32 records are widened to double on the host
+  auto pullf = [&](double* dst, const float* src) -> pd_status {
+    if (!dst) return PD_OK;
+    std::vector<float> buf(n);
+    HIPCHK(c, hipMemcpy(buf.data(), src, 4 * n, hipMemcpyDeviceToHost));
+    int64_t w = 0;
+    for (int64_t p = 0; p < n; ++p)
+      if (k[p] != c->g.sentinel) dst[w++] = (double)buf[p];
+    return PD_OK;
+  };
+  if (c->fp32) {
+    if ((s = pullf(r, c->Af.r)) || (s = pullf(z, c->Af.z)) || (s = pullf(vr, c->Af.vr)) ||
+        (s = pullf(vt, c->Af.vt)) || (s = pullf(vz, c->Af.vz)) || (s = pull(sp, c->Af.sp, 1)) ||
+        (s = pull(id, c->Af.id, 4)) || (s = pull(key, c->Af.key, 4)))
+      return s;
+    return PD_OK;
+  }
   if ((s = pull(r, c->A.r, 8)) || (s = pull(z, c->A.z, 8)) || (s = pull(vr, c->A.vr, 8)) ||
       (s = pull(vt, c->A.vt, 8)) || (s = pull(vz, c->A.vz, 8)) || (s = pull(sp, c->A.sp, 1)) ||
       (s = pull(id, c->A.id, 4)) || (s = pull(key, c->A.key, 4)))

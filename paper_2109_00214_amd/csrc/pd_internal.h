@@ -33,12 +33,16 @@ struct DevState {
   unsigned long long absorbed[3 * kNS];
 };
 
-// Structure-of-arrays particle store (FP64 deterministic form).
-struct Parts {
-  double *r, *z, *vr, *vt, *vz;
+// Structure-of-arrays particle store; T = double in the FP64 deterministic
+// form, float in the FP32 precision form.
+template <typename T>
+struct PartsT {
+  T *r, *z, *vr, *vt, *vz;
   uint8_t* sp;
   uint32_t *id, *key;
 };
+using Parts = PartsT<double>;
+using PartsF = PartsT<float>;
 
 struct Grid {
   int nr, nz;
@@ -94,8 +98,9 @@ struct SortWork {
 // Stable LSD radix sort of the st->n_total keys of src; the last pass moves
 // the records into dst (every key, the sentinel ones included, lands in
 // dst.key).  part = 0: every pass but the last; part = 1: the last pass.
-void sort_particles(const Parts& src, const Parts& dst, int key_bits, SortWork& w, DevState* st,
-                    uint32_t sentinel, int part, hipStream_t s);
+template <typename T>
+void sort_particles(const PartsT<T>& src, const PartsT<T>& dst, int key_bits, SortWork& w,
+                    DevState* st, uint32_t sentinel, int part, hipStream_t s);
 // Exclusive scan of *len u32 values (device length), total to *total.  With
 // a guard state the total counts new particles: it is forced to 0 and the
 // error flagged when they would not fit in cap (or the ids would wrap).
@@ -112,7 +117,8 @@ struct CollideWork {
   uint32_t *target, *claim, *ccount, *cbase, *scan_len;
   int64_t cap;
 };
-void collide(const Parts& P, const uint32_t* off, DevState* st, const Grid& g,
+template <typename T>
+void collide(const PartsT<T>& P, const uint32_t* off, DevState* st, const Grid& g,
              const CollideParams& cp, CollideWork& w, uint32_t* bsum, int64_t cap,
              hipStream_t s);
 
@@ -120,6 +126,7 @@ void collide(const Parts& P, const uint32_t* off, DevState* st, const Grid& g,
 struct FieldWork {
   int64_t* Q;           // nodes
   double *phi, *Er, *Ez;
+  float *Erf, *Ezf;     // FP32 copies of the field (FP32 form), else NULL
   double* f;            // [(nz-1) * (nr+1)] right-hand side, interior rows
   double* fh;           // [(nr+1) * (nz-1)] transformed, mode fastest
   double* g;            // [(nz-1) * (nr+1)] per-mode solutions, r fastest
@@ -130,7 +137,8 @@ struct FieldWork {
   const double* Vnode;  // [nr+1]
   double qunit;
 };
-void deposit(const Parts& P, const DevState* st, const uint32_t* off, const Grid& g,
+template <typename T>
+void deposit(const PartsT<T>& P, const DevState* st, const uint32_t* off, const Grid& g,
              const SpeciesParams& sp, int64_t* Q, int64_t cap, hipStream_t s);
 void poisson_direct(const Grid& g, FieldWork& fw, hipStream_t s);
 size_t poisson_lds_bytes(int nr, int nz);
@@ -183,16 +191,20 @@ void mg_residual(const MGWork& w, const double* phi, const int64_t* Q, hipStream
 // residual, phi += correction, new residual
 void mg_outer(MGWork& w, double* phi, const int64_t* Q, int inner, hipStream_t s);
 void field(const Grid& g, FieldWork& fw, hipStream_t s);
-void push(const Parts& P, DevState* st, const Grid& g, const SpeciesParams& sp,
+template <typename T>
+void push(const PartsT<T>& P, DevState* st, const Grid& g, const SpeciesParams& sp,
           const FieldWork& fw, int64_t cap, hipStream_t s);
 // append this step's scheduled particles and roll the step counters
-void inject_and_roll(const Parts& P, DevState* st, const Grid& g, const Schedule& sc,
+template <typename T>
+void inject_and_roll(const PartsT<T>& P, DevState* st, const Grid& g, const Schedule& sc,
                      int64_t cap, hipStream_t s);
-void append(const Parts& P, DevState* st, const Grid& g, const Parts& src, uint32_t n,
+template <typename T>
+void append(const PartsT<T>& P, DevState* st, const Grid& g, const PartsT<T>& src, uint32_t n,
             hipStream_t s);
 // snapshot reductions: per-block partial counts, KE sums, spectrum bins
 constexpr int kDiagBlocks = 512;
-void diag_snapshot(const Parts& P, const DevState* st, const Grid& g, const SpeciesParams& sp,
+template <typename T>
+void diag_snapshot(const PartsT<T>& P, const DevState* st, const Grid& g, const SpeciesParams& sp,
                    const double* edges, unsigned long long* counts /*[kDiagBlocks*6]*/,
                    double* ke /*[kDiagBlocks*6]*/, unsigned long long* spec /*[3*66]*/,
                    hipStream_t s);

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libpd.so")
 PD_OK, PD_EINVAL, PD_ENOMEM, PD_EDEVICE, PD_ESTATE, PD_ENOCONV, PD_ECAPACITY = 0, -1, -2, -3, -4, -5, -6
 STATUS_NAMES = {0: "PD_OK", -1: "PD_EINVAL", -2: "PD_ENOMEM", -3: "PD_EDEVICE", -4: "PD_ESTATE",
                 -5: "PD_ENOCONV", -6: "PD_ECAPACITY"}
-PD_FP64_DET = 0
+PD_FP64_DET, PD_FP32_MIXED = 0, 1
 PD_POISSON_DIRECT64, PD_POISSON_MGPCG = 0, 1
 TIMER_NAMES = ("radix", "permute", "offsets", "collide", "deposit", "poisson", "field", "push",
                "inject")
@@ -227,11 +227,11 @@ class Simulation:
 
     def __init__(self, cfg, capacity, tables, species, enable_di=None, deposit_off=False,
                  collisions_off=False, timing=False, stream=None, poisson=PD_POISSON_DIRECT64,
-                 poisson_rtol=0.0):
+                 poisson_rtol=0.0, precision=PD_FP64_DET):
         dom = pd_domain(cfg.nr, cfg.nz, cfg.R, cfg.L, cfg.V, cfg.dt, cfg.weight, cfg.seed,
                         int(capacity))
         di = cfg.enable_di if enable_di is None else enable_di
-        opts = pd_opts(PD_FP64_DET, poisson, int(di), int(deposit_off), int(collisions_off),
+        opts = pd_opts(precision, poisson, int(di), int(deposit_off), int(collisions_off),
                        int(timing), stream, float(poisson_rtol))
         self.cfg = cfg
         self.h = pd_create(dom, opts)
