@@ -70,11 +70,14 @@ enum { PD_CATHODE = 0, PD_ANODE = 1, PD_OUTER = 2 };
  * arithmetic and diagnostics */
 enum { PD_FP64_DET = 0, PD_FP32_MIXED = 1 };
 /* Poisson solvers: the direct FP64 solve (sine transform in z, tridiagonal
- * in r), or conjugate gradients in FP32 preconditioned by a geometric
- * multigrid V-cycle inside FP64 iterative refinement, started from the
- * previous step's potential and stopped at the relative residual
- * poisson_rtol (falls back to the direct solve if it does not get there) */
-enum { PD_POISSON_DIRECT64 = 0, PD_POISSON_MGPCG = 1 };
+ * in r); conjugate gradients in FP32 preconditioned by a geometric
+ * multigrid V-cycle inside FP64 iterative refinement; or flexible CG in FP32
+ * inside the same refinement whose first direction comes from a trained
+ * U-Net (pd_set_unet) applied to the residual and the others from the
+ * V-cycle.  The iterative solvers start from the previous step's
+ * potential and stop at the relative residual poisson_rtol; a solve that
+ * does not get there falls back to the direct solve. */
+enum { PD_POISSON_DIRECT64 = 0, PD_POISSON_MGPCG = 1, PD_POISSON_LEARNED = 2 };
 /* stages timed by pd_get_timing: radix passes of the sort, payload
  * permutation, CSR offsets, collisions, deposit, Poisson, field, push,
  * injection + counter roll */
@@ -205,6 +208,51 @@ pd_status pd_get_field(pd_ctx* ctx, double* phi, double* Er, double* Ez, int64_t
  * fallback), PD_EDEVICE.                                                */
 pd_status pd_poisson(pd_ctx* ctx, const int64_t* Q, double* phi, int32_t* iters,
                      double* rel_res);
+
+/* ---- learned Poisson part (Eq. 8 solved with a network's help) ----------
+ * A U-Net (levels, base width; 3x3 bias-free BF16 convolutions with FP32
+ * accumulation and ReLU, 2x2 average pooling, nearest upsampling with skip
+ * concatenation, a 1x1 FP32 output) maps [b / rms(b), r / R] -- b the
+ * right-hand side of the node equations times their control volumes, on the
+ * interior rows -- to the potential's charge part over its RMS, on an image
+ * of the node grid (H = nz+1, W = nr+1, zero-padded to multiples of
+ * 2^(levels-1); row = z node, column = r node).  Weights travel as one FP32
+ * vector, layer by layer (encoder levels, then decoder levels from the
+ * bottom, then the 1x1 layer), each 3x3 layer [c_out][tap][c_in] with
+ * tap = 3 (dy+1) + (dx+1) the offset of the input pixel.  The network is
+ * trained on the GPU on pairs dumped from a running context.  One network
+ * may serve one context at a time.                                      */
+typedef struct pd_unet pd_unet;
+
+/* Network for the node grid of nr x nz cells; batch = most images per
+ * forward/backward call; dataset_capacity = most stored training pairs.
+ * base must be 16, 32, 48 or 64.  Weights start at zero (set them).
+ * Errors: PD_EINVAL (sizes), PD_ENOMEM.                                */
+pd_status pd_unet_create(int32_t nr, int32_t nz, int32_t levels, int32_t base, int32_t batch,
+                         int64_t dataset_capacity, pd_unet** out);
+/* number of weights; image size H x W */
+pd_status pd_unet_info(const pd_unet* net, int64_t* n_params, int32_t* H, int32_t* W);
+/* copy the FP32 weights in (resets the optimiser) or out */
+pd_status pd_unet_set_weights(pd_unet* net, const float* w);
+pd_status pd_unet_get_weights(const pd_unet* net, float* w);
+/* forward of n images x[n][2][H][W] -> out[n][H][W] (host FP32 arrays) */
+pd_status pd_unet_forward(pd_unet* net, int32_t n, const float* x, float* out);
+/* gradient of sum(dout * out) with respect to the weights, for the same
+ * inputs as pd_unet_forward (dw: n_params values)                       */
+pd_status pd_unet_gradient(pd_unet* net, int32_t n, const float* x, const float* dout, float* dw);
+/* store the context's current (node charge, potential) as a training pair;
+ * the context's grid must be the network's.  PD_ECAPACITY when full.    */
+pd_status pd_unet_add_sample(pd_unet* net, pd_ctx* ctx);
+/* Adam (beta 0.9, 0.999) on minibatches of the stored pairs, mean squared
+ * error of the normalised potential over the real interior nodes; loss
+ * (may be NULL) receives the last epoch's mean loss.                   */
+pd_status pd_unet_train(pd_unet* net, int32_t epochs, int32_t batch, double lr, uint64_t seed,
+                        double* loss);
+/* attach the network to a context created with PD_POISSON_LEARNED (NULL
+ * detaches; the solver then uses the direct solve)                     */
+pd_status pd_set_unet(pd_ctx* ctx, pd_unet* net);
+const char* pd_unet_last_error(const pd_unet* net);
+void pd_unet_destroy(pd_unet* net);
 
 /* Accumulated device time per stage (ms, PD_NTIMERS entries) and the
  * number of steps timed, since creation or the last reset (requires

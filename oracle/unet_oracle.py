@@ -70,38 +70,56 @@ def _conv(x, w):
     return F.conv2d(x, w, padding=w.shape[-1] // 2)
 
 
-def forward_t(x, ws, levels):
-    enc, h, k = [], x, 0
+def bf16_round(t):
+    """round a float64 tensor to the nearest-even BF16 value (through FP32)"""
+    a = t.detach().to(torch.float32).contiguous().view(torch.int32).to(torch.int64) & 0xFFFFFFFF
+    a = ((a + 0x7FFF + ((a >> 16) & 1)) >> 16) << 16
+    a = torch.where(a >= 2 ** 31, a - 2 ** 32, a).to(torch.int32)
+    return a.view(torch.float32).to(torch.float64)
+
+
+def _store(h, rounding):
+    # activations kept in a storage precision: rounded forward, gradient
+    # passed straight through
+    if rounding is None:
+        return h
+    return h + (bf16_round(h) - h).detach()
+
+
+def forward_t(x, ws, levels, rounding=None):
+    enc, h, k = [], _store(x, rounding), 0
     for l in range(levels):
         if l > 0:
-            h = F.avg_pool2d(h, 2)
-        h = F.relu(_conv(h, ws[k]))
-        h = F.relu(_conv(h, ws[k + 1]))
+            h = _store(F.avg_pool2d(h, 2), rounding)
+        h = _store(F.relu(_conv(h, ws[k])), rounding)
+        h = _store(F.relu(_conv(h, ws[k + 1])), rounding)
         k += 2
         enc.append(h)
     d = enc[-1]
     for l in range(levels - 2, -1, -1):
         u = F.interpolate(d, scale_factor=2, mode="nearest")
         h = torch.cat([enc[l], u], dim=1)
-        h = F.relu(_conv(h, ws[k]))
-        d = F.relu(_conv(h, ws[k + 1]))
+        h = _store(F.relu(_conv(h, ws[k])), rounding)
+        d = _store(F.relu(_conv(h, ws[k + 1])), rounding)
         k += 2
     return _conv(d, ws[k])
 
 
-def forward(x, w, levels=4, base=16):
-    """x: [n][cin][H][W] float64 numpy -> [n][1][H][W]"""
+def forward(x, w, levels=4, base=16, rounding=None):
+    """x: [n][cin][H][W] float64 numpy -> [n][1][H][W]; rounding="bf16" keeps
+    the input and every activation in BF16 (the storage precision of a BF16
+    implementation), all arithmetic in float64"""
     xt = torch.as_tensor(np.asarray(x, dtype=np.float64))
     ws = _split(w, levels, base, xt.shape[1])
     with torch.no_grad():
-        return forward_t(xt, ws, levels).numpy()
+        return forward_t(xt, ws, levels, rounding).numpy()
 
 
-def weight_gradient(x, w, dout, levels=4, base=16):
+def weight_gradient(x, w, dout, levels=4, base=16, rounding=None):
     """d(sum(dout * out)) / dw, flat, in the weight order; and d/dx."""
     xt = torch.as_tensor(np.asarray(x, dtype=np.float64)).clone().requires_grad_(True)
     ws = [t.clone().requires_grad_(True) for t in _split(w, levels, base, xt.shape[1])]
-    out = forward_t(xt, ws, levels)
+    out = forward_t(xt, ws, levels, rounding)
     (out * torch.as_tensor(np.asarray(dout, dtype=np.float64))).sum().backward()
     return _join([t.grad for t in ws]), xt.grad.numpy()
 

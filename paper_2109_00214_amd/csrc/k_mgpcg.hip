@@ -451,9 +451,11 @@ __global__ void __launch_bounds__(kB) k_cg_s(MGLevel m, const float* r, float* s
 // beta = r.z / r.z(previous); p = z + beta p, q = s + beta q (= A p), so
 // p.Ap = z.s + 2 beta z.q + beta^2 p.q; alpha = r.z / p.Ap;
 // x += alpha p, r -= alpha q; block partials of r.r
+// (flex: flexible CG with one stored direction for a nonlinear
+// preconditioner, beta = -z.q / p.q of the previous direction)
 __global__ void __launch_bounds__(kB) k_cg_x(MGLevel m, float* r, const float* s, float* p, float* q,
                                              float* x, MGScal* sc, const float* part4, float* part_rr,
-                                             int it) {
+                                             int it, int flex) {
   if (sc->done) return;
   const int nb = gridDim.x;
   float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
@@ -468,7 +470,9 @@ __global__ void __launch_bounds__(kB) k_cg_x(MGLevel m, float* r, const float* s
   const float zs = block_total<float>(a1);
   const float zq = block_total<float>(a2);
   const float pq = block_total<float>(a3);
-  const float beta = (it == 0 || !(prev > 0.f)) ? 0.f : rz / prev;
+  float beta;
+  if (flex) beta = (it == 0 || !(pq > 0.f)) ? 0.f : -zq / pq;
+  else beta = (it == 0 || !(prev > 0.f)) ? 0.f : rz / prev;
   const float pap = (zs + 2.f * beta * zq) + (beta * beta) * pq;
   // (a breakdown leaves x and r unchanged; the next gate sees the same r.r)
   const float alpha = (pap > 0.f) ? rz / pap : 0.f;
@@ -631,7 +635,29 @@ void mg_outer(MGWork& w, double* phi, const int64_t* Q, int inner, hipStream_t s
   for (int it = 0; it < inner; ++it) {
     vcycle(w, Gate{part_rr, g, it}, s);
     k_cg_s<<<g, kB, 0, s>>>(m, m.b, w.s, w.p, w.q, w.sc, part4);
-    k_cg_x<<<g, kB, 0, s>>>(m, const_cast<float*>(m.b), w.s, w.p, w.q, w.xc, w.sc, part4, part_rr, it);
+    k_cg_x<<<g, kB, 0, s>>>(m, const_cast<float*>(m.b), w.s, w.p, w.q, w.xc, w.sc, part4, part_rr, it,
+                            0);
+  }
+  k_phi_update<<<g, kB, 0, s>>>(m.nr, m.nz, w.xc, phi, w.sc);
+  mg_residual(w, phi, Q, s);
+}
+
+void mg_outer_learned(MGWork& w, Unet* u, double* phi, const int64_t* Q, int inner, hipStream_t s) {
+  const MGLevel& m = w.lev[0];
+  const int n = (m.nr + 1) * (m.nz - 1), g = grid_for(n);
+  k_cg_init<<<g, kB, 0, s>>>(w.op, phi, Q, m, w.xc, w.p, w.q, w.sc);
+  float* part4 = w.part;
+  float* part_rr = w.part + 4 * kMGParts;
+  for (int it = 0; it < inner; ++it) {
+    // the network gives the first direction (its input is then the
+    // right-hand side it was trained on: charge, or the change of charge
+    // since the last solve); the V-cycle preconditions the rest, and the
+    // flexible recurrence keeps each direction A-orthogonal to the last
+    if (it == 0) unet_apply(u, m, w.sc, part_rr, g, it, s);
+    else vcycle(w, Gate{part_rr, g, it}, s);
+    k_cg_s<<<g, kB, 0, s>>>(m, m.b, w.s, w.p, w.q, w.sc, part4);
+    k_cg_x<<<g, kB, 0, s>>>(m, const_cast<float*>(m.b), w.s, w.p, w.q, w.xc, w.sc, part4, part_rr, it,
+                            1);
   }
   k_phi_update<<<g, kB, 0, s>>>(m.nr, m.nz, w.xc, phi, w.sc);
   mg_residual(w, phi, Q, s);

@@ -69,6 +69,8 @@ struct pd_ctx {
   MGWork mg{};
   MGScal* h_sc = nullptr;  // pinned host copy of the solve scalars
   bool mg_on = false;
+  bool learned = false;
+  struct pd_unet* net = nullptr;
   int mg_inner = 8, mg_inner_max = 16, mg_outer_max = 8;
   int64_t p_solves = 0, p_fallbacks = 0;
 
@@ -79,9 +81,18 @@ struct pd_ctx {
   int64_t t_steps = 0;
 };
 
+struct pd_unet {
+  pd::Unet* u = nullptr;
+  hipStream_t stream = nullptr;
+  std::string err;
+};
+
 namespace {
 
 thread_local std::string g_create_err;
+thread_local std::string g_unet_err;
+
+pd::Unet* unet_of(pd_unet* n) { return n->u; }
 
 pd_status set_err(pd_ctx* c, pd_status s, const char* fmt, ...) {
   char buf[512];
@@ -392,7 +403,7 @@ pd_status read_mg(pd_ctx* c) {
 pd_status solve_poisson(pd_ctx* c) {
   hipStream_t s = c->stream;
   c->p_solves += 1;
-  if (!c->mg_on) {
+  if (!c->mg_on || (c->learned && !c->net)) {
     poisson_direct(c->g, c->fw, s);
     return PD_OK;
   }
@@ -400,7 +411,8 @@ pd_status solve_poisson(pd_ctx* c) {
   // already meets the tolerance turns it into no-ops on the device
   mg_residual(c->mg, c->fw.phi, c->fw.Q, s);
   for (int o = 0;; ++o) {
-    mg_outer(c->mg, c->fw.phi, c->fw.Q, c->mg_inner, s);
+    if (c->learned) mg_outer_learned(c->mg, unet_of(c->net), c->fw.phi, c->fw.Q, c->mg_inner, s);
+    else mg_outer(c->mg, c->fw.phi, c->fw.Q, c->mg_inner, s);
     pd_status st = read_mg(c);
     if (st) return st;
     // CG iterations for the next refinement: one more than the last took
@@ -545,10 +557,12 @@ pd_status pd_create(const pd_domain* dom, const pd_opts* opts, pd_ctx** out) {
       dom->capacity > (int64_t)kScanChunk * kScanMaxBlocks)
     return fail(set_err(c, PD_EINVAL, "invalid domain"));
   if ((opts->precision != PD_FP64_DET && opts->precision != PD_FP32_MIXED) ||
-      (opts->poisson != PD_POISSON_DIRECT64 && opts->poisson != PD_POISSON_MGPCG) ||
+      (opts->poisson != PD_POISSON_DIRECT64 && opts->poisson != PD_POISSON_MGPCG &&
+       opts->poisson != PD_POISSON_LEARNED) ||
       !(opts->poisson_rtol >= 0.0) || !std::isfinite(opts->poisson_rtol))
     return fail(set_err(c, PD_EINVAL, "unsupported precision or Poisson mode"));
-  c->mg_on = opts->poisson == PD_POISSON_MGPCG;
+  c->mg_on = opts->poisson != PD_POISSON_DIRECT64;
+  c->learned = opts->poisson == PD_POISSON_LEARNED;
   c->fp32 = opts->precision == PD_FP32_MIXED;
   if (opts->stream) {
     c->stream = (hipStream_t)opts->stream;
@@ -1001,6 +1015,125 @@ pd_status pd_poisson(pd_ctx* c, const int64_t* Q, double* phi, int32_t* iters, d
   if (rel_res) *rel_res = c->h_sc->rel;
   if (phi) HIPCHK(c, hipMemcpy(phi, c->fw.phi, 8 * nn, hipMemcpyDeviceToHost));
   return PD_OK;
+}
+
+pd_status pd_unet_create(int32_t nr, int32_t nz, int32_t levels, int32_t base, int32_t batch,
+                         int64_t dataset_capacity, pd_unet** out) {
+  if (!out) return PD_EINVAL;
+  *out = nullptr;
+  pd_unet* n = new (std::nothrow) pd_unet();
+  if (!n) return PD_ENOMEM;
+  std::string err;
+  n->u = unet_create(nr, nz, levels, base, batch, dataset_capacity, err);
+  if (!n->u) {
+    g_unet_err = err;
+    delete n;
+    return err.find("alloc") != std::string::npos ? PD_ENOMEM : PD_EINVAL;
+  }
+  if (hipStreamCreate(&n->stream) != hipSuccess) {
+    unet_destroy(n->u);
+    delete n;
+    g_unet_err = "stream";
+    return PD_EDEVICE;
+  }
+  std::vector<float> zero((size_t)unet_nparams(n->u), 0.f);
+  unet_set_weights(n->u, zero.data(), n->stream);
+  *out = n;
+  return PD_OK;
+}
+
+pd_status pd_unet_info(const pd_unet* n, int64_t* np, int32_t* H, int32_t* W) {
+  if (!n) return PD_EINVAL;
+  if (np) *np = unet_nparams(n->u);
+  if (H) *H = unet_height(n->u);
+  if (W) *W = unet_width(n->u);
+  return PD_OK;
+}
+
+pd_status pd_unet_set_weights(pd_unet* n, const float* w) {
+  if (!n || !w) return PD_EINVAL;
+  const int64_t np = unet_nparams(n->u);
+  for (int64_t k = 0; k < np; ++k)
+    if (!std::isfinite(w[k])) {
+      n->err = "non-finite weight";
+      return PD_EINVAL;
+    }
+  if (unet_set_weights(n->u, w, n->stream)) {
+    n->err = "device error";
+    return PD_EDEVICE;
+  }
+  return PD_OK;
+}
+
+pd_status pd_unet_get_weights(const pd_unet* n, float* w) {
+  if (!n || !w) return PD_EINVAL;
+  return unet_get_weights(n->u, w) ? PD_EDEVICE : PD_OK;
+}
+
+pd_status pd_unet_forward(pd_unet* n, int32_t k, const float* x, float* out) {
+  if (!n || !x || !out || k < 1) return PD_EINVAL;
+  if (unet_forward_host(n->u, k, x, out, n->stream)) {
+    n->err = "batch too large or device error";
+    return PD_EINVAL;
+  }
+  return PD_OK;
+}
+
+pd_status pd_unet_gradient(pd_unet* n, int32_t k, const float* x, const float* dout, float* dw) {
+  if (!n || !x || !dout || !dw || k < 1) return PD_EINVAL;
+  if (unet_gradient_host(n->u, k, x, dout, dw, n->stream)) {
+    n->err = "batch too large or device error";
+    return PD_EINVAL;
+  }
+  return PD_OK;
+}
+
+pd_status pd_unet_add_sample(pd_unet* n, pd_ctx* c) {
+  if (!n || !c) return PD_EINVAL;
+  pd_status s = sync(c);
+  if (s) return s;
+  const int rc = unet_add_sample(n->u, c->mg.op, c->fw.phi, c->fw.Q, c->dom.V_cathode, c->stream);
+  if (rc == -1) {
+    n->err = "training set full";
+    return PD_ECAPACITY;
+  }
+  if (rc) {
+    n->err = "grid of the context differs from the network's";
+    return PD_EINVAL;
+  }
+  return sync(c);
+}
+
+pd_status pd_unet_train(pd_unet* n, int32_t epochs, int32_t batch, double lr, uint64_t seed,
+                        double* loss) {
+  if (!n || epochs < 1 || batch < 1 || !(lr > 0)) return PD_EINVAL;
+  if (unet_train(n->u, epochs, batch, lr, seed, loss, n->stream)) {
+    n->err = "empty training set, batch too large, or device error";
+    return PD_EINVAL;
+  }
+  return PD_OK;
+}
+
+pd_status pd_set_unet(pd_ctx* c, pd_unet* n) {
+  if (!c) return PD_EINVAL;
+  if (n && !c->learned) return set_err(c, PD_ESTATE, "context not created with PD_POISSON_LEARNED");
+  if (n && (unet_height(n->u) < c->g.nz + 1 || unet_width(n->u) < c->g.nr + 1))
+    return set_err(c, PD_EINVAL, "network grid smaller than the context's");
+  pd_status s = sync(c);
+  if (s) return s;
+  if (n && hipStreamSynchronize(n->stream) != hipSuccess) return set_err(c, PD_EDEVICE, "network");
+  c->net = n;
+  return PD_OK;
+}
+
+const char* pd_unet_last_error(const pd_unet* n) { return n ? n->err.c_str() : g_unet_err.c_str(); }
+
+void pd_unet_destroy(pd_unet* n) {
+  if (!n) return;
+  if (n->stream) (void)hipStreamSynchronize(n->stream);
+  unet_destroy(n->u);
+  if (n->stream) (void)hipStreamDestroy(n->stream);
+  delete n;
 }
 
 pd_status pd_get_timing(pd_ctx* c, double* ms, int64_t* steps, int reset) {

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <string>
 
 namespace pd {
 
@@ -208,6 +209,32 @@ void diag_snapshot(const PartsT<T>& P, const DevState* st, const Grid& g, const 
                    const double* edges, unsigned long long* counts /*[kDiagBlocks*6]*/,
                    double* ke /*[kDiagBlocks*6]*/, unsigned long long* spec /*[3*66]*/,
                    hipStream_t s);
+// ---- learned Poisson part: U-Net on the BF16 matrix cores (k_unet.hip) ----
+struct Unet;
+Unet* unet_create(int nr, int nz, int levels, int base, int batch, int64_t dataset_cap,
+                  std::string& err);
+void unet_destroy(Unet* u);
+int64_t unet_nparams(const Unet* u);
+int unet_height(const Unet* u);
+int unet_width(const Unet* u);
+int64_t unet_samples(const Unet* u);
+int unet_set_weights(Unet* u, const float* host, hipStream_t s);
+int unet_get_weights(const Unet* u, float* host);
+// host [n][2][H][W] FP32 -> host [n][H][W] FP32
+int unet_forward_host(Unet* u, int n, const float* x, float* out, hipStream_t s);
+// gradient of sum(dout * out) with respect to the weights (flat FP32)
+int unet_gradient_host(Unet* u, int n, const float* x, const float* dout, float* dw, hipStream_t s);
+// the (b, phi_p) pair of the node charge Q and potential phi into the training set
+int unet_add_sample(Unet* u, const MGOp64& op, const double* phi, const int64_t* Q, double V,
+                    hipStream_t s);
+int unet_train(Unet* u, int epochs, int batch, double lr, uint64_t seed, double* loss, hipStream_t s);
+// preconditioner: z (level-0 x) = net(r) for CG iteration it (gated on sc)
+void unet_apply(Unet* u, const MGLevel& m, MGScal* sc, const float* part_rr, int nb, int it,
+                hipStream_t s);
+// one refinement with flexible CG: first direction from the network, the
+// rest preconditioned by the V-cycle
+void mg_outer_learned(MGWork& w, Unet* u, double* phi, const int64_t* Q, int inner, hipStream_t s);
+
 void fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 void fill_i64(int64_t* p, int64_t v, int64_t n, hipStream_t s);
 

@@ -17,13 +17,16 @@ PD_OK, PD_EINVAL, PD_ENOMEM, PD_EDEVICE, PD_ESTATE, PD_ENOCONV, PD_ECAPACITY = 0
 STATUS_NAMES = {0: "PD_OK", -1: "PD_EINVAL", -2: "PD_ENOMEM", -3: "PD_EDEVICE", -4: "PD_ESTATE",
                 -5: "PD_ENOCONV", -6: "PD_ECAPACITY"}
 PD_FP64_DET, PD_FP32_MIXED = 0, 1
-PD_POISSON_DIRECT64, PD_POISSON_MGPCG = 0, 1
+PD_POISSON_DIRECT64, PD_POISSON_MGPCG, PD_POISSON_LEARNED = 0, 1, 2
 TIMER_NAMES = ("radix", "permute", "offsets", "collide", "deposit", "poisson", "field", "push",
                "inject")
 EXPORTED = ("pd_create", "pd_set_species", "pd_set_cross_section", "pd_inject",
             "pd_schedule_injection", "pd_step", "pd_synchronize", "pd_get_diagnostics",
             "pd_get_spectrum", "pd_get_count", "pd_get_particles", "pd_get_field",
-            "pd_poisson", "pd_get_timing", "pd_last_error", "pd_destroy")
+            "pd_poisson", "pd_get_timing", "pd_last_error", "pd_destroy",
+            "pd_unet_create", "pd_unet_info", "pd_unet_set_weights", "pd_unet_get_weights",
+            "pd_unet_forward", "pd_unet_gradient", "pd_unet_add_sample", "pd_unet_train",
+            "pd_set_unet", "pd_unet_last_error", "pd_unet_destroy")
 
 
 class PdError(RuntimeError):
@@ -84,10 +87,25 @@ def load_library(path=LIB_PATH):
     lib.pd_get_timing.argtypes = [P, P, C.POINTER(C.c_int64), C.c_int]
     lib.pd_last_error.argtypes = [P]
     lib.pd_last_error.restype = C.c_char_p
+    lib.pd_unet_create.argtypes = [C.c_int32] * 5 + [C.c_int64, C.POINTER(C.c_void_p)]
+    lib.pd_unet_info.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
+                                 C.POINTER(C.c_int32)]
+    lib.pd_unet_set_weights.argtypes = [P, P]
+    lib.pd_unet_get_weights.argtypes = [P, P]
+    lib.pd_unet_forward.argtypes = [P, C.c_int32, P, P]
+    lib.pd_unet_gradient.argtypes = [P, C.c_int32, P, P, P]
+    lib.pd_unet_add_sample.argtypes = [P, P]
+    lib.pd_unet_train.argtypes = [P, C.c_int32, C.c_int32, C.c_double, C.c_uint64,
+                                  C.POINTER(C.c_double)]
+    lib.pd_set_unet.argtypes = [P, P]
+    lib.pd_unet_last_error.argtypes = [P]
+    lib.pd_unet_last_error.restype = C.c_char_p
+    lib.pd_unet_destroy.argtypes = [P]
+    lib.pd_unet_destroy.restype = None
     lib.pd_destroy.argtypes = [P]
     lib.pd_destroy.restype = None
     for name in EXPORTED:
-        if name not in ("pd_last_error", "pd_destroy"):
+        if name not in ("pd_last_error", "pd_destroy", "pd_unet_last_error", "pd_unet_destroy"):
             getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -202,6 +220,77 @@ def pd_poisson(ctx, Q, nr, nz):
     rel = C.c_double()
     _check(ctx, load_library().pd_poisson(ctx, _ptr(q), _ptr(phi), C.byref(it), C.byref(rel)))
     return phi.reshape(nz + 1, nr + 1), it.value, rel.value
+
+
+def _check_net(net, status):
+    if status != PD_OK:
+        msg = load_library().pd_unet_last_error(net)
+        raise PdError(status, msg.decode() if msg else "")
+
+
+def pd_unet_create(nr, nz, levels=4, base=16, batch=4, dataset_capacity=0):
+    h = C.c_void_p()
+    _check_net(None, load_library().pd_unet_create(nr, nz, levels, base, batch,
+                                                   int(dataset_capacity), C.byref(h)))
+    return h
+
+
+def pd_unet_info(net):
+    n, H, W = C.c_int64(), C.c_int32(), C.c_int32()
+    _check_net(net, load_library().pd_unet_info(net, C.byref(n), C.byref(H), C.byref(W)))
+    return n.value, H.value, W.value
+
+
+def pd_unet_set_weights(net, w):
+    w = np.ascontiguousarray(w, np.float32)
+    _check_net(net, load_library().pd_unet_set_weights(net, _ptr(w)))
+
+
+def pd_unet_get_weights(net):
+    n, _, _ = pd_unet_info(net)
+    w = np.zeros(n, np.float32)
+    _check_net(net, load_library().pd_unet_get_weights(net, _ptr(w)))
+    return w
+
+
+def pd_unet_forward(net, x):
+    x = np.ascontiguousarray(x, np.float32)
+    out = np.zeros((x.shape[0], x.shape[2], x.shape[3]), np.float32)
+    _check_net(net, load_library().pd_unet_forward(net, x.shape[0], _ptr(x), _ptr(out)))
+    return out
+
+
+def pd_unet_gradient(net, x, dout):
+    x = np.ascontiguousarray(x, np.float32)
+    d = np.ascontiguousarray(dout, np.float32)
+    n, _, _ = pd_unet_info(net)
+    dw = np.zeros(n, np.float32)
+    _check_net(net, load_library().pd_unet_gradient(net, x.shape[0], _ptr(x), _ptr(d), _ptr(dw)))
+    return dw
+
+
+def pd_unet_add_sample(net, ctx):
+    _check_net(net, load_library().pd_unet_add_sample(net, ctx))
+
+
+def pd_unet_train(net, epochs, batch, lr, seed=1):
+    loss = C.c_double()
+    _check_net(net, load_library().pd_unet_train(net, epochs, batch, lr, seed, C.byref(loss)))
+    return loss.value
+
+
+def pd_set_unet(ctx, net):
+    _check(ctx, load_library().pd_set_unet(ctx, net))
+
+
+def pd_unet_last_error(net):
+    msg = load_library().pd_unet_last_error(net)
+    return msg.decode() if msg else ""
+
+
+def pd_unet_destroy(net):
+    if net:
+        load_library().pd_unet_destroy(net)
 
 
 def pd_get_timing(ctx, reset=False):

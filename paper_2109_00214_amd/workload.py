@@ -192,3 +192,30 @@ def injection_schedule(cfg, nsteps, first_step=0):
 
 def subset(parts, idx):
     return {k: np.ascontiguousarray(v[idx]) for k, v in parts.items()}
+
+
+# ---------------------------------------------------------------------------
+# learned Poisson part: initial weights of the U-Net (seeded He-normal), in the
+# layer order of the library's flat weight vector
+def unet_layer_shapes(levels=4, base=16, cin=2):
+    """(c_out, c_in, k) per layer: encoder levels, decoder levels from the
+    bottom up to level 0, then the 1x1 output layer."""
+    out, prev = [], cin
+    for l in range(levels):
+        c = base << l
+        out += [(c, prev, 3), (c, c, 3)]
+        prev = c
+    for l in range(levels - 2, -1, -1):
+        c = base << l
+        out += [(c, c + (base << (l + 1)), 3), (c, c, 3)]
+    out.append((1, base, 1))
+    return out
+
+
+def unet_init_weights(levels=4, base=16, seed=1):
+    rng = np.random.Generator(np.random.Philox(key=[seed, 0x4E4554]))
+    parts = []
+    for co, ci, k in unet_layer_shapes(levels, base):
+        std = np.sqrt(2.0 / (ci * k * k)) if k == 3 else np.sqrt(1.0 / ci)
+        parts.append(rng.normal(0.0, std, size=co * k * k * ci))
+    return np.concatenate(parts).astype(np.float32)

@@ -1,0 +1,165 @@
+"""GPU checks of the learned Poisson part through the C-ABI: the BF16-MFMA
+U-Net forward pass and weight gradient against the FP64 oracle (on inputs
+and weights rounded to BF16 the way the kernels store them), training on
+pairs dumped from a running simulation, and the learned solver (flexible CG
+preconditioned by the trained network inside FP64 refinement) reaching the
+relative residual 1e-8 as the oracle measures it."""
+import numpy as np
+import pytest
+
+from conftest import make_oracle
+from gpu_common import gpu_sim, log
+from oracle import unet_oracle as U
+from paper_2109_00214_amd import pd
+from paper_2109_00214_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+
+
+def bf16(a):
+    """round to nearest-even BF16, returned as float64"""
+    a = np.ascontiguousarray(a, np.float32)
+    b = a.view(np.uint32).astype(np.uint64)
+    b = ((b + 0x7FFF + ((b >> 16) & 1)) >> 16) << 16
+    return b.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def net_small():
+    cfg = W.config("tiny")  # 32 x 64 cells: images 72 x 40
+    net = pd.pd_unet_create(cfg.nr, cfg.nz, 4, 16, 2, 256)
+    yield cfg, net
+    pd.pd_unet_destroy(net)
+
+
+def test_unet_forward_matches_oracle(net_small):
+    cfg, net = net_small
+    n, H, Wd = pd.pd_unet_info(net)
+    assert (n, H, Wd) == (U.n_params(4, 16, 2), 72, 40)
+    log("case: U-Net forward, 2 images of %dx%d, %d weights" % (H, Wd, n))
+    w = W.unet_init_weights(4, 16, seed=3)
+    pd.pd_unet_set_weights(net, w)
+    rng = np.random.default_rng(5)
+    x = rng.normal(size=(2, 2, H, Wd)).astype(np.float32)
+    out = pd.pd_unet_forward(net, x)
+    wq = bf16(w[:-16]).tolist() + w[-16:].astype(np.float64).tolist()
+    ref = U.forward(x, wq, 4, 16, rounding="bf16")[:, 0]
+    e = _rel(out, ref)
+    log("  relative L2 error vs the FP64 oracle with BF16 activations: %.3e" % e)
+    assert e < 1e-2
+    e0 = _rel(out, U.forward(bf16(x), wq, 4, 16)[:, 0])
+    log("  relative L2 error vs the FP64 oracle with FP64 activations: %.3e" % e0)
+    assert e0 < 3e-2
+    # positive homogeneity survives the BF16 arithmetic to its rounding
+    out2 = pd.pd_unet_forward(net, 4.0 * x)
+    assert _rel(out2, 4.0 * out) < 1e-6
+
+
+def test_unet_weight_gradient_matches_oracle(net_small):
+    cfg, net = net_small
+    n, H, Wd = pd.pd_unet_info(net)
+    log("case: U-Net weight gradient against the oracle")
+    w = W.unet_init_weights(4, 16, seed=4)
+    pd.pd_unet_set_weights(net, w)
+    rng = np.random.default_rng(6)
+    x = rng.normal(size=(2, 2, H, Wd)).astype(np.float32)
+    # a coherent output gradient (as a loss against a smooth target gives),
+    # so that each weight gradient is not a random-sign sum
+    yy, xx = np.meshgrid(np.arange(H), np.arange(Wd), indexing="ij")
+    dout = np.stack([np.sin(np.pi * yy / H) * (1 + xx / Wd), np.cos(np.pi * yy / H)]).astype(np.float32)
+    dout += 0.1 * rng.normal(size=dout.shape).astype(np.float32)
+    dw = pd.pd_unet_gradient(net, x, dout)
+    wq = bf16(w[:-16]).tolist() + w[-16:].astype(np.float64).tolist()
+    gref, _ = U.weight_gradient(x, wq, dout[:, None].astype(np.float64), 4, 16, rounding="bf16")
+    o = 0
+    worst = 0.0
+    cosines = []
+    for k, (co, ci, kk) in enumerate(U.layer_shapes(4, 16, 2)):
+        m = co * ci * kk * kk
+        e = _rel(dw[o:o + m], gref[o:o + m])
+        cos = float(np.dot(dw[o:o + m], gref[o:o + m]) /
+                    (np.linalg.norm(dw[o:o + m]) * np.linalg.norm(gref[o:o + m])))
+        log("  layer %2d (%3d <- %3d): rel %.3e cos %.6f" % (k, co, ci, e, cos))
+        worst = max(worst, e)
+        cosines.append(cos)
+        o += m
+    assert min(cosines) > 0.999 and worst < 5e-2
+
+
+def _dump_pairs(cfg, net, steps, every):
+    g = gpu_sim(cfg, 400_000)
+    g.inject(W.initial_population(cfg))
+    off, inj = W.injection_schedule(cfg, steps)
+    g.schedule_injection(off, inj)
+    for s in range(steps):
+        g.step(1)
+        if s % every == 0:
+            pd.pd_unet_add_sample(net, g.h)
+    g.close()
+
+
+def _held_out(cfg, seed):
+    """a charge the network has not seen: the oracle's deposit of a fresh
+    population, its exact potential (direct solve) and the network sample"""
+    o = make_oracle(cfg, collisions_off=True)
+    o.inject(W.initial_population(W.config(cfg.name, seed=seed), n=30_000))
+    for st in ("sort", "collide", "deposit", "poisson"):
+        o.stage(st)
+    f = o.field()
+    j = np.arange(cfg.nz + 1)
+    vac = np.repeat(((-cfg.V) + cfg.V * (j / cfg.nz))[:, None], cfg.nr + 1, axis=1)
+    x, y = U.sample(o, f["Q"], f["phi"] - vac)
+    return o, f["Q"].copy(), x, y
+
+
+def _scaled_error(pred, y, nr, nz):
+    """relative L2 error of the best positive multiple of pred (the CG line
+    search finds that multiple) on the real interior nodes"""
+    p = pred[1:nz, :nr + 1].astype(np.float64)
+    t = y[1:nz, :nr + 1]
+    a = max(float(np.dot(p.ravel(), t.ravel()) / np.dot(p.ravel(), p.ravel())), 0.0)
+    return float(np.linalg.norm(a * p - t) / np.linalg.norm(t))
+
+
+def test_unet_training_and_learned_solver(net_small):
+    cfg, net = net_small
+    log("case: train on pairs dumped from the 32x64 workload, then predict and solve")
+    w0 = W.unet_init_weights(4, 16, seed=7)
+    pd.pd_unet_set_weights(net, w0)
+    _dump_pairs(cfg, net, 200, 1)
+    l0 = pd.pd_unet_train(net, 1, 2, 1e-3, seed=1)
+    l1 = pd.pd_unet_train(net, 11, 2, 1e-3, seed=2)
+    log("  training loss: first epoch %.4f, after 12 epochs %.4f" % (l0, l1))
+    assert np.isfinite(l1) and l1 < 0.25 * l0
+    wt = pd.pd_unet_get_weights(net)
+    # what the trained network gains: its guess of a held-out potential
+    # against the untrained network's and against no guess (error 1)
+    errs = {"trained": [], "untrained": []}
+    for seed in (11, 12):
+        o, Q, x, y = _held_out(cfg, seed)
+        for name, w in (("trained", wt), ("untrained", w0)):
+            pd.pd_unet_set_weights(net, w)
+            pred = pd.pd_unet_forward(net, x[None].astype(np.float32))[0]
+            errs[name].append(_scaled_error(pred, y, cfg.nr, cfg.nz))
+    log("  held-out potential, error of the best multiple of the guess: trained %s, "
+        "untrained %s (no guess: 1)" % (np.round(errs["trained"], 4), np.round(errs["untrained"], 4)))
+    assert max(errs["trained"]) < 0.3 and max(errs["trained"]) < 0.5 * min(errs["untrained"])
+    # the learned solver reaches the tolerance (as the oracle measures it)
+    pd.pd_unet_set_weights(net, wt)
+    o, Q, _, _ = _held_out(cfg, 11)
+    g = gpu_sim(cfg, 1024, poisson=pd.PD_POISSON_LEARNED)
+    pd.pd_set_unet(g.h, net)
+    phi, it, rel = g.poisson(Q)
+    rn, bn = o.poisson_residual(Q, phi)
+    d = g.diag()
+    g.close()
+    gm = gpu_sim(cfg, 1024, poisson=pd.PD_POISSON_MGPCG)
+    _, itm, _ = gm.poisson(Q)
+    gm.close()
+    log("  learned: %d FCG iterations, rel-res %.3e (oracle %.3e), fallbacks %d; MG-PCG: %d" %
+        (it, rel, rn / bn, d["poisson_fallbacks"], itm))
+    assert rn / bn <= 1e-8 and d["poisson_fallbacks"] == 0

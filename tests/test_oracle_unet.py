@@ -104,3 +104,26 @@ def test_sample_target_is_the_solution_of_the_input():
     assert np.sqrt(np.mean(x[0, 1:cfg.nz, :cfg.nr + 1] ** 2)) == pytest.approx(1.0)
     assert np.sqrt(np.mean(y[1:cfg.nz, :cfg.nr + 1] ** 2)) == pytest.approx(1.0)
     assert np.all(x[:, cfg.nz + 1:] == 0) and np.all(y[cfg.nz:] == 0)
+
+
+def test_bf16_rounding_helper():
+    """nearest-even BF16: exact values stay, halfway cases go to even, and
+    the error is at most half a BF16 ulp (2^-8 relative)"""
+    import torch
+    # BF16 keeps 8 significant bits: the ulp at 1 is 2^-7
+    v = torch.tensor([1.0 + 2 ** -7, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, 1.0 + 3 * 2 ** -9, -3.5, 0.0],
+                     dtype=torch.float64)
+    r = U.bf16_round(v).numpy()
+    # halfway cases 1 + 2^-8 (-> 1) and 1 + 3 2^-8 (-> 1 + 2^-6) go to the even neighbour
+    assert list(r) == [1.0 + 2 ** -7, 1.0, 1.0 + 2 ** -6, 1.0 + 2 ** -7, -3.5, 0.0]
+    rng = np.random.default_rng(9)
+    x = torch.as_tensor(rng.normal(size=1000) * 1e3)
+    e = np.abs(U.bf16_round(x).numpy() - x.numpy()) / np.abs(x.numpy())
+    assert e.max() <= 2 ** -8 + 1e-12
+    # the rounded forward is the plain forward up to that rounding, and the
+    # straight-through gradient is finite and close to the plain one
+    xx = rng.normal(size=(1, 2, 8, 8))
+    w = rng.normal(size=U.n_params(2, 4, 2)) * 0.5
+    a = U.forward(xx, w, 2, 4)
+    b = U.forward(xx, w, 2, 4, rounding="bf16")
+    assert np.linalg.norm(a - b) / np.linalg.norm(a) < 2e-2
