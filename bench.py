@@ -40,8 +40,12 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--config", default="paper")
     ap.add_argument("--n-init", type=int, default=None)
-    ap.add_argument("--poisson", choices=("direct", "mgpcg"), default="direct",
-                    help="direct FP64 solve, or FP32 multigrid CG with FP64 refinement")
+    ap.add_argument("--poisson", choices=("direct", "mgpcg", "learned"), default="direct",
+                    help="direct FP64 solve; FP32 multigrid CG with FP64 refinement; or flexible "
+                         "CG whose first direction comes from a U-Net trained here first")
+    ap.add_argument("--train-samples", type=int, default=1000,
+                    help="learned: (charge, potential) pairs dumped from the workload")
+    ap.add_argument("--train-epochs", type=int, default=4, help="learned: training epochs")
     ap.add_argument("--precision", choices=("fp64", "fp32"), default="fp64",
                     help="FP64 deterministic, or the FP32 particle record (FP32 gather/push)")
     ap.add_argument("--cpu-steps", type=int, default=40,
@@ -90,8 +94,9 @@ def main():
     import torch
 
     from paper_2109_00214_amd import workload as W
+    from paper_2109_00214_amd import pd as P
     from paper_2109_00214_amd.pd import (PD_FP32_MIXED, PD_FP64_DET, PD_POISSON_DIRECT64,
-                                         PD_POISSON_MGPCG, Simulation)
+                                         PD_POISSON_LEARNED, PD_POISSON_MGPCG, Simulation)
 
     kw = {} if a.n_init is None else {"n_init": a.n_init}
     cfg = W.config(a.config, **kw)
@@ -104,10 +109,35 @@ def main():
     torch.cuda.init()
     stream = torch.cuda.current_stream()
     cap = int(1.25 * cfg.n_init + cfg.inj_cu * nsteps + 40 * cfg.inj_e + 1_000_000)
+    precision = PD_FP32_MIXED if a.precision == "fp32" else PD_FP64_DET
+    net, learned = None, {}
+    if a.poisson == "learned":
+        # training pairs from the same workload (direct solves), then Adam on
+        # the GPU; none of this is inside the timed region
+        t1 = time.time()
+        net = P.pd_unet_create(cfg.nr, cfg.nz, 4, 16, 4, a.train_samples)
+        P.pd_unet_set_weights(net, W.unet_init_weights(4, 16, seed=cfg.seed))
+        gen = Simulation(cfg, cap, W.cross_section_tables(), W.species_table(), precision=precision)
+        gen.inject(parts)
+        off_t, inj_t = W.injection_schedule(cfg, a.train_samples)
+        gen.schedule_injection(off_t, inj_t)
+        for _ in range(a.train_samples):
+            gen.step(1)
+            P.pd_unet_add_sample(net, gen.h)
+        gen.close()
+        t2 = time.time()
+        loss = P.pd_unet_train(net, a.train_epochs, 4, 1e-3, seed=cfg.seed)
+        torch.cuda.synchronize()
+        learned = {"train_samples": a.train_samples, "train_epochs": a.train_epochs,
+                   "dump_s": round(t2 - t1, 2), "train_s": round(time.time() - t2, 2),
+                   "final_loss": loss, "network": "U-Net 4 levels, 16-128 channels, BF16 MFMA"}
+        print("learned: %s" % learned, file=sys.stderr)
+    pmode = {"direct": PD_POISSON_DIRECT64, "mgpcg": PD_POISSON_MGPCG,
+             "learned": PD_POISSON_LEARNED}[a.poisson]
     sim = Simulation(cfg, cap, W.cross_section_tables(), W.species_table(), timing=True,
-                     stream=stream.cuda_stream,
-                     poisson=PD_POISSON_MGPCG if a.poisson == "mgpcg" else PD_POISSON_DIRECT64,
-                     precision=PD_FP32_MIXED if a.precision == "fp32" else PD_FP64_DET)
+                     stream=stream.cuda_stream, poisson=pmode, precision=precision)
+    if net is not None:
+        P.pd_set_unet(sim.h, net)
     sim.inject(parts)
     sim.schedule_injection(off, inj)
     sim.step(a.warmup)
@@ -162,9 +192,12 @@ def main():
                                 cfg.inj_e + cfg.inj_cu,
                                 "FP32 record/gather/push, FP64 collisions" if a.precision == "fp32"
                                 else "FP64 deterministic"),
-                   "poisson": ("direct FP64 (sine transform + tridiagonal)"
-                               if a.poisson == "direct" else
-                               "FP32 multigrid-preconditioned CG, FP64 refinement, rtol 1e-8"),
+                   "poisson": {"direct": "direct FP64 (sine transform + tridiagonal)",
+                               "mgpcg": "FP32 multigrid-preconditioned CG, FP64 refinement, "
+                                        "rtol 1e-8",
+                               "learned": "FP32 flexible CG, first direction from the U-Net, "
+                                          "then multigrid; FP64 refinement, rtol 1e-8"}[a.poisson],
+                   "learned": learned or None,
                    "poisson_s_per_step": per_step["poisson"] / 1e3,
                    "poisson_rel_res_final": d1["poisson_rel_res"],
                    "poisson_cg_iters_per_step": (d1["poisson_iters"] - d0["poisson_iters"]) / a.steps,
@@ -178,6 +211,8 @@ def main():
         "cpu_baseline": None,
     }
     sim.close()
+    if net is not None:
+        P.pd_unet_destroy(net)
     if a.cpu_steps > 0:
         out["cpu_baseline"] = cpu_baseline(cfg, parts, off, inj, a.cpu_steps)
     del np

@@ -136,28 +136,27 @@ __global__ void __launch_bounds__(64) k_wgrad(WgradArgs a) {
   const int s = blockIdx.z;
   const int cin = a.c0 + a.c1, co = co0 + l32, ci = ci0 + l32;
   const int Hh = a.H >> 1, Wh = a.W >> 1;
-  const int64_t P = (int64_t)a.N * a.H * a.W;
-  const int64_t chunks = (P + 15) / 16;
+  // pixels in chunks of 16 along image rows: chunk = (row, 16-pixel segment)
+  const int xc = (a.W + 15) / 16;
+  const int total = a.N * a.H * xc;
+  const bool coin = co < a.cop, ciin = ci < cin, from0 = ci < a.c0;
   f32x16 acc;
 #pragma unroll
   for (int i = 0; i < 16; ++i) acc[i] = 0.f;
-  for (int64_t ch = s; ch < chunks; ch += a.nsplit) {
+  for (int ch = s; ch < total; ch += a.nsplit) {
+    const int row = ch / xc, x0 = (ch - row * xc) * 16 + 8 * h;
+    const int n = row / a.H, y = row - n * a.H, yy = y + dy;
+    const bool rowin = yy >= 0 && yy < a.H && ciin;
+    const __bf16* pa = a.dP + ((size_t)row * a.W) * a.cop + co;
+    const __bf16* pb = from0 ? a.in0 + (((size_t)n * a.H + yy) * a.W) * a.c0 + ci
+                             : a.in1 + (((size_t)n * Hh + (yy >> 1)) * Wh) * a.c1 + (ci - a.c0);
     bf16x8 av, bv;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      const int64_t q = ch * 16 + 8 * h + i;
-      float va = 0.f, vb = 0.f;
-      if (q < P) {
-        if (co < a.cop) va = (float)a.dP[q * a.cop + co];
-        const int x = (int)(q % a.W), y = (int)((q / a.W) % a.H), n = (int)(q / ((int64_t)a.W * a.H));
-        const int yy = y + dy, xx = x + dx;
-        if (ci < cin && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W) {
-          if (ci < a.c0) vb = (float)a.in0[(((size_t)n * a.H + yy) * a.W + xx) * a.c0 + ci];
-          else vb = (float)a.in1[(((size_t)n * Hh + (yy >> 1)) * Wh + (xx >> 1)) * a.c1 + (ci - a.c0)];
-        }
-      }
-      av[i] = (__bf16)va;
-      bv[i] = (__bf16)vb;
+      const int x = x0 + i, xx = x + dx;
+      av[i] = (coin && x < a.W) ? pa[(size_t)x * a.cop] : (__bf16)0.f;
+      const bool ok = rowin && x < a.W && xx >= 0 && xx < a.W;
+      bv[i] = ok ? (from0 ? pb[(size_t)xx * a.c0] : pb[(size_t)(xx >> 1) * a.c1]) : (__bf16)0.f;
     }
     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
   }
@@ -270,12 +269,19 @@ __global__ void __launch_bounds__(256) k_conv1x1_bwd(const __bf16* in, const flo
   }
 }
 
-__global__ void k_reduce_cols(const float* part, int nb, int C, float* out) {
-  const int c = threadIdx.x;
-  if (c >= C) return;
+// out[c] = sum_b part[b][c]: one block per column, fixed order
+__global__ void __launch_bounds__(256) k_reduce_cols(const float* part, int nb, int C, float* out) {
+  const int c = blockIdx.x;
   float s = 0.f;
-  for (int b = 0; b < nb; ++b) s += part[b * C + c];
-  out[c] = s;
+  for (int b = threadIdx.x; b < nb; b += 256) s += part[b * C + c];
+  __shared__ float sh[256];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[c] = sh[0];
 }
 
 // dP = bf16(g * (y > 0))
@@ -561,6 +567,14 @@ bool ualloc(Unet* u, T** p, size_t n) {
 
 constexpr int kNT = 2;
 
+// pixel splits of a weight-gradient launch: about 4096 waves in all, at
+// most one split per 16-pixel chunk
+int wgrad_splits(int cot, int cit, int chunks) {
+  int ns = 4096 / (cot * cit * 9);
+  ns = std::max(1, std::min(512, ns));
+  return std::min(ns, std::max(1, chunks));
+}
+
 int nt_for(int cot) { return cot >= 2 ? kNT : 1; }
 
 void conv(const Unet& u, int N, int level, const __bf16* in0, int c0, const __bf16* in1, int c1,
@@ -660,7 +674,8 @@ Unet* unet_create(int nr, int nz, int levels, int base, int nbmax, int64_t ds_ca
     maxact = std::max(maxact, (size_t)N * u->lh(ly.level) * u->lw(ly.level) * (ly.c0p + ly.c1p));
     maxact = std::max(maxact, n);
     const int cot = ly.rows / 32, cit = tiles32(ly.c0p + ly.c1p);
-    u->wpart_n = std::max(u->wpart_n, (size_t)64 * cot * 32 * 9 * cit * 32);
+    const int ns = wgrad_splits(cot, cit, N * u->lh(ly.level) * ((u->lw(ly.level) + 15) / 16));
+    u->wpart_n = std::max(u->wpart_n, (size_t)ns * cot * 32 * 9 * cit * 32);
   }
   for (int l = 1; l < levels && ok; ++l)
     ok = ualloc(u, &u->pooled[l], (size_t)N * u->lh(l) * u->lw(l) * up16(base << (l - 1)));
@@ -754,7 +769,8 @@ void unet_backward_dev(Unet* u, int N, hipStream_t s) {
       case 48: k_conv1x1_bwd<48><<<nb, 256, 0, s>>>(a0, w1, P0, u->gout, u->gact.back(), u->opart); break;
       default: k_conv1x1_bwd<64><<<nb, 256, 0, s>>>(a0, w1, P0, u->gout, u->gact.back(), u->opart); break;
     }
-    k_reduce_cols<<<1, 64, 0, s>>>(u->opart, nb, u->layers.back().coutp, u->grad + (u->np - u->C));
+    k_reduce_cols<<<u->layers.back().coutp, 256, 0, s>>>(u->opart, nb, u->layers.back().coutp,
+                                                        u->grad + (u->np - u->C));
   }
   for (int k = nl - 1; k >= 0; --k) {
     const Unet::Layer& ly = u->layers[k];
@@ -766,10 +782,7 @@ void unet_backward_dev(Unet* u, int N, hipStream_t s) {
     // weight gradient
     {
       const int cot = ly.rows / 32, cit = tiles32(ly.c0p + ly.c1p);
-      int nsplit = 2048 / (cot * cit * 9);
-      nsplit = std::max(1, std::min(64, nsplit));
-      const int64_t chunks = (Pl + 15) / 16;
-      if (nsplit > chunks) nsplit = (int)chunks;
+      const int nsplit = wgrad_splits(cot, cit, N * Hl * ((Wl + 15) / 16));
       WgradArgs a{u->dP, in0, in1, ly.coutp, ly.c0p, ly.c1p, N, Hl, Wl, cit, nsplit, u->wpart};
       k_wgrad<<<dim3(cot * cit, 9, nsplit), 64, 0, s>>>(a);
       k_wgrad_reduce<<<gridn((int64_t)ly.cout * 9 * ly.cin), 256, 0, s>>>(
