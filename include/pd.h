@@ -209,6 +209,28 @@ pd_status pd_get_field(pd_ctx* ctx, double* phi, double* Er, double* Ez, int64_t
 pd_status pd_poisson(pd_ctx* ctx, const int64_t* Q, double* phi, int32_t* iters,
                      double* rel_res);
 
+/* ---- ensembles of independent replicas ----------------------------------
+ * Replicas (their own domain, seed, voltage, size and precision, created and
+ * set up as usual with the direct Poisson solver and timing off) advance
+ * together: two steps of every replica are captured once into one HIP graph
+ * (replica i on worker stream i mod nstreams, so independent replicas may
+ * overlap) and the graph is replayed.  The library does not own the members:
+ * destroy the ensemble before them.  Calls on members between ensemble steps
+ * are ordered after the ensemble's work; while a context is in an ensemble,
+ * pd_step and pd_schedule_injection on it return PD_ESTATE (the graph holds
+ * its buffers and the parity of its double buffer); pd_inject is allowed. */
+typedef struct pd_ensemble pd_ensemble;
+/* Errors: PD_EINVAL (no members, a repeated member, an iterative Poisson
+ * solver, timing on), PD_ESTATE (tables not set), PD_EDEVICE (capture).  */
+pd_status pd_ensemble_create(int32_t n, pd_ctx* const* members, int32_t nstreams,
+                             pd_ensemble** out);
+/* nsteps (even) steps of every member; returns after enqueueing.        */
+pd_status pd_ensemble_step(pd_ensemble* ens, int32_t nsteps);
+/* wait for the ensemble and report device errors of any member          */
+pd_status pd_ensemble_synchronize(pd_ensemble* ens);
+const char* pd_ensemble_last_error(const pd_ensemble* ens);
+void pd_ensemble_destroy(pd_ensemble* ens);
+
 /* ---- learned Poisson part (Eq. 8 solved with a network's help) ----------
  * A U-Net (levels, base width; 3x3 bias-free BF16 convolutions with FP32
  * accumulation and ReLU, 2x2 average pooling, nearest upsampling with skip

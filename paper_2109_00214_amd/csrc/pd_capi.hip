@@ -70,6 +70,7 @@ struct pd_ctx {
   MGScal* h_sc = nullptr;  // pinned host copy of the solve scalars
   bool mg_on = false;
   bool learned = false;
+  int in_ensemble = 0;    // the ensemble's graph holds this context's buffers
   struct pd_unet* net = nullptr;
   int mg_inner = 8, mg_inner_max = 16, mg_outer_max = 8;
   int64_t p_solves = 0, p_fallbacks = 0;
@@ -87,10 +88,22 @@ struct pd_unet {
   std::string err;
 };
 
+struct pd_ensemble {
+  std::vector<pd_ctx*> m;
+  hipStream_t s0 = nullptr;           // launch stream of the graph
+  std::vector<hipStream_t> ws;        // worker streams of the capture
+  std::vector<hipEvent_t> ev;         // K joins, fork, member ordering
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool owns = false;                  // members marked as in this ensemble
+  std::string err;
+};
+
 namespace {
 
 thread_local std::string g_create_err;
 thread_local std::string g_unet_err;
+thread_local std::string g_ens_err;
 
 pd::Unet* unet_of(pd_unet* n) { return n->u; }
 
@@ -485,6 +498,15 @@ void harvest_timing(pd_ctx* c) {
   c->ev_pending.clear();
 }
 
+// host-side bookkeeping of one step (injected counts from the schedule)
+void host_after_step(pd_ctx* c) {
+  if (c->host_sched_pos < c->sched_n) {
+    for (int k = 0; k < kNS; ++k) c->injected[k] += c->sched_species[c->host_sched_pos][k];
+    c->host_sched_pos += 1;
+  }
+  c->host_step += 1;
+}
+
 // host arrays -> staging buffers (converted to the record's precision) ->
 // appended after the particles held now
 template <class T>
@@ -735,6 +757,7 @@ pd_status pd_schedule_injection(pd_ctx* c, int nsteps, const int64_t* offs, cons
                                 const double* z, const double* vr, const double* vt,
                                 const double* vz, const uint8_t* sp) {
   if (!c) return PD_EINVAL;
+  if (c->in_ensemble) return set_err(c, PD_ESTATE, "schedule is fixed while in an ensemble");
   if (c->poisoned) return set_err(c, PD_ESTATE, "context unusable after an earlier error");
   if (nsteps < 0 || (nsteps > 0 && !offs) || (nsteps > 0 && offs[0] != 0))
     return set_err(c, PD_EINVAL, "bad schedule offsets");
@@ -788,6 +811,7 @@ pd_status pd_schedule_injection(pd_ctx* c, int nsteps, const int64_t* offs, cons
 
 pd_status pd_step(pd_ctx* c, int nsteps) {
   if (!c) return PD_EINVAL;
+  if (c->in_ensemble) return set_err(c, PD_ESTATE, "context steps through its ensemble");
   if (c->poisoned) return set_err(c, PD_ESTATE, "context unusable after an earlier error");
   if (nsteps < 0) return set_err(c, PD_EINVAL, "nsteps < 0");
   if (!c->species_set) return set_err(c, PD_ESTATE, "species not set");
@@ -813,11 +837,7 @@ pd_status pd_step(pd_ctx* c, int nsteps) {
       c->poisoned = true;
       return set_err(c, PD_EDEVICE, "launch failed: %s", hipGetErrorString(e));
     }
-    if (c->host_sched_pos < c->sched_n) {
-      for (int k = 0; k < kNS; ++k) c->injected[k] += c->sched_species[c->host_sched_pos][k];
-      c->host_sched_pos += 1;
-    }
-    c->host_step += 1;
+    host_after_step(c);
     if (c->opts.timing) {
       c->ev_pending.push_back(ev);
       if (c->ev_pending.size() >= 512) {
@@ -1015,6 +1035,157 @@ pd_status pd_poisson(pd_ctx* c, const int64_t* Q, double* phi, int32_t* iters, d
   if (rel_res) *rel_res = c->h_sc->rel;
   if (phi) HIPCHK(c, hipMemcpy(phi, c->fw.phi, 8 * nn, hipMemcpyDeviceToHost));
   return PD_OK;
+}
+
+pd_status pd_ensemble_create(int32_t n, pd_ctx* const* members, int32_t nstreams,
+                             pd_ensemble** out) {
+  if (!out || n < 1 || !members || nstreams < 1) return PD_EINVAL;
+  *out = nullptr;
+  for (int i = 0; i < n; ++i) {
+    pd_ctx* c = members[i];
+    if (!c || c->poisoned || !c->species_set || c->mg_on || c->opts.timing) {
+      g_ens_err = "member %d: missing, unusable, iterative Poisson solver or timing on";
+      g_ens_err.replace(g_ens_err.find("%d"), 2, std::to_string(i));
+      return PD_EINVAL;
+    }
+    if (!c->opts.collisions_off)
+      for (int k = 0; k < kNC; ++k)
+        if (!c->xs_set[k]) {
+          g_ens_err = "member " + std::to_string(i) + ": cross section not set";
+          return PD_ESTATE;
+        }
+    for (int j = 0; j < i; ++j)
+      if (members[j] == c) {
+        g_ens_err = "a context appears twice";
+        return PD_EINVAL;
+      }
+  }
+  pd_ensemble* e = new (std::nothrow) pd_ensemble();
+  if (!e) return PD_ENOMEM;
+  e->m.assign(members, members + n);
+  auto fail = [&](pd_status st, const char* msg) {
+    g_ens_err = msg;
+    pd_ensemble_destroy(e);
+    return st;
+  };
+  for (pd_ctx* c : e->m)
+    if (sync(c)) return fail(PD_EDEVICE, "member stream");
+  const int K = std::min(nstreams, n);
+  if (hipStreamCreate(&e->s0) != hipSuccess) return fail(PD_EDEVICE, "stream");
+  e->ws.assign(K, nullptr);
+  e->ev.assign(K + 2, nullptr);
+  for (int k = 0; k < K; ++k)
+    if (hipStreamCreate(&e->ws[k]) != hipSuccess) return fail(PD_EDEVICE, "stream");
+  for (auto& v : e->ev)
+    if (hipEventCreateWithFlags(&v, hipEventDisableTiming) != hipSuccess)
+      return fail(PD_EDEVICE, "event");
+  // capture two steps of every member, member i on worker stream i % K
+  std::vector<hipStream_t> own(n);
+  for (int i = 0; i < n; ++i) own[i] = e->m[i]->stream;
+  bool ok = hipStreamBeginCapture(e->s0, hipStreamCaptureModeRelaxed) == hipSuccess &&
+            hipEventRecord(e->ev[K], e->s0) == hipSuccess;
+  for (int k = 0; ok && k < K; ++k) ok = hipStreamWaitEvent(e->ws[k], e->ev[K], 0) == hipSuccess;
+  auto nomark = []() {};
+  for (int i = 0; ok && i < n; ++i) {
+    pd_ctx* c = e->m[i];
+    c->stream = e->ws[i % K];
+    const int64_t nn = (int64_t)(c->g.nr + 1) * (c->g.nz + 1);
+    for (int t = 0; ok && t < 2; ++t) {
+      const pd_status ps = c->fp32 ? enqueue_step(c, c->Af, c->Bf, nn, nomark)
+                                   : enqueue_step(c, c->A, c->B, nn, nomark);
+      ok = ps == PD_OK && hipGetLastError() == hipSuccess;
+    }
+  }
+  for (int k = 0; ok && k < K; ++k)
+    ok = hipEventRecord(e->ev[k], e->ws[k]) == hipSuccess &&
+         hipStreamWaitEvent(e->s0, e->ev[k], 0) == hipSuccess;
+  hipGraph_t g = nullptr;
+  const bool ended = hipStreamEndCapture(e->s0, &g) == hipSuccess;
+  for (int i = 0; i < n; ++i) {
+    e->m[i]->stream = own[i];
+    e->m[i]->p_solves -= 2;  // counted at replay
+  }
+  e->graph = g;
+  if (!ok || !ended || !g) return fail(PD_EDEVICE, "graph capture failed");
+  if (hipGraphInstantiate(&e->exec, g, nullptr, nullptr, 0) != hipSuccess)
+    return fail(PD_EDEVICE, "graph instantiation failed");
+  for (pd_ctx* c : e->m) c->in_ensemble += 1;
+  e->owns = true;
+  *out = e;
+  return PD_OK;
+}
+
+pd_status pd_ensemble_step(pd_ensemble* e, int32_t nsteps) {
+  if (!e) return PD_EINVAL;
+  if (nsteps < 0 || nsteps % 2) {
+    e->err = "nsteps must be even and >= 0";
+    return PD_EINVAL;
+  }
+  const int K = (int)e->ws.size();
+  // order after each member's own pending work
+  for (pd_ctx* c : e->m) {
+    if (c->poisoned) {
+      e->err = "a member is unusable";
+      return PD_ESTATE;
+    }
+    if (hipEventRecord(e->ev[K + 1], c->stream) != hipSuccess ||
+        hipStreamWaitEvent(e->s0, e->ev[K + 1], 0) != hipSuccess) {
+      e->err = "event";
+      return PD_EDEVICE;
+    }
+  }
+  for (int t = 0; t < nsteps; t += 2) {
+    if (hipGraphLaunch(e->exec, e->s0) != hipSuccess) {
+      e->err = "graph launch failed";
+      for (pd_ctx* c : e->m) c->poisoned = true;
+      return PD_EDEVICE;
+    }
+    for (pd_ctx* c : e->m) {
+      host_after_step(c);
+      host_after_step(c);
+      c->p_solves += 2;
+    }
+  }
+  // each member's later work waits for the ensemble's
+  if (hipEventRecord(e->ev[K + 1], e->s0) != hipSuccess) return PD_EDEVICE;
+  for (pd_ctx* c : e->m)
+    if (hipStreamWaitEvent(c->stream, e->ev[K + 1], 0) != hipSuccess) return PD_EDEVICE;
+  return PD_OK;
+}
+
+pd_status pd_ensemble_synchronize(pd_ensemble* e) {
+  if (!e) return PD_EINVAL;
+  if (hipStreamSynchronize(e->s0) != hipSuccess) {
+    e->err = "device error";
+    return PD_EDEVICE;
+  }
+  for (pd_ctx* c : e->m) {
+    pd_status s = pd_synchronize(c);
+    if (s) {
+      e->err = c->err;
+      return s;
+    }
+  }
+  return PD_OK;
+}
+
+const char* pd_ensemble_last_error(const pd_ensemble* e) {
+  return e ? e->err.c_str() : g_ens_err.c_str();
+}
+
+void pd_ensemble_destroy(pd_ensemble* e) {
+  if (!e) return;
+  if (e->s0) (void)hipStreamSynchronize(e->s0);
+  if (e->owns)
+    for (pd_ctx* c : e->m) c->in_ensemble -= 1;
+  if (e->exec) (void)hipGraphExecDestroy(e->exec);
+  if (e->graph) (void)hipGraphDestroy(e->graph);
+  for (auto v : e->ev)
+    if (v) (void)hipEventDestroy(v);
+  for (auto st : e->ws)
+    if (st) (void)hipStreamDestroy(st);
+  if (e->s0) (void)hipStreamDestroy(e->s0);
+  delete e;
 }
 
 pd_status pd_unet_create(int32_t nr, int32_t nz, int32_t levels, int32_t base, int32_t batch,

@@ -26,7 +26,9 @@ EXPORTED = ("pd_create", "pd_set_species", "pd_set_cross_section", "pd_inject",
             "pd_poisson", "pd_get_timing", "pd_last_error", "pd_destroy",
             "pd_unet_create", "pd_unet_info", "pd_unet_set_weights", "pd_unet_get_weights",
             "pd_unet_forward", "pd_unet_gradient", "pd_unet_add_sample", "pd_unet_train",
-            "pd_set_unet", "pd_unet_last_error", "pd_unet_destroy")
+            "pd_set_unet", "pd_unet_last_error", "pd_unet_destroy",
+            "pd_ensemble_create", "pd_ensemble_step", "pd_ensemble_synchronize",
+            "pd_ensemble_last_error", "pd_ensemble_destroy")
 
 
 class PdError(RuntimeError):
@@ -102,10 +104,18 @@ def load_library(path=LIB_PATH):
     lib.pd_unet_last_error.restype = C.c_char_p
     lib.pd_unet_destroy.argtypes = [P]
     lib.pd_unet_destroy.restype = None
+    lib.pd_ensemble_create.argtypes = [C.c_int32, P, C.c_int32, C.POINTER(C.c_void_p)]
+    lib.pd_ensemble_step.argtypes = [P, C.c_int32]
+    lib.pd_ensemble_synchronize.argtypes = [P]
+    lib.pd_ensemble_last_error.argtypes = [P]
+    lib.pd_ensemble_last_error.restype = C.c_char_p
+    lib.pd_ensemble_destroy.argtypes = [P]
+    lib.pd_ensemble_destroy.restype = None
     lib.pd_destroy.argtypes = [P]
     lib.pd_destroy.restype = None
     for name in EXPORTED:
-        if name not in ("pd_last_error", "pd_destroy", "pd_unet_last_error", "pd_unet_destroy"):
+        if name not in ("pd_last_error", "pd_destroy", "pd_unet_last_error", "pd_unet_destroy",
+                        "pd_ensemble_last_error", "pd_ensemble_destroy"):
             getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -291,6 +301,37 @@ def pd_unet_last_error(net):
 def pd_unet_destroy(net):
     if net:
         load_library().pd_unet_destroy(net)
+
+
+def _check_ens(ens, status):
+    if status != PD_OK:
+        msg = load_library().pd_ensemble_last_error(ens)
+        raise PdError(status, msg.decode() if msg else "")
+
+
+def pd_ensemble_create(ctxs, nstreams=4):
+    arr = (C.c_void_p * len(ctxs))(*[c.value if isinstance(c, C.c_void_p) else c for c in ctxs])
+    h = C.c_void_p()
+    _check_ens(None, load_library().pd_ensemble_create(len(ctxs), arr, nstreams, C.byref(h)))
+    return h
+
+
+def pd_ensemble_step(ens, nsteps):
+    _check_ens(ens, load_library().pd_ensemble_step(ens, nsteps))
+
+
+def pd_ensemble_synchronize(ens):
+    _check_ens(ens, load_library().pd_ensemble_synchronize(ens))
+
+
+def pd_ensemble_last_error(ens):
+    msg = load_library().pd_ensemble_last_error(ens)
+    return msg.decode() if msg else ""
+
+
+def pd_ensemble_destroy(ens):
+    if ens:
+        load_library().pd_ensemble_destroy(ens)
 
 
 def pd_get_timing(ctx, reset=False):
