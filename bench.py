@@ -48,6 +48,9 @@ def parse():
     ap.add_argument("--train-epochs", type=int, default=4, help="learned: training epochs")
     ap.add_argument("--precision", choices=("fp64", "fp32"), default="fp64",
                     help="FP64 deterministic, or the FP32 particle record (FP32 gather/push)")
+    ap.add_argument("--ensemble", type=int, default=0,
+                    help="run the batched ensemble of this many uneven replicas (FP32 records, "
+                         "one HIP graph per two steps) instead of the single workload")
     ap.add_argument("--cpu-steps", type=int, default=40,
                     help="oracle steps timed for the CPU baseline (0: skip)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles",
@@ -84,12 +87,104 @@ def cpu_baseline(cfg, parts, off, inj, nsteps):
             "seconds": dt}
 
 
+def run_ensemble(a):
+    """Uneven replicas (grid, voltage, size, seed) stepped together by replaying
+    one captured HIP graph of two steps; the number of worker streams of the
+    capture is picked by timing each candidate (the autotuner)."""
+    import torch
+
+    from paper_2109_00214_amd import pd as P
+    from paper_2109_00214_amd import workload as W
+    from paper_2109_00214_amd.pd import PD_FP32_MIXED, Simulation
+    cfgs = W.ensemble_configs(a.ensemble)
+    cands = (1, 2, 4, 8)
+    tune_steps, eager_steps = 6, 10
+    nsteps = len(cands) * tune_steps + a.warmup + a.steps + eager_steps
+    torch.cuda.init()
+    t0 = time.time()
+    sims = []
+    tables, species = W.cross_section_tables(), W.species_table()
+    for k, cfg in enumerate(cfgs):
+        parts = W.initial_population(cfg)
+        off, inj = W.injection_schedule(cfg, nsteps)
+        cap = int(1.25 * cfg.n_init + cfg.inj_cu * nsteps + 40 * cfg.inj_e + 65536)
+        sim = Simulation(cfg, cap, tables, species, precision=PD_FP32_MIXED)
+        sim.inject(parts)
+        sim.schedule_injection(off, inj)
+        sims.append(sim)
+        del parts
+        if k % 8 == 7:
+            print("replicas ready: %d of %d (%.1f s)" % (k + 1, len(cfgs), time.time() - t0),
+                  file=sys.stderr, flush=True)
+    hs = [s.h for s in sims]
+
+    def pushed():
+        return sum(s.diag()["particle_steps"] for s in sims)
+
+    def timed(ens, nst):
+        torch.cuda.synchronize()
+        p0 = pushed()
+        t = time.perf_counter()
+        P.pd_ensemble_step(ens, nst)
+        P.pd_ensemble_synchronize(ens)
+        dt = time.perf_counter() - t
+        return (pushed() - p0) / dt, dt
+
+    tune = {}
+    for ns in cands:
+        ens = P.pd_ensemble_create(hs, ns)
+        P.pd_ensemble_step(ens, 2)
+        P.pd_ensemble_synchronize(ens)
+        tune[ns] = timed(ens, tune_steps - 2)[0]
+        P.pd_ensemble_destroy(ens)
+    best = max(tune, key=tune.get)
+    print("autotune (worker streams -> particle-steps/s): %s; using %d" % (tune, best),
+          file=sys.stderr, flush=True)
+    ens = P.pd_ensemble_create(hs, best)
+    P.pd_ensemble_step(ens, a.warmup + (a.warmup % 2))
+    P.pd_ensemble_synchronize(ens)
+    ksteps = a.steps + (a.steps % 2)
+    value, secs = timed(ens, ksteps)
+    P.pd_ensemble_destroy(ens)
+    # the same replicas stepped one launch at a time (each on its own stream)
+    torch.cuda.synchronize()
+    p0 = pushed()
+    t = time.perf_counter()
+    for _ in range(eager_steps):
+        for s in sims:
+            s.step(1)
+    for s in sims:
+        s.synchronize()
+    eager = (pushed() - p0) / (time.perf_counter() - t)
+    n_particles = sum(c.n_init for c in cfgs)
+    out = {
+        "metric": "particle-steps/s incl. DSMC", "value": value, "unit": "particle-steps/s",
+        "n_gpus": 1, "steps": ksteps, "warmup": a.warmup, "ms_per_step": secs * 1e3 / ksteps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "ensemble: %d replicas, 128x256 or 256x512 r-z cells, V 1-5 kV, "
+                               "%d initial super-particles in all (log-uniform 0.2M-8M each), "
+                               "FP32 records, direct FP64 Poisson, one HIP graph per two steps"
+                               % (len(cfgs), n_particles),
+                   "replicas_256x512": sum(c.nr == 256 for c in cfgs),
+                   "worker_streams": best, "autotune": {str(k): v for k, v in tune.items()},
+                   "eager_particle_steps_per_s": eager},
+        "roofline": None, "cpu_baseline": None,
+    }
+    for s in sims:
+        s.close()
+    print(json.dumps(out))
+
+
 def main():
     a = parse()
     if a.gpus != 1:
         print("bench.py: this build runs on one GPU only (--gpus %d requested)" % a.gpus,
               file=sys.stderr)
         sys.exit(2)
+    if a.ensemble > 0:
+        run_ensemble(a)
+        return
     import numpy as np
     import torch
 

@@ -219,3 +219,22 @@ def unet_init_weights(levels=4, base=16, seed=1):
         std = np.sqrt(2.0 / (ci * k * k)) if k == 3 else np.sqrt(1.0 / ci)
         parts.append(rng.normal(0.0, std, size=co * k * k * ci))
     return np.concatenate(parts).astype(np.float32)
+
+
+# ---------------------------------------------------------------------------
+# batched ensemble: uneven replicas (grid 128x256 or 256x512 with p = 1/2,
+# cathode voltage uniform in 1-5 kV, particle count log-uniform in
+# [0.2M, 8M], seed 1000 + k, weight 5e6 / N so every replica carries the same
+# real charge, injection scaled with N from the paper-shaped rates)
+def ensemble_configs(n=48, seed=1000, nmin=200_000, nmax=8_000_000):
+    rng = _rng(seed, 0xE45E)
+    out = []
+    for k in range(n):
+        big = rng.random() < 0.5
+        V = 1000.0 + 4000.0 * rng.random()
+        N = int(round(np.exp(np.log(nmin) + (np.log(nmax) - np.log(nmin)) * rng.random())))
+        f = N / 5_000_000
+        out.append(Config("ensemble-%d" % k, 256 if big else 128, 512 if big else 256, V=V,
+                          weight=5e6 / N, seed=seed + k, n_init=N,
+                          inj_e=max(1, int(round(10_000 * f))), inj_cu=max(1, int(round(300 * f)))))
+    return out
