@@ -260,11 +260,12 @@ def main():
     dom = max(cand, key=cand.get)
     units = pst / a.steps
     achieved = ALGO_BYTES[dom] * units / (per_step[dom] / 1e3) / 1e9
-    # HBM bytes per launch from the counters, if taken on this workload and
-    # on the kernel as it is now
+    # HBM bytes per launch: bytes per particle from the counters (taken on
+    # this workload and on the kernel as it is now) times particles per launch
     from paper_2109_00214_amd.profiling import read_traffic
-    traffic = read_traffic(a.traffic).get(dom) if (cfg.name == "paper" and a.n_init is None and
-                                                    a.precision == "fp64") else None
+    bpp = read_traffic(a.traffic).get(dom) if (cfg.name == "paper" and a.n_init is None and
+                                                a.precision == "fp64") else None
+    traffic = round(bpp * units) if bpp is not None else None
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "bytes_per_particle": ALGO_BYTES[dom], "particles_per_launch": round(units)}

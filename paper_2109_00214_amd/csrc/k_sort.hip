@@ -347,7 +347,10 @@ __global__ void __launch_bounds__(256) k_gather(PartsT<T> src, PartsT<T> dst,
     uint8_t sp[kGatherPer];
 #pragma unroll
     for (int u = 0; u < kGatherPer; ++u) {
-      const uint32_t s = q[u];
+      // an absorbed particle's record is not written: read the (contiguous)
+      // record at its own position instead of its scattered source
+      const uint32_t p = p0 + u * blockDim.x;
+      const uint32_t s = (k[u] == sentinel) ? ((p < n) ? p : n - 1) : q[u];
       r[u] = src.r[s];
       z[u] = src.z[s];
       vr[u] = src.vr[s];
