@@ -64,56 +64,89 @@ struct ConvArgs {
   const int* done;    // skip the launch when *done (solver use), or NULL
 };
 
-template <int NT>
+// Block = 4 waves over 4 MT image rows x 32 columns and NT x 32 output
+// channels; wave w takes rows w MT .. w MT + MT - 1 (MT x NT accumulator
+// tiles).  Per 16-channel chunk the input patch (rows and columns with a
+// one-pixel halo, zero outside the image) and the weights [tap][c_out][16]
+// are staged in LDS; the MFMA operands are then 16-byte LDS reads (A: 32
+// consecutive pixels of one patch row, B: 32 consecutive output channels),
+// both conflict-free.
+template <int MT, int NT>
 __global__ void __launch_bounds__(256) k_conv3x3(ConvArgs a) {
+  constexpr int PR = 4 * MT + 2, PW = 34, NC = NT * 32;
+  __shared__ bf16x8 ps[PR * PW * 2];
+  __shared__ bf16x8 wl[9 * NC * 2];
   if (a.done && *a.done) return;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, h = lane >> 5, l32 = lane & 31;
   const int cog = (a.cot + NT - 1) / NT;
-  const int n = blockIdx.z / cog, t0 = (blockIdx.z % cog) * NT;
-  const int y = blockIdx.y * 4 + wv;
-  if (y >= a.H) return;  // the whole wave (no block barriers below)
-  const int x0 = blockIdx.x * 32;
-  const int px = x0 + (lane & 31), h = lane >> 5;
+  const int n = blockIdx.z / cog, cob = (blockIdx.z % cog) * NC;
+  const int y0 = blockIdx.y * 4 * MT, x0 = blockIdx.x * 32;
   const int cin = a.c0 + a.c1;
   const int Hh = a.H >> 1, Wh = a.W >> 1;
-  f32x16 acc[NT];
+  f32x16 acc[MT][NT];
 #pragma unroll
-  for (int t = 0; t < NT; ++t)
+  for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-    for (int i = 0; i < 16; ++i) acc[t][i] = 0.f;
-  for (int tap = 0; tap < 9; ++tap) {
-    const int yy = y + tap / 3 - 1, xx = px + tap % 3 - 1;
-    const bool inb = yy >= 0 && yy < a.H && xx >= 0 && xx < a.W;
-    const size_t q0 = inb ? (((size_t)n * a.H + yy) * a.W + xx) * a.c0 : 0;
-    const size_t q1 = (inb && a.in1) ? (((size_t)n * Hh + (yy >> 1)) * Wh + (xx >> 1)) * a.c1 : 0;
-    for (int c = 0; c < cin; c += 16) {
-      bf16x8 av;
+    for (int q = 0; q < NT; ++q)
 #pragma unroll
-      for (int i = 0; i < 8; ++i) av[i] = (__bf16)0.f;
-      if (inb) {
-        if (c < a.c0) av = *(const bf16x8*)(a.in0 + q0 + c + 8 * h);
-        else av = *(const bf16x8*)(a.in1 + q1 + (c - a.c0) + 8 * h);
+      for (int i = 0; i < 16; ++i) acc[mt][q][i] = 0.f;
+  bf16x8 zero;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) zero[i] = (__bf16)0.f;
+  for (int c = 0; c < cin; c += 16) {
+    __syncthreads();
+    // input patch: unit u = (pixel, half)
+    for (int u = t; u < PR * PW * 2; u += 256) {
+      const int pp = u >> 1, half = u & 1, r = pp / PW, cx = pp - r * PW;
+      const int y = y0 - 1 + r, x = x0 - 1 + cx;
+      bf16x8 v = zero;
+      if (y >= 0 && y < a.H && x >= 0 && x < a.W) {
+        if (c < a.c0)
+          v = *(const bf16x8*)(a.in0 + (((size_t)n * a.H + y) * a.W + x) * a.c0 + c + 8 * half);
+        else
+          v = *(const bf16x8*)(a.in1 + (((size_t)n * Hh + (y >> 1)) * Wh + (x >> 1)) * a.c1 +
+                               (c - a.c0) + 8 * half);
       }
+      ps[u] = v;
+    }
+    // weights: unit u = ((tap, co), half)
+    for (int u = t; u < 9 * NC * 2; u += 256) {
+      const int half = u & 1, tc = u >> 1, tap = tc / NC, co = tc - tap * NC;
+      wl[u] = *(const bf16x8*)(a.w + ((size_t)(cob + co) * 9 + tap) * cin + c + 8 * half);
+    }
+    __syncthreads();
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        const int co = (t0 + t) * 32 + (lane & 31);
-        const bf16x8 bv = *(const bf16x8*)(a.w + ((size_t)co * 9 + tap) * cin + c + 8 * h);
-        acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[t], 0, 0, 0);
+    for (int tap = 0; tap < 9; ++tap) {
+      const int dy = tap / 3, dx = tap % 3;
+      bf16x8 bv[NT];
+#pragma unroll
+      for (int q = 0; q < NT; ++q) bv[q] = wl[(tap * NC + q * 32 + l32) * 2 + h];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        const bf16x8 av = ps[((w * MT + mt + dy) * PW + l32 + dx) * 2 + h];
+#pragma unroll
+        for (int q = 0; q < NT; ++q)
+          acc[mt][q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv[q], acc[mt][q], 0, 0, 0);
       }
     }
   }
 #pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const int co = (t0 + t) * 32 + (lane & 31);
+  for (int q = 0; q < NT; ++q) {
+    const int co = cob + q * 32 + l32;
     if (co >= a.cstore) continue;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const int x = x0 + 8 * (i / 4) + 4 * h + (i % 4);
-      if (x >= a.W) continue;
-      const size_t o = (((size_t)n * a.H + y) * a.W + x) * a.cstore + co;
-      const float v = acc[t][i];
-      if (a.out_bf) a.out_bf[o] = (__bf16)(a.relu ? (v > 0.f ? v : 0.f) : v);
-      else a.out_f[o] = v;
+    for (int mt = 0; mt < MT; ++mt) {
+      const int y = y0 + w * MT + mt;
+      if (y >= a.H) continue;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int x = x0 + 8 * (i / 4) + 4 * h + (i % 4);
+        if (x >= a.W) continue;
+        const size_t o = (((size_t)n * a.H + y) * a.W + x) * a.cstore + co;
+        const float v = acc[mt][q][i];
+        if (a.out_bf) a.out_bf[o] = (__bf16)(a.relu ? (v > 0.f ? v : 0.f) : v);
+        else a.out_f[o] = v;
+      }
     }
   }
 }
@@ -583,9 +616,13 @@ void conv(const Unet& u, int N, int level, const __bf16* in0, int c0, const __bf
   ConvArgs a{in0, in1, w, c0, c1, N, u.lh(level), u.lw(level), cot, cstore, out_bf, out_f, relu,
              done};
   const int NT = nt_for(cot);
-  dim3 grid((a.W + 31) / 32, (a.H + 3) / 4, N * ((cot + NT - 1) / NT));
-  if (NT == 1) k_conv3x3<1><<<grid, 256, 0, s>>>(a);
-  else k_conv3x3<kNT><<<grid, 256, 0, s>>>(a);
+  if (NT == 1) {  // 4 rows x 32 channels per wave
+    dim3 grid((a.W + 31) / 32, (a.H + 15) / 16, N * cot);
+    k_conv3x3<4, 1><<<grid, 256, 0, s>>>(a);
+  } else {        // 2 rows x 64 channels per wave
+    dim3 grid((a.W + 31) / 32, (a.H + 7) / 8, N * ((cot + kNT - 1) / kNT));
+    k_conv3x3<2, kNT><<<grid, 256, 0, s>>>(a);
+  }
 }
 
 // input sources of 3x3 layer k in the forward pass
