@@ -40,9 +40,12 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--config", default="paper")
     ap.add_argument("--n-init", type=int, default=None)
-    ap.add_argument("--poisson", choices=("direct", "mgpcg", "learned"), default="direct",
-                    help="direct FP64 solve; FP32 multigrid CG with FP64 refinement; or flexible "
-                         "CG whose first direction comes from a U-Net trained here first")
+    ap.add_argument("--poisson", choices=("direct", "spectral", "mgpcg", "learned"),
+                    default="direct",
+                    help="direct FP64 solve with every sum in a fixed order (bit-identical to "
+                         "the oracle); the same direct solve on the FP64 matrix cores with "
+                         "scan-based tridiagonal solves; FP32 multigrid CG with FP64 refinement; "
+                         "or flexible CG whose first direction comes from a U-Net trained here")
     ap.add_argument("--train-samples", type=int, default=1000,
                     help="learned: (charge, potential) pairs dumped from the workload")
     ap.add_argument("--train-epochs", type=int, default=4, help="learned: training epochs")
@@ -191,7 +194,8 @@ def main():
     from paper_2109_00214_amd import workload as W
     from paper_2109_00214_amd import pd as P
     from paper_2109_00214_amd.pd import (PD_FP32_MIXED, PD_FP64_DET, PD_POISSON_DIRECT64,
-                                         PD_POISSON_LEARNED, PD_POISSON_MGPCG, Simulation)
+                                         PD_POISSON_LEARNED, PD_POISSON_MGPCG,
+                                         PD_POISSON_SPECTRAL, Simulation)
 
     kw = {} if a.n_init is None else {"n_init": a.n_init}
     cfg = W.config(a.config, **kw)
@@ -227,8 +231,8 @@ def main():
                    "dump_s": round(t2 - t1, 2), "train_s": round(time.time() - t2, 2),
                    "final_loss": loss, "network": "U-Net 4 levels, 16-128 channels, BF16 MFMA"}
         print("learned: %s" % learned, file=sys.stderr)
-    pmode = {"direct": PD_POISSON_DIRECT64, "mgpcg": PD_POISSON_MGPCG,
-             "learned": PD_POISSON_LEARNED}[a.poisson]
+    pmode = {"direct": PD_POISSON_DIRECT64, "spectral": PD_POISSON_SPECTRAL,
+             "mgpcg": PD_POISSON_MGPCG, "learned": PD_POISSON_LEARNED}[a.poisson]
     sim = Simulation(cfg, cap, W.cross_section_tables(), W.species_table(), timing=True,
                      stream=stream.cuda_stream, poisson=pmode, precision=precision)
     if net is not None:
@@ -288,7 +292,10 @@ def main():
                                 cfg.inj_e + cfg.inj_cu,
                                 "FP32 record/gather/push, FP64 collisions" if a.precision == "fp32"
                                 else "FP64 deterministic"),
-                   "poisson": {"direct": "direct FP64 (sine transform + tridiagonal)",
+                   "poisson": {"direct": "direct FP64 (sine transform + tridiagonal), "
+                                         "fixed summation order",
+                               "spectral": "direct FP64, transforms on the FP64 matrix cores, "
+                                           "tridiagonal solves as wave scans",
                                "mgpcg": "FP32 multigrid-preconditioned CG, FP64 refinement, "
                                         "rtol 1e-8",
                                "learned": "FP32 flexible CG, first direction from the U-Net, "

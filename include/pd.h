@@ -70,14 +70,19 @@ enum { PD_CATHODE = 0, PD_ANODE = 1, PD_OUTER = 2 };
  * arithmetic and diagnostics */
 enum { PD_FP64_DET = 0, PD_FP32_MIXED = 1 };
 /* Poisson solvers: the direct FP64 solve (sine transform in z, tridiagonal
- * in r); conjugate gradients in FP32 preconditioned by a geometric
+ * in r), every sum in a fixed order (bit-identical to the method's binary64
+ * arithmetic); the same direct solve with the two transforms as FP64
+ * matrix-core products and the tridiagonal recurrences as parallel scans
+ * (equal to the former to rounding, about 1e-15 relative, and several times
+ * faster); conjugate gradients in FP32 preconditioned by a geometric
  * multigrid V-cycle inside FP64 iterative refinement; or flexible CG in FP32
  * inside the same refinement whose first direction comes from a trained
  * U-Net (pd_set_unet) applied to the residual and the others from the
  * V-cycle.  The iterative solvers start from the previous step's
  * potential and stop at the relative residual poisson_rtol; a solve that
  * does not get there falls back to the direct solve. */
-enum { PD_POISSON_DIRECT64 = 0, PD_POISSON_MGPCG = 1, PD_POISSON_LEARNED = 2 };
+enum { PD_POISSON_DIRECT64 = 0, PD_POISSON_MGPCG = 1, PD_POISSON_LEARNED = 2,
+       PD_POISSON_SPECTRAL = 3 };
 /* stages timed by pd_get_timing: radix passes of the sort, payload
  * permutation, CSR offsets, collisions, deposit, Poisson, field, push,
  * injection + counter roll */

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpd.so")
 SOURCES = ["pd_capi.hip", "k_sort.hip", "k_collide.hip", "k_pic.hip", "k_poisson.hip",
-           "k_mgpcg.hip", "k_unet.hip"]
+           "k_mgpcg.hip", "k_unet.hip", "k_spectral.hip"]
 ARCH = os.environ.get("PD_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH, "-ffp-contract=off",
          "-fno-fast-math", "-Wall", "-Wno-unused-result",

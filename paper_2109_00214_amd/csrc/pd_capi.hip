@@ -70,6 +70,7 @@ struct pd_ctx {
   MGScal* h_sc = nullptr;  // pinned host copy of the solve scalars
   bool mg_on = false;
   bool learned = false;
+  bool spectral = false;  // direct solve on the matrix cores
   int in_ensemble = 0;    // the ensemble's graph holds this context's buffers
   struct pd_unet* net = nullptr;
   int mg_inner = 8, mg_inner_max = 16, mg_outer_max = 8;
@@ -416,6 +417,10 @@ pd_status read_mg(pd_ctx* c) {
 pd_status solve_poisson(pd_ctx* c) {
   hipStream_t s = c->stream;
   c->p_solves += 1;
+  if (c->spectral) {
+    poisson_spectral(c->g, c->fw, s);
+    return PD_OK;
+  }
   if (!c->mg_on || (c->learned && !c->net)) {
     poisson_direct(c->g, c->fw, s);
     return PD_OK;
@@ -572,7 +577,8 @@ pd_status pd_create(const pd_domain* dom, const pd_opts* opts, pd_ctx** out) {
     pd_destroy(c);
     return s;
   };
-  if (dom->nr < 2 || dom->nz < 2 || poisson_lds_bytes(dom->nr, dom->nz) > 65536 || dom->nz > 8192 ||
+  if (dom->nr < 2 || dom->nz < 2 || dom->nz > 8192 ||
+      (opts->poisson != PD_POISSON_SPECTRAL && poisson_lds_bytes(dom->nr, dom->nz) > 65536) ||
       (int64_t)dom->nr * dom->nz * 6 >= (1LL << 31) || !(dom->R > 0) || !(dom->L > 0) ||
       !(dom->dt > 0) || !(dom->weight > 0) || !std::isfinite(dom->V_cathode) ||
       !std::isfinite(dom->R) || !std::isfinite(dom->L) || dom->capacity < 1 ||
@@ -580,10 +586,12 @@ pd_status pd_create(const pd_domain* dom, const pd_opts* opts, pd_ctx** out) {
     return fail(set_err(c, PD_EINVAL, "invalid domain"));
   if ((opts->precision != PD_FP64_DET && opts->precision != PD_FP32_MIXED) ||
       (opts->poisson != PD_POISSON_DIRECT64 && opts->poisson != PD_POISSON_MGPCG &&
-       opts->poisson != PD_POISSON_LEARNED) ||
+       opts->poisson != PD_POISSON_LEARNED && opts->poisson != PD_POISSON_SPECTRAL) ||
+      (opts->poisson == PD_POISSON_SPECTRAL && !spectral_fits(dom->nr, dom->nz)) ||
       !(opts->poisson_rtol >= 0.0) || !std::isfinite(opts->poisson_rtol))
     return fail(set_err(c, PD_EINVAL, "unsupported precision or Poisson mode"));
-  c->mg_on = opts->poisson != PD_POISSON_DIRECT64;
+  c->spectral = opts->poisson == PD_POISSON_SPECTRAL;
+  c->mg_on = opts->poisson != PD_POISSON_DIRECT64 && !c->spectral;
   c->learned = opts->poisson == PD_POISSON_LEARNED;
   c->fp32 = opts->precision == PD_FP32_MIXED;
   if (opts->stream) {
@@ -667,6 +675,27 @@ pd_status pd_create(const pd_domain* dom, const pd_opts* opts, pd_ctx** out) {
   c->fw.tinv = dti;
   c->fw.tcp = dtc;
   c->fw.qunit = c->qunit;
+  if (c->spectral) {
+    // the factors with r fastest per mode, and the right-hand-side scale
+    const int W = nr + 1;
+    std::vector<double> invT((size_t)M * W), cT((size_t)M * W), coef(W);
+    for (int k = 0; k < M; ++k)
+      for (int i = 0; i < W; ++i) {
+        invT[(size_t)k * W + i] = tinv[(size_t)i * M + k];
+        cT[(size_t)k * W + i] = tcp[(size_t)i * M + k];
+      }
+    for (int i = 0; i < W; ++i) coef[i] = -(c->qunit / (Vnode[i] * kEPS0));
+    double *dinvT, *dcT, *dcoef;
+    if ((s = dalloc(c, &dinvT, invT.size())) || (s = dalloc(c, &dcT, cT.size())) ||
+        (s = dalloc(c, &dcoef, coef.size())))
+      return fail(s);
+    if (!up(dinvT, invT.data(), invT.size() * 8) || !up(dcT, cT.data(), cT.size() * 8) ||
+        !up(dcoef, coef.data(), coef.size() * 8))
+      return fail(set_err(c, PD_EDEVICE, "table upload failed"));
+    c->fw.invT = dinvT;
+    c->fw.cT = dcT;
+    c->fw.coef = dcoef;
+  }
   c->cpar.Vcell = dVc;
   if ((s = build_mg(c, dVn))) return fail(s);
 

@@ -137,12 +137,20 @@ struct FieldWork {
   const double* ra;     // [nr+1] radial lower coefficients
   const double* Vnode;  // [nr+1]
   double qunit;
+  // tables of the matrix-core form of the direct solve (else NULL)
+  const double* invT;   // [(nz-1) * (nr+1)] Thomas reciprocals, r fastest
+  const double* cT;     // [(nz-1) * (nr+1)] Thomas upper factors, r fastest
+  const double* coef;   // [nr+1] -qunit / (V_node eps0)
 };
 template <typename T>
 void deposit(const PartsT<T>& P, const DevState* st, const uint32_t* off, const Grid& g,
              const SpeciesParams& sp, int64_t* Q, int64_t cap, hipStream_t s);
 void poisson_direct(const Grid& g, FieldWork& fw, hipStream_t s);
 size_t poisson_lds_bytes(int nr, int nz);
+// the same solve with the transforms on the FP64 matrix cores and the
+// tridiagonal recurrences as wave scans (k_spectral.hip)
+void poisson_spectral(const Grid& g, FieldWork& fw, hipStream_t s);
+bool spectral_fits(int nr, int nz);
 
 // ---- multigrid-preconditioned CG with FP64 refinement (k_mgpcg.hip) ----
 constexpr int kMGBlock = 256;

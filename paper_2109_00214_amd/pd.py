@@ -17,7 +17,7 @@ PD_OK, PD_EINVAL, PD_ENOMEM, PD_EDEVICE, PD_ESTATE, PD_ENOCONV, PD_ECAPACITY = 0
 STATUS_NAMES = {0: "PD_OK", -1: "PD_EINVAL", -2: "PD_ENOMEM", -3: "PD_EDEVICE", -4: "PD_ESTATE",
                 -5: "PD_ENOCONV", -6: "PD_ECAPACITY"}
 PD_FP64_DET, PD_FP32_MIXED = 0, 1
-PD_POISSON_DIRECT64, PD_POISSON_MGPCG, PD_POISSON_LEARNED = 0, 1, 2
+PD_POISSON_DIRECT64, PD_POISSON_MGPCG, PD_POISSON_LEARNED, PD_POISSON_SPECTRAL = 0, 1, 2, 3
 TIMER_NAMES = ("radix", "permute", "offsets", "collide", "deposit", "poisson", "field", "push",
                "inject")
 EXPORTED = ("pd_create", "pd_set_species", "pd_set_cross_section", "pd_inject",
