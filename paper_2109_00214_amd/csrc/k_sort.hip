@@ -8,16 +8,27 @@
 //
 // A pass over a digit of D <= 10 bits:
 //   up   -- per-tile digit histogram (wave ballots, one LDS update per
-//           distinct digit), digit-major in memory;
-//   scan -- exclusive scan of that histogram: global start of every
-//           (digit, tile) run;
-//   down -- stable ranking inside the tile: each wave walks its contiguous
+//           distinct digit), tile-major in memory (each tile one row);
+//   scan -- per digit, exclusive prefix over the tiles (in place) and the
+//           digit totals (one launch, one lane per digit);
+//   down -- start of every digit from the totals, plus the tile's prefix;
+//           stable ranking inside the tile: each wave walks its contiguous
 //           1024 keys 64 at a time, finds the lanes holding the same digit
 //           with one ballot per digit bit, ranks by popcount under the lane
 //           mask and carries a per-wave count per digit in LDS; a prefix
 //           over waves and digits then places every key at its tile-local
 //           sorted position in LDS, and the tile is written out in that
 //           order, so the stores of one digit run are contiguous.
+// Between steps the order changes little: the particles are still sorted
+// as the last sort left them, with the keys the push recomputed.  A
+// particle whose key did not change (a stayer) keeps its order relative to
+// the other stayers; only the others (movers: key changed, created,
+// injected, absorbed) are radix-sorted, by (key, index).  The two sorted
+// sequences are then merged by (key, index): a stayer's place is its rank
+// among stayers plus the movers before it (binary search over the sorted
+// movers); a mover's place is its rank among movers plus the stayers before
+// it, read off the previous order's per-key offsets and the count of movers
+// before each old position.  The result is the stable sort of all keys.
 // The particle records then move once, gathered by the source index with
 // contiguous stores.  No kernel waits on another block: every launch
 // finishes for any input.
@@ -180,8 +191,8 @@ __device__ inline uint32_t match_rank(uint32_t d, bool valid, uint64_t lt, uint3
 // Tiles are taken in a grid-stride loop by a grid of at most a few blocks
 // per CU: launching one block per possible tile of the capacity would
 // dispatch many empty blocks, each reserving its LDS.
-static inline int tile_grid(int64_t cap, int per_cu) {
-  int64_t tiles = (cap + kSortTile - 1) / kSortTile;
+static inline int tile_grid(int64_t cap, int per_cu, int tile) {
+  int64_t tiles = (cap + tile - 1) / tile;
   int64_t lim = 256 * per_cu;
   if (tiles < 1) tiles = 1;
   return (int)(tiles < lim ? tiles : lim);
@@ -190,67 +201,164 @@ static inline int tile_grid(int64_t cap, int per_cu) {
 // per-tile digit histogram: each wave ranks its contiguous 1024 keys 64 at a
 // time (all 16 rankings first, so their ballot chains overlap), then adds
 // one count per distinct digit to its LDS row (no atomics)
-template <int DB>
+template <int DB, int IT>
 __global__ void __launch_bounds__(256) k_radix_up(const uint32_t* __restrict__ keys,
-                                                  const DevState* st, int shift,
-                                                  uint32_t* __restrict__ hist,
-                                                  uint32_t* __restrict__ scan_len) {
+                                                  const uint32_t* np, int shift,
+                                                  uint32_t* __restrict__ hist) {
   constexpr int R = 1 << DB;
   __shared__ uint32_t wh[4][R];
-  const uint32_t n = st->n_total;
-  const uint32_t ntiles = (n + kSortTile - 1) / kSortTile;
+  const uint32_t n = *np;
+  const uint32_t ntiles = (n + (256 * IT) - 1) / (256 * IT);
   constexpr uint32_t mask = (uint32_t)R - 1u;
-  if (blockIdx.x == 0 && threadIdx.x == 0) *scan_len = (uint32_t)R * ntiles;
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     for (int d = t; d < R; d += 256) wh[0][d] = wh[1][d] = wh[2][d] = wh[3][d] = 0;
-    const uint32_t base = tile * kSortTile + w * (kSortTile / 4);
-    uint32_t dd[kSortItems], rr[kSortItems], cc[kSortItems];
+    const uint32_t base = tile * (256 * IT) + w * ((256 * IT) / 4);
+    uint32_t dd[IT], rr[IT], cc[IT];
 #pragma unroll
-    for (int it = 0; it < kSortItems; ++it) {
+    for (int it = 0; it < IT; ++it) {
       const uint32_t idx = base + it * 64 + lane;
       dd[it] = (keys[(idx < n) ? idx : n - 1] >> shift) & mask;  // clamped, unconditional
     }
 #pragma unroll
-    for (int it = 0; it < kSortItems; ++it)
+    for (int it = 0; it < IT; ++it)
       rr[it] = match_rank<DB>(dd[it], base + it * 64 + lane < n, lt, &cc[it]);
     __syncthreads();
 #pragma unroll
-    for (int it = 0; it < kSortItems; ++it)
+    for (int it = 0; it < IT; ++it)
       if (base + it * 64 + lane < n && rr[it] == 0) wh[w][dd[it]] += cc[it];
     __syncthreads();
     for (int d = t; d < R; d += 256)
-      hist[(size_t)d * ntiles + tile] = wh[0][d] + wh[1][d] + wh[2][d] + wh[3][d];
+      hist[(size_t)tile * R + d] = wh[0][d] + wh[1][d] + wh[2][d] + wh[3][d];
     __syncthreads();
   }
 }
 
-template <int DB, bool FIRST>  // FIRST: the values are the source indices
+// Per digit (one lane each, 64 digits per block): hist[t][d] <- sum of
+// hist[t'][d] over t' < t, and tot[d] <- the sum over all tiles.  The 16
+// waves of a block take consecutive runs of tiles; their run sums are
+// combined in LDS, then each wave rewrites its run.
+constexpr int kColWaves = 16;
+template <int R, int IT>
+__global__ void __launch_bounds__(64 * kColWaves) k_radix_colscan(uint32_t* __restrict__ hist,
+                                                                  uint32_t* __restrict__ tot,
+                                                                  const uint32_t* np) {
+  __shared__ uint32_t part[kColWaves][64];
+  const uint32_t n = *np;
+  const uint32_t ntiles = (n + (256 * IT) - 1) / (256 * IT);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int d = blockIdx.x * 64 + lane;
+  const uint32_t ch = (ntiles + kColWaves - 1) / kColWaves;
+  const uint32_t t0 = (uint32_t)w * ch;
+  const uint32_t t1 = (t0 + ch < ntiles) ? t0 + ch : ntiles;
+  uint32_t s = 0;
+  for (uint32_t tb = t0; tb < t1; tb += 8) {
+    uint32_t v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = (tb + u < t1) ? hist[(size_t)(tb + u) * R + d] : 0u;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
+  part[w][lane] = s;
+  __syncthreads();
+  uint32_t run = 0;
+  for (int q = 0; q < w; ++q) run += part[q][lane];
+  if (w == kColWaves - 1) tot[d] = run + s;
+  for (uint32_t tb = t0; tb < t1; tb += 8) {
+    uint32_t v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = (tb + u < t1) ? hist[(size_t)(tb + u) * R + d] : 0u;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (tb + u < t1) hist[(size_t)(tb + u) * R + d] = run;
+      run += v[u];
+    }
+  }
+}
+
+// Sorted movers sampled for the merge: every stride-th, stride a power of
+// two >= 64 that keeps the sample within kPlaceSamples entries.
+constexpr int kPlaceSamples = 2048;
+__host__ __device__ inline uint32_t sample_stride(uint32_t n) {
+  uint32_t s = 64;
+  while ((uint64_t)s * kPlaceSamples < n) s <<= 1;
+  return s;
+}
+
+// What the last pass over the movers needs to place them: a mover of
+// sorted rank r with (key k, index i) goes to ins + r, ins = stayers before
+// it = p - mpre[p] with p = i clamped to the old run of key k
+// [off_prev[k], off_prev[k+1]] (all stayers for the sentinel key).  ins is
+// kept per rank (non-decreasing) with a sample for the stayers' searches.
+struct MoverPlace {
+  const uint32_t* off_prev;
+  const uint32_t* mpre;
+  const DevState* st;
+  uint32_t sentinel;
+  uint32_t* skey;
+  uint32_t* perm;
+  uint32_t* ins;
+  uint32_t* samp;
+};
+
+__device__ inline uint32_t stayers_before(const MoverPlace& mp, uint32_t n_prev, uint32_t k,
+                                          uint32_t i) {
+  if (n_prev == 0) return 0;
+  if (k >= mp.sentinel) return n_prev - mp.mpre[n_prev];
+  const uint32_t lo = mp.off_prev[k], hi = mp.off_prev[k + 1];
+  const uint32_t p = (i < lo) ? lo : ((i > hi) ? hi : i);
+  return p - mp.mpre[p];
+}
+
+template <int DB, int IT, bool FIRST>  // FIRST: the values are the source indices
 __global__ void __launch_bounds__(256) k_radix_down(const uint32_t* __restrict__ kin,
                                                     const uint32_t* __restrict__ vin,
                                                     uint32_t* __restrict__ kout,
                                                     uint32_t* __restrict__ vout,
-                                                    const DevState* st, int shift,
-                                                    const uint32_t* __restrict__ hist) {
+                                                    const uint32_t* np, int shift,
+                                                    const uint32_t* __restrict__ hist,
+                                                    const uint32_t* __restrict__ tot,
+                                                    MoverPlace mp) {
   constexpr int R = 1 << DB;
   constexpr uint32_t mask = (uint32_t)R - 1u;
+  constexpr int PER = (R + 255) / 256;
   __shared__ uint32_t wh[4][R];
   __shared__ uint32_t gofs[R];
-  __shared__ uint32_t tkey[kSortTile];
-  __shared__ uint32_t tval[kSortTile];
+  __shared__ uint32_t dbase[R];
+  __shared__ uint32_t tkey[(256 * IT)];
+  __shared__ uint32_t tval[(256 * IT)];
   __shared__ uint32_t sh[4];
-  const uint32_t n = st->n_total;
-  const uint32_t ntiles = (n + kSortTile - 1) / kSortTile;
+  const uint32_t n = *np;
+  const uint32_t ntiles = (n + (256 * IT) - 1) / (256 * IT);
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  // global start of every digit: exclusive scan of the digit totals
+  {
+    uint32_t c[PER];
+    uint32_t s = 0;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int d = t * PER + q;
+      c[q] = (d < R) ? tot[d] : 0u;
+      s += c[q];
+    }
+    uint32_t total;
+    uint32_t run = block_scan256(s, &total, sh);
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int d = t * PER + q;
+      if (d < R) dbase[d] = run;
+      run += c[q];
+    }
+  }
   for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     for (int d = t; d < R; d += 256) wh[0][d] = wh[1][d] = wh[2][d] = wh[3][d] = 0;
-    const uint32_t tile0 = tile * kSortTile;
-    const uint32_t base = tile0 + w * (kSortTile / 4);
-    uint32_t kk[kSortItems], vv[kSortItems], rk[kSortItems], cc[kSortItems];
+    const uint32_t tile0 = tile * (256 * IT);
+    const uint32_t base = tile0 + w * ((256 * IT) / 4);
+    uint32_t kk[IT], vv[IT], rk[IT], cc[IT];
 #pragma unroll
-    for (int it = 0; it < kSortItems; ++it) {
+    for (int it = 0; it < IT; ++it) {
       const uint32_t idx = base + it * 64 + lane;
       const bool valid = idx < n;
       const uint32_t ic = valid ? idx : n - 1;  // clamped, unconditional loads
@@ -258,12 +366,12 @@ __global__ void __launch_bounds__(256) k_radix_down(const uint32_t* __restrict__
       vv[it] = FIRST ? idx : vin[ic];
     }
 #pragma unroll
-    for (int it = 0; it < kSortItems; ++it)
+    for (int it = 0; it < IT; ++it)
       rk[it] = match_rank<DB>((kk[it] >> shift) & mask, base + it * 64 + lane < n, lt, &cc[it]);
     __syncthreads();
     // carry the per-digit counts of earlier iterations (in-order per wave)
 #pragma unroll
-    for (int it = 0; it < kSortItems; ++it) {
+    for (int it = 0; it < IT; ++it) {
       const uint32_t d = (kk[it] >> shift) & mask;
       const uint32_t old = wh[w][d];
       if (base + it * 64 + lane < n && rk[it] == 0) wh[w][d] = old + cc[it];
@@ -273,7 +381,6 @@ __global__ void __launch_bounds__(256) k_radix_down(const uint32_t* __restrict__
     // tile-local start of every digit, start of each wave's share, and
     // global minus local start
     {
-      constexpr int PER = (R + 255) / 256;
       uint32_t cnt[PER];
       uint32_t s = 0;
 #pragma unroll
@@ -289,7 +396,7 @@ __global__ void __launch_bounds__(256) k_radix_down(const uint32_t* __restrict__
         const int d = t * PER + q;
         if (d < R) {
           const uint32_t a0 = wh[0][d], a1 = wh[1][d], a2 = wh[2][d];
-          gofs[d] = hist[(size_t)d * ntiles + tile] - run;
+          gofs[d] = dbase[d] + hist[(size_t)tile * R + d] - run;
           wh[0][d] = run;
           wh[1][d] = run + a0;
           wh[2][d] = run + a0 + a1;
@@ -300,7 +407,7 @@ __global__ void __launch_bounds__(256) k_radix_down(const uint32_t* __restrict__
     }
     __syncthreads();
 #pragma unroll
-    for (int it = 0; it < kSortItems; ++it) {
+    for (int it = 0; it < IT; ++it) {
       if (base + it * 64 + lane < n) {
         const uint32_t lp = wh[w][(kk[it] >> shift) & mask] + rk[it];
         tkey[lp] = kk[it];
@@ -308,13 +415,29 @@ __global__ void __launch_bounds__(256) k_radix_down(const uint32_t* __restrict__
       }
     }
     __syncthreads();
-    const uint32_t cnt = (n - tile0 < (uint32_t)kSortTile) ? (n - tile0) : (uint32_t)kSortTile;
+    const uint32_t cnt = (n - tile0 < (uint32_t)(256 * IT)) ? (n - tile0) : (uint32_t)(256 * IT);
+    if (!mp.skey) {
 #pragma unroll 4
-    for (uint32_t q = t; q < cnt; q += 256) {
-      const uint32_t k = tkey[q];
-      const uint32_t p = gofs[(k >> shift) & mask] + q;
-      kout[p] = k;
-      vout[p] = tval[q];
+      for (uint32_t q = t; q < cnt; q += 256) {
+        const uint32_t k = tkey[q];
+        const uint32_t p = gofs[(k >> shift) & mask] + q;
+        kout[p] = k;
+        vout[p] = tval[q];
+      }
+    } else {
+      // last pass: place the movers (p = final rank among the movers)
+      const uint32_t n_prev = mp.st->n_alive;
+      const uint32_t smask = sample_stride(n) - 1u;
+#pragma unroll 4
+      for (uint32_t q = t; q < cnt; q += 256) {
+        const uint32_t k = tkey[q], i = tval[q];
+        const uint32_t p = gofs[(k >> shift) & mask] + q;
+        const uint32_t ins = stayers_before(mp, n_prev, k, i);
+        mp.ins[p] = ins;
+        mp.skey[ins + p] = k;
+        mp.perm[ins + p] = i;
+        if ((p & smask) == 0) mp.samp[p / (smask + 1u)] = ins;
+      }
     }
     __syncthreads();
   }
@@ -376,54 +499,263 @@ __global__ void __launch_bounds__(256) k_gather(PartsT<T> src, PartsT<T> dst,
   }
 }
 
-template <int DB>
+// one pass over tiles of 256 IT keys (IT = 4: short tiles, many blocks,
+// for the movers, which are usually few)
+template <int DB, int IT>
 static void radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
-                       int shift, SortWork& w, DevState* st, hipStream_t s) {
-  const int tiles = (int)((w.cap + kSortTile - 1) / kSortTile);
-  k_radix_up<DB><<<tile_grid(w.cap, 4), 256, 0, s>>>(kin, st, shift, w.hist, w.scan_len);
-  scan_exclusive(w.hist, w.hist, w.scan_len, nullptr, w.bsum,
-                 (int64_t)(1 << DB) * (tiles < 1 ? 1 : tiles), s, nullptr, 0);
+                       int shift, SortWork& w, const uint32_t* np, const MoverPlace& samp,
+                       hipStream_t s) {
+  constexpr int R = 1 << DB;
+  k_radix_up<DB, IT><<<tile_grid(w.cap, 8, 256 * IT), 256, 0, s>>>(kin, np, shift, w.hist);
+  k_radix_colscan<R, IT><<<R / 64, 64 * kColWaves, 0, s>>>(w.hist, w.bsum, np);
   if (!vin)
-    k_radix_down<DB, true><<<tile_grid(w.cap, 3), 256, 0, s>>>(kin, vin, kout, vout, st, shift,
-                                                               w.hist);
+    k_radix_down<DB, IT, true><<<tile_grid(w.cap, 6, 256 * IT), 256, 0, s>>>(
+        kin, vin, kout, vout, np, shift, w.hist, w.bsum, samp);
   else
-    k_radix_down<DB, false><<<tile_grid(w.cap, 3), 256, 0, s>>>(kin, vin, kout, vout, st, shift,
-                                                                w.hist);
+    k_radix_down<DB, IT, false><<<tile_grid(w.cap, 6, 256 * IT), 256, 0, s>>>(
+        kin, vin, kout, vout, np, shift, w.hist, w.bsum, samp);
+}
+
+// ---- stayers and movers ---------------------------------------------------
+// position i is a mover unless it lies in the previous sorted prefix
+// (i < n_prev) with its key unchanged.  A thread takes kScanPer consecutive
+// positions, read as two 16-byte vectors when all of them are in range.
+__device__ inline void mover_flags(uint32_t base, uint32_t n, uint32_t n_prev,
+                                   const uint32_t* __restrict__ key,
+                                   const uint32_t* __restrict__ kprev, uint32_t* f,
+                                   uint32_t* kv) {
+  static_assert(kScanPer == 8, "two 16-byte vectors per thread");
+  if (base + 8 <= n) {
+    const uint4 a0 = *(const uint4*)(key + base), a1 = *(const uint4*)(key + base + 4);
+    kv[0] = a0.x; kv[1] = a0.y; kv[2] = a0.z; kv[3] = a0.w;
+    kv[4] = a1.x; kv[5] = a1.y; kv[6] = a1.z; kv[7] = a1.w;
+    if (base + 8 <= n_prev) {
+      const uint4 b0 = *(const uint4*)(kprev + base), b1 = *(const uint4*)(kprev + base + 4);
+      const uint32_t pv[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
+#pragma unroll
+      for (int k = 0; k < 8; ++k) f[k] = (kv[k] != pv[k]) ? 1u : 0u;
+      return;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) kv[k] = (base + k < n) ? key[base + k] : 0u;
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const uint32_t i = base + k;
+    f[k] = (i >= n) ? 0u : ((i >= n_prev) ? 1u : ((kv[k] != kprev[i]) ? 1u : 0u));
+  }
+}
+
+// movers per chunk of kScanChunk positions
+__global__ void __launch_bounds__(256) k_cls_count(const uint32_t* __restrict__ key,
+                                                   const uint32_t* __restrict__ kprev,
+                                                   const DevState* st, uint32_t* __restrict__ bsum,
+                                                   uint32_t* __restrict__ scan_len) {
+  __shared__ uint32_t sh[4];
+  const uint32_t n = st->n_total, n_prev = st->n_alive;
+  const uint32_t nb = (n + kScanChunk - 1) / kScanChunk;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *scan_len = n;
+  if (blockIdx.x >= nb) return;
+  const uint32_t base = blockIdx.x * kScanChunk + threadIdx.x * kScanPer;
+  uint32_t f[kScanPer], kv[kScanPer];
+  mover_flags(base, n, n_prev, key, kprev, f, kv);
+  uint32_t acc = 0;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) acc += f[k];
+  uint32_t tot;
+  block_scan256(acc, &tot, sh);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+// mpre[i] = movers in [0, i) for i <= n_prev; the movers' (key, index) in
+// index order to mk, mi
+__global__ void __launch_bounds__(256) k_cls_compact(const uint32_t* __restrict__ key,
+                                                     const uint32_t* __restrict__ kprev,
+                                                     const DevState* st,
+                                                     const uint32_t* __restrict__ bsum,
+                                                     uint32_t* __restrict__ mpre,
+                                                     uint32_t* __restrict__ mk,
+                                                     uint32_t* __restrict__ mi) {
+  __shared__ uint32_t sh[4];
+  const uint32_t n = st->n_total, n_prev = st->n_alive;
+  const uint32_t nb = (n + kScanChunk - 1) / kScanChunk;
+  if (blockIdx.x >= nb) return;
+  const uint32_t base = blockIdx.x * kScanChunk + threadIdx.x * kScanPer;
+  uint32_t f[kScanPer], kv[kScanPer];
+  mover_flags(base, n, n_prev, key, kprev, f, kv);
+  uint32_t acc = 0;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) acc += f[k];
+  uint32_t tot;
+  uint32_t run = bsum[blockIdx.x] + block_scan256(acc, &tot, sh);
+  uint32_t pre[kScanPer];
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    pre[k] = run;
+    const uint32_t i = base + k;
+    if (f[k]) {
+      mk[run] = kv[k];
+      mi[run] = i;
+    }
+    run += f[k];
+  }
+  if (base + 8 <= n_prev) {
+    *(uint4*)(mpre + base) = make_uint4(pre[0], pre[1], pre[2], pre[3]);
+    *(uint4*)(mpre + base + 4) = make_uint4(pre[4], pre[5], pre[6], pre[7]);
+  } else {
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k)
+      if (base + k <= n_prev && base + k < n) mpre[base + k] = pre[k];
+  }
+  // the entry after the last old position
+  if (n_prev == n && base < n && base + kScanPer >= n) mpre[n] = run;
+}
+
+// first j in [lo, hi) with ins[j] > s (the movers placed before the stayer
+// of rank s)
+__device__ inline uint32_t movers_upto(const uint32_t* __restrict__ ins, uint32_t lo, uint32_t hi,
+                                       uint32_t s) {
+  while (lo < hi) {
+    const uint32_t mid = lo + ((hi - lo) >> 1);
+    if (ins[mid] <= s) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+// the same over all nm movers, through the sample (entry j = ins[j stride])
+__device__ inline uint32_t movers_upto_sampled(const uint32_t* __restrict__ ins,
+                                               const uint32_t* __restrict__ samp, uint32_t nm,
+                                               uint32_t s) {
+  const uint32_t stride = sample_stride(nm);
+  uint32_t lo = 0, hi = (nm + stride - 1) / stride;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (samp[mid] <= s) lo = mid + 1;
+    else hi = mid;
+  }
+  if (lo == 0) return 0;
+  const uint32_t a = (lo - 1) * stride + 1;
+  const uint32_t b = (lo * stride < nm) ? lo * stride : nm;
+  return movers_upto(ins, a, b, s);
+}
+
+// Stayers' places, in chunks of kPlaceChunk old positions: the stayer of
+// rank s goes to s + (movers with ins <= s).  Chunk ch holds the stayer
+// ranks [s0(ch), s0(ch+1)), s0(ch) = base - mpre[base], so the movers it
+// needs are those of ranks [bound(ch), bound(ch+1)), bound(ch) = the count
+// for s0(ch): one search per chunk boundary (k_place_bounds), then the
+// chunk searches only its own movers, staged in LDS.
+constexpr int kPlaceChunk = 1024;
+constexpr int kPlaceLds = 2048;
+
+__global__ void __launch_bounds__(256) k_place_bounds(const DevState* st,
+                                                      const uint32_t* __restrict__ mpre,
+                                                      const uint32_t* __restrict__ ins,
+                                                      const uint32_t* __restrict__ samp,
+                                                      const uint32_t* __restrict__ n_mov,
+                                                      uint32_t* __restrict__ bound) {
+  const uint32_t n_prev = st->n_alive, nm = *n_mov;
+  const uint32_t nch = (n_prev + kPlaceChunk - 1) / kPlaceChunk;
+  for (uint32_t ch = blockIdx.x * blockDim.x + threadIdx.x; ch <= nch;
+       ch += gridDim.x * blockDim.x) {
+    const uint32_t base = (ch * kPlaceChunk < n_prev) ? ch * kPlaceChunk : n_prev;
+    bound[ch] = movers_upto_sampled(ins, samp, nm, base - mpre[base]);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_place(const uint32_t* __restrict__ key,
+                                               const DevState* st,
+                                               const uint32_t* __restrict__ mpre,
+                                               const uint32_t* __restrict__ ins,
+                                               const uint32_t* __restrict__ bound,
+                                               uint32_t* __restrict__ skey,
+                                               uint32_t* __restrict__ perm) {
+  __shared__ uint32_t lins[kPlaceLds];
+  const uint32_t n_prev = st->n_alive;
+  const int t = threadIdx.x;
+  const uint32_t nch = (n_prev + kPlaceChunk - 1) / kPlaceChunk;
+  for (uint32_t ch = blockIdx.x; ch < nch; ch += gridDim.x) {
+    const uint32_t base = ch * kPlaceChunk;
+    const uint32_t end = (base + kPlaceChunk < n_prev) ? base + kPlaceChunk : n_prev;
+    const uint32_t c0 = bound[ch], c1 = bound[ch + 1];
+    const bool in_lds = (c1 - c0) <= (uint32_t)kPlaceLds;
+    if (in_lds)
+      for (uint32_t j = c0 + t; j < c1; j += 256) lins[j - c0] = ins[j];
+    __syncthreads();
+#pragma unroll 4
+    for (uint32_t i = base + t; i < end; i += 256) {
+      const uint32_t m = mpre[i];
+      if (mpre[i + 1] != m) continue;  // a mover
+      const uint32_t sr = i - m;
+      uint32_t cnt;
+      if (in_lds) {
+        uint32_t lo = 0, hi = c1 - c0;
+        while (lo < hi) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (lins[mid] <= sr) lo = mid + 1;
+          else hi = mid;
+        }
+        cnt = c0 + lo;
+      } else {
+        cnt = movers_upto(ins, c0, c1, sr);
+      }
+      const uint32_t pos = sr + cnt;
+      skey[pos] = key[i];
+      perm[pos] = i;
+    }
+    __syncthreads();
+  }
 }
 
 // key_bits <= 20: two passes of ceil(key_bits/2) bits (at most 10);
 // wider keys: passes of 10 bits
 template <typename T>
 void sort_particles(const PartsT<T>& src, const PartsT<T>& dst, int key_bits, SortWork& w,
-                    DevState* st, uint32_t sentinel, int part, hipStream_t s) {
+                    DevState* st, const uint32_t* off, uint32_t sentinel, int part,
+                    hipStream_t s) {
   int passes = (key_bits + kRadixMaxBits - 1) / kRadixMaxBits;
   if (passes < 2) passes = 2;
   const int dbits = (key_bits + passes - 1) / passes;
+  const int nb = (int)((w.cap + kScanChunk - 1) / kScanChunk);
   if (part == 0) {
-    const uint32_t* kin = src.key;
-    const uint32_t* vin = nullptr;
+    // classify, count and compact the movers (key, index) into k0/v0
+    k_cls_count<<<nb, 256, 0, s>>>(src.key, w.skey, st, w.bsum, w.scan_len);
+    k_scan_bsums<<<1, 1024, 0, s>>>(w.bsum, w.scan_len, w.n_mov, nullptr, 0);
+    k_cls_compact<<<nb, 256, 0, s>>>(src.key, w.skey, st, w.bsum, w.mpre, w.k0, w.v0);
+    // stable radix sort of the movers
+    const uint32_t* kin = w.k0;
+    const uint32_t* vin = w.v0;
+    const MoverPlace none{};
+    const MoverPlace last{off, w.mpre, st, sentinel, w.skey, w.perm, w.ins, w.samp};
     for (int p = 0; p < passes; ++p) {
-      uint32_t* kout = (p & 1) ? w.k1 : w.k0;
-      uint32_t* vout = (p & 1) ? w.v1 : w.v0;
+      uint32_t* kout = (p & 1) ? w.k0 : w.k1;
+      uint32_t* vout = (p & 1) ? w.v0 : w.v1;
       const int shift = p * dbits;
-      if (dbits <= 8) radix_pass<8>(kin, vin, kout, vout, shift, w, st, s);
-      else radix_pass<10>(kin, vin, kout, vout, shift, w, st, s);
+      const MoverPlace& mp = (p == passes - 1) ? last : none;
+      if (dbits <= 8) radix_pass<8, kMoverItems>(kin, vin, kout, vout, shift, w, w.n_mov, mp, s);
+      else radix_pass<10, kMoverItems>(kin, vin, kout, vout, shift, w, w.n_mov, mp, s);
       kin = kout;
       vin = vout;
     }
+    // the stayers between them
+    const int64_t nch = (w.cap + kPlaceChunk - 1) / kPlaceChunk;
+    k_place_bounds<<<grid_for(nch + 1), 256, 0, s>>>(st, w.mpre, w.ins, w.samp, w.n_mov,
+                                                    w.bound);
+    int pg = (int)(nch < 16384 ? nch : 16384);
+    if (pg < 1) pg = 1;
+    k_place<<<pg, 256, 0, s>>>(src.key, st, w.mpre, w.ins, w.bound, w.skey, w.perm);
   } else {
-    const uint32_t* skeys = ((passes - 1) & 1) ? w.k1 : w.k0;
-    const uint32_t* perm = ((passes - 1) & 1) ? w.v1 : w.v0;
     int64_t gb = (w.cap + 256 * kGatherPer - 1) / (256 * kGatherPer);
     if (gb < 1) gb = 1;
     if (gb > 2048) gb = 2048;
-    k_gather<T><<<(int)gb, 256, 0, s>>>(src, dst, skeys, perm, st, sentinel);
+    k_gather<T><<<(int)gb, 256, 0, s>>>(src, dst, w.skey, w.perm, st, sentinel);
   }
 }
 template void sort_particles<double>(const Parts&, const Parts&, int, SortWork&, DevState*,
-                                     uint32_t, int, hipStream_t);
+                                     const uint32_t*, uint32_t, int, hipStream_t);
 template void sort_particles<float>(const PartsF&, const PartsF&, int, SortWork&, DevState*,
-                                    uint32_t, int, hipStream_t);
+                                    const uint32_t*, uint32_t, int, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // off[k] = first sorted position whose key >= k, for k = 0 .. nkeys-1;

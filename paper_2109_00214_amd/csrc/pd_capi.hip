@@ -537,9 +537,9 @@ template <class T, class Mark>
 pd_status enqueue_step(pd_ctx* c, PartsT<T>& A, PartsT<T>& B, int64_t nn, Mark& mark) {
   hipStream_t s = c->stream;
   mark();
-  sort_particles(A, B, c->key_bits, c->sw, c->st, c->g.sentinel, 0, s);
+  sort_particles(A, B, c->key_bits, c->sw, c->st, c->off, c->g.sentinel, 0, s);
   mark();
-  sort_particles(A, B, c->key_bits, c->sw, c->st, c->g.sentinel, 1, s);
+  sort_particles(A, B, c->key_bits, c->sw, c->st, c->off, c->g.sentinel, 1, s);
   std::swap(A, B);
   mark();
   build_offsets(A.key, c->st, c->off, c->g.sentinel + 1, c->fw.Q, (uint32_t)nn, s);
@@ -629,7 +629,7 @@ pd_status pd_create(const pd_domain* dom, const pd_opts* opts, pd_ctx** out) {
   const int64_t cap = c->cap;
   const int64_t nn = (int64_t)(nr + 1) * (nz + 1);
   const int M = nz - 1;
-  const int64_t tiles = (cap + kSortTile - 1) / kSortTile;
+  const int64_t tiles = (cap + kSortBlock * kMoverItems - 1) / (kSortBlock * kMoverItems);
   pd_status s;
   if ((c->fp32 ? ((s = alloc_parts(c, c->Af, cap)) || (s = alloc_parts(c, c->Bf, cap)) ||
                   (s = dalloc(c, &c->fw.Erf, nn)) || (s = dalloc(c, &c->fw.Ezf, nn)))
@@ -638,6 +638,10 @@ pd_status pd_create(const pd_domain* dom, const pd_opts* opts, pd_ctx** out) {
       (s = dalloc(c, &c->sw.v0, cap)) || (s = dalloc(c, &c->sw.v1, cap)) ||
       (s = dalloc(c, &c->sw.hist, (size_t)kRadix * (tiles < 1 ? 1 : tiles))) ||
       (s = dalloc(c, &c->sw.bsum, kScanMaxBlocks)) || (s = dalloc(c, &c->sw.scan_len, 4)) ||
+      (s = dalloc(c, &c->sw.skey, cap)) || (s = dalloc(c, &c->sw.mpre, cap + 1)) ||
+      (s = dalloc(c, &c->sw.n_mov, 1)) || (s = dalloc(c, &c->sw.perm, cap)) ||
+      (s = dalloc(c, &c->sw.samp, 2048)) || (s = dalloc(c, &c->sw.ins, cap)) ||
+      (s = dalloc(c, &c->sw.bound, cap / 1024 + 2)) ||
       (s = dalloc(c, &c->cw.choice, cap)) || (s = dalloc(c, &c->cw.target, cap)) ||
       (s = dalloc(c, &c->cw.claim, cap)) || (s = dalloc(c, &c->cw.ccount, cap)) ||
       (s = dalloc(c, &c->cw.cbase, cap)) || (s = dalloc(c, &c->cw.scan_len, 4)) ||

@@ -83,6 +83,7 @@ struct Schedule {
 constexpr int kSortBlock = 256;
 constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortBlock * kSortItems;  // 4096 keys per tile
+constexpr int kMoverItems = 4;                      // movers: 1024 keys per tile
 constexpr int kRadixMaxBits = 10;                  // digit width of a pass
 constexpr int kRadix = 1 << kRadixMaxBits;
 constexpr int kScanChunk = 2048;                    // elements per scan block
@@ -90,18 +91,30 @@ constexpr int kScanMaxBlocks = 65536;
 
 struct SortWork {
   uint32_t *k0, *k1, *v0, *v1;  // key/value ping-pong [cap]
-  uint32_t* hist;               // [kRadix * tiles_cap]
+  uint32_t* hist;               // [kRadix * tiles of 256 kMoverItems keys in cap]
   uint32_t* bsum;               // [kScanMaxBlocks]
   uint32_t* scan_len;           // device scalar
+  uint32_t* skey;               // [cap] keys in the last sorted order
+  uint32_t* mpre;               // [cap + 1] movers before each position
+  uint32_t* n_mov;              // device scalar: movers of this sort
+  uint32_t* perm;               // [cap] source of every sorted position
+  uint32_t* ins;                // [cap] stayers before each sorted mover
+  uint32_t* samp;               // [2048] every stride-th entry of ins
+  uint32_t* bound;              // [cap / 1024 + 2] movers before each chunk of old positions
   int64_t cap;
 };
 
-// Stable LSD radix sort of the st->n_total keys of src; the last pass moves
-// the records into dst (every key, the sentinel ones included, lands in
-// dst.key).  part = 0: every pass but the last; part = 1: the last pass.
+// Stable sort of the st->n_total particles of src by key (ties in index
+// order), then the records moved into dst in that order (every key, the
+// sentinel ones included, lands in dst.key).  The first st->n_alive
+// positions hold the previous sort's order with updated keys: the particles
+// whose key did not change stay in order and are merged with the others
+// (radix-sorted) by (key, index), using the previous order's offsets off.
+// part = 0: the order; part = 1: the record moves.
 template <typename T>
 void sort_particles(const PartsT<T>& src, const PartsT<T>& dst, int key_bits, SortWork& w,
-                    DevState* st, uint32_t sentinel, int part, hipStream_t s);
+                    DevState* st, const uint32_t* off, uint32_t sentinel, int part,
+                    hipStream_t s);
 // Exclusive scan of *len u32 values (device length), total to *total.  With
 // a guard state the total counts new particles: it is forced to 0 and the
 // error flagged when they would not fit in cap (or the ids would wrap).
