@@ -299,7 +299,7 @@ struct MoverPlace {
   uint32_t* skey;
   uint32_t* perm;
   uint32_t* ins;
-  uint32_t* samp;
+  uint32_t* samp;  // every stride-th ins
 };
 
 __device__ inline uint32_t stayers_before(const MoverPlace& mp, uint32_t n_prev, uint32_t k,
@@ -649,6 +649,7 @@ __device__ inline uint32_t movers_upto_sampled(const uint32_t* __restrict__ ins,
 constexpr int kPlaceChunk = 1024;
 constexpr int kPlaceLds = 2048;
 
+// The merge's searches, one thread per chunk boundary of old positions.
 __global__ void __launch_bounds__(256) k_place_bounds(const DevState* st,
                                                       const uint32_t* __restrict__ mpre,
                                                       const uint32_t* __restrict__ ins,
@@ -683,11 +684,21 @@ __global__ void __launch_bounds__(256) k_place(const uint32_t* __restrict__ key,
     if (in_lds)
       for (uint32_t j = c0 + t; j < c1; j += 256) lins[j - c0] = ins[j];
     __syncthreads();
-#pragma unroll 4
-    for (uint32_t i = base + t; i < end; i += 256) {
-      const uint32_t m = mpre[i];
-      if (mpre[i + 1] != m) continue;  // a mover
-      const uint32_t sr = i - m;
+    constexpr int U = kPlaceChunk / 256;
+    uint32_t m0[U], m1[U], kv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t i = base + u * 256 + t;
+      const uint32_t ic = (i < end) ? i : base;
+      m0[u] = mpre[ic];
+      m1[u] = mpre[ic + 1];
+      kv[u] = key[ic];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t i = base + u * 256 + t;
+      if (i >= end || m1[u] != m0[u]) continue;  // past the chunk, or a mover
+      const uint32_t sr = i - m0[u];
       uint32_t cnt;
       if (in_lds) {
         uint32_t lo = 0, hi = c1 - c0;
@@ -701,7 +712,7 @@ __global__ void __launch_bounds__(256) k_place(const uint32_t* __restrict__ key,
         cnt = movers_upto(ins, c0, c1, sr);
       }
       const uint32_t pos = sr + cnt;
-      skey[pos] = key[i];
+      skey[pos] = kv[u];
       perm[pos] = i;
     }
     __syncthreads();
