@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--config", default="paper")
     ap.add_argument("--n-init", type=int, default=None)
     ap.add_argument("--poisson", choices=("direct", "spectral", "mgpcg", "learned"),
-                    default="direct",
+                    default="spectral",
                     help="direct FP64 solve with every sum in a fixed order (bit-identical to "
                          "the oracle); the same direct solve on the FP64 matrix cores with "
                          "scan-based tridiagonal solves; FP32 multigrid CG with FP64 refinement; "
@@ -98,7 +98,7 @@ def run_ensemble(a):
 
     from paper_2109_00214_amd import pd as P
     from paper_2109_00214_amd import workload as W
-    from paper_2109_00214_amd.pd import PD_FP32_MIXED, Simulation
+    from paper_2109_00214_amd.pd import PD_FP32_MIXED, PD_POISSON_SPECTRAL, Simulation
     cfgs = W.ensemble_configs(a.ensemble)
     cands = (1, 2, 4, 8)
     tune_steps, eager_steps = 6, 10
@@ -111,7 +111,8 @@ def run_ensemble(a):
         parts = W.initial_population(cfg)
         off, inj = W.injection_schedule(cfg, nsteps)
         cap = int(1.25 * cfg.n_init + cfg.inj_cu * nsteps + 40 * cfg.inj_e + 65536)
-        sim = Simulation(cfg, cap, tables, species, precision=PD_FP32_MIXED)
+        sim = Simulation(cfg, cap, tables, species, precision=PD_FP32_MIXED,
+                         poisson=PD_POISSON_SPECTRAL)
         sim.inject(parts)
         sim.schedule_injection(off, inj)
         sims.append(sim)

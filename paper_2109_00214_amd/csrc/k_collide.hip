@@ -185,15 +185,19 @@ __global__ void __launch_bounds__(256) k_decide(PartsT<T> P, const uint32_t* off
   }
 }
 
+// Claims are resolved per chunk of 256 electrons (one per thread): a
+// winner keeps its channel and counts the electrons it creates (0, 1 or 2);
+// the chunk's total goes to bsum for the scan of the created slots.
 __global__ void __launch_bounds__(256) k_resolve(const uint32_t* off, DevState* st, Grid g,
                                                  uint8_t* choice, const uint32_t* target,
-                                                 const uint32_t* claim, uint32_t* ccount) {
+                                                 const uint32_t* claim, uint32_t* ccount,
+                                                 uint32_t* bsum) {
+  __shared__ uint32_t sh[4];
   const uint32_t n_e = off[g.C];
+  const uint32_t nb = (n_e + 255) / 256;
   const int lane = threadIdx.x & 63;
-  // grid-stride over whole waves so that every lane of a wave takes part in the ballots
-  const uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t e0 = blockIdx.x * blockDim.x; e0 < n_e; e0 += stride) {
-    const uint32_t e = e0 + threadIdx.x;
+  for (uint32_t b = blockIdx.x; b < nb; b += gridDim.x) {
+    const uint32_t e = b * 256 + threadIdx.x;
     int ch = -1;
     bool lost = false;
     uint32_t cnt = 0;
@@ -217,78 +221,92 @@ __global__ void __launch_bounds__(256) k_resolve(const uint32_t* off, DevState* 
       const uint64_t m = __ballot(ch == k);
       if (lane == 0 && m) atomicAdd(&st->events[k], (unsigned long long)__popcll(m));
     }
+    uint32_t tot;
+    block_scan256(cnt, &tot, sh);
+    if (threadIdx.x == 0) bsum[b] = tot;
   }
 }
 
+// The winners' outcomes; the created slots of a chunk start at its scanned
+// block sum, in electron order inside the block.
 template <typename T>
 __global__ void __launch_bounds__(256) k_apply(PartsT<T> P, const uint32_t* off, DevState* st, Grid g,
                                                CollideParams cp, const uint8_t* choice,
-                                               const uint32_t* target, const uint32_t* cbase,
-                                               uint32_t* claim, uint32_t cap) {
+                                               const uint32_t* target, const uint32_t* ccount,
+                                               const uint32_t* bsum, uint32_t* claim) {
+  __shared__ uint32_t sh[4];
   const uint32_t n_e = off[g.C];
+  const uint32_t nb = (n_e + 255) / 256;
   const uint32_t n_alive = st->n_alive;
   const uint32_t next_id = st->next_id;
   const uint32_t step = st->step;
   if (st->err) return;  // the guard found no room for the new electrons
-  for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < n_e; e += gridDim.x * blockDim.x) {
-    const uint32_t c = choice[e];
-    if (!c) continue;
-    const int ch = (int)c - 1;
-    const uint32_t tp = target[e];
-    const uint32_t id = P.id[e];
-    double e1[3] = {P.vr[e], P.vt[e], P.vz[e]};
-    double A[3] = {P.vr[tp], P.vt[tp], P.vz[tp]};
-    double nh[3];
-    claim[tp] = 0xFFFFFFFFu;
-    // stage 1: elastic, or inelastic losing the channel threshold (Eq. 12)
-    isotropic(cp, id, step, 2u, nh);
-    binary(e1, A, cp.two_dE_mr[ch], cp.f1[ch], cp.f2[ch], nh);
-    P.vr[tp] = (T)A[0];
-    P.vt[tp] = (T)A[1];
-    P.vz[tp] = (T)A[2];
-    if (ch == 0) {
+  for (uint32_t b = blockIdx.x; b < nb; b += gridDim.x) {
+    const uint32_t e = b * 256 + threadIdx.x;
+    const uint32_t cnt = (e < n_e) ? ccount[e] : 0u;
+    uint32_t tot;
+    const uint32_t cbase = bsum[b] + block_scan256(cnt, &tot, sh);
+    {
+      if (e >= n_e) continue;
+      const uint32_t c = choice[e];
+      if (!c) continue;
+      const int ch = (int)c - 1;
+      const uint32_t tp = target[e];
+      const uint32_t id = P.id[e];
+      double e1[3] = {P.vr[e], P.vt[e], P.vz[e]};
+      double A[3] = {P.vr[tp], P.vt[tp], P.vz[tp]};
+      double nh[3];
+      claim[tp] = 0xFFFFFFFFu;
+      // stage 1: elastic, or inelastic losing the channel threshold (Eq. 12)
+      isotropic(cp, id, step, 2u, nh);
+      binary(e1, A, cp.two_dE_mr[ch], cp.f1[ch], cp.f2[ch], nh);
+      P.vr[tp] = (T)A[0];
+      P.vt[tp] = (T)A[1];
+      P.vz[tp] = (T)A[2];
+      if (ch == 0) {
+        P.vr[e] = (T)e1[0];
+        P.vt[e] = (T)e1[1];
+        P.vz[e] = (T)e1[2];
+        continue;
+      }
+      // stage 2 (Eq. 13): the target keeps its slot and id, changes label;
+      // the new electron e2 takes the target's position and velocity
+      P.sp[tp] = (uint8_t)(ch == 1 ? 2 : (ch == 2 ? 4 : 3));
+      double e2[3] = {A[0], A[1], A[2]};
+      // stage 3 (Eq. 14): e1-e2 elastic, equal masses
+      isotropic(cp, id, step, 3u, nh);
+      binary(e1, e2, 0.0, 0.5, 0.5, nh);
+      const uint32_t slot = n_alive + cbase;
+      const uint32_t nid = next_id + cbase;
+      P.r[slot] = P.r[tp];
+      P.z[slot] = P.z[tp];
+      P.vr[slot] = (T)e2[0];
+      P.vt[slot] = (T)e2[1];
+      P.vz[slot] = (T)e2[2];
+      P.sp[slot] = 0;
+      P.id[slot] = nid;
+      if (ch == 2) {
+        // stage 4 (Eq. 15): e3 splits into the two orthogonal edges of the
+        // rectangle whose diagonal is v3
+        isotropic(cp, id, step, 4u, nh);
+        const double d = ((e1[0] * nh[0]) + (e1[1] * nh[1])) + (e1[2] * nh[2]);
+        const double v5[3] = {d * nh[0], d * nh[1], d * nh[2]};
+        const uint32_t s6 = slot + 1;
+        P.r[s6] = P.r[e];
+        P.z[s6] = P.z[e];
+        P.vr[s6] = (T)(e1[0] - v5[0]);
+        P.vt[s6] = (T)(e1[1] - v5[1]);
+        P.vz[s6] = (T)(e1[2] - v5[2]);
+        P.sp[s6] = 0;
+        P.id[s6] = nid + 1;
+        e1[0] = v5[0];
+        e1[1] = v5[1];
+        e1[2] = v5[2];
+      }
       P.vr[e] = (T)e1[0];
       P.vt[e] = (T)e1[1];
       P.vz[e] = (T)e1[2];
-      continue;
     }
-    // stage 2 (Eq. 13): the target keeps its slot and id, changes label;
-    // the new electron e2 takes the target's position and velocity
-    P.sp[tp] = (uint8_t)(ch == 1 ? 2 : (ch == 2 ? 4 : 3));
-    double e2[3] = {A[0], A[1], A[2]};
-    // stage 3 (Eq. 14): e1-e2 elastic, equal masses
-    isotropic(cp, id, step, 3u, nh);
-    binary(e1, e2, 0.0, 0.5, 0.5, nh);
-    const uint32_t slot = n_alive + cbase[e];
-    const uint32_t nid = next_id + cbase[e];
-    P.r[slot] = P.r[tp];
-    P.z[slot] = P.z[tp];
-    P.vr[slot] = (T)e2[0];
-    P.vt[slot] = (T)e2[1];
-    P.vz[slot] = (T)e2[2];
-    P.sp[slot] = 0;
-    P.id[slot] = nid;
-    if (ch == 2) {
-      // stage 4 (Eq. 15): e3 splits into the two orthogonal edges of the
-      // rectangle whose diagonal is v3
-      isotropic(cp, id, step, 4u, nh);
-      const double d = ((e1[0] * nh[0]) + (e1[1] * nh[1])) + (e1[2] * nh[2]);
-      const double v5[3] = {d * nh[0], d * nh[1], d * nh[2]};
-      const uint32_t s6 = slot + 1;
-      P.r[s6] = P.r[e];
-      P.z[s6] = P.z[e];
-      P.vr[s6] = (T)(e1[0] - v5[0]);
-      P.vt[s6] = (T)(e1[1] - v5[1]);
-      P.vz[s6] = (T)(e1[2] - v5[2]);
-      P.sp[s6] = 0;
-      P.id[s6] = nid + 1;
-      e1[0] = v5[0];
-      e1[1] = v5[1];
-      e1[2] = v5[2];
-    }
-    P.vr[e] = (T)e1[0];
-    P.vt[e] = (T)e1[1];
-    P.vz[e] = (T)e1[2];
   }
 }
 
@@ -296,14 +314,15 @@ template <typename T>
 void collide(const PartsT<T>& P, const uint32_t* off, DevState* st, const Grid& g,
              const CollideParams& cp, CollideWork& w, uint32_t* bsum, int64_t cap, hipStream_t s) {
   const int gr = grid_for(cap);
+  int nb = (int)((cap + 255) / 256);
+  if (nb > 8192) nb = 8192;
   k_decide<T><<<gr, 256, 0, s>>>(P, off, st, g, cp, w.choice, w.target, w.claim, w.scan_len);
-  k_resolve<<<gr, 256, 0, s>>>(off, st, g, w.choice, w.target, w.claim, w.ccount);
-  // created-electron slots; the scan's guard flags an overflow and then
-  // creates nothing, so every later launch touches only [0, n_alive)
-  scan_exclusive(w.ccount, w.cbase, w.scan_len, &st->n_created, bsum, cap, s, st,
-                 (uint32_t)cap);
-  k_apply<T><<<gr, 256, 0, s>>>(P, off, st, g, cp, w.choice, w.target, w.cbase, w.claim,
-                                (uint32_t)cap);
+  k_resolve<<<nb, 256, 0, s>>>(off, st, g, w.choice, w.target, w.claim, w.ccount, bsum);
+  // created-electron slots: the scan of the chunk sums; its guard flags an
+  // overflow and then creates nothing, so every later launch touches only
+  // [0, n_alive)
+  scan_block_sums(bsum, w.scan_len, &st->n_created, st, (uint32_t)cap, 256, s);
+  k_apply<T><<<nb, 256, 0, s>>>(P, off, st, g, cp, w.choice, w.target, w.ccount, bsum, w.claim);
 }
 template void collide<double>(const Parts&, const uint32_t*, DevState*, const Grid&,
                               const CollideParams&, CollideWork&, uint32_t*, int64_t, hipStream_t);

@@ -43,32 +43,8 @@ static inline int grid_for(int64_t n, int block = 256) {
   return (int)g;
 }
 
-// exclusive scan of one value per thread over a 256-thread block
-__device__ inline uint32_t block_scan256(uint32_t v, uint32_t* total, uint32_t* sh) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  uint32_t x = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
-  }
-  if (lane == 63) sh[wid] = x;
-  __syncthreads();
-  uint32_t wbase = 0, tot = 0;
-#pragma unroll
-  for (int w = 0; w < 4; ++w) {
-    const uint32_t t = sh[w];
-    wbase += (w < wid) ? t : 0u;
-    tot += t;
-  }
-  __syncthreads();
-  *total = tot;
-  return wbase + x - v;
-}
-
 // ---------------------------------------------------------------------------
 // exclusive scan of *len_p u32 values; chunks of kScanChunk = 256 x 8
-constexpr int kScanPer = kScanChunk / 256;
 
 __global__ void __launch_bounds__(256) k_scan_reduce(const uint32_t* __restrict__ in,
                                                      const uint32_t* len_p,
@@ -96,10 +72,10 @@ __global__ void __launch_bounds__(256) k_scan_reduce(const uint32_t* __restrict_
 // launch of the step touches only the live particles.
 __global__ void __launch_bounds__(1024) k_scan_bsums(uint32_t* bsum, const uint32_t* len_p,
                                                      uint32_t* total, DevState* guard,
-                                                     uint32_t cap) {
+                                                     uint32_t cap, uint32_t chunk) {
   __shared__ uint32_t sh[16];
   const uint32_t len = *len_p;
-  const uint32_t nb = (len + kScanChunk - 1) / kScanChunk;
+  const uint32_t nb = (len + chunk - 1) / chunk;
   const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
   const uint32_t per = (nb + 1023) / 1024;
   const uint32_t b0 = t * per;
@@ -161,13 +137,18 @@ __global__ void __launch_bounds__(256) k_scan_down(const uint32_t* in, uint32_t*
   }
 }
 
+void scan_block_sums(uint32_t* bsum, const uint32_t* len, uint32_t* total, DevState* guard,
+                     uint32_t cap, uint32_t chunk, hipStream_t s) {
+  k_scan_bsums<<<1, 1024, 0, s>>>(bsum, len, total, guard, cap, chunk);
+}
+
 void scan_exclusive(const uint32_t* in, uint32_t* out, const uint32_t* len, uint32_t* total,
                     uint32_t* bsum, int64_t max_len, hipStream_t s, DevState* guard,
                     uint32_t cap) {
   int nb = (int)((max_len + kScanChunk - 1) / kScanChunk);
   if (nb < 1) nb = 1;
   k_scan_reduce<<<nb, 256, 0, s>>>(in, len, bsum);
-  k_scan_bsums<<<1, 1024, 0, s>>>(bsum, len, total, guard, cap);
+  k_scan_bsums<<<1, 1024, 0, s>>>(bsum, len, total, guard, cap, kScanChunk);
   k_scan_down<<<nb, 256, 0, s>>>(in, out, len, bsum);
 }
 
@@ -732,7 +713,7 @@ void sort_particles(const PartsT<T>& src, const PartsT<T>& dst, int key_bits, So
   if (part == 0) {
     // classify, count and compact the movers (key, index) into k0/v0
     k_cls_count<<<nb, 256, 0, s>>>(src.key, w.skey, st, w.bsum, w.scan_len);
-    k_scan_bsums<<<1, 1024, 0, s>>>(w.bsum, w.scan_len, w.n_mov, nullptr, 0);
+    k_scan_bsums<<<1, 1024, 0, s>>>(w.bsum, w.scan_len, w.n_mov, nullptr, 0, kScanChunk);
     k_cls_compact<<<nb, 256, 0, s>>>(src.key, w.skey, st, w.bsum, w.mpre, w.k0, w.v0);
     // stable radix sort of the movers
     const uint32_t* kin = w.k0;

@@ -637,7 +637,7 @@ pd_status pd_create(const pd_domain* dom, const pd_opts* opts, pd_ctx** out) {
       (s = dalloc(c, &c->sw.k0, cap)) || (s = dalloc(c, &c->sw.k1, cap)) ||
       (s = dalloc(c, &c->sw.v0, cap)) || (s = dalloc(c, &c->sw.v1, cap)) ||
       (s = dalloc(c, &c->sw.hist, (size_t)kRadix * (tiles < 1 ? 1 : tiles))) ||
-      (s = dalloc(c, &c->sw.bsum, kScanMaxBlocks)) || (s = dalloc(c, &c->sw.scan_len, 4)) ||
+      (s = dalloc(c, &c->sw.bsum, std::max<int64_t>(kScanMaxBlocks, cap / 256 + 1))) || (s = dalloc(c, &c->sw.scan_len, 4)) ||
       (s = dalloc(c, &c->sw.skey, cap)) || (s = dalloc(c, &c->sw.mpre, cap + 1)) ||
       (s = dalloc(c, &c->sw.n_mov, 1)) || (s = dalloc(c, &c->sw.perm, cap)) ||
       (s = dalloc(c, &c->sw.samp, 2048)) || (s = dalloc(c, &c->sw.ins, cap)) ||

@@ -121,6 +121,36 @@ void sort_particles(const PartsT<T>& src, const PartsT<T>& dst, int key_bits, So
 void scan_exclusive(const uint32_t* in, uint32_t* out, const uint32_t* len,
                     uint32_t* total, uint32_t* bsum, int64_t max_len, hipStream_t s,
                     DevState* guard, uint32_t cap);
+// the middle launch of that scan alone: exclusive scan, in place, of the
+// per-chunk sums of ceil(*len / chunk) chunks (same guard and total)
+void scan_block_sums(uint32_t* bsum, const uint32_t* len, uint32_t* total, DevState* guard,
+                     uint32_t cap, uint32_t chunk, hipStream_t s);
+
+constexpr int kScanPer = kScanChunk / 256;  // consecutive elements per thread
+
+// exclusive scan of one value per thread over a 256-thread block (total of
+// the block to *total); sh: 4 words of LDS
+__device__ inline uint32_t block_scan256(uint32_t v, uint32_t* total, uint32_t* sh) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) sh[wid] = x;
+  __syncthreads();
+  uint32_t wbase = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    const uint32_t t = sh[w];
+    wbase += (w < wid) ? t : 0u;
+    tot += t;
+  }
+  __syncthreads();
+  *total = tot;
+  return wbase + x - v;
+}
 // CSR offsets of the sorted keys; the same launch clears the node charge Q.
 void build_offsets(const uint32_t* skeys, DevState* st, uint32_t* off, uint32_t nkeys,
                    int64_t* Q, uint32_t nnodes, hipStream_t s);
