@@ -27,9 +27,10 @@ HBM_PEAK_GBS = 8000.0
 # record: r, z, vr, vt, vz = 5F, species 1 B, id 4 B, key 4 B)
 def algo_bytes(F):
     return {
-        "push": (5 * F + 1) + 5 * F + 4,              # read state + species, write state + key
-        "permute": 4 + 4 + (5 * F + 5) + (5 * F + 9),  # read key + perm + record, write record + key
-        "deposit": 2 * F + 1,                          # read r, z, species
+        # read perm + record (state, species, id) at its old place, write the
+        # record and its new key at the sorted place
+        "push": (4 + 5 * F + 5) + (5 * F + 5 + 4),
+        "deposit": 4 + 1 + 2 * F,                      # read perm, species, r, z
     }
 
 
@@ -54,6 +55,10 @@ def parse():
     ap.add_argument("--ensemble", type=int, default=0,
                     help="run the batched ensemble of this many uneven replicas (FP32 records, "
                          "one HIP graph per two steps) instead of the single workload")
+    ap.add_argument("--stage-steps", type=int, default=100,
+                    help="steps after the timed ones run with per-stage HIP events for the stage "
+                         "breakdown and the roofline (the events cost device time, so the timed "
+                         "steps run without them)")
     ap.add_argument("--cpu-steps", type=int, default=40,
                     help="oracle steps timed for the CPU baseline (0: skip)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles",
@@ -200,7 +205,7 @@ def main():
 
     kw = {} if a.n_init is None else {"n_init": a.n_init}
     cfg = W.config(a.config, **kw)
-    nsteps = a.warmup + a.steps
+    nsteps = a.warmup + a.steps + a.stage_steps
     t0 = time.time()
     parts = W.initial_population(cfg)
     off, inj = W.injection_schedule(cfg, nsteps)
@@ -240,10 +245,10 @@ def main():
         P.pd_set_unet(sim.h, net)
     sim.inject(parts)
     sim.schedule_injection(off, inj)
+    sim.set_timing(False)
     sim.step(a.warmup)
     sim.synchronize()
     d0 = sim.diag()
-    sim.timing(reset=True)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -254,16 +259,24 @@ def main():
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
     d1 = sim.diag()
-    stages, tsteps = sim.timing()
     pst = d1["particle_steps"] - d0["particle_steps"]
     value = pst / (ms / 1e3)
+    # stage breakdown: the following steps, each stage bracketed by HIP
+    # events on the library's stream
+    sim.set_timing(True)
+    sim.timing(reset=True)
+    sim.step(max(a.stage_steps, 1))
+    sim.synchronize()
+    d2 = sim.diag()
+    stages, tsteps = sim.timing()
+    pst_stage = d2["particle_steps"] - d1["particle_steps"]
     per_step = {k: v / max(tsteps, 1) for k, v in stages.items()}
     print("stage ms/step: " + ", ".join("%s %.4f" % kv for kv in per_step.items()), file=sys.stderr)
     # roofline of the dominant single-kernel stage
     ALGO_BYTES = algo_bytes(4 if a.precision == "fp32" else 8)
     cand = {k: per_step[k] for k in ALGO_BYTES}
     dom = max(cand, key=cand.get)
-    units = pst / a.steps
+    units = pst_stage / max(tsteps, 1)
     achieved = ALGO_BYTES[dom] * units / (per_step[dom] / 1e3) / 1e9
     # HBM bytes per launch: bytes per particle from the counters (taken on
     # this workload and on the kernel as it is now) times particles per launch

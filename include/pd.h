@@ -283,8 +283,16 @@ void pd_unet_destroy(pd_unet* net);
 
 /* Accumulated device time per stage (ms, PD_NTIMERS entries) and the
  * number of steps timed, since creation or the last reset (requires
- * opts.timing).  reset != 0 clears the accumulators after reading.    */
+ * opts.timing, or pd_set_timing, for some steps).  reset != 0 clears the
+ * accumulators after reading.                                          */
 pd_status pd_get_timing(pd_ctx* ctx, double* ms, int64_t* steps, int reset);
+
+/* Switch the per-stage timing on (on != 0) or off for the steps that
+ * follow, as opts.timing does at creation; what was accumulated is kept.
+ * The stage events cost device time (tens of microseconds per step), so a
+ * throughput measurement runs with the timing off.  PD_ESTATE for a
+ * member of an ensemble.                                               */
+pd_status pd_set_timing(pd_ctx* ctx, int on);
 
 /* Message of the last failed call on this context (never NULL).      */
 const char* pd_last_error(const pd_ctx* ctx);

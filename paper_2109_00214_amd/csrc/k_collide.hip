@@ -111,21 +111,25 @@ __device__ inline void binary(double v1[3], double v2[3], double two_dE_mr, doub
 }
 
 // (T: precision of the particle record; the collision arithmetic is FP64)
+// (indices e, tc, t1 are sorted positions; the records are read in U
+// through perm)
 template <typename T>
-__global__ void __launch_bounds__(256) k_decide(PartsT<T> P, const uint32_t* off, const DevState* st,
+__global__ void __launch_bounds__(256) k_decide(Flow<T> f, const uint32_t* off, const DevState* st,
                                                 Grid g, CollideParams cp, uint8_t* choice,
                                                 uint32_t* target, uint32_t* claim,
                                                 uint32_t* scan_len) {
+  const PartsT<T>& P = f.U;
   const uint32_t C = g.C;
   const uint32_t n_e = off[C];
   const uint32_t step = st->step;
   if (blockIdx.x == 0 && threadIdx.x == 0) *scan_len = n_e;
   for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < n_e; e += gridDim.x * blockDim.x) {
-    const uint32_t cell = P.key[e];
+    const uint32_t cell = f.skey[e];
+    const uint32_t pe = f.perm[e];
     const int ci = (int)(cell % (uint32_t)g.nr);
     const uint32_t b_cu = off[C + cell], n_cu = off[C + cell + 1] - b_cu;
     const uint32_t b_c1 = off[2 * C + cell], n_c1 = off[2 * C + cell + 1] - b_c1;
-    const uint32_t id = P.id[e];
+    const uint32_t id = P.id[pe];
     uint32_t w[4], t[4];
     philox(id, 0u, step, 0u, cp.seed_lo, cp.seed_hi, w);
     philox(id, 0u, step, 1u << 24, cp.seed_lo, cp.seed_hi, t);
@@ -133,13 +137,14 @@ __global__ void __launch_bounds__(256) k_decide(PartsT<T> P, const uint32_t* off
     const double R2 = u53(w[2], w[3]);
     const uint32_t tc = b_cu + __umulhi(t[0], n_cu);
     const uint32_t t1 = b_c1 + __umulhi(t[1], n_c1);
-    const double evr = P.vr[e], evt = P.vt[e], evz = P.vz[e];
+    const double evr = P.vr[pe], evt = P.vt[pe], evz = P.vz[pe];
     double x[kNC] = {0.0, 0.0, 0.0, 0.0};
     const double Vc = cp.Vcell[ci];
     // Cu target: EL, SI, DI share the pick and the relative speed
     if (n_cu > 0) {
-      const double dvr = evr - (double)P.vr[tc], dvt = evt - (double)P.vt[tc],
-                   dvz = evz - (double)P.vz[tc];
+      const uint32_t q = f.perm[tc];
+      const double dvr = evr - (double)P.vr[q], dvt = evt - (double)P.vt[q],
+                   dvz = evz - (double)P.vz[q];
       const double gg = sqrt(((dvr * dvr) + (dvt * dvt)) + (dvz * dvz));
       const double dens = ((double)n_cu * cp.W) / Vc;
 #pragma unroll
@@ -149,8 +154,9 @@ __global__ void __launch_bounds__(256) k_decide(PartsT<T> P, const uint32_t* off
       }
     }
     if (n_c1 > 0) {
-      const double dvr = evr - (double)P.vr[t1], dvt = evt - (double)P.vt[t1],
-                   dvz = evz - (double)P.vz[t1];
+      const uint32_t q = f.perm[t1];
+      const double dvr = evr - (double)P.vr[q], dvt = evt - (double)P.vt[q],
+                   dvz = evz - (double)P.vz[q];
       const double gg = sqrt(((dvr * dvr) + (dvt * dvt)) + (dvz * dvz));
       const double dens = ((double)n_c1 * cp.W) / Vc;
       x[3] = ((cp.dt * gg) * dens) * sigma_of(cp, 3, gg);
@@ -230,11 +236,13 @@ __global__ void __launch_bounds__(256) k_resolve(const uint32_t* off, DevState* 
 // The winners' outcomes; the created slots of a chunk start at its scanned
 // block sum, in electron order inside the block.
 template <typename T>
-__global__ void __launch_bounds__(256) k_apply(PartsT<T> P, const uint32_t* off, DevState* st, Grid g,
+__global__ void __launch_bounds__(256) k_apply(Flow<T> f, const uint32_t* off, DevState* st, Grid g,
                                                CollideParams cp, const uint8_t* choice,
                                                const uint32_t* target, const uint32_t* ccount,
                                                const uint32_t* bsum, uint32_t* claim) {
   __shared__ uint32_t sh[4];
+  const PartsT<T>& P = f.U;
+  const PartsT<T>& S = f.S;
   const uint32_t n_e = off[g.C];
   const uint32_t nb = (n_e + 255) / 256;
   const uint32_t n_alive = st->n_alive;
@@ -252,39 +260,40 @@ __global__ void __launch_bounds__(256) k_apply(PartsT<T> P, const uint32_t* off,
       if (!c) continue;
       const int ch = (int)c - 1;
       const uint32_t tp = target[e];
-      const uint32_t id = P.id[e];
-      double e1[3] = {P.vr[e], P.vt[e], P.vz[e]};
-      double A[3] = {P.vr[tp], P.vt[tp], P.vz[tp]};
+      const uint32_t pe = f.perm[e], pt = f.perm[tp];
+      const uint32_t id = P.id[pe];
+      double e1[3] = {P.vr[pe], P.vt[pe], P.vz[pe]};
+      double A[3] = {P.vr[pt], P.vt[pt], P.vz[pt]};
       double nh[3];
       claim[tp] = 0xFFFFFFFFu;
       // stage 1: elastic, or inelastic losing the channel threshold (Eq. 12)
       isotropic(cp, id, step, 2u, nh);
       binary(e1, A, cp.two_dE_mr[ch], cp.f1[ch], cp.f2[ch], nh);
-      P.vr[tp] = (T)A[0];
-      P.vt[tp] = (T)A[1];
-      P.vz[tp] = (T)A[2];
+      P.vr[pt] = (T)A[0];
+      P.vt[pt] = (T)A[1];
+      P.vz[pt] = (T)A[2];
       if (ch == 0) {
-        P.vr[e] = (T)e1[0];
-        P.vt[e] = (T)e1[1];
-        P.vz[e] = (T)e1[2];
+        P.vr[pe] = (T)e1[0];
+        P.vt[pe] = (T)e1[1];
+        P.vz[pe] = (T)e1[2];
         continue;
       }
       // stage 2 (Eq. 13): the target keeps its slot and id, changes label;
       // the new electron e2 takes the target's position and velocity
-      P.sp[tp] = (uint8_t)(ch == 1 ? 2 : (ch == 2 ? 4 : 3));
+      P.sp[pt] = (uint8_t)(ch == 1 ? 2 : (ch == 2 ? 4 : 3));
       double e2[3] = {A[0], A[1], A[2]};
       // stage 3 (Eq. 14): e1-e2 elastic, equal masses
       isotropic(cp, id, step, 3u, nh);
       binary(e1, e2, 0.0, 0.5, 0.5, nh);
       const uint32_t slot = n_alive + cbase;
       const uint32_t nid = next_id + cbase;
-      P.r[slot] = P.r[tp];
-      P.z[slot] = P.z[tp];
-      P.vr[slot] = (T)e2[0];
-      P.vt[slot] = (T)e2[1];
-      P.vz[slot] = (T)e2[2];
-      P.sp[slot] = 0;
-      P.id[slot] = nid;
+      S.r[slot] = P.r[pt];
+      S.z[slot] = P.z[pt];
+      S.vr[slot] = (T)e2[0];
+      S.vt[slot] = (T)e2[1];
+      S.vz[slot] = (T)e2[2];
+      S.sp[slot] = 0;
+      S.id[slot] = nid;
       if (ch == 2) {
         // stage 4 (Eq. 15): e3 splits into the two orthogonal edges of the
         // rectangle whose diagonal is v3
@@ -292,26 +301,26 @@ __global__ void __launch_bounds__(256) k_apply(PartsT<T> P, const uint32_t* off,
         const double d = ((e1[0] * nh[0]) + (e1[1] * nh[1])) + (e1[2] * nh[2]);
         const double v5[3] = {d * nh[0], d * nh[1], d * nh[2]};
         const uint32_t s6 = slot + 1;
-        P.r[s6] = P.r[e];
-        P.z[s6] = P.z[e];
-        P.vr[s6] = (T)(e1[0] - v5[0]);
-        P.vt[s6] = (T)(e1[1] - v5[1]);
-        P.vz[s6] = (T)(e1[2] - v5[2]);
-        P.sp[s6] = 0;
-        P.id[s6] = nid + 1;
+        S.r[s6] = P.r[pe];
+        S.z[s6] = P.z[pe];
+        S.vr[s6] = (T)(e1[0] - v5[0]);
+        S.vt[s6] = (T)(e1[1] - v5[1]);
+        S.vz[s6] = (T)(e1[2] - v5[2]);
+        S.sp[s6] = 0;
+        S.id[s6] = nid + 1;
         e1[0] = v5[0];
         e1[1] = v5[1];
         e1[2] = v5[2];
       }
-      P.vr[e] = (T)e1[0];
-      P.vt[e] = (T)e1[1];
-      P.vz[e] = (T)e1[2];
+      P.vr[pe] = (T)e1[0];
+      P.vt[pe] = (T)e1[1];
+      P.vz[pe] = (T)e1[2];
     }
   }
 }
 
 template <typename T>
-void collide(const PartsT<T>& P, const uint32_t* off, DevState* st, const Grid& g,
+void collide(const Flow<T>& P, const uint32_t* off, DevState* st, const Grid& g,
              const CollideParams& cp, CollideWork& w, uint32_t* bsum, int64_t cap, hipStream_t s) {
   const int gr = grid_for(cap);
   int nb = (int)((cap + 255) / 256);
@@ -324,9 +333,9 @@ void collide(const PartsT<T>& P, const uint32_t* off, DevState* st, const Grid& 
   scan_block_sums(bsum, w.scan_len, &st->n_created, st, (uint32_t)cap, 256, s);
   k_apply<T><<<nb, 256, 0, s>>>(P, off, st, g, cp, w.choice, w.target, w.ccount, bsum, w.claim);
 }
-template void collide<double>(const Parts&, const uint32_t*, DevState*, const Grid&,
+template void collide<double>(const Flow<double>&, const uint32_t*, DevState*, const Grid&,
                               const CollideParams&, CollideWork&, uint32_t*, int64_t, hipStream_t);
-template void collide<float>(const PartsF&, const uint32_t*, DevState*, const Grid&,
+template void collide<float>(const Flow<float>&, const uint32_t*, DevState*, const Grid&,
                              const CollideParams&, CollideWork&, uint32_t*, int64_t, hipStream_t);
 
 }  // namespace pd

@@ -40,23 +40,29 @@ __device__ inline void cell_of(const Grid& g, T r, T z, int& i, int& j, T& fr, T
 // collisions ionize targets inside it in place.)  In the FP32 form the
 // fractions come from the FP32 positions; the rounding to 2^-20 is the
 // same, so the node charges stay exact integers.
+// (sorted position p: the record is U[perm[p]] for the live particles, S[p]
+// for the electrons created this step)
 template <typename T>
-__global__ void __launch_bounds__(256) k_deposit(PartsT<T> P, const DevState* st, Grid g,
+__global__ void __launch_bounds__(256) k_deposit(Flow<T> f, const DevState* st, Grid g,
                                                  SpeciesParams spp, unsigned long long* Q) {
-  const uint32_t n = st->n_alive + st->n_created;
+  const uint32_t n_alive = st->n_alive;
+  const uint32_t n = n_alive + st->n_created;
   const int W = g.nr + 1;
   const int lane = threadIdx.x & 63;
   const uint64_t upto = (lane == 63) ? 0ull : (~0ull << (lane + 1));  // lanes above this one
   for (uint32_t q0 = blockIdx.x * blockDim.x; q0 < n; q0 += gridDim.x * blockDim.x) {
     const uint32_t p = q0 + threadIdx.x;
-    const long long Zp = (p < n) ? spp.Z[P.sp[p]] : 0;
+    const bool old = p < n_alive;
+    const uint32_t q = old ? f.perm[p] : p;
+    const PartsT<T>& P = old ? f.U : f.S;
+    const long long Zp = (p < n) ? spp.Z[P.sp[q]] : 0;
     if (!__ballot(Zp != 0)) continue;
     int b = -1;
     long long v0 = 0, v1 = 0, v2 = 0, v3 = 0;
     if (Zp != 0) {
       int i, j;
       T fr, fz;
-      cell_of<T>(g, P.r[p], P.z[p], i, j, fr, fz);
+      cell_of<T>(g, P.r[q], P.z[q], i, j, fr, fz);
       const long long ar = (long long)floor((fr * (T)1048576) + (T)0.5), br = 1048576 - ar;
       const long long az = (long long)floor((fz * (T)1048576) + (T)0.5), bz = 1048576 - az;
       b = j * W + i;
@@ -107,14 +113,14 @@ void fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
 }
 
 template <typename T>
-void deposit(const PartsT<T>& P, const DevState* st, const uint32_t* off, const Grid& g,
-             const SpeciesParams& sp, int64_t* Q, int64_t cap, hipStream_t s) {
-  (void)off;  // Q was cleared by the offsets launch
-  k_deposit<T><<<grid_for(cap), 256, 0, s>>>(P, st, g, sp, (unsigned long long*)Q);
+void deposit(const Flow<T>& f, const DevState* st, const Grid& g, const SpeciesParams& sp,
+             int64_t* Q, int64_t cap, hipStream_t s) {
+  // Q was cleared by the offsets launch
+  k_deposit<T><<<grid_for(cap), 256, 0, s>>>(f, st, g, sp, (unsigned long long*)Q);
 }
-template void deposit<double>(const Parts&, const DevState*, const uint32_t*, const Grid&,
+template void deposit<double>(const Flow<double>&, const DevState*, const Grid&,
                               const SpeciesParams&, int64_t*, int64_t, hipStream_t);
-template void deposit<float>(const PartsF&, const DevState*, const uint32_t*, const Grid&,
+template void deposit<float>(const Flow<float>&, const DevState*, const Grid&,
                              const SpeciesParams&, int64_t*, int64_t, hipStream_t);
 
 // E = -grad(phi): central differences, second-order one-sided at the
@@ -165,31 +171,39 @@ __device__ inline void count_codes(int code, unsigned long long* ctr) {
 // gather (bilinear, the deposit's weights) and leapfrog push in the record's
 // precision T: v += (q/m) E dt, Cartesian move, rotation back to the r-z
 // plane; absorbed particles get the sentinel key, the others their new key
+// The record of sorted position p comes from U[perm[p]] (live particles) or
+// S[p] (created this step) and goes to S[p], the id and label with it.
 template <typename T>
-__global__ void __launch_bounds__(256) k_push(PartsT<T> P, DevState* st, Grid g, SpeciesParams spp,
+__global__ void __launch_bounds__(256) k_push(Flow<T> f, DevState* st, Grid g, SpeciesParams spp,
                                               const T* Er, const T* Ez) {
-  const uint32_t n = st->n_alive + st->n_created;
+  const uint32_t n_alive = st->n_alive;
+  const uint32_t n = n_alive + st->n_created;
   const int W = g.nr + 1;
   const T dt = (T)g.dt;
   const uint32_t stride = gridDim.x * blockDim.x;
+  const PartsT<T>& D = f.S;
   for (uint32_t p0 = blockIdx.x * blockDim.x; p0 < n; p0 += stride) {
     const uint32_t p = p0 + threadIdx.x;
     int code = -1;
     if (p < n) {
+      const bool old = p < n_alive;
+      const uint32_t q = old ? f.perm[p] : p;
+      const PartsT<T>& P = old ? f.U : f.S;
       int i, j;
       T fr, fz;
-      const T r = P.r[p], z0 = P.z[p];
+      const T r = P.r[q], z0 = P.z[q];
       cell_of<T>(g, r, z0, i, j, fr, fz);
       const int b = j * W + i;
       const T gr = (T)1 - fr, gz = (T)1 - fz;
       const T w00 = gr * gz, w10 = fr * gz, w01 = gr * fz, w11 = fr * fz;
       const T er = (((w00 * Er[b]) + (w10 * Er[b + 1])) + (w01 * Er[b + W])) + (w11 * Er[b + W + 1]);
       const T ez = (((w00 * Ez[b]) + (w10 * Ez[b + 1])) + (w01 * Ez[b + W])) + (w11 * Ez[b + W + 1]);
-      const int s = P.sp[p];
+      const int s = P.sp[q];
+      const uint32_t pid = P.id[q];
       const T qm = (T)spp.qmdt[s];
-      T vr = P.vr[p] + (qm * er);
-      T vz = P.vz[p] + (qm * ez);
-      T vt = P.vt[p];
+      T vr = P.vr[q] + (qm * er);
+      T vz = P.vz[q] + (qm * ez);
+      T vt = P.vt[q];
       const T x = r + (vr * dt);
       const T y = vt * dt;
       const T z = z0 + (vz * dt);
@@ -201,23 +215,25 @@ __global__ void __launch_bounds__(256) k_push(PartsT<T> P, DevState* st, Grid g,
         vr = vr2;
         vt = vt2;
       }
-      P.r[p] = rn;
-      P.z[p] = z;
-      P.vr[p] = vr;
-      P.vt[p] = vt;
-      P.vz[p] = vz;
+      D.r[p] = rn;
+      D.z[p] = z;
+      D.vr[p] = vr;
+      D.vt[p] = vt;
+      D.vz[p] = vz;
+      D.sp[p] = (uint8_t)s;
+      D.id[p] = pid;
       int bnd = -1;
       if (z < (T)0) bnd = 0;
       else if (!(z < (T)g.L)) bnd = 1;
       else if (!(rn < (T)g.R)) bnd = 2;
       if (bnd >= 0) {
         code = bnd * kNS + s;
-        P.key[p] = g.sentinel;
+        D.key[p] = g.sentinel;
       } else {
         int i2, j2;
         T a, c;
         cell_of<T>(g, rn, z, i2, j2, a, c);
-        P.key[p] = (uint32_t)s * g.C + (uint32_t)(j2 * g.nr + i2);
+        D.key[p] = (uint32_t)s * g.C + (uint32_t)(j2 * g.nr + i2);
       }
     }
     count_codes(code, st->absorbed);
@@ -225,14 +241,14 @@ __global__ void __launch_bounds__(256) k_push(PartsT<T> P, DevState* st, Grid g,
 }
 
 template <>
-void push<double>(const Parts& P, DevState* st, const Grid& g, const SpeciesParams& sp,
+void push<double>(const Flow<double>& f, DevState* st, const Grid& g, const SpeciesParams& sp,
                   const FieldWork& fw, int64_t cap, hipStream_t s) {
-  k_push<double><<<grid_for(cap), 256, 0, s>>>(P, st, g, sp, fw.Er, fw.Ez);
+  k_push<double><<<grid_for(cap), 256, 0, s>>>(f, st, g, sp, fw.Er, fw.Ez);
 }
 template <>
-void push<float>(const PartsF& P, DevState* st, const Grid& g, const SpeciesParams& sp,
+void push<float>(const Flow<float>& f, DevState* st, const Grid& g, const SpeciesParams& sp,
                  const FieldWork& fw, int64_t cap, hipStream_t s) {
-  k_push<float><<<grid_for(cap), 256, 0, s>>>(P, st, g, sp, fw.Erf, fw.Ezf);
+  k_push<float><<<grid_for(cap), 256, 0, s>>>(f, st, g, sp, fw.Erf, fw.Ezf);
 }
 
 // ---------------------------------------------------------------------------

@@ -29,9 +29,9 @@
 // movers); a mover's place is its rank among movers plus the stayers before
 // it, read off the previous order's per-key offsets and the count of movers
 // before each old position.  The result is the stable sort of all keys.
-// The particle records then move once, gathered by the source index with
-// contiguous stores.  No kernel waits on another block: every launch
-// finishes for any input.
+// The result is the permutation (sorted position -> index) and the sorted
+// keys; the push moves the records.  No kernel waits on another block:
+// every launch finishes for any input.
 #include "pd_internal.h"
 
 namespace pd {
@@ -424,62 +424,6 @@ __global__ void __launch_bounds__(256) k_radix_down(const uint32_t* __restrict__
   }
 }
 
-// payload permutation: dst[p] = src[perm[p]] for the live particles; every
-// sorted key (the sentinel ones included) goes to dst.key
-constexpr int kGatherPer = 4;
-template <typename T>
-__global__ void __launch_bounds__(256) k_gather(PartsT<T> src, PartsT<T> dst,
-                                                const uint32_t* __restrict__ skeys,
-                                                const uint32_t* __restrict__ perm,
-                                                const DevState* st, uint32_t sentinel) {
-  const uint32_t n = st->n_total;
-  const uint32_t stride = gridDim.x * blockDim.x * kGatherPer;
-  // every load uses a valid index (clamped position; perm holds source
-  // indices < n), so all of a thread's loads are in flight together; only
-  // the stores are guarded
-  for (uint32_t p0 = blockIdx.x * blockDim.x * kGatherPer + threadIdx.x; p0 < n; p0 += stride) {
-    uint32_t k[kGatherPer], q[kGatherPer];
-#pragma unroll
-    for (int u = 0; u < kGatherPer; ++u) {
-      const uint32_t p = p0 + u * blockDim.x;
-      const uint32_t pc = (p < n) ? p : n - 1;
-      k[u] = skeys[pc];
-      q[u] = perm[pc];
-    }
-    T r[kGatherPer], z[kGatherPer], vr[kGatherPer], vt[kGatherPer], vz[kGatherPer];
-    uint32_t id[kGatherPer];
-    uint8_t sp[kGatherPer];
-#pragma unroll
-    for (int u = 0; u < kGatherPer; ++u) {
-      // an absorbed particle's record is not written: read the (contiguous)
-      // record at its own position instead of its scattered source
-      const uint32_t p = p0 + u * blockDim.x;
-      const uint32_t s = (k[u] == sentinel) ? ((p < n) ? p : n - 1) : q[u];
-      r[u] = src.r[s];
-      z[u] = src.z[s];
-      vr[u] = src.vr[s];
-      vt[u] = src.vt[s];
-      vz[u] = src.vz[s];
-      sp[u] = src.sp[s];
-      id[u] = src.id[s];
-    }
-#pragma unroll
-    for (int u = 0; u < kGatherPer; ++u) {
-      const uint32_t p = p0 + u * blockDim.x;
-      if (p >= n) continue;
-      dst.key[p] = k[u];
-      if (k[u] == sentinel) continue;
-      dst.r[p] = r[u];
-      dst.z[p] = z[u];
-      dst.vr[p] = vr[u];
-      dst.vt[p] = vt[u];
-      dst.vz[p] = vz[u];
-      dst.sp[p] = sp[u];
-      dst.id[p] = id[u];
-    }
-  }
-}
-
 // one pass over tiles of 256 IT keys (IT = 4: short tiles, many blocks,
 // for the movers, which are usually few)
 template <int DB, int IT>
@@ -702,19 +646,17 @@ __global__ void __launch_bounds__(256) k_place(const uint32_t* __restrict__ key,
 
 // key_bits <= 20: two passes of ceil(key_bits/2) bits (at most 10);
 // wider keys: passes of 10 bits
-template <typename T>
-void sort_particles(const PartsT<T>& src, const PartsT<T>& dst, int key_bits, SortWork& w,
-                    DevState* st, const uint32_t* off, uint32_t sentinel, int part,
-                    hipStream_t s) {
+void sort_keys(const uint32_t* key, int key_bits, SortWork& w, DevState* st, const uint32_t* off,
+               uint32_t sentinel, hipStream_t s) {
   int passes = (key_bits + kRadixMaxBits - 1) / kRadixMaxBits;
   if (passes < 2) passes = 2;
   const int dbits = (key_bits + passes - 1) / passes;
   const int nb = (int)((w.cap + kScanChunk - 1) / kScanChunk);
-  if (part == 0) {
+  {
     // classify, count and compact the movers (key, index) into k0/v0
-    k_cls_count<<<nb, 256, 0, s>>>(src.key, w.skey, st, w.bsum, w.scan_len);
+    k_cls_count<<<nb, 256, 0, s>>>(key, w.skey, st, w.bsum, w.scan_len);
     k_scan_bsums<<<1, 1024, 0, s>>>(w.bsum, w.scan_len, w.n_mov, nullptr, 0, kScanChunk);
-    k_cls_compact<<<nb, 256, 0, s>>>(src.key, w.skey, st, w.bsum, w.mpre, w.k0, w.v0);
+    k_cls_compact<<<nb, 256, 0, s>>>(key, w.skey, st, w.bsum, w.mpre, w.k0, w.v0);
     // stable radix sort of the movers
     const uint32_t* kin = w.k0;
     const uint32_t* vin = w.v0;
@@ -736,18 +678,9 @@ void sort_particles(const PartsT<T>& src, const PartsT<T>& dst, int key_bits, So
                                                     w.bound);
     int pg = (int)(nch < 16384 ? nch : 16384);
     if (pg < 1) pg = 1;
-    k_place<<<pg, 256, 0, s>>>(src.key, st, w.mpre, w.ins, w.bound, w.skey, w.perm);
-  } else {
-    int64_t gb = (w.cap + 256 * kGatherPer - 1) / (256 * kGatherPer);
-    if (gb < 1) gb = 1;
-    if (gb > 2048) gb = 2048;
-    k_gather<T><<<(int)gb, 256, 0, s>>>(src, dst, w.skey, w.perm, st, sentinel);
+    k_place<<<pg, 256, 0, s>>>(key, st, w.mpre, w.ins, w.bound, w.skey, w.perm);
   }
 }
-template void sort_particles<double>(const Parts&, const Parts&, int, SortWork&, DevState*,
-                                     const uint32_t*, uint32_t, int, hipStream_t);
-template void sort_particles<float>(const PartsF&, const PartsF&, int, SortWork&, DevState*,
-                                    const uint32_t*, uint32_t, int, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // off[k] = first sorted position whose key >= k, for k = 0 .. nkeys-1;

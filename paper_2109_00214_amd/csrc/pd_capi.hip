@@ -493,12 +493,17 @@ hipEvent_t get_event(pd_ctx* c) {
 
 void harvest_timing(pd_ctx* c) {
   for (auto& set : c->ev_pending) {
+    // a null entry repeats the boundary before it
+    for (size_t k = 1; k < set.size(); ++k)
+      if (!set[k]) set[k] = set[k - 1];
     for (int k = 0; k < PD_NTIMERS; ++k) {
       float ms = 0.f;
-      if (hipEventElapsedTime(&ms, set[k], set[k + 1]) == hipSuccess) c->t_ms[k] += ms;
+      if (set[k] != set[k + 1] && hipEventElapsedTime(&ms, set[k], set[k + 1]) == hipSuccess)
+        c->t_ms[k] += ms;
     }
     c->t_steps += 1;
-    for (auto e : set) c->ev_pool.push_back(e);
+    for (size_t k = 0; k < set.size(); ++k)
+      if (k == 0 || set[k] != set[k - 1]) c->ev_pool.push_back(set[k]);
   }
   c->ev_pending.clear();
 }
@@ -532,30 +537,32 @@ pd_status stage_append(pd_ctx* c, const PartsT<T>& A, const PartsT<T>& B, int64_
 }
 
 // one step on the context's stream: sort -> collide -> deposit -> Poisson
-// -> field -> push -> inject (mark() records the stage boundaries)
+// -> field -> push -> inject (mark() records the stage boundaries; the
+// records stay in A, in the previous order, until the push writes them
+// sorted into B, which then becomes A)
 template <class T, class Mark>
 pd_status enqueue_step(pd_ctx* c, PartsT<T>& A, PartsT<T>& B, int64_t nn, Mark& mark) {
   hipStream_t s = c->stream;
   mark();
-  sort_particles(A, B, c->key_bits, c->sw, c->st, c->off, c->g.sentinel, 0, s);
+  sort_keys(A.key, c->key_bits, c->sw, c->st, c->off, c->g.sentinel, s);
   mark();
-  sort_particles(A, B, c->key_bits, c->sw, c->st, c->off, c->g.sentinel, 1, s);
-  std::swap(A, B);
+  mark(true);  // no separate record permutation: the push moves the records
+  build_offsets(c->sw.skey, c->st, c->off, c->g.sentinel + 1, c->fw.Q, (uint32_t)nn, s);
+  const Flow<T> f{A, B, c->sw.perm, c->sw.skey};
   mark();
-  build_offsets(A.key, c->st, c->off, c->g.sentinel + 1, c->fw.Q, (uint32_t)nn, s);
+  if (!c->opts.collisions_off) collide(f, c->off, c->st, c->g, c->cpar, c->cw, c->sw.bsum, c->cap, s);
   mark();
-  if (!c->opts.collisions_off) collide(A, c->off, c->st, c->g, c->cpar, c->cw, c->sw.bsum, c->cap, s);
-  mark();
-  if (!c->opts.deposit_off) deposit(A, c->st, c->off, c->g, c->spp, c->fw.Q, c->cap, s);
+  if (!c->opts.deposit_off) deposit(f, c->st, c->g, c->spp, c->fw.Q, c->cap, s);
   mark();
   pd_status ps = solve_poisson(c);
   if (ps) return ps;
   mark();
   field(c->g, c->fw, s);
   mark();
-  push(A, c->st, c->g, c->spp, c->fw, c->cap, s);
+  push(f, c->st, c->g, c->spp, c->fw, c->cap, s);
   mark();
-  inject_and_roll(A, c->st, c->g, c->sched, c->cap, s);
+  inject_and_roll(B, c->st, c->g, c->sched, c->cap, s);
+  std::swap(A, B);
   mark();
   return PD_OK;
 }
@@ -855,8 +862,14 @@ pd_status pd_step(pd_ctx* c, int nsteps) {
   const int64_t nn = (int64_t)(c->g.nr + 1) * (c->g.nz + 1);
   for (int t = 0; t < nsteps; ++t) {
     std::vector<hipEvent_t> ev;
-    auto mark = [&]() {
+    // same: the boundary coincides with the previous one (an empty stage,
+    // kept as a null entry, no event recorded)
+    auto mark = [&](bool same = false) {
       if (c->opts.timing) {
+        if (same && !ev.empty()) {
+          ev.push_back(nullptr);
+          return;
+        }
         hipEvent_t e = get_event(c);
         (void)hipEventRecord(e, s);
         ev.push_back(e);
@@ -1118,7 +1131,7 @@ pd_status pd_ensemble_create(int32_t n, pd_ctx* const* members, int32_t nstreams
   bool ok = hipStreamBeginCapture(e->s0, hipStreamCaptureModeRelaxed) == hipSuccess &&
             hipEventRecord(e->ev[K], e->s0) == hipSuccess;
   for (int k = 0; ok && k < K; ++k) ok = hipStreamWaitEvent(e->ws[k], e->ev[K], 0) == hipSuccess;
-  auto nomark = []() {};
+  auto nomark = [](bool = false) {};
   for (int i = 0; ok && i < n; ++i) {
     pd_ctx* c = e->m[i];
     c->stream = e->ws[i % K];
@@ -1340,9 +1353,17 @@ void pd_unet_destroy(pd_unet* n) {
   delete n;
 }
 
+pd_status pd_set_timing(pd_ctx* c, int on) {
+  if (!c) return PD_EINVAL;
+  if (c->in_ensemble) return set_err(c, PD_ESTATE, "context belongs to an ensemble");
+  c->opts.timing = on ? 1 : 0;
+  return PD_OK;
+}
+
 pd_status pd_get_timing(pd_ctx* c, double* ms, int64_t* steps, int reset) {
   if (!c) return PD_EINVAL;
-  if (!c->opts.timing) return set_err(c, PD_ESTATE, "timing was not enabled");
+  if (!c->opts.timing && c->t_steps == 0 && c->ev_pending.empty())
+    return set_err(c, PD_ESTATE, "timing was not enabled");
   pd_status s = sync(c);
   if (s) return s;
   harvest_timing(c);

@@ -45,6 +45,20 @@ struct PartsT {
 using Parts = PartsT<double>;
 using PartsF = PartsT<float>;
 
+// The records of a step: U holds them in the previous step's order (as the
+// push left them, with the injected ones after); the sort gives the new
+// order as perm (sorted position -> index in U) and skey (the keys in that
+// order).  Collisions and the deposit read and update U through perm; the
+// push reads U through perm and writes every record at its sorted position
+// in S, where the collisions also put the electrons they create (after the
+// live particles).  The records therefore move once per step.
+template <typename T>
+struct Flow {
+  PartsT<T> U, S;
+  const uint32_t* perm;
+  const uint32_t* skey;
+};
+
 struct Grid {
   int nr, nz;
   uint32_t C;         // cells nr*nz
@@ -104,17 +118,14 @@ struct SortWork {
   int64_t cap;
 };
 
-// Stable sort of the st->n_total particles of src by key (ties in index
-// order), then the records moved into dst in that order (every key, the
-// sentinel ones included, lands in dst.key).  The first st->n_alive
-// positions hold the previous sort's order with updated keys: the particles
-// whose key did not change stay in order and are merged with the others
-// (radix-sorted) by (key, index), using the previous order's offsets off.
-// part = 0: the order; part = 1: the record moves.
-template <typename T>
-void sort_particles(const PartsT<T>& src, const PartsT<T>& dst, int key_bits, SortWork& w,
-                    DevState* st, const uint32_t* off, uint32_t sentinel, int part,
-                    hipStream_t s);
+// Stable sort of the st->n_total keys of the records by key (ties in index
+// order) into w.perm (sorted position -> index) and w.skey.  The first
+// st->n_alive positions hold the previous sort's order with updated keys:
+// the particles whose key did not change stay in order and are merged with
+// the others (radix-sorted) by (key, index), using the previous order's
+// offsets off.
+void sort_keys(const uint32_t* key, int key_bits, SortWork& w, DevState* st, const uint32_t* off,
+               uint32_t sentinel, hipStream_t s);
 // Exclusive scan of *len u32 values (device length), total to *total.  With
 // a guard state the total counts new particles: it is forced to 0 and the
 // error flagged when they would not fit in cap (or the ids would wrap).
@@ -162,7 +173,7 @@ struct CollideWork {
   int64_t cap;
 };
 template <typename T>
-void collide(const PartsT<T>& P, const uint32_t* off, DevState* st, const Grid& g,
+void collide(const Flow<T>& f, const uint32_t* off, DevState* st, const Grid& g,
              const CollideParams& cp, CollideWork& w, uint32_t* bsum, int64_t cap,
              hipStream_t s);
 
@@ -186,8 +197,8 @@ struct FieldWork {
   const double* coef;   // [nr+1] -qunit / (V_node eps0)
 };
 template <typename T>
-void deposit(const PartsT<T>& P, const DevState* st, const uint32_t* off, const Grid& g,
-             const SpeciesParams& sp, int64_t* Q, int64_t cap, hipStream_t s);
+void deposit(const Flow<T>& f, const DevState* st, const Grid& g, const SpeciesParams& sp,
+             int64_t* Q, int64_t cap, hipStream_t s);
 void poisson_direct(const Grid& g, FieldWork& fw, hipStream_t s);
 size_t poisson_lds_bytes(int nr, int nz);
 // the same solve with the transforms on the FP64 matrix cores and the
@@ -244,7 +255,7 @@ void mg_residual(const MGWork& w, const double* phi, const int64_t* Q, hipStream
 void mg_outer(MGWork& w, double* phi, const int64_t* Q, int inner, hipStream_t s);
 void field(const Grid& g, FieldWork& fw, hipStream_t s);
 template <typename T>
-void push(const PartsT<T>& P, DevState* st, const Grid& g, const SpeciesParams& sp,
+void push(const Flow<T>& f, DevState* st, const Grid& g, const SpeciesParams& sp,
           const FieldWork& fw, int64_t cap, hipStream_t s);
 // append this step's scheduled particles and roll the step counters
 template <typename T>

@@ -23,7 +23,7 @@ TIMER_NAMES = ("radix", "permute", "offsets", "collide", "deposit", "poisson", "
 EXPORTED = ("pd_create", "pd_set_species", "pd_set_cross_section", "pd_inject",
             "pd_schedule_injection", "pd_step", "pd_synchronize", "pd_get_diagnostics",
             "pd_get_spectrum", "pd_get_count", "pd_get_particles", "pd_get_field",
-            "pd_poisson", "pd_get_timing", "pd_last_error", "pd_destroy",
+            "pd_poisson", "pd_get_timing", "pd_set_timing", "pd_last_error", "pd_destroy",
             "pd_unet_create", "pd_unet_info", "pd_unet_set_weights", "pd_unet_get_weights",
             "pd_unet_forward", "pd_unet_gradient", "pd_unet_add_sample", "pd_unet_train",
             "pd_set_unet", "pd_unet_last_error", "pd_unet_destroy",
@@ -87,6 +87,7 @@ def load_library(path=LIB_PATH):
     lib.pd_get_field.argtypes = [P, P, P, P, P]
     lib.pd_poisson.argtypes = [P, P, P, C.POINTER(C.c_int32), C.POINTER(C.c_double)]
     lib.pd_get_timing.argtypes = [P, P, C.POINTER(C.c_int64), C.c_int]
+    lib.pd_set_timing.argtypes = [P, C.c_int]
     lib.pd_last_error.argtypes = [P]
     lib.pd_last_error.restype = C.c_char_p
     lib.pd_unet_create.argtypes = [C.c_int32] * 5 + [C.c_int64, C.POINTER(C.c_void_p)]
@@ -341,6 +342,10 @@ def pd_get_timing(ctx, reset=False):
     return dict(zip(TIMER_NAMES, ms.tolist())), steps.value
 
 
+def pd_set_timing(ctx, on):
+    _check(ctx, load_library().pd_set_timing(ctx, int(bool(on))))
+
+
 def pd_last_error(ctx):
     msg = load_library().pd_last_error(ctx)
     return msg.decode() if msg else ""
@@ -401,6 +406,9 @@ class Simulation:
 
     def timing(self, reset=False):
         return pd_get_timing(self.h, reset)
+
+    def set_timing(self, on):
+        pd_set_timing(self.h, on)
 
     def close(self):
         if getattr(self, "h", None):
