@@ -173,7 +173,7 @@ def run_ensemble(a):
         "data": "synthetic",
         "config": {"workload": "ensemble: %d replicas, 128x256 or 256x512 r-z cells, V 1-5 kV, "
                                "%d initial super-particles in all (log-uniform 0.2M-8M each), "
-                               "FP32 records, direct FP64 Poisson, one HIP graph per two steps"
+                               "FP32 records, matrix-core direct FP64 Poisson, one HIP graph per two steps"
                                % (len(cfgs), n_particles),
                    "replicas_256x512": sum(c.nr == 256 for c in cfgs),
                    "worker_streams": best, "autotune": {str(k): v for k, v in tune.items()},

@@ -64,8 +64,10 @@ enum { PD_E = 0, PD_CU = 1, PD_CU1 = 2, PD_CU2_STEP = 3, PD_CU2_DOUBLE = 4,
 enum { PD_EL = 0, PD_SI = 1, PD_DI = 2, PD_SI2 = 3, PD_NCHANNELS = 4 };
 /* absorbing boundaries */
 enum { PD_CATHODE = 0, PD_ANODE = 1, PD_OUTER = 2 };
-/* precision forms: FP64 deterministic (every result bit-identical to the
- * binary64 arithmetic of the method), or FP32 mixed: FP32 particle record,
+/* precision forms: FP64 deterministic (with PD_POISSON_DIRECT64 every result
+ * bit-identical to the binary64 arithmetic of the method; with
+ * PD_POISSON_SPECTRAL the potential and field equal to it to rounding, the
+ * integer results identical in practice), or FP32 mixed: FP32 particle record,
  * gather and push; int64 fixed-point deposit (exact); FP64 collision
  * arithmetic and diagnostics */
 enum { PD_FP64_DET = 0, PD_FP32_MIXED = 1 };
