@@ -322,9 +322,11 @@ __global__ void __launch_bounds__(256) k_apply(Flow<T> f, const uint32_t* off, D
 template <typename T>
 void collide(const Flow<T>& P, const uint32_t* off, DevState* st, const Grid& g,
              const CollideParams& cp, CollideWork& w, uint32_t* bsum, int64_t cap, hipStream_t s) {
-  const int gr = grid_for(cap);
+  // grids for the electrons (a few percent of the capacity in a steady
+  // state); the launches loop over whatever there is
+  const int gr = grid_for(cap) < 1024 ? grid_for(cap) : 1024;
   int nb = (int)((cap + 255) / 256);
-  if (nb > 8192) nb = 8192;
+  if (nb > 1024) nb = 1024;
   k_decide<T><<<gr, 256, 0, s>>>(P, off, st, g, cp, w.choice, w.target, w.claim, w.scan_len);
   k_resolve<<<nb, 256, 0, s>>>(off, st, g, w.choice, w.target, w.claim, w.ccount, bsum);
   // created-electron slots: the scan of the chunk sums; its guard flags an

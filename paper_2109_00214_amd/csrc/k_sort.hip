@@ -44,28 +44,8 @@ static inline int grid_for(int64_t n, int block = 256) {
 }
 
 // ---------------------------------------------------------------------------
-// exclusive scan of *len_p u32 values; chunks of kScanChunk = 256 x 8
-
-__global__ void __launch_bounds__(256) k_scan_reduce(const uint32_t* __restrict__ in,
-                                                     const uint32_t* len_p,
-                                                     uint32_t* __restrict__ bsum) {
-  __shared__ uint32_t sh[4];
-  const uint32_t len = *len_p;
-  const uint32_t nb = (len + kScanChunk - 1) / kScanChunk;
-  if (blockIdx.x >= nb) return;
-  const uint32_t base = blockIdx.x * kScanChunk + threadIdx.x * kScanPer;
-  uint32_t acc = 0;
-#pragma unroll
-  for (int k = 0; k < kScanPer; ++k) {
-    const uint32_t x = in[(base + k < len) ? base + k : len - 1];  // no branch around the load
-    acc += (base + k < len) ? x : 0u;
-  }
-  uint32_t tot;
-  block_scan256(acc, &tot, sh);
-  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
-}
-
-// Exclusive scan of the block sums by one 1024-thread block (<= 65536 sums).
+// Exclusive scan of per-chunk sums (chunks of `chunk` elements of a length
+// *len_p) by one 1024-thread block, each thread a run of them.
 // With a guard state, the total is the number of electrons a collision step
 // creates: if they do not fit (capacity, 32-bit ids) or an error is already
 // flagged, the error is flagged and the total forced to 0, so every later
@@ -112,44 +92,9 @@ __global__ void __launch_bounds__(1024) k_scan_bsums(uint32_t* bsum, const uint3
   }
 }
 
-__global__ void __launch_bounds__(256) k_scan_down(const uint32_t* in, uint32_t* out,
-                                                   const uint32_t* len_p,
-                                                   const uint32_t* __restrict__ bsum) {
-  __shared__ uint32_t sh[4];
-  const uint32_t len = *len_p;
-  const uint32_t nb = (len + kScanChunk - 1) / kScanChunk;
-  if (blockIdx.x >= nb) return;
-  const uint32_t base = blockIdx.x * kScanChunk + threadIdx.x * kScanPer;
-  uint32_t v[kScanPer];
-  uint32_t acc = 0;
-#pragma unroll
-  for (int k = 0; k < kScanPer; ++k) {
-    const uint32_t x = in[(base + k < len) ? base + k : len - 1];
-    v[k] = (base + k < len) ? x : 0u;
-    acc += v[k];
-  }
-  uint32_t tot;
-  uint32_t run = bsum[blockIdx.x] + block_scan256(acc, &tot, sh);
-#pragma unroll
-  for (int k = 0; k < kScanPer; ++k) {
-    if (base + k < len) out[base + k] = run;
-    run += v[k];
-  }
-}
-
 void scan_block_sums(uint32_t* bsum, const uint32_t* len, uint32_t* total, DevState* guard,
                      uint32_t cap, uint32_t chunk, hipStream_t s) {
   k_scan_bsums<<<1, 1024, 0, s>>>(bsum, len, total, guard, cap, chunk);
-}
-
-void scan_exclusive(const uint32_t* in, uint32_t* out, const uint32_t* len, uint32_t* total,
-                    uint32_t* bsum, int64_t max_len, hipStream_t s, DevState* guard,
-                    uint32_t cap) {
-  int nb = (int)((max_len + kScanChunk - 1) / kScanChunk);
-  if (nb < 1) nb = 1;
-  k_scan_reduce<<<nb, 256, 0, s>>>(in, len, bsum);
-  k_scan_bsums<<<1, 1024, 0, s>>>(bsum, len, total, guard, cap, kScanChunk);
-  k_scan_down<<<nb, 256, 0, s>>>(in, out, len, bsum);
 }
 
 // ---------------------------------------------------------------------------
@@ -431,13 +376,13 @@ static void radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout,
                        int shift, SortWork& w, const uint32_t* np, const MoverPlace& samp,
                        hipStream_t s) {
   constexpr int R = 1 << DB;
-  k_radix_up<DB, IT><<<tile_grid(w.cap, 8, 256 * IT), 256, 0, s>>>(kin, np, shift, w.hist);
+  k_radix_up<DB, IT><<<tile_grid(w.cap, 2, 256 * IT), 256, 0, s>>>(kin, np, shift, w.hist);
   k_radix_colscan<R, IT><<<R / 64, 64 * kColWaves, 0, s>>>(w.hist, w.bsum, np);
   if (!vin)
-    k_radix_down<DB, IT, true><<<tile_grid(w.cap, 6, 256 * IT), 256, 0, s>>>(
+    k_radix_down<DB, IT, true><<<tile_grid(w.cap, 2, 256 * IT), 256, 0, s>>>(
         kin, vin, kout, vout, np, shift, w.hist, w.bsum, samp);
   else
-    k_radix_down<DB, IT, false><<<tile_grid(w.cap, 6, 256 * IT), 256, 0, s>>>(
+    k_radix_down<DB, IT, false><<<tile_grid(w.cap, 2, 256 * IT), 256, 0, s>>>(
         kin, vin, kout, vout, np, shift, w.hist, w.bsum, samp);
 }
 
@@ -676,7 +621,7 @@ void sort_keys(const uint32_t* key, int key_bits, SortWork& w, DevState* st, con
     const int64_t nch = (w.cap + kPlaceChunk - 1) / kPlaceChunk;
     k_place_bounds<<<grid_for(nch + 1), 256, 0, s>>>(st, w.mpre, w.ins, w.samp, w.n_mov,
                                                     w.bound);
-    int pg = (int)(nch < 16384 ? nch : 16384);
+    int pg = (int)(nch < 4096 ? nch : 4096);
     if (pg < 1) pg = 1;
     k_place<<<pg, 256, 0, s>>>(key, st, w.mpre, w.ins, w.bound, w.skey, w.perm);
   }

@@ -33,7 +33,8 @@ typedef double dx4 __attribute__((ext_vector_type(4)));
 constexpr int kDstSteps = 32;  // k-steps of 4 loaded ahead of their products
 
 template <bool FWD>
-__global__ void __launch_bounds__(256) k_dst_mfma(const int64_t* __restrict__ Q,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2)))
+k_dst_mfma(const int64_t* __restrict__ Q,
                                                  const double* __restrict__ coef,
                                                  const double* __restrict__ G,
                                                  const double* __restrict__ T, int nr, int nz,
@@ -53,19 +54,32 @@ __global__ void __launch_bounds__(256) k_dst_mfma(const int64_t* __restrict__ Q,
   int c = cw0 + lk;
   int m = (int)(((int64_t)(c + 1) * sb) % N2);
   dx4 acc = {0.0, 0.0, 0.0, 0.0};
+  const double cf = FWD ? coef[ac] : 1.0;
   for (int s0 = 0; s0 < nsteps; s0 += kDstSteps) {
+    // every load of the chunk first (clamped, unconditional), then the
+    // products, so that the loads are in flight together
+    int mi[kDstSteps];
+#pragma unroll
+    for (int u = 0; u < kDstSteps; ++u) {
+      mi[u] = m;
+      m += dm;
+      if (m >= N2) m -= N2;
+    }
     double av[kDstSteps], bv[kDstSteps];
+    int64_t qv[kDstSteps];
+#pragma unroll
+    for (int u = 0; u < kDstSteps; ++u) {
+      const int cu = c + 4 * u;
+      const int cl = (cu < M) ? cu : M - 1;
+      av[u] = T[mi[u]];
+      if (FWD) qv[u] = Q[(size_t)(cl + 1) * W + ac];
+      else bv[u] = G[(size_t)cl * W + ac];
+    }
 #pragma unroll
     for (int u = 0; u < kDstSteps; ++u) {
       const int cu = c + 4 * u;
       const bool ok = (s0 + u < nsteps) && (cu < M);
-      const int cl = (cu < M) ? cu : M - 1;  // clamped, unconditional loads
-      av[u] = T[m];
-      m += dm;
-      if (m >= N2) m -= N2;
-      double x;
-      if (FWD) x = (double)Q[(size_t)(cl + 1) * W + ac] * coef[ac];
-      else x = G[(size_t)cl * W + ac];
+      const double x = FWD ? (double)qv[u] * cf : bv[u];
       bv[u] = ok ? x : 0.0;
     }
 #pragma unroll
@@ -113,32 +127,41 @@ __device__ inline double shfl_down_f64(double v, int o) {
 
 // One wave per sine mode k: fh[k][i] -> G[k][i] by the factored tridiagonal
 // solve (invT = the pivots' reciprocals, cT = the upper factors, ra = the
-// radial lower coefficients), lane l holding rows l P .. l P + P - 1.
+// radial lower coefficients), lane l holding rows l P .. l P + P - 1
+// (P <= PM).  Every load comes first, then the scans.
 constexpr int kTriMaxP = 16;  // rows per lane: nr + 1 <= 1024
 
-__global__ void __launch_bounds__(256) k_tri_scan(const double* __restrict__ fh,
-                                                 const double* __restrict__ invT,
-                                                 const double* __restrict__ cT,
-                                                 const double* __restrict__ ra, int nr, int nz,
-                                                 double* __restrict__ G) {
+template <int PM>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2)))
+k_tri_scan(const double* __restrict__ fh, const double* __restrict__ invT,
+           const double* __restrict__ cT, const double* __restrict__ ra, int nr, int nz,
+           double* __restrict__ G) {
   const int W = nr + 1, M = nz - 1;
   const int lane = threadIdx.x & 63;
   const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (k >= M) return;  // whole wave
   const int P = (W + 63) / 64;
   const size_t base = (size_t)k * W;
-  double y[kTriMaxP];
-  Aff f[kTriMaxP];
+  double fv[PM], iv[PM], rv[PM], cv[PM];
+#pragma unroll
+  for (int p = 0; p < PM; ++p) {
+    const int i = lane * P + p;
+    const int ic = (p < P && i < W) ? i : 0;  // clamped, unconditional loads
+    fv[p] = fh[base + ic];
+    iv[p] = invT[base + ic];
+    rv[p] = ra[ic];
+    cv[p] = cT[base + ic];
+  }
+  double y[PM];
+  Aff f[PM];
   // forward: dp_i = u_i - w_i dp_{i-1}, u_i = f_i inv_i, w_i = a_i inv_i (w_0 = 0)
   Aff run = {0.0, 1.0};
 #pragma unroll
-  for (int p = 0; p < kTriMaxP; ++p) {
+  for (int p = 0; p < PM; ++p) {
     const int i = lane * P + p;
     const bool ok = (p < P) && (i < W);
-    const int ic = ok ? i : 0;
-    const double inv = invT[base + ic];
-    const double u = fh[base + ic] * inv;
-    const double wv = (ic == 0) ? 0.0 : ra[ic] * inv;
+    const double u = fv[p] * iv[p];
+    const double wv = (i == 0) ? 0.0 : rv[p] * iv[p];
     f[p] = ok ? Aff{u, -wv} : Aff{0.0, 1.0};
     run = after(f[p], run);
   }
@@ -150,19 +173,18 @@ __global__ void __launch_bounds__(256) k_tri_scan(const double* __restrict__ fh,
   double v = shfl_up_f64(run.al, 1);
   if (lane == 0) v = 0.0;
 #pragma unroll
-  for (int p = 0; p < kTriMaxP; ++p) {
+  for (int p = 0; p < PM; ++p) {
     v = f[p].al + f[p].be * v;
     y[p] = v;
   }
   // backward: x_{W-1} = dp_{W-1}, x_i = dp_i - c_i x_{i+1}
   run = {0.0, 1.0};
 #pragma unroll
-  for (int p = kTriMaxP - 1; p >= 0; --p) {
+  for (int p = PM - 1; p >= 0; --p) {
     const int i = lane * P + p;
     const bool ok = (p < P) && (i < W);
-    const int ic = ok ? i : 0;
-    const double cv = (ic == W - 1) ? 0.0 : cT[base + ic];
-    f[p] = ok ? Aff{y[p], -cv} : Aff{0.0, 1.0};
+    const double c = (i == W - 1) ? 0.0 : cv[p];
+    f[p] = ok ? Aff{y[p], -c} : Aff{0.0, 1.0};
     run = after(f[p], run);
   }
 #pragma unroll
@@ -173,7 +195,7 @@ __global__ void __launch_bounds__(256) k_tri_scan(const double* __restrict__ fh,
   v = shfl_down_f64(run.al, 1);
   if (lane == 63) v = 0.0;
 #pragma unroll
-  for (int p = kTriMaxP - 1; p >= 0; --p) {
+  for (int p = PM - 1; p >= 0; --p) {
     v = f[p].al + f[p].be * v;
     const int i = lane * P + p;
     if (p < P && i < W) G[base + i] = v;
@@ -186,7 +208,10 @@ void poisson_spectral(const Grid& g, FieldWork& fw, hipStream_t s) {
   const int nr = g.nr, nz = g.nz, M = nz - 1, W = nr + 1;
   const dim3 grid((W + 15) / 16, (M + 15) / 16);
   k_dst_mfma<true><<<grid, 256, 0, s>>>(fw.Q, fw.coef, nullptr, fw.T, nr, nz, g.V, fw.fh);
-  k_tri_scan<<<(M + 3) / 4, 256, 0, s>>>(fw.fh, fw.invT, fw.cT, fw.ra, nr, nz, fw.g);
+  const int P = (W + 63) / 64;
+  if (P <= 4) k_tri_scan<4><<<(M + 3) / 4, 256, 0, s>>>(fw.fh, fw.invT, fw.cT, fw.ra, nr, nz, fw.g);
+  else if (P <= 8) k_tri_scan<8><<<(M + 3) / 4, 256, 0, s>>>(fw.fh, fw.invT, fw.cT, fw.ra, nr, nz, fw.g);
+  else k_tri_scan<kTriMaxP><<<(M + 3) / 4, 256, 0, s>>>(fw.fh, fw.invT, fw.cT, fw.ra, nr, nz, fw.g);
   k_dst_mfma<false><<<grid, 256, 0, s>>>(nullptr, nullptr, fw.g, fw.T, nr, nz, g.V, fw.phi);
 }
 

@@ -71,6 +71,7 @@ struct pd_ctx {
   bool mg_on = false;
   bool learned = false;
   bool spectral = false;  // direct solve on the matrix cores
+  bool timing_used = false;  // stage timing was on at some point
   int in_ensemble = 0;    // the ensemble's graph holds this context's buffers
   struct pd_unet* net = nullptr;
   int mg_inner = 8, mg_inner_max = 16, mg_outer_max = 8;
@@ -598,6 +599,7 @@ pd_status pd_create(const pd_domain* dom, const pd_opts* opts, pd_ctx** out) {
       !(opts->poisson_rtol >= 0.0) || !std::isfinite(opts->poisson_rtol))
     return fail(set_err(c, PD_EINVAL, "unsupported precision or Poisson mode"));
   c->spectral = opts->poisson == PD_POISSON_SPECTRAL;
+  c->timing_used = opts->timing != 0;
   c->mg_on = opts->poisson != PD_POISSON_DIRECT64 && !c->spectral;
   c->learned = opts->poisson == PD_POISSON_LEARNED;
   c->fp32 = opts->precision == PD_FP32_MIXED;
@@ -651,7 +653,7 @@ pd_status pd_create(const pd_domain* dom, const pd_opts* opts, pd_ctx** out) {
       (s = dalloc(c, &c->sw.bound, cap / 1024 + 2)) ||
       (s = dalloc(c, &c->cw.choice, cap)) || (s = dalloc(c, &c->cw.target, cap)) ||
       (s = dalloc(c, &c->cw.claim, cap)) || (s = dalloc(c, &c->cw.ccount, cap)) ||
-      (s = dalloc(c, &c->cw.cbase, cap)) || (s = dalloc(c, &c->cw.scan_len, 4)) ||
+      (s = dalloc(c, &c->cw.scan_len, 4)) ||
       (s = dalloc(c, &c->fw.Q, nn)) || (s = dalloc(c, &c->fw.phi, nn)) ||
       (s = dalloc(c, &c->fw.Er, nn)) || (s = dalloc(c, &c->fw.Ez, nn)) ||
       (s = dalloc(c, &c->fw.fh, (size_t)M * (nr + 1))) ||
@@ -1357,12 +1359,13 @@ pd_status pd_set_timing(pd_ctx* c, int on) {
   if (!c) return PD_EINVAL;
   if (c->in_ensemble) return set_err(c, PD_ESTATE, "context belongs to an ensemble");
   c->opts.timing = on ? 1 : 0;
+  if (on) c->timing_used = true;
   return PD_OK;
 }
 
 pd_status pd_get_timing(pd_ctx* c, double* ms, int64_t* steps, int reset) {
   if (!c) return PD_EINVAL;
-  if (!c->opts.timing && c->t_steps == 0 && c->ev_pending.empty())
+  if (!c->opts.timing && !c->timing_used)
     return set_err(c, PD_ESTATE, "timing was not enabled");
   pd_status s = sync(c);
   if (s) return s;

@@ -126,14 +126,10 @@ struct SortWork {
 // offsets off.
 void sort_keys(const uint32_t* key, int key_bits, SortWork& w, DevState* st, const uint32_t* off,
                uint32_t sentinel, hipStream_t s);
-// Exclusive scan of *len u32 values (device length), total to *total.  With
-// a guard state the total counts new particles: it is forced to 0 and the
-// error flagged when they would not fit in cap (or the ids would wrap).
-void scan_exclusive(const uint32_t* in, uint32_t* out, const uint32_t* len,
-                    uint32_t* total, uint32_t* bsum, int64_t max_len, hipStream_t s,
-                    DevState* guard, uint32_t cap);
-// the middle launch of that scan alone: exclusive scan, in place, of the
-// per-chunk sums of ceil(*len / chunk) chunks (same guard and total)
+// Exclusive scan, in place, of per-chunk sums of ceil(*len / chunk) chunks,
+// total to *total.  With a guard state the total counts new particles: it is
+// forced to 0 and the error flagged when they would not fit in cap (or the
+// ids would wrap).
 void scan_block_sums(uint32_t* bsum, const uint32_t* len, uint32_t* total, DevState* guard,
                      uint32_t cap, uint32_t chunk, hipStream_t s);
 
@@ -169,7 +165,7 @@ void build_offsets(const uint32_t* skeys, DevState* st, uint32_t* off, uint32_t 
 // ---- collisions (k_collide.hip) ----
 struct CollideWork {
   uint8_t* choice;
-  uint32_t *target, *claim, *ccount, *cbase, *scan_len;
+  uint32_t *target, *claim, *ccount, *scan_len;
   int64_t cap;
 };
 template <typename T>

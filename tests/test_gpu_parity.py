@@ -111,6 +111,39 @@ def test_gpu_runs_are_deterministic():
         assert np.array_equal(runs[0][k], runs[1][k]), k
 
 
+def test_stage_timing_switch():
+    """Stage events only for the steps run with timing on; the result of the
+    steps does not depend on it."""
+    log("case: stage timing switched off and on")
+    cfg = W.config("tiny")
+    parts = W.initial_population(cfg)
+    off, inj = W.injection_schedule(cfg, 12)
+    g = gpu_sim(cfg, 200_000, timing=True)
+    g.inject(parts)
+    g.schedule_injection(off, inj)
+    g.step(3)
+    st, n = g.timing(reset=True)
+    assert n == 3 and st["permute"] == 0.0 and min(st.values()) >= 0.0
+    assert st["radix"] > 0 and st["push"] > 0
+    g.set_timing(False)
+    g.step(5)
+    st, n = g.timing()
+    assert n == 0 and max(st.values()) == 0.0
+    g.set_timing(True)
+    g.step(4)
+    st, n = g.timing()
+    assert n == 4 and st["push"] > 0
+    ref = gpu_sim(cfg, 200_000)
+    ref.inject(parts)
+    ref.schedule_injection(off, inj)
+    ref.step(12)
+    a, b = g.particles(), ref.particles()
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+    g.close()
+    ref.close()
+
+
 def test_errors_leave_state_unchanged():
     from paper_2109_00214_amd.pd import PdError, PD_EINVAL, PD_ECAPACITY
     log("case: error paths")
