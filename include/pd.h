@@ -136,6 +136,7 @@ typedef struct {
 
 /* Create a context on the current HIP device.  dom and opts are copied.
  * Device memory for dom->capacity particles is allocated here.
+ * PD_POISSON_SPECTRAL needs nr <= 1023 and nz <= 4096.
  * Errors: PD_EINVAL (sizes, NaN), PD_ENOMEM, PD_EDEVICE.            */
 pd_status pd_create(const pd_domain* dom, const pd_opts* opts, pd_ctx** out);
 

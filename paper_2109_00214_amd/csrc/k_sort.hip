@@ -631,27 +631,83 @@ void sort_keys(const uint32_t* key, int key_bits, SortWork& w, DevState* st, con
 // off[k] = first sorted position whose key >= k, for k = 0 .. nkeys-1;
 // off[sentinel] is the number of live particles.  The same launch clears the
 // node charge for the deposit that follows.
+//
+// off is the merge of the sorted keys A[0..n) with the key list 0..nkeys-1
+// (a key before the equal A entries): in the merged order A[i] stands at
+// i + A[i] + 1 and key k at k + off[k].  Each block takes an equal share of
+// the n + nkeys merged places (dense stretches of the keys and empty cells
+// cost the same), finds the A entries of its share by a 64-way search of the
+// monotone i + A[i] + 1, stages them in LDS and searches them for its keys.
+constexpr int kOffMax = 4096;  // merged places per block at most
+
+// smallest i in [0, n] with i == n or i + A[i] + 1 >= d; the whole wave
+// (each step probes 64 places, so about log_65(n) steps of one load)
+__device__ inline uint32_t merged_split(const uint32_t* __restrict__ A, uint32_t n, uint32_t d,
+                                        int lane) {
+  uint32_t lo = 0, hi = n;
+  while (hi > lo) {
+    const uint64_t r = hi - lo;
+    const uint32_t p = lo + (uint32_t)((r * (uint64_t)(lane + 1)) / 65u);
+    const bool pred = (uint64_t)p + A[p] + 1u >= d;  // p < hi <= n
+    const unsigned long long bt = __ballot(pred);
+    if (bt == 0ull) {
+      lo = __shfl(p, 63, 64) + 1u;
+    } else {
+      const int f = __ffsll((long long)bt) - 1;
+      const uint32_t pf = __shfl(p, f, 64);
+      const uint32_t pb = __shfl(p, f > 0 ? f - 1 : 0, 64);
+      hi = pf;
+      if (f > 0) lo = pb + 1u;
+    }
+  }
+  return lo;
+}
+
 __global__ void __launch_bounds__(256) k_offsets(const uint32_t* __restrict__ skeys, DevState* st,
                                                  uint32_t* __restrict__ off, uint32_t nkeys,
                                                  int64_t* __restrict__ Q, uint32_t nnodes) {
-  const uint32_t n = st->n_total;
+  __shared__ uint32_t As[kOffMax];
+  __shared__ uint32_t split[2];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < nkeys; k += stride) {
-    uint32_t lo = 0, hi = n;
+  for (uint32_t b = blockIdx.x * blockDim.x + t; b < nnodes; b += stride) Q[b] = 0;
+  const uint32_t n = st->n_total;
+  const uint32_t tot = n + nkeys;
+  const uint32_t D = (tot + gridDim.x - 1) / gridDim.x;  // <= kOffMax by the launch
+  const uint32_t d0 = blockIdx.x * D;
+  if (d0 >= tot) return;  // whole block
+  const uint32_t d1 = (tot - d0 < D) ? tot : d0 + D;
+  if (w < 2) {
+    const uint32_t v = merged_split(skeys, n, w == 0 ? d0 : d1, lane);
+    if (lane == 0) split[w] = v;
+  }
+  __syncthreads();
+  const uint32_t ia = split[0], ib = split[1];
+  const uint32_t na = ib - ia;  // <= D
+  for (uint32_t i = t; i < na; i += blockDim.x) As[i] = skeys[ia + i];
+  __syncthreads();
+  const uint32_t j0 = d0 - ia, j1 = d1 - ib;
+  const uint32_t c = (j1 - j0 + blockDim.x - 1) / blockDim.x;  // keys per thread
+  const uint32_t ja = j0 + t * c;
+  const uint32_t je = (ja + c < j1) ? ja + c : j1;
+  for (uint32_t k = ja; k < je; ++k) {
+    uint32_t lo = 0, hi = na;
     while (lo < hi) {
-      const uint32_t mid = lo + ((hi - lo) >> 1);
-      if (skeys[mid] < k) lo = mid + 1;
+      const uint32_t mid = (lo + hi) >> 1;
+      if (As[mid] < k) lo = mid + 1;
       else hi = mid;
     }
-    off[k] = lo;
-    if (k == nkeys - 1) st->n_alive = lo;
+    off[k] = ia + lo;
+    if (k == nkeys - 1) st->n_alive = ia + lo;
   }
-  for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < nnodes; b += stride) Q[b] = 0;
 }
 
-void build_offsets(const uint32_t* skeys, DevState* st, uint32_t* off, uint32_t nkeys,
-                   int64_t* Q, uint32_t nnodes, hipStream_t s) {
-  k_offsets<<<grid_for(nkeys), 256, 0, s>>>(skeys, st, off, nkeys, Q, nnodes);
+void build_offsets(const SortWork& w, DevState* st, uint32_t* off, uint32_t nkeys, int64_t* Q,
+                   uint32_t nnodes, hipStream_t s) {
+  const int64_t places = w.cap + (int64_t)nkeys;
+  int64_t gr = (places + kOffMax - 1) / kOffMax;
+  if (gr < 1024) gr = 1024;  // a fuller chip for small runs
+  k_offsets<<<(int)gr, 256, 0, s>>>(w.skey, st, off, nkeys, Q, nnodes);
 }
 
 }  // namespace pd

@@ -30,18 +30,34 @@ typedef double dx4 __attribute__((ext_vector_type(4)));
 // electrode rows.  Operand layout of the 16x16x4 product: lane l holds
 // A[l%16][l/16] and B[l/16][l%16]; result register r of lane l is
 // D[4r + l/16][l%16].
-constexpr int kDstSteps = 32;  // k-steps of 4 loaded ahead of their products
+constexpr int kDstSteps = 16;  // k-steps of 4 loaded ahead of their products
 
+// At most 128 registers a lane, so that four waves share a SIMD: the 16 x 16
+// tiles of a 256 x 512 grid (544 blocks) then run in one round.
 template <bool FWD>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2)))
-k_dst_mfma(const int64_t* __restrict__ Q,
-                                                 const double* __restrict__ coef,
-                                                 const double* __restrict__ G,
-                                                 const double* __restrict__ T, int nr, int nz,
-                                                 double V, double* __restrict__ out) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+k_dst_mfma(const int64_t* __restrict__ Q, const double* __restrict__ coef,
+           const double* __restrict__ G, const double* __restrict__ T, int nr, int nz, double V,
+           double* __restrict__ out) {
+  extern __shared__ double Ts[];  // the sine table, 2 nz entries (dynamic LDS)
   __shared__ double red[3][4][64];
   const int W = nr + 1, M = nz - 1, N2 = 2 * nz;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  // the operand entries are scattered over the table: served from LDS, a
+  // gather from the vector cache costs one tag lookup per lane
+  for (int i0 = 0; i0 < N2; i0 += 4 * 256) {
+    double tv[4];  // four loads in flight, then the four stores
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = i0 + u * 256 + t;
+      tv[u] = T[(i < N2) ? i : 0];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = i0 + u * 256 + t;
+      if (i < N2) Ts[i] = tv[u];
+    }
+  }
   const int li = lane & 15, lk = lane >> 4;
   const int a0 = blockIdx.x * 16, b0 = blockIdx.y * 16;
   const int a = a0 + li, ac = (a < W) ? a : W - 1;
@@ -50,11 +66,12 @@ k_dst_mfma(const int64_t* __restrict__ Q,
   const int cw0 = w * KW;
   const int nsteps = KW / 4;
   const int sb = bc + 1;
-  const int dm = (int)(((int64_t)4 * sb) % N2);
+  const int dm = (4 * sb) % N2;  // products below nz^2 <= 2^26: 32-bit
   int c = cw0 + lk;
-  int m = (int)(((int64_t)(c + 1) * sb) % N2);
+  int m = ((c + 1) * sb) % N2;
   dx4 acc = {0.0, 0.0, 0.0, 0.0};
   const double cf = FWD ? coef[ac] : 1.0;
+  __syncthreads();
   for (int s0 = 0; s0 < nsteps; s0 += kDstSteps) {
     // every load of the chunk first (clamped, unconditional), then the
     // products, so that the loads are in flight together
@@ -71,10 +88,11 @@ k_dst_mfma(const int64_t* __restrict__ Q,
     for (int u = 0; u < kDstSteps; ++u) {
       const int cu = c + 4 * u;
       const int cl = (cu < M) ? cu : M - 1;
-      av[u] = T[mi[u]];
+      av[u] = Ts[mi[u]];
       if (FWD) qv[u] = Q[(size_t)(cl + 1) * W + ac];
       else bv[u] = G[(size_t)cl * W + ac];
     }
+    __builtin_amdgcn_sched_barrier(0);  // keep every load of the chunk ahead
 #pragma unroll
     for (int u = 0; u < kDstSteps; ++u) {
       const int cu = c + 4 * u;
@@ -207,14 +225,18 @@ k_tri_scan(const double* __restrict__ fh, const double* __restrict__ invT,
 void poisson_spectral(const Grid& g, FieldWork& fw, hipStream_t s) {
   const int nr = g.nr, nz = g.nz, M = nz - 1, W = nr + 1;
   const dim3 grid((W + 15) / 16, (M + 15) / 16);
-  k_dst_mfma<true><<<grid, 256, 0, s>>>(fw.Q, fw.coef, nullptr, fw.T, nr, nz, g.V, fw.fh);
+  const size_t lds = (size_t)2 * nz * sizeof(double);
+  k_dst_mfma<true><<<grid, 256, lds, s>>>(fw.Q, fw.coef, nullptr, fw.T, nr, nz, g.V, fw.fh);
   const int P = (W + 63) / 64;
   if (P <= 4) k_tri_scan<4><<<(M + 3) / 4, 256, 0, s>>>(fw.fh, fw.invT, fw.cT, fw.ra, nr, nz, fw.g);
   else if (P <= 8) k_tri_scan<8><<<(M + 3) / 4, 256, 0, s>>>(fw.fh, fw.invT, fw.cT, fw.ra, nr, nz, fw.g);
   else k_tri_scan<kTriMaxP><<<(M + 3) / 4, 256, 0, s>>>(fw.fh, fw.invT, fw.cT, fw.ra, nr, nz, fw.g);
-  k_dst_mfma<false><<<grid, 256, 0, s>>>(nullptr, nullptr, fw.g, fw.T, nr, nz, g.V, fw.phi);
+  k_dst_mfma<false><<<grid, 256, lds, s>>>(nullptr, nullptr, fw.g, fw.T, nr, nz, g.V, fw.phi);
 }
 
-bool spectral_fits(int nr, int nz) { return nr + 1 <= 64 * kTriMaxP && nz >= 2; }
+// rows per lane of the scan; the sine table (2 nz doubles) within 64 KiB of LDS
+bool spectral_fits(int nr, int nz) {
+  return nr + 1 <= 64 * kTriMaxP && nz >= 2 && (size_t)2 * nz * sizeof(double) <= 65536;
+}
 
 }  // namespace pd

@@ -548,7 +548,7 @@ pd_status enqueue_step(pd_ctx* c, PartsT<T>& A, PartsT<T>& B, int64_t nn, Mark& 
   sort_keys(A.key, c->key_bits, c->sw, c->st, c->off, c->g.sentinel, s);
   mark();
   mark(true);  // no separate record permutation: the push moves the records
-  build_offsets(c->sw.skey, c->st, c->off, c->g.sentinel + 1, c->fw.Q, (uint32_t)nn, s);
+  build_offsets(c->sw, c->st, c->off, c->g.sentinel + 1, c->fw.Q, (uint32_t)nn, s);
   const Flow<T> f{A, B, c->sw.perm, c->sw.skey};
   mark();
   if (!c->opts.collisions_off) collide(f, c->off, c->st, c->g, c->cpar, c->cw, c->sw.bsum, c->cap, s);

@@ -158,9 +158,11 @@ __device__ inline uint32_t block_scan256(uint32_t v, uint32_t* total, uint32_t* 
   *total = tot;
   return wbase + x - v;
 }
-// CSR offsets of the sorted keys; the same launch clears the node charge Q.
-void build_offsets(const uint32_t* skeys, DevState* st, uint32_t* off, uint32_t nkeys,
-                   int64_t* Q, uint32_t nnodes, hipStream_t s);
+// CSR offsets of the sorted keys w.skey (off[k] = first sorted position with
+// key >= k, k < nkeys; st->n_alive = off[nkeys - 1]); the same launch clears
+// the node charge Q.
+void build_offsets(const SortWork& w, DevState* st, uint32_t* off, uint32_t nkeys, int64_t* Q,
+                   uint32_t nnodes, hipStream_t s);
 
 // ---- collisions (k_collide.hip) ----
 struct CollideWork {

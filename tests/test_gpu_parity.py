@@ -52,6 +52,20 @@ def test_ragged_sizes_short_run(n):
         assert_same_state(g, o, "n=%d step %d" % (n, s))
 
 
+@pytest.mark.parametrize("n", [6000, 60000])
+def test_sparse_keys_paper_grid(n):
+    """The 256 x 512 grid with few particles: most cells are empty (two whole
+    species among them), so the cell offsets come from long runs of empty
+    cells as well as from dense stretches of the sorted keys."""
+    log("case: sparse keys, 256x512 grid, n=%d" % n)
+    cfg = W.config("tiny", nr=256, nz=512, n_init=n)
+    g, o = pair(cfg, n_init=n, steps=3)
+    for s in range(1, 4):
+        g.step(1)
+        o.step(1)
+        assert_same_state(g, o, "sparse n=%d step %d" % (n, s))
+
+
 def test_tiny_config_200_steps_bit_exact():
     """32x64 cells, 50k particles, W = 100, seed 1, 200 steps."""
     cfg = W.config("tiny")
