@@ -416,4 +416,7 @@ class Simulation:
             self.h = None
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except Exception:  # interpreter shutdown: the module's functions may be gone
+            pass

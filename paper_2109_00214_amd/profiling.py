@@ -38,6 +38,14 @@ def source_digest(files):
     return h.hexdigest()[:16]
 
 
+def stage_line(stage, fetch_b, write_b, particles):
+    """The summary line of one roofline stage (read back by read_traffic)."""
+    k, files = STAGE_KERNELS[stage]
+    return "stage %s %s %.0f %.0f %.0f %.0f %.2f %s %s" % (
+        stage, k, fetch_b, write_b, fetch_b + write_b, particles, (fetch_b + write_b) / particles,
+        "+".join(os.path.basename(x) for x in files), source_digest(files))
+
+
 def read_traffic(path):
     """{stage: HBM bytes per particle} for the stages whose sources are unchanged."""
     out = {}
@@ -45,9 +53,10 @@ def read_traffic(path):
         return out
     for line in open(path):
         w = line.split()
-        if len(w) == 11 and w[0] == "stage" and w[1] in STAGE_KERNELS:
-            if w[10] == source_digest(STAGE_KERNELS[w[1]][1]):
-                out[w[1]] = float(w[8])
+        # stage, name, kernel, fetch, write, total, particles, B/particle, sources, digest
+        if len(w) == 10 and w[0] == "stage" and w[1] in STAGE_KERNELS:
+            if w[9] == source_digest(STAGE_KERNELS[w[1]][1]):
+                out[w[1]] = float(w[7])
     return out
 
 
@@ -120,9 +129,7 @@ def traffic_text(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, cal_bytes, 
     for s, (k, files) in STAGE_KERNELS.items():
         if k in rows:
             n, fb, wb = rows[k]
-            out.append("stage %s %s %.0f %.0f %.0f %.0f %.2f %s %s" % (
-                s, k, fb, wb, fb + wb, ppl, (fb + wb) / ppl,
-                "+".join(os.path.basename(x) for x in files), source_digest(files)))
+            out.append(stage_line(s, fb, wb, ppl))
     return "\n".join(out)
 
 

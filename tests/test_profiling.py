@@ -1,0 +1,32 @@
+"""Host logic of the profile summaries: a stage line written by the traffic
+summary is read back by the benchmark, and only while the kernel's sources
+are unchanged."""
+import os
+
+from paper_2109_00214_amd import profiling as PR
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_stage_line_round_trip(tmp_path):
+    p = tmp_path / "t.txt"
+    p.write_text("# header\n" + PR.stage_line("push", 2.0e8, 1.5e8, 3.0e6) + "\n" +
+                 PR.stage_line("deposit", 4.0e7, 8.0e6, 3.0e6) + "\n")
+    got = PR.read_traffic(str(p))
+    assert abs(got["push"] - 350.0e6 / 3.0e6) < 0.01
+    assert abs(got["deposit"] - 48.0e6 / 3.0e6) < 0.01
+
+
+def test_stale_digest_is_ignored(tmp_path):
+    line = PR.stage_line("push", 2.0e8, 1.5e8, 3.0e6).split()
+    line[-1] = "0" * 16
+    p = tmp_path / "t.txt"
+    p.write_text(" ".join(line) + "\n")
+    assert PR.read_traffic(str(p)) == {}
+
+
+def test_committed_summary_has_stage_lines():
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_paper_256x512.txt")
+    stages = [l.split() for l in open(path) if l.startswith("stage ")]
+    assert {w[1] for w in stages} == set(PR.STAGE_KERNELS)
+    assert all(len(w) == 10 for w in stages)
