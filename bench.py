@@ -30,7 +30,6 @@ def algo_bytes(F):
         # read perm + record (state, species, id) at its old place, write the
         # record and its new key at the sorted place
         "push": (4 + 5 * F + 5) + (5 * F + 5 + 4),
-        "deposit": 4 + 1 + 2 * F,                      # read perm, species, r, z
     }
 
 

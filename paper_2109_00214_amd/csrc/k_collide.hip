@@ -113,17 +113,26 @@ __device__ inline void binary(double v1[3], double v2[3], double two_dE_mr, doub
 // (T: precision of the particle record; the collision arithmetic is FP64)
 // (indices e, tc, t1 are sorted positions; the records are read in U
 // through perm)
+// Blocks from ndec on deposit the sorted state's charge into Q instead: the
+// decisions are a chain of dependent loads with few electrons, the deposit
+// a bandwidth-bound pass over the charged particles, and neither reads what
+// the other writes.
 template <typename T>
 __global__ void __launch_bounds__(256) k_decide(Flow<T> f, const uint32_t* off, const DevState* st,
                                                 Grid g, CollideParams cp, uint8_t* choice,
                                                 uint32_t* target, uint32_t* claim,
-                                                uint32_t* scan_len) {
+                                                uint32_t* scan_len, SpeciesParams spp,
+                                                unsigned long long* Q, uint32_t ndec) {
+  if (blockIdx.x >= ndec) {
+    deposit_blocks<T>(f, off, g, spp, Q, blockIdx.x - ndec, gridDim.x - ndec);
+    return;
+  }
   const PartsT<T>& P = f.U;
   const uint32_t C = g.C;
   const uint32_t n_e = off[C];
   const uint32_t step = st->step;
   if (blockIdx.x == 0 && threadIdx.x == 0) *scan_len = n_e;
-  for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < n_e; e += gridDim.x * blockDim.x) {
+  for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < n_e; e += ndec * blockDim.x) {
     const uint32_t cell = f.skey[e];
     const uint32_t pe = f.perm[e];
     const int ci = (int)(cell % (uint32_t)g.nr);
@@ -233,11 +242,20 @@ __global__ void __launch_bounds__(256) k_resolve(const uint32_t* off, DevState* 
   }
 }
 
+__device__ inline void cic_atomic(unsigned long long* Q, int b, int W, long long Z,
+                                  const long long v[4]) {
+  atomicAdd(&Q[b], (unsigned long long)(Z * v[0]));
+  atomicAdd(&Q[b + 1], (unsigned long long)(Z * v[1]));
+  atomicAdd(&Q[b + W], (unsigned long long)(Z * v[2]));
+  atomicAdd(&Q[b + W + 1], (unsigned long long)(Z * v[3]));
+}
+
 // The winners' outcomes; the created slots of a chunk start at its scanned
 // block sum, in electron order inside the block.
 template <typename T>
 __global__ void __launch_bounds__(256) k_apply(Flow<T> f, const uint32_t* off, DevState* st, Grid g,
-                                               CollideParams cp, const uint8_t* choice,
+                                               CollideParams cp, SpeciesParams spp,
+                                               unsigned long long* Q, const uint8_t* choice,
                                                const uint32_t* target, const uint32_t* ccount,
                                                const uint32_t* bsum, uint32_t* claim) {
   __shared__ uint32_t sh[4];
@@ -280,7 +298,23 @@ __global__ void __launch_bounds__(256) k_apply(Flow<T> f, const uint32_t* off, D
       }
       // stage 2 (Eq. 13): the target keeps its slot and id, changes label;
       // the new electron e2 takes the target's position and velocity
-      P.sp[pt] = (uint8_t)(ch == 1 ? 2 : (ch == 2 ? 4 : 3));
+      const int sp_old = P.sp[pt], sp_new = (ch == 1 ? 2 : (ch == 2 ? 4 : 3));
+      P.sp[pt] = (uint8_t)sp_new;
+      if (Q) {
+        // the deposit counted the target with its old charge and none of
+        // the new electrons: add the target's change with e2 (at the target)
+        // and, for e6, one electron at the primary's place
+        const long long zt = (long long)spp.Z[sp_new] - spp.Z[sp_old] + spp.Z[0];
+        long long v[4];
+        if (zt) {
+          const int b = cic_fixed<T>(g, P.r[pt], P.z[pt], v);
+          cic_atomic(Q, b, g.nr + 1, zt, v);
+        }
+        if (ch == 2) {
+          const int b = cic_fixed<T>(g, P.r[pe], P.z[pe], v);
+          cic_atomic(Q, b, g.nr + 1, (long long)spp.Z[0], v);
+        }
+      }
       double e2[3] = {A[0], A[1], A[2]};
       // stage 3 (Eq. 14): e1-e2 elastic, equal masses
       isotropic(cp, id, step, 3u, nh);
@@ -321,23 +355,31 @@ __global__ void __launch_bounds__(256) k_apply(Flow<T> f, const uint32_t* off, D
 
 template <typename T>
 void collide(const Flow<T>& P, const uint32_t* off, DevState* st, const Grid& g,
-             const CollideParams& cp, CollideWork& w, uint32_t* bsum, int64_t cap, hipStream_t s) {
+             const CollideParams& cp, const SpeciesParams& sp, int64_t* Q, CollideWork& w,
+             uint32_t* bsum, int64_t cap, hipStream_t s) {
   // grids for the electrons (a few percent of the capacity in a steady
   // state); the launches loop over whatever there is
   const int gr = grid_for(cap) < 1024 ? grid_for(cap) : 1024;
   int nb = (int)((cap + 255) / 256);
   if (nb > 1024) nb = 1024;
-  k_decide<T><<<gr, 256, 0, s>>>(P, off, st, g, cp, w.choice, w.target, w.claim, w.scan_len);
+  // deposit blocks after the decision blocks (dispatched in order)
+  int nd = 0;
+  if (Q) nd = (int)((cap + 255) / 256) < 4096 ? (int)((cap + 255) / 256) : 4096;
+  k_decide<T><<<gr + nd, 256, 0, s>>>(P, off, st, g, cp, w.choice, w.target, w.claim, w.scan_len,
+                                      sp, (unsigned long long*)Q, (uint32_t)gr);
   k_resolve<<<nb, 256, 0, s>>>(off, st, g, w.choice, w.target, w.claim, w.ccount, bsum);
   // created-electron slots: the scan of the chunk sums; its guard flags an
   // overflow and then creates nothing, so every later launch touches only
   // [0, n_alive)
   scan_block_sums(bsum, w.scan_len, &st->n_created, st, (uint32_t)cap, 256, s);
-  k_apply<T><<<nb, 256, 0, s>>>(P, off, st, g, cp, w.choice, w.target, w.ccount, bsum, w.claim);
+  k_apply<T><<<nb, 256, 0, s>>>(P, off, st, g, cp, sp, (unsigned long long*)Q, w.choice, w.target,
+                                w.ccount, bsum, w.claim);
 }
 template void collide<double>(const Flow<double>&, const uint32_t*, DevState*, const Grid&,
-                              const CollideParams&, CollideWork&, uint32_t*, int64_t, hipStream_t);
+                              const CollideParams&, const SpeciesParams&, int64_t*, CollideWork&,
+                              uint32_t*, int64_t, hipStream_t);
 template void collide<float>(const Flow<float>&, const uint32_t*, DevState*, const Grid&,
-                             const CollideParams&, CollideWork&, uint32_t*, int64_t, hipStream_t);
+                             const CollideParams&, const SpeciesParams&, int64_t*, CollideWork&,
+                             uint32_t*, int64_t, hipStream_t);
 
 }  // namespace pd

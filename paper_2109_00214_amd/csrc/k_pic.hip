@@ -14,85 +14,14 @@ static inline int grid_for(int64_t n, int block = 256) {
   return (int)g;
 }
 
-// cell and in-cell fractions: i = min((int)(r/dr), nr-1), fr = r/dr - i,
-// in the precision T of the particle record
-template <typename T>
-__device__ inline void cell_of(const Grid& g, T r, T z, int& i, int& j, T& fr, T& fz) {
-  const T xr = r / (T)g.dr, xz = z / (T)g.dz;
-  i = (int)xr;
-  j = (int)xz;
-  if (i > g.nr - 1) i = g.nr - 1;
-  if (j > g.nz - 1) j = g.nz - 1;
-  fr = xr - (T)i;
-  fz = xz - (T)j;
-}
-
 // ---------------------------------------------------------------------------
-// deposit: weights rounded to 2^-20 per dimension, complementary, so each
-// particle adds exactly Z * 2^40 to the four nodes of its cell
-// The particles are sorted by (species, cell), so neighbouring lanes mostly
-// share a cell: each wave sums the contributions of every run of equal cells
-// (a segmented suffix sum over the lanes) and only the first lane of a run
-// issues the four int64 atomics.  Integer addition is associative, so the
-// node charges do not depend on this grouping.  Waves holding only neutral
-// particles (the long Cu run of the species-major order) read the species
-// byte and nothing else.  (The Cu run cannot be skipped by offsets alone:
-// collisions ionize targets inside it in place.)  In the FP32 form the
-// fractions come from the FP32 positions; the rounding to 2^-20 is the
-// same, so the node charges stay exact integers.
-// (sorted position p: the record is U[perm[p]] for the live particles, S[p]
-// for the electrons created this step)
+// deposit on its own (no collisions this step); with collisions the same
+// blocks run inside the decisions' launch
 template <typename T>
-__global__ void __launch_bounds__(256) k_deposit(Flow<T> f, const DevState* st, Grid g,
-                                                 SpeciesParams spp, unsigned long long* Q) {
-  const uint32_t n_alive = st->n_alive;
-  const uint32_t n = n_alive + st->n_created;
-  const int W = g.nr + 1;
-  const int lane = threadIdx.x & 63;
-  const uint64_t upto = (lane == 63) ? 0ull : (~0ull << (lane + 1));  // lanes above this one
-  for (uint32_t q0 = blockIdx.x * blockDim.x; q0 < n; q0 += gridDim.x * blockDim.x) {
-    const uint32_t p = q0 + threadIdx.x;
-    const bool old = p < n_alive;
-    const uint32_t q = old ? f.perm[p] : p;
-    const PartsT<T>& P = old ? f.U : f.S;
-    const long long Zp = (p < n) ? spp.Z[P.sp[q]] : 0;
-    if (!__ballot(Zp != 0)) continue;
-    int b = -1;
-    long long v0 = 0, v1 = 0, v2 = 0, v3 = 0;
-    if (Zp != 0) {
-      int i, j;
-      T fr, fz;
-      cell_of<T>(g, P.r[q], P.z[q], i, j, fr, fz);
-      const long long ar = (long long)floor((fr * (T)1048576) + (T)0.5), br = 1048576 - ar;
-      const long long az = (long long)floor((fz * (T)1048576) + (T)0.5), bz = 1048576 - az;
-      b = j * W + i;
-      v0 = Zp * (br * bz);
-      v1 = Zp * (ar * bz);
-      v2 = Zp * (br * az);
-      v3 = Zp * (ar * az);
-    }
-    const int bprev = __shfl_up(b, 1, 64);
-    const bool head = (lane == 0) || (b != bprev);
-    const uint64_t later = __ballot(head) & upto;
-    const int end = later ? (__ffsll((long long)later) - 1) : 64;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const long long t0 = __shfl_down(v0, o, 64), t1 = __shfl_down(v1, o, 64);
-      const long long t2 = __shfl_down(v2, o, 64), t3 = __shfl_down(v3, o, 64);
-      if (lane + o < end) {
-        v0 += t0;
-        v1 += t1;
-        v2 += t2;
-        v3 += t3;
-      }
-    }
-    if (head && b >= 0) {
-      if (v0) atomicAdd(&Q[b], (unsigned long long)v0);
-      if (v1) atomicAdd(&Q[b + 1], (unsigned long long)v1);
-      if (v2) atomicAdd(&Q[b + W], (unsigned long long)v2);
-      if (v3) atomicAdd(&Q[b + W + 1], (unsigned long long)v3);
-    }
-  }
+__global__ void __launch_bounds__(256) k_deposit(Flow<T> f, const uint32_t* __restrict__ off,
+                                                 Grid g, SpeciesParams spp,
+                                                 unsigned long long* Q) {
+  deposit_blocks<T>(f, off, g, spp, Q, blockIdx.x, gridDim.x);
 }
 
 __global__ void k_fill_i64(int64_t* p, int64_t v, int64_t n) {
@@ -113,14 +42,14 @@ void fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
 }
 
 template <typename T>
-void deposit(const Flow<T>& f, const DevState* st, const Grid& g, const SpeciesParams& sp,
+void deposit(const Flow<T>& f, const uint32_t* off, const Grid& g, const SpeciesParams& sp,
              int64_t* Q, int64_t cap, hipStream_t s) {
   // Q was cleared by the offsets launch
-  k_deposit<T><<<grid_for(cap), 256, 0, s>>>(f, st, g, sp, (unsigned long long*)Q);
+  k_deposit<T><<<grid_for(cap), 256, 0, s>>>(f, off, g, sp, (unsigned long long*)Q);
 }
-template void deposit<double>(const Flow<double>&, const DevState*, const Grid&,
+template void deposit<double>(const Flow<double>&, const uint32_t*, const Grid&,
                               const SpeciesParams&, int64_t*, int64_t, hipStream_t);
-template void deposit<float>(const Flow<float>&, const DevState*, const Grid&,
+template void deposit<float>(const Flow<float>&, const uint32_t*, const Grid&,
                              const SpeciesParams&, int64_t*, int64_t, hipStream_t);
 
 // E = -grad(phi): central differences, second-order one-sided at the

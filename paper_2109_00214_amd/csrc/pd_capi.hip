@@ -551,10 +551,21 @@ pd_status enqueue_step(pd_ctx* c, PartsT<T>& A, PartsT<T>& B, int64_t nn, Mark& 
   build_offsets(c->sw, c->st, c->off, c->g.sentinel + 1, c->fw.Q, (uint32_t)nn, s);
   const Flow<T> f{A, B, c->sw.perm, c->sw.skey};
   mark();
-  if (!c->opts.collisions_off) collide(f, c->off, c->st, c->g, c->cpar, c->cw, c->sw.bsum, c->cap, s);
+  // The deposit reads only what the collisions leave alone (positions, the
+  // sort's keys and permutation), and the collisions add their charge
+  // changes with integer atomics: with collisions, the deposit runs as extra
+  // blocks of the collision decisions' launch (which is bound by latency,
+  // not by bandwidth), otherwise on its own.
+  int64_t* Qd = c->opts.deposit_off ? nullptr : c->fw.Q;
+  if (!c->opts.collisions_off)
+    collide(f, c->off, c->st, c->g, c->cpar, c->spp, Qd, c->cw, c->sw.bsum, c->cap, s);
   mark();
-  if (!c->opts.deposit_off) deposit(f, c->st, c->g, c->spp, c->fw.Q, c->cap, s);
-  mark();
+  if (c->opts.collisions_off && !c->opts.deposit_off) {
+    deposit(f, c->off, c->g, c->spp, c->fw.Q, c->cap, s);
+    mark();
+  } else {
+    mark(true);  // inside the collisions' stage
+  }
   pd_status ps = solve_poisson(c);
   if (ps) return ps;
   mark();

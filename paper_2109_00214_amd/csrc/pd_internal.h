@@ -93,6 +93,111 @@ struct Schedule {
   const uint8_t* sp;
 };
 
+// cell and in-cell fractions: i = min((int)(r/dr), nr-1), fr = r/dr - i,
+// in the precision T of the particle record
+template <typename T>
+__device__ inline void cell_of(const Grid& g, T r, T z, int& i, int& j, T& fr, T& fz) {
+  const T xr = r / (T)g.dr, xz = z / (T)g.dz;
+  i = (int)xr;
+  j = (int)xz;
+  if (i > g.nr - 1) i = g.nr - 1;
+  if (j > g.nz - 1) j = g.nz - 1;
+  fr = xr - (T)i;
+  fz = xz - (T)j;
+}
+
+// Fixed-point cloud-in-cell share of a unit charge at (r, z) (paper Eqs.
+// 9-10): the 1D weights rounded to 2^-20, complementary, so the four node
+// shares v[0..3] (nodes b, b+1, b+nr+1, b+nr+2) are exact integers adding
+// up to 2^40.  Returns b.
+template <typename T>
+__device__ inline int cic_fixed(const Grid& g, T r, T z, long long v[4]) {
+  int i, j;
+  T fr, fz;
+  cell_of<T>(g, r, z, i, j, fr, fz);
+  const long long ar = (long long)floor((fr * (T)1048576) + (T)0.5), br = 1048576 - ar;
+  const long long az = (long long)floor((fz * (T)1048576) + (T)0.5), bz = 1048576 - az;
+  v[0] = br * bz;
+  v[1] = ar * bz;
+  v[2] = br * az;
+  v[3] = ar * az;
+  return j * (g.nr + 1) + i;
+}
+
+// deposit: weights rounded to 2^-20 per dimension, complementary, so each
+// particle adds exactly Z * 2^40 to the four nodes of its cell
+// The deposit covers the sorted state before this step's collisions: the
+// charged species' ranges of the sorted order (the offsets give them; the
+// neutral run is not read at all), each particle with the charge of the
+// species in its sort key.  The collisions add what their outcomes change
+// (an ionization moves charge only when the new electrons do not sit where
+// the charge appeared).  Neighbouring lanes mostly share a cell: each wave
+// sums the contributions of every run of equal cells (a segmented suffix
+// sum over the lanes) and only the first lane of a run issues the four
+// int64 atomics.  Integer addition is associative, so the node charges do
+// not depend on this grouping or on the order of the collisions' additions.
+// In the FP32 form the fractions come from the FP32 positions; the rounding
+// to 2^-20 is the same, so the node charges stay exact integers.
+// (blocks blk = 0 .. nblk-1 of a 256-thread launch share the work)
+template <typename T>
+__device__ inline void deposit_blocks(const Flow<T>& f, const uint32_t* __restrict__ off,
+                                      const Grid& g, const SpeciesParams& spp,
+                                      unsigned long long* Q, uint32_t blk, uint32_t nblk) {
+  // the charged species' ranges laid end to end: cum[s] charged particles
+  // before species s, its range starting at lo[s]
+  uint32_t lo[kNS], cum[kNS + 1];
+  cum[0] = 0;
+#pragma unroll
+  for (int s = 0; s < kNS; ++s) {
+    lo[s] = off[(uint32_t)s * g.C];
+    const uint32_t hi = off[(uint32_t)(s + 1) * g.C];
+    cum[s + 1] = cum[s] + ((spp.Z[s] != 0) ? hi - lo[s] : 0u);
+  }
+  const uint32_t n = cum[kNS];
+  const int W = g.nr + 1;
+  const int lane = threadIdx.x & 63;
+  const uint64_t upto = (lane == 63) ? 0ull : (~0ull << (lane + 1));  // lanes above this one
+  for (uint32_t q0 = blk * blockDim.x; q0 < n; q0 += nblk * blockDim.x) {
+    const uint32_t q = q0 + threadIdx.x;
+    int b = -1;
+    long long v[4] = {0, 0, 0, 0};
+    if (q < n) {
+      uint32_t p = 0;
+      long long Zp = 0;
+#pragma unroll
+      for (int s = 0; s < kNS; ++s)
+        if (q >= cum[s] && q < cum[s + 1]) {
+          p = lo[s] + (q - cum[s]);
+          Zp = spp.Z[s];
+        }
+      const uint32_t u = f.perm[p];
+      b = cic_fixed<T>(g, f.U.r[u], f.U.z[u], v);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) v[k] *= Zp;
+    }
+    const int bprev = __shfl_up(b, 1, 64);
+    const bool head = (lane == 0) || (b != bprev);
+    const uint64_t later = __ballot(head) & upto;
+    const int end = later ? (__ffsll((long long)later) - 1) : 64;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      long long t[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) t[k] = __shfl_down(v[k], o, 64);
+      if (lane + o < end) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] += t[k];
+      }
+    }
+    if (head && b >= 0) {
+      if (v[0]) atomicAdd(&Q[b], (unsigned long long)v[0]);
+      if (v[1]) atomicAdd(&Q[b + 1], (unsigned long long)v[1]);
+      if (v[2]) atomicAdd(&Q[b + W], (unsigned long long)v[2]);
+      if (v[3]) atomicAdd(&Q[b + W + 1], (unsigned long long)v[3]);
+    }
+  }
+}
+
 // ---- sort (k_sort.hip) ----
 constexpr int kSortBlock = 256;
 constexpr int kSortItems = 16;
@@ -170,10 +275,12 @@ struct CollideWork {
   uint32_t *target, *claim, *ccount, *scan_len;
   int64_t cap;
 };
+// Q: the node charge the deposit of the sorted state goes to (NULL when
+// there is no deposit): the apply adds what the outcomes change in it.
 template <typename T>
 void collide(const Flow<T>& f, const uint32_t* off, DevState* st, const Grid& g,
-             const CollideParams& cp, CollideWork& w, uint32_t* bsum, int64_t cap,
-             hipStream_t s);
+             const CollideParams& cp, const SpeciesParams& sp, int64_t* Q, CollideWork& w,
+             uint32_t* bsum, int64_t cap, hipStream_t s);
 
 // ---- particle-in-cell (k_pic.hip) ----
 struct FieldWork {
@@ -194,8 +301,10 @@ struct FieldWork {
   const double* cT;     // [(nz-1) * (nr+1)] Thomas upper factors, r fastest
   const double* coef;   // [nr+1] -qunit / (V_node eps0)
 };
+// Node charge of the sorted state: every particle of a charged species with
+// the species of its sort key (before this step's collisions), through perm.
 template <typename T>
-void deposit(const Flow<T>& f, const DevState* st, const Grid& g, const SpeciesParams& sp,
+void deposit(const Flow<T>& f, const uint32_t* off, const Grid& g, const SpeciesParams& sp,
              int64_t* Q, int64_t cap, hipStream_t s);
 void poisson_direct(const Grid& g, FieldWork& fw, hipStream_t s);
 size_t poisson_lds_bytes(int nr, int nz);

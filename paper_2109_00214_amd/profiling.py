@@ -27,7 +27,6 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # stage -> (kernel name, sources that define it)
 STAGE_KERNELS = {
     "push": ("pd::k_push<double>", ("csrc/k_pic.hip", "csrc/pd_internal.h")),
-    "deposit": ("pd::k_deposit<double>", ("csrc/k_pic.hip", "csrc/pd_internal.h")),
 }
 
 

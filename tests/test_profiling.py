@@ -10,11 +10,9 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def test_stage_line_round_trip(tmp_path):
     p = tmp_path / "t.txt"
-    p.write_text("# header\n" + PR.stage_line("push", 2.0e8, 1.5e8, 3.0e6) + "\n" +
-                 PR.stage_line("deposit", 4.0e7, 8.0e6, 3.0e6) + "\n")
+    p.write_text("# header\n" + PR.stage_line("push", 2.0e8, 1.5e8, 3.0e6) + "\n")
     got = PR.read_traffic(str(p))
     assert abs(got["push"] - 350.0e6 / 3.0e6) < 0.01
-    assert abs(got["deposit"] - 48.0e6 / 3.0e6) < 0.01
 
 
 def test_stale_digest_is_ignored(tmp_path):
