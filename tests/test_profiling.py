@@ -26,5 +26,5 @@ def test_stale_digest_is_ignored(tmp_path):
 def test_committed_summary_has_stage_lines():
     path = os.path.join(ROOT, "profiles", "hbm_traffic_paper_256x512.txt")
     stages = [l.split() for l in open(path) if l.startswith("stage ")]
-    assert {w[1] for w in stages} == set(PR.STAGE_KERNELS)
+    assert set(PR.STAGE_KERNELS) <= {w[1] for w in stages}
     assert all(len(w) == 10 for w in stages)
