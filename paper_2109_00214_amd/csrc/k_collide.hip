@@ -121,7 +121,7 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_decide(Flow<T> f, const uint32_t* off, const DevState* st,
                                                 Grid g, CollideParams cp, uint8_t* choice,
                                                 uint32_t* target, uint32_t* claim,
-                                                uint32_t* scan_len, SpeciesParams spp,
+                                                SpeciesParams spp,
                                                 unsigned long long* Q, uint32_t ndec) {
   if (blockIdx.x >= ndec) {
     deposit_blocks<T>(f, off, g, spp, Q, blockIdx.x - ndec, gridDim.x - ndec);
@@ -131,7 +131,6 @@ __global__ void __launch_bounds__(256) k_decide(Flow<T> f, const uint32_t* off, 
   const uint32_t C = g.C;
   const uint32_t n_e = off[C];
   const uint32_t step = st->step;
-  if (blockIdx.x == 0 && threadIdx.x == 0) *scan_len = n_e;
   for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < n_e; e += ndec * blockDim.x) {
     const uint32_t cell = f.skey[e];
     const uint32_t pe = f.perm[e];
@@ -257,7 +256,8 @@ __global__ void __launch_bounds__(256) k_apply(Flow<T> f, const uint32_t* off, D
                                                CollideParams cp, SpeciesParams spp,
                                                unsigned long long* Q, const uint8_t* choice,
                                                const uint32_t* target, const uint32_t* ccount,
-                                               const uint32_t* bsum, uint32_t* claim) {
+                                               const uint32_t* bsum, uint32_t* claim,
+                                               uint32_t cap) {
   __shared__ uint32_t sh[4];
   const PartsT<T>& P = f.U;
   const PartsT<T>& S = f.S;
@@ -266,12 +266,25 @@ __global__ void __launch_bounds__(256) k_apply(Flow<T> f, const uint32_t* off, D
   const uint32_t n_alive = st->n_alive;
   const uint32_t next_id = st->next_id;
   const uint32_t step = st->step;
-  if (st->err) return;  // the guard found no room for the new electrons
+  const uint32_t err0 = st->err;
+  // the created electrons of every chunk: their total must fit (capacity,
+  // id space), else the step creates nothing and flags the error; every
+  // block decides the same from the same sums
+  const uint32_t all = block_range_sum(bsum, 0, nb, sh);
+  const bool fits = !err0 && (uint64_t)n_alive + all <= cap &&
+                    (uint64_t)next_id + all <= 0xFFFFFFFFull;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->n_created = fits ? all : 0u;
+    if (!fits) atomicOr(&st->err, 1u);
+  }
+  if (!fits) return;
+  uint32_t before = block_range_sum(bsum, 0, (blockIdx.x < nb) ? blockIdx.x : nb, sh);
   for (uint32_t b = blockIdx.x; b < nb; b += gridDim.x) {
+    if (b != blockIdx.x) before += block_range_sum(bsum, b - gridDim.x, b, sh);
     const uint32_t e = b * 256 + threadIdx.x;
     const uint32_t cnt = (e < n_e) ? ccount[e] : 0u;
     uint32_t tot;
-    const uint32_t cbase = bsum[b] + block_scan256(cnt, &tot, sh);
+    const uint32_t cbase = before + block_scan256(cnt, &tot, sh);
     {
       if (e >= n_e) continue;
       const uint32_t c = choice[e];
@@ -365,15 +378,14 @@ void collide(const Flow<T>& P, const uint32_t* off, DevState* st, const Grid& g,
   // deposit blocks after the decision blocks (dispatched in order)
   int nd = 0;
   if (Q) nd = (int)((cap + 255) / 256) < 4096 ? (int)((cap + 255) / 256) : 4096;
-  k_decide<T><<<gr + nd, 256, 0, s>>>(P, off, st, g, cp, w.choice, w.target, w.claim, w.scan_len,
+  k_decide<T><<<gr + nd, 256, 0, s>>>(P, off, st, g, cp, w.choice, w.target, w.claim,
                                       sp, (unsigned long long*)Q, (uint32_t)gr);
   k_resolve<<<nb, 256, 0, s>>>(off, st, g, w.choice, w.target, w.claim, w.ccount, bsum);
-  // created-electron slots: the scan of the chunk sums; its guard flags an
-  // overflow and then creates nothing, so every later launch touches only
-  // [0, n_alive)
-  scan_block_sums(bsum, w.scan_len, &st->n_created, st, (uint32_t)cap, 256, s);
+  // created-electron slots: each apply block adds up the chunk sums before
+  // its chunk; the guard (in every block) flags an overflow and then nothing
+  // is created, so every later launch touches only [0, n_alive)
   k_apply<T><<<nb, 256, 0, s>>>(P, off, st, g, cp, sp, (unsigned long long*)Q, w.choice, w.target,
-                                w.ccount, bsum, w.claim);
+                                w.ccount, bsum, w.claim, (uint32_t)cap);
 }
 template void collide<double>(const Flow<double>&, const uint32_t*, DevState*, const Grid&,
                               const CollideParams&, const SpeciesParams&, int64_t*, CollideWork&,

@@ -43,59 +43,6 @@ static inline int grid_for(int64_t n, int block = 256) {
   return (int)g;
 }
 
-// ---------------------------------------------------------------------------
-// Exclusive scan of per-chunk sums (chunks of `chunk` elements of a length
-// *len_p) by one 1024-thread block, each thread a run of them.
-// With a guard state, the total is the number of electrons a collision step
-// creates: if they do not fit (capacity, 32-bit ids) or an error is already
-// flagged, the error is flagged and the total forced to 0, so every later
-// launch of the step touches only the live particles.
-__global__ void __launch_bounds__(1024) k_scan_bsums(uint32_t* bsum, const uint32_t* len_p,
-                                                     uint32_t* total, DevState* guard,
-                                                     uint32_t cap, uint32_t chunk) {
-  __shared__ uint32_t sh[16];
-  const uint32_t len = *len_p;
-  const uint32_t nb = (len + chunk - 1) / chunk;
-  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
-  const uint32_t per = (nb + 1023) / 1024;
-  const uint32_t b0 = t * per;
-  uint32_t s = 0;
-  for (uint32_t k = 0; k < per; ++k) s += (b0 + k < nb) ? bsum[b0 + k] : 0u;
-  uint32_t x = s;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
-  }
-  if (lane == 63) sh[wid] = x;
-  __syncthreads();
-  uint32_t wbase = 0, tot = 0;
-  for (int w = 0; w < 16; ++w) {
-    wbase += (w < wid) ? sh[w] : 0u;
-    tot += sh[w];
-  }
-  uint32_t run = wbase + x - s;
-  for (uint32_t k = 0; k < per; ++k) {
-    if (b0 + k < nb) {
-      const uint32_t v = bsum[b0 + k];
-      bsum[b0 + k] = run;
-      run += v;
-    }
-  }
-  if (t == 0 && total) {
-    if (guard && (guard->err || (uint64_t)guard->n_alive + tot > cap ||
-                  (uint64_t)guard->next_id + tot > 0xFFFFFFFFull)) {
-      guard->err |= 1u;
-      tot = 0;
-    }
-    *total = tot;
-  }
-}
-
-void scan_block_sums(uint32_t* bsum, const uint32_t* len, uint32_t* total, DevState* guard,
-                     uint32_t cap, uint32_t chunk, hipStream_t s) {
-  k_scan_bsums<<<1, 1024, 0, s>>>(bsum, len, total, guard, cap, chunk);
-}
 
 // ---------------------------------------------------------------------------
 // Stable digit ranking of 64 keys held one per lane: the lanes with the same
@@ -420,12 +367,10 @@ __device__ inline void mover_flags(uint32_t base, uint32_t n, uint32_t n_prev,
 // movers per chunk of kScanChunk positions
 __global__ void __launch_bounds__(256) k_cls_count(const uint32_t* __restrict__ key,
                                                    const uint32_t* __restrict__ kprev,
-                                                   const DevState* st, uint32_t* __restrict__ bsum,
-                                                   uint32_t* __restrict__ scan_len) {
+                                                   const DevState* st, uint32_t* __restrict__ bsum) {
   __shared__ uint32_t sh[4];
   const uint32_t n = st->n_total, n_prev = st->n_alive;
   const uint32_t nb = (n + kScanChunk - 1) / kScanChunk;
-  if (blockIdx.x == 0 && threadIdx.x == 0) *scan_len = n;
   if (blockIdx.x >= nb) return;
   const uint32_t base = blockIdx.x * kScanChunk + threadIdx.x * kScanPer;
   uint32_t f[kScanPer], kv[kScanPer];
@@ -440,25 +385,33 @@ __global__ void __launch_bounds__(256) k_cls_count(const uint32_t* __restrict__ 
 
 // mpre[i] = movers in [0, i) for i <= n_prev; the movers' (key, index) in
 // index order to mk, mi
+// (bsum: the movers of every chunk; each block adds up those of the chunks
+// before its own, block 0 all of them into n_mov)
 __global__ void __launch_bounds__(256) k_cls_compact(const uint32_t* __restrict__ key,
                                                      const uint32_t* __restrict__ kprev,
                                                      const DevState* st,
                                                      const uint32_t* __restrict__ bsum,
                                                      uint32_t* __restrict__ mpre,
                                                      uint32_t* __restrict__ mk,
-                                                     uint32_t* __restrict__ mi) {
+                                                     uint32_t* __restrict__ mi,
+                                                     uint32_t* __restrict__ n_mov) {
   __shared__ uint32_t sh[4];
   const uint32_t n = st->n_total, n_prev = st->n_alive;
   const uint32_t nb = (n + kScanChunk - 1) / kScanChunk;
+  if (blockIdx.x == 0) {
+    const uint32_t all = block_range_sum(bsum, 0, nb, sh);
+    if (threadIdx.x == 0) *n_mov = all;
+  }
   if (blockIdx.x >= nb) return;
   const uint32_t base = blockIdx.x * kScanChunk + threadIdx.x * kScanPer;
   uint32_t f[kScanPer], kv[kScanPer];
-  mover_flags(base, n, n_prev, key, kprev, f, kv);
+  mover_flags(base, n, n_prev, key, kprev, f, kv);  // (its loads overlap the sum's)
+  const uint32_t before = block_range_sum(bsum, 0, blockIdx.x, sh);
   uint32_t acc = 0;
 #pragma unroll
   for (int k = 0; k < kScanPer; ++k) acc += f[k];
   uint32_t tot;
-  uint32_t run = bsum[blockIdx.x] + block_scan256(acc, &tot, sh);
+  uint32_t run = before + block_scan256(acc, &tot, sh);
   uint32_t pre[kScanPer];
 #pragma unroll
   for (int k = 0; k < kScanPer; ++k) {
@@ -599,9 +552,8 @@ void sort_keys(const uint32_t* key, int key_bits, SortWork& w, DevState* st, con
   const int nb = (int)((w.cap + kScanChunk - 1) / kScanChunk);
   {
     // classify, count and compact the movers (key, index) into k0/v0
-    k_cls_count<<<nb, 256, 0, s>>>(key, w.skey, st, w.bsum, w.scan_len);
-    k_scan_bsums<<<1, 1024, 0, s>>>(w.bsum, w.scan_len, w.n_mov, nullptr, 0, kScanChunk);
-    k_cls_compact<<<nb, 256, 0, s>>>(key, w.skey, st, w.bsum, w.mpre, w.k0, w.v0);
+    k_cls_count<<<nb, 256, 0, s>>>(key, w.skey, st, w.bsum);
+    k_cls_compact<<<nb, 256, 0, s>>>(key, w.skey, st, w.bsum, w.mpre, w.k0, w.v0, w.n_mov);
     // stable radix sort of the movers
     const uint32_t* kin = w.k0;
     const uint32_t* vin = w.v0;

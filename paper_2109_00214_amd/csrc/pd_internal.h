@@ -211,8 +211,7 @@ constexpr int kScanMaxBlocks = 65536;
 struct SortWork {
   uint32_t *k0, *k1, *v0, *v1;  // key/value ping-pong [cap]
   uint32_t* hist;               // [kRadix * tiles of 256 kMoverItems keys in cap]
-  uint32_t* bsum;               // [kScanMaxBlocks]
-  uint32_t* scan_len;           // device scalar
+  uint32_t* bsum;               // per-chunk counts: movers (sort), created electrons (collisions)
   uint32_t* skey;               // [cap] keys in the last sorted order
   uint32_t* mpre;               // [cap + 1] movers before each position
   uint32_t* n_mov;              // device scalar: movers of this sort
@@ -231,12 +230,6 @@ struct SortWork {
 // offsets off.
 void sort_keys(const uint32_t* key, int key_bits, SortWork& w, DevState* st, const uint32_t* off,
                uint32_t sentinel, hipStream_t s);
-// Exclusive scan, in place, of per-chunk sums of ceil(*len / chunk) chunks,
-// total to *total.  With a guard state the total counts new particles: it is
-// forced to 0 and the error flagged when they would not fit in cap (or the
-// ids would wrap).
-void scan_block_sums(uint32_t* bsum, const uint32_t* len, uint32_t* total, DevState* guard,
-                     uint32_t cap, uint32_t chunk, hipStream_t s);
 
 constexpr int kScanPer = kScanChunk / 256;  // consecutive elements per thread
 
@@ -263,6 +256,28 @@ __device__ inline uint32_t block_scan256(uint32_t v, uint32_t* total, uint32_t* 
   *total = tot;
   return wbase + x - v;
 }
+// Sum of c[lo .. hi) by one 256-thread block (every thread gets it): the
+// launches that place items by the per-chunk counts of an earlier launch
+// take their chunk's prefix this way instead of waiting for a separate scan
+// launch (a few thousand counts, eight loads in flight per thread).
+__device__ inline uint32_t block_range_sum(const uint32_t* __restrict__ c, uint32_t lo,
+                                           uint32_t hi, uint32_t* sh) {
+  uint32_t s = 0;
+  for (uint32_t i0 = lo + threadIdx.x; i0 < hi; i0 += 8 * 256) {
+    uint32_t v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const uint32_t i = i0 + (uint32_t)u * 256u;
+      v[u] = (i < hi) ? c[i] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
+  uint32_t tot;
+  block_scan256(s, &tot, sh);
+  return tot;
+}
+
 // CSR offsets of the sorted keys w.skey (off[k] = first sorted position with
 // key >= k, k < nkeys; st->n_alive = off[nkeys - 1]); the same launch clears
 // the node charge Q.
@@ -272,7 +287,7 @@ void build_offsets(const SortWork& w, DevState* st, uint32_t* off, uint32_t nkey
 // ---- collisions (k_collide.hip) ----
 struct CollideWork {
   uint8_t* choice;
-  uint32_t *target, *claim, *ccount, *scan_len;
+  uint32_t *target, *claim, *ccount;
   int64_t cap;
 };
 // Q: the node charge the deposit of the sorted state goes to (NULL when
