@@ -150,20 +150,11 @@ __global__ void __launch_bounds__(64 * kColWaves) k_radix_colscan(uint32_t* __re
   }
 }
 
-// Sorted movers sampled for the merge: every stride-th, stride a power of
-// two >= 64 that keeps the sample within kPlaceSamples entries.
-constexpr int kPlaceSamples = 2048;
-__host__ __device__ inline uint32_t sample_stride(uint32_t n) {
-  uint32_t s = 64;
-  while ((uint64_t)s * kPlaceSamples < n) s <<= 1;
-  return s;
-}
-
 // What the last pass over the movers needs to place them: a mover of
 // sorted rank r with (key k, index i) goes to ins + r, ins = stayers before
 // it = p - mpre[p] with p = i clamped to the old run of key k
 // [off_prev[k], off_prev[k+1]] (all stayers for the sentinel key).  ins is
-// kept per rank (non-decreasing) with a sample for the stayers' searches.
+// kept per rank (non-decreasing) for the stayers' searches.
 struct MoverPlace {
   const uint32_t* off_prev;
   const uint32_t* mpre;
@@ -172,7 +163,6 @@ struct MoverPlace {
   uint32_t* skey;
   uint32_t* perm;
   uint32_t* ins;
-  uint32_t* samp;  // every stride-th ins
 };
 
 __device__ inline uint32_t stayers_before(const MoverPlace& mp, uint32_t n_prev, uint32_t k,
@@ -300,7 +290,6 @@ __global__ void __launch_bounds__(256) k_radix_down(const uint32_t* __restrict__
     } else {
       // last pass: place the movers (p = final rank among the movers)
       const uint32_t n_prev = mp.st->n_alive;
-      const uint32_t smask = sample_stride(n) - 1u;
 #pragma unroll 4
       for (uint32_t q = t; q < cnt; q += 256) {
         const uint32_t k = tkey[q], i = tval[q];
@@ -309,7 +298,6 @@ __global__ void __launch_bounds__(256) k_radix_down(const uint32_t* __restrict__
         mp.ins[p] = ins;
         mp.skey[ins + p] = k;
         mp.perm[ins + p] = i;
-        if ((p & smask) == 0) mp.samp[p / (smask + 1u)] = ins;
       }
     }
     __syncthreads();
@@ -320,17 +308,17 @@ __global__ void __launch_bounds__(256) k_radix_down(const uint32_t* __restrict__
 // for the movers, which are usually few)
 template <int DB, int IT>
 static void radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
-                       int shift, SortWork& w, const uint32_t* np, const MoverPlace& samp,
+                       int shift, SortWork& w, const uint32_t* np, const MoverPlace& mp,
                        hipStream_t s) {
   constexpr int R = 1 << DB;
   k_radix_up<DB, IT><<<tile_grid(w.cap, 2, 256 * IT), 256, 0, s>>>(kin, np, shift, w.hist);
   k_radix_colscan<R, IT><<<R / 64, 64 * kColWaves, 0, s>>>(w.hist, w.bsum, np);
   if (!vin)
     k_radix_down<DB, IT, true><<<tile_grid(w.cap, 2, 256 * IT), 256, 0, s>>>(
-        kin, vin, kout, vout, np, shift, w.hist, w.bsum, samp);
+        kin, vin, kout, vout, np, shift, w.hist, w.bsum, mp);
   else
     k_radix_down<DB, IT, false><<<tile_grid(w.cap, 2, 256 * IT), 256, 0, s>>>(
-        kin, vin, kout, vout, np, shift, w.hist, w.bsum, samp);
+        kin, vin, kout, vout, np, shift, w.hist, w.bsum, mp);
 }
 
 // ---- stayers and movers ---------------------------------------------------
@@ -446,67 +434,56 @@ __device__ inline uint32_t movers_upto(const uint32_t* __restrict__ ins, uint32_
   }
   return lo;
 }
-// the same over all nm movers, through the sample (entry j = ins[j stride])
-__device__ inline uint32_t movers_upto_sampled(const uint32_t* __restrict__ ins,
-                                               const uint32_t* __restrict__ samp, uint32_t nm,
-                                               uint32_t s) {
-  const uint32_t stride = sample_stride(nm);
-  uint32_t lo = 0, hi = (nm + stride - 1) / stride;
-  while (lo < hi) {
-    const uint32_t mid = (lo + hi) >> 1;
-    if (samp[mid] <= s) lo = mid + 1;
-    else hi = mid;
-  }
-  if (lo == 0) return 0;
-  const uint32_t a = (lo - 1) * stride + 1;
-  const uint32_t b = (lo * stride < nm) ? lo * stride : nm;
-  return movers_upto(ins, a, b, s);
-}
-
 // Stayers' places, in chunks of kPlaceChunk old positions: the stayer of
 // rank s goes to s + (movers with ins <= s).  Chunk ch holds the stayer
 // ranks [s0(ch), s0(ch+1)), s0(ch) = base - mpre[base], so the movers it
 // needs are those of ranks [bound(ch), bound(ch+1)), bound(ch) = the count
-// for s0(ch): one search per chunk boundary (k_place_bounds), then the
-// chunk searches only its own movers, staged in LDS.
+// for s0(ch): two searches per chunk, then the chunk searches only its own
+// movers, staged in LDS.
 constexpr int kPlaceChunk = 1024;
 constexpr int kPlaceLds = 2048;
 
-// The merge's searches, one thread per chunk boundary of old positions.
-__global__ void __launch_bounds__(256) k_place_bounds(const DevState* st,
-                                                      const uint32_t* __restrict__ mpre,
-                                                      const uint32_t* __restrict__ ins,
-                                                      const uint32_t* __restrict__ samp,
-                                                      const uint32_t* __restrict__ n_mov,
-                                                      uint32_t* __restrict__ bound) {
-  const uint32_t n_prev = st->n_alive, nm = *n_mov;
-  const uint32_t nch = (n_prev + kPlaceChunk - 1) / kPlaceChunk;
-  for (uint32_t ch = blockIdx.x * blockDim.x + threadIdx.x; ch <= nch;
-       ch += gridDim.x * blockDim.x) {
-    const uint32_t base = (ch * kPlaceChunk < n_prev) ? ch * kPlaceChunk : n_prev;
-    bound[ch] = movers_upto_sampled(ins, samp, nm, base - mpre[base]);
+// movers m with ins[m] <= s (ins is non-decreasing): the whole wave, a
+// 64-way search (each step probes 64 places, about log_65(nm) steps of one
+// load)
+__device__ inline uint32_t movers_upto_wave(const uint32_t* __restrict__ ins, uint32_t nm,
+                                            uint32_t s, int lane) {
+  uint32_t lo = 0, hi = nm;  // the answer is in [lo, hi]
+  while (hi > lo) {
+    const uint64_t r = hi - lo;
+    const uint32_t p = lo + (uint32_t)((r * (uint64_t)(lane + 1)) / 65u);  // < hi
+    const unsigned long long bt = __ballot(ins[p] > s);
+    if (bt == 0ull) {
+      lo = __shfl(p, 63, 64) + 1u;
+    } else {
+      const int f = __ffsll((long long)bt) - 1;
+      const uint32_t pf = __shfl(p, f, 64);
+      const uint32_t pb = __shfl(p, f > 0 ? f - 1 : 0, 64);
+      hi = pf;
+      if (f > 0) lo = pb + 1u;
+    }
   }
+  return lo;
 }
 
+// Each block finds its chunk's mover range itself: waves 0 and 1 search for
+// the movers placed before the chunk's first stayer and before the next
+// chunk's (s0 = the chunk start minus the movers before it).
 __global__ void __launch_bounds__(256) k_place(const uint32_t* __restrict__ key,
                                                const DevState* st,
                                                const uint32_t* __restrict__ mpre,
                                                const uint32_t* __restrict__ ins,
-                                               const uint32_t* __restrict__ bound,
+                                               const uint32_t* __restrict__ n_mov,
                                                uint32_t* __restrict__ skey,
                                                uint32_t* __restrict__ perm) {
   __shared__ uint32_t lins[kPlaceLds];
-  const uint32_t n_prev = st->n_alive;
-  const int t = threadIdx.x;
+  __shared__ uint32_t cb[2];
+  const uint32_t n_prev = st->n_alive, nm = *n_mov;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const uint32_t nch = (n_prev + kPlaceChunk - 1) / kPlaceChunk;
   for (uint32_t ch = blockIdx.x; ch < nch; ch += gridDim.x) {
     const uint32_t base = ch * kPlaceChunk;
     const uint32_t end = (base + kPlaceChunk < n_prev) ? base + kPlaceChunk : n_prev;
-    const uint32_t c0 = bound[ch], c1 = bound[ch + 1];
-    const bool in_lds = (c1 - c0) <= (uint32_t)kPlaceLds;
-    if (in_lds)
-      for (uint32_t j = c0 + t; j < c1; j += 256) lins[j - c0] = ins[j];
-    __syncthreads();
     constexpr int U = kPlaceChunk / 256;
     uint32_t m0[U], m1[U], kv[U];
 #pragma unroll
@@ -517,6 +494,17 @@ __global__ void __launch_bounds__(256) k_place(const uint32_t* __restrict__ key,
       m1[u] = mpre[ic + 1];
       kv[u] = key[ic];
     }
+    if (w < 2) {
+      const uint32_t b = (w == 0) ? base : end;  // end = the next chunk's start, or n_prev
+      const uint32_t v = movers_upto_wave(ins, nm, b - mpre[b], lane);
+      if (lane == 0) cb[w] = v;
+    }
+    __syncthreads();
+    const uint32_t c0 = cb[0], c1 = cb[1];
+    const bool in_lds = (c1 - c0) <= (uint32_t)kPlaceLds;
+    if (in_lds)
+      for (uint32_t j = c0 + t; j < c1; j += 256) lins[j - c0] = ins[j];
+    __syncthreads();
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const uint32_t i = base + u * 256 + t;
@@ -558,7 +546,7 @@ void sort_keys(const uint32_t* key, int key_bits, SortWork& w, DevState* st, con
     const uint32_t* kin = w.k0;
     const uint32_t* vin = w.v0;
     const MoverPlace none{};
-    const MoverPlace last{off, w.mpre, st, sentinel, w.skey, w.perm, w.ins, w.samp};
+    const MoverPlace last{off, w.mpre, st, sentinel, w.skey, w.perm, w.ins};
     for (int p = 0; p < passes; ++p) {
       uint32_t* kout = (p & 1) ? w.k0 : w.k1;
       uint32_t* vout = (p & 1) ? w.v0 : w.v1;
@@ -571,11 +559,9 @@ void sort_keys(const uint32_t* key, int key_bits, SortWork& w, DevState* st, con
     }
     // the stayers between them
     const int64_t nch = (w.cap + kPlaceChunk - 1) / kPlaceChunk;
-    k_place_bounds<<<grid_for(nch + 1), 256, 0, s>>>(st, w.mpre, w.ins, w.samp, w.n_mov,
-                                                    w.bound);
     int pg = (int)(nch < 4096 ? nch : 4096);
     if (pg < 1) pg = 1;
-    k_place<<<pg, 256, 0, s>>>(key, st, w.mpre, w.ins, w.bound, w.skey, w.perm);
+    k_place<<<pg, 256, 0, s>>>(key, st, w.mpre, w.ins, w.n_mov, w.skey, w.perm);
   }
 }
 

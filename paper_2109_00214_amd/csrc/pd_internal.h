@@ -217,8 +217,6 @@ struct SortWork {
   uint32_t* n_mov;              // device scalar: movers of this sort
   uint32_t* perm;               // [cap] source of every sorted position
   uint32_t* ins;                // [cap] stayers before each sorted mover
-  uint32_t* samp;               // [2048] every stride-th entry of ins
-  uint32_t* bound;              // [cap / 1024 + 2] movers before each chunk of old positions
   int64_t cap;
 };
 
