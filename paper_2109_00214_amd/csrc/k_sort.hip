@@ -295,6 +295,7 @@ __global__ void __launch_bounds__(256) k_radix_down(const uint32_t* __restrict__
         const uint32_t k = tkey[q], i = tval[q];
         const uint32_t p = gofs[(k >> shift) & mask] + q;
         const uint32_t ins = stayers_before(mp, n_prev, k, i);
+        kout[p] = k;  // the movers' keys in order (for the offsets)
         mp.ins[p] = ins;
         mp.skey[ins + p] = k;
         mp.perm[ins + p] = i;
@@ -388,7 +389,10 @@ __global__ void __launch_bounds__(256) k_cls_compact(const uint32_t* __restrict_
   const uint32_t nb = (n + kScanChunk - 1) / kScanChunk;
   if (blockIdx.x == 0) {
     const uint32_t all = block_range_sum(bsum, 0, nb, sh);
-    if (threadIdx.x == 0) *n_mov = all;
+    if (threadIdx.x == 0) {
+      n_mov[0] = all;
+      n_mov[1] = n_prev;  // the old order's live count, for the offsets
+    }
   }
   if (blockIdx.x >= nb) return;
   const uint32_t base = blockIdx.x * kScanChunk + threadIdx.x * kScanPer;
@@ -557,6 +561,7 @@ void sort_keys(const uint32_t* key, int key_bits, SortWork& w, DevState* st, con
       kin = kout;
       vin = vout;
     }
+    w.msorted = kin;  // the last pass's keys: the movers' keys in sorted order
     // the stayers between them
     const int64_t nch = (w.cap + kPlaceChunk - 1) / kPlaceChunk;
     int pg = (int)(nch < 4096 ? nch : 4096);
@@ -570,12 +575,17 @@ void sort_keys(const uint32_t* key, int key_bits, SortWork& w, DevState* st, con
 // off[sentinel] is the number of live particles.  The same launch clears the
 // node charge for the deposit that follows.
 //
-// off is the merge of the sorted keys A[0..n) with the key list 0..nkeys-1
-// (a key before the equal A entries): in the merged order A[i] stands at
-// i + A[i] + 1 and key k at k + off[k].  Each block takes an equal share of
-// the n + nkeys merged places (dense stretches of the keys and empty cells
-// cost the same), finds the A entries of its share by a 64-way search of the
-// monotone i + A[i] + 1, stages them in LDS and searches them for its keys.
+// off[k] = (stayers with key < k) + (movers with key < k).  A stayer keeps
+// its old key and the old order is sorted, so the stayers with key < k are
+// those at old positions below off_prev[k]: off_prev[k] - mpre[off_prev[k]]
+// (mpre = movers before an old position); each key reads its own old entry
+// and overwrites it.  The movers' count is the merge of their sorted keys
+// A[0..nm) with the key list 0..nkeys-1 (a key before the A entries equal
+// to it): in the merged order A[i] stands at i + A[i] + 1 and key k at
+// k + (movers below k).  Each block takes an equal share of the nm + nkeys
+// merged places, finds the A entries of its share by a 64-way search of the
+// strictly increasing i + A[i] + 1, stages them in LDS and searches them for
+// each of its keys.
 constexpr int kOffMax = 4096;  // merged places per block at most
 
 // smallest i in [0, n] with i == n or i + A[i] + 1 >= d; the whole wave
@@ -601,7 +611,9 @@ __device__ inline uint32_t merged_split(const uint32_t* __restrict__ A, uint32_t
   return lo;
 }
 
-__global__ void __launch_bounds__(256) k_offsets(const uint32_t* __restrict__ skeys, DevState* st,
+__global__ void __launch_bounds__(256) k_offsets(const uint32_t* __restrict__ A,
+                                                 const uint32_t* __restrict__ n_mov,
+                                                 const uint32_t* __restrict__ mpre, DevState* st,
                                                  uint32_t* __restrict__ off, uint32_t nkeys,
                                                  int64_t* __restrict__ Q, uint32_t nnodes) {
   __shared__ uint32_t As[kOffMax];
@@ -609,34 +621,40 @@ __global__ void __launch_bounds__(256) k_offsets(const uint32_t* __restrict__ sk
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const uint32_t stride = gridDim.x * blockDim.x;
   for (uint32_t b = blockIdx.x * blockDim.x + t; b < nnodes; b += stride) Q[b] = 0;
-  const uint32_t n = st->n_total;
+  const uint32_t n = n_mov[0], n_prev = n_mov[1];
   const uint32_t tot = n + nkeys;
   const uint32_t D = (tot + gridDim.x - 1) / gridDim.x;  // <= kOffMax by the launch
   const uint32_t d0 = blockIdx.x * D;
   if (d0 >= tot) return;  // whole block
   const uint32_t d1 = (tot - d0 < D) ? tot : d0 + D;
   if (w < 2) {
-    const uint32_t v = merged_split(skeys, n, w == 0 ? d0 : d1, lane);
+    const uint32_t v = merged_split(A, n, w == 0 ? d0 : d1, lane);
     if (lane == 0) split[w] = v;
   }
   __syncthreads();
   const uint32_t ia = split[0], ib = split[1];
   const uint32_t na = ib - ia;  // <= D
-  for (uint32_t i = t; i < na; i += blockDim.x) As[i] = skeys[ia + i];
+  for (uint32_t i = t; i < na; i += blockDim.x) As[i] = A[ia + i];
   __syncthreads();
   const uint32_t j0 = d0 - ia, j1 = d1 - ib;
   const uint32_t c = (j1 - j0 + blockDim.x - 1) / blockDim.x;  // keys per thread
   const uint32_t ja = j0 + t * c;
   const uint32_t je = (ja + c < j1) ? ja + c : j1;
   for (uint32_t k = ja; k < je; ++k) {
+    uint32_t stay = 0;
+    if (n_prev) {
+      const uint32_t x = off[k];  // <= n_prev
+      stay = x - mpre[x];
+    }
     uint32_t lo = 0, hi = na;
     while (lo < hi) {
       const uint32_t mid = (lo + hi) >> 1;
       if (As[mid] < k) lo = mid + 1;
       else hi = mid;
     }
-    off[k] = ia + lo;
-    if (k == nkeys - 1) st->n_alive = ia + lo;
+    const uint32_t o = stay + ia + lo;
+    off[k] = o;
+    if (k == nkeys - 1) st->n_alive = o;
   }
 }
 
@@ -645,7 +663,7 @@ void build_offsets(const SortWork& w, DevState* st, uint32_t* off, uint32_t nkey
   const int64_t places = w.cap + (int64_t)nkeys;
   int64_t gr = (places + kOffMax - 1) / kOffMax;
   if (gr < 1024) gr = 1024;  // a fuller chip for small runs
-  k_offsets<<<(int)gr, 256, 0, s>>>(w.skey, st, off, nkeys, Q, nnodes);
+  k_offsets<<<(int)gr, 256, 0, s>>>(w.msorted, w.n_mov, w.mpre, st, off, nkeys, Q, nnodes);
 }
 
 }  // namespace pd

@@ -214,7 +214,8 @@ struct SortWork {
   uint32_t* bsum;               // per-chunk counts: movers (sort), created electrons (collisions)
   uint32_t* skey;               // [cap] keys in the last sorted order
   uint32_t* mpre;               // [cap + 1] movers before each position
-  uint32_t* n_mov;              // device scalar: movers of this sort
+  uint32_t* n_mov;              // device [2]: movers of this sort, live count of the old order
+  const uint32_t* msorted;      // the movers' keys in sorted order (after sort_keys)
   uint32_t* perm;               // [cap] source of every sorted position
   uint32_t* ins;                // [cap] stayers before each sorted mover
   int64_t cap;
@@ -276,9 +277,10 @@ __device__ inline uint32_t block_range_sum(const uint32_t* __restrict__ c, uint3
   return tot;
 }
 
-// CSR offsets of the sorted keys w.skey (off[k] = first sorted position with
-// key >= k, k < nkeys; st->n_alive = off[nkeys - 1]); the same launch clears
-// the node charge Q.
+// CSR offsets of the sorted keys (off[k] = first sorted position with key
+// >= k, k < nkeys; st->n_alive = off[nkeys - 1]) from the previous order's
+// offsets (off, updated in place) and the sort's movers (after sort_keys);
+// the same launch clears the node charge Q.
 void build_offsets(const SortWork& w, DevState* st, uint32_t* off, uint32_t nkeys, int64_t* Q,
                    uint32_t nnodes, hipStream_t s);
 
