@@ -207,9 +207,12 @@ __global__ void __launch_bounds__(256) k_resolve(const uint32_t* off, DevState* 
                                                  const uint32_t* claim, uint32_t* ccount,
                                                  uint32_t* bsum) {
   __shared__ uint32_t sh[4];
+  __shared__ uint32_t tally[1 + kNC];  // conflicts, events per channel: one atomic per block
   const uint32_t n_e = off[g.C];
   const uint32_t nb = (n_e + 255) / 256;
   const int lane = threadIdx.x & 63;
+  if (threadIdx.x <= kNC) tally[threadIdx.x] = 0;
+  __syncthreads();
   for (uint32_t b = blockIdx.x; b < nb; b += gridDim.x) {
     const uint32_t e = b * 256 + threadIdx.x;
     int ch = -1;
@@ -229,15 +232,20 @@ __global__ void __launch_bounds__(256) k_resolve(const uint32_t* off, DevState* 
       ccount[e] = cnt;
     }
     const uint64_t ml = __ballot(lost);
-    if (lane == 0 && ml) atomicAdd(&st->conflicts, (unsigned long long)__popcll(ml));
+    if (lane == 0 && ml) atomicAdd(&tally[0], (uint32_t)__popcll(ml));
 #pragma unroll
     for (int k = 0; k < kNC; ++k) {
       const uint64_t m = __ballot(ch == k);
-      if (lane == 0 && m) atomicAdd(&st->events[k], (unsigned long long)__popcll(m));
+      if (lane == 0 && m) atomicAdd(&tally[1 + k], (uint32_t)__popcll(m));
     }
     uint32_t tot;
     block_scan256(cnt, &tot, sh);
     if (threadIdx.x == 0) bsum[b] = tot;
+  }
+  __syncthreads();
+  if (threadIdx.x <= kNC && tally[threadIdx.x]) {
+    unsigned long long* dst = (threadIdx.x == 0) ? &st->conflicts : &st->events[threadIdx.x - 1];
+    atomicAdd(dst, (unsigned long long)tally[threadIdx.x]);
   }
 }
 

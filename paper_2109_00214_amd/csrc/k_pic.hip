@@ -183,7 +183,10 @@ void push<float>(const Flow<float>& f, DevState* st, const Grid& g, const Specie
 // ---------------------------------------------------------------------------
 // this step's scheduled particles, appended after the pushed ones
 // The last block to finish (a ticket counter, no waiting) then rolls the
-// counters: the arrays now hold alive + created + injected.
+// counters: the arrays now hold alive + created + injected.  The roll reads
+// only counters that no block of this launch writes, so no block fences its
+// stores (the launch's end publishes them; a device-wide fence writes the
+// L2 back).
 template <typename T>
 __global__ void __launch_bounds__(256) k_inject(PartsT<T> P, DevState* st, Grid g, Schedule sc,
                                                 uint32_t cap) {
@@ -214,13 +217,9 @@ __global__ void __launch_bounds__(256) k_inject(PartsT<T> P, DevState* st, Grid 
     P.key[d] = s * g.C + (uint32_t)(j * g.nr + i);
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    last = (atomicAdd(&st->ticket, 1u) == gridDim.x - 1) ? 1u : 0u;
-  }
+  if (threadIdx.x == 0) last = (atomicAdd(&st->ticket, 1u) == gridDim.x - 1) ? 1u : 0u;
   __syncthreads();
   if (!last || threadIdx.x != 0) return;
-  __threadfence();
   if (!fits) atomicOr(&st->err, 1u);
   if (have) st->sched_pos = pos + 1;
   st->created += st->n_created;
