@@ -150,14 +150,24 @@ __global__ void __launch_bounds__(64 * kColWaves) k_radix_colscan(uint32_t* __re
   }
 }
 
+// Movers among the old positions [0, i): the word prefix of the flag bits
+// and the bits of i's own word below it (i <= n, the arrays written by the
+// classification up to the word of position n).
+__device__ inline uint32_t movers_before(const uint32_t* __restrict__ mbits,
+                                         const uint32_t* __restrict__ mword, uint32_t i) {
+  const uint32_t w = i >> 5;
+  return mword[w] + __popc(mbits[w] & ((1u << (i & 31)) - 1u));
+}
+
 // What the last pass over the movers needs to place them: a mover of
 // sorted rank r with (key k, index i) goes to ins + r, ins = stayers before
-// it = p - mpre[p] with p = i clamped to the old run of key k
+// it = p - movers_before(p) with p = i clamped to the old run of key k
 // [off_prev[k], off_prev[k+1]] (all stayers for the sentinel key).  ins is
 // kept per rank (non-decreasing) for the stayers' searches.
 struct MoverPlace {
   const uint32_t* off_prev;
-  const uint32_t* mpre;
+  const uint32_t* mbits;
+  const uint32_t* mword;
   const DevState* st;
   uint32_t sentinel;
   uint32_t* skey;
@@ -168,10 +178,10 @@ struct MoverPlace {
 __device__ inline uint32_t stayers_before(const MoverPlace& mp, uint32_t n_prev, uint32_t k,
                                           uint32_t i) {
   if (n_prev == 0) return 0;
-  if (k >= mp.sentinel) return n_prev - mp.mpre[n_prev];
+  if (k >= mp.sentinel) return n_prev - movers_before(mp.mbits, mp.mword, n_prev);
   const uint32_t lo = mp.off_prev[k], hi = mp.off_prev[k + 1];
   const uint32_t p = (i < lo) ? lo : ((i > hi) ? hi : i);
-  return p - mp.mpre[p];
+  return p - movers_before(mp.mbits, mp.mword, p);
 }
 
 template <int DB, int IT, bool FIRST>  // FIRST: the values are the source indices
@@ -356,37 +366,47 @@ __device__ inline void mover_flags(uint32_t base, uint32_t n, uint32_t n_prev,
 // movers per chunk of kScanChunk positions
 __global__ void __launch_bounds__(256) k_cls_count(const uint32_t* __restrict__ key,
                                                    const uint32_t* __restrict__ kprev,
-                                                   const DevState* st, uint32_t* __restrict__ bsum) {
+                                                   const DevState* st, uint32_t* __restrict__ bsum,
+                                                   uint32_t* __restrict__ mbits) {
   __shared__ uint32_t sh[4];
   const uint32_t n = st->n_total, n_prev = st->n_alive;
-  const uint32_t nb = (n + kScanChunk - 1) / kScanChunk;
+  const uint32_t nb = n / kScanChunk + 1;  // the chunks up to position n itself
   if (blockIdx.x >= nb) return;
   const uint32_t base = blockIdx.x * kScanChunk + threadIdx.x * kScanPer;
   uint32_t f[kScanPer], kv[kScanPer];
   mover_flags(base, n, n_prev, key, kprev, f, kv);
-  uint32_t acc = 0;
+  uint32_t acc = 0, m = 0;
 #pragma unroll
-  for (int k = 0; k < kScanPer; ++k) acc += f[k];
+  for (int k = 0; k < kScanPer; ++k) {
+    acc += f[k];
+    m |= f[k] << k;
+  }
+  // four threads' eight flags make one word of 32 positions
+  const uint32_t m1 = __shfl_down(m, 1, 64), m2 = __shfl_down(m, 2, 64),
+                 m3 = __shfl_down(m, 3, 64);
+  if ((threadIdx.x & 3) == 0)
+    mbits[(base >> 5)] = m | (m1 << 8) | (m2 << 16) | (m3 << 24);
   uint32_t tot;
   block_scan256(acc, &tot, sh);
   if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
 }
 
-// mpre[i] = movers in [0, i) for i <= n_prev; the movers' (key, index) in
-// index order to mk, mi
+// The movers' (key, index) in index order to mk, mi, and mword[w] = movers
+// before position 32 w, so that movers_before(i) = mword[i/32] + the flags
+// of mbits[i/32] below i.
 // (bsum: the movers of every chunk; each block adds up those of the chunks
 // before its own, block 0 all of them into n_mov)
 __global__ void __launch_bounds__(256) k_cls_compact(const uint32_t* __restrict__ key,
-                                                     const uint32_t* __restrict__ kprev,
                                                      const DevState* st,
                                                      const uint32_t* __restrict__ bsum,
-                                                     uint32_t* __restrict__ mpre,
+                                                     const uint32_t* __restrict__ mbits,
+                                                     uint32_t* __restrict__ mword,
                                                      uint32_t* __restrict__ mk,
                                                      uint32_t* __restrict__ mi,
                                                      uint32_t* __restrict__ n_mov) {
   __shared__ uint32_t sh[4];
   const uint32_t n = st->n_total, n_prev = st->n_alive;
-  const uint32_t nb = (n + kScanChunk - 1) / kScanChunk;
+  const uint32_t nb = n / kScanChunk + 1;
   if (blockIdx.x == 0) {
     const uint32_t all = block_range_sum(bsum, 0, nb, sh);
     if (threadIdx.x == 0) {
@@ -396,35 +416,30 @@ __global__ void __launch_bounds__(256) k_cls_compact(const uint32_t* __restrict_
   }
   if (blockIdx.x >= nb) return;
   const uint32_t base = blockIdx.x * kScanChunk + threadIdx.x * kScanPer;
-  uint32_t f[kScanPer], kv[kScanPer];
-  mover_flags(base, n, n_prev, key, kprev, f, kv);  // (its loads overlap the sum's)
-  const uint32_t before = block_range_sum(bsum, 0, blockIdx.x, sh);
-  uint32_t acc = 0;
+  const uint32_t m = (mbits[base >> 5] >> (8 * (threadIdx.x & 3))) & 0xFFu;
+  uint32_t kv[kScanPer];
+  if (m) {  // the keys only where there are movers
+    if (base + 8 <= n) {
+      const uint4 a0 = *(const uint4*)(key + base), a1 = *(const uint4*)(key + base + 4);
+      kv[0] = a0.x; kv[1] = a0.y; kv[2] = a0.z; kv[3] = a0.w;
+      kv[4] = a1.x; kv[5] = a1.y; kv[6] = a1.z; kv[7] = a1.w;
+    } else {
 #pragma unroll
-  for (int k = 0; k < kScanPer; ++k) acc += f[k];
+      for (int k = 0; k < kScanPer; ++k) kv[k] = (base + k < n) ? key[base + k] : 0u;
+    }
+  }
+  const uint32_t before = block_range_sum(bsum, 0, blockIdx.x, sh);
   uint32_t tot;
-  uint32_t run = before + block_scan256(acc, &tot, sh);
-  uint32_t pre[kScanPer];
+  uint32_t run = before + block_scan256(__popc(m), &tot, sh);
+  if ((threadIdx.x & 3) == 0) mword[base >> 5] = run;
 #pragma unroll
   for (int k = 0; k < kScanPer; ++k) {
-    pre[k] = run;
-    const uint32_t i = base + k;
-    if (f[k]) {
+    if ((m >> k) & 1u) {
       mk[run] = kv[k];
-      mi[run] = i;
+      mi[run] = base + k;
+      ++run;
     }
-    run += f[k];
   }
-  if (base + 8 <= n_prev) {
-    *(uint4*)(mpre + base) = make_uint4(pre[0], pre[1], pre[2], pre[3]);
-    *(uint4*)(mpre + base + 4) = make_uint4(pre[4], pre[5], pre[6], pre[7]);
-  } else {
-#pragma unroll
-    for (int k = 0; k < kScanPer; ++k)
-      if (base + k <= n_prev && base + k < n) mpre[base + k] = pre[k];
-  }
-  // the entry after the last old position
-  if (n_prev == n && base < n && base + kScanPer >= n) mpre[n] = run;
 }
 
 // first j in [lo, hi) with ins[j] > s (the movers placed before the stayer
@@ -440,7 +455,7 @@ __device__ inline uint32_t movers_upto(const uint32_t* __restrict__ ins, uint32_
 }
 // Stayers' places, in chunks of kPlaceChunk old positions: the stayer of
 // rank s goes to s + (movers with ins <= s).  Chunk ch holds the stayer
-// ranks [s0(ch), s0(ch+1)), s0(ch) = base - mpre[base], so the movers it
+// ranks [s0(ch), s0(ch+1)), s0(ch) = base - movers_before(base), so the movers it
 // needs are those of ranks [bound(ch), bound(ch+1)), bound(ch) = the count
 // for s0(ch): two searches per chunk, then the chunk searches only its own
 // movers, staged in LDS.
@@ -475,7 +490,8 @@ __device__ inline uint32_t movers_upto_wave(const uint32_t* __restrict__ ins, ui
 // chunk's (s0 = the chunk start minus the movers before it).
 __global__ void __launch_bounds__(256) k_place(const uint32_t* __restrict__ key,
                                                const DevState* st,
-                                               const uint32_t* __restrict__ mpre,
+                                               const uint32_t* __restrict__ mbits,
+                                               const uint32_t* __restrict__ mword,
                                                const uint32_t* __restrict__ ins,
                                                const uint32_t* __restrict__ n_mov,
                                                uint32_t* __restrict__ skey,
@@ -489,18 +505,18 @@ __global__ void __launch_bounds__(256) k_place(const uint32_t* __restrict__ key,
     const uint32_t base = ch * kPlaceChunk;
     const uint32_t end = (base + kPlaceChunk < n_prev) ? base + kPlaceChunk : n_prev;
     constexpr int U = kPlaceChunk / 256;
-    uint32_t m0[U], m1[U], kv[U];
+    uint32_t wb[U], wp[U], kv[U];  // mover flags and movers before, by words of 32
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const uint32_t i = base + u * 256 + t;
       const uint32_t ic = (i < end) ? i : base;
-      m0[u] = mpre[ic];
-      m1[u] = mpre[ic + 1];
+      wb[u] = mbits[ic >> 5];
+      wp[u] = mword[ic >> 5];
       kv[u] = key[ic];
     }
     if (w < 2) {
       const uint32_t b = (w == 0) ? base : end;  // end = the next chunk's start, or n_prev
-      const uint32_t v = movers_upto_wave(ins, nm, b - mpre[b], lane);
+      const uint32_t v = movers_upto_wave(ins, nm, b - movers_before(mbits, mword, b), lane);
       if (lane == 0) cb[w] = v;
     }
     __syncthreads();
@@ -512,8 +528,9 @@ __global__ void __launch_bounds__(256) k_place(const uint32_t* __restrict__ key,
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const uint32_t i = base + u * 256 + t;
-      if (i >= end || m1[u] != m0[u]) continue;  // past the chunk, or a mover
-      const uint32_t sr = i - m0[u];
+      const uint32_t below = (1u << (i & 31)) - 1u;
+      if (i >= end || ((wb[u] >> (i & 31)) & 1u)) continue;  // past the chunk, or a mover
+      const uint32_t sr = i - (wp[u] + __popc(wb[u] & below));
       uint32_t cnt;
       if (in_lds) {
         uint32_t lo = 0, hi = c1 - c0;
@@ -541,16 +558,16 @@ void sort_keys(const uint32_t* key, int key_bits, SortWork& w, DevState* st, con
   int passes = (key_bits + kRadixMaxBits - 1) / kRadixMaxBits;
   if (passes < 2) passes = 2;
   const int dbits = (key_bits + passes - 1) / passes;
-  const int nb = (int)((w.cap + kScanChunk - 1) / kScanChunk);
+  const int nb = (int)(w.cap / kScanChunk + 1);
   {
     // classify, count and compact the movers (key, index) into k0/v0
-    k_cls_count<<<nb, 256, 0, s>>>(key, w.skey, st, w.bsum);
-    k_cls_compact<<<nb, 256, 0, s>>>(key, w.skey, st, w.bsum, w.mpre, w.k0, w.v0, w.n_mov);
+    k_cls_count<<<nb, 256, 0, s>>>(key, w.skey, st, w.bsum, w.mbits);
+    k_cls_compact<<<nb, 256, 0, s>>>(key, st, w.bsum, w.mbits, w.mword, w.k0, w.v0, w.n_mov);
     // stable radix sort of the movers
     const uint32_t* kin = w.k0;
     const uint32_t* vin = w.v0;
     const MoverPlace none{};
-    const MoverPlace last{off, w.mpre, st, sentinel, w.skey, w.perm, w.ins};
+    const MoverPlace last{off, w.mbits, w.mword, st, sentinel, w.skey, w.perm, w.ins};
     for (int p = 0; p < passes; ++p) {
       uint32_t* kout = (p & 1) ? w.k0 : w.k1;
       uint32_t* vout = (p & 1) ? w.v0 : w.v1;
@@ -566,7 +583,7 @@ void sort_keys(const uint32_t* key, int key_bits, SortWork& w, DevState* st, con
     const int64_t nch = (w.cap + kPlaceChunk - 1) / kPlaceChunk;
     int pg = (int)(nch < 4096 ? nch : 4096);
     if (pg < 1) pg = 1;
-    k_place<<<pg, 256, 0, s>>>(key, st, w.mpre, w.ins, w.n_mov, w.skey, w.perm);
+    k_place<<<pg, 256, 0, s>>>(key, st, w.mbits, w.mword, w.ins, w.n_mov, w.skey, w.perm);
   }
 }
 
@@ -577,8 +594,8 @@ void sort_keys(const uint32_t* key, int key_bits, SortWork& w, DevState* st, con
 //
 // off[k] = (stayers with key < k) + (movers with key < k).  A stayer keeps
 // its old key and the old order is sorted, so the stayers with key < k are
-// those at old positions below off_prev[k]: off_prev[k] - mpre[off_prev[k]]
-// (mpre = movers before an old position); each key reads its own old entry
+// those at old positions below off_prev[k]: off_prev[k] -
+// movers_before(off_prev[k]); each key reads its own old entry
 // and overwrites it.  The movers' count is the merge of their sorted keys
 // A[0..nm) with the key list 0..nkeys-1 (a key before the A entries equal
 // to it): in the merged order A[i] stands at i + A[i] + 1 and key k at
@@ -613,7 +630,8 @@ __device__ inline uint32_t merged_split(const uint32_t* __restrict__ A, uint32_t
 
 __global__ void __launch_bounds__(256) k_offsets(const uint32_t* __restrict__ A,
                                                  const uint32_t* __restrict__ n_mov,
-                                                 const uint32_t* __restrict__ mpre, DevState* st,
+                                                 const uint32_t* __restrict__ mbits,
+                                                 const uint32_t* __restrict__ mword, DevState* st,
                                                  uint32_t* __restrict__ off, uint32_t nkeys,
                                                  int64_t* __restrict__ Q, uint32_t nnodes) {
   __shared__ uint32_t As[kOffMax];
@@ -644,7 +662,7 @@ __global__ void __launch_bounds__(256) k_offsets(const uint32_t* __restrict__ A,
     uint32_t stay = 0;
     if (n_prev) {
       const uint32_t x = off[k];  // <= n_prev
-      stay = x - mpre[x];
+      stay = x - movers_before(mbits, mword, x);
     }
     uint32_t lo = 0, hi = na;
     while (lo < hi) {
@@ -663,7 +681,8 @@ void build_offsets(const SortWork& w, DevState* st, uint32_t* off, uint32_t nkey
   const int64_t places = w.cap + (int64_t)nkeys;
   int64_t gr = (places + kOffMax - 1) / kOffMax;
   if (gr < 1024) gr = 1024;  // a fuller chip for small runs
-  k_offsets<<<(int)gr, 256, 0, s>>>(w.msorted, w.n_mov, w.mpre, st, off, nkeys, Q, nnodes);
+  k_offsets<<<(int)gr, 256, 0, s>>>(w.msorted, w.n_mov, w.mbits, w.mword, st, off, nkeys, Q,
+                                    nnodes);
 }
 
 }  // namespace pd

@@ -658,7 +658,8 @@ pd_status pd_create(const pd_domain* dom, const pd_opts* opts, pd_ctx** out) {
       (s = dalloc(c, &c->sw.v0, cap)) || (s = dalloc(c, &c->sw.v1, cap)) ||
       (s = dalloc(c, &c->sw.hist, (size_t)kRadix * (tiles < 1 ? 1 : tiles))) ||
       (s = dalloc(c, &c->sw.bsum, std::max<int64_t>(kScanMaxBlocks, cap / 256 + 1))) ||
-      (s = dalloc(c, &c->sw.skey, cap)) || (s = dalloc(c, &c->sw.mpre, cap + 1)) ||
+      (s = dalloc(c, &c->sw.skey, cap)) || (s = dalloc(c, &c->sw.mbits, cap / 32 + 66)) ||
+      (s = dalloc(c, &c->sw.mword, cap / 32 + 66)) ||
       (s = dalloc(c, &c->sw.n_mov, 2)) || (s = dalloc(c, &c->sw.perm, cap)) ||
       (s = dalloc(c, &c->sw.ins, cap)) ||
       (s = dalloc(c, &c->cw.choice, cap)) || (s = dalloc(c, &c->cw.target, cap)) ||

@@ -213,7 +213,8 @@ struct SortWork {
   uint32_t* hist;               // [kRadix * tiles of 256 kMoverItems keys in cap]
   uint32_t* bsum;               // per-chunk counts: movers (sort), created electrons (collisions)
   uint32_t* skey;               // [cap] keys in the last sorted order
-  uint32_t* mpre;               // [cap + 1] movers before each position
+  uint32_t* mbits;              // [cap / 32 + 66] mover flag of each old position, 32 per word
+  uint32_t* mword;              // [cap / 32 + 66] movers before each word of mbits
   uint32_t* n_mov;              // device [2]: movers of this sort, live count of the old order
   const uint32_t* msorted;      // the movers' keys in sorted order (after sort_keys)
   uint32_t* perm;               // [cap] source of every sorted position
