@@ -55,13 +55,14 @@ template void deposit<float>(const Flow<float>&, const uint32_t*, const Grid&,
 // E = -grad(phi): central differences, second-order one-sided at the
 // electrodes, E_r = 0 on the axis and at the wall; FP32 copies for the FP32
 // push when Erf is not NULL
-__global__ void __launch_bounds__(256) k_field(const double* phi, int nr, int nz, double dr,
-                                               double dz, double* Er, double* Ez, float* Erf,
-                                               float* Ezf) {
+// (blocks blk = 0 .. nblk-1 of a 256-thread launch share the nodes)
+__device__ inline void field_nodes(const double* phi, int nr, int nz, double dr, double dz,
+                                   double* Er, double* Ez, float* Erf, float* Ezf, int blk,
+                                   int nblk) {
   const int W = nr + 1;
   const int n = (nz + 1) * W;
   const double tdz = 2.0 * dz, tdr = 2.0 * dr;
-  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < n; b += gridDim.x * blockDim.x) {
+  for (int b = blk * blockDim.x + threadIdx.x; b < n; b += nblk * blockDim.x) {
     const int j = b / W, i = b % W;
     double ez;
     if (j == 0) ez = (((3.0 * phi[b]) - (4.0 * phi[b + W])) + phi[b + 2 * W]) / tdz;
@@ -75,6 +76,12 @@ __global__ void __launch_bounds__(256) k_field(const double* phi, int nr, int nz
       Erf[b] = (float)er;
     }
   }
+}
+
+__global__ void __launch_bounds__(256) k_field(const double* phi, int nr, int nz, double dr,
+                                               double dz, double* Er, double* Ez, float* Erf,
+                                               float* Ezf) {
+  field_nodes(phi, nr, nz, dr, dz, Er, Ez, Erf, Ezf, blockIdx.x, gridDim.x);
 }
 
 void field(const Grid& g, FieldWork& fw, hipStream_t s) {
@@ -97,6 +104,94 @@ __device__ inline void count_codes(int code, unsigned long long* ctr) {
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// this step's scheduled particles, appended after the pushed ones (the slots
+// after alive + created, which the push does not touch), as extra blocks of
+// the field's launch; the push's first thread then rolls the step counters.
+// Both read the same counters (no launch between them changes them), so
+// they take the same decision; the roll leaves n_created to the next
+// collisions, which set it.
+struct InjectPlan {
+  uint32_t pos, cnt, base, id0;
+  int64_t a;  // first schedule entry
+  bool have, fits;
+};
+
+__device__ inline InjectPlan inject_plan(const DevState* st, const Schedule& sc, uint32_t cap) {
+  InjectPlan ip;
+  ip.pos = st->sched_pos;
+  ip.have = sc.off && ip.pos < st->sched_n;
+  ip.a = ip.have ? sc.off[ip.pos] : 0;
+  ip.cnt = ip.have ? (uint32_t)(sc.off[ip.pos + 1] - ip.a) : 0u;
+  ip.base = st->n_alive + st->n_created;
+  ip.id0 = st->next_id + st->n_created;
+  ip.fits = (uint64_t)ip.base + ip.cnt <= cap && (uint64_t)ip.id0 + ip.cnt <= 0xFFFFFFFFull;
+  if (!ip.fits) ip.cnt = 0;
+  return ip;
+}
+
+template <typename T>
+__device__ inline void inject_records(const PartsT<T>& P, const Grid& g, const Schedule& sc,
+                                      const InjectPlan& ip, uint32_t blk, uint32_t nblk) {
+  for (uint32_t q = blk * blockDim.x + threadIdx.x; q < ip.cnt; q += nblk * blockDim.x) {
+    const int64_t src = ip.a + q;
+    const uint32_t d = ip.base + q;
+    const T r = (T)sc.r[src], z = (T)sc.z[src];
+    const uint32_t s = sc.sp[src];
+    P.r[d] = r;
+    P.z[d] = z;
+    P.vr[d] = (T)sc.vr[src];
+    P.vt[d] = (T)sc.vt[src];
+    P.vz[d] = (T)sc.vz[src];
+    P.sp[d] = (uint8_t)s;
+    P.id[d] = ip.id0 + q;
+    int i, j;
+    T fr, fz;
+    cell_of<T>(g, r, z, i, j, fr, fz);
+    P.key[d] = s * g.C + (uint32_t)(j * g.nr + i);
+  }
+}
+
+// (one thread) the arrays now hold alive + created + injected
+__device__ inline void roll_counters(DevState* st, const InjectPlan& ip) {
+  if (!ip.fits) atomicOr(&st->err, 1u);
+  if (ip.have) st->sched_pos = ip.pos + 1;
+  st->created += st->n_created;
+  st->pushed += st->n_alive + st->n_created;
+  st->n_total = ip.base + ip.cnt;
+  st->next_id = ip.id0 + ip.cnt;
+  st->step += 1;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_field_inject(const double* phi, int nr, int nz, double dr,
+                                                      double dz, double* Er, double* Ez,
+                                                      float* Erf, float* Ezf, PartsT<T> P,
+                                                      const DevState* st, Grid g, Schedule sc,
+                                                      uint32_t cap, uint32_t nf) {
+  if (blockIdx.x < nf) {
+    field_nodes(phi, nr, nz, dr, dz, Er, Ez, Erf, Ezf, blockIdx.x, nf);
+    return;
+  }
+  const InjectPlan ip = inject_plan(st, sc, cap);
+  inject_records<T>(P, g, sc, ip, blockIdx.x - nf, gridDim.x - nf);
+}
+
+template <typename T>
+void field_and_inject(const Grid& g, FieldWork& fw, const PartsT<T>& P, const DevState* st,
+                      const Schedule& sc, int64_t cap, hipStream_t s) {
+  const int64_t n = (int64_t)(g.nr + 1) * (g.nz + 1);
+  const int nf = grid_for(n), ni = grid_for(sc.off ? sc.max_count : 1);
+  k_field_inject<T><<<nf + ni, 256, 0, s>>>(fw.phi, g.nr, g.nz, g.dr, g.dz, fw.Er, fw.Ez,
+                                            fw.Erf, fw.Ezf, P, st, g, sc, (uint32_t)cap,
+                                            (uint32_t)nf);
+}
+template void field_and_inject<double>(const Grid&, FieldWork&, const Parts&, const DevState*,
+                                       const Schedule&, int64_t, hipStream_t);
+template void field_and_inject<float>(const Grid&, FieldWork&, const PartsF&, const DevState*,
+                                      const Schedule&, int64_t, hipStream_t);
+
 // gather (bilinear, the deposit's weights) and leapfrog push in the record's
 // precision T: v += (q/m) E dt, Cartesian move, rotation back to the r-z
 // plane; absorbed particles get the sentinel key, the others their new key
@@ -104,9 +199,11 @@ __device__ inline void count_codes(int code, unsigned long long* ctr) {
 // S[p] (created this step) and goes to S[p], the id and label with it.
 template <typename T>
 __global__ void __launch_bounds__(256) k_push(Flow<T> f, DevState* st, Grid g, SpeciesParams spp,
-                                              const T* Er, const T* Ez) {
+                                              const T* Er, const T* Ez, Schedule sc,
+                                              uint32_t cap) {
   const uint32_t n_alive = st->n_alive;
   const uint32_t n = n_alive + st->n_created;
+  if (blockIdx.x == 0 && threadIdx.x == 0) roll_counters(st, inject_plan(st, sc, cap));
   const int W = g.nr + 1;
   const T dt = (T)g.dt;
   const uint32_t stride = gridDim.x * blockDim.x;
@@ -171,75 +268,14 @@ __global__ void __launch_bounds__(256) k_push(Flow<T> f, DevState* st, Grid g, S
 
 template <>
 void push<double>(const Flow<double>& f, DevState* st, const Grid& g, const SpeciesParams& sp,
-                  const FieldWork& fw, int64_t cap, hipStream_t s) {
-  k_push<double><<<grid_for(cap), 256, 0, s>>>(f, st, g, sp, fw.Er, fw.Ez);
+                  const FieldWork& fw, const Schedule& sc, int64_t cap, hipStream_t s) {
+  k_push<double><<<grid_for(cap), 256, 0, s>>>(f, st, g, sp, fw.Er, fw.Ez, sc, (uint32_t)cap);
 }
 template <>
 void push<float>(const Flow<float>& f, DevState* st, const Grid& g, const SpeciesParams& sp,
-                 const FieldWork& fw, int64_t cap, hipStream_t s) {
-  k_push<float><<<grid_for(cap), 256, 0, s>>>(f, st, g, sp, fw.Erf, fw.Ezf);
+                 const FieldWork& fw, const Schedule& sc, int64_t cap, hipStream_t s) {
+  k_push<float><<<grid_for(cap), 256, 0, s>>>(f, st, g, sp, fw.Erf, fw.Ezf, sc, (uint32_t)cap);
 }
-
-// ---------------------------------------------------------------------------
-// this step's scheduled particles, appended after the pushed ones
-// The last block to finish (a ticket counter, no waiting) then rolls the
-// counters: the arrays now hold alive + created + injected.  The roll reads
-// only counters that no block of this launch writes, so no block fences its
-// stores (the launch's end publishes them; a device-wide fence writes the
-// L2 back).
-template <typename T>
-__global__ void __launch_bounds__(256) k_inject(PartsT<T> P, DevState* st, Grid g, Schedule sc,
-                                                uint32_t cap) {
-  __shared__ uint32_t last;
-  const uint32_t pos = st->sched_pos;
-  const bool have = sc.off && pos < st->sched_n;
-  const int64_t a = have ? sc.off[pos] : 0;
-  uint32_t cnt = have ? (uint32_t)(sc.off[pos + 1] - a) : 0u;
-  const uint32_t base = st->n_alive + st->n_created;
-  const uint32_t id0 = st->next_id + st->n_created;
-  const bool fits = (uint64_t)base + cnt <= cap && (uint64_t)id0 + cnt <= 0xFFFFFFFFull;
-  if (!fits) cnt = 0;
-  for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < cnt; q += gridDim.x * blockDim.x) {
-    const int64_t src = a + q;
-    const uint32_t d = base + q;
-    const T r = (T)sc.r[src], z = (T)sc.z[src];
-    const uint32_t s = sc.sp[src];
-    P.r[d] = r;
-    P.z[d] = z;
-    P.vr[d] = (T)sc.vr[src];
-    P.vt[d] = (T)sc.vt[src];
-    P.vz[d] = (T)sc.vz[src];
-    P.sp[d] = (uint8_t)s;
-    P.id[d] = id0 + q;
-    int i, j;
-    T fr, fz;
-    cell_of<T>(g, r, z, i, j, fr, fz);
-    P.key[d] = s * g.C + (uint32_t)(j * g.nr + i);
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) last = (atomicAdd(&st->ticket, 1u) == gridDim.x - 1) ? 1u : 0u;
-  __syncthreads();
-  if (!last || threadIdx.x != 0) return;
-  if (!fits) atomicOr(&st->err, 1u);
-  if (have) st->sched_pos = pos + 1;
-  st->created += st->n_created;
-  st->pushed += st->n_alive + st->n_created;
-  st->n_total = base + cnt;
-  st->next_id = id0 + cnt;
-  st->n_created = 0;
-  st->step += 1;
-  st->ticket = 0;
-}
-
-template <typename T>
-void inject_and_roll(const PartsT<T>& P, DevState* st, const Grid& g, const Schedule& sc,
-                     int64_t cap, hipStream_t s) {
-  k_inject<T><<<grid_for(sc.off ? sc.max_count : 1), 256, 0, s>>>(P, st, g, sc, (uint32_t)cap);
-}
-template void inject_and_roll<double>(const Parts&, DevState*, const Grid&, const Schedule&,
-                                      int64_t, hipStream_t);
-template void inject_and_roll<float>(const PartsF&, DevState*, const Grid&, const Schedule&,
-                                     int64_t, hipStream_t);
 
 // host-initiated append of n particles already copied to src
 template <typename T>

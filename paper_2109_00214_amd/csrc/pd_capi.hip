@@ -537,8 +537,8 @@ pd_status stage_append(pd_ctx* c, const PartsT<T>& A, const PartsT<T>& B, int64_
   return PD_OK;
 }
 
-// one step on the context's stream: sort -> collide -> deposit -> Poisson
-// -> field -> push -> inject (mark() records the stage boundaries; the
+// one step on the context's stream: sort -> offsets -> collide (+ deposit)
+// -> Poisson -> field (+ inject) -> push (mark() records the stage boundaries; the
 // records stay in A, in the previous order, until the push writes them
 // sorted into B, which then becomes A)
 template <class T, class Mark>
@@ -569,13 +569,12 @@ pd_status enqueue_step(pd_ctx* c, PartsT<T>& A, PartsT<T>& B, int64_t nn, Mark& 
   pd_status ps = solve_poisson(c);
   if (ps) return ps;
   mark();
-  field(c->g, c->fw, s);
+  field_and_inject(c->g, c->fw, B, c->st, c->sched, c->cap, s);
   mark();
-  push(f, c->st, c->g, c->spp, c->fw, c->cap, s);
+  push(f, c->st, c->g, c->spp, c->fw, c->sched, c->cap, s);
   mark();
-  inject_and_roll(B, c->st, c->g, c->sched, c->cap, s);
   std::swap(A, B);
-  mark();
+  mark(true);  // the injection ran with the field
   return PD_OK;
 }
 

@@ -25,7 +25,7 @@ struct DevState {
   uint32_t sched_pos;  // next injection-schedule slot
   uint32_t sched_n;    // schedule length (steps)
   uint32_t err;        // bit 0: capacity overflow
-  uint32_t ticket;     // finished blocks of the injection launch (last one rolls)
+  uint32_t pad1_;
   uint32_t pad_;
   unsigned long long events[kNC];
   unsigned long long conflicts;
@@ -377,13 +377,16 @@ void mg_residual(const MGWork& w, const double* phi, const int64_t* Q, hipStream
 // residual, phi += correction, new residual
 void mg_outer(MGWork& w, double* phi, const int64_t* Q, int inner, hipStream_t s);
 void field(const Grid& g, FieldWork& fw, hipStream_t s);
+// the field, the same launch appending this step's scheduled particles to P
+// (after alive + created)
+template <typename T>
+void field_and_inject(const Grid& g, FieldWork& fw, const PartsT<T>& P, const DevState* st,
+                      const Schedule& sc, int64_t cap, hipStream_t s);
+// gather + push into f.S; its first thread rolls the step counters (the
+// injection above included)
 template <typename T>
 void push(const Flow<T>& f, DevState* st, const Grid& g, const SpeciesParams& sp,
-          const FieldWork& fw, int64_t cap, hipStream_t s);
-// append this step's scheduled particles and roll the step counters
-template <typename T>
-void inject_and_roll(const PartsT<T>& P, DevState* st, const Grid& g, const Schedule& sc,
-                     int64_t cap, hipStream_t s);
+          const FieldWork& fw, const Schedule& sc, int64_t cap, hipStream_t s);
 template <typename T>
 void append(const PartsT<T>& P, DevState* st, const Grid& g, const PartsT<T>& src, uint32_t n,
             hipStream_t s);
