@@ -202,7 +202,7 @@ __device__ inline void deposit_blocks(const Flow<T>& f, const uint32_t* __restri
 constexpr int kSortBlock = 256;
 constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortBlock * kSortItems;  // 4096 keys per tile
-constexpr int kMoverItems = 4;                      // movers: 1024 keys per tile
+constexpr int kMoverItems = 2;                      // movers: 512 keys per tile
 constexpr int kRadixMaxBits = 10;                  // digit width of a pass
 constexpr int kRadix = 1 << kRadixMaxBits;
 constexpr int kScanChunk = 2048;                    // elements per scan block
