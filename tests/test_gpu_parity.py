@@ -197,3 +197,24 @@ def test_capacity_overflow_on_device_is_reported():
     with pytest.raises(PdError) as e:
         g.synchronize()
     assert e.value.status == PD_ECAPACITY
+
+
+def test_created_electrons_beyond_capacity_are_reported():
+    """Ionizations that would create more electrons than the capacity holds:
+    the collision launch decides this in every block from the same chunk
+    sums, creates nothing, flags the error, and the next synchronising call
+    reports PD_ECAPACITY."""
+    from paper_2109_00214_amd.pd import PdError, PD_ECAPACITY
+    log("case: created electrons beyond capacity")
+    cfg = W.config("tiny", nr=8, nz=16, weight=1e6, V=500.0, inj_e=0, inj_cu=0)
+    tables = W.constant_tables((3e-19, 2e-19, 1e-19, 2e-19), thresholds=(0, 7.73, 28.0, 20.29),
+                               n=2048)
+    parts = W.initial_population(cfg, n=20000)
+    n = len(parts["r"])
+    g = gpu_sim(cfg, n + 8, tables)
+    g.inject(parts)
+    g.step(3)
+    with pytest.raises(PdError) as e:
+        g.synchronize()
+    assert e.value.status == PD_ECAPACITY
+
