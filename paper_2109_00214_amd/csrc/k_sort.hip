@@ -488,20 +488,22 @@ __device__ inline uint32_t movers_upto_wave(const uint32_t* __restrict__ ins, ui
 // Each block finds its chunk's mover range itself: waves 0 and 1 search for
 // the movers placed before the chunk's first stayer and before the next
 // chunk's (s0 = the chunk start minus the movers before it).
-__global__ void __launch_bounds__(256) k_place(const uint32_t* __restrict__ key,
-                                               const DevState* st,
-                                               const uint32_t* __restrict__ mbits,
-                                               const uint32_t* __restrict__ mword,
-                                               const uint32_t* __restrict__ ins,
-                                               const uint32_t* __restrict__ n_mov,
-                                               uint32_t* __restrict__ skey,
-                                               uint32_t* __restrict__ perm) {
+// (blocks blk = 0 .. nblk-1 of a 256-thread launch share the chunks; the old
+// order's live count comes from n_mov[1], as the same launch computes the
+// new one)
+__device__ inline void place_blocks(const uint32_t* __restrict__ key,
+                                    const uint32_t* __restrict__ mbits,
+                                    const uint32_t* __restrict__ mword,
+                                    const uint32_t* __restrict__ ins,
+                                    const uint32_t* __restrict__ n_mov,
+                                    uint32_t* __restrict__ skey, uint32_t* __restrict__ perm,
+                                    uint32_t blk, uint32_t nblk) {
   __shared__ uint32_t lins[kPlaceLds];
   __shared__ uint32_t cb[2];
-  const uint32_t n_prev = st->n_alive, nm = *n_mov;
+  const uint32_t nm = n_mov[0], n_prev = n_mov[1];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const uint32_t nch = (n_prev + kPlaceChunk - 1) / kPlaceChunk;
-  for (uint32_t ch = blockIdx.x; ch < nch; ch += gridDim.x) {
+  for (uint32_t ch = blk; ch < nch; ch += nblk) {
     const uint32_t base = ch * kPlaceChunk;
     const uint32_t end = (base + kPlaceChunk < n_prev) ? base + kPlaceChunk : n_prev;
     constexpr int U = kPlaceChunk / 256;
@@ -579,11 +581,6 @@ void sort_keys(const uint32_t* key, int key_bits, SortWork& w, DevState* st, con
       vin = vout;
     }
     w.msorted = kin;  // the last pass's keys: the movers' keys in sorted order
-    // the stayers between them
-    const int64_t nch = (w.cap + kPlaceChunk - 1) / kPlaceChunk;
-    int pg = (int)(nch < 4096 ? nch : 4096);
-    if (pg < 1) pg = 1;
-    k_place<<<pg, 256, 0, s>>>(key, st, w.mbits, w.mword, w.ins, w.n_mov, w.skey, w.perm);
   }
 }
 
@@ -628,21 +625,23 @@ __device__ inline uint32_t merged_split(const uint32_t* __restrict__ A, uint32_t
   return lo;
 }
 
-__global__ void __launch_bounds__(256) k_offsets(const uint32_t* __restrict__ A,
-                                                 const uint32_t* __restrict__ n_mov,
-                                                 const uint32_t* __restrict__ mbits,
-                                                 const uint32_t* __restrict__ mword, DevState* st,
-                                                 uint32_t* __restrict__ off, uint32_t nkeys,
-                                                 int64_t* __restrict__ Q, uint32_t nnodes) {
+// (blocks blk = 0 .. nblk-1 of a 256-thread launch)
+__device__ inline void offsets_blocks(const uint32_t* __restrict__ A,
+                                      const uint32_t* __restrict__ n_mov,
+                                      const uint32_t* __restrict__ mbits,
+                                      const uint32_t* __restrict__ mword, DevState* st,
+                                      uint32_t* __restrict__ off, uint32_t nkeys,
+                                      int64_t* __restrict__ Q, uint32_t nnodes, uint32_t blk,
+                                      uint32_t nblk) {
   __shared__ uint32_t As[kOffMax];
   __shared__ uint32_t split[2];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t b = blockIdx.x * blockDim.x + t; b < nnodes; b += stride) Q[b] = 0;
+  const uint32_t stride = nblk * blockDim.x;
+  for (uint32_t b = blk * blockDim.x + t; b < nnodes; b += stride) Q[b] = 0;
   const uint32_t n = n_mov[0], n_prev = n_mov[1];
   const uint32_t tot = n + nkeys;
-  const uint32_t D = (tot + gridDim.x - 1) / gridDim.x;  // <= kOffMax by the launch
-  const uint32_t d0 = blockIdx.x * D;
+  const uint32_t D = (tot + nblk - 1) / nblk;  // <= kOffMax by the launch
+  const uint32_t d0 = blk * D;
   if (d0 >= tot) return;  // whole block
   const uint32_t d1 = (tot - d0 < D) ? tot : d0 + D;
   if (w < 2) {
@@ -676,13 +675,33 @@ __global__ void __launch_bounds__(256) k_offsets(const uint32_t* __restrict__ A,
   }
 }
 
-void build_offsets(const SortWork& w, DevState* st, uint32_t* off, uint32_t nkeys, int64_t* Q,
-                   uint32_t nnodes, hipStream_t s) {
+// The stayers' placement and the offsets read nothing the other writes
+// (both take the old order's live count from n_mov[1]): one launch, the
+// placement's blocks first.
+__global__ void __launch_bounds__(256) k_place_offsets(
+    const uint32_t* __restrict__ key, const uint32_t* __restrict__ mbits,
+    const uint32_t* __restrict__ mword, const uint32_t* __restrict__ ins,
+    const uint32_t* __restrict__ n_mov, uint32_t* __restrict__ skey, uint32_t* __restrict__ perm,
+    const uint32_t* __restrict__ A, DevState* st, uint32_t* __restrict__ off, uint32_t nkeys,
+    int64_t* __restrict__ Q, uint32_t nnodes, uint32_t npl) {
+  if (blockIdx.x < npl)
+    place_blocks(key, mbits, mword, ins, n_mov, skey, perm, blockIdx.x, npl);
+  else
+    offsets_blocks(A, n_mov, mbits, mword, st, off, nkeys, Q, nnodes, blockIdx.x - npl,
+                   gridDim.x - npl);
+}
+
+void place_and_offsets(const uint32_t* key, const SortWork& w, DevState* st, uint32_t* off,
+                       uint32_t nkeys, int64_t* Q, uint32_t nnodes, hipStream_t s) {
+  const int64_t nch = (w.cap + kPlaceChunk - 1) / kPlaceChunk;
+  int pg = (int)(nch < 4096 ? nch : 4096);
+  if (pg < 1) pg = 1;
   const int64_t places = w.cap + (int64_t)nkeys;
   int64_t gr = (places + kOffMax - 1) / kOffMax;
   if (gr < 1024) gr = 1024;  // a fuller chip for small runs
-  k_offsets<<<(int)gr, 256, 0, s>>>(w.msorted, w.n_mov, w.mbits, w.mword, st, off, nkeys, Q,
-                                    nnodes);
+  k_place_offsets<<<pg + (int)gr, 256, 0, s>>>(key, w.mbits, w.mword, w.ins, w.n_mov, w.skey,
+                                                w.perm, w.msorted, st, off, nkeys, Q, nnodes,
+                                                (uint32_t)pg);
 }
 
 }  // namespace pd

@@ -548,7 +548,7 @@ pd_status enqueue_step(pd_ctx* c, PartsT<T>& A, PartsT<T>& B, int64_t nn, Mark& 
   sort_keys(A.key, c->key_bits, c->sw, c->st, c->off, c->g.sentinel, s);
   mark();
   mark(true);  // no separate record permutation: the push moves the records
-  build_offsets(c->sw, c->st, c->off, c->g.sentinel + 1, c->fw.Q, (uint32_t)nn, s);
+  place_and_offsets(A.key, c->sw, c->st, c->off, c->g.sentinel + 1, c->fw.Q, (uint32_t)nn, s);
   const Flow<T> f{A, B, c->sw.perm, c->sw.skey};
   mark();
   // The deposit reads only what the collisions leave alone (positions, the

@@ -227,7 +227,8 @@ struct SortWork {
 // st->n_alive positions hold the previous sort's order with updated keys:
 // the particles whose key did not change stay in order and are merged with
 // the others (radix-sorted) by (key, index), using the previous order's
-// offsets off.
+// offsets off.  This places the movers; place_and_offsets places the
+// stayers.
 void sort_keys(const uint32_t* key, int key_bits, SortWork& w, DevState* st, const uint32_t* off,
                uint32_t sentinel, hipStream_t s);
 
@@ -282,8 +283,10 @@ __device__ inline uint32_t block_range_sum(const uint32_t* __restrict__ c, uint3
 // >= k, k < nkeys; st->n_alive = off[nkeys - 1]) from the previous order's
 // offsets (off, updated in place) and the sort's movers (after sort_keys);
 // the same launch clears the node charge Q.
-void build_offsets(const SortWork& w, DevState* st, uint32_t* off, uint32_t nkeys, int64_t* Q,
-                   uint32_t nnodes, hipStream_t s);
+// With the stayers' places (skey and perm for the positions that are not
+// movers' places; key = the records' keys) in the same launch.
+void place_and_offsets(const uint32_t* key, const SortWork& w, DevState* st, uint32_t* off,
+                       uint32_t nkeys, int64_t* Q, uint32_t nnodes, hipStream_t s);
 
 // ---- collisions (k_collide.hip) ----
 struct CollideWork {
