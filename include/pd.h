@@ -85,9 +85,12 @@ enum { PD_FP64_DET = 0, PD_FP32_MIXED = 1 };
  * does not get there falls back to the direct solve. */
 enum { PD_POISSON_DIRECT64 = 0, PD_POISSON_MGPCG = 1, PD_POISSON_LEARNED = 2,
        PD_POISSON_SPECTRAL = 3 };
-/* stages timed by pd_get_timing: radix passes of the sort, payload
- * permutation, CSR offsets, collisions, deposit, Poisson, field, push,
- * injection + counter roll */
+/* stages timed by pd_get_timing: the sort's classification and mover radix
+ * passes; payload permutation (empty: the push moves the records); the
+ * stayers' places with the CSR offsets; collisions (the deposit runs in
+ * their first launch when collisions are on); deposit (collisions off);
+ * Poisson; field (with this step's injection); push (with the counter
+ * roll); injection (empty: it runs with the field) */
 enum { PD_T_RADIX = 0, PD_T_PERMUTE = 1, PD_T_OFFSETS = 2, PD_T_COLLIDE = 3,
        PD_T_DEPOSIT = 4, PD_T_POISSON = 5, PD_T_FIELD = 6, PD_T_PUSH = 7,
        PD_T_INJECT = 8, PD_NTIMERS = 9 };
