@@ -66,6 +66,25 @@ def test_sparse_keys_paper_grid(n):
         assert_same_state(g, o, "sparse n=%d step %d" % (n, s))
 
 
+def test_all_stayers_no_movers():
+    """Neutral atoms at rest, no collisions, no injection: after the first
+    sort nothing changes cell, so the sort has no movers at all (empty radix
+    passes, every position a stayer) and the offsets come from the old ones
+    alone."""
+    log("case: all stayers")
+    cfg = W.config("tiny")
+    rng = np.random.default_rng(3)
+    n = 5000
+    p = {"r": rng.uniform(0.0, 0.99 * cfg.R, n), "z": rng.uniform(0.01 * cfg.L, 0.99 * cfg.L, n),
+         "vr": np.zeros(n), "vt": np.zeros(n), "vz": np.zeros(n),
+         "sp": np.full(n, W.CU, np.uint8)}
+    g, o = pair(cfg, parts=p, capacity=2 * n, collisions_off=True, sched=False)
+    for s in range(1, 5):
+        g.step(1)
+        o.step(1)
+        assert_same_state(g, o, "stayers step %d" % s)
+
+
 def test_tiny_config_200_steps_bit_exact():
     """32x64 cells, 50k particles, W = 100, seed 1, 200 steps."""
     cfg = W.config("tiny")
