@@ -13,7 +13,7 @@
 //           digit totals (one launch, one lane per digit);
 //   down -- start of every digit from the totals, plus the tile's prefix;
 //           stable ranking inside the tile: each wave walks its contiguous
-//           1024 keys 64 at a time, finds the lanes holding the same digit
+//           quarter of the tile 64 keys at a time, finds the lanes holding the same digit
 //           with one ballot per digit bit, ranks by popcount under the lane
 //           mask and carries a per-wave count per digit in LDS; a prefix
 //           over waves and digits then places every key at its tile-local
@@ -28,10 +28,12 @@
 // among stayers plus the movers before it (binary search over the sorted
 // movers); a mover's place is its rank among movers plus the stayers before
 // it, read off the previous order's per-key offsets and the count of movers
-// before each old position.  The result is the stable sort of all keys.
-// The result is the permutation (sorted position -> index) and the sorted
-// keys; the push moves the records.  No kernel waits on another block:
-// every launch finishes for any input.
+// before each old position (kept as one flag bit per old position and a
+// prefix per 32 of them).  The result is the stable sort of all keys: the
+// permutation (sorted position -> index) and the sorted keys; the push
+// moves the records.  The cell offsets follow from the old ones and the
+// sorted movers.  No kernel waits on another block: every launch finishes
+// for any input.
 #include "pd_internal.h"
 
 namespace pd {
@@ -71,7 +73,7 @@ static inline int tile_grid(int64_t cap, int per_cu, int tile) {
   return (int)(tiles < lim ? tiles : lim);
 }
 
-// per-tile digit histogram: each wave ranks its contiguous 1024 keys 64 at a
+// per-tile digit histogram: each wave ranks its contiguous quarter of the tile 64 keys at a
 // time (all 16 rankings first, so their ballot chains overlap), then adds
 // one count per distinct digit to its LDS row (no atomics)
 template <int DB, int IT>
@@ -315,7 +317,7 @@ __global__ void __launch_bounds__(256) k_radix_down(const uint32_t* __restrict__
   }
 }
 
-// one pass over tiles of 256 IT keys (IT = 4: short tiles, many blocks,
+// one pass over tiles of 256 IT keys (IT = kMoverItems: short tiles, many blocks,
 // for the movers, which are usually few)
 template <int DB, int IT>
 static void radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
