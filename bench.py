@@ -212,7 +212,7 @@ def main():
                                                                   off[-1]), file=sys.stderr)
     torch.cuda.init()
     stream = torch.cuda.current_stream()
-    cap = int(1.25 * cfg.n_init + cfg.inj_cu * nsteps + 40 * cfg.inj_e + 1_000_000)
+    cap = W.run_capacity(cfg, nsteps)
     precision = PD_FP32_MIXED if a.precision == "fp32" else PD_FP64_DET
     net, learned = None, {}
     if a.poisson == "learned":

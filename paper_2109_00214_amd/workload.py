@@ -114,6 +114,14 @@ def config(name, **kw):
     return replace(CONFIGS[name], **kw)
 
 
+def run_capacity(cfg, nsteps):
+    """Particle capacity of a run of nsteps: the initial population with a
+    quarter to spare, every scheduled neutral, forty steps' worth of emitted
+    electrons (they leave the gap within a few tens of steps) and a fixed
+    margin for the electrons the collisions create."""
+    return int(1.25 * cfg.n_init + cfg.inj_cu * nsteps + 40 * cfg.inj_e + 1_000_000)
+
+
 def _rng(seed, tag):
     return np.random.Generator(np.random.Philox(key=[int(seed), int(tag)]))
 

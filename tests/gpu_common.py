@@ -72,3 +72,45 @@ def assert_same_state(g, o, where=""):
     for t in range(3):
         assert np.array_equal(g.spectrum(t), do["spectrum"][t]), (where, "spectrum", t)
     return pg
+
+
+def _rel_close(x, y, rel):
+    """max |x - y| within rel times the largest |y|."""
+    scale = max(float(np.max(np.abs(y))), 1e-300) if y.size else 1.0
+    return y.size == 0 or float(np.max(np.abs(x - y))) <= rel * scale
+
+
+def assert_close_state(g, o, where="", rel=1e-10):
+    """As assert_same_state, with floating point results (positions,
+    velocities, potential, field, kinetic energies) within rel of the
+    oracle's (largest deviation over the largest magnitude) and every integer
+    result (keys, ids, species, counts, events, charge, spectra) identical.
+    The node charges are sums of fixed-point weights (each 1D weight rounded
+    to 2^-20, a particle of charge Z adding exactly Z 2^40 to its four
+    nodes): a position that differs by far less than a rounding step can
+    still round the other way and move Z 2^20 between two nodes.  So the
+    total charge must be exact and each node within 1e-4 of one particle's
+    charge (room for some twenty such roundings at one node)."""
+    pg, po = g.particles(), o.particles()
+    assert len(pg["r"]) == len(po["r"]), (where, "count", len(pg["r"]), len(po["r"]))
+    for k in ("sp", "id", "key"):
+        bad = np.nonzero(pg[k] != po[k])[0]
+        assert bad.size == 0, (where, k, int(bad[0]), pg[k][bad[0]], po[k][bad[0]], bad.size)
+    for k in ("r", "z", "vr", "vt", "vz"):
+        assert _rel_close(pg[k], po[k], rel), (where, k)
+    fg, fo = g.field(), o.field()
+    assert int(fg["Q"].sum()) == int(fo["Q"].sum()), where + " total Q"
+    dq = np.abs(fg["Q"] - fo["Q"])
+    assert int(dq.max()) <= int(1e-4 * 2.0 ** 40), (where, "Q", int(dq.max()))
+    for k in ("phi", "Er", "Ez"):
+        assert _rel_close(fg[k], fo[k], rel), (where, k)
+    dg, do = g.diag(), o.diag()
+    for k in ("n_alive", "next_id", "conflicts", "created", "charge_alive", "charge_absorbed",
+              "charge_injected"):
+        assert dg[k] == do[k], (where, k, dg[k], do[k])
+    for k in ("count", "events", "absorbed", "injected"):
+        assert np.array_equal(np.asarray(dg[k]), np.asarray(do[k])), (where, k, dg[k], do[k])
+    np.testing.assert_allclose(dg["ke_J"], do["ke_J"], rtol=rel, atol=0)
+    for t in range(3):
+        assert np.array_equal(g.spectrum(t), do["spectrum"][t]), (where, "spectrum", t)
+    return pg
