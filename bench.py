@@ -187,7 +187,7 @@ def run_ensemble(a):
 def main():
     a = parse()
     if a.gpus != 1:
-        print("bench.py: this build runs on one GPU only (--gpus %d requested)" % a.gpus,
+        print("bench.py: the step runs on one GPU only (--gpus %d requested)" % a.gpus,
               file=sys.stderr)
         sys.exit(2)
     if a.ensemble > 0:
