@@ -499,9 +499,9 @@ __device__ inline void place_blocks(const uint32_t* __restrict__ key,
                                     const uint32_t* __restrict__ ins,
                                     const uint32_t* __restrict__ n_mov,
                                     uint32_t* __restrict__ skey, uint32_t* __restrict__ perm,
-                                    uint32_t blk, uint32_t nblk) {
-  __shared__ uint32_t lins[kPlaceLds];
-  __shared__ uint32_t cb[2];
+                                    uint32_t blk, uint32_t nblk, uint32_t* sm) {
+  uint32_t* lins = sm;             // [kPlaceLds]
+  uint32_t* cb = sm + kPlaceLds;   // [2]
   const uint32_t nm = n_mov[0], n_prev = n_mov[1];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const uint32_t nch = (n_prev + kPlaceChunk - 1) / kPlaceChunk;
@@ -634,9 +634,9 @@ __device__ inline void offsets_blocks(const uint32_t* __restrict__ A,
                                       const uint32_t* __restrict__ mword, DevState* st,
                                       uint32_t* __restrict__ off, uint32_t nkeys,
                                       int64_t* __restrict__ Q, uint32_t nnodes, uint32_t blk,
-                                      uint32_t nblk) {
-  __shared__ uint32_t As[kOffMax];
-  __shared__ uint32_t split[2];
+                                      uint32_t nblk, uint32_t* sm) {
+  uint32_t* As = sm;              // [kOffMax]
+  uint32_t* split = sm + kOffMax;  // [2]
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const uint32_t stride = nblk * blockDim.x;
   for (uint32_t b = blk * blockDim.x + t; b < nnodes; b += stride) Q[b] = 0;
@@ -686,11 +686,14 @@ __global__ void __launch_bounds__(256) k_place_offsets(
     const uint32_t* __restrict__ n_mov, uint32_t* __restrict__ skey, uint32_t* __restrict__ perm,
     const uint32_t* __restrict__ A, DevState* st, uint32_t* __restrict__ off, uint32_t nkeys,
     int64_t* __restrict__ Q, uint32_t nnodes, uint32_t npl) {
+  // one LDS buffer for either kind of block (the larger need: the offsets')
+  static_assert(kPlaceLds <= kOffMax, "placement staging fits the offsets' buffer");
+  __shared__ uint32_t sm[kOffMax + 2];
   if (blockIdx.x < npl)
-    place_blocks(key, mbits, mword, ins, n_mov, skey, perm, blockIdx.x, npl);
+    place_blocks(key, mbits, mword, ins, n_mov, skey, perm, blockIdx.x, npl, sm);
   else
     offsets_blocks(A, n_mov, mbits, mword, st, off, nkeys, Q, nnodes, blockIdx.x - npl,
-                   gridDim.x - npl);
+                   gridDim.x - npl, sm);
 }
 
 void place_and_offsets(const uint32_t* key, const SortWork& w, DevState* st, uint32_t* off,
