@@ -115,6 +115,7 @@ __global__ void __launch_bounds__(256) k_radix_up(const uint32_t* __restrict__ k
 // waves of a block take consecutive runs of tiles; their run sums are
 // combined in LDS, then each wave rewrites its run.
 constexpr int kColWaves = 16;
+constexpr uint32_t kColHeld = 32;  // tiles per wave held in registers
 template <int R, int IT>
 __global__ void __launch_bounds__(64 * kColWaves) k_radix_colscan(uint32_t* __restrict__ hist,
                                                                   uint32_t* __restrict__ tot,
@@ -128,6 +129,27 @@ __global__ void __launch_bounds__(64 * kColWaves) k_radix_colscan(uint32_t* __re
   const uint32_t t0 = (uint32_t)w * ch;
   const uint32_t t1 = (t0 + ch < ntiles) ? t0 + ch : ntiles;
   uint32_t s = 0;
+  if (ch <= kColHeld) {
+    // the usual case (few movers): the run is loaded once, all at once, and
+    // rewritten from registers
+    uint32_t v[kColHeld];
+#pragma unroll
+    for (int u = 0; u < kColHeld; ++u)
+      v[u] = (t0 + u < t1) ? hist[(size_t)(t0 + u) * R + d] : 0u;
+#pragma unroll
+    for (int u = 0; u < kColHeld; ++u) s += v[u];
+    part[w][lane] = s;
+    __syncthreads();
+    uint32_t run = 0;
+    for (int q = 0; q < w; ++q) run += part[q][lane];
+    if (w == kColWaves - 1) tot[d] = run + s;
+#pragma unroll
+    for (int u = 0; u < kColHeld; ++u) {
+      if (t0 + u < t1) hist[(size_t)(t0 + u) * R + d] = run;
+      run += v[u];
+    }
+    return;
+  }
   for (uint32_t tb = t0; tb < t1; tb += 8) {
     uint32_t v[8];
 #pragma unroll
