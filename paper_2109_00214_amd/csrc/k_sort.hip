@@ -225,35 +225,23 @@ __global__ void __launch_bounds__(256) k_radix_down(const uint32_t* __restrict__
   __shared__ uint32_t dbase[R];
   __shared__ uint32_t tkey[(256 * IT)];
   __shared__ uint32_t tval[(256 * IT)];
+  __shared__ uint32_t tins[(256 * IT)];  // last pass: stayers before each mover
   __shared__ uint32_t sh[4];
   const uint32_t n = *np;
   const uint32_t ntiles = (n + (256 * IT) - 1) / (256 * IT);
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  // global start of every digit: exclusive scan of the digit totals
-  {
-    uint32_t c[PER];
-    uint32_t s = 0;
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int d = t * PER + q;
-      c[q] = (d < R) ? tot[d] : 0u;
-      s += c[q];
-    }
-    uint32_t total;
-    uint32_t run = block_scan256(s, &total, sh);
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int d = t * PER + q;
-      if (d < R) dbase[d] = run;
-      run += c[q];
-    }
-  }
+  const bool last = mp.skey != nullptr;
+  const uint32_t n_prev = last ? mp.st->n_alive : 0u;
+  bool have_base = false;
   for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    for (int d = t; d < R; d += 256) wh[0][d] = wh[1][d] = wh[2][d] = wh[3][d] = 0;
     const uint32_t tile0 = tile * (256 * IT);
     const uint32_t base = tile0 + w * ((256 * IT) / 4);
-    uint32_t kk[IT], vv[IT], rk[IT], cc[IT];
+    // everything the tile reads from memory is requested first: its keys
+    // and values, its prefix of every digit over the earlier tiles, and (in
+    // the last pass) the stayers before each mover, so that the reads are in
+    // flight together
+    uint32_t kk[IT], vv[IT], rk[IT], cc[IT], hh[PER], in[IT];
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
       const uint32_t idx = base + it * 64 + lane;
@@ -262,6 +250,36 @@ __global__ void __launch_bounds__(256) k_radix_down(const uint32_t* __restrict__
       kk[it] = kin[ic];
       vv[it] = FIRST ? idx : vin[ic];
     }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int d = t * PER + q;
+      hh[q] = (d < R) ? hist[(size_t)tile * R + d] : 0u;
+    }
+    if (last) {
+#pragma unroll
+      for (int it = 0; it < IT; ++it) in[it] = stayers_before(mp, n_prev, kk[it], vv[it]);
+    }
+    if (!have_base) {
+      // global start of every digit: exclusive scan of the digit totals
+      have_base = true;
+      uint32_t c[PER];
+      uint32_t s = 0;
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int d = t * PER + q;
+        c[q] = (d < R) ? tot[d] : 0u;
+        s += c[q];
+      }
+      uint32_t total;
+      uint32_t run = block_scan256(s, &total, sh);
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int d = t * PER + q;
+        if (d < R) dbase[d] = run;
+        run += c[q];
+      }
+    }
+    for (int d = t; d < R; d += 256) wh[0][d] = wh[1][d] = wh[2][d] = wh[3][d] = 0;
 #pragma unroll
     for (int it = 0; it < IT; ++it)
       rk[it] = match_rank<DB>((kk[it] >> shift) & mask, base + it * 64 + lane < n, lt, &cc[it]);
@@ -293,7 +311,7 @@ __global__ void __launch_bounds__(256) k_radix_down(const uint32_t* __restrict__
         const int d = t * PER + q;
         if (d < R) {
           const uint32_t a0 = wh[0][d], a1 = wh[1][d], a2 = wh[2][d];
-          gofs[d] = dbase[d] + hist[(size_t)tile * R + d] - run;
+          gofs[d] = dbase[d] + hh[q] - run;
           wh[0][d] = run;
           wh[1][d] = run + a0;
           wh[2][d] = run + a0 + a1;
@@ -309,11 +327,12 @@ __global__ void __launch_bounds__(256) k_radix_down(const uint32_t* __restrict__
         const uint32_t lp = wh[w][(kk[it] >> shift) & mask] + rk[it];
         tkey[lp] = kk[it];
         tval[lp] = vv[it];
+        if (last) tins[lp] = in[it];
       }
     }
     __syncthreads();
     const uint32_t cnt = (n - tile0 < (uint32_t)(256 * IT)) ? (n - tile0) : (uint32_t)(256 * IT);
-    if (!mp.skey) {
+    if (!last) {
 #pragma unroll 4
       for (uint32_t q = t; q < cnt; q += 256) {
         const uint32_t k = tkey[q];
@@ -323,12 +342,10 @@ __global__ void __launch_bounds__(256) k_radix_down(const uint32_t* __restrict__
       }
     } else {
       // last pass: place the movers (p = final rank among the movers)
-      const uint32_t n_prev = mp.st->n_alive;
 #pragma unroll 4
       for (uint32_t q = t; q < cnt; q += 256) {
-        const uint32_t k = tkey[q], i = tval[q];
+        const uint32_t k = tkey[q], i = tval[q], ins = tins[q];
         const uint32_t p = gofs[(k >> shift) & mask] + q;
-        const uint32_t ins = stayers_before(mp, n_prev, k, i);
         kout[p] = k;  // the movers' keys in order (for the offsets)
         mp.ins[p] = ins;
         mp.skey[ins + p] = k;
