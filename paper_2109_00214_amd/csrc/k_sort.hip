@@ -718,7 +718,7 @@ __device__ inline void offsets_blocks(const uint32_t* __restrict__ A,
 
 // The stayers' placement and the offsets read nothing the other writes
 // (both take the old order's live count from n_mov[1]): one launch, the
-// placement's blocks first.
+// offsets' blocks first (their chains of dependent reads are the longer).
 __global__ void __launch_bounds__(256) k_place_offsets(
     const uint32_t* __restrict__ key, const uint32_t* __restrict__ mbits,
     const uint32_t* __restrict__ mword, const uint32_t* __restrict__ ins,
@@ -728,11 +728,11 @@ __global__ void __launch_bounds__(256) k_place_offsets(
   // one LDS buffer for either kind of block (the larger need: the offsets')
   static_assert(kPlaceLds <= kOffMax, "placement staging fits the offsets' buffer");
   __shared__ uint32_t sm[kOffMax + 2];
-  if (blockIdx.x < npl)
-    place_blocks(key, mbits, mword, ins, n_mov, skey, perm, blockIdx.x, npl, sm);
+  const uint32_t nof = gridDim.x - npl;  // the offsets' blocks come first
+  if (blockIdx.x >= nof)
+    place_blocks(key, mbits, mword, ins, n_mov, skey, perm, blockIdx.x - nof, npl, sm);
   else
-    offsets_blocks(A, n_mov, mbits, mword, st, off, nkeys, Q, nnodes, blockIdx.x - npl,
-                   gridDim.x - npl, sm);
+    offsets_blocks(A, n_mov, mbits, mword, st, off, nkeys, Q, nnodes, blockIdx.x, nof, sm);
 }
 
 void place_and_offsets(const uint32_t* key, const SortWork& w, DevState* st, uint32_t* off,
