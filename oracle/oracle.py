@@ -46,44 +46,51 @@ def oracle_lib():
     if _lib is None:
         if not os.path.exists(_LIB):
             build_oracle(force=False)
-        lib = C.CDLL(_LIB)
-        P = C.c_void_p
-        dp = C.POINTER(C.c_double)
-        lib.or_create.restype = P
-        lib.or_create.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, C.c_double,
-                                  C.c_double, C.c_double, C.c_uint64, C.c_int, C.c_int, C.c_int]
-        lib.or_destroy.argtypes = [P]
-        lib.or_last_error.restype = C.c_char_p
-        lib.or_set_species.argtypes = [P, C.c_int, P, P]
-        lib.or_set_cross_section.argtypes = [P, C.c_int, C.c_double, C.c_int, C.c_double, P]
-        lib.or_inject.argtypes = [P, C.c_int64, P, P, P, P, P, P]
-        lib.or_schedule_injection.argtypes = [P, C.c_int, P, P, P, P, P, P, P]
-        lib.or_step.argtypes = [P, C.c_int]
-        for nm in ("sort", "collide", "deposit", "poisson", "field", "push",
-                   "compact_inject", "end"):
-            getattr(lib, "or_stage_" + nm).argtypes = [P]
-        lib.or_count.restype = C.c_int64
-        lib.or_count.argtypes = [P]
-        lib.or_get_particles.argtypes = [P] + [P] * 8
-        lib.or_set_velocities.argtypes = [P, P, P, P]
-        lib.or_get_field.argtypes = [P, P, P, P, P]
-        lib.or_set_charge.argtypes = [P, P]
-        lib.or_get_offsets.argtypes = [P, P]
-        lib.or_get_collisions.argtypes = [P, P, P, P]
-        lib.or_get_diag.argtypes = [P, C.POINTER(_Diag)]
-        lib.or_philox4x32_10.argtypes = [P, P, P]
-        lib.or_poisson_solve.argtypes = [P, P, P]
-        lib.or_poisson_residual.argtypes = [P, P, P, dp, dp]
-        lib.or_poisson_residual.restype = None
-        lib.or_isotropic.argtypes = [P, C.c_uint32, C.c_uint32, P]
-        lib.or_rotation.argtypes = [C.c_double, C.c_double, P]
-        lib.or_split_literal.argtypes = [P, C.c_double, C.c_double, P]
-        lib.or_node_volumes.argtypes = [P, P, P]
-        lib.or_cross_section.restype = C.c_double
-        lib.or_cross_section.argtypes = [P, C.c_int, C.c_double]
-        del dp
-        _lib = lib
+        _lib = load_oracle(_LIB)
     return _lib
+
+
+def load_oracle(path):
+    """A ctypes handle of an oracle library built at ``path`` (the tests that
+    check that a pin catches a planted mistake load mutated copies this way)."""
+    lib = C.CDLL(path)
+    P = C.c_void_p
+    dp = C.POINTER(C.c_double)
+    lib.or_create.restype = P
+    lib.or_create.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, C.c_double,
+                              C.c_double, C.c_double, C.c_uint64, C.c_int, C.c_int, C.c_int]
+    lib.or_destroy.argtypes = [P]
+    lib.or_last_error.restype = C.c_char_p
+    lib.or_set_species.argtypes = [P, C.c_int, P, P]
+    lib.or_set_cross_section.argtypes = [P, C.c_int, C.c_double, C.c_int, C.c_double, P]
+    lib.or_inject.argtypes = [P, C.c_int64, P, P, P, P, P, P]
+    lib.or_schedule_injection.argtypes = [P, C.c_int, P, P, P, P, P, P, P]
+    lib.or_step.argtypes = [P, C.c_int]
+    for nm in ("sort", "collide", "deposit", "poisson", "field", "push",
+               "compact_inject", "end"):
+        getattr(lib, "or_stage_" + nm).argtypes = [P]
+    lib.or_count.restype = C.c_int64
+    lib.or_count.argtypes = [P]
+    lib.or_get_particles.argtypes = [P] + [P] * 8
+    lib.or_set_velocities.argtypes = [P, P, P, P]
+    lib.or_get_field.argtypes = [P, P, P, P, P]
+    lib.or_set_charge.argtypes = [P, P]
+    lib.or_set_potential.argtypes = [P, P]
+    lib.or_get_offsets.argtypes = [P, P]
+    lib.or_get_collisions.argtypes = [P, P, P, P]
+    lib.or_get_diag.argtypes = [P, C.POINTER(_Diag)]
+    lib.or_philox4x32_10.argtypes = [P, P, P]
+    lib.or_poisson_solve.argtypes = [P, P, P]
+    lib.or_poisson_residual.argtypes = [P, P, P, dp, dp]
+    lib.or_poisson_residual.restype = None
+    lib.or_isotropic.argtypes = [P, C.c_uint32, C.c_uint32, P]
+    lib.or_rotation.argtypes = [C.c_double, C.c_double, P]
+    lib.or_split_literal.argtypes = [P, C.c_double, C.c_double, P]
+    lib.or_node_volumes.argtypes = [P, P, P]
+    lib.or_cross_section.restype = C.c_double
+    lib.or_cross_section.argtypes = [P, C.c_int, C.c_double]
+    del dp
+    return lib
 
 
 def _p(a):
@@ -104,8 +111,8 @@ class Oracle:
     """One oracle simulation (mirrors the C-ABI calls of the GPU library)."""
 
     def __init__(self, nr, nz, R, L, V, dt, weight, seed, enable_di=True,
-                 deposit_off=False, collisions_off=False):
-        self.lib = oracle_lib()
+                 deposit_off=False, collisions_off=False, lib=None):
+        self.lib = oracle_lib() if lib is None else lib
         self.nr, self.nz = nr, nz
         self.R, self.L, self.V, self.dt, self.weight, self.seed = R, L, V, dt, weight, seed
         h = self.lib.or_create(nr, nz, R, L, V, dt, weight, seed, int(enable_di),
@@ -187,6 +194,11 @@ class Oracle:
         q = np.ascontiguousarray(Q, dtype=np.int64).reshape(-1)
         assert q.size == (self.nr + 1) * (self.nz + 1)
         self.lib.or_set_charge(self.h, _p(q))
+
+    def set_potential(self, phi):
+        f = np.ascontiguousarray(phi, dtype=np.float64).reshape(-1)
+        assert f.size == (self.nr + 1) * (self.nz + 1)
+        self.lib.or_set_potential(self.h, _p(f))
 
     def offsets(self):
         o = np.zeros(6 * self.nr * self.nz + 1, np.int64)

@@ -15,9 +15,10 @@
  * Parity pins for every function are in tests/test_oracle_*.py.  Two
  * pieces are pinned only by conservation identities ("parity unpinned"
  * beyond them): the scattering law of the e-e stage of the double
- * ionization (Eq. 14 says only "similar to Coulomb scattering") and the
- * energy sharing of the single-ionization events (the paper calls their
- * schemes mature and gives none).
+ * ionization (Sec. 2.2, Eq. 14 names a Coulomb-like stage but gives no law;
+ * an isotropic elastic collision of equal masses in the centre-of-mass
+ * frame is used) and the energy sharing of the single-ionization events
+ * (Sec. 2.2 refers to earlier work for them and states no scheme).
  */
 #include "pd_oracle.h"
 
@@ -631,6 +632,11 @@ void or_stage_deposit(or_sim* s) {
 
 void or_set_charge(or_sim* s, const int64_t* Q) {
   memcpy(s->Q, Q, sizeof(int64_t) * (size_t)(s->nr + 1) * (s->nz + 1));
+}
+
+/* set the node potential directly (tests of the field and gather stages) */
+void or_set_potential(or_sim* s, const double* phi) {
+  memcpy(s->phi, phi, sizeof(double) * (size_t)(s->nr + 1) * (s->nz + 1));
 }
 
 /* ------------------------------------------------------------------ */

@@ -83,6 +83,8 @@ void or_get_field(const or_sim* s, double* phi, double* Er, double* Ez,
                   int64_t* Q);
 /* set the node charge directly (tests of the Poisson stage) */
 void or_set_charge(or_sim* s, const int64_t* Q);
+/* set the node potential directly (tests of the field and gather stages) */
+void or_set_potential(or_sim* s, const double* phi);
 void or_get_offsets(const or_sim* s, int64_t* offsets); /* 6*nr*nz + 2 */
 /* per-electron decisions of the last collide stage, in sorted order */
 void or_get_collisions(const or_sim* s, uint8_t* choice, uint32_t* target,
