@@ -12,8 +12,9 @@
 
 namespace pd {
 
-// f[c][a] = -(rho / eps0) at interior row c+1, node a, rho = Q qunit / V_node;
-// the electrode rows of phi take the vacuum values (the sine series is zero).
+// The right-hand side on the interior rows: f[c][a] = -(rho / eps0) at row
+// c+1, radial node a, rho = Q qunit / V_node; the electrode rows of phi take
+// the vacuum values (the sine series is zero there).
 __global__ void __launch_bounds__(256) k_rhs(const int64_t* __restrict__ Q,
                                              const double* __restrict__ Vnode, double qunit,
                                              int nr, int nz, double V, double* __restrict__ f,
@@ -31,99 +32,98 @@ __global__ void __launch_bounds__(256) k_rhs(const int64_t* __restrict__ Q,
   }
 }
 
-// Out[a][b] = sum_c X[c][a] S[c][b], c ascending, S[c][b] the DST-I entry of
-// sine index k = b+1 (resp. c+1) and node j = c+1 (resp. b+1).  The entry
-// depends only on m = ((c+1)(b+1)) mod 2nz, so it is looked up in a table T
-// of 2nz values (built on the host with the same formula as the entries
-// themselves) held in LDS; m advances by b+1 per term.  Block = 4 waves
-// covering 64 b (lanes) x 8 a (2 per wave: two independent accumulation
-// chains per lane); the block's X columns (all c) sit in LDS too.  No global
-// traffic in the loop and no barriers.
-//   FWD: X = f (rows = interior z nodes), Out -> fh[a][b] (a = r node, b = mode)
-//   INV: X = G (rows = modes),            Out -> phi[b+1][a] with phi_vac, 2/nz
-constexpr int kSineA = 4, kSineWaves = 4, kSineAPW = kSineA / kSineWaves;
+// Sine transform with every sum in ascending order of its index:
+//   Out[b][a] = sum_{c = 0 .. M-1} X[c][a] Sm[b][c], from +0.0, c ascending,
+// Sm[b][c] = sin(pi (b+1)(c+1) / nz) (the DST-I matrix, symmetric; a host
+// table).
+//   FWD: X = f (c = interior row, a = radial node), Out -> fh[b][a] (b = mode)
+//   INV: X = G (c = mode),                          Out -> phi[b+1][a], with
+//        phi_vac added and the factor 2/nz.
+// Each output is one chain of dependent additions.  A wave's lanes take
+// consecutive radial nodes a (the radial extent split into equal groups of at
+// most 64) and two b, the same for every lane: a term costs one vector load
+// of a row of X (coalesced; the four waves of a block read the same rows) and
+// the two sine entries come as scalar operands, eight consecutive c of a
+// table row per scalar load.  No LDS: with one wave per SIMD every
+// instruction takes an issue slot, and the operands need no staging.  The
+// row loads are requested kFoAhead terms ahead; no contraction: each term is
+// the product rounded, then the sum rounded, as written.
+constexpr int kFoWaves = 4, kFoRb = 3, kFoAhead = 16;
+constexpr int kFoB = kFoWaves * kFoRb;  // b per block
 
 template <bool FWD>
-__global__ void __launch_bounds__(64 * kSineWaves) k_sine(const double* __restrict__ X,
-                                                          const double* __restrict__ T, int nr,
-                                                          int nz, double V,
-                                                          double* __restrict__ out) {
-  extern __shared__ double lds[];
-  constexpr int NT = 64 * kSineWaves;
-  const int W = nr + 1, M = nz - 1, N2 = 2 * nz;
-  const int nA = W, nB = M, nC = M;
-  double* Tsh = lds;             // [2 nz]
-  double* Xsh = lds + N2;        // [nC][kSineA]
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int b = blockIdx.x * 64 + lane;
-  const int bl = (b < nB) ? b : nB - 1;
-  const int a0 = blockIdx.y * kSineA;
-  // loads use clamped (always valid) indices and no branches, so that a
-  // thread's loads are all in flight together
-  for (int i0 = 0; i0 < N2; i0 += NT * 4) {
-    double v[4];
+__global__ void __launch_bounds__(256, 1) k_sine_fo(const double* __restrict__ X,
+                                                    const double* __restrict__ Sm, int nr,
+                                                    int nz, int ag, double V,
+                                                    double* __restrict__ out) {
+  const int W = nr + 1, M = nz - 1;
+  const int t = threadIdx.x, lane = t & 63;
+  const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int a = (int)blockIdx.x * ag + lane;
+  const bool live = lane < ag && a < W;
+  const int ac = live ? a : 0;
+  const int bw = (int)blockIdx.y * kFoB + w * kFoRb;  // this wave's first b
+  const double* __restrict__ sr[kFoRb];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int i = i0 + NT * u + t;
-      v[u] = T[(i < N2) ? i : N2 - 1];
-    }
+  for (int q = 0; q < kFoRb; ++q) sr[q] = Sm + (size_t)((bw + q < M) ? bw + q : M - 1) * M;
+  double acc[kFoRb];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (i0 + NT * u + t < N2) Tsh[i0 + NT * u + t] = v[u];
+  for (int q = 0; q < kFoRb; ++q) acc[q] = 0.0;
+  // ring of row values requested kFoAhead terms ahead
+  const uint32_t last = (uint32_t)(M - 1) * (uint32_t)W + (uint32_t)ac;
+  double xr[kFoAhead];
+#pragma unroll
+  for (int u = 0; u < kFoAhead; ++u) {
+    const uint32_t o = (uint32_t)u * (uint32_t)W + (uint32_t)ac;
+    xr[u] = X[(o < last) ? o : last];
   }
-  const int nX = nC * kSineA;
-  for (int i0 = 0; i0 < nX; i0 += NT * 4) {
-    double v[4];
-    int ix[4];
+  const double* __restrict__ xp = X + (size_t)kFoAhead * W + ac;
+  const int mfull = (M / kFoAhead) * kFoAhead;
+  int c0 = 0;
+  // a block of kFoAhead terms in two halves; each half's sine entries (three
+  // table rows, eight words each) are loaded just before it, which keeps
+  // them within the scalar registers
+  auto block = [&](bool clamp) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      ix[u] = i0 + NT * u + t;
-      const int idx = (ix[u] < nX) ? ix[u] : nX - 1;
-      const int c = idx / kSineA, a = a0 + idx % kSineA;
-      v[u] = X[(size_t)c * W + ((a < nA) ? a : nA - 1)];
-      if (a >= nA) v[u] = 0.0;
+    for (int h = 0; h < kFoAhead; h += 8) {
+      double sv[kFoRb][8];
+#pragma unroll
+      for (int q = 0; q < kFoRb; ++q)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) sv[q][u] = sr[q][c0 + h + u];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        double p[kFoRb];
+#pragma unroll
+        for (int q = 0; q < kFoRb; ++q) p[q] = xr[h + u] * sv[q][u];
+        if (clamp) {
+          const uint32_t o = (uint32_t)(c0 + kFoAhead + h + u) * (uint32_t)W + (uint32_t)ac;
+          xr[h + u] = X[(o < last) ? o : last];
+        } else {
+          xr[h + u] = xp[(size_t)(h + u) * W];
+        }
+#pragma unroll
+        for (int q = 0; q < kFoRb; ++q) acc[q] = acc[q] + p[q];
+      }
+      __builtin_amdgcn_sched_barrier(0);
     }
+    xp += (size_t)kFoAhead * W;
+  };
+  // the blocks whose look-ahead rows all exist, then the last full block,
+  // then the remaining rows (already in the ring)
+  for (; c0 + 2 * kFoAhead <= M; c0 += kFoAhead) block(false);
+  for (; c0 < mfull; c0 += kFoAhead) block(true);
+  for (int u = 0; c0 + u < M; ++u) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (ix[u] < nX) Xsh[ix[u]] = v[u];
+    for (int q = 0; q < kFoRb; ++q) acc[q] = acc[q] + (xr[u] * sr[q][c0 + u]);
   }
-  __syncthreads();
-  double acc[kSineAPW];
+  if (!live) return;
 #pragma unroll
-  for (int q = 0; q < kSineAPW; ++q) acc[q] = 0.0;
-  const double* x0 = Xsh + kSineAPW * w;
-  const int step = bl + 1;
-  int m = step;  // (c+1)(b+1) mod 2nz at c = 0
-  const int nfull = (nC / 8) * 8;
-  for (int c0 = 0; c0 < nfull; c0 += 8) {
-    double s[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      s[u] = Tsh[m];
-      m += step;
-      if (m >= N2) m -= N2;
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-#pragma unroll
-      for (int q = 0; q < kSineAPW; ++q)
-        acc[q] = acc[q] + (x0[(c0 + u) * kSineA + q] * s[u]);
-    }
-  }
-  for (int c = nfull; c < nC; ++c) {
-    const double s = Tsh[m];
-    m += step;
-    if (m >= N2) m -= N2;
-#pragma unroll
-    for (int q = 0; q < kSineAPW; ++q) acc[q] = acc[q] + (x0[c * kSineA + q] * s);
-  }
-  if (b >= nB) return;
-#pragma unroll
-  for (int q = 0; q < kSineAPW; ++q) {
-    const int a = a0 + kSineAPW * w + q;
-    if (a >= nA) break;
+  for (int q = 0; q < kFoRb; ++q) {
+    const int b = bw + q;
+    if (b >= M) break;
     if (FWD) {
-      out[(size_t)a * M + b] = acc[q];
+      out[(size_t)b * W + a] = acc[q];
     } else {
       const int j = b + 1;
       const double vac = (-V) + (V * ((double)j / (double)nz));
@@ -132,144 +132,153 @@ __global__ void __launch_bounds__(64 * kSineWaves) k_sine(const double* __restri
   }
 }
 
-// Tridiagonal solve per sine mode with the host-factored reciprocals
-// (tinv) and upper factors (tcp): dp_0 = f_0 inv_0, dp_i = (f_i - a_i
-// dp_{i-1}) inv_i; x_nr = dp_nr, x_i = dp_i - cp_i x_{i+1}.  A block takes
-// kThomasModes modes; their columns are staged in LDS with coalesced loads;
-// the upper factors are staged by the idle waves while the first wave runs
-// the forward sweep.  Each sweep fetches the next 8 rows from LDS while it
-// computes the current 8.  The result is written mode-major (G[k][i]) for
-// the inverse transform.
-constexpr int kThomasModes = 8;
+// Tridiagonal solve per sine mode with the host-factored reciprocals (tinv)
+// and upper factors (tcp), both [mode][i]: dp_0 = f_0 inv_0,
+// dp_i = (f_i - a_i dp_{i-1}) inv_i; x_nr = dp_nr, x_i = dp_i - cp_i x_{i+1}.
+// Each mode is one chain of dependent operations, so one lane per mode.  The
+// block first stages every input of its modes in LDS with all loads in
+// flight at once (one memory latency), then each lane runs its two sweeps
+// from LDS with the next kThomasAhead rows read ahead into registers (dp
+// and then x overwrite the right-hand side in place).  The result is
+// written [mode][i], the layout the inverse transform reads.
+constexpr int kThomasAhead = 8;
+constexpr int kThomasStage = 12;  // staged words per thread and input array
 
-__global__ void __launch_bounds__(256) k_thomas_lds(const double* __restrict__ fh,
-                                                   const double* __restrict__ tinv,
-                                                   const double* __restrict__ tcp,
-                                                   const double* __restrict__ ra, int nr, int nz,
-                                                   double* __restrict__ G) {
+__global__ void __launch_bounds__(256) k_thomas_fo(const double* __restrict__ fh,
+                                                  const double* __restrict__ tinv,
+                                                  const double* __restrict__ tcp,
+                                                  const double* __restrict__ ra, int nr, int nz,
+                                                  int mpb, double* __restrict__ G) {
   extern __shared__ double sh[];
-  const int W = nr + 1, M = nz - 1;
-  const int nL = W * kThomasModes;
-  double* fL = sh;                 // [W][kThomasModes]: rhs, then dp, then x
-  double* tL = sh + nL;            // reciprocals
-  double* cL = sh + 2 * nL;        // upper factors
-  double* aL = sh + 3 * nL;        // [W] lower coefficients
-  const int k0 = blockIdx.x * kThomasModes;
+  const int M = nz - 1, W = nr + 1;
+  const int nL = W * mpb;
+  double* fL = sh;            // [W][mpb] rhs, then dp
+  double* iL = sh + nL;       // reciprocals
+  double* cL = sh + 2 * nL;   // upper factors
+  double* aL = sh + 3 * nL;   // [W] lower coefficients
   const int t = threadIdx.x;
+  const int k0 = (int)blockIdx.x * mpb;
   for (int i = t; i < W; i += 256) aL[i] = ra[i];
-  // clamped indices, no branches around the loads (all in flight together)
-  for (int j0 = 0; j0 < nL; j0 += 256 * 4) {
-    double fv[4], tv[4];
-    int ix[4];
+  // every load in flight at once (mpb * W <= kThomasStage * 256 by the
+  // choice of mpb), then the stores; element e = (mode kk, row i), i fastest
+  double fv[kThomasStage], iv[kThomasStage], cv[kThomasStage];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      ix[u] = j0 + 256 * u + t;
-      const int idx = (ix[u] < nL) ? ix[u] : nL - 1;
-      const int i = idx / kThomasModes, k = k0 + idx % kThomasModes;
-      const size_t q = (size_t)i * M + ((k < M) ? k : M - 1);
-      fv[u] = fh[q];
-      tv[u] = tinv[q];
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (ix[u] < nL) {
-        fL[ix[u]] = fv[u];
-        tL[ix[u]] = tv[u];
-      }
+  for (int u = 0; u < kThomasStage; ++u) {
+    int e = 256 * u + t;
+    e = (e < nL) ? e : nL - 1;
+    const int kk = e / W, i = e % W;
+    const int k = (k0 + kk < M) ? k0 + kk : M - 1;
+    const size_t q = (size_t)k * W + i;
+    fv[u] = fh[q];
+    iv[u] = tinv[q];
+    cv[u] = tcp[q];
   }
-  __syncthreads();
-  const bool act = (t < kThomasModes) && (k0 + t < M);
-  double dp = 0.0;
-  if (t < 64) {
-    if (act) {
-      dp = fL[t] * tL[t];
-      fL[t] = dp;
-      double fa[8], ia[8], aa[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int i = (1 + u <= nr) ? 1 + u : nr;
-        fa[u] = fL[i * kThomasModes + t];
-        ia[u] = tL[i * kThomasModes + t];
-        aa[u] = aL[i];
-      }
-      for (int i0 = 1; i0 <= nr; i0 += 8) {
-        double fb[8], ib[8], ab[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int i = (i0 + 8 + u <= nr) ? i0 + 8 + u : nr;
-          fb[u] = fL[i * kThomasModes + t];
-          ib[u] = tL[i * kThomasModes + t];
-          ab[u] = aL[i];
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          if (i0 + u <= nr) {
-            dp = (fa[u] - (aa[u] * dp)) * ia[u];
-            fL[(i0 + u) * kThomasModes + t] = dp;
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          fa[u] = fb[u];
-          ia[u] = ib[u];
-          aa[u] = ab[u];
-        }
-      }
-    }
-  } else {
-    for (int j0 = 0; j0 < nL; j0 += 192 * 4) {
-      double cv[4];
-      int ix[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        ix[u] = j0 + 192 * u + (t - 64);
-        const int idx = (ix[u] < nL) ? ix[u] : nL - 1;
-        const int i = idx / kThomasModes, k = k0 + idx % kThomasModes;
-        cv[u] = tcp[(size_t)i * M + ((k < M) ? k : M - 1)];
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (ix[u] < nL) cL[ix[u]] = cv[u];
+  for (int u = 0; u < kThomasStage; ++u) {
+    const int e = 256 * u + t;
+    if (e < nL) {
+      const int kk = e / W, i = e % W;
+      fL[i * mpb + kk] = fv[u];
+      iL[i * mpb + kk] = iv[u];
+      cL[i * mpb + kk] = cv[u];
     }
   }
   __syncthreads();
-  if (act) {
+  // the two sweeps, one lane per mode: full runs of kThomasAhead rows with no
+  // bounds checks (the rows of the next run are read while this one is
+  // computed), then the remaining rows one at a time
+  if (t < mpb) {
+    double dp = fL[t] * iL[t];
+    fL[t] = dp;
+    {
+      double fa[kThomasAhead], ia[kThomasAhead], aa[kThomasAhead];
+      double fb[kThomasAhead], ib[kThomasAhead], ab[kThomasAhead];
+      auto rd = [&](double* f, double* iv, double* a, int i0) {
+#pragma unroll
+        for (int u = 0; u < kThomasAhead; ++u) {
+          const int i = (i0 + u <= nr) ? i0 + u : nr;
+          f[u] = fL[i * mpb + t];
+          iv[u] = iL[i * mpb + t];
+          a[u] = aL[i];
+        }
+      };
+      auto run = [&](const double* f, const double* iv, const double* a, int i0) {
+#pragma unroll
+        for (int u = 0; u < kThomasAhead; ++u) {
+          dp = (f[u] - (a[u] * dp)) * iv[u];
+          fL[(i0 + u) * mpb + t] = dp;
+        }
+      };
+      int i = 1;
+      rd(fa, ia, aa, 1);
+      for (; i + 2 * kThomasAhead - 1 <= nr; i += 2 * kThomasAhead) {
+        rd(fb, ib, ab, i + kThomasAhead);
+        run(fa, ia, aa, i);
+        rd(fa, ia, aa, i + 2 * kThomasAhead);
+        run(fb, ib, ab, i + kThomasAhead);
+      }
+      if (i + kThomasAhead - 1 <= nr) {
+        run(fa, ia, aa, i);
+        i += kThomasAhead;
+      }
+      for (; i <= nr; ++i) {
+        dp = (fL[i * mpb + t] - (aL[i] * dp)) * iL[i * mpb + t];
+        fL[i * mpb + t] = dp;
+      }
+    }
+    // backward sweep from x_nr = dp_nr; x overwrites dp in LDS
     double x = dp;
-    double fa[8], ca[8];
+    {
+      double da[kThomasAhead], ca[kThomasAhead], db[kThomasAhead], cb[kThomasAhead];
+      auto rd = [&](double* d, double* c, int i0) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int i = (nr - 1 - u >= 0) ? nr - 1 - u : 0;
-      fa[u] = fL[i * kThomasModes + t];
-      ca[u] = cL[i * kThomasModes + t];
-    }
-    for (int i0 = nr - 1; i0 >= 0; i0 -= 8) {
-      double fb[8], cb[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int i = (i0 - 8 - u >= 0) ? i0 - 8 - u : 0;
-        fb[u] = fL[i * kThomasModes + t];
-        cb[u] = cL[i * kThomasModes + t];
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        if (i0 - u >= 0) {
-          x = fa[u] - (ca[u] * x);
-          fL[(i0 - u) * kThomasModes + t] = x;
+        for (int u = 0; u < kThomasAhead; ++u) {
+          const int i = (i0 - u >= 0) ? i0 - u : 0;
+          d[u] = fL[i * mpb + t];
+          c[u] = cL[i * mpb + t];
         }
-      }
+      };
+      auto run = [&](const double* d, const double* c, int i0) {
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        fa[u] = fb[u];
-        ca[u] = cb[u];
+        for (int u = 0; u < kThomasAhead; ++u) {
+          x = d[u] - (c[u] * x);
+          fL[(i0 - u) * mpb + t] = x;
+        }
+      };
+      int i = nr - 1;
+      rd(da, ca, nr - 1);
+      for (; i - 2 * kThomasAhead + 1 >= 0; i -= 2 * kThomasAhead) {
+        rd(db, cb, i - kThomasAhead);
+        run(da, ca, i);
+        rd(da, ca, i - 2 * kThomasAhead);
+        run(db, cb, i - kThomasAhead);
+      }
+      if (i - kThomasAhead + 1 >= 0) {
+        run(da, ca, i);
+        i -= kThomasAhead;
+      }
+      for (; i >= 0; --i) {
+        x = fL[i * mpb + t] - (cL[i * mpb + t] * x);
+        fL[i * mpb + t] = x;
       }
     }
   }
   __syncthreads();
-#pragma unroll 8
-  for (int idx = t; idx < nL; idx += 256) {
-    const int kk = idx / W, i = idx % W, k = k0 + kk;
-    if (k < M) G[(size_t)k * W + i] = fL[i * kThomasModes + kk];
+  // the block's solutions to G[mode][i], coalesced over the rows
+  for (int e = t; e < nL; e += 256) {
+    const int kk = e / W, i = e % W, k = k0 + kk;
+    if (k < M) G[(size_t)k * W + i] = fL[i * mpb + kk];
   }
+}
+
+// modes per Thomas block: the block's three input columns per mode and the
+// lower coefficients in 64 KB of LDS
+static int thomas_modes(int nr) {
+  int mpb = 64;
+  while (mpb > 1 && (((size_t)3 * mpb + 1) * (size_t)(nr + 1) * sizeof(double) > 65536 ||
+                     (size_t)mpb * (size_t)(nr + 1) > (size_t)kThomasStage * 256))
+    mpb >>= 1;
+  return mpb;
 }
 
 void poisson_direct(const Grid& g, FieldWork& fw, hipStream_t s) {
@@ -277,19 +286,21 @@ void poisson_direct(const Grid& g, FieldWork& fw, hipStream_t s) {
   int gr = (M * W + 255) / 256;
   if (gr > 4096) gr = 4096;
   k_rhs<<<gr, 256, 0, s>>>(fw.Q, fw.Vnode, fw.qunit, nr, nz, g.V, fw.f, fw.phi);
-  const dim3 grid((M + 63) / 64, (W + kSineA - 1) / kSineA);
-  const size_t xlds = sizeof(double) * ((size_t)M * kSineA + 2 * (size_t)nz);
-  k_sine<true><<<grid, 64 * kSineWaves, xlds, s>>>(fw.f, fw.T, nr, nz, g.V, fw.fh);
-  k_thomas_lds<<<(M + kThomasModes - 1) / kThomasModes, 256, poisson_lds_bytes(nr, nz), s>>>(
-      fw.fh, fw.tinv, fw.tcp, fw.ra, nr, nz, fw.g);
-  k_sine<false><<<grid, 64 * kSineWaves, xlds, s>>>(fw.g, fw.T, nr, nz, g.V, fw.phi);
+  // the radial nodes in equal groups of at most 64 (one group per lane set)
+  const int ngrp = (W + 63) / 64, ag = (W + ngrp - 1) / ngrp;
+  const dim3 grid(ngrp, (M + kFoB - 1) / kFoB);
+  k_sine_fo<true><<<grid, 256, 0, s>>>(fw.f, fw.Sm, nr, nz, ag, g.V, fw.fh);
+  const int mpb = thomas_modes(nr);
+  k_thomas_fo<<<(M + mpb - 1) / mpb, 256, sizeof(double) * ((size_t)3 * mpb + 1) * W, s>>>(
+      fw.fh, fw.tinv, fw.tcp, fw.ra, nr, nz, mpb, fw.g);
+  k_sine_fo<false><<<grid, 256, 0, s>>>(fw.g, fw.Sm, nr, nz, ag, g.V, fw.phi);
 }
 
-// the larger of the two dynamic LDS needs (Thomas columns, transform rows)
-size_t poisson_lds_bytes(int nr, int nz) {
-  const size_t th = sizeof(double) * (3 * (size_t)kThomasModes + 1) * (size_t)(nr + 1);
-  const size_t tr = sizeof(double) * ((size_t)(nz - 1) * kSineA + 2 * (size_t)nz);
-  return th > tr ? th : tr;
+// the direct solve's limits: the full sine table (nz-1)^2 words; the
+// tridiagonal inputs of at least one mode in 64 KB of LDS
+bool direct_fits(int nr, int nz) {
+  return nz - 1 <= 2048 && (size_t)4 * (size_t)(nr + 1) * sizeof(double) <= 65536 &&
+         (size_t)(nr + 1) <= (size_t)kThomasStage * 256;
 }
 
 }  // namespace pd

@@ -228,9 +228,9 @@ void poisson_spectral(const Grid& g, FieldWork& fw, hipStream_t s) {
   const size_t lds = (size_t)2 * nz * sizeof(double);
   k_dst_mfma<true><<<grid, 256, lds, s>>>(fw.Q, fw.coef, nullptr, fw.T, nr, nz, g.V, fw.fh);
   const int P = (W + 63) / 64;
-  if (P <= 4) k_tri_scan<4><<<(M + 3) / 4, 256, 0, s>>>(fw.fh, fw.invT, fw.cT, fw.ra, nr, nz, fw.g);
-  else if (P <= 8) k_tri_scan<8><<<(M + 3) / 4, 256, 0, s>>>(fw.fh, fw.invT, fw.cT, fw.ra, nr, nz, fw.g);
-  else k_tri_scan<kTriMaxP><<<(M + 3) / 4, 256, 0, s>>>(fw.fh, fw.invT, fw.cT, fw.ra, nr, nz, fw.g);
+  if (P <= 4) k_tri_scan<4><<<(M + 3) / 4, 256, 0, s>>>(fw.fh, fw.tinv, fw.tcp, fw.ra, nr, nz, fw.g);
+  else if (P <= 8) k_tri_scan<8><<<(M + 3) / 4, 256, 0, s>>>(fw.fh, fw.tinv, fw.tcp, fw.ra, nr, nz, fw.g);
+  else k_tri_scan<kTriMaxP><<<(M + 3) / 4, 256, 0, s>>>(fw.fh, fw.tinv, fw.tcp, fw.ra, nr, nz, fw.g);
   k_dst_mfma<false><<<grid, 256, lds, s>>>(nullptr, nullptr, fw.g, fw.T, nr, nz, g.V, fw.phi);
 }
 

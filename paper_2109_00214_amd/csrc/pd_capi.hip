@@ -221,21 +221,21 @@ void build_tables(pd_ctx* c, std::vector<double>& Vnode, std::vector<double>& Vc
   }
   // per-mode tridiagonal factors of (D_r + mu_k), mu_k the eigenvalue of
   // the 3-point d2/dz2 on sin(pi k j / nz)
-  tinv.assign((size_t)(nr + 1) * M, 0.0);
+  tinv.assign((size_t)(nr + 1) * M, 0.0);  // [mode][i], i fastest
   tcp.assign((size_t)(nr + 1) * M, 0.0);
   for (int k = 1; k <= M; ++k) {
     const double h = std::sin((kPI * (double)k) / (2.0 * (double)nz));
     const double mu = -(4.0 * (h * h)) / (dz * dz);
     double inv = 1.0 / (rb[0] + mu);
     double cp = rc[0] * inv;
-    tinv[(size_t)0 * M + (k - 1)] = inv;
-    tcp[(size_t)0 * M + (k - 1)] = cp;
+    tinv[(size_t)(k - 1) * (nr + 1) + 0] = inv;
+    tcp[(size_t)(k - 1) * (nr + 1) + 0] = cp;
     for (int i = 1; i <= nr; ++i) {
       const double den = (rb[i] + mu) - (ra[i] * cp);
       inv = 1.0 / den;
       cp = rc[i] * inv;
-      tinv[(size_t)i * M + (k - 1)] = inv;
-      tcp[(size_t)i * M + (k - 1)] = cp;
+      tinv[(size_t)(k - 1) * (nr + 1) + i] = inv;
+      tcp[(size_t)(k - 1) * (nr + 1) + i] = cp;
     }
   }
   edges.assign(65, 0.0);
@@ -596,7 +596,7 @@ pd_status pd_create(const pd_domain* dom, const pd_opts* opts, pd_ctx** out) {
     return s;
   };
   if (dom->nr < 2 || dom->nz < 2 || dom->nz > 8192 ||
-      (opts->poisson != PD_POISSON_SPECTRAL && poisson_lds_bytes(dom->nr, dom->nz) > 65536) ||
+      (opts->poisson != PD_POISSON_SPECTRAL && !direct_fits(dom->nr, dom->nz)) ||
       (int64_t)dom->nr * dom->nz * 6 >= (1LL << 31) || !(dom->R > 0) || !(dom->L > 0) ||
       !(dom->dt > 0) || !(dom->weight > 0) || !std::isfinite(dom->V_cathode) ||
       !std::isfinite(dom->R) || !std::isfinite(dom->L) || dom->capacity < 1 ||
@@ -697,25 +697,27 @@ pd_status pd_create(const pd_domain* dom, const pd_opts* opts, pd_ctx** out) {
   c->fw.tinv = dti;
   c->fw.tcp = dtc;
   c->fw.qunit = c->qunit;
+  if (!c->spectral) {
+    // the whole DST-I matrix for the fixed-order transforms (its entries are
+    // the reduced table's, by (c+1)(b+1) mod 2 nz)
+    std::vector<double> Sm((size_t)M * M);
+    for (int cc = 0; cc < M; ++cc)
+      for (int b = 0; b < M; ++b)
+        Sm[(size_t)cc * M + b] = S[((size_t)(cc + 1) * (size_t)(b + 1)) % (size_t)(2 * nz)];
+    double* dSm;
+    if ((s = dalloc(c, &dSm, Sm.size()))) return fail(s);
+    if (!up(dSm, Sm.data(), Sm.size() * 8)) return fail(set_err(c, PD_EDEVICE, "table upload failed"));
+    c->fw.Sm = dSm;
+  }
   if (c->spectral) {
-    // the factors with r fastest per mode, and the right-hand-side scale
+    // the right-hand-side scale of the matrix-core form
     const int W = nr + 1;
-    std::vector<double> invT((size_t)M * W), cT((size_t)M * W), coef(W);
-    for (int k = 0; k < M; ++k)
-      for (int i = 0; i < W; ++i) {
-        invT[(size_t)k * W + i] = tinv[(size_t)i * M + k];
-        cT[(size_t)k * W + i] = tcp[(size_t)i * M + k];
-      }
+    std::vector<double> coef(W);
     for (int i = 0; i < W; ++i) coef[i] = -(c->qunit / (Vnode[i] * kEPS0));
-    double *dinvT, *dcT, *dcoef;
-    if ((s = dalloc(c, &dinvT, invT.size())) || (s = dalloc(c, &dcT, cT.size())) ||
-        (s = dalloc(c, &dcoef, coef.size())))
-      return fail(s);
-    if (!up(dinvT, invT.data(), invT.size() * 8) || !up(dcT, cT.data(), cT.size() * 8) ||
-        !up(dcoef, coef.data(), coef.size() * 8))
+    double* dcoef;
+    if ((s = dalloc(c, &dcoef, coef.size()))) return fail(s);
+    if (!up(dcoef, coef.data(), coef.size() * 8))
       return fail(set_err(c, PD_EDEVICE, "table upload failed"));
-    c->fw.invT = dinvT;
-    c->fw.cT = dcT;
     c->fw.coef = dcoef;
   }
   c->cpar.Vcell = dVc;

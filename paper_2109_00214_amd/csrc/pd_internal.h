@@ -306,18 +306,17 @@ struct FieldWork {
   int64_t* Q;           // nodes
   double *phi, *Er, *Ez;
   float *Erf, *Ezf;     // FP32 copies of the field (FP32 form), else NULL
-  double* f;            // [(nz-1) * (nr+1)] right-hand side, interior rows
-  double* fh;           // [(nr+1) * (nz-1)] transformed, mode fastest
+  double* f;            // [(nz-1) * (nr+1)] right-hand side, interior rows, r fastest
+  double* fh;           // [(nz-1) * (nr+1)] transformed, per mode, r fastest
   double* g;            // [(nz-1) * (nr+1)] per-mode solutions, r fastest
   const double* T;      // [2 nz] DST-I entries by (k j) mod 2 nz
-  const double* tinv;   // [(nr+1) * (nz-1)] Thomas reciprocals
-  const double* tcp;    // [(nr+1) * (nz-1)] Thomas upper factors
+  const double* Sm;     // [(nz-1) * (nz-1)] DST-I matrix sin(pi (b+1)(c+1) / nz)
+  const double* tinv;   // [(nz-1) * (nr+1)] Thomas reciprocals, per mode, r fastest
+  const double* tcp;    // [(nz-1) * (nr+1)] Thomas upper factors, per mode, r fastest
   const double* ra;     // [nr+1] radial lower coefficients
   const double* Vnode;  // [nr+1]
   double qunit;
-  // tables of the matrix-core form of the direct solve (else NULL)
-  const double* invT;   // [(nz-1) * (nr+1)] Thomas reciprocals, r fastest
-  const double* cT;     // [(nz-1) * (nr+1)] Thomas upper factors, r fastest
+  // the right-hand-side scale of the matrix-core form of the direct solve
   const double* coef;   // [nr+1] -qunit / (V_node eps0)
 };
 // Node charge of the sorted state: every particle of a charged species with
@@ -326,7 +325,7 @@ template <typename T>
 void deposit(const Flow<T>& f, const uint32_t* off, const Grid& g, const SpeciesParams& sp,
              int64_t* Q, int64_t cap, hipStream_t s);
 void poisson_direct(const Grid& g, FieldWork& fw, hipStream_t s);
-size_t poisson_lds_bytes(int nr, int nz);
+bool direct_fits(int nr, int nz);
 // the same solve with the transforms on the FP64 matrix cores and the
 // tridiagonal recurrences as wave scans (k_spectral.hip)
 void poisson_spectral(const Grid& g, FieldWork& fw, hipStream_t s);

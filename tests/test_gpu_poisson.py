@@ -93,6 +93,32 @@ def test_direct_pd_poisson_is_bit_exact():
         assert np.array_equal(fg[k].view(np.uint64), fo[k].view(np.uint64)), k
 
 
+# grids: the paper's, the tiny one, ragged (radial nodes not a multiple of the
+# eight per transform block, rows not a multiple of 64 or of the 32-row
+# staging chunks), one interior row, wide radial extents (16 and 8 modes per
+# tridiagonal block) and a tall one
+@pytest.mark.parametrize("grid,n", [((32, 64), 50_000), ((30, 50), 20_000), ((3, 2), 2_000),
+                                    ((700, 40), 100_000), ((1023, 20), 50_000),
+                                    ((5, 300), 20_000)])
+def test_direct_solve_bit_exact_on_ragged_grids(grid, n):
+    nr, nz = grid
+    log("case: fixed-order direct solve, %dx%d, %d particles" % (nr, nz, n))
+    cfg = W.config("tiny", nr=nr, nz=nz)
+    o, Q = _charge(cfg, n)
+    g = gpu_sim(cfg, 1024, poisson=PD_POISSON_DIRECT64)
+    phi, it, rel = g.poisson(Q)
+    ref = _direct(o)
+    assert it == 0
+    bad = np.nonzero(phi.view(np.uint64) != ref.view(np.uint64))
+    assert bad[0].size == 0, "first differing node (row, column): %s" % (
+        [int(bad[0][0]), int(bad[1][0])],)
+    o.stage("field")
+    fg, fo = g.field(), o.field()
+    for k in ("Er", "Ez"):
+        assert np.array_equal(fg[k].view(np.uint64), fo[k].view(np.uint64)), k
+    g.close()
+
+
 def test_mgpcg_steps_keep_rtol():
     """The tiny workload stepped with the iterative solver: every step's
     potential meets the tolerance (checked at the end and on the way),
