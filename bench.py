@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--config", default="paper")
     ap.add_argument("--n-init", type=int, default=None)
     ap.add_argument("--poisson", choices=("direct", "spectral", "mgpcg", "learned"),
-                    default="spectral",
+                    default="direct",
                     help="direct FP64 solve with every sum in a fixed order (bit-identical to "
                          "the oracle); the same direct solve on the FP64 matrix cores with "
                          "scan-based tridiagonal solves; FP32 multigrid CG with FP64 refinement; "
@@ -58,8 +58,13 @@ def parse():
                     help="steps after the timed ones run with per-stage HIP events for the stage "
                          "breakdown and the roofline (the events cost device time, so the timed "
                          "steps run without them)")
-    ap.add_argument("--cpu-steps", type=int, default=40,
-                    help="oracle steps timed for the CPU baseline (0: skip)")
+    ap.add_argument("--cpu-steps", type=int, default=-1,
+                    help="oracle steps timed for the CPU baseline, after the same warm-up "
+                         "steps as the GPU run (-1: as many as the GPU timed, capped at 40; "
+                         "0: skip)")
+    ap.add_argument("--form-solves", type=int, default=10,
+                    help="successive node charges of the run solved by every Poisson form "
+                         "(0: skip the comparison)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles",
                                                       "hbm_traffic_paper_256x512.txt"),
                     help="rocprofv3 FETCH/WRITE summary written by "
@@ -67,8 +72,27 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(cfg, parts, off, inj, nsteps):
-    """The oracle, single-threaded, on a bounded sample of the same workload."""
+def host_info():
+    """CPU model and the number of cores this process may use."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": usable, "cpu_count": os.cpu_count()}
+
+
+def cpu_baseline(cfg, parts, off, inj, nskip, nsteps):
+    """The oracle, single-threaded, on a bounded sample of the same workload:
+    nskip untimed steps from the initial state, then nsteps timed ones (the
+    same window of the run as the GPU's timed steps)."""
     import oracle
     from paper_2109_00214_amd import workload as W
     o = oracle.Oracle(cfg.nr, cfg.nz, cfg.R, cfg.L, cfg.V, cfg.dt, cfg.weight, cfg.seed,
@@ -78,7 +102,9 @@ def cpu_baseline(cfg, parts, off, inj, nsteps):
     for ch, thr, dsq, sig in W.cross_section_tables():
         o.set_cross_section(ch, thr, dsq, sig)
     o.inject(parts)
-    o.schedule_injection(off[: nsteps + 1], {k: v[: off[nsteps]] for k, v in inj.items()})
+    nall = nskip + nsteps
+    o.schedule_injection(off[: nall + 1], {k: v[: off[nall]] for k, v in inj.items()})
+    o.step(nskip)
     tot = 0
     t0 = time.perf_counter()
     for _ in range(nsteps):
@@ -88,10 +114,51 @@ def cpu_baseline(cfg, parts, off, inj, nsteps):
         for st in ("deposit", "poisson", "field", "push", "compact_inject", "end"):
             o.stage(st)
     dt = time.perf_counter() - t0
-    return {"value": tot / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": "%d step(s) of the %s workload from its initial state (%d particles), "
-                      "single-threaded FP64 C oracle" % (nsteps, cfg.name, len(parts["r"])),
-            "seconds": dt}
+    out = {"value": tot / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+           "sample": "steps %d-%d of the %s workload (%d initial particles), the window the "
+                     "GPU timed, single-threaded FP64 C oracle" %
+                     (nskip, nskip + nsteps - 1, cfg.name, len(parts["r"])),
+           "seconds": dt}
+    out.update(host_info())
+    return out
+
+
+def poisson_forms(cfg, charges, net):
+    """Every Poisson form on the same node charges (successive steps of the
+    benchmark run): device seconds per solve (HIP events around each solve),
+    CG iterations and the FP64 relative residual the library measures.  The
+    iterative forms start from the previous solve's potential, as in a run;
+    the first solve (from the vacuum potential) is reported apart."""
+    from paper_2109_00214_amd import pd as P
+    from paper_2109_00214_amd import workload as W
+    from paper_2109_00214_amd.pd import (PD_POISSON_DIRECT64, PD_POISSON_LEARNED,
+                                         PD_POISSON_MGPCG, PD_POISSON_SPECTRAL, Simulation)
+    out = {}
+    for name, mode in (("direct", PD_POISSON_DIRECT64), ("spectral", PD_POISSON_SPECTRAL),
+                       ("mgpcg", PD_POISSON_MGPCG), ("learned", PD_POISSON_LEARNED)):
+        if name == "learned" and net is None:
+            continue
+        sim = Simulation(cfg, 1024, W.cross_section_tables(), W.species_table(), poisson=mode)
+        if name == "learned":
+            P.pd_set_unet(sim.h, net)
+        rows = []
+        for Q in charges:
+            d0 = sim.diag()
+            _, it, rel = sim.poisson(Q)
+            d1 = sim.diag()
+            rows.append((d1["poisson_seconds"] - d0["poisson_seconds"], int(it), float(rel),
+                         d1["poisson_fallbacks"] - d0["poisson_fallbacks"]))
+        warm = rows[1:] or rows
+        out[name] = {"s_per_solve": sum(r[0] for r in warm) / len(warm),
+                     "cg_iters_per_solve": sum(r[1] for r in warm) / len(warm),
+                     "rel_res_max": max(r[2] for r in warm),
+                     "fallbacks": sum(r[3] for r in rows),
+                     "first_solve_s": rows[0][0], "first_solve_cg_iters": rows[0][1],
+                     "solves": len(rows)}
+        if name == "learned":
+            P.pd_set_unet(sim.h, None)
+        sim.close()
+    return out
 
 
 def run_ensemble(a):
@@ -204,7 +271,7 @@ def main():
 
     kw = {} if a.n_init is None else {"n_init": a.n_init}
     cfg = W.config(a.config, **kw)
-    nsteps = a.warmup + a.steps + a.stage_steps
+    nsteps = a.warmup + a.steps + max(a.stage_steps, 1) + max(a.form_solves, 0)
     t0 = time.time()
     parts = W.initial_population(cfg)
     off, inj = W.injection_schedule(cfg, nsteps)
@@ -215,7 +282,7 @@ def main():
     cap = W.run_capacity(cfg, nsteps)
     precision = PD_FP32_MIXED if a.precision == "fp32" else PD_FP64_DET
     net, learned = None, {}
-    if a.poisson == "learned":
+    if a.poisson == "learned" or a.form_solves > 0:
         # training pairs from the same workload (direct solves), then Adam on
         # the GPU; none of this is inside the timed region
         t1 = time.time()
@@ -240,7 +307,7 @@ def main():
              "mgpcg": PD_POISSON_MGPCG, "learned": PD_POISSON_LEARNED}[a.poisson]
     sim = Simulation(cfg, cap, W.cross_section_tables(), W.species_table(), timing=True,
                      stream=stream.cuda_stream, poisson=pmode, precision=precision)
-    if net is not None:
+    if net is not None and a.poisson == "learned":
         P.pd_set_unet(sim.h, net)
     sim.inject(parts)
     sim.schedule_injection(off, inj)
@@ -269,6 +336,11 @@ def main():
     d2 = sim.diag()
     stages, tsteps = sim.timing()
     pst_stage = d2["particle_steps"] - d1["particle_steps"]
+    # node charges of the next steps, solved afterwards by every Poisson form
+    charges = []
+    for _ in range(max(a.form_solves, 0)):
+        sim.step(1)
+        charges.append(sim.field()["Q"].copy())
     per_step = {k: v / max(tsteps, 1) for k, v in stages.items()}
     print("stage ms/step: " + ", ".join("%s %.4f" % kv for kv in per_step.items()), file=sys.stderr)
     # roofline of the dominant single-kernel stage
@@ -320,17 +392,26 @@ def main():
                    "poisson_refinements_per_step":
                        (d1["poisson_refinements"] - d0["poisson_refinements"]) / a.steps,
                    "poisson_fallbacks": d1["poisson_fallbacks"],
+                   "poisson_forms": None,
+                   "collision_events": int(sum(d1["events"]) - sum(d0["events"])),
+                   "collision_conflicts": int(d1["conflicts"] - d0["conflicts"]),
                    "mean_particles_per_step": round(units),
                    "final_particles": int(d1["n_alive"])},
         "roofline": roof,
         "stages_ms_per_step": {k: round(v, 5) for k, v in per_step.items()},
         "cpu_baseline": None,
     }
+    ev = out["config"]["collision_events"]
+    out["config"]["conflicts_per_event"] = (out["config"]["collision_conflicts"] / ev) if ev else None
     sim.close()
+    if charges:
+        out["config"]["poisson_forms"] = poisson_forms(cfg, charges, net)
+        print("poisson forms: %s" % json.dumps(out["config"]["poisson_forms"]), file=sys.stderr)
     if net is not None:
         P.pd_unet_destroy(net)
-    if a.cpu_steps > 0:
-        out["cpu_baseline"] = cpu_baseline(cfg, parts, off, inj, a.cpu_steps)
+    ncpu = min(a.steps, 40) if a.cpu_steps < 0 else a.cpu_steps
+    if ncpu > 0:
+        out["cpu_baseline"] = cpu_baseline(cfg, parts, off, inj, a.warmup, ncpu)
     del np
     print(json.dumps(out))
 

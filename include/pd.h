@@ -135,6 +135,9 @@ typedef struct {
   int64_t poisson_iters;         /* cumulative CG iterations (iterative solver) */
   int64_t poisson_refinements;   /* cumulative FP64 refinement steps */
   int64_t poisson_fallbacks;     /* solves that fell back to the direct solve */
+  double poisson_seconds;        /* device time of the solves made by pd_poisson
+                                  * (HIP events around each solve; the steps'
+                                  * solves are timed by pd_get_timing) */
 } pd_diag;
 
 /* Create a context on the current HIP device.  dom and opts are copied.

@@ -76,6 +76,7 @@ struct pd_ctx {
   struct pd_unet* net = nullptr;
   int mg_inner = 8, mg_inner_max = 16, mg_outer_max = 8;
   int64_t p_solves = 0, p_fallbacks = 0;
+  double p_call_ms = 0.0;  // device time of the solves made by pd_poisson
 
   // timing
   std::vector<hipEvent_t> ev_pool;
@@ -984,6 +985,7 @@ pd_status pd_get_diagnostics(pd_ctx* c, pd_diag* out) {
   out->poisson_iters = c->h_sc->iters;
   out->poisson_refinements = c->h_sc->outer;
   out->poisson_fallbacks = c->p_fallbacks;
+  out->poisson_seconds = c->p_call_ms * 1e-3;
   const double N0 = (double)counts[PD_CU], N1 = (double)counts[PD_CU1];
   const double N2 = (double)(counts[PD_CU2_STEP] + counts[PD_CU2_DOUBLE] + counts[PD_CU2_INIT]);
   out->gamma = (N0 + N1 + N2) > 0 ? (N1 + N2) / ((N0 + N1) + N2) : 0.0;
@@ -1085,11 +1087,20 @@ pd_status pd_poisson(pd_ctx* c, const int64_t* Q, double* phi, int32_t* iters, d
   HIPCHK(c, hipMemcpy(c->fw.Q, Q, 8 * nn, hipMemcpyHostToDevice));
   if ((s = read_mg(c))) return s;
   const int it0 = c->h_sc->iters;
+  hipEvent_t e0 = get_event(c), e1 = get_event(c);
+  HIPCHK(c, hipEventRecord(e0, c->stream));
   if ((s = solve_poisson(c))) return s;
+  HIPCHK(c, hipEventRecord(e1, c->stream));
   field(c->g, c->fw, c->stream);
   mg_residual(c->mg, c->fw.phi, c->fw.Q, c->stream);
   HIPCHK(c, hipGetLastError());
   if ((s = read_mg(c))) return s;
+  {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess) c->p_call_ms += ms;
+    c->ev_pool.push_back(e0);
+    c->ev_pool.push_back(e1);
+  }
   if (iters) *iters = c->h_sc->iters - it0;
   if (rel_res) *rel_res = c->h_sc->rel;
   if (phi) HIPCHK(c, hipMemcpy(phi, c->fw.phi, 8 * nn, hipMemcpyDeviceToHost));
@@ -1396,9 +1407,11 @@ const char* pd_last_error(const pd_ctx* c) { return c ? c->err.c_str() : g_creat
 void pd_destroy(pd_ctx* c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
-  for (auto& set : c->ev_pending)
-    for (auto e : set) (void)hipEventDestroy(e);
-  for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+  // the pending steps' events go back to the pool once each (their null
+  // entries repeat the boundary before them)
+  harvest_timing(c);
+  for (auto e : c->ev_pool)
+    if (e) (void)hipEventDestroy(e);
   for (void* p : c->sched_allocs) (void)hipFree(p);
   for (void* p : c->allocs) (void)hipFree(p);
   if (c->h_sc) (void)hipHostFree(c->h_sc);

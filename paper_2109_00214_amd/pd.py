@@ -58,7 +58,8 @@ class pd_diag(C.Structure):
                 ("ke_J", C.c_double * 6), ("gamma", C.c_double), ("qbar", C.c_double),
                 ("particle_steps", C.c_int64), ("poisson_rel_res", C.c_double),
                 ("poisson_solves", C.c_int64), ("poisson_iters", C.c_int64),
-                ("poisson_refinements", C.c_int64), ("poisson_fallbacks", C.c_int64)]
+                ("poisson_refinements", C.c_int64), ("poisson_fallbacks", C.c_int64),
+                ("poisson_seconds", C.c_double)]
 
 
 _lib = None

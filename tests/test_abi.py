@@ -47,9 +47,9 @@ def test_struct_layouts_match_header():
 #include <stdio.h>
 #include <stddef.h>
 #include "pd.h"
-int main(void){ printf("%zu %zu %zu %zu %zu %zu\n", sizeof(pd_domain), sizeof(pd_opts), sizeof(pd_diag),
+int main(void){ printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(pd_domain), sizeof(pd_opts), sizeof(pd_diag),
   offsetof(pd_diag, particle_steps), offsetof(pd_opts, poisson_rtol),
-  offsetof(pd_diag, poisson_fallbacks)); return 0; }
+  offsetof(pd_diag, poisson_fallbacks), offsetof(pd_diag, poisson_seconds)); return 0; }
 '''
     with tempfile.TemporaryDirectory() as d:
         c = os.path.join(d, "t.c")
@@ -63,6 +63,7 @@ int main(void){ printf("%zu %zu %zu %zu %zu %zu\n", sizeof(pd_domain), sizeof(pd
     assert int(out[3]) == pd.pd_diag.particle_steps.offset
     assert int(out[4]) == pd.pd_opts.poisson_rtol.offset
     assert int(out[5]) == pd.pd_diag.poisson_fallbacks.offset
+    assert int(out[6]) == pd.pd_diag.poisson_seconds.offset
 
 
 def test_missing_library_fails_loudly(tmp_path):
