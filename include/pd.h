@@ -223,6 +223,26 @@ pd_status pd_get_field(pd_ctx* ctx, double* phi, double* Er, double* Ez, int64_t
 pd_status pd_poisson(pd_ctx* ctx, const int64_t* Q, double* phi, int32_t* iters,
                      double* rel_res);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * fixed-order direct solve of pd_poisson for a node charge Q already in
+ * device memory ((nr+1)*(nz+1) int64 values, units of e * weight * 2^-40,
+ * node-major, r fastest), writing the potential phi (same layout, device
+ * memory, caller-owned) on `stream` (hipStream_t; NULL: the context's
+ * stream).  It enqueues four kernels and returns without synchronising:
+ * no allocation, no memset, no copy.  The context supplies the grid and its
+ * tables (it must not be a PD_POISSON_SPECTRAL context); the intermediate
+ * arrays live in a fixed per-GPU scratch area of the library (4 MiB, held
+ * until the process ends), so the grid must satisfy
+ * 3 (nz-1)(nr+1) <= 524288, and calls that overlap on one GPU (different
+ * streams, threads or contexts) race on it.  The scratch needs no clearing:
+ * the solve writes every word before reading it.  The context's own
+ * potential, field and charge are left unchanged.
+ * Errors: PD_EINVAL (NULL pointers, a PD_POISSON_SPECTRAL context, a grid
+ * beyond the scratch), PD_EDEVICE (current device is not the context's, or
+ * a launch failure).                                                   */
+pd_status pd_poisson_noalloc(pd_ctx* ctx, const int64_t* Q, double* phi, void* stream);
+
 /* ---- ensembles of independent replicas ----------------------------------
  * Replicas (their own domain, seed, voltage, size and precision, created and
  * set up as usual with the direct Poisson solver and timing off) advance

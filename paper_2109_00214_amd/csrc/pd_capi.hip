@@ -12,6 +12,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -77,6 +78,7 @@ struct pd_ctx {
   int mg_inner = 8, mg_inner_max = 16, mg_outer_max = 8;
   int64_t p_solves = 0, p_fallbacks = 0;
   double p_call_ms = 0.0;  // device time of the solves made by pd_poisson
+  int device = -1;         // the HIP device the context was created on
 
   // timing
   std::vector<hipEvent_t> ev_pool;
@@ -101,6 +103,37 @@ struct pd_ensemble {
   bool owns = false;                  // members marked as in this ensemble
   std::string err;
 };
+
+// Scratch of pd_poisson_noalloc, the entry point that allocates nothing: the
+// direct solve's right-hand side, transformed right-hand side and per-mode
+// solutions, 3 (nz-1)(nr+1) words.  Each GPU the library runs on holds one
+// copy until the process ends; host code reaches it only through the
+// address hipGetSymbolAddress returns for the current device.
+constexpr size_t kScratchWords = (size_t)1 << 19;  // 4 MiB
+static __device__ __align__(256) double scratch[kScratchWords];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// the scratch address on the current device, looked up once per device
+// (at context creation); nullptr if the lookup fails
+double* scratch_on_current_device(int* dev_out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  if (dev_out) *dev_out = dev;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  return g_scratch_ptr[dev];
+}
+
+}  // namespace
 
 namespace {
 
@@ -614,6 +647,8 @@ pd_status pd_create(const pd_domain* dom, const pd_opts* opts, pd_ctx** out) {
   c->mg_on = opts->poisson != PD_POISSON_DIRECT64 && !c->spectral;
   c->learned = opts->poisson == PD_POISSON_LEARNED;
   c->fp32 = opts->precision == PD_FP32_MIXED;
+  if (!scratch_on_current_device(&c->device))
+    return fail(set_err(c, PD_EDEVICE, "scratch address of the current device"));
   if (opts->stream) {
     c->stream = (hipStream_t)opts->stream;
   } else {
@@ -1104,6 +1139,38 @@ pd_status pd_poisson(pd_ctx* c, const int64_t* Q, double* phi, int32_t* iters, d
   if (iters) *iters = c->h_sc->iters - it0;
   if (rel_res) *rel_res = c->h_sc->rel;
   if (phi) HIPCHK(c, hipMemcpy(phi, c->fw.phi, 8 * nn, hipMemcpyDeviceToHost));
+  return PD_OK;
+}
+
+pd_status pd_poisson_noalloc(pd_ctx* c, const int64_t* Q, double* phi, void* stream) {
+  if (!c) return PD_EINVAL;
+  if (c->poisoned) return set_err(c, PD_ESTATE, "context unusable after an earlier error");
+  if (!Q || !phi) return set_err(c, PD_EINVAL, "Q or phi is NULL");
+  if (c->spectral)
+    return set_err(c, PD_EINVAL, "the context has no fixed-order solve (created with PD_POISSON_SPECTRAL)");
+  const size_t words = (size_t)3 * (size_t)(c->g.nz - 1) * (size_t)(c->g.nr + 1);
+  if (words > kScratchWords)
+    return set_err(c, PD_EINVAL, "grid %dx%d needs %zu scratch words, more than the %zu held",
+                   c->g.nr, c->g.nz, words, kScratchWords);
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != c->device)
+    return set_err(c, PD_EDEVICE, "current device %d is not the context's device %d", dev,
+                   c->device);
+  double* sp;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    sp = g_scratch_ptr[dev];
+  }
+  if (!sp) return set_err(c, PD_EDEVICE, "no scratch address for device %d", dev);
+  const size_t part = (size_t)(c->g.nz - 1) * (size_t)(c->g.nr + 1);
+  FieldWork fw = c->fw;
+  fw.Q = const_cast<int64_t*>(Q);
+  fw.phi = phi;
+  fw.f = sp;
+  fw.fh = sp + part;
+  fw.g = sp + 2 * part;
+  poisson_direct(c->g, fw, stream ? (hipStream_t)stream : c->stream);
+  HIPCHK(c, hipGetLastError());
   return PD_OK;
 }
 

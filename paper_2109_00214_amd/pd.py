@@ -23,7 +23,7 @@ TIMER_NAMES = ("radix", "permute", "offsets", "collide", "deposit", "poisson", "
 EXPORTED = ("pd_create", "pd_set_species", "pd_set_cross_section", "pd_inject",
             "pd_schedule_injection", "pd_step", "pd_synchronize", "pd_get_diagnostics",
             "pd_get_spectrum", "pd_get_count", "pd_get_particles", "pd_get_field",
-            "pd_poisson", "pd_get_timing", "pd_set_timing", "pd_last_error", "pd_destroy",
+            "pd_poisson", "pd_poisson_noalloc", "pd_get_timing", "pd_set_timing", "pd_last_error", "pd_destroy",
             "pd_unet_create", "pd_unet_info", "pd_unet_set_weights", "pd_unet_get_weights",
             "pd_unet_forward", "pd_unet_gradient", "pd_unet_add_sample", "pd_unet_train",
             "pd_set_unet", "pd_unet_last_error", "pd_unet_destroy",
@@ -87,6 +87,7 @@ def load_library(path=LIB_PATH):
     lib.pd_get_particles.argtypes = [P, C.c_int64] + [P] * 8
     lib.pd_get_field.argtypes = [P, P, P, P, P]
     lib.pd_poisson.argtypes = [P, P, P, C.POINTER(C.c_int32), C.POINTER(C.c_double)]
+    lib.pd_poisson_noalloc.argtypes = [P, P, P, P]
     lib.pd_get_timing.argtypes = [P, P, C.POINTER(C.c_int64), C.c_int]
     lib.pd_set_timing.argtypes = [P, C.c_int]
     lib.pd_last_error.argtypes = [P]
@@ -232,6 +233,13 @@ def pd_poisson(ctx, Q, nr, nz):
     rel = C.c_double()
     _check(ctx, load_library().pd_poisson(ctx, _ptr(q), _ptr(phi), C.byref(it), C.byref(rel)))
     return phi.reshape(nz + 1, nr + 1), it.value, rel.value
+
+
+def pd_poisson_noalloc(ctx, q_dev, phi_dev, stream=None):
+    """Direct solve for a node charge in device memory (q_dev, phi_dev:
+    device addresses as integers); enqueues and returns (no synchronisation)."""
+    _check(ctx, load_library().pd_poisson_noalloc(ctx, C.c_void_p(q_dev), C.c_void_p(phi_dev),
+                                                  C.c_void_p(stream)))
 
 
 def _check_net(net, status):
