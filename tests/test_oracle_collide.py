@@ -51,6 +51,8 @@ def test_event_rate_matches_n_sigma_v():
         n = o.count()
         o.stage("collide")
         ch, tg, wn = o.collisions(n)
+        d = o.diag()
+        assert int(np.sum(d["events"])) + d["conflicts"] == int((ch > 0).sum())
         got_total += int((ch > 0).sum())
         got_ch += np.bincount(ch, minlength=5)[1:]
         _, vc = o.node_volumes()
@@ -158,7 +160,11 @@ def test_claim_lowest_position_wins():
     for t in np.unique(tg[chosen]):
         who = chosen[tg[chosen] == t]
         assert wn[who[0]] == 1 and np.all(wn[who[1:]] == 0)
-    assert o.diag()["conflicts"] == int((ch > 0).sum() - wn.sum())
+    d = o.diag()
+    # every passed trial is either a realized event or a lost claim
+    assert d["conflicts"] == int((ch > 0).sum() - wn.sum())
+    assert int(np.sum(d["events"])) == int(wn.sum())
+    assert int(np.sum(d["events"])) + d["conflicts"] == int((ch > 0).sum())
 
 
 def test_targets_are_uniform_in_cell():
