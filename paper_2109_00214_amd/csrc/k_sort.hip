@@ -73,36 +73,50 @@ static inline int tile_grid(int64_t cap, int per_cu, int tile) {
   return (int)(tiles < lim ? tiles : lim);
 }
 
+// Keys per thread of a radix tile (tiles of 256 * items keys), chosen from
+// the number of movers n alone, so that every launch of a sort agrees: short
+// tiles when the movers are few (the usual step: many blocks), long ones
+// when most particles moved (the first steps: the per-tile digit rows, and
+// the column scan over them, stay few).
+constexpr int kMoverItemsMax = 16;
+__device__ inline int mover_items(uint32_t n) {
+  return (n > (1u << 20)) ? 16 : ((n > (1u << 18)) ? 8 : kMoverItems);
+}
+
 // per-tile digit histogram: each wave ranks its contiguous quarter of the tile 64 keys at a
-// time (all 16 rankings first, so their ballot chains overlap), then adds
+// time (all rankings first, so their ballot chains overlap), then adds
 // one count per distinct digit to its LDS row (no atomics)
-template <int DB, int IT>
+template <int DB, int ITM>
 __global__ void __launch_bounds__(256) k_radix_up(const uint32_t* __restrict__ keys,
                                                   const uint32_t* np, int shift,
                                                   uint32_t* __restrict__ hist) {
   constexpr int R = 1 << DB;
   __shared__ uint32_t wh[4][R];
   const uint32_t n = *np;
-  const uint32_t ntiles = (n + (256 * IT) - 1) / (256 * IT);
+  const int itn = mover_items(n);
+  const uint32_t tsz = 256u * (uint32_t)itn;
+  const uint32_t ntiles = (n + tsz - 1) / tsz;
   constexpr uint32_t mask = (uint32_t)R - 1u;
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     for (int d = t; d < R; d += 256) wh[0][d] = wh[1][d] = wh[2][d] = wh[3][d] = 0;
-    const uint32_t base = tile * (256 * IT) + w * ((256 * IT) / 4);
-    uint32_t dd[IT], rr[IT], cc[IT];
+    const uint32_t base = tile * tsz + w * (tsz / 4);
+    uint32_t dd[ITM], rr[ITM], cc[ITM];
 #pragma unroll
-    for (int it = 0; it < IT; ++it) {
-      const uint32_t idx = base + it * 64 + lane;
-      dd[it] = (keys[(idx < n) ? idx : n - 1] >> shift) & mask;  // clamped, unconditional
+    for (int it = 0; it < ITM; ++it) {
+      if (it < itn) {
+        const uint32_t idx = base + it * 64 + lane;
+        dd[it] = (keys[(idx < n) ? idx : n - 1] >> shift) & mask;  // clamped, unconditional
+      }
     }
 #pragma unroll
-    for (int it = 0; it < IT; ++it)
-      rr[it] = match_rank<DB>(dd[it], base + it * 64 + lane < n, lt, &cc[it]);
+    for (int it = 0; it < ITM; ++it)
+      if (it < itn) rr[it] = match_rank<DB>(dd[it], base + it * 64 + lane < n, lt, &cc[it]);
     __syncthreads();
 #pragma unroll
-    for (int it = 0; it < IT; ++it)
-      if (base + it * 64 + lane < n && rr[it] == 0) wh[w][dd[it]] += cc[it];
+    for (int it = 0; it < ITM; ++it)
+      if (it < itn && base + it * 64 + lane < n && rr[it] == 0) wh[w][dd[it]] += cc[it];
     __syncthreads();
     for (int d = t; d < R; d += 256)
       hist[(size_t)tile * R + d] = wh[0][d] + wh[1][d] + wh[2][d] + wh[3][d];
@@ -116,13 +130,14 @@ __global__ void __launch_bounds__(256) k_radix_up(const uint32_t* __restrict__ k
 // combined in LDS, then each wave rewrites its run.
 constexpr int kColWaves = 16;
 constexpr uint32_t kColHeld = 32;  // tiles per wave held in registers
-template <int R, int IT>
+template <int R>
 __global__ void __launch_bounds__(64 * kColWaves) k_radix_colscan(uint32_t* __restrict__ hist,
                                                                   uint32_t* __restrict__ tot,
                                                                   const uint32_t* np) {
   __shared__ uint32_t part[kColWaves][64];
   const uint32_t n = *np;
-  const uint32_t ntiles = (n + (256 * IT) - 1) / (256 * IT);
+  const uint32_t tsz = 256u * (uint32_t)mover_items(n);
+  const uint32_t ntiles = (n + tsz - 1) / tsz;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int d = blockIdx.x * 64 + lane;
   const uint32_t ch = (ntiles + kColWaves - 1) / kColWaves;
@@ -208,7 +223,7 @@ __device__ inline uint32_t stayers_before(const MoverPlace& mp, uint32_t n_prev,
   return p - movers_before(mp.mbits, mp.mword, p);
 }
 
-template <int DB, int IT, bool FIRST>  // FIRST: the values are the source indices
+template <int DB, int ITM, bool FIRST>  // FIRST: the values are the source indices
 __global__ void __launch_bounds__(256) k_radix_down(const uint32_t* __restrict__ kin,
                                                     const uint32_t* __restrict__ vin,
                                                     uint32_t* __restrict__ kout,
@@ -220,35 +235,41 @@ __global__ void __launch_bounds__(256) k_radix_down(const uint32_t* __restrict__
   constexpr int R = 1 << DB;
   constexpr uint32_t mask = (uint32_t)R - 1u;
   constexpr int PER = (R + 255) / 256;
+  constexpr int kStage = 256 * kMoverItems;  // short tiles are reordered in LDS
   __shared__ uint32_t wh[4][R];
   __shared__ uint32_t gofs[R];
   __shared__ uint32_t dbase[R];
-  __shared__ uint32_t tkey[(256 * IT)];
-  __shared__ uint32_t tval[(256 * IT)];
-  __shared__ uint32_t tins[(256 * IT)];  // last pass: stayers before each mover
+  __shared__ uint32_t tkey[kStage];
+  __shared__ uint32_t tval[kStage];
+  __shared__ uint32_t tins[kStage];  // last pass: stayers before each mover
   __shared__ uint32_t sh[4];
   const uint32_t n = *np;
-  const uint32_t ntiles = (n + (256 * IT) - 1) / (256 * IT);
+  const int itn = mover_items(n);
+  const uint32_t tsz = 256u * (uint32_t)itn;
+  const bool staged = itn == kMoverItems;
+  const uint32_t ntiles = (n + tsz - 1) / tsz;
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const bool last = mp.skey != nullptr;
   const uint32_t n_prev = last ? mp.st->n_alive : 0u;
   bool have_base = false;
   for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const uint32_t tile0 = tile * (256 * IT);
-    const uint32_t base = tile0 + w * ((256 * IT) / 4);
+    const uint32_t tile0 = tile * tsz;
+    const uint32_t base = tile0 + w * (tsz / 4);
     // everything the tile reads from memory is requested first: its keys
     // and values, its prefix of every digit over the earlier tiles, and (in
     // the last pass) the stayers before each mover, so that the reads are in
     // flight together
-    uint32_t kk[IT], vv[IT], rk[IT], cc[IT], hh[PER], in[IT];
+    uint32_t kk[ITM], vv[ITM], rk[ITM], cc[ITM], hh[PER], in[ITM];
 #pragma unroll
-    for (int it = 0; it < IT; ++it) {
-      const uint32_t idx = base + it * 64 + lane;
-      const bool valid = idx < n;
-      const uint32_t ic = valid ? idx : n - 1;  // clamped, unconditional loads
-      kk[it] = kin[ic];
-      vv[it] = FIRST ? idx : vin[ic];
+    for (int it = 0; it < ITM; ++it) {
+      if (it < itn) {
+        const uint32_t idx = base + it * 64 + lane;
+        const bool valid = idx < n;
+        const uint32_t ic = valid ? idx : n - 1;  // clamped, unconditional loads
+        kk[it] = kin[ic];
+        vv[it] = FIRST ? idx : vin[ic];
+      }
     }
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
@@ -257,7 +278,8 @@ __global__ void __launch_bounds__(256) k_radix_down(const uint32_t* __restrict__
     }
     if (last) {
 #pragma unroll
-      for (int it = 0; it < IT; ++it) in[it] = stayers_before(mp, n_prev, kk[it], vv[it]);
+      for (int it = 0; it < ITM; ++it)
+        if (it < itn) in[it] = stayers_before(mp, n_prev, kk[it], vv[it]);
     }
     if (!have_base) {
       // global start of every digit: exclusive scan of the digit totals
@@ -281,16 +303,19 @@ __global__ void __launch_bounds__(256) k_radix_down(const uint32_t* __restrict__
     }
     for (int d = t; d < R; d += 256) wh[0][d] = wh[1][d] = wh[2][d] = wh[3][d] = 0;
 #pragma unroll
-    for (int it = 0; it < IT; ++it)
-      rk[it] = match_rank<DB>((kk[it] >> shift) & mask, base + it * 64 + lane < n, lt, &cc[it]);
+    for (int it = 0; it < ITM; ++it)
+      if (it < itn)
+        rk[it] = match_rank<DB>((kk[it] >> shift) & mask, base + it * 64 + lane < n, lt, &cc[it]);
     __syncthreads();
     // carry the per-digit counts of earlier iterations (in-order per wave)
 #pragma unroll
-    for (int it = 0; it < IT; ++it) {
-      const uint32_t d = (kk[it] >> shift) & mask;
-      const uint32_t old = wh[w][d];
-      if (base + it * 64 + lane < n && rk[it] == 0) wh[w][d] = old + cc[it];
-      rk[it] += old;
+    for (int it = 0; it < ITM; ++it) {
+      if (it < itn) {
+        const uint32_t d = (kk[it] >> shift) & mask;
+        const uint32_t old = wh[w][d];
+        if (base + it * 64 + lane < n && rk[it] == 0) wh[w][d] = old + cc[it];
+        rk[it] += old;
+      }
     }
     __syncthreads();
     // tile-local start of every digit, start of each wave's share, and
@@ -321,56 +346,79 @@ __global__ void __launch_bounds__(256) k_radix_down(const uint32_t* __restrict__
       }
     }
     __syncthreads();
+    if (staged) {
+      // short tile: reordered in LDS so that the stores of a digit run are
+      // contiguous
 #pragma unroll
-    for (int it = 0; it < IT; ++it) {
-      if (base + it * 64 + lane < n) {
-        const uint32_t lp = wh[w][(kk[it] >> shift) & mask] + rk[it];
-        tkey[lp] = kk[it];
-        tval[lp] = vv[it];
-        if (last) tins[lp] = in[it];
+      for (int it = 0; it < kMoverItems; ++it) {
+        if (base + it * 64 + lane < n) {
+          const uint32_t lp = wh[w][(kk[it] >> shift) & mask] + rk[it];
+          tkey[lp] = kk[it];
+          tval[lp] = vv[it];
+          if (last) tins[lp] = in[it];
+        }
       }
-    }
-    __syncthreads();
-    const uint32_t cnt = (n - tile0 < (uint32_t)(256 * IT)) ? (n - tile0) : (uint32_t)(256 * IT);
-    if (!last) {
+      __syncthreads();
+      const uint32_t cnt = (n - tile0 < tsz) ? (n - tile0) : tsz;
+      if (!last) {
 #pragma unroll 4
-      for (uint32_t q = t; q < cnt; q += 256) {
-        const uint32_t k = tkey[q];
-        const uint32_t p = gofs[(k >> shift) & mask] + q;
-        kout[p] = k;
-        vout[p] = tval[q];
+        for (uint32_t q = t; q < cnt; q += 256) {
+          const uint32_t k = tkey[q];
+          const uint32_t p = gofs[(k >> shift) & mask] + q;
+          kout[p] = k;
+          vout[p] = tval[q];
+        }
+      } else {
+        // last pass: place the movers (p = final rank among the movers)
+#pragma unroll 4
+        for (uint32_t q = t; q < cnt; q += 256) {
+          const uint32_t k = tkey[q], i = tval[q], ins = tins[q];
+          const uint32_t p = gofs[(k >> shift) & mask] + q;
+          kout[p] = k;  // the movers' keys in order (for the offsets)
+          mp.ins[p] = ins;
+          mp.skey[ins + p] = k;
+          mp.perm[ins + p] = i;
+        }
       }
     } else {
-      // last pass: place the movers (p = final rank among the movers)
-#pragma unroll 4
-      for (uint32_t q = t; q < cnt; q += 256) {
-        const uint32_t k = tkey[q], i = tval[q], ins = tins[q];
-        const uint32_t p = gofs[(k >> shift) & mask] + q;
-        kout[p] = k;  // the movers' keys in order (for the offsets)
-        mp.ins[p] = ins;
-        mp.skey[ins + p] = k;
-        mp.perm[ins + p] = i;
+      // long tile: each key straight to its place
+#pragma unroll
+      for (int it = 0; it < ITM; ++it) {
+        if (it < itn && base + it * 64 + lane < n) {
+          const uint32_t d = (kk[it] >> shift) & mask;
+          const uint32_t p = gofs[d] + wh[w][d] + rk[it];
+          kout[p] = kk[it];
+          if (!last) {
+            vout[p] = vv[it];
+          } else {
+            mp.ins[p] = in[it];
+            mp.skey[in[it] + p] = kk[it];
+            mp.perm[in[it] + p] = vv[it];
+          }
+        }
       }
     }
     __syncthreads();
   }
 }
 
-// one pass over tiles of 256 IT keys (IT = kMoverItems: short tiles, many blocks,
-// for the movers, which are usually few)
-template <int DB, int IT>
+// one pass over the movers' tiles (their length chosen on the device from the
+// number of movers, mover_items)
+template <int DB>
 static void radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
                        int shift, SortWork& w, const uint32_t* np, const MoverPlace& mp,
                        hipStream_t s) {
   constexpr int R = 1 << DB;
-  k_radix_up<DB, IT><<<tile_grid(w.cap, 2, 256 * IT), 256, 0, s>>>(kin, np, shift, w.hist);
-  k_radix_colscan<R, IT><<<R / 64, 64 * kColWaves, 0, s>>>(w.hist, w.bsum, np);
+  constexpr int ITM = kMoverItemsMax;
+  const int grid = tile_grid(w.cap, 2, 256 * kMoverItems);
+  k_radix_up<DB, ITM><<<grid, 256, 0, s>>>(kin, np, shift, w.hist);
+  k_radix_colscan<R><<<R / 64, 64 * kColWaves, 0, s>>>(w.hist, w.bsum, np);
   if (!vin)
-    k_radix_down<DB, IT, true><<<tile_grid(w.cap, 2, 256 * IT), 256, 0, s>>>(
-        kin, vin, kout, vout, np, shift, w.hist, w.bsum, mp);
+    k_radix_down<DB, ITM, true><<<grid, 256, 0, s>>>(kin, vin, kout, vout, np, shift, w.hist,
+                                                     w.bsum, mp);
   else
-    k_radix_down<DB, IT, false><<<tile_grid(w.cap, 2, 256 * IT), 256, 0, s>>>(
-        kin, vin, kout, vout, np, shift, w.hist, w.bsum, mp);
+    k_radix_down<DB, ITM, false><<<grid, 256, 0, s>>>(kin, vin, kout, vout, np, shift, w.hist,
+                                                      w.bsum, mp);
 }
 
 // ---- stayers and movers ---------------------------------------------------
@@ -616,8 +664,8 @@ void sort_keys(const uint32_t* key, int key_bits, SortWork& w, DevState* st, con
       uint32_t* vout = (p & 1) ? w.v0 : w.v1;
       const int shift = p * dbits;
       const MoverPlace& mp = (p == passes - 1) ? last : none;
-      if (dbits <= 8) radix_pass<8, kMoverItems>(kin, vin, kout, vout, shift, w, w.n_mov, mp, s);
-      else radix_pass<10, kMoverItems>(kin, vin, kout, vout, shift, w, w.n_mov, mp, s);
+      if (dbits <= 8) radix_pass<8>(kin, vin, kout, vout, shift, w, w.n_mov, mp, s);
+      else radix_pass<10>(kin, vin, kout, vout, shift, w, w.n_mov, mp, s);
       kin = kout;
       vin = vout;
     }

@@ -66,6 +66,21 @@ def test_sparse_keys_paper_grid(n):
         assert_same_state(g, o, "sparse n=%d step %d" % (n, s))
 
 
+@pytest.mark.parametrize("n", [300_000, 1_200_000])
+def test_many_movers_long_radix_tiles(n):
+    """Populations whose first sorts have every particle (then every
+    electron) moving: beyond 2^18 and 2^20 movers the mover radix passes use
+    tiles of 2048 and 4096 keys, placed without the LDS reorder of the short
+    tiles; the sort order and the whole state stay bit-identical."""
+    log("case: many movers, 256x512 grid, n=%d" % n)
+    cfg = W.config("tiny", nr=256, nz=512, n_init=n)
+    g, o = pair(cfg, n_init=n, steps=3)
+    for s in range(1, 4):
+        g.step(1)
+        o.step(1)
+        assert_same_state(g, o, "many movers n=%d step %d" % (n, s))
+
+
 def test_all_stayers_no_movers():
     """Neutral atoms at rest, no collisions, no injection: after the first
     sort nothing changes cell, so the sort has no movers at all (empty radix
