@@ -223,6 +223,26 @@ pd_status pd_get_field(pd_ctx* ctx, double* phi, double* Er, double* Ez, int64_t
 pd_status pd_poisson(pd_ctx* ctx, const int64_t* Q, double* phi, int32_t* iters,
                      double* rel_res);
 
+/* Checkpoint of the whole state between two steps (Sec. 2: the particle
+ * records, the per-cell order and offsets the next sort starts from, the node
+ * charge, potential and field, the device and host counters, the collision
+ * tables and the injection schedule with its position), written to one
+ * binary file at `path` (host byte order, this library version's layout).
+ * pd_load reads such a file into a context created with the same domain
+ * (nr, nz, R, L, V, dt, weight, seed) and the same precision and switches
+ * (enable_di, deposit_off, collisions_off), with capacity for the saved
+ * particles; the species and cross-section tables come from the file.  A
+ * context stepped on after pd_load gives bit for bit what the saved one gives
+ * (for the iterative Poisson solvers: with the same solver; a network
+ * attached with pd_set_unet is not part of the file).  Timing accumulators
+ * are not saved.
+ * Errors: PD_EINVAL (NULL path, the file cannot be opened or written, a
+ * wrong magic, version, layout, domain, switch, size or count, a truncated
+ * file: pd_load then leaves the context unchanged), PD_ESTATE (a member of
+ * an ensemble; species not set when saving), PD_EDEVICE.               */
+pd_status pd_save(pd_ctx* ctx, const char* path);
+pd_status pd_load(pd_ctx* ctx, const char* path);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the
  * fixed-order direct solve of pd_poisson for a node charge Q already in

@@ -1142,6 +1142,302 @@ pd_status pd_poisson(pd_ctx* c, const int64_t* Q, double* phi, int32_t* iters, d
   return PD_OK;
 }
 
+// ---- checkpoint: the whole state between two steps in one file -----------
+// Layout (host byte order, this library's struct layouts): the magic, the
+// version, sizeof of the saved structs; the domain and the options that
+// shape the state; species and cross-section tables; the device counters;
+// the particle records in the order the next sort receives them (native
+// precision); the last sort's keys and cell offsets (the next sort starts
+// from them); the node charge, potential and field; the injection schedule
+// with its read position; the host-side counters; the solver's scalars; the
+// magic again.
+static const char kSaveMagic[8] = {'P', 'D', 'S', 'T', 'A', 'T', 'E', '1'};
+constexpr uint32_t kSaveVersion = 1;
+
+struct SaveHead {
+  char magic[8];
+  uint32_t version, sz_domain, sz_state, sz_mgscal;
+  pd_domain dom;
+  int32_t precision, poisson, enable_di, deposit_off, collisions_off, pad;
+};
+
+struct SaveHost {
+  int64_t injected[kNS];
+  int64_t host_step, host_sched_pos, sched_n, p_solves, p_fallbacks;
+  int32_t mg_inner, pad;
+};
+
+pd_status pd_save(pd_ctx* c, const char* path) {
+  if (!c) return PD_EINVAL;
+  if (!path) return set_err(c, PD_EINVAL, "path is NULL");
+  if (c->poisoned) return set_err(c, PD_ESTATE, "context unusable after an earlier error");
+  if (c->in_ensemble) return set_err(c, PD_ESTATE, "context is in an ensemble");
+  if (!c->species_set) return set_err(c, PD_ESTATE, "species not set");
+  DevState st;
+  pd_status s = read_state(c, &st);
+  if (s) return s;
+  std::vector<unsigned char> out;
+  auto put = [&](const void* p, size_t n) {
+    const unsigned char* b = (const unsigned char*)p;
+    out.insert(out.end(), b, b + n);
+  };
+  auto putd = [&](const void* dev, size_t n) -> pd_status {
+    const size_t o = out.size();
+    out.resize(o + n);
+    if (n) HIPCHK(c, hipMemcpy(out.data() + o, dev, n, hipMemcpyDeviceToHost));
+    return PD_OK;
+  };
+  SaveHead h{};
+  std::memcpy(h.magic, kSaveMagic, 8);
+  h.version = kSaveVersion;
+  h.sz_domain = sizeof(pd_domain);
+  h.sz_state = sizeof(DevState);
+  h.sz_mgscal = sizeof(MGScal);
+  h.dom = c->dom;
+  h.precision = c->opts.precision;
+  h.poisson = c->opts.poisson;
+  h.enable_di = c->opts.enable_di;
+  h.deposit_off = c->opts.deposit_off;
+  h.collisions_off = c->opts.collisions_off;
+  put(&h, sizeof h);
+  put(c->spp.Z, sizeof c->spp.Z);
+  put(c->spp.m, sizeof c->spp.m);
+  for (int k = 0; k < kNC; ++k) {
+    const int32_t set = c->xs_set[k] ? 1 : 0;
+    const int32_t n = set ? c->cpar.tabn[k] : 0;
+    put(&set, 4);
+    put(&n, 4);
+    put(&c->cpar.thr[k], 8);
+    put(&c->cpar.dsq[k], 8);
+    if (set && (s = putd(c->d_xs[k], 8 * (size_t)n))) return s;
+  }
+  put(&st, sizeof st);
+  const size_t n = st.n_total, esz = c->fp32 ? 4 : 8;
+  const size_t nn = (size_t)(c->g.nr + 1) * (c->g.nz + 1);
+  void* rec[5];
+  uint8_t* sp;
+  uint32_t *id, *key;
+  if (c->fp32) {
+    float* a[5] = {c->Af.r, c->Af.z, c->Af.vr, c->Af.vt, c->Af.vz};
+    for (int k = 0; k < 5; ++k) rec[k] = a[k];
+    sp = c->Af.sp; id = c->Af.id; key = c->Af.key;
+  } else {
+    double* a[5] = {c->A.r, c->A.z, c->A.vr, c->A.vt, c->A.vz};
+    for (int k = 0; k < 5; ++k) rec[k] = a[k];
+    sp = c->A.sp; id = c->A.id; key = c->A.key;
+  }
+  for (int k = 0; k < 5; ++k)
+    if ((s = putd(rec[k], esz * n))) return s;
+  if ((s = putd(sp, n)) || (s = putd(id, 4 * n)) || (s = putd(key, 4 * n)) ||
+      (s = putd(c->sw.skey, 4 * (size_t)st.n_alive)) ||
+      (s = putd(c->off, 4 * ((size_t)c->g.sentinel + 1))) || (s = putd(c->fw.Q, 8 * nn)) ||
+      (s = putd(c->fw.phi, 8 * nn)) || (s = putd(c->fw.Er, 8 * nn)) ||
+      (s = putd(c->fw.Ez, 8 * nn)))
+    return s;
+  const int64_t sn = c->sched_n;
+  put(&sn, 8);
+  if (sn > 0) {
+    std::vector<int64_t> off(sn + 1);
+    HIPCHK(c, hipMemcpy(off.data(), c->sched.off, 8 * (sn + 1), hipMemcpyDeviceToHost));
+    put(off.data(), 8 * (sn + 1));
+    const size_t tot = (size_t)off[sn];
+    const double* a[5] = {c->sched.r, c->sched.z, c->sched.vr, c->sched.vt, c->sched.vz};
+    for (int k = 0; k < 5; ++k)
+      if ((s = putd(a[k], 8 * tot))) return s;
+    if ((s = putd(c->sched.sp, tot))) return s;
+  }
+  SaveHost hh{};
+  for (int k = 0; k < kNS; ++k) hh.injected[k] = c->injected[k];
+  hh.host_step = c->host_step;
+  hh.host_sched_pos = c->host_sched_pos;
+  hh.sched_n = c->sched_n;
+  hh.p_solves = c->p_solves;
+  hh.p_fallbacks = c->p_fallbacks;
+  hh.mg_inner = c->mg_inner;
+  put(&hh, sizeof hh);
+  if ((s = putd(c->mg.sc, sizeof(MGScal)))) return s;
+  put(kSaveMagic, 8);
+  FILE* f = std::fopen(path, "wb");
+  if (!f) return set_err(c, PD_EINVAL, "cannot open %s for writing", path);
+  const size_t w = std::fwrite(out.data(), 1, out.size(), f);
+  const int cl = std::fclose(f);
+  if (w != out.size() || cl != 0) return set_err(c, PD_EINVAL, "short write to %s", path);
+  return PD_OK;
+}
+
+pd_status pd_load(pd_ctx* c, const char* path) {
+  if (!c) return PD_EINVAL;
+  if (!path) return set_err(c, PD_EINVAL, "path is NULL");
+  if (c->poisoned) return set_err(c, PD_ESTATE, "context unusable after an earlier error");
+  if (c->in_ensemble) return set_err(c, PD_ESTATE, "context is in an ensemble");
+  std::vector<unsigned char> in;
+  {
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return set_err(c, PD_EINVAL, "cannot open %s", path);
+    unsigned char buf[1 << 16];
+    size_t r;
+    while ((r = std::fread(buf, 1, sizeof buf, f)) > 0) in.insert(in.end(), buf, buf + r);
+    std::fclose(f);
+  }
+  // parse and check everything before the context is touched
+  size_t pos = 0;
+  bool ok = true;
+  auto get = [&](void* p, size_t n) {
+    if (!ok || n > in.size() - pos) {
+      ok = false;
+      return;
+    }
+    std::memcpy(p, in.data() + pos, n);
+    pos += n;
+  };
+  auto span = [&](size_t n) -> const unsigned char* {
+    if (!ok || n > in.size() - pos) {
+      ok = false;
+      return nullptr;
+    }
+    const unsigned char* p = in.data() + pos;
+    pos += n;
+    return p;
+  };
+  SaveHead h{};
+  get(&h, sizeof h);
+  if (!ok || std::memcmp(h.magic, kSaveMagic, 8) != 0 || h.version != kSaveVersion ||
+      h.sz_domain != sizeof(pd_domain) || h.sz_state != sizeof(DevState) ||
+      h.sz_mgscal != sizeof(MGScal))
+    return set_err(c, PD_EINVAL, "%s: not a state file of this library version", path);
+  const pd_domain& d = h.dom;
+  if (d.nr != c->dom.nr || d.nz != c->dom.nz || d.R != c->dom.R || d.L != c->dom.L ||
+      d.V_cathode != c->dom.V_cathode || d.dt != c->dom.dt || d.weight != c->dom.weight ||
+      d.seed != c->dom.seed || h.precision != c->opts.precision ||
+      h.enable_di != c->opts.enable_di || h.deposit_off != c->opts.deposit_off ||
+      h.collisions_off != c->opts.collisions_off)
+    return set_err(c, PD_EINVAL, "%s: domain or options differ from the context's", path);
+  int32_t Z[kNS];
+  double m[kNS];
+  get(Z, sizeof Z);
+  get(m, sizeof m);
+  int32_t xset[kNC], xn[kNC];
+  double xthr[kNC], xdsq[kNC];
+  const double* xsig[kNC];
+  for (int k = 0; k < kNC; ++k) {
+    get(&xset[k], 4);
+    get(&xn[k], 4);
+    get(&xthr[k], 8);
+    get(&xdsq[k], 8);
+    xsig[k] = nullptr;
+    if (ok && xset[k]) {
+      if (xn[k] < 2 || xn[k] > (1 << 24)) ok = false;
+      else xsig[k] = (const double*)span(8 * (size_t)xn[k]);
+    }
+  }
+  DevState st{};
+  get(&st, sizeof st);
+  if (!ok) return set_err(c, PD_EINVAL, "%s: truncated", path);
+  if ((int64_t)st.n_total > c->cap || st.n_alive > st.n_total || st.err != 0)
+    return set_err(c, PD_EINVAL, "%s: %u particles do not fit the capacity %lld", path,
+                   st.n_total, (long long)c->cap);
+  const size_t n = st.n_total, esz = c->fp32 ? 4 : 8;
+  const size_t nn = (size_t)(c->g.nr + 1) * (c->g.nz + 1);
+  const unsigned char* rec[5];
+  for (int k = 0; k < 5; ++k) rec[k] = span(esz * n);
+  const unsigned char* sp = span(n);
+  const unsigned char* id = span(4 * n);
+  const unsigned char* key = span(4 * n);
+  const unsigned char* skey = span(4 * (size_t)st.n_alive);
+  const unsigned char* off = span(4 * ((size_t)c->g.sentinel + 1));
+  const unsigned char* Q = span(8 * nn);
+  const unsigned char* phi = span(8 * nn);
+  const unsigned char* Er = span(8 * nn);
+  const unsigned char* Ez = span(8 * nn);
+  int64_t sn = 0;
+  get(&sn, 8);
+  std::vector<int64_t> soff;
+  const unsigned char* sarr[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  if (ok && (sn < 0 || sn > (1 << 26))) ok = false;
+  if (ok && sn > 0) {
+    soff.resize(sn + 1);
+    get(soff.data(), 8 * (sn + 1));
+    if (ok && soff[0] != 0) ok = false;
+    for (int64_t k = 0; ok && k < sn; ++k)
+      if (soff[k + 1] < soff[k]) ok = false;
+    if (ok) {
+      const size_t tot = (size_t)soff[sn];
+      for (int k = 0; k < 5; ++k) sarr[k] = span(8 * tot);
+      sarr[5] = span(tot);
+    }
+  }
+  SaveHost hh{};
+  get(&hh, sizeof hh);
+  const unsigned char* sc = span(sizeof(MGScal));
+  char tail[8] = {0};
+  get(tail, 8);
+  if (!ok || pos != in.size() || std::memcmp(tail, kSaveMagic, 8) != 0)
+    return set_err(c, PD_EINVAL, "%s: truncated or malformed", path);
+  if (hh.sched_n != sn || hh.host_sched_pos < 0 || hh.host_sched_pos > sn ||
+      st.sched_n != (uint32_t)sn || st.sched_pos > (uint32_t)sn)
+    return set_err(c, PD_EINVAL, "%s: inconsistent injection schedule", path);
+  for (size_t p = 0; p < n; ++p)
+    if (sp[p] >= kNS) return set_err(c, PD_EINVAL, "%s: species out of range", path);
+  for (int64_t p = 0; p < (sn > 0 ? soff[sn] : 0); ++p)
+    if (sarr[5][p] >= kNS) return set_err(c, PD_EINVAL, "%s: schedule species out of range", path);
+  // apply: tables, then the device state
+  pd_status s = pd_set_species(c, kNS, Z, m);
+  if (s) return s;
+  for (int k = 0; k < kNC; ++k)
+    if (xset[k] && (s = pd_set_cross_section(c, k, xthr[k], xn[k], xdsq[k], xsig[k]))) return s;
+  if (sn > 0) {
+    std::vector<double> a[5];
+    for (int k = 0; k < 5; ++k) {
+      a[k].resize((size_t)soff[sn]);
+      std::memcpy(a[k].data(), sarr[k], 8 * a[k].size());
+    }
+    if ((s = pd_schedule_injection(c, (int)sn, soff.data(), a[0].data(), a[1].data(),
+                                   a[2].data(), a[3].data(), a[4].data(), sarr[5])))
+      return s;
+  } else if ((s = pd_schedule_injection(c, 0, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                        nullptr, nullptr))) {
+    return s;
+  }
+  if ((s = sync(c))) return s;
+  void* drec[5];
+  uint8_t* dsp;
+  uint32_t *did, *dkey;
+  if (c->fp32) {
+    float* a[5] = {c->Af.r, c->Af.z, c->Af.vr, c->Af.vt, c->Af.vz};
+    for (int k = 0; k < 5; ++k) drec[k] = a[k];
+    dsp = c->Af.sp; did = c->Af.id; dkey = c->Af.key;
+  } else {
+    double* a[5] = {c->A.r, c->A.z, c->A.vr, c->A.vt, c->A.vz};
+    for (int k = 0; k < 5; ++k) drec[k] = a[k];
+    dsp = c->A.sp; did = c->A.id; dkey = c->A.key;
+  }
+  auto up = [&](void* dst, const void* src, size_t bytes) -> pd_status {
+    if (bytes) HIPCHK(c, hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
+    return PD_OK;
+  };
+  for (int k = 0; k < 5; ++k)
+    if ((s = up(drec[k], rec[k], esz * n))) return s;
+  if ((s = up(dsp, sp, n)) || (s = up(did, id, 4 * n)) || (s = up(dkey, key, 4 * n)) ||
+      (s = up(c->sw.skey, skey, 4 * (size_t)st.n_alive)) ||
+      (s = up(c->off, off, 4 * ((size_t)c->g.sentinel + 1))) || (s = up(c->fw.Q, Q, 8 * nn)) ||
+      (s = up(c->fw.phi, phi, 8 * nn)) || (s = up(c->fw.Er, Er, 8 * nn)) ||
+      (s = up(c->fw.Ez, Ez, 8 * nn)) || (s = up(c->st, &st, sizeof st)) ||
+      (s = up(c->mg.sc, sc, sizeof(MGScal))))
+    return s;
+  for (int k = 0; k < kNS; ++k) c->injected[k] = hh.injected[k];
+  c->host_step = hh.host_step;
+  c->host_sched_pos = hh.host_sched_pos;
+  c->p_solves = hh.p_solves;
+  c->p_fallbacks = hh.p_fallbacks;
+  c->mg_inner = hh.mg_inner;
+  if (c->fp32) {
+    // the FP32 copies of the field follow the FP64 field
+    field(c->g, c->fw, c->stream);
+    HIPCHK(c, hipGetLastError());
+  }
+  return sync(c);
+}
+
 pd_status pd_poisson_noalloc(pd_ctx* c, const int64_t* Q, double* phi, void* stream) {
   if (!c) return PD_EINVAL;
   if (c->poisoned) return set_err(c, PD_ESTATE, "context unusable after an earlier error");

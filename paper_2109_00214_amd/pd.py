@@ -23,7 +23,7 @@ TIMER_NAMES = ("radix", "permute", "offsets", "collide", "deposit", "poisson", "
 EXPORTED = ("pd_create", "pd_set_species", "pd_set_cross_section", "pd_inject",
             "pd_schedule_injection", "pd_step", "pd_synchronize", "pd_get_diagnostics",
             "pd_get_spectrum", "pd_get_count", "pd_get_particles", "pd_get_field",
-            "pd_poisson", "pd_poisson_noalloc", "pd_get_timing", "pd_set_timing", "pd_last_error", "pd_destroy",
+            "pd_poisson", "pd_poisson_noalloc", "pd_save", "pd_load", "pd_get_timing", "pd_set_timing", "pd_last_error", "pd_destroy",
             "pd_unet_create", "pd_unet_info", "pd_unet_set_weights", "pd_unet_get_weights",
             "pd_unet_forward", "pd_unet_gradient", "pd_unet_add_sample", "pd_unet_train",
             "pd_set_unet", "pd_unet_last_error", "pd_unet_destroy",
@@ -88,6 +88,8 @@ def load_library(path=LIB_PATH):
     lib.pd_get_field.argtypes = [P, P, P, P, P]
     lib.pd_poisson.argtypes = [P, P, P, C.POINTER(C.c_int32), C.POINTER(C.c_double)]
     lib.pd_poisson_noalloc.argtypes = [P, P, P, P]
+    lib.pd_save.argtypes = [P, C.c_char_p]
+    lib.pd_load.argtypes = [P, C.c_char_p]
     lib.pd_get_timing.argtypes = [P, P, C.POINTER(C.c_int64), C.c_int]
     lib.pd_set_timing.argtypes = [P, C.c_int]
     lib.pd_last_error.argtypes = [P]
@@ -240,6 +242,14 @@ def pd_poisson_noalloc(ctx, q_dev, phi_dev, stream=None):
     device addresses as integers); enqueues and returns (no synchronisation)."""
     _check(ctx, load_library().pd_poisson_noalloc(ctx, C.c_void_p(q_dev), C.c_void_p(phi_dev),
                                                   C.c_void_p(stream)))
+
+
+def pd_save(ctx, path):
+    _check(ctx, load_library().pd_save(ctx, os.fsencode(path)))
+
+
+def pd_load(ctx, path):
+    _check(ctx, load_library().pd_load(ctx, os.fsencode(path)))
 
 
 def _check_net(net, status):
@@ -397,6 +407,12 @@ class Simulation:
 
     def diag(self):
         return pd_get_diagnostics(self.h)
+
+    def save(self, path):
+        pd_save(self.h, path)
+
+    def load(self, path):
+        pd_load(self.h, path)
 
     def spectrum(self, tag):
         return pd_get_spectrum(self.h, tag)
