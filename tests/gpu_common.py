@@ -114,3 +114,19 @@ def assert_close_state(g, o, where="", rel=1e-10):
     for t in range(3):
         assert np.array_equal(g.spectrum(t), do["spectrum"][t]), (where, "spectrum", t)
     return pg
+
+
+def state_deviation(g, o):
+    """Largest deviation of the GPU's floating-point state from the oracle's,
+    over the oracle's largest magnitude, per quantity (for logs; the particles
+    must be the same ones in the same order)."""
+    pg, po = g.particles(), o.particles()
+    out = {}
+    if len(pg["r"]) == len(po["r"]):
+        for k in ("r", "z", "vr", "vt", "vz"):
+            out[k] = float(np.max(np.abs(pg[k] - po[k])) / max(np.max(np.abs(po[k])), 1e-300))
+    fg, fo = g.field(), o.field()
+    for k in ("phi", "Er", "Ez"):
+        out[k] = float(np.max(np.abs(fg[k] - fo[k])) / max(np.max(np.abs(fo[k])), 1e-300))
+    out["Q_units_2^20"] = float(np.max(np.abs(fg["Q"] - fo["Q"]))) / 2.0 ** 20
+    return out

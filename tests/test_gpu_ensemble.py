@@ -5,7 +5,8 @@ of the same replicas stepped one by one."""
 import numpy as np
 import pytest
 
-from gpu_common import first_diff, gpu_sim, log
+from conftest import make_oracle
+from gpu_common import assert_same_state, first_diff, gpu_sim, log
 from paper_2109_00214_amd import pd
 from paper_2109_00214_amd import workload as W
 
@@ -89,3 +90,42 @@ def test_ensemble_errors():
         pd.pd_ensemble_step(ens, 0)
     finally:
         pd.pd_ensemble_destroy(ens)
+
+
+def test_fp64_members_match_the_oracle():
+    """Members drawn as the batched form draws its replicas (grid 128 x 256 or
+    256 x 512, voltage 1-5 kV, weight 5e6 / N, their own seed), here in the FP64
+    form and with the population cut to 0.2M (the smallest the batched form
+    draws) so that the oracle can step beside them: after graph replays, every
+    member equals, bit for bit, its own oracle stepped alongside."""
+    import dataclasses
+    cfgs = W.ensemble_configs(8)
+    picked = [c for c in cfgs if c.nr == 128][:2] + [c for c in cfgs if c.nr == 256][:1]
+    picked = [dataclasses.replace(c, n_init=200_000) for c in picked]
+    steps = 8
+    log("case: ensemble members against the oracle: %s" %
+        [(c.nr, c.nz, round(c.V), c.n_init) for c in picked])
+    mems, orcs = [], []
+    for c in picked:
+        parts = W.initial_population(c)
+        off, inj = W.injection_schedule(c, steps)
+        g = gpu_sim(c, int(1.5 * c.n_init + 4 * (c.inj_e + c.inj_cu) * steps + 65536))
+        o = make_oracle(c)
+        for sim in (g, o):
+            sim.inject(parts)
+            sim.schedule_injection(off, inj)
+        mems.append(g)
+        orcs.append(o)
+    ens = pd.pd_ensemble_create([m.h for m in mems], nstreams=2)
+    try:
+        for rep in range(steps // 2):
+            pd.pd_ensemble_step(ens, 2)
+            pd.pd_ensemble_synchronize(ens)
+            for i, (m, o) in enumerate(zip(mems, orcs)):
+                o.step(2)
+                assert_same_state(m, o, "replay %d member %d (%dx%d)" %
+                                  (rep, i, picked[i].nr, picked[i].nz))
+    finally:
+        pd.pd_ensemble_destroy(ens)
+    for m in mems:
+        m.close()

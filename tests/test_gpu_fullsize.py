@@ -3,25 +3,37 @@ super-particles, and the capacity of the benchmark's default 2100-step run,
 so every launch has the benchmark's grid.  The GPU and the oracle step the
 same seeded inputs.
 
-With the fixed-order direct Poisson solve the whole state is bit-identical
-after every step.  With the matrix-core solve (the benchmark's default) the
-potential differs from the oracle's in the last bits, and the fixed-point
-deposit turns that into rare differences of one 2^-20 weight step at the
-next deposit; so the whole state is compared after the first step (every
-integer result identical, positions, velocities, potential and field within
-1e-10 relative), and after the later steps the field of the GPU's own node
-charges is checked against the oracle's solve of those same charges."""
+With the fixed-order direct Poisson solve (the benchmark's default) the whole
+state is bit-identical after every step.  With the matrix-core solve the
+potential differs from the oracle's in the last bits; the state after the
+first step is within 1e-10 (every integer result identical), and from then on
+the fixed-point deposit turns those last bits into rare differences of one
+2^-20 weight step (a few units of Z 2^20 at some nodes, total exact), which
+move the field by about 1e-7 of its largest value near those nodes.  So the
+oracle is stepped beside it for ten steps: after each one every integer
+result (keys, hence the sort order, ids, species, counts, events) must be
+identical, each node charge within 1e-4 of one particle's charge (total
+exact), positions, velocities, potential and field within REL_STEPS of the
+oracle's (the measured deviations are logged), and the field of the GPU's own
+node charges within 1e-10 of the oracle's solve of those same charges.  A
+failure names the first step and the first differing particle."""
 import numpy as np
 import pytest
 
 from conftest import make_oracle
-from gpu_common import assert_close_state, assert_same_state, gpu_sim, log
+from gpu_common import assert_close_state, assert_same_state, gpu_sim, log, state_deviation
 from paper_2109_00214_amd import workload as W
 
 pytestmark = pytest.mark.gpu
 
-BENCH_STEPS = 20 + 1980 + 100  # warm-up, timed and stage-timed steps of the default run
-STEPS = 3
+# warm-up, timed, stage-timed and solver-comparison steps of the benchmark run
+# the end of each round times (bench.py --steps 20 --warmup 5)
+BENCH_STEPS = 5 + 20 + 100 + 10
+STEPS = {"direct": 3, "spectral": 10}
+# measured over the ten steps: integer results identical throughout, positions
+# and velocities within 5.5e-10, potential 9.5e-12, field 1.0e-8 (growing
+# from step to step); about 100 times that
+REL_STEPS = 1e-6
 
 
 def _field_close(fg, fo, rel):
@@ -37,7 +49,7 @@ def _field_close(fg, fo, rel):
 @pytest.mark.parametrize("mode", ["direct", "spectral"])
 def test_paper_workload_full_size(mode):
     from paper_2109_00214_amd.pd import PD_POISSON_DIRECT64, PD_POISSON_SPECTRAL
-    log("case: paper workload, full size, %s Poisson, %d steps" % (mode, STEPS))
+    log("case: paper workload, full size, %s Poisson, %d steps" % (mode, STEPS[mode]))
     cfg = W.config("paper")
     parts = W.initial_population(cfg)
     off, inj = W.injection_schedule(cfg, BENCH_STEPS)
@@ -48,16 +60,17 @@ def test_paper_workload_full_size(mode):
         sim.inject(parts)
         sim.schedule_injection(off, inj)
     solver = make_oracle(cfg)  # no particles: solves given node charges
-    for s in range(1, STEPS + 1):
+    for s in range(1, STEPS[mode] + 1):
         where = "full size, %s, step %d" % (mode, s)
         g.step(1)
+        o.step(1)
         if mode == "direct":
-            o.step(1)
             assert_same_state(g, o, where)
-        elif s == 1:
-            o.step(1)
-            assert_close_state(g, o, where, rel=1e-10)
         else:
+            errs = state_deviation(g, o)
+            log("  step %d: largest deviation of the oracle's, over its largest magnitude: %s" %
+                (s, {k: "%.1e" % v for k, v in errs.items()}))
+            assert_close_state(g, o, where, rel=1e-10 if s == 1 else REL_STEPS)
             fg = g.field()
             solver.set_charge(fg["Q"])
             solver.stage("poisson")

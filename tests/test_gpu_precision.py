@@ -5,10 +5,12 @@ CG with FP64 refinement) against the FP64 oracle, per result:
   - one step from the same state: positions and velocities agree to FP32
     rounding, node charges stay exact integers that sum to the total charge;
   - the tiny workload after 200 steps: potential, per-species counts and the
-    channel-resolved Cu2+ spectra agree with the oracle's within the stated
-    tolerances (the two runs part ways where a collision test or a cell
-    boundary falls differently in FP32, so these are distribution-level
-    comparisons).
+    channel-resolved Cu2+ spectra (every bin of every label) agree with the
+    oracle's within the stated tolerances;
+  - the paper-shaped workload (5M particles) for three steps: per-particle
+    position and velocity errors as quantiles, the particles whose history
+    parted ways (a collision test or a wall that falls the other way in FP32)
+    counted, potential and species counts.
 """
 import numpy as np
 import pytest
@@ -20,11 +22,21 @@ from paper_2109_00214_amd.pd import PD_FP32_MIXED, PD_POISSON_MGPCG
 
 pytestmark = pytest.mark.gpu
 
-# per-result tolerances of the tiny workload after 200 steps (FP32 form vs
-# the FP64 oracle)
-TOL_PHI = 2e-2        # max |phi32 - phi64| / max |phi64|
-TOL_COUNT = 0.03      # relative, species with >= 1000 particles
-TOL_SPEC_TV = 0.15    # total-variation distance of the normalised spectra (tags with >= 200)
+# per-result tolerances of the FP32 form against the FP64 oracle, about 100
+# times what was measured (the measured values are in the test log):
+#   tiny workload after 200 steps: potential 2.3e-8 of max |phi|; every
+#   species count and every spectrum bin equal
+TOL_PHI = 3e-6        # max |phi32 - phi64| / max |phi64|
+TOL_COUNT = 2         # particles, per species (absolute)
+TOL_BIN = 2           # particles, per Cu2+ spectrum bin and label (absolute)
+#   paper workload, 3 steps: the 99.99 % quantile of the position error 2e-7
+#   of the extent and of the velocity error 3e-6 of the speed; 2 to 15 of
+#   4.7M particles parted ways; potential 1e-7; species counts within 1
+TOL_PAPER_POS = 2e-5     # 99.99 % quantile of |d(r, z)| / extent
+TOL_PAPER_VEL = 3e-4     # 99.99 % quantile of |dv| / |v|
+TOL_PAPER_PARTED = 1000  # particles whose history parted ways, or in one run only
+TOL_PAPER_PHI = 1e-5     # max |d| / max |phi|
+TOL_PAPER_COUNT = 100    # per species
 
 
 def _fp32_pair(cfg, parts, steps, **kw):
@@ -86,21 +98,71 @@ def test_fp32_tiny_200_steps_error_per_result():
     assert dg["poisson_fallbacks"] == 0 and dg["poisson_rel_res"] <= 1e-8
     fg, fo = g.field(), o.field()
     ephi = np.max(np.abs(fg["phi"] - fo["phi"])) / np.max(np.abs(fo["phi"]))
-    log("  potential: max |d| / max |phi| = %.3e" % ephi)
+    log("  potential: max |d| / max |phi| = %.3e (tolerance %.1e)" % (ephi, TOL_PHI))
     assert ephi < TOL_PHI
     for s in range(6):
         n32, n64 = int(dg["count"][s]), int(do["count"][s])
-        rel = abs(n32 - n64) / max(n64, 1)
-        log("  species %d: FP32 %d, FP64 %d, rel %.3e" % (s, n32, n64, rel))
-        if n64 >= 1000:
-            assert rel < TOL_COUNT
+        log("  species %d: FP32 %d, FP64 %d" % (s, n32, n64))
+        assert abs(n32 - n64) <= TOL_COUNT, s
+    # the Cu2+ spectrum of every label (step-wise, double ionization,
+    # initial), all 66 bins (64 log bins, under- and overflow), however few
+    # ions a label holds
     for t in range(3):
-        h32, h64 = g.spectrum(t)[:64].astype(float), np.asarray(do["spectrum"][t][:64], float)
-        if h64.sum() < 200:
-            log("  spectrum tag %d: %d vs %d particles (too few to compare)" % (t, h32.sum(), h64.sum()))
-            continue
-        tv = 0.5 * np.sum(np.abs(h32 / max(h32.sum(), 1) - h64 / h64.sum()))
-        log("  spectrum tag %d: %d vs %d particles, TV distance %.3f" % (t, h32.sum(), h64.sum(), tv))
-        assert tv < TOL_SPEC_TV
+        h32 = g.spectrum(t).astype(np.int64)
+        h64 = np.asarray(do["spectrum"][t], np.int64)
+        dmax = int(np.max(np.abs(h32 - h64)))
+        log("  spectrum label %d: %d vs %d ions, largest bin difference %d" %
+            (t, h32.sum(), h64.sum(), dmax))
+        assert abs(int(h32.sum()) - int(h64.sum())) <= TOL_BIN, t
+        assert dmax <= TOL_BIN, t
     ev = [(int(a), int(b)) for a, b in zip(dg["events"], do["events"])]
     log("  events per channel (FP32, FP64): %s" % ev)
+
+
+def test_fp32_paper_size_error_per_result():
+    """The FP32 form on the paper-shaped workload (256 x 512 cells, 5M
+    particles, W = 1) for three steps beside the FP64 oracle.  A collision
+    test (or a wall) that falls the other way in FP32 gives that particle a
+    different history from then on, so the per-particle errors are stated as
+    quantiles over the particles present in both runs (matched by id), with
+    the number of particles whose velocity parted ways (|dv| above 1e-3 of
+    their speed) counted apart; the potential and the species counts are
+    compared directly."""
+    log("case: FP32 form vs FP64 oracle, paper workload, 3 steps")
+    cfg = W.config("paper")
+    parts = W.initial_population(cfg)
+    g, o = _fp32_pair(cfg, parts, 3)
+    n0 = len(parts["r"])
+    for s in range(1, 4):
+        g.step(1)
+        o.step(1)
+        a, b = _by_id(g.particles()), _by_id(o.particles())
+        # the initial particles keep their ids in both runs (the ids of the
+        # electrons a collision creates, and of every particle injected after
+        # it, shift when one run has a collision the other does not)
+        a = {k: v[a["id"] < n0] for k, v in a.items()}
+        b = {k: v[b["id"] < n0] for k, v in b.items()}
+        common, ia, ib = np.intersect1d(a["id"], b["id"], assume_unique=True,
+                                        return_indices=True)
+        lost = len(b["id"]) - len(common) + len(a["id"]) - len(common)
+        dpos = np.hypot((a["r"][ia] - b["r"][ib]) / cfg.R, (a["z"][ia] - b["z"][ib]) / cfg.L)
+        va = np.stack([a[k][ia] for k in ("vr", "vt", "vz")])
+        vb = np.stack([b[k][ib] for k in ("vr", "vt", "vz")])
+        speed = np.maximum(np.linalg.norm(vb, axis=0), 1e-300)
+        dvel = np.linalg.norm(va - vb, axis=0) / speed
+        parted = int(np.count_nonzero(dvel > 1e-3))
+        q = lambda x: [float(np.quantile(x, f)) for f in (0.5, 0.99, 0.9999)]
+        fg, fo = g.field(), o.field()
+        ephi = float(np.max(np.abs(fg["phi"] - fo["phi"])) / np.max(np.abs(fo["phi"])))
+        dg, do = g.diag(), o.diag()
+        dcount = [int(x) - int(y) for x, y in zip(dg["count"], do["count"])]
+        log("  step %d: %d initial particles, %d in one run only, %d parted ways; position error "
+            "(of the extent) quantiles 50/99/99.99 %% %s, velocity error (of the speed) %s; "
+            "potential %.2e; count differences %s" %
+            (s, len(b["id"]), lost, parted, ["%.1e" % x for x in q(dpos)],
+             ["%.1e" % x for x in q(dvel)], ephi, dcount))
+        assert q(dpos)[2] < TOL_PAPER_POS and q(dvel)[2] < TOL_PAPER_VEL, s
+        assert parted <= TOL_PAPER_PARTED and lost <= TOL_PAPER_PARTED, s
+        assert ephi < TOL_PAPER_PHI, s
+        assert max(abs(x) for x in dcount) <= TOL_PAPER_COUNT, s
+        assert dg["poisson_fallbacks"] == 0 and dg["poisson_rel_res"] <= 1e-8
