@@ -66,6 +66,7 @@ def load_oracle(path):
     lib.or_inject.argtypes = [P, C.c_int64, P, P, P, P, P, P]
     lib.or_schedule_injection.argtypes = [P, C.c_int, P, P, P, P, P, P, P]
     lib.or_step.argtypes = [P, C.c_int]
+    lib.or_set_heavy_subcycle.argtypes = [P, C.c_int]
     for nm in ("sort", "collide", "deposit", "poisson", "field", "push",
                "compact_inject", "end"):
         getattr(lib, "or_stage_" + nm).argtypes = [P]
@@ -156,6 +157,9 @@ class Oracle:
         a = self._arrs(parts)
         self._chk(self.lib.or_schedule_injection(self.h, len(off) - 1, _p(off),
                                                  *[_p(x) for x in a]))
+
+    def set_heavy_subcycle(self, every):
+        self._chk(self.lib.or_set_heavy_subcycle(self.h, int(every)))
 
     def step(self, nsteps=1):
         self._chk(self.lib.or_step(self.h, nsteps))

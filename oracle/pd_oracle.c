@@ -45,6 +45,7 @@ struct or_sim {
   double R, L, V, dt, W;
   uint64_t seed;
   int enable_di, deposit_off, collisions_off;
+  int heavy_every;  /* heavy particles advance every heavy_every steps (1: every step) */
 
   int Z[OR_NSPECIES];
   double m[OR_NSPECIES];
@@ -154,6 +155,7 @@ or_sim* or_create(int nr, int nz, double R, double L, double V, double dt,
   s->R = R; s->L = L; s->V = V; s->dt = dt; s->W = weight; s->seed = seed;
   s->enable_di = enable_di; s->deposit_off = deposit_off;
   s->collisions_off = collisions_off;
+  s->heavy_every = 1;
   s->dr = R / (double)nr;
   s->dz = L / (double)nz;
   s->qunit = (Q_E * weight) * 0x1p-40;
@@ -759,13 +761,34 @@ void or_stage_field(or_sim* s) {
 }
 
 /* ------------------------------------------------------------------ */
+/* Heavy-particle subcycling (Sec. 2.3: the heavy particles' time step is
+ * ten times the electrons'): with heavy_every = K > 1 the electrons are
+ * pushed every step with dt, the heavy species only on the steps whose
+ * counter is a multiple of K, with the step K dt, and they stay where they
+ * are in between (collisions still change their velocity and label).      */
+int or_set_heavy_subcycle(or_sim* s, int every) {
+  if (every < 1 || every > 1000) return fail("or_set_heavy_subcycle: every must be in 1..1000");
+  s->heavy_every = every;
+  return 0;
+}
+
 /* 9. gather (the deposit's bilinear weights, unrounded) and leapfrog push
  *    in 2D3V: v += (q/m) E dt; straight move in the particle's local
  *    Cartesian frame; rotate back to the r-z plane                        */
 void or_stage_push(or_sim* s) {
   const int nr = s->nr, W = nr + 1;
-  const double dt = s->dt;
+  const int K = s->heavy_every;
+  const int heavy_now = (K <= 1) || ((s->step % K) == 0);
+  const double dt_h = (double)K * s->dt;
   for (int64_t p = 0; p < s->n; ++p) {
+    const int heavy = s->sp[p] != OR_E;
+    if (heavy && !heavy_now) {
+      /* not a heavy step: the particle stays; its key follows its label */
+      s->alive[p] = 1;
+      s->key[p] = key_of(s, s->r[p], s->z[p], s->sp[p]);
+      continue;
+    }
+    const double dt = (heavy && K > 1) ? dt_h : s->dt;
     int i, j; double fr, fz;
     cell_of(s, s->r[p], s->z[p], &i, &j, &fr, &fz);
     size_t b = (size_t)j * W + i;
@@ -773,7 +796,8 @@ void or_stage_push(or_sim* s) {
     double w00 = gr * gz, w10 = fr * gz, w01 = gr * fz, w11 = fr * fz;
     double Er = (((w00 * s->Er[b]) + (w10 * s->Er[b + 1])) + (w01 * s->Er[b + W])) + (w11 * s->Er[b + W + 1]);
     double Ez = (((w00 * s->Ez[b]) + (w10 * s->Ez[b + 1])) + (w01 * s->Ez[b + W])) + (w11 * s->Ez[b + W + 1]);
-    double qm = s->qmdt[s->sp[p]];
+    double qm = (heavy && K > 1) ? (((double)s->Z[s->sp[p]] * Q_E) / s->m[s->sp[p]]) * dt_h
+                                 : s->qmdt[s->sp[p]];
     double vr = s->vr[p] + (qm * Er);
     double vz = s->vz[p] + (qm * Ez);
     double vt = s->vt[p];

@@ -62,6 +62,9 @@ int or_schedule_injection(or_sim* s, int nsteps, const int64_t* offsets,
                           const double* r, const double* z, const double* vr,
                           const double* vt, const double* vz, const uint8_t* sp);
 int or_step(or_sim* s, int nsteps);
+/* heavy-particle subcycling: heavy species advance every `every` steps with
+ * the step every*dt (1, the default: every step) */
+int or_set_heavy_subcycle(or_sim* s, int every);
 
 /* stage-level entry points (a full step is these in this order) */
 void or_stage_sort(or_sim* s);
