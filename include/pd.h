@@ -159,6 +159,16 @@ pd_status pd_set_species(pd_ctx* ctx, int n, const int32_t* Z, const double* mas
 pd_status pd_set_cross_section(pd_ctx* ctx, int channel, double threshold_eV, int n,
                                double dsqrtE, const double* sigma);
 
+/* Heavy-particle subcycling (Sec. 2.3: the heavy particles' time step is ten
+ * times the electrons'): with every = K > 1 the electrons are pushed every
+ * step with dt, the heavy species (Cu and its ions) only on the steps whose
+ * counter is a multiple of K, with the step K dt, and they keep their
+ * positions in between (collisions still act on them every step).  K = 1,
+ * the default, pushes every species every step.  Velocities of injected
+ * heavy particles are taken at the half step K dt / 2 before their first
+ * push.  Errors: PD_EINVAL (K outside 1..1000), PD_ESTATE (ensemble member).*/
+pd_status pd_set_heavy_subcycle(pd_ctx* ctx, int32_t every);
+
 /* Append n particles now: positions r, z (0 <= r < R, 0 <= z < L),
  * velocities vr, vt, vz at the half step before their first push
  * (leapfrog), species sp[n].  They receive ids next_id, next_id+1, ...

@@ -197,15 +197,19 @@ template void field_and_inject<float>(const Grid&, FieldWork&, const PartsF&, co
 // plane; absorbed particles get the sentinel key, the others their new key
 // The record of sorted position p comes from U[perm[p]] (live particles) or
 // S[p] (created this step) and goes to S[p], the id and label with it.
+// With heavy subcycling the heavy species advance only on heavy steps, with
+// their own step; on the other steps their record is moved unchanged and its
+// key recomputed (a collision may have changed the label).
 template <typename T>
 __global__ void __launch_bounds__(256) k_push(Flow<T> f, DevState* st, Grid g, SpeciesParams spp,
                                               const T* Er, const T* Ez, Schedule sc,
                                               uint32_t cap) {
   const uint32_t n_alive = st->n_alive;
   const uint32_t n = n_alive + st->n_created;
+  const bool heavy_now = st->heavy_now != 0u;
   if (blockIdx.x == 0 && threadIdx.x == 0) roll_counters(st, inject_plan(st, sc, cap));
   const int W = g.nr + 1;
-  const T dt = (T)g.dt;
+  const bool sub = g.heavy_every > 1;
   const uint32_t stride = gridDim.x * blockDim.x;
   const PartsT<T>& D = f.S;
   for (uint32_t p0 = blockIdx.x * blockDim.x; p0 < n; p0 += stride) {
@@ -226,20 +230,26 @@ __global__ void __launch_bounds__(256) k_push(Flow<T> f, DevState* st, Grid g, S
       const T ez = (((w00 * Ez[b]) + (w10 * Ez[b + 1])) + (w01 * Ez[b + W])) + (w11 * Ez[b + W + 1]);
       const int s = P.sp[q];
       const uint32_t pid = P.id[q];
-      const T qm = (T)spp.qmdt[s];
-      T vr = P.vr[q] + (qm * er);
-      T vz = P.vz[q] + (qm * ez);
-      T vt = P.vt[q];
-      const T x = r + (vr * dt);
-      const T y = vt * dt;
-      const T z = z0 + (vz * dt);
-      const T rn = sqrt((x * x) + (y * y));
-      if (rn > (T)0) {
-        const T c = x / rn, sn = y / rn;
-        const T vr2 = (c * vr) + (sn * vt);
-        const T vt2 = (c * vt) - (sn * vr);
-        vr = vr2;
-        vt = vt2;
+      const bool heavy = s != 0;
+      T vr = P.vr[q], vz = P.vz[q], vt = P.vt[q];
+      T rn = r, z = z0;
+      if (!heavy || heavy_now) {
+        const bool hs = heavy && sub;
+        const T qm = (T)(hs ? spp.qmdt_heavy[s] : spp.qmdt[s]);
+        const T dt = (T)(hs ? g.dt_heavy : g.dt);
+        vr = vr + (qm * er);
+        vz = vz + (qm * ez);
+        const T x = r + (vr * dt);
+        const T y = vt * dt;
+        z = z0 + (vz * dt);
+        rn = sqrt((x * x) + (y * y));
+        if (rn > (T)0) {
+          const T c = x / rn, sn = y / rn;
+          const T vr2 = (c * vr) + (sn * vt);
+          const T vt2 = (c * vt) - (sn * vr);
+          vr = vr2;
+          vt = vt2;
+        }
       }
       D.r[p] = rn;
       D.z[p] = z;

@@ -492,7 +492,9 @@ __global__ void __launch_bounds__(256) k_cls_compact(const uint32_t* __restrict_
                                                      uint32_t* __restrict__ mword,
                                                      uint32_t* __restrict__ mk,
                                                      uint32_t* __restrict__ mi,
-                                                     uint32_t* __restrict__ n_mov) {
+                                                     uint32_t* __restrict__ n_mov,
+                                                     int heavy_every,
+                                                     uint32_t* __restrict__ heavy_now) {
   __shared__ uint32_t sh[4];
   const uint32_t n = st->n_total, n_prev = st->n_alive;
   const uint32_t nb = n / kScanChunk + 1;
@@ -501,6 +503,9 @@ __global__ void __launch_bounds__(256) k_cls_compact(const uint32_t* __restrict_
     if (threadIdx.x == 0) {
       n_mov[0] = all;
       n_mov[1] = n_prev;  // the old order's live count, for the offsets
+      // whether this step's push advances the heavy species (the push itself
+      // cannot read the step counter: its first thread advances it)
+      *heavy_now = (heavy_every <= 1 || (st->step % (uint32_t)heavy_every) == 0u) ? 1u : 0u;
     }
   }
   if (blockIdx.x >= nb) return;
@@ -653,7 +658,8 @@ void sort_keys(const uint32_t* key, int key_bits, SortWork& w, DevState* st, con
   {
     // classify, count and compact the movers (key, index) into k0/v0
     k_cls_count<<<nb, 256, 0, s>>>(key, w.skey, st, w.bsum, w.mbits);
-    k_cls_compact<<<nb, 256, 0, s>>>(key, st, w.bsum, w.mbits, w.mword, w.k0, w.v0, w.n_mov);
+    k_cls_compact<<<nb, 256, 0, s>>>(key, st, w.bsum, w.mbits, w.mword, w.k0, w.v0, w.n_mov,
+                                     w.heavy_every, &st->heavy_now);
     // stable radix sort of the movers
     const uint32_t* kin = w.k0;
     const uint32_t* vin = w.v0;

@@ -667,6 +667,9 @@ pd_status pd_create(const pd_domain* dom, const pd_opts* opts, pd_ctx** out) {
   c->g.L = dom->L;
   c->g.V = dom->V_cathode;
   c->g.dt = dom->dt;
+  c->g.heavy_every = 1;
+  c->g.dt_heavy = dom->dt;
+  c->sw.heavy_every = 1;
   c->qunit = (kQE * dom->weight) * 0x1p-40;
   {
     int b = 0;
@@ -790,6 +793,7 @@ pd_status pd_set_species(pd_ctx* c, int n, const int32_t* Z, const double* mass)
     c->spp.Z[k] = Z[k];
     c->spp.m[k] = mass[k];
     c->spp.qmdt[k] = (((double)Z[k] * kQE) / mass[k]) * c->dom.dt;
+    c->spp.qmdt_heavy[k] = (((double)Z[k] * kQE) / mass[k]) * c->g.dt_heavy;
   }
   c->species_set = true;
   derive_pairs(c);
@@ -818,6 +822,20 @@ pd_status pd_set_cross_section(pd_ctx* c, int ch, double thr, int n, double dsq,
   c->xs_thr[ch] = thr;
   c->xs_set[ch] = true;
   if (c->species_set) derive_pairs(c);
+  return PD_OK;
+}
+
+pd_status pd_set_heavy_subcycle(pd_ctx* c, int32_t every) {
+  if (!c) return PD_EINVAL;
+  if (c->in_ensemble) return set_err(c, PD_ESTATE, "the ensemble's graph holds the step period");
+  if (every < 1 || every > 1000) return set_err(c, PD_EINVAL, "every must be in 1..1000");
+  pd_status s = sync(c);
+  if (s) return s;
+  c->g.heavy_every = every;
+  c->g.dt_heavy = (double)every * c->dom.dt;
+  c->sw.heavy_every = every;
+  for (int k = 0; k < kNS; ++k)
+    c->spp.qmdt_heavy[k] = (((double)c->spp.Z[k] * kQE) / c->spp.m[k]) * c->g.dt_heavy;
   return PD_OK;
 }
 
@@ -1158,7 +1176,7 @@ struct SaveHead {
   char magic[8];
   uint32_t version, sz_domain, sz_state, sz_mgscal;
   pd_domain dom;
-  int32_t precision, poisson, enable_di, deposit_off, collisions_off, pad;
+  int32_t precision, poisson, enable_di, deposit_off, collisions_off, heavy_every;
 };
 
 struct SaveHost {
@@ -1199,6 +1217,7 @@ pd_status pd_save(pd_ctx* c, const char* path) {
   h.enable_di = c->opts.enable_di;
   h.deposit_off = c->opts.deposit_off;
   h.collisions_off = c->opts.collisions_off;
+  h.heavy_every = c->g.heavy_every;
   put(&h, sizeof h);
   put(c->spp.Z, sizeof c->spp.Z);
   put(c->spp.m, sizeof c->spp.m);
@@ -1310,7 +1329,7 @@ pd_status pd_load(pd_ctx* c, const char* path) {
       d.V_cathode != c->dom.V_cathode || d.dt != c->dom.dt || d.weight != c->dom.weight ||
       d.seed != c->dom.seed || h.precision != c->opts.precision ||
       h.enable_di != c->opts.enable_di || h.deposit_off != c->opts.deposit_off ||
-      h.collisions_off != c->opts.collisions_off)
+      h.collisions_off != c->opts.collisions_off || h.heavy_every < 1 || h.heavy_every > 1000)
     return set_err(c, PD_EINVAL, "%s: domain or options differ from the context's", path);
   int32_t Z[kNS];
   double m[kNS];
@@ -1383,6 +1402,7 @@ pd_status pd_load(pd_ctx* c, const char* path) {
   // apply: tables, then the device state
   pd_status s = pd_set_species(c, kNS, Z, m);
   if (s) return s;
+  if ((s = pd_set_heavy_subcycle(c, h.heavy_every))) return s;
   for (int k = 0; k < kNC; ++k)
     if (xset[k] && (s = pd_set_cross_section(c, k, xthr[k], xn[k], xdsq[k], xsig[k]))) return s;
   if (sn > 0) {

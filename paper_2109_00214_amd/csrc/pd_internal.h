@@ -25,7 +25,7 @@ struct DevState {
   uint32_t sched_pos;  // next injection-schedule slot
   uint32_t sched_n;    // schedule length (steps)
   uint32_t err;        // bit 0: capacity overflow
-  uint32_t pad1_;
+  uint32_t heavy_now;  // this step advances the heavy species (set by the sort)
   uint32_t pad_;
   unsigned long long events[kNC];
   unsigned long long conflicts;
@@ -64,12 +64,15 @@ struct Grid {
   uint32_t C;         // cells nr*nz
   uint32_t sentinel;  // key of an absorbed particle (= 6*C)
   double dr, dz, R, L, V, dt;
+  int heavy_every;    // heavy species advance every heavy_every steps (1: every step)
+  double dt_heavy;    // their step, heavy_every * dt
 };
 
 struct SpeciesParams {
   int Z[kNS];
   double qmdt[kNS];   // ((Z e) / m) dt
   double m[kNS];
+  double qmdt_heavy[kNS];  // ((Z e) / m) dt_heavy
 };
 
 struct CollideParams {
@@ -220,6 +223,7 @@ struct SortWork {
   uint32_t* perm;               // [cap] source of every sorted position
   uint32_t* ins;                // [cap] stayers before each sorted mover
   int64_t cap;
+  int heavy_every;              // the heavy-step period (the sort marks heavy steps)
 };
 
 // Stable sort of the st->n_total keys of the records by key (ties in index

@@ -20,7 +20,8 @@ PD_FP64_DET, PD_FP32_MIXED = 0, 1
 PD_POISSON_DIRECT64, PD_POISSON_MGPCG, PD_POISSON_LEARNED, PD_POISSON_SPECTRAL = 0, 1, 2, 3
 TIMER_NAMES = ("radix", "permute", "offsets", "collide", "deposit", "poisson", "field", "push",
                "inject")
-EXPORTED = ("pd_create", "pd_set_species", "pd_set_cross_section", "pd_inject",
+EXPORTED = ("pd_create", "pd_set_species", "pd_set_cross_section", "pd_set_heavy_subcycle",
+            "pd_inject",
             "pd_schedule_injection", "pd_step", "pd_synchronize", "pd_get_diagnostics",
             "pd_get_spectrum", "pd_get_count", "pd_get_particles", "pd_get_field",
             "pd_poisson", "pd_poisson_noalloc", "pd_save", "pd_load", "pd_get_timing", "pd_set_timing", "pd_last_error", "pd_destroy",
@@ -89,6 +90,7 @@ def load_library(path=LIB_PATH):
     lib.pd_poisson.argtypes = [P, P, P, C.POINTER(C.c_int32), C.POINTER(C.c_double)]
     lib.pd_poisson_noalloc.argtypes = [P, P, P, P]
     lib.pd_save.argtypes = [P, C.c_char_p]
+    lib.pd_set_heavy_subcycle.argtypes = [P, C.c_int32]
     lib.pd_load.argtypes = [P, C.c_char_p]
     lib.pd_get_timing.argtypes = [P, P, C.POINTER(C.c_int64), C.c_int]
     lib.pd_set_timing.argtypes = [P, C.c_int]
@@ -242,6 +244,10 @@ def pd_poisson_noalloc(ctx, q_dev, phi_dev, stream=None):
     device addresses as integers); enqueues and returns (no synchronisation)."""
     _check(ctx, load_library().pd_poisson_noalloc(ctx, C.c_void_p(q_dev), C.c_void_p(phi_dev),
                                                   C.c_void_p(stream)))
+
+
+def pd_set_heavy_subcycle(ctx, every):
+    _check(ctx, load_library().pd_set_heavy_subcycle(ctx, int(every)))
 
 
 def pd_save(ctx, path):
@@ -407,6 +413,9 @@ class Simulation:
 
     def diag(self):
         return pd_get_diagnostics(self.h)
+
+    def set_heavy_subcycle(self, every):
+        pd_set_heavy_subcycle(self.h, every)
 
     def save(self, path):
         pd_save(self.h, path)

@@ -252,3 +252,23 @@ def test_created_electrons_beyond_capacity_are_reported():
         g.synchronize()
     assert e.value.status == PD_ECAPACITY
 
+
+
+@pytest.mark.parametrize("every", [10, 3])
+def test_heavy_subcycle_bit_exact(every):
+    """Heavy subcycling (the heavy species advance every K steps with the step
+    K dt): the 32x64 workload for 200 steps, every state bit-identical to the
+    oracle's with the same K, checked on heavy and on ordinary steps."""
+    log("case: heavy subcycling K=%d, tiny config, 200 steps" % every)
+    cfg = W.config("tiny")
+    g, o = pair(cfg, steps=cfg.steps)
+    g.set_heavy_subcycle(every)
+    o.set_heavy_subcycle(every)
+    done = 0
+    for target in (1, 2, every, every + 1, 2 * every + 1, 60, 200):
+        g.step(target - done)
+        o.step(target - done)
+        done = target
+        assert_same_state(g, o, "K=%d step %d" % (every, done))
+    d = g.diag()
+    assert d["events"][W.DI] > 0
