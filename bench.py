@@ -9,14 +9,18 @@ collisions -> deposit -> Poisson -> field -> gather+push -> absorb ->
 inject.  The metric is particle-steps per second including DSMC: the sum
 over the timed steps of the particles pushed, divided by the wall time of
 those steps (HIP events on the library's stream, bracketed by
-synchronisation).
+synchronisation).  The stage breakdown and the roofline's kernel time come
+from the same window replayed from a checkpoint taken at its start (the same
+work, bit for bit), with HIP events around every stage.
 
 Prints one JSON line.  --gpus N > 1 is not supported (one GPU only).
 """
 import argparse
 import json
 import os
+import shutil
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -54,10 +58,6 @@ def parse():
     ap.add_argument("--ensemble", type=int, default=0,
                     help="run the batched ensemble of this many uneven replicas (FP32 records, "
                          "one HIP graph per two steps) instead of the single workload")
-    ap.add_argument("--stage-steps", type=int, default=100,
-                    help="steps after the timed ones run with per-stage HIP events for the stage "
-                         "breakdown and the roofline (the events cost device time, so the timed "
-                         "steps run without them)")
     ap.add_argument("--cpu-steps", type=int, default=-1,
                     help="oracle steps timed for the CPU baseline, after the same warm-up "
                          "steps as the GPU run (-1: as many as the GPU timed, capped at 40; "
@@ -121,6 +121,36 @@ def cpu_baseline(cfg, parts, off, inj, nskip, nsteps):
            "seconds": dt}
     out.update(host_info())
     return out
+
+
+def train_net(a, cfg, cap, parts, precision):
+    """The U-Net of the learned Poisson form, trained on the GPU on (charge,
+    potential) pairs that a run of the same workload dumps (direct solves);
+    none of this is inside the timed region."""
+    import torch
+
+    from paper_2109_00214_amd import pd as P
+    from paper_2109_00214_amd import workload as W
+    from paper_2109_00214_amd.pd import Simulation
+    t1 = time.time()
+    net = P.pd_unet_create(cfg.nr, cfg.nz, 4, 16, 4, a.train_samples)
+    P.pd_unet_set_weights(net, W.unet_init_weights(4, 16, seed=cfg.seed))
+    gen = Simulation(cfg, cap, W.cross_section_tables(), W.species_table(), precision=precision)
+    gen.inject(parts)
+    off_t, inj_t = W.injection_schedule(cfg, a.train_samples)
+    gen.schedule_injection(off_t, inj_t)
+    for _ in range(a.train_samples):
+        gen.step(1)
+        P.pd_unet_add_sample(net, gen.h)
+    gen.close()
+    t2 = time.time()
+    loss = P.pd_unet_train(net, a.train_epochs, 4, 1e-3, seed=cfg.seed)
+    torch.cuda.synchronize()
+    learned = {"train_samples": a.train_samples, "train_epochs": a.train_epochs,
+               "dump_s": round(t2 - t1, 2), "train_s": round(time.time() - t2, 2),
+               "final_loss": loss, "network": "U-Net 4 levels, 16-128 channels, BF16 MFMA"}
+    print("learned: %s" % learned, file=sys.stderr)
+    return net, learned
 
 
 def poisson_forms(cfg, charges, net):
@@ -271,7 +301,7 @@ def main():
 
     kw = {} if a.n_init is None else {"n_init": a.n_init}
     cfg = W.config(a.config, **kw)
-    nsteps = a.warmup + a.steps + max(a.stage_steps, 1) + max(a.form_solves, 0)
+    nsteps = a.warmup + a.steps + max(a.form_solves, 0) + 1
     t0 = time.time()
     parts = W.initial_population(cfg)
     off, inj = W.injection_schedule(cfg, nsteps)
@@ -282,38 +312,23 @@ def main():
     cap = W.run_capacity(cfg, nsteps)
     precision = PD_FP32_MIXED if a.precision == "fp32" else PD_FP64_DET
     net, learned = None, {}
-    if a.poisson == "learned" or a.form_solves > 0:
-        # training pairs from the same workload (direct solves), then Adam on
-        # the GPU; none of this is inside the timed region
-        t1 = time.time()
-        net = P.pd_unet_create(cfg.nr, cfg.nz, 4, 16, 4, a.train_samples)
-        P.pd_unet_set_weights(net, W.unet_init_weights(4, 16, seed=cfg.seed))
-        gen = Simulation(cfg, cap, W.cross_section_tables(), W.species_table(), precision=precision)
-        gen.inject(parts)
-        off_t, inj_t = W.injection_schedule(cfg, a.train_samples)
-        gen.schedule_injection(off_t, inj_t)
-        for _ in range(a.train_samples):
-            gen.step(1)
-            P.pd_unet_add_sample(net, gen.h)
-        gen.close()
-        t2 = time.time()
-        loss = P.pd_unet_train(net, a.train_epochs, 4, 1e-3, seed=cfg.seed)
-        torch.cuda.synchronize()
-        learned = {"train_samples": a.train_samples, "train_epochs": a.train_epochs,
-                   "dump_s": round(t2 - t1, 2), "train_s": round(time.time() - t2, 2),
-                   "final_loss": loss, "network": "U-Net 4 levels, 16-128 channels, BF16 MFMA"}
-        print("learned: %s" % learned, file=sys.stderr)
+    if a.poisson == "learned":
+        net, learned = train_net(a, cfg, cap, parts, precision)
     pmode = {"direct": PD_POISSON_DIRECT64, "spectral": PD_POISSON_SPECTRAL,
              "mgpcg": PD_POISSON_MGPCG, "learned": PD_POISSON_LEARNED}[a.poisson]
     sim = Simulation(cfg, cap, W.cross_section_tables(), W.species_table(), timing=True,
                      stream=stream.cuda_stream, poisson=pmode, precision=precision)
-    if net is not None and a.poisson == "learned":
+    if net is not None:
         P.pd_set_unet(sim.h, net)
     sim.inject(parts)
     sim.schedule_injection(off, inj)
     sim.set_timing(False)
     sim.step(a.warmup)
     sim.synchronize()
+    # the state at the start of the timed window, to replay it with stage events
+    ckpt_dir = tempfile.mkdtemp(prefix="pd_bench_")
+    ckpt = os.path.join(ckpt_dir, "window_start.pd")
+    sim.save(ckpt)
     d0 = sim.diag()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -327,15 +342,23 @@ def main():
     d1 = sim.diag()
     pst = d1["particle_steps"] - d0["particle_steps"]
     value = pst / (ms / 1e3)
-    # stage breakdown: the following steps, each stage bracketed by HIP
-    # events on the library's stream
+    # stage breakdown of the same window: the timed steps replayed from the
+    # checkpoint (bit-identical work), each stage bracketed by HIP events on
+    # the library's stream (the events cost device time, so the timed steps
+    # run without them)
+    sim.load(ckpt)
+    shutil.rmtree(ckpt_dir, ignore_errors=True)
     sim.set_timing(True)
     sim.timing(reset=True)
-    sim.step(max(a.stage_steps, 1))
+    sim.step(a.steps)
     sim.synchronize()
     d2 = sim.diag()
     stages, tsteps = sim.timing()
-    pst_stage = d2["particle_steps"] - d1["particle_steps"]
+    sim.set_timing(False)
+    pst_stage = d2["particle_steps"] - d0["particle_steps"]
+    if pst_stage != pst or d2["n_alive"] != d1["n_alive"]:
+        raise SystemExit("bench.py: the replayed window differs from the timed one "
+                         "(%d vs %d particle-steps)" % (pst_stage, pst))
     # node charges of the next steps, solved afterwards by every Poisson form
     charges = []
     for _ in range(max(a.form_solves, 0)):
@@ -404,6 +427,9 @@ def main():
     ev = out["config"]["collision_events"]
     out["config"]["conflicts_per_event"] = (out["config"]["collision_conflicts"] / ev) if ev else None
     sim.close()
+    if charges and net is None:
+        net, learned = train_net(a, cfg, cap, parts, precision)
+        out["config"]["learned"] = learned
     if charges:
         out["config"]["poisson_forms"] = poisson_forms(cfg, charges, net)
         print("poisson forms: %s" % json.dumps(out["config"]["poisson_forms"]), file=sys.stderr)

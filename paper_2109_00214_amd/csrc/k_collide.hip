@@ -137,7 +137,8 @@ __global__ void __launch_bounds__(256) k_decide(Flow<T> f, const uint32_t* off, 
     const int ci = (int)(cell % (uint32_t)g.nr);
     const uint32_t b_cu = off[C + cell], n_cu = off[C + cell + 1] - b_cu;
     const uint32_t b_c1 = off[2 * C + cell], n_c1 = off[2 * C + cell + 1] - b_c1;
-    const uint32_t id = P.id[pe];
+    const RecT<T> ev = P.v[pe];
+    const uint32_t id = ev.id;
     uint32_t w[4], t[4];
     philox(id, 0u, step, 0u, cp.seed_lo, cp.seed_hi, w);
     philox(id, 0u, step, 1u << 24, cp.seed_lo, cp.seed_hi, t);
@@ -145,14 +146,14 @@ __global__ void __launch_bounds__(256) k_decide(Flow<T> f, const uint32_t* off, 
     const double R2 = u53(w[2], w[3]);
     const uint32_t tc = b_cu + __umulhi(t[0], n_cu);
     const uint32_t t1 = b_c1 + __umulhi(t[1], n_c1);
-    const double evr = P.vr[pe], evt = P.vt[pe], evz = P.vz[pe];
+    const double evr = ev.vr, evt = ev.vt, evz = ev.vz;
     double x[kNC] = {0.0, 0.0, 0.0, 0.0};
     const double Vc = cp.Vcell[ci];
     // Cu target: EL, SI, DI share the pick and the relative speed
     if (n_cu > 0) {
-      const uint32_t q = f.perm[tc];
-      const double dvr = evr - (double)P.vr[q], dvt = evt - (double)P.vt[q],
-                   dvz = evz - (double)P.vz[q];
+      const RecT<T> tv = P.v[f.perm[tc]];
+      const double dvr = evr - (double)tv.vr, dvt = evt - (double)tv.vt,
+                   dvz = evz - (double)tv.vz;
       const double gg = sqrt(((dvr * dvr) + (dvt * dvt)) + (dvz * dvz));
       const double dens = ((double)n_cu * cp.W) / Vc;
 #pragma unroll
@@ -162,9 +163,9 @@ __global__ void __launch_bounds__(256) k_decide(Flow<T> f, const uint32_t* off, 
       }
     }
     if (n_c1 > 0) {
-      const uint32_t q = f.perm[t1];
-      const double dvr = evr - (double)P.vr[q], dvt = evt - (double)P.vt[q],
-                   dvz = evz - (double)P.vz[q];
+      const RecT<T> tv = P.v[f.perm[t1]];
+      const double dvr = evr - (double)tv.vr, dvt = evt - (double)tv.vt,
+                   dvz = evz - (double)tv.vz;
       const double gg = sqrt(((dvr * dvr) + (dvt * dvt)) + (dvz * dvz));
       const double dens = ((double)n_c1 * cp.W) / Vc;
       x[3] = ((cp.dt * gg) * dens) * sigma_of(cp, 3, gg);
@@ -300,27 +301,34 @@ __global__ void __launch_bounds__(256) k_apply(Flow<T> f, const uint32_t* off, D
       const int ch = (int)c - 1;
       const uint32_t tp = target[e];
       const uint32_t pe = f.perm[e], pt = f.perm[tp];
-      const uint32_t id = P.id[pe];
-      double e1[3] = {P.vr[pe], P.vt[pe], P.vz[pe]};
-      double A[3] = {P.vr[pt], P.vt[pt], P.vz[pt]};
+      const RecT<T> ve = P.v[pe];
+      RecT<T> vt = P.v[pt];
+      const uint32_t id = ve.id;
+      double e1[3] = {ve.vr, ve.vt, ve.vz};
+      double A[3] = {vt.vr, vt.vt, vt.vz};
       double nh[3];
       claim[tp] = 0xFFFFFFFFu;
       // stage 1: elastic, or inelastic losing the channel threshold (Eq. 12)
       isotropic(cp, id, step, 2u, nh);
       binary(e1, A, cp.two_dE_mr[ch], cp.f1[ch], cp.f2[ch], nh);
-      P.vr[pt] = (T)A[0];
-      P.vt[pt] = (T)A[1];
-      P.vz[pt] = (T)A[2];
+      vt.vr = (T)A[0];
+      vt.vt = (T)A[1];
+      vt.vz = (T)A[2];
       if (ch == 0) {
-        P.vr[pe] = (T)e1[0];
-        P.vt[pe] = (T)e1[1];
-        P.vz[pe] = (T)e1[2];
+        P.v[pt] = vt;
+        RecT<T> v1 = ve;
+        v1.vr = (T)e1[0];
+        v1.vt = (T)e1[1];
+        v1.vz = (T)e1[2];
+        P.v[pe] = v1;
         continue;
       }
       // stage 2 (Eq. 13): the target keeps its slot and id, changes label;
       // the new electron e2 takes the target's position and velocity
-      const int sp_old = P.sp[pt], sp_new = (ch == 1 ? 2 : (ch == 2 ? 4 : 3));
-      P.sp[pt] = (uint8_t)sp_new;
+      const int sp_old = (int)vt.sp, sp_new = (ch == 1 ? 2 : (ch == 2 ? 4 : 3));
+      vt.sp = (uint32_t)sp_new;
+      P.v[pt] = vt;
+      const PosT<T> xt = P.x[pt];
       if (Q) {
         // the deposit counted the target with its old charge and none of
         // the new electrons: add the target's change with e2 (at the target)
@@ -328,11 +336,12 @@ __global__ void __launch_bounds__(256) k_apply(Flow<T> f, const uint32_t* off, D
         const long long zt = (long long)spp.Z[sp_new] - spp.Z[sp_old] + spp.Z[0];
         long long v[4];
         if (zt) {
-          const int b = cic_fixed<T>(g, P.r[pt], P.z[pt], v);
+          const int b = cic_fixed<T>(g, xt.r, xt.z, v);
           cic_atomic(Q, b, g.nr + 1, zt, v);
         }
         if (ch == 2) {
-          const int b = cic_fixed<T>(g, P.r[pe], P.z[pe], v);
+          const PosT<T> xe = P.x[pe];
+          const int b = cic_fixed<T>(g, xe.r, xe.z, v);
           cic_atomic(Q, b, g.nr + 1, (long long)spp.Z[0], v);
         }
       }
@@ -342,13 +351,8 @@ __global__ void __launch_bounds__(256) k_apply(Flow<T> f, const uint32_t* off, D
       binary(e1, e2, 0.0, 0.5, 0.5, nh);
       const uint32_t slot = n_alive + cbase;
       const uint32_t nid = next_id + cbase;
-      S.r[slot] = P.r[pt];
-      S.z[slot] = P.z[pt];
-      S.vr[slot] = (T)e2[0];
-      S.vt[slot] = (T)e2[1];
-      S.vz[slot] = (T)e2[2];
-      S.sp[slot] = 0;
-      S.id[slot] = nid;
+      S.x[slot] = xt;
+      S.v[slot] = RecT<T>{(T)e2[0], (T)e2[1], (T)e2[2], nid, 0u};
       if (ch == 2) {
         // stage 4 (Eq. 15): e3 splits into the two orthogonal edges of the
         // rectangle whose diagonal is v3
@@ -356,20 +360,18 @@ __global__ void __launch_bounds__(256) k_apply(Flow<T> f, const uint32_t* off, D
         const double d = ((e1[0] * nh[0]) + (e1[1] * nh[1])) + (e1[2] * nh[2]);
         const double v5[3] = {d * nh[0], d * nh[1], d * nh[2]};
         const uint32_t s6 = slot + 1;
-        S.r[s6] = P.r[pe];
-        S.z[s6] = P.z[pe];
-        S.vr[s6] = (T)(e1[0] - v5[0]);
-        S.vt[s6] = (T)(e1[1] - v5[1]);
-        S.vz[s6] = (T)(e1[2] - v5[2]);
-        S.sp[s6] = 0;
-        S.id[s6] = nid + 1;
+        S.x[s6] = P.x[pe];
+        S.v[s6] = RecT<T>{(T)(e1[0] - v5[0]), (T)(e1[1] - v5[1]), (T)(e1[2] - v5[2]), nid + 1,
+                          0u};
         e1[0] = v5[0];
         e1[1] = v5[1];
         e1[2] = v5[2];
       }
-      P.vr[pe] = (T)e1[0];
-      P.vt[pe] = (T)e1[1];
-      P.vz[pe] = (T)e1[2];
+      RecT<T> v1 = ve;
+      v1.vr = (T)e1[0];
+      v1.vt = (T)e1[1];
+      v1.vz = (T)e1[2];
+      P.v[pe] = v1;
     }
   }
 }

@@ -139,13 +139,8 @@ __device__ inline void inject_records(const PartsT<T>& P, const Grid& g, const S
     const uint32_t d = ip.base + q;
     const T r = (T)sc.r[src], z = (T)sc.z[src];
     const uint32_t s = sc.sp[src];
-    P.r[d] = r;
-    P.z[d] = z;
-    P.vr[d] = (T)sc.vr[src];
-    P.vt[d] = (T)sc.vt[src];
-    P.vz[d] = (T)sc.vz[src];
-    P.sp[d] = (uint8_t)s;
-    P.id[d] = ip.id0 + q;
+    P.x[d] = PosT<T>{r, z};
+    P.v[d] = RecT<T>{(T)sc.vr[src], (T)sc.vt[src], (T)sc.vz[src], ip.id0 + q, s};
     int i, j;
     T fr, fz;
     cell_of<T>(g, r, z, i, j, fr, fz);
@@ -221,17 +216,18 @@ __global__ void __launch_bounds__(256) k_push(Flow<T> f, DevState* st, Grid g, S
       const PartsT<T>& P = old ? f.U : f.S;
       int i, j;
       T fr, fz;
-      const T r = P.r[q], z0 = P.z[q];
+      const PosT<T> x0 = P.x[q];
+      const RecT<T> v0 = P.v[q];
+      const T r = x0.r, z0 = x0.z;
       cell_of<T>(g, r, z0, i, j, fr, fz);
       const int b = j * W + i;
       const T gr = (T)1 - fr, gz = (T)1 - fz;
       const T w00 = gr * gz, w10 = fr * gz, w01 = gr * fz, w11 = fr * fz;
       const T er = (((w00 * Er[b]) + (w10 * Er[b + 1])) + (w01 * Er[b + W])) + (w11 * Er[b + W + 1]);
       const T ez = (((w00 * Ez[b]) + (w10 * Ez[b + 1])) + (w01 * Ez[b + W])) + (w11 * Ez[b + W + 1]);
-      const int s = P.sp[q];
-      const uint32_t pid = P.id[q];
+      const int s = (int)v0.sp;
       const bool heavy = s != 0;
-      T vr = P.vr[q], vz = P.vz[q], vt = P.vt[q];
+      T vr = v0.vr, vz = v0.vz, vt = v0.vt;
       T rn = r, z = z0;
       if (!heavy || heavy_now) {
         const bool hs = heavy && sub;
@@ -251,13 +247,8 @@ __global__ void __launch_bounds__(256) k_push(Flow<T> f, DevState* st, Grid g, S
           vt = vt2;
         }
       }
-      D.r[p] = rn;
-      D.z[p] = z;
-      D.vr[p] = vr;
-      D.vt[p] = vt;
-      D.vz[p] = vz;
-      D.sp[p] = (uint8_t)s;
-      D.id[p] = pid;
+      D.x[p] = PosT<T>{rn, z};
+      D.v[p] = RecT<T>{vr, vt, vz, v0.id, v0.sp};
       int bnd = -1;
       if (z < (T)0) bnd = 0;
       else if (!(z < (T)g.L)) bnd = 1;
@@ -295,15 +286,13 @@ __global__ void __launch_bounds__(256) k_append(PartsT<T> P, const DevState* st,
   const uint32_t id0 = st->next_id;
   for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
     const uint32_t d = base + q;
-    const T r = src.r[q], z = src.z[q];
-    const uint32_t s = src.sp[q];
-    P.r[d] = r;
-    P.z[d] = z;
-    P.vr[d] = src.vr[q];
-    P.vt[d] = src.vt[q];
-    P.vz[d] = src.vz[q];
-    P.sp[d] = (uint8_t)s;
-    P.id[d] = id0 + q;
+    const PosT<T> x = src.x[q];
+    RecT<T> v = src.v[q];
+    const T r = x.r, z = x.z;
+    const uint32_t s = v.sp;
+    v.id = id0 + q;
+    P.x[d] = x;
+    P.v[d] = v;
     int i, j;
     T fr, fz;
     cell_of<T>(g, r, z, i, j, fr, fz);
@@ -345,9 +334,10 @@ __global__ void __launch_bounds__(256) k_diag(PartsT<T> P, const DevState* st, G
   __syncthreads();
   for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
     if (P.key[p] == g.sentinel) continue;
-    const int s = P.sp[p];
+    const RecT<T> v = P.v[p];
+    const int s = (int)v.sp;
     atomicAdd(&sc[s], 1ull);
-    const double vr = P.vr[p], vt = P.vt[p], vz = P.vz[p];
+    const double vr = v.vr, vt = v.vt, vz = v.vz;
     const double v2 = ((vr * vr) + (vt * vt)) + (vz * vz);
     acc[s] += (0.5 * spp.m[s]) * v2;
     if (s >= 3) {

@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <mutex>
+#include <type_traits>
 #include <new>
 #include <string>
 #include <vector>
@@ -178,10 +179,22 @@ pd_status dalloc(pd_ctx* c, T** p, size_t n) {
 template <class T>
 pd_status alloc_parts(pd_ctx* c, PartsT<T>& P, int64_t n) {
   pd_status s;
-  if ((s = dalloc(c, &P.r, n)) || (s = dalloc(c, &P.z, n)) || (s = dalloc(c, &P.vr, n)) ||
-      (s = dalloc(c, &P.vt, n)) || (s = dalloc(c, &P.vz, n)) || (s = dalloc(c, &P.sp, n)) ||
-      (s = dalloc(c, &P.id, n)) || (s = dalloc(c, &P.key, n)))
+  if ((s = dalloc(c, &P.x, n)) || (s = dalloc(c, &P.v, n)) || (s = dalloc(c, &P.key, n)))
     return s;
+  return PD_OK;
+}
+
+// the first n records of P on the host, in the device layout
+template <class T>
+pd_status pull_records(pd_ctx* c, const PartsT<T>& P, size_t n, std::vector<PosT<T>>& x,
+                       std::vector<RecT<T>>& v, std::vector<uint32_t>& key) {
+  x.resize(n);
+  v.resize(n);
+  key.resize(n);
+  if (n == 0) return PD_OK;
+  HIPCHK(c, hipMemcpy(x.data(), P.x, sizeof(PosT<T>) * n, hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(v.data(), P.v, sizeof(RecT<T>) * n, hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(key.data(), P.key, 4 * n, hipMemcpyDeviceToHost));
   return PD_OK;
 }
 
@@ -558,14 +571,14 @@ template <class T>
 pd_status stage_append(pd_ctx* c, const PartsT<T>& A, const PartsT<T>& B, int64_t n,
                               const double* r, const double* z, const double* vr,
                               const double* vt, const double* vz, const uint8_t* sp) {
-  const double* h[5] = {r, z, vr, vt, vz};
-  T* d[5] = {B.r, B.z, B.vr, B.vt, B.vz};
-  std::vector<T> buf((size_t)n);
-  for (int k = 0; k < 5; ++k) {
-    for (int64_t p = 0; p < n; ++p) buf[p] = (T)h[k][p];
-    HIPCHK(c, hipMemcpy(d[k], buf.data(), sizeof(T) * n, hipMemcpyHostToDevice));
+  std::vector<PosT<T>> x((size_t)n);
+  std::vector<RecT<T>> v((size_t)n);
+  for (int64_t p = 0; p < n; ++p) {
+    x[p] = PosT<T>{(T)r[p], (T)z[p]};
+    v[p] = RecT<T>{(T)vr[p], (T)vt[p], (T)vz[p], 0u, (uint32_t)sp[p]};  // ids set on the device
   }
-  HIPCHK(c, hipMemcpy(B.sp, sp, n, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(B.x, x.data(), sizeof(PosT<T>) * n, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(B.v, v.data(), sizeof(RecT<T>) * n, hipMemcpyHostToDevice));
   append(A, c->st, c->g, B, (uint32_t)n, c->stream);
   HIPCHK(c, hipGetLastError());
   return PD_OK;
@@ -1079,43 +1092,34 @@ pd_status pd_get_particles(pd_ctx* c, int64_t cap, double* r, double* z, double*
   pd_status s = read_state(c, &h);
   if (s) return s;
   const int64_t n = h.n_total;
-  std::vector<uint32_t> k(n);
-  HIPCHK(c, hipMemcpy(k.data(), c->fp32 ? c->Af.key : c->A.key, 4 * n, hipMemcpyDeviceToHost));
-  int64_t alive = 0;
-  for (int64_t p = 0; p < n; ++p) alive += (k[p] != c->g.sentinel);
-  if (cap < alive) return set_err(c, PD_EINVAL, "cap %lld < %lld particles", (long long)cap,
-                                  (long long)alive);
-  auto pull = [&](auto* dst, const auto* src, size_t esz) -> pd_status {
-    if (!dst) return PD_OK;
-    std::vector<unsigned char> buf(esz * n);
-    HIPCHK(c, hipMemcpy(buf.data(), src, esz * n, hipMemcpyDeviceToHost));
+  auto out = [&](const auto& P) -> pd_status {
+    using T = std::remove_reference_t<decltype(P.x[0].r)>;
+    std::vector<PosT<T>> x;
+    std::vector<RecT<T>> v;
+    std::vector<uint32_t> k;
+    pd_status s = pull_records(c, P, (size_t)n, x, v, k);
+    if (s) return s;
+    int64_t alive = 0;
+    for (int64_t p = 0; p < n; ++p) alive += (k[p] != c->g.sentinel);
+    if (cap < alive)
+      return set_err(c, PD_EINVAL, "cap %lld < %lld particles", (long long)cap, (long long)alive);
+    // FP32 records are widened to double
     int64_t w = 0;
-    for (int64_t p = 0; p < n; ++p)
-      if (k[p] != c->g.sentinel) std::memcpy((unsigned char*)dst + esz * (w++), &buf[esz * p], esz);
+    for (int64_t p = 0; p < n; ++p) {
+      if (k[p] == c->g.sentinel) continue;
+      if (r) r[w] = (double)x[p].r;
+      if (z) z[w] = (double)x[p].z;
+      if (vr) vr[w] = (double)v[p].vr;
+      if (vt) vt[w] = (double)v[p].vt;
+      if (vz) vz[w] = (double)v[p].vz;
+      if (sp) sp[w] = (uint8_t)v[p].sp;
+      if (id) id[w] = v[p].id;
+      if (key) key[w] = k[p];
+      ++w;
+    }
     return PD_OK;
   };
-  // FP32 records are widened to double on the host
-  auto pullf = [&](double* dst, const float* src) -> pd_status {
-    if (!dst) return PD_OK;
-    std::vector<float> buf(n);
-    HIPCHK(c, hipMemcpy(buf.data(), src, 4 * n, hipMemcpyDeviceToHost));
-    int64_t w = 0;
-    for (int64_t p = 0; p < n; ++p)
-      if (k[p] != c->g.sentinel) dst[w++] = (double)buf[p];
-    return PD_OK;
-  };
-  if (c->fp32) {
-    if ((s = pullf(r, c->Af.r)) || (s = pullf(z, c->Af.z)) || (s = pullf(vr, c->Af.vr)) ||
-        (s = pullf(vt, c->Af.vt)) || (s = pullf(vz, c->Af.vz)) || (s = pull(sp, c->Af.sp, 1)) ||
-        (s = pull(id, c->Af.id, 4)) || (s = pull(key, c->Af.key, 4)))
-      return s;
-    return PD_OK;
-  }
-  if ((s = pull(r, c->A.r, 8)) || (s = pull(z, c->A.z, 8)) || (s = pull(vr, c->A.vr, 8)) ||
-      (s = pull(vt, c->A.vt, 8)) || (s = pull(vz, c->A.vz, 8)) || (s = pull(sp, c->A.sp, 1)) ||
-      (s = pull(id, c->A.id, 4)) || (s = pull(key, c->A.key, 4)))
-    return s;
-  return PD_OK;
+  return c->fp32 ? out(c->Af) : out(c->A);
 }
 
 pd_status pd_get_field(pd_ctx* c, double* phi, double* Er, double* Ez, int64_t* Q) {
@@ -1170,7 +1174,7 @@ pd_status pd_poisson(pd_ctx* c, const int64_t* Q, double* phi, int32_t* iters, d
 // with its read position; the host-side counters; the solver's scalars; the
 // magic again.
 static const char kSaveMagic[8] = {'P', 'D', 'S', 'T', 'A', 'T', 'E', '1'};
-constexpr uint32_t kSaveVersion = 1;
+constexpr uint32_t kSaveVersion = 2;
 
 struct SaveHead {
   char magic[8];
@@ -1231,24 +1235,19 @@ pd_status pd_save(pd_ctx* c, const char* path) {
     if (set && (s = putd(c->d_xs[k], 8 * (size_t)n))) return s;
   }
   put(&st, sizeof st);
-  const size_t n = st.n_total, esz = c->fp32 ? 4 : 8;
+  const size_t n = st.n_total;
   const size_t nn = (size_t)(c->g.nr + 1) * (c->g.nz + 1);
-  void* rec[5];
-  uint8_t* sp;
-  uint32_t *id, *key;
+  // the records in the device layout (position pairs, then the rest), keys
   if (c->fp32) {
-    float* a[5] = {c->Af.r, c->Af.z, c->Af.vr, c->Af.vt, c->Af.vz};
-    for (int k = 0; k < 5; ++k) rec[k] = a[k];
-    sp = c->Af.sp; id = c->Af.id; key = c->Af.key;
+    if ((s = putd(c->Af.x, sizeof(PosT<float>) * n)) ||
+        (s = putd(c->Af.v, sizeof(RecT<float>) * n)) || (s = putd(c->Af.key, 4 * n)))
+      return s;
   } else {
-    double* a[5] = {c->A.r, c->A.z, c->A.vr, c->A.vt, c->A.vz};
-    for (int k = 0; k < 5; ++k) rec[k] = a[k];
-    sp = c->A.sp; id = c->A.id; key = c->A.key;
+    if ((s = putd(c->A.x, sizeof(PosT<double>) * n)) ||
+        (s = putd(c->A.v, sizeof(RecT<double>) * n)) || (s = putd(c->A.key, 4 * n)))
+      return s;
   }
-  for (int k = 0; k < 5; ++k)
-    if ((s = putd(rec[k], esz * n))) return s;
-  if ((s = putd(sp, n)) || (s = putd(id, 4 * n)) || (s = putd(key, 4 * n)) ||
-      (s = putd(c->sw.skey, 4 * (size_t)st.n_alive)) ||
+  if ((s = putd(c->sw.skey, 4 * (size_t)st.n_alive)) ||
       (s = putd(c->off, 4 * ((size_t)c->g.sentinel + 1))) || (s = putd(c->fw.Q, 8 * nn)) ||
       (s = putd(c->fw.phi, 8 * nn)) || (s = putd(c->fw.Er, 8 * nn)) ||
       (s = putd(c->fw.Ez, 8 * nn)))
@@ -1355,12 +1354,13 @@ pd_status pd_load(pd_ctx* c, const char* path) {
   if ((int64_t)st.n_total > c->cap || st.n_alive > st.n_total || st.err != 0)
     return set_err(c, PD_EINVAL, "%s: %u particles do not fit the capacity %lld", path,
                    st.n_total, (long long)c->cap);
-  const size_t n = st.n_total, esz = c->fp32 ? 4 : 8;
+  const size_t n = st.n_total;
   const size_t nn = (size_t)(c->g.nr + 1) * (c->g.nz + 1);
-  const unsigned char* rec[5];
-  for (int k = 0; k < 5; ++k) rec[k] = span(esz * n);
-  const unsigned char* sp = span(n);
-  const unsigned char* id = span(4 * n);
+  const size_t xsz = c->fp32 ? sizeof(PosT<float>) : sizeof(PosT<double>);
+  const size_t vsz = c->fp32 ? sizeof(RecT<float>) : sizeof(RecT<double>);
+  const size_t sp_at = c->fp32 ? offsetof(RecT<float>, sp) : offsetof(RecT<double>, sp);
+  const unsigned char* xrec = span(xsz * n);
+  const unsigned char* vrec = span(vsz * n);
   const unsigned char* key = span(4 * n);
   const unsigned char* skey = span(4 * (size_t)st.n_alive);
   const unsigned char* off = span(4 * ((size_t)c->g.sentinel + 1));
@@ -1395,8 +1395,11 @@ pd_status pd_load(pd_ctx* c, const char* path) {
   if (hh.sched_n != sn || hh.host_sched_pos < 0 || hh.host_sched_pos > sn ||
       st.sched_n != (uint32_t)sn || st.sched_pos > (uint32_t)sn)
     return set_err(c, PD_EINVAL, "%s: inconsistent injection schedule", path);
-  for (size_t p = 0; p < n; ++p)
-    if (sp[p] >= kNS) return set_err(c, PD_EINVAL, "%s: species out of range", path);
+  for (size_t p = 0; p < n; ++p) {
+    uint32_t sp;
+    std::memcpy(&sp, vrec + vsz * p + sp_at, 4);
+    if (sp >= kNS) return set_err(c, PD_EINVAL, "%s: species out of range", path);
+  }
   for (int64_t p = 0; p < (sn > 0 ? soff[sn] : 0); ++p)
     if (sarr[5][p] >= kNS) return set_err(c, PD_EINVAL, "%s: schedule species out of range", path);
   // apply: tables, then the device state
@@ -1419,25 +1422,14 @@ pd_status pd_load(pd_ctx* c, const char* path) {
     return s;
   }
   if ((s = sync(c))) return s;
-  void* drec[5];
-  uint8_t* dsp;
-  uint32_t *did, *dkey;
-  if (c->fp32) {
-    float* a[5] = {c->Af.r, c->Af.z, c->Af.vr, c->Af.vt, c->Af.vz};
-    for (int k = 0; k < 5; ++k) drec[k] = a[k];
-    dsp = c->Af.sp; did = c->Af.id; dkey = c->Af.key;
-  } else {
-    double* a[5] = {c->A.r, c->A.z, c->A.vr, c->A.vt, c->A.vz};
-    for (int k = 0; k < 5; ++k) drec[k] = a[k];
-    dsp = c->A.sp; did = c->A.id; dkey = c->A.key;
-  }
+  void* dx = c->fp32 ? (void*)c->Af.x : (void*)c->A.x;
+  void* dv = c->fp32 ? (void*)c->Af.v : (void*)c->A.v;
+  uint32_t* dkey = c->fp32 ? c->Af.key : c->A.key;
   auto up = [&](void* dst, const void* src, size_t bytes) -> pd_status {
     if (bytes) HIPCHK(c, hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
     return PD_OK;
   };
-  for (int k = 0; k < 5; ++k)
-    if ((s = up(drec[k], rec[k], esz * n))) return s;
-  if ((s = up(dsp, sp, n)) || (s = up(did, id, 4 * n)) || (s = up(dkey, key, 4 * n)) ||
+  if ((s = up(dx, xrec, xsz * n)) || (s = up(dv, vrec, vsz * n)) || (s = up(dkey, key, 4 * n)) ||
       (s = up(c->sw.skey, skey, 4 * (size_t)st.n_alive)) ||
       (s = up(c->off, off, 4 * ((size_t)c->g.sentinel + 1))) || (s = up(c->fw.Q, Q, 8 * nn)) ||
       (s = up(c->fw.phi, phi, 8 * nn)) || (s = up(c->fw.Er, Er, 8 * nn)) ||

@@ -34,13 +34,30 @@ struct DevState {
   unsigned long long absorbed[3 * kNS];
 };
 
-// Structure-of-arrays particle store; T = double in the FP64 deterministic
-// form, float in the FP32 precision form.
+// Particle store in three arrays; T = double in the FP64 deterministic form,
+// float in the FP32 precision form.  The record of a particle is split in
+// two: its position pair (what the deposit and the cell index need) and the
+// rest (velocity, id, label: what the collisions and the push also need), so
+// that a particle read out of order (a mover, a collision target) costs two
+// memory transactions, not one per field; the sort key lives apart (the sort
+// reads nothing else).
+template <typename T>
+struct alignas(2 * sizeof(T)) PosT {
+  T r, z;
+};
+template <typename T>
+struct alignas(sizeof(T) == 8 ? 16 : 8) RecT {
+  T vr, vt, vz;
+  uint32_t id;
+  uint32_t sp;  // species / label
+};
+static_assert(sizeof(PosT<double>) == 16 && sizeof(RecT<double>) == 32, "FP64 record layout");
+static_assert(sizeof(PosT<float>) == 8 && sizeof(RecT<float>) == 24, "FP32 record layout");
 template <typename T>
 struct PartsT {
-  T *r, *z, *vr, *vt, *vz;
-  uint8_t* sp;
-  uint32_t *id, *key;
+  PosT<T>* x;
+  RecT<T>* v;
+  uint32_t* key;
 };
 using Parts = PartsT<double>;
 using PartsF = PartsT<float>;
@@ -173,8 +190,8 @@ __device__ inline void deposit_blocks(const Flow<T>& f, const uint32_t* __restri
           p = lo[s] + (q - cum[s]);
           Zp = spp.Z[s];
         }
-      const uint32_t u = f.perm[p];
-      b = cic_fixed<T>(g, f.U.r[u], f.U.z[u], v);
+      const PosT<T> x = f.U.x[f.perm[p]];
+      b = cic_fixed<T>(g, x.r, x.z, v);
 #pragma unroll
       for (int k = 0; k < 4; ++k) v[k] *= Zp;
     }

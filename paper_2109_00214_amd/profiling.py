@@ -2,6 +2,17 @@
 
     python -m paper_2109_00214_amd.profiling stats DIR CMD...
         kernel-trace stats (rocprofv3 --kernel-trace --stats) -> text table
+    python -m paper_2109_00214_amd.profiling window DIR FIRST LAST CMD...
+        the same table from the kernel trace of DIR over the steps FIRST .. LAST-1
+        of the run: the launches from the first sort launch after the end of push
+        launch FIRST-1 to the end of push launch LAST-1 (a step ends with its push)
+    python -m paper_2109_00214_amd.profiling deposit STEPS
+        the paper workload with collisions off, so that the deposit has a launch
+        of its own: 5 warm-up steps, then STEPS steps; prints a JSON line whose
+        config.mean_particles_per_step is the charged particles deposited per step
+    python -m paper_2109_00214_amd.profiling unet REPS
+        the learned solver's U-Net (4 levels, 16-128 channels) on the 256 x 512
+        grid: REPS inferences of one image, for its matrix-core counters
     python -m paper_2109_00214_amd.profiling copy BYTES
         a plain device copy of BYTES bytes, three times (the counter calibration run)
     python -m paper_2109_00214_amd.profiling traffic FETCH_DIR WRITE_DIR CAL_FETCH_DIR
@@ -27,6 +38,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # stage -> (kernel name, sources that define it)
 STAGE_KERNELS = {
     "push": ("pd::k_push<double>", ("csrc/k_pic.hip", "csrc/pd_internal.h")),
+    "deposit": ("pd::k_deposit<double>", ("csrc/k_pic.hip", "csrc/pd_internal.h")),
 }
 
 
@@ -85,6 +97,83 @@ def kernel_stats_text(d, cmd):
             _kname(r["Name"])[:56], r["Calls"], float(r["AverageNs"]) / 1e3,
             float(r["TotalDurationNs"]) / 1e6, float(r["Percentage"])))
     return "\n".join(out)
+
+
+def window_stats_text(d, first, last, cmd):
+    rows = list(csv.DictReader(open(_csv(d, "kernel_trace.csv"))))
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    push_end = [int(r["End_Timestamp"]) for r in rows if _kname(r["Kernel_Name"]).startswith(
+        "pd::k_push")]
+    if len(push_end) < last:
+        raise SystemExit("only %d push launches in the trace" % len(push_end))
+    # the window opens with the first sort launch after push launch first-1
+    # (host-initiated copies and snapshot launches before it are not steps)
+    after = push_end[first - 1] if first > 0 else -1
+    lo = min(int(r["Start_Timestamp"]) for r in rows if int(r["Start_Timestamp"]) > after and
+             _kname(r["Kernel_Name"]).startswith("pd::k_cls_count"))
+    hi = push_end[last - 1]
+    agg = defaultdict(list)
+    for r in rows:
+        if lo <= int(r["Start_Timestamp"]) <= hi:
+            agg[_kname(r["Kernel_Name"])].append(
+                int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    busy = sum(sum(v) for v in agg.values())
+    nst = last - first
+    out = ["# rocprofv3 --kernel-trace, steps %d-%d of the run (%d steps)" % (first, last - 1, nst),
+           "# command: " + cmd,
+           "# from the start of step %d's sort to the end of step %d's push: wall %.1f us per "
+           "step, kernels busy %.1f us per step" % (first, last - 1, (hi - lo) / 1e3 / nst,
+                                                     busy / 1e3 / nst),
+           "%-56s %7s %10s %12s %6s" % ("kernel", "calls", "avg_us", "us_per_step", "pct")]
+    for k, v in sorted(agg.items(), key=lambda kv: -sum(kv[1])):
+        out.append("%-56s %7d %10.2f %12.2f %6.2f" % (
+            k[:56], len(v), sum(v) / len(v) / 1e3, sum(v) / 1e3 / nst, 100.0 * sum(v) / busy))
+    return "\n".join(out)
+
+
+def deposit_run(steps):
+    import json
+
+    import torch
+
+    from . import workload as W
+    from .pd import Simulation
+    cfg = W.config("paper")
+    nsteps = 5 + steps
+    parts = W.initial_population(cfg)
+    off, inj = W.injection_schedule(cfg, nsteps)
+    sim = Simulation(cfg, W.run_capacity(cfg, nsteps), W.cross_section_tables(),
+                     W.species_table(), collisions_off=True)
+    sim.inject(parts)
+    sim.schedule_injection(off, inj)
+    sim.step(5)
+    Z = W.species_table()[0]
+    charged = 0
+    for _ in range(steps):
+        # charged particles at this step's sort (the deposit's units)
+        c = sim.diag()["count"]
+        charged += sum(int(c[s]) for s in range(len(Z)) if Z[s] != 0)
+        sim.step(1)
+    sim.synchronize()
+    torch.cuda.synchronize()
+    sim.close()
+    print(json.dumps({"config": {"workload": "paper, collisions off", "steps": steps,
+                                 "mean_particles_per_step": charged / steps}}))
+
+
+def unet_run(reps):
+    import numpy as np
+
+    from . import pd as P
+    from . import workload as W
+    net = P.pd_unet_create(256, 512, 4, 16, 1, 0)
+    P.pd_unet_set_weights(net, W.unet_init_weights(4, 16, seed=1))
+    _, H, Wd = P.pd_unet_info(net)
+    x = np.random.default_rng(1).standard_normal((1, 2, H, Wd)).astype(np.float32)
+    for _ in range(reps):
+        P.pd_unet_forward(net, x)
+    P.pd_unet_destroy(net)
+    print("unet: %d inferences" % reps)
 
 
 def _per_kernel(d, skip=0):
@@ -146,6 +235,12 @@ def copy_run(nbytes):
 def main(argv):
     if argv and argv[0] == "stats":
         print(kernel_stats_text(argv[1], " ".join(argv[2:])))
+    elif argv and argv[0] == "window":
+        print(window_stats_text(argv[1], int(argv[2]), int(argv[3]), " ".join(argv[4:])))
+    elif argv and argv[0] == "deposit":
+        deposit_run(int(argv[1]))
+    elif argv and argv[0] == "unet":
+        unet_run(int(argv[1]))
     elif argv and argv[0] == "copy":
         copy_run(int(argv[1]))
     elif argv and argv[0] == "traffic":

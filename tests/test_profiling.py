@@ -23,8 +23,12 @@ def test_stale_digest_is_ignored(tmp_path):
     assert PR.read_traffic(str(p)) == {}
 
 
-def test_committed_summary_has_stage_lines():
-    path = os.path.join(ROOT, "profiles", "hbm_traffic_paper_256x512.txt")
-    stages = [l.split() for l in open(path) if l.startswith("stage ")]
-    assert set(PR.STAGE_KERNELS) <= {w[1] for w in stages}
-    assert all(len(w) == 10 for w in stages)
+def test_committed_summaries_have_stage_lines():
+    """The benchmark's summary carries the push line, the deposit run's
+    summary the deposit line."""
+    for name, stage in (("hbm_traffic_paper_256x512.txt", "push"),
+                        ("hbm_traffic_deposit_paper_256x512.txt", "deposit")):
+        path = os.path.join(ROOT, "profiles", name)
+        stages = [l.split() for l in open(path) if l.startswith("stage ")]
+        assert stage in {w[1] for w in stages}, name
+        assert all(len(w) == 10 and w[1] in PR.STAGE_KERNELS for w in stages), name
