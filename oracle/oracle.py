@@ -13,8 +13,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "pd_oracle.c")
 _LIB = os.path.join(_HERE, "libpd_oracle.so")
 
-NSPECIES = 6
-NCHANNELS = 4
+NSPECIES = 8
+NKEYS = 6
+NCHANNELS = 6
 
 
 def build_oracle(force=True):
@@ -29,11 +30,11 @@ def build_oracle(force=True):
 
 class _Diag(C.Structure):
     _fields_ = [("step", C.c_int64), ("n_alive", C.c_int64), ("next_id", C.c_int64),
-                ("count", C.c_int64 * 6), ("events", C.c_int64 * 4),
+                ("count", C.c_int64 * NSPECIES), ("events", C.c_int64 * NCHANNELS),
                 ("conflicts", C.c_int64), ("created", C.c_int64),
-                ("absorbed", (C.c_int64 * 6) * 3), ("injected", C.c_int64 * 6),
+                ("absorbed", (C.c_int64 * NSPECIES) * 3), ("injected", C.c_int64 * NSPECIES),
                 ("charge_alive", C.c_int64), ("charge_absorbed", C.c_int64),
-                ("charge_injected", C.c_int64), ("ke_J", C.c_double * 6),
+                ("charge_injected", C.c_int64), ("ke_J", C.c_double * NSPECIES),
                 ("gamma", C.c_double), ("qbar", C.c_double),
                 ("spectrum", (C.c_int64 * 66) * 3)]
 
@@ -205,7 +206,7 @@ class Oracle:
         self.lib.or_set_potential(self.h, _p(f))
 
     def offsets(self):
-        o = np.zeros(6 * self.nr * self.nz + 1, np.int64)
+        o = np.zeros(NKEYS * self.nr * self.nz + 1, np.int64)
         self.lib.or_get_offsets(self.h, _p(o))
         return o
 

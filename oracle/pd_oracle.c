@@ -85,7 +85,7 @@ struct or_sim {
   /* grids: node-major, r fastest, (nz+1) rows of (nr+1) */
   int64_t* Q;
   double *phi, *Er, *Ez;
-  int64_t* off; /* CSR offsets [6*ncell+1] */
+  int64_t* off; /* CSR offsets [OR_NKEYS*ncell+1] */
 
   /* injection schedule */
   int sched_n, sched_pos;
@@ -238,9 +238,15 @@ void or_destroy(or_sim* s) {
   free(s);
 }
 
+/* the species each channel's target is drawn from (any Cu2+ tag for SI3:
+ * all tags have the Cu2+ mass) and the label the target takes             */
+static const int TARGET_OF[OR_NCHANNELS] = {OR_CU, OR_CU, OR_CU, OR_CU1, OR_CU2_STEP, OR_CU3};
+static const int PRODUCT_OF[OR_NCHANNELS] = {OR_CU, OR_CU1, OR_CU2_DOUBLE, OR_CU2_STEP,
+                                             OR_CU3, OR_CU4};
+
 static void derive_pairs(or_sim* s) {
-  /* projectile = electron, target = Cu (EL, SI, DI) or Cu+ (SI2) */
-  const int tgt[OR_NCHANNELS] = {OR_CU, OR_CU, OR_CU, OR_CU1};
+  /* projectile = electron, target = TARGET_OF[channel] */
+  const int* tgt = TARGET_OF;
   for (int k = 0; k < OR_NCHANNELS; ++k) {
     double m1 = s->m[OR_E], m2 = s->m[tgt[k]];
     s->mr[k] = (m1 * m2) / (m1 + m2);
@@ -252,7 +258,10 @@ static void derive_pairs(or_sim* s) {
 }
 
 int or_set_species(or_sim* s, int n, const int* Z, const double* mass) {
-  if (n != OR_NSPECIES) return fail("or_set_species: need 6 species");
+  if (n != OR_NSPECIES) return fail("or_set_species: need 8 species");
+  if (Z[OR_CU2_DOUBLE] != Z[OR_CU2_STEP] || Z[OR_CU2_INIT] != Z[OR_CU2_STEP] ||
+      mass[OR_CU2_DOUBLE] != mass[OR_CU2_STEP] || mass[OR_CU2_INIT] != mass[OR_CU2_STEP])
+    return fail("or_set_species: the Cu2+ tags must share one charge and mass");
   for (int k = 0; k < n; ++k)
     if (!(mass[k] > 0) || !isfinite(mass[k])) return fail("or_set_species: bad mass");
   for (int k = 0; k < n; ++k) { s->Z[k] = Z[k]; s->m[k] = mass[k]; }
@@ -310,11 +319,14 @@ static void cell_of(const or_sim* s, double r, double z, int* ci, int* cj,
   *fz = xz - (double)j;
 }
 
-/* sort key: species-major, then cell = j*nr + i */
+/* sort key: key class of the species (the three Cu2+ tags share one),
+ * then cell = j*nr + i                                                 */
+static const int KEY_CLASS[OR_NSPECIES] = {0, 1, 2, 3, 3, 3, 4, 5};
+
 static uint32_t key_of(const or_sim* s, double r, double z, int sp) {
   int i, j; double fr, fz;
   cell_of(s, r, z, &i, &j, &fr, &fz);
-  return (uint32_t)((int64_t)sp * s->ncell + (int64_t)j * s->nr + i);
+  return (uint32_t)((int64_t)KEY_CLASS[sp] * s->ncell + (int64_t)j * s->nr + i);
 }
 
 static int check_particles(const or_sim* s, int64_t n, const double* r,
@@ -415,8 +427,8 @@ void or_stage_sort(or_sim* s) {
   memcpy(s->sp, t8, n);
   free(tmp);
   free(kv);
-  /* CSR offsets over the flattened (species, cell) key space */
-  int64_t nk = 6 * s->ncell;
+  /* CSR offsets over the flattened (key class, cell) key space */
+  int64_t nk = OR_NKEYS * s->ncell;
   memset(s->off, 0, sizeof(int64_t) * (nk + 1));
   for (int64_t p = 0; p < n; ++p) s->off[s->key[p] + 1] += 1;
   for (int64_t k = 0; k < nk; ++k) s->off[k + 1] += s->off[k];
@@ -500,34 +512,40 @@ void or_stage_collide(or_sim* s) {
   const int64_t C = s->ncell;
   const int64_t n_e = s->off[C]; /* electrons occupy [0, off[C]) */
 
-  /* decide: reads the pre-collision state only (Eq. 4) */
+  /* decide: reads the pre-collision state only (Eq. 4).  Each electron
+   * draws one target of each target class in its cell (Cu, Cu+, Cu2+ of any
+   * tag, Cu3+): the channels of one target class share the draw and the
+   * relative speed.  SI3 and SI4 take part only when their tables are set. */
+  const int cls_of[OR_NCHANNELS] = {1, 1, 1, 2, 3, 4}; /* key class of the target */
   for (int64_t p = 0; p < n_e; ++p) {
-    int64_t cell = s->key[p]; /* species 0 */
+    int64_t cell = s->key[p]; /* key class 0 */
     int ci = (int)(cell % s->nr);
-    int64_t b_cu = s->off[1 * C + cell], n_cu = s->off[1 * C + cell + 1] - b_cu;
-    int64_t b_c1 = s->off[2 * C + cell], n_c1 = s->off[2 * C + cell + 1] - b_c1;
+    int64_t b[5], nt[5], tp[5];
     uint32_t w[4], t[4];
     draw4(s, s->id[p], 0, 0, w);
     draw4(s, s->id[p], 1, 0, t);
     double R1 = u53(w[0], w[1]);
     double R2 = u53(w[2], w[3]);
-    int64_t tc = b_cu + (int64_t)(((uint64_t)t[0] * (uint64_t)n_cu) >> 32);
-    int64_t t1 = b_c1 + (int64_t)(((uint64_t)t[1] * (uint64_t)n_c1) >> 32);
-    double x[OR_NCHANNELS] = {0.0, 0.0, 0.0, 0.0};
+    for (int c = 1; c <= 4; ++c) {
+      b[c] = s->off[c * C + cell];
+      nt[c] = s->off[c * C + cell + 1] - b[c];
+      /* uniform pick: floor(u32 * n / 2^32), word c-1 of the second draw */
+      tp[c] = b[c] + (int64_t)(((uint64_t)t[c - 1] * (uint64_t)nt[c]) >> 32);
+    }
+    double x[OR_NCHANNELS] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int k = 0; k < OR_NCHANNELS; ++k) {
-      int64_t nt = (k == OR_SI2) ? n_c1 : n_cu;
-      int64_t tp = (k == OR_SI2) ? t1 : tc;
-      if (nt == 0) continue;
+      int c = cls_of[k];
+      if (nt[c] == 0 || !s->xs_set[k]) continue;
       if (k == OR_DI && !s->enable_di) continue;
-      double dvr = s->vr[p] - s->vr[tp];
-      double dvt = s->vt[p] - s->vt[tp];
-      double dvz = s->vz[p] - s->vz[tp];
+      double dvr = s->vr[p] - s->vr[tp[c]];
+      double dvt = s->vt[p] - s->vt[tp[c]];
+      double dvz = s->vz[p] - s->vz[tp[c]];
       double g = sqrt(((dvr * dvr) + (dvt * dvt)) + (dvz * dvz));
       double sig = sigma_of(s, k, g);
-      double dens = ((double)nt * s->W) / s->Vcell[ci];
+      double dens = ((double)nt[c] * s->W) / s->Vcell[ci];
       x[k] = ((s->dt * g) * dens) * sig;
     }
-    double X = ((x[0] + x[1]) + x[2]) + x[3];
+    double X = ((((x[0] + x[1]) + x[2]) + x[3]) + x[4]) + x[5];
     double pc = 1.0 - exp(-X);
     if (!(R1 < pc)) continue;
     double u = R2 * X, c = 0.0;
@@ -540,7 +558,7 @@ void or_stage_collide(or_sim* s) {
       for (int k = OR_NCHANNELS - 1; k >= 0; --k)
         if (x[k] > 0.0) { ch = k; break; }
     s->choice[p] = (uint8_t)(ch + 1);
-    s->target[p] = (uint32_t)((ch == OR_SI2) ? t1 : tc);
+    s->target[p] = (uint32_t)tp[cls_of[ch]];
   }
 
   /* claim: a target takes part in at most one event; the electron with
@@ -579,7 +597,7 @@ void or_stage_collide(or_sim* s) {
     }
     /* stage 2: the excited target emits e2, which inherits its position
      * and post-stage-1 velocity; the target keeps its slot and id        */
-    s->sp[tp] = (uint8_t)(ch == OR_SI ? OR_CU1 : (ch == OR_DI ? OR_CU2_DOUBLE : OR_CU2_STEP));
+    s->sp[tp] = (uint8_t)PRODUCT_OF[ch];
     double e2[3] = {A[0], A[1], A[2]};
     /* stage 3: e1-e2 elastic, equal masses (m_r/m = 1/2), isotropic    */
     or_isotropic(s, s->id[p], 3, nh);
@@ -853,7 +871,7 @@ void or_stage_end(or_sim* s) { s->step += 1; }
 int or_step(or_sim* s, int nsteps) {
   if (!s->species_set) return fail("or_step: species not set");
   if (!s->collisions_off)
-    for (int k = 0; k < OR_NCHANNELS; ++k)
+    for (int k = 0; k <= OR_SI2; ++k)
       if (!s->xs_set[k]) return fail("or_step: cross section missing");
   for (int t = 0; t < nsteps; ++t) {
     if (s->next_id + 2 * s->n > (int64_t)UINT32_MAX) return fail("or_step: id overflow");
@@ -897,7 +915,7 @@ void or_get_field(const or_sim* s, double* phi, double* Er, double* Ez, int64_t*
 }
 
 void or_get_offsets(const or_sim* s, int64_t* offsets) {
-  memcpy(offsets, s->off, sizeof(int64_t) * (6 * s->ncell + 1));
+  memcpy(offsets, s->off, sizeof(int64_t) * (OR_NKEYS * s->ncell + 1));
 }
 
 void or_get_collisions(const or_sim* s, uint8_t* choice, uint32_t* target, uint8_t* winner) {
@@ -928,7 +946,7 @@ void or_get_diag(const or_sim* s, or_diag* d) {
     d->charge_alive += s->Z[sp];
     double v2 = ((s->vr[p] * s->vr[p]) + (s->vt[p] * s->vt[p])) + (s->vz[p] * s->vz[p]);
     d->ke_J[sp] += (0.5 * s->m[sp]) * v2;
-    if (sp >= OR_CU2_STEP) {
+    if (sp >= OR_CU2_STEP && sp <= OR_CU2_INIT) {
       double ke = ((0.5 * s->m[sp]) * v2) / Q_E;
       int bin;
       if (ke < s->edges[0]) bin = 64;
@@ -937,11 +955,16 @@ void or_get_diag(const or_sim* s, or_diag* d) {
       d->spectrum[sp - OR_CU2_STEP][bin] += 1;
     }
   }
-  /* Eq. 21 over charge states 0..2 */
-  double N0 = (double)d->count[OR_CU], N1 = (double)d->count[OR_CU1];
-  double N2 = (double)(d->count[OR_CU2_STEP] + d->count[OR_CU2_DOUBLE] + d->count[OR_CU2_INIT]);
-  d->gamma = (N0 + N1 + N2) > 0 ? (N1 + N2) / ((N0 + N1) + N2) : 0.0;
-  d->qbar = (N1 + N2) > 0 ? (N1 + (2.0 * N2)) / (N1 + N2) : 0.0;
+  /* Eq. 21 over the charge states q = 0..4 (N_2 counts every Cu2+ tag):
+   * gamma = sum_{q>=1} N_q / sum_q N_q, qbar = sum_q q N_q / sum_{q>=1} N_q;
+   * the counts are summed as integers, each ratio is one division        */
+  int64_t N[5] = {d->count[OR_CU], d->count[OR_CU1],
+                  d->count[OR_CU2_STEP] + d->count[OR_CU2_DOUBLE] + d->count[OR_CU2_INIT],
+                  d->count[OR_CU3], d->count[OR_CU4]};
+  int64_t ions = N[1] + N[2] + N[3] + N[4];
+  int64_t qsum = N[1] + 2 * N[2] + 3 * N[3] + 4 * N[4];
+  d->gamma = (ions + N[0]) > 0 ? (double)ions / (double)(ions + N[0]) : 0.0;
+  d->qbar = ions > 0 ? (double)qsum / (double)ions : 0.0;
 }
 
 /* ------------------------------------------------------------------ */

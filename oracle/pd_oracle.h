@@ -22,11 +22,18 @@
 extern "C" {
 #endif
 
-/* species enum (fixed order); the three Cu2+ tags are separate species */
+/* species enum (fixed order); the three Cu2+ tags are separate species; the
+ * step-wise chain goes on to Cu3+ and Cu4+ (Sec. 2.3) */
 enum { OR_E = 0, OR_CU = 1, OR_CU1 = 2, OR_CU2_STEP = 3, OR_CU2_DOUBLE = 4,
-       OR_CU2_INIT = 5, OR_NSPECIES = 6 };
-/* collision channels in cumulative-sum order */
-enum { OR_EL = 0, OR_SI = 1, OR_DI = 2, OR_SI2 = 3, OR_NCHANNELS = 4 };
+       OR_CU2_INIT = 5, OR_CU3 = 6, OR_CU4 = 7, OR_NSPECIES = 8 };
+/* classes of the sort key: e, Cu, Cu+, Cu2+ (the three tags together), Cu3+,
+ * Cu4+ */
+enum { OR_NKEYS = 6 };
+/* collision channels in cumulative-sum order: elastic, Cu -> Cu+, Cu -> Cu2+
+ * (double), Cu+ -> Cu2+, Cu2+ -> Cu3+, Cu3+ -> Cu4+; the last two take part
+ * only when their cross sections are set */
+enum { OR_EL = 0, OR_SI = 1, OR_DI = 2, OR_SI2 = 3, OR_SI3 = 4, OR_SI4 = 5,
+       OR_NCHANNELS = 6 };
 /* absorbing boundaries */
 enum { OR_CATHODE = 0, OR_ANODE = 1, OR_OUTER = 2 };
 
@@ -42,7 +49,7 @@ typedef struct {
   int64_t injected[OR_NSPECIES];    /* cumulative, incl. initial population */
   int64_t charge_alive, charge_absorbed, charge_injected; /* sum of Z */
   double ke_J[OR_NSPECIES];
-  double gamma, qbar;
+  double gamma, qbar; /* Eq. 21 over the charge states 0..4 */
   int64_t spectrum[3][66]; /* Cu2+ tags STEP, DOUBLE, INIT: 64 bins, <1 eV, >=1000 eV */
 } or_diag;
 
@@ -88,7 +95,7 @@ void or_get_field(const or_sim* s, double* phi, double* Er, double* Ez,
 void or_set_charge(or_sim* s, const int64_t* Q);
 /* set the node potential directly (tests of the field and gather stages) */
 void or_set_potential(or_sim* s, const double* phi);
-void or_get_offsets(const or_sim* s, int64_t* offsets); /* 6*nr*nz + 2 */
+void or_get_offsets(const or_sim* s, int64_t* offsets); /* OR_NKEYS*nr*nz + 1 */
 /* per-electron decisions of the last collide stage, in sorted order */
 void or_get_collisions(const or_sim* s, uint8_t* choice, uint32_t* target,
                        uint8_t* winner);

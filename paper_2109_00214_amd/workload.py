@@ -34,19 +34,25 @@ KB = 1.380649e-23
 EPS0 = 8.8541878128e-12
 M_CU = 63.546 * AMU
 
-# species enum: E, CU, CU1, CU2_STEP, CU2_DOUBLE, CU2_INIT
-E, CU, CU1, CU2_STEP, CU2_DOUBLE, CU2_INIT = range(6)
-SPECIES_NAMES = ("e", "Cu", "Cu+", "Cu2+(step)", "Cu2+(double)", "Cu2+(init)")
-# channels in cumulative order
-EL, SI, DI, SI2 = range(4)
-CHANNEL_NAMES = ("elastic", "Cu->Cu+", "Cu->Cu2+ (double)", "Cu+->Cu2+")
-THRESHOLDS_EV = (0.0, 7.73, 28.0, 20.29)
+# species enum: E, CU, CU1, CU2_STEP, CU2_DOUBLE, CU2_INIT, CU3, CU4
+E, CU, CU1, CU2_STEP, CU2_DOUBLE, CU2_INIT, CU3, CU4 = range(8)
+NSPECIES = 8
+SPECIES_NAMES = ("e", "Cu", "Cu+", "Cu2+(step)", "Cu2+(double)", "Cu2+(init)", "Cu3+", "Cu4+")
+# channels in cumulative order; SI3 and SI4 (the step-wise chain on to Cu4+)
+# take part only when their tables are given
+EL, SI, DI, SI2, SI3, SI4 = range(6)
+NCHANNELS = 6
+CHANNEL_NAMES = ("elastic", "Cu->Cu+", "Cu->Cu2+ (double)", "Cu+->Cu2+", "Cu2+->Cu3+",
+                 "Cu3+->Cu4+")
+# ionization energies (eV) of Cu, Cu+, Cu2+, Cu3+ and the paper's double-
+# ionization threshold
+THRESHOLDS_EV = (0.0, 7.73, 28.0, 20.29, 36.84, 57.38)
 
 
 def species_table():
     """Charge numbers and masses, enum order (every Cu state has M_Cu)."""
-    Z = np.array([-1, 0, 1, 2, 2, 2], dtype=np.int32)
-    m = np.array([ME, M_CU, M_CU, M_CU, M_CU, M_CU], dtype=np.float64)
+    Z = np.array([-1, 0, 1, 2, 2, 2, 3, 4], dtype=np.int32)
+    m = np.array([ME] + [M_CU] * 7, dtype=np.float64)
     return Z, m
 
 
@@ -58,8 +64,9 @@ def lotz(E, P, q, a_cm2=4.5e-14):
     return np.where(E >= P, s, 0.0) * 1e-4
 
 
-def cross_section_tables(dsqrtE=2.0 ** -4, n=1025):
-    """(channel, threshold_eV, dsqrtE, sigma[n]) for EL, SI, DI, SI2.
+def cross_section_tables(dsqrtE=2.0 ** -4, n=1025, chain=False):
+    """(channel, threshold_eV, dsqrtE, sigma[n]) for EL, SI, DI, SI2, and with
+    chain=True also SI3 and SI4 (Lotz forms with 9 and 8 d electrons).
 
     Tables are uniform in sqrt(E/eV) with spacing dsqrtE (a power of 2).
     """
@@ -69,13 +76,18 @@ def cross_section_tables(dsqrtE=2.0 ** -4, n=1025):
     si = lotz(En, 7.73, 1.0)
     di = lotz(En, 28.0, 1.0)
     si2 = lotz(En, 20.29, 10.0)
-    return [(EL, 0.0, dsqrtE, el), (SI, 7.73, dsqrtE, si), (DI, 28.0, dsqrtE, di),
-            (SI2, 20.29, dsqrtE, si2)]
+    out = [(EL, 0.0, dsqrtE, el), (SI, 7.73, dsqrtE, si), (DI, 28.0, dsqrtE, di),
+           (SI2, 20.29, dsqrtE, si2)]
+    if chain:
+        out += [(SI3, 36.84, dsqrtE, lotz(En, 36.84, 9.0)), (SI4, 57.38, dsqrtE, lotz(En, 57.38, 8.0))]
+    return out
 
 
-def constant_tables(sig, dsqrtE=2.0 ** -4, n=64, thresholds=(0.0, 0.0, 0.0, 0.0)):
-    """Constant-sigma tables (rate tests); sig = 4 values, one per channel."""
-    return [(k, float(thresholds[k]), dsqrtE, np.full(n, float(sig[k]))) for k in range(4)]
+def constant_tables(sig, dsqrtE=2.0 ** -4, n=64, thresholds=None):
+    """Constant-sigma tables (rate tests); sig = one value per channel given
+    (4: the paper's four channels, 6: with the chain to Cu4+)."""
+    thresholds = thresholds or (0.0,) * len(sig)
+    return [(k, float(thresholds[k]), dsqrtE, np.full(n, float(sig[k]))) for k in range(len(sig))]
 
 
 @dataclass(frozen=True)

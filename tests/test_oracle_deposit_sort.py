@@ -9,7 +9,8 @@ from paper_2109_00214_amd import workload as W
 
 def _random_parts(cfg, n, seed, species=None):
     rng = np.random.default_rng(seed)
-    sp = rng.integers(0, 6, n).astype(np.uint8) if species is None else np.full(n, species, np.uint8)
+    sp = (rng.integers(0, W.NSPECIES, n).astype(np.uint8) if species is None
+          else np.full(n, species, np.uint8))
     return {"r": cfg.R * np.sqrt(rng.random(n)) * 0.999999, "z": cfg.L * rng.random(n),
             "vr": rng.normal(size=n), "vt": rng.normal(size=n), "vz": rng.normal(size=n), "sp": sp}
 
@@ -25,7 +26,9 @@ def test_sort_is_stable_by_key():
     dr, dz = cfg.R / cfg.nr, cfg.L / cfg.nz
     i = np.minimum((before["r"] / dr).astype(int), cfg.nr - 1)
     j = np.minimum((before["z"] / dz).astype(int), cfg.nz - 1)
-    key = before["sp"].astype(np.int64) * cfg.nr * cfg.nz + j * cfg.nr + i
+    # key class: e, Cu, Cu+, Cu2+ (the three tags together), Cu3+, Cu4+
+    kclass = np.array([0, 1, 2, 3, 3, 3, 4, 5])[before["sp"]]
+    key = kclass * cfg.nr * cfg.nz + j * cfg.nr + i
     assert np.array_equal(key, before["key"])
     order = np.argsort(key, kind="stable")
     o.stage("sort")
@@ -33,7 +36,7 @@ def test_sort_is_stable_by_key():
     assert np.array_equal(after["id"], before["id"][order])
     assert np.array_equal(after["key"], key[order])
     off = o.offsets()
-    nk = 6 * cfg.nr * cfg.nz
+    nk = 6 * cfg.nr * cfg.nz  # six key classes
     assert np.array_equal(off, np.searchsorted(key[order], np.arange(nk + 1), side="left"))
 
 

@@ -79,7 +79,8 @@ def test_split_steps_equal_one_call():
 def test_eq21_and_spectrum_on_built_population():
     cfg = W.config("tiny")
     o = make_oracle(cfg)
-    counts = {W.CU: 30, W.CU1: 12, W.CU2_STEP: 5, W.CU2_DOUBLE: 2, W.CU2_INIT: 1, W.E: 7}
+    counts = {W.CU: 30, W.CU1: 12, W.CU2_STEP: 5, W.CU2_DOUBLE: 2, W.CU2_INIT: 1, W.CU3: 4,
+              W.CU4: 3, W.E: 7}
     sp = np.concatenate([np.full(c, s, np.uint8) for s, c in counts.items()])
     n = sp.size
     # Cu2+ energies chosen in the middle of known log bins (1..1000 eV, 64 bins)
@@ -90,14 +91,15 @@ def test_eq21_and_spectrum_on_built_population():
     o.inject({"r": np.full(n, 0.5e-6), "z": np.full(n, 1e-6), "vr": np.zeros(n),
               "vt": np.zeros(n), "vz": v, "sp": sp})
     d = o.diag()
-    N0, N1, N2 = 30, 12, 8
-    assert d["gamma"] == pytest.approx((N1 + N2) / (N0 + N1 + N2), rel=1e-15)
-    assert d["qbar"] == pytest.approx((N1 + 2 * N2) / (N1 + N2), rel=1e-15)
+    # Eq. 21 over q = 0..4 with N = (30, 12, 8, 4, 3): 27 ions of 57 heavy
+    # particles, charge 12 + 16 + 12 + 12 = 52 over the 27 ions
+    assert d["gamma"] == 27 / 57
+    assert d["qbar"] == 52 / 27
     for t, s in enumerate((W.CU2_STEP, W.CU2_DOUBLE, W.CU2_INIT)):
         ref = np.bincount(bins[sp == s], minlength=66)
         assert np.array_equal(d["spectrum"][t], ref)
     ke_J = 0.5 * m * v * v
-    for s in range(6):
+    for s in range(W.NSPECIES):
         assert d["ke_J"][s] == pytest.approx(ke_J[sp == s].sum(), rel=1e-12)
 
 
@@ -118,7 +120,7 @@ def test_injection_validation(bad):
     elif bad == "z_big":
         p["z"][0] = cfg.L
     else:
-        p["sp"][0] = 6
+        p["sp"][0] = W.NSPECIES
     with pytest.raises(ValueError):
         o.inject(p)
     assert o.count() == 0
