@@ -9,7 +9,9 @@
  *   - DSMC electron-impact collisions (Sec. 2.1, Eqs. 4-7): elastic,
  *     Cu -> Cu+, Cu+ -> Cu2+ and the paper's direct Cu -> Cu2+ double
  *     ionization done as four binary stages (Sec. 2.2, Eqs. 11-15); Cu2+
- *     super-particles carry the label of the channel that made them,
+ *     super-particles carry the label of the channel that made them; the
+ *     step-wise chain goes on to Cu3+ and Cu4+ (Sec. 2.3) when those two
+ *     channels' cross sections are set,
  *   - cloud-in-cell charge deposit (Eqs. 9-10) in int64 fixed point,
  *   - the cylindrical Poisson equation (Eq. 8) and E = -grad(phi),
  *   - field gather and leapfrog push in 2D3V (Sec. 2.1, Newton's law),
@@ -57,11 +59,18 @@ typedef enum {
   PD_ECAPACITY = -6   /* particle capacity or 32-bit id space exhausted */
 } pd_status;
 
-/* species (fixed order); the three Cu2+ labels are separate species */
+/* species (fixed order); the three Cu2+ labels are separate species (they
+ * must share one charge number and one mass); particles are sorted by the
+ * key classes e, Cu, Cu+, Cu2+ (the three labels together), Cu3+, Cu4+ and
+ * then by cell */
 enum { PD_E = 0, PD_CU = 1, PD_CU1 = 2, PD_CU2_STEP = 3, PD_CU2_DOUBLE = 4,
-       PD_CU2_INIT = 5, PD_NSPECIES = 6 };
-/* collision channels, in the order their probabilities are summed */
-enum { PD_EL = 0, PD_SI = 1, PD_DI = 2, PD_SI2 = 3, PD_NCHANNELS = 4 };
+       PD_CU2_INIT = 5, PD_CU3 = 6, PD_CU4 = 7, PD_NSPECIES = 8 };
+/* collision channels, in the order their probabilities are summed:
+ * elastic, Cu -> Cu+, Cu -> Cu2+ (double), Cu+ -> Cu2+ (these four must be
+ * set before stepping), Cu2+ of any label -> Cu3+, Cu3+ -> Cu4+ (these two
+ * take part only when set) */
+enum { PD_EL = 0, PD_SI = 1, PD_DI = 2, PD_SI2 = 3, PD_SI3 = 4, PD_SI4 = 5,
+       PD_NCHANNELS = 6 };
 /* absorbing boundaries */
 enum { PD_CATHODE = 0, PD_ANODE = 1, PD_OUTER = 2 };
 /* precision forms: FP64 deterministic (with PD_POISSON_DIRECT64 every result
@@ -128,7 +137,7 @@ typedef struct {
   int64_t injected[PD_NSPECIES]; /* cumulative, initial population included */
   int64_t charge_alive, charge_absorbed, charge_injected; /* sums of Z, exact */
   double ke_J[PD_NSPECIES];      /* kinetic energy per species at v(n+1/2) */
-  double gamma, qbar;            /* Eq. 21 over charge states 0..2 */
+  double gamma, qbar;            /* Eq. 21 over charge states 0..4 */
   int64_t particle_steps;        /* sum over steps of the particles pushed */
   double poisson_rel_res;        /* relative residual of the current phi (FP64) */
   int64_t poisson_solves;        /* cumulative Poisson solves */
@@ -172,7 +181,7 @@ pd_status pd_set_heavy_subcycle(pd_ctx* ctx, int32_t every);
 /* Append n particles now: positions r, z (0 <= r < R, 0 <= z < L),
  * velocities vr, vt, vz at the half step before their first push
  * (leapfrog), species sp[n].  They receive ids next_id, next_id+1, ...
- * Errors: PD_EINVAL (non-finite, outside the domain, species >= 6) and
+ * Errors: PD_EINVAL (non-finite, outside the domain, species >= 8) and
  * PD_ECAPACITY; the context is unchanged on error.                   */
 pd_status pd_inject(pd_ctx* ctx, int64_t n, const double* r, const double* z,
                     const double* vr, const double* vt, const double* vz,

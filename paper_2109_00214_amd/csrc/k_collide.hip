@@ -5,7 +5,8 @@
 //   decide  -- one lane per electron (electrons occupy sorted positions
 //              [0, off[C]) because keys are species-major): counter-based
 //              Philox draws keyed by particle id, one uniform Cu and one
-//              Cu+ target in the electron's cell, relative speed, sigma
+//              Cu+ target in the electron's cell (with the step-wise chain
+//              on, also one Cu2+ of any label and one Cu3+), relative speed, sigma
 //              from the sqrt(E) tables, x_k = dt g n_t sigma_k, the test
 //              R1 < 1 - exp(-X) and the channel; successful trials claim
 //              their target with atomicMin of the sorted position;
@@ -147,7 +148,7 @@ __global__ void __launch_bounds__(256) k_decide(Flow<T> f, const uint32_t* off, 
     const uint32_t tc = b_cu + __umulhi(t[0], n_cu);
     const uint32_t t1 = b_c1 + __umulhi(t[1], n_c1);
     const double evr = ev.vr, evt = ev.vt, evz = ev.vz;
-    double x[kNC] = {0.0, 0.0, 0.0, 0.0};
+    double x[kNC] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     const double Vc = cp.Vcell[ci];
     // Cu target: EL, SI, DI share the pick and the relative speed
     if (n_cu > 0) {
@@ -170,7 +171,28 @@ __global__ void __launch_bounds__(256) k_decide(Flow<T> f, const uint32_t* off, 
       const double dens = ((double)n_c1 * cp.W) / Vc;
       x[3] = ((cp.dt * gg) * dens) * sigma_of(cp, 3, gg);
     }
-    const double X = ((x[0] + x[1]) + x[2]) + x[3];
+    // the step-wise chain on: a Cu2+ target of any label (the labels share
+    // one key class) and a Cu3+ target, words 2 and 3 of the same draw
+    uint32_t t2 = 0, t3 = 0;
+    if (cp.chain) {
+#pragma unroll
+      for (int c = 3; c <= 4; ++c) {
+        const int k = c + 1;  // SI3 on class 3, SI4 on class 4
+        const uint32_t bt = off[(uint32_t)c * C + cell], nt = off[(uint32_t)c * C + cell + 1] - bt;
+        const uint32_t tp = bt + __umulhi(t[c - 1], nt);
+        if (c == 3) t2 = tp;
+        else t3 = tp;
+        if (nt > 0 && cp.tabn[k] > 0) {
+          const RecT<T> tv = P.v[f.perm[tp]];
+          const double dvr = evr - (double)tv.vr, dvt = evt - (double)tv.vt,
+                       dvz = evz - (double)tv.vz;
+          const double gg = sqrt(((dvr * dvr) + (dvt * dvt)) + (dvz * dvz));
+          const double dens = ((double)nt * cp.W) / Vc;
+          x[k] = ((cp.dt * gg) * dens) * sigma_of(cp, k, gg);
+        }
+      }
+    }
+    const double X = ((((x[0] + x[1]) + x[2]) + x[3]) + x[4]) + x[5];
     const double pc = 1.0 - exp(-X);
     int ch = -1;
     if (R1 < pc) {
@@ -190,7 +212,7 @@ __global__ void __launch_bounds__(256) k_decide(Flow<T> f, const uint32_t* off, 
       }
     }
     if (ch >= 0) {
-      const uint32_t tp = (ch == 3) ? t1 : tc;
+      const uint32_t tp = (ch == 3) ? t1 : (ch == 4) ? t2 : (ch == 5) ? t3 : tc;
       choice[e] = (uint8_t)(ch + 1);
       target[e] = tp;
       atomicMin(&claim[tp], e);
@@ -325,7 +347,7 @@ __global__ void __launch_bounds__(256) k_apply(Flow<T> f, const uint32_t* off, D
       }
       // stage 2 (Eq. 13): the target keeps its slot and id, changes label;
       // the new electron e2 takes the target's position and velocity
-      const int sp_old = (int)vt.sp, sp_new = (ch == 1 ? 2 : (ch == 2 ? 4 : 3));
+      const int sp_old = (int)vt.sp, sp_new = (int)product_of(ch, vt.sp);
       vt.sp = (uint32_t)sp_new;
       P.v[pt] = vt;
       const PosT<T> xt = P.x[pt];

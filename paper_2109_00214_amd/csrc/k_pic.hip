@@ -144,7 +144,7 @@ __device__ inline void inject_records(const PartsT<T>& P, const Grid& g, const S
     int i, j;
     T fr, fz;
     cell_of<T>(g, r, z, i, j, fr, fz);
-    P.key[d] = s * g.C + (uint32_t)(j * g.nr + i);
+    P.key[d] = key_class(s) * g.C + (uint32_t)(j * g.nr + i);
   }
 }
 
@@ -260,7 +260,7 @@ __global__ void __launch_bounds__(256) k_push(Flow<T> f, DevState* st, Grid g, S
         int i2, j2;
         T a, c;
         cell_of<T>(g, rn, z, i2, j2, a, c);
-        D.key[p] = (uint32_t)s * g.C + (uint32_t)(j2 * g.nr + i2);
+        D.key[p] = key_class((uint32_t)s) * g.C + (uint32_t)(j2 * g.nr + i2);
       }
     }
     count_codes(code, st->absorbed);
@@ -296,7 +296,7 @@ __global__ void __launch_bounds__(256) k_append(PartsT<T> P, const DevState* st,
     int i, j;
     T fr, fz;
     cell_of<T>(g, r, z, i, j, fr, fz);
-    P.key[d] = s * g.C + (uint32_t)(j * g.nr + i);
+    P.key[d] = key_class(s) * g.C + (uint32_t)(j * g.nr + i);
   }
 }
 __global__ void k_append_end(DevState* st, uint32_t n) {
@@ -330,7 +330,7 @@ __global__ void __launch_bounds__(256) k_diag(PartsT<T> P, const DevState* st, G
   __shared__ double sk[256][kNS];
   const uint32_t n = st->n_total;
   if (threadIdx.x < kNS) sc[threadIdx.x] = 0;
-  double acc[kNS] = {0, 0, 0, 0, 0, 0};
+  double acc[kNS] = {0, 0, 0, 0, 0, 0, 0, 0};
   __syncthreads();
   for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
     if (P.key[p] == g.sentinel) continue;
@@ -340,7 +340,7 @@ __global__ void __launch_bounds__(256) k_diag(PartsT<T> P, const DevState* st, G
     const double vr = v.vr, vt = v.vt, vz = v.vz;
     const double v2 = ((vr * vr) + (vt * vt)) + (vz * vz);
     acc[s] += (0.5 * spp.m[s]) * v2;
-    if (s >= 3) {
+    if (s >= 3 && s <= 5) {  // the Cu2+ labels
       const double e = ((0.5 * spp.m[s]) * v2) / kQE;
       int bin;
       if (e < edges[0]) bin = 64;

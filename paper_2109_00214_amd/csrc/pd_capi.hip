@@ -35,8 +35,8 @@ struct pd_ctx {
   SpeciesParams spp{};
   CollideParams cpar{};
   bool species_set = false;
-  bool xs_set[kNC] = {false, false, false, false};
-  double xs_thr[kNC] = {0, 0, 0, 0};
+  bool xs_set[kNC] = {};
+  double xs_thr[kNC] = {};
   double qunit = 0;
   int key_bits = 0;
   int64_t cap = 0;
@@ -51,7 +51,7 @@ struct pd_ctx {
   FieldWork fw{};
   DevState* st = nullptr;
   uint32_t* off = nullptr;
-  double* d_xs[kNC] = {nullptr, nullptr, nullptr, nullptr};
+  double* d_xs[kNC] = {};
   double* d_edges = nullptr;
   unsigned long long* d_dcount = nullptr;
   double* d_dke = nullptr;
@@ -65,7 +65,7 @@ struct pd_ctx {
 
   // host-side bookkeeping
   int64_t host_step = 0;
-  int64_t injected[kNS] = {0, 0, 0, 0, 0, 0};
+  int64_t injected[kNS] = {};
 
   // Poisson: FP64 residual operator (every solver) and the multigrid-CG work
   MGWork mg{};
@@ -495,8 +495,9 @@ pd_status solve_poisson(pd_ctx* c) {
 }
 
 void derive_pairs(pd_ctx* c) {
-  // projectile: electron; target: Cu (EL, SI, DI) or Cu+ (SI2)
-  const int tgt[kNC] = {PD_CU, PD_CU, PD_CU, PD_CU1};
+  // projectile: electron; target: Cu (EL, SI, DI), Cu+ (SI2), Cu2+ of any
+  // label (SI3: the labels share the Cu2+ mass) or Cu3+ (SI4)
+  const int tgt[kNC] = {PD_CU, PD_CU, PD_CU, PD_CU1, PD_CU2_STEP, PD_CU3};
   for (int k = 0; k < kNC; ++k) {
     const double m1 = c->spp.m[PD_E], m2 = c->spp.m[tgt[k]];
     const double mr = (m1 * m2) / (m1 + m2);
@@ -644,7 +645,7 @@ pd_status pd_create(const pd_domain* dom, const pd_opts* opts, pd_ctx** out) {
   };
   if (dom->nr < 2 || dom->nz < 2 || dom->nz > 8192 ||
       (opts->poisson != PD_POISSON_SPECTRAL && !direct_fits(dom->nr, dom->nz)) ||
-      (int64_t)dom->nr * dom->nz * 6 >= (1LL << 31) || !(dom->R > 0) || !(dom->L > 0) ||
+      (int64_t)dom->nr * dom->nz * kNK >= (1LL << 31) || !(dom->R > 0) || !(dom->L > 0) ||
       !(dom->dt > 0) || !(dom->weight > 0) || !std::isfinite(dom->V_cathode) ||
       !std::isfinite(dom->R) || !std::isfinite(dom->L) || dom->capacity < 1 ||
       dom->capacity > (int64_t)kScanChunk * kScanMaxBlocks)
@@ -673,7 +674,7 @@ pd_status pd_create(const pd_domain* dom, const pd_opts* opts, pd_ctx** out) {
   c->g.nr = nr;
   c->g.nz = nz;
   c->g.C = (uint32_t)(nr * nz);
-  c->g.sentinel = 6u * c->g.C;
+  c->g.sentinel = (uint32_t)kNK * c->g.C;
   c->g.dr = dom->R / (double)nr;
   c->g.dz = dom->L / (double)nz;
   c->g.R = dom->R;
@@ -689,8 +690,9 @@ pd_status pd_create(const pd_domain* dom, const pd_opts* opts, pd_ctx** out) {
     while ((1u << b) <= c->g.sentinel) ++b;
     c->key_bits = b;
   }
-  const int Zd[kNS] = {-1, 0, 1, 2, 2, 2};
+  const int Zd[kNS] = {-1, 0, 1, 2, 2, 2, 3, 4};
   for (int k = 0; k < kNS; ++k) c->spp.Z[k] = Zd[k];
+  for (int k = 0; k < kNS; ++k) c->spp.Zk[key_class((uint32_t)k)] = Zd[k];
   c->cpar.W = dom->weight;
   c->cpar.dt = dom->dt;
   c->cpar.seed_lo = (uint32_t)dom->seed;
@@ -802,8 +804,13 @@ pd_status pd_set_species(pd_ctx* c, int n, const int32_t* Z, const double* mass)
   for (int k = 0; k < n; ++k)
     if (!(mass[k] > 0) || !std::isfinite(mass[k]) || Z[k] < -8 || Z[k] > 8)
       return set_err(c, PD_EINVAL, "species %d: bad charge or mass", k);
+  // the Cu2+ labels share a key class (one charge) and the SI3 pair (one mass)
+  for (int k = PD_CU2_DOUBLE; k <= PD_CU2_INIT; ++k)
+    if (Z[k] != Z[PD_CU2_STEP] || mass[k] != mass[PD_CU2_STEP])
+      return set_err(c, PD_EINVAL, "the Cu2+ labels must share one charge and mass");
   for (int k = 0; k < n; ++k) {
     c->spp.Z[k] = Z[k];
+    c->spp.Zk[key_class((uint32_t)k)] = Z[k];
     c->spp.m[k] = mass[k];
     c->spp.qmdt[k] = (((double)Z[k] * kQE) / mass[k]) * c->dom.dt;
     c->spp.qmdt_heavy[k] = (((double)Z[k] * kQE) / mass[k]) * c->g.dt_heavy;
@@ -834,6 +841,7 @@ pd_status pd_set_cross_section(pd_ctx* c, int ch, double thr, int n, double dsq,
   c->cpar.dsq[ch] = dsq;
   c->xs_thr[ch] = thr;
   c->xs_set[ch] = true;
+  c->cpar.chain = (c->xs_set[PD_SI3] || c->xs_set[PD_SI4]) ? 1 : 0;
   if (c->species_set) derive_pairs(c);
   return PD_OK;
 }
@@ -936,7 +944,7 @@ pd_status pd_step(pd_ctx* c, int nsteps) {
   if (nsteps < 0) return set_err(c, PD_EINVAL, "nsteps < 0");
   if (!c->species_set) return set_err(c, PD_ESTATE, "species not set");
   if (!c->opts.collisions_off)
-    for (int k = 0; k < kNC; ++k)
+    for (int k = 0; k <= PD_SI2; ++k)
       if (!c->xs_set[k]) return set_err(c, PD_ESTATE, "cross section %d not set", k);
   hipStream_t s = c->stream;
   const int64_t nn = (int64_t)(c->g.nr + 1) * (c->g.nz + 1);
@@ -1052,10 +1060,15 @@ pd_status pd_get_diagnostics(pd_ctx* c, pd_diag* out) {
   out->poisson_refinements = c->h_sc->outer;
   out->poisson_fallbacks = c->p_fallbacks;
   out->poisson_seconds = c->p_call_ms * 1e-3;
-  const double N0 = (double)counts[PD_CU], N1 = (double)counts[PD_CU1];
-  const double N2 = (double)(counts[PD_CU2_STEP] + counts[PD_CU2_DOUBLE] + counts[PD_CU2_INIT]);
-  out->gamma = (N0 + N1 + N2) > 0 ? (N1 + N2) / ((N0 + N1) + N2) : 0.0;
-  out->qbar = (N1 + N2) > 0 ? (N1 + (2.0 * N2)) / (N1 + N2) : 0.0;
+  // Eq. 21 over the charge states 0..4 (N_2: every Cu2+ label), integer
+  // sums, one division each
+  const int64_t N[5] = {counts[PD_CU], counts[PD_CU1],
+                        counts[PD_CU2_STEP] + counts[PD_CU2_DOUBLE] + counts[PD_CU2_INIT],
+                        counts[PD_CU3], counts[PD_CU4]};
+  const int64_t ions = N[1] + N[2] + N[3] + N[4];
+  const int64_t qsum = N[1] + 2 * N[2] + 3 * N[3] + 4 * N[4];
+  out->gamma = (ions + N[0]) > 0 ? (double)ions / (double)(ions + N[0]) : 0.0;
+  out->qbar = ions > 0 ? (double)qsum / (double)ions : 0.0;
   return PD_OK;
 }
 
@@ -1494,7 +1507,7 @@ pd_status pd_ensemble_create(int32_t n, pd_ctx* const* members, int32_t nstreams
       return PD_EINVAL;
     }
     if (!c->opts.collisions_off)
-      for (int k = 0; k < kNC; ++k)
+      for (int k = 0; k <= PD_SI2; ++k)
         if (!c->xs_set[k]) {
           g_ens_err = "member " + std::to_string(i) + ": cross section not set";
           return PD_ESTATE;

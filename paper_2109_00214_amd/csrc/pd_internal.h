@@ -11,8 +11,19 @@ namespace pd {
 constexpr double kQE = 1.602176634e-19;    // elementary charge, C (CODATA 2018)
 constexpr double kEPS0 = 8.8541878128e-12; // vacuum permittivity, F/m
 constexpr double kPI = 3.14159265358979323846;
-constexpr int kNS = 6;                     // species
-constexpr int kNC = 4;                     // collision channels
+constexpr int kNS = 8;                     // species (the three Cu2+ labels apart)
+constexpr int kNK = 6;                     // sort-key classes (the Cu2+ labels together)
+constexpr int kNC = 6;                     // collision channels
+
+// sort-key class of a species: e, Cu, Cu+, Cu2+ (every label), Cu3+, Cu4+
+__host__ __device__ inline uint32_t key_class(uint32_t s) {
+  return s < 4u ? s : (s < 6u ? 3u : s - 2u);
+}
+// the label a channel's target takes: Cu+, Cu2+ (double), Cu2+ (step-wise),
+// Cu3+, Cu4+ (elastic: unchanged)
+__host__ __device__ inline uint32_t product_of(int ch, uint32_t sp) {
+  return ch == 1 ? 2u : ch == 2 ? 4u : ch == 3 ? 3u : ch == 4 ? 6u : ch == 5 ? 7u : sp;
+}
 
 // Device-resident counters: every launch reads the particle counts from
 // here, so a step needs no host round trip and can be replayed as a graph.
@@ -79,7 +90,7 @@ struct Flow {
 struct Grid {
   int nr, nz;
   uint32_t C;         // cells nr*nz
-  uint32_t sentinel;  // key of an absorbed particle (= 6*C)
+  uint32_t sentinel;  // key of an absorbed particle (= kNK*C)
   double dr, dz, R, L, V, dt;
   int heavy_every;    // heavy species advance every heavy_every steps (1: every step)
   double dt_heavy;    // their step, heavy_every * dt
@@ -87,6 +98,7 @@ struct Grid {
 
 struct SpeciesParams {
   int Z[kNS];
+  int Zk[kNK];        // charge number of each key class
   double qmdt[kNS];   // ((Z e) / m) dt
   double m[kNS];
   double qmdt_heavy[kNS];  // ((Z e) / m) dt_heavy
@@ -102,7 +114,8 @@ struct CollideParams {
   double f1[kNC], f2[kNC];
   double two_dE_mr[kNC]; // 2 (-E_th e) / m_r
   const double* tab[kNC];
-  int tabn[kNC];
+  int tabn[kNC];         // 0: the channel takes no part (its table is not set)
+  int chain;             // the Cu2+ -> Cu3+ or Cu3+ -> Cu4+ channel takes part
   const double* Vcell;   // cell volumes [nr]
 };
 
@@ -163,17 +176,17 @@ template <typename T>
 __device__ inline void deposit_blocks(const Flow<T>& f, const uint32_t* __restrict__ off,
                                       const Grid& g, const SpeciesParams& spp,
                                       unsigned long long* Q, uint32_t blk, uint32_t nblk) {
-  // the charged species' ranges laid end to end: cum[s] charged particles
-  // before species s, its range starting at lo[s]
-  uint32_t lo[kNS], cum[kNS + 1];
+  // the charged key classes' ranges laid end to end: cum[s] charged
+  // particles before class s, its range starting at lo[s]
+  uint32_t lo[kNK], cum[kNK + 1];
   cum[0] = 0;
 #pragma unroll
-  for (int s = 0; s < kNS; ++s) {
+  for (int s = 0; s < kNK; ++s) {
     lo[s] = off[(uint32_t)s * g.C];
     const uint32_t hi = off[(uint32_t)(s + 1) * g.C];
-    cum[s + 1] = cum[s] + ((spp.Z[s] != 0) ? hi - lo[s] : 0u);
+    cum[s + 1] = cum[s] + ((spp.Zk[s] != 0) ? hi - lo[s] : 0u);
   }
-  const uint32_t n = cum[kNS];
+  const uint32_t n = cum[kNK];
   const int W = g.nr + 1;
   const int lane = threadIdx.x & 63;
   const uint64_t upto = (lane == 63) ? 0ull : (~0ull << (lane + 1));  // lanes above this one
@@ -185,10 +198,10 @@ __device__ inline void deposit_blocks(const Flow<T>& f, const uint32_t* __restri
       uint32_t p = 0;
       long long Zp = 0;
 #pragma unroll
-      for (int s = 0; s < kNS; ++s)
+      for (int s = 0; s < kNK; ++s)
         if (q >= cum[s] && q < cum[s + 1]) {
           p = lo[s] + (q - cum[s]);
-          Zp = spp.Z[s];
+          Zp = spp.Zk[s];
         }
       const PosT<T> x = f.U.x[f.perm[p]];
       b = cic_fixed<T>(g, x.r, x.z, v);

@@ -50,13 +50,17 @@ class pd_opts(C.Structure):
                 ("stream", C.c_void_p), ("poisson_rtol", C.c_double)]
 
 
+PD_NSPECIES, PD_NCHANNELS = 8, 6
+
+
 class pd_diag(C.Structure):
     _fields_ = [("step", C.c_int64), ("n_alive", C.c_int64), ("next_id", C.c_int64),
-                ("count", C.c_int64 * 6), ("events", C.c_int64 * 4), ("conflicts", C.c_int64),
-                ("created", C.c_int64), ("absorbed", (C.c_int64 * 6) * 3),
-                ("injected", C.c_int64 * 6), ("charge_alive", C.c_int64),
+                ("count", C.c_int64 * PD_NSPECIES), ("events", C.c_int64 * PD_NCHANNELS),
+                ("conflicts", C.c_int64),
+                ("created", C.c_int64), ("absorbed", (C.c_int64 * PD_NSPECIES) * 3),
+                ("injected", C.c_int64 * PD_NSPECIES), ("charge_alive", C.c_int64),
                 ("charge_absorbed", C.c_int64), ("charge_injected", C.c_int64),
-                ("ke_J", C.c_double * 6), ("gamma", C.c_double), ("qbar", C.c_double),
+                ("ke_J", C.c_double * PD_NSPECIES), ("gamma", C.c_double), ("qbar", C.c_double),
                 ("particle_steps", C.c_int64), ("poisson_rel_res", C.c_double),
                 ("poisson_solves", C.c_int64), ("poisson_iters", C.c_int64),
                 ("poisson_refinements", C.c_int64), ("poisson_fallbacks", C.c_int64),

@@ -71,6 +71,9 @@ def assert_same_state(g, o, where=""):
     np.testing.assert_allclose(dg["ke_J"], do["ke_J"], rtol=1e-12, atol=0)
     for t in range(3):
         assert np.array_equal(g.spectrum(t), do["spectrum"][t]), (where, "spectrum", t)
+    # Eq. 21 from the exact counts, the same arithmetic on both sides
+    for k in ("gamma", "qbar"):
+        assert dg[k] == do[k], (where, k, dg[k], do[k])
     return pg
 
 

@@ -117,6 +117,59 @@ def test_tiny_config_200_steps_bit_exact():
     assert d["particle_steps"] > 200 * 30000
 
 
+def _chain_population(cfg, n_base, n_per_species, seed):
+    """The workload's population plus Cu2+ of every label and Cu3+ spread
+    over the volume with thermal velocities (targets of the chain)."""
+    parts = W.initial_population(cfg, n=n_base)
+    rng = np.random.default_rng(seed)
+    extra = [parts]
+    for sp in (W.CU2_STEP, W.CU2_DOUBLE, W.CU2_INIT, W.CU3):
+        n = n_per_species
+        extra.append({"r": cfg.R * np.sqrt(rng.random(n)) * 0.999,
+                      "z": cfg.L * (0.02 + 0.96 * rng.random(n)),
+                      "vr": rng.normal(0.0, 600.0, n), "vt": rng.normal(0.0, 600.0, n),
+                      "vz": rng.normal(0.0, 600.0, n), "sp": np.full(n, sp, np.uint8)})
+    return {k: np.concatenate([e[k] for e in extra]) for k in parts}
+
+
+def test_chain_to_cu4_dense_bit_exact():
+    """All six channels firing (constant cross sections with the channel
+    thresholds, dense Cu2+ of every label and Cu3+): Cu3+ and Cu4+ are made
+    and the whole state, Eq. 21 included, stays bit-identical."""
+    log("case: step-wise chain to Cu4+, dense")
+    cfg = W.config("tiny", nr=16, nz=32, weight=1e6)
+    tables = W.constant_tables([2e-19] * W.NCHANNELS, thresholds=list(W.THRESHOLDS_EV), n=4096)
+    parts = _chain_population(cfg, 20000, 3000, 11)
+    g, o = pair(cfg, parts=parts, steps=12, tables=tables)
+    for s in range(1, 13):
+        g.step(1)
+        o.step(1)
+        assert_same_state(g, o, "chain dense step %d" % s)
+    d = g.diag()
+    log("  events per channel %s, Cu3+ %d, Cu4+ %d, gamma %.4f, qbar %.4f" %
+        (list(d["events"]), d["count"][W.CU3], d["count"][W.CU4], d["gamma"], d["qbar"]))
+    assert np.all(np.asarray(d["events"]) > 0)
+    assert d["count"][W.CU4] + np.asarray(d["absorbed"])[:, W.CU4].sum() > 0
+
+
+def test_chain_tiny_config_200_steps_bit_exact():
+    """The tiny configuration with the Lotz tables of the whole chain."""
+    log("case: tiny config with the chain to Cu4+, 200 steps")
+    cfg = W.config("tiny")
+    tables = W.cross_section_tables(chain=True)
+    g, o = pair(cfg, parts=_chain_population(cfg, cfg.n_init, 1000, 12), steps=cfg.steps,
+                tables=tables)
+    done = 0
+    for target in (1, 7, 50, 200):
+        g.step(target - done)
+        o.step(target - done)
+        done = target
+        assert_same_state(g, o, "chain step %d" % done)
+    d = g.diag()
+    log("  events per channel %s" % list(d["events"]))
+    assert d["events"][W.SI3] > 0
+
+
 def test_di_disabled_and_seed_dependence():
     log("case: DI off, seed 7")
     cfg = W.config("tiny", seed=7, enable_di=False)
@@ -140,7 +193,7 @@ def test_dense_collisions_many_conflicts():
         o.step(1)
         assert_same_state(g, o, "dense step %d" % s)
     d = g.diag()
-    assert d["conflicts"] > 100 and d["events"].min() > 10
+    assert d["conflicts"] > 100 and d["events"][:4].min() > 10
 
 
 def test_gpu_runs_are_deterministic():

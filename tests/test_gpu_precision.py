@@ -100,7 +100,7 @@ def test_fp32_tiny_200_steps_error_per_result():
     ephi = np.max(np.abs(fg["phi"] - fo["phi"])) / np.max(np.abs(fo["phi"]))
     log("  potential: max |d| / max |phi| = %.3e (tolerance %.1e)" % (ephi, TOL_PHI))
     assert ephi < TOL_PHI
-    for s in range(6):
+    for s in range(W.NSPECIES):
         n32, n64 = int(dg["count"][s]), int(do["count"][s])
         log("  species %d: FP32 %d, FP64 %d" % (s, n32, n64))
         assert abs(n32 - n64) <= TOL_COUNT, s
