@@ -15,7 +15,7 @@ _LIB = os.path.join(_HERE, "libpd_oracle.so")
 
 NSPECIES = 8
 NKEYS = 6
-NCHANNELS = 6
+NCHANNELS = 8
 
 
 def build_oracle(force=True):

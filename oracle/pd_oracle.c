@@ -240,20 +240,22 @@ void or_destroy(or_sim* s) {
 
 /* the species each channel's target is drawn from (any Cu2+ tag for SI3:
  * all tags have the Cu2+ mass) and the label the target takes             */
-static const int TARGET_OF[OR_NCHANNELS] = {OR_CU, OR_CU, OR_CU, OR_CU1, OR_CU2_STEP, OR_CU3};
+static const int TARGET_OF[OR_NCHANNELS] = {OR_CU, OR_CU, OR_CU, OR_CU1, OR_CU2_STEP, OR_CU3,
+                                            OR_CU, OR_CU};
+static const int PROJECTILE_OF[OR_NCHANNELS] = {OR_E, OR_E, OR_E, OR_E, OR_E, OR_E, OR_CU1, OR_CU};
 static const int PRODUCT_OF[OR_NCHANNELS] = {OR_CU, OR_CU1, OR_CU2_DOUBLE, OR_CU2_STEP,
-                                             OR_CU3, OR_CU4};
+                                             OR_CU3, OR_CU4, OR_CU1, OR_CU};
 
 static void derive_pairs(or_sim* s) {
-  /* projectile = electron, target = TARGET_OF[channel] */
+  /* projectile PROJECTILE_OF[channel], target TARGET_OF[channel] */
   const int* tgt = TARGET_OF;
   for (int k = 0; k < OR_NCHANNELS; ++k) {
-    double m1 = s->m[OR_E], m2 = s->m[tgt[k]];
+    double m1 = s->m[PROJECTILE_OF[k]], m2 = s->m[tgt[k]];
     s->mr[k] = (m1 * m2) / (m1 + m2);
     s->f1[k] = s->mr[k] / m1;
     s->f2[k] = s->mr[k] / m2;
     s->ck[k] = sqrt(s->mr[k] / (2.0 * Q_E));
-    s->two_dE_mr[k] = (k == OR_EL) ? 0.0 : (2.0 * (-(s->xs_thr[k] * Q_E))) / s->mr[k];
+    s->two_dE_mr[k] = (k == OR_EL || k >= OR_CEX) ? 0.0 : (2.0 * (-(s->xs_thr[k] * Q_E))) / s->mr[k];
   }
 }
 
@@ -532,8 +534,8 @@ void or_stage_collide(or_sim* s) {
       /* uniform pick: floor(u32 * n / 2^32), word c-1 of the second draw */
       tp[c] = b[c] + (int64_t)(((uint64_t)t[c - 1] * (uint64_t)nt[c]) >> 32);
     }
-    double x[OR_NCHANNELS] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int k = 0; k < OR_NCHANNELS; ++k) {
+    double x[OR_NELECTRON_CHANNELS] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int k = 0; k < OR_NELECTRON_CHANNELS; ++k) {
       int c = cls_of[k];
       if (nt[c] == 0 || !s->xs_set[k]) continue;
       if (k == OR_DI && !s->enable_di) continue;
@@ -550,26 +552,75 @@ void or_stage_collide(or_sim* s) {
     if (!(R1 < pc)) continue;
     double u = R2 * X, c = 0.0;
     int ch = -1;
-    for (int k = 0; k < OR_NCHANNELS; ++k) {
+    for (int k = 0; k < OR_NELECTRON_CHANNELS; ++k) {
       c = c + x[k];
       if (u < c) { ch = k; break; }
     }
     if (ch < 0)
-      for (int k = OR_NCHANNELS - 1; k >= 0; --k)
+      for (int k = OR_NELECTRON_CHANNELS - 1; k >= 0; --k)
         if (x[k] > 0.0) { ch = k; break; }
     s->choice[p] = (uint8_t)(ch + 1);
     s->target[p] = (uint32_t)tp[cls_of[ch]];
   }
 
-  /* claim: a target takes part in at most one event; the electron with
-   * the lowest sorted position wins                                    */
+  /* heavy projectiles (Sec. 2.3 lists ion-neutral charge exchange and
+   * neutral-neutral elastic collisions; their cross sections are given
+   * here as tables like the others).  They collide on the steps that move
+   * them, over the heavy step K dt.  Each Cu+ draws one Cu of its cell (CEX);
+   * each Cu draws one other Cu of its cell (NN), and since every pair is
+   * then tried from both sides, its probability carries a factor 1/2 and
+   * the partner density counts the other N - 1 atoms.  One channel each:
+   * the event test is R1 < 1 - exp(-x).                                   */
+  const int K = s->heavy_every;
+  const int heavy_now = (K <= 1) || ((s->step % K) == 0);
+  const double dth = (double)K * s->dt;
+  for (int hc = 0; hc < 2 && heavy_now; ++hc) {
+    const int k = hc == 0 ? OR_CEX : OR_NN;
+    if (!s->xs_set[k]) continue;
+    const int pc_cls = hc == 0 ? 2 : 1; /* projectile key class: Cu+ or Cu */
+    for (int64_t p = s->off[pc_cls * C]; p < s->off[(pc_cls + 1) * C]; ++p) {
+      int64_t cell = (int64_t)s->key[p] - (int64_t)pc_cls * C;
+      int ci = (int)(cell % s->nr);
+      int64_t b = s->off[C + cell], nt = s->off[C + cell + 1] - b;
+      int64_t partners = hc == 0 ? nt : nt - 1;
+      if (partners < 1) continue;
+      uint32_t w[4], t[4];
+      draw4(s, s->id[p], 0, 0, w);
+      draw4(s, s->id[p], 1, 0, t);
+      double R1 = u53(w[0], w[1]);
+      int64_t u = (int64_t)(((uint64_t)t[0] * (uint64_t)partners) >> 32);
+      if (hc == 1 && b + u >= p) u += 1; /* skip the projectile itself */
+      int64_t tp = b + u;
+      double dvr = s->vr[p] - s->vr[tp];
+      double dvt = s->vt[p] - s->vt[tp];
+      double dvz = s->vz[p] - s->vz[tp];
+      double g = sqrt(((dvr * dvr) + (dvt * dvt)) + (dvz * dvz));
+      double dens = ((double)partners * s->W) / s->Vcell[ci];
+      double x = ((dth * g) * dens) * sigma_of(s, k, g);
+      if (hc == 1) x = 0.5 * x;
+      double pc = 1.0 - exp(-x);
+      if (!(R1 < pc)) continue;
+      s->choice[p] = (uint8_t)(k + 1);
+      s->target[p] = (uint32_t)tp;
+    }
+  }
+
+  /* claim: a particle takes part in at most one event per step; the event
+   * of the lowest sorted projectile position touching it wins it (an
+   * electron event touches its target, a heavy event its target and its
+   * projectile), and an event happens iff it wins everything it touches */
   for (int64_t p = 0; p < n; ++p) s->claim[p] = UINT32_MAX;
-  for (int64_t p = 0; p < n_e; ++p)
-    if (s->choice[p] && s->claim[s->target[p]] == UINT32_MAX)
-      s->claim[s->target[p]] = (uint32_t)p;
-  for (int64_t p = 0; p < n_e; ++p)
+  for (int64_t p = 0; p < n; ++p) {
+    if (!s->choice[p]) continue;
+    uint32_t t = s->target[p];
+    if (s->claim[t] == UINT32_MAX) s->claim[t] = (uint32_t)p;
+    if (p >= n_e && s->claim[p] == UINT32_MAX) s->claim[p] = (uint32_t)p;
+  }
+  for (int64_t p = 0; p < n; ++p)
     if (s->choice[p]) {
-      if (s->claim[s->target[p]] == (uint32_t)p) s->win[p] = 1;
+      int won = s->claim[s->target[p]] == (uint32_t)p;
+      if (p >= n_e) won = won && s->claim[p] == (uint32_t)p;
+      if (won) s->win[p] = 1;
       else s->conflicts += 1;
     }
 
@@ -624,6 +675,30 @@ void or_stage_collide(or_sim* s) {
       s->n += 1; s->next_id += 1; s->created += 1;
     }
     s->vr[p] = e1[0]; s->vt[p] = e1[1]; s->vz[p] = e1[2];
+  }
+
+  /* heavy events: charge exchange passes the charge from the ion to the
+   * atom, each keeping its position and velocity (the labels swap);
+   * neutral-neutral elastic scattering is Eq. 5 with dE = 0, equal masses,
+   * an isotropic direction in the centre-of-mass frame                   */
+  for (int64_t p = n_e; p < s->n_sorted; ++p) {
+    if (!s->win[p]) continue;
+    int ch = s->choice[p] - 1;
+    uint32_t tp = s->target[p];
+    s->events[ch] += 1;
+    if (ch == OR_CEX) {
+      uint8_t a = s->sp[p];
+      s->sp[p] = s->sp[tp];
+      s->sp[tp] = a;
+      continue;
+    }
+    double A[3] = {s->vr[p], s->vt[p], s->vz[p]};
+    double B[3] = {s->vr[tp], s->vt[tp], s->vz[tp]};
+    double nh[3];
+    or_isotropic(s, s->id[p], 2, nh);
+    binary(A, B, 0.0, s->f1[ch], s->f2[ch], nh);
+    s->vr[p] = A[0]; s->vt[p] = A[1]; s->vz[p] = A[2];
+    s->vr[tp] = B[0]; s->vt[tp] = B[1]; s->vz[tp] = B[2];
   }
 }
 

@@ -29,11 +29,13 @@ enum { OR_E = 0, OR_CU = 1, OR_CU1 = 2, OR_CU2_STEP = 3, OR_CU2_DOUBLE = 4,
 /* classes of the sort key: e, Cu, Cu+, Cu2+ (the three tags together), Cu3+,
  * Cu4+ */
 enum { OR_NKEYS = 6 };
-/* collision channels in cumulative-sum order: elastic, Cu -> Cu+, Cu -> Cu2+
- * (double), Cu+ -> Cu2+, Cu2+ -> Cu3+, Cu3+ -> Cu4+; the last two take part
- * only when their cross sections are set */
+/* collision channels.  Electron impact, in cumulative-sum order: elastic,
+ * Cu -> Cu+, Cu -> Cu2+ (double), Cu+ -> Cu2+, Cu2+ -> Cu3+, Cu3+ -> Cu4+.
+ * Heavy projectiles: Cu+ + Cu charge exchange, Cu + Cu elastic.  Channels
+ * from SI3 on take part only when their cross sections are set. */
 enum { OR_EL = 0, OR_SI = 1, OR_DI = 2, OR_SI2 = 3, OR_SI3 = 4, OR_SI4 = 5,
-       OR_NCHANNELS = 6 };
+       OR_CEX = 6, OR_NN = 7, OR_NCHANNELS = 8 };
+enum { OR_NELECTRON_CHANNELS = 6 };
 /* absorbing boundaries */
 enum { OR_CATHODE = 0, OR_ANODE = 1, OR_OUTER = 2 };
 

@@ -38,15 +38,17 @@ M_CU = 63.546 * AMU
 E, CU, CU1, CU2_STEP, CU2_DOUBLE, CU2_INIT, CU3, CU4 = range(8)
 NSPECIES = 8
 SPECIES_NAMES = ("e", "Cu", "Cu+", "Cu2+(step)", "Cu2+(double)", "Cu2+(init)", "Cu3+", "Cu4+")
-# channels in cumulative order; SI3 and SI4 (the step-wise chain on to Cu4+)
-# take part only when their tables are given
-EL, SI, DI, SI2, SI3, SI4 = range(6)
-NCHANNELS = 6
+# channels: electron impact in cumulative order, then the heavy projectiles'
+# charge exchange (Cu+ + Cu) and neutral-neutral elastic (Cu + Cu); SI3 and
+# SI4 (the step-wise chain on to Cu4+), CEX and NN take part only when their
+# tables are given
+EL, SI, DI, SI2, SI3, SI4, CEX, NN = range(8)
+NCHANNELS = 8
 CHANNEL_NAMES = ("elastic", "Cu->Cu+", "Cu->Cu2+ (double)", "Cu+->Cu2+", "Cu2+->Cu3+",
-                 "Cu3+->Cu4+")
+                 "Cu3+->Cu4+", "Cu+ + Cu charge exchange", "Cu + Cu elastic")
 # ionization energies (eV) of Cu, Cu+, Cu2+, Cu3+ and the paper's double-
-# ionization threshold
-THRESHOLDS_EV = (0.0, 7.73, 28.0, 20.29, 36.84, 57.38)
+# ionization threshold; the heavy channels lose no energy
+THRESHOLDS_EV = (0.0, 7.73, 28.0, 20.29, 36.84, 57.38, 0.0, 0.0)
 
 
 def species_table():
@@ -64,11 +66,15 @@ def lotz(E, P, q, a_cm2=4.5e-14):
     return np.where(E >= P, s, 0.0) * 1e-4
 
 
-def cross_section_tables(dsqrtE=2.0 ** -4, n=1025, chain=False):
-    """(channel, threshold_eV, dsqrtE, sigma[n]) for EL, SI, DI, SI2, and with
-    chain=True also SI3 and SI4 (Lotz forms with 9 and 8 d electrons).
+def cross_section_tables(dsqrtE=2.0 ** -4, n=1025, chain=False, heavy=False):
+    """(channel, threshold_eV, dsqrtE, sigma[n]) for EL, SI, DI, SI2, with
+    chain=True also SI3 and SI4 (Lotz forms with 9 and 8 d electrons), with
+    heavy=True also CEX and NN (stand-ins: a resonant charge-exchange form
+    (a - b ln E)^2, a = 7.5 A, b = 0.4 A, E >= 0.01 eV; hard spheres of
+    diameter 2.6 A).
 
-    Tables are uniform in sqrt(E/eV) with spacing dsqrtE (a power of 2).
+    Tables are uniform in sqrt(E/eV) with spacing dsqrtE (a power of 2); E is
+    the energy of relative motion of the pair.
     """
     sq = np.arange(n, dtype=np.float64) * dsqrtE
     En = sq * sq
@@ -80,6 +86,10 @@ def cross_section_tables(dsqrtE=2.0 ** -4, n=1025, chain=False):
            (SI2, 20.29, dsqrtE, si2)]
     if chain:
         out += [(SI3, 36.84, dsqrtE, lotz(En, 36.84, 9.0)), (SI4, 57.38, dsqrtE, lotz(En, 57.38, 8.0))]
+    if heavy:
+        cex = (7.5 - 0.4 * np.log(np.maximum(En, 0.01))) ** 2 * 1e-20
+        nn = np.full(n, np.pi * 2.6e-10 ** 2)
+        out += [(CEX, 0.0, dsqrtE, cex), (NN, 0.0, dsqrtE, nn)]
     return out
 
 
