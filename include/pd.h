@@ -65,12 +65,20 @@ typedef enum {
  * then by cell */
 enum { PD_E = 0, PD_CU = 1, PD_CU1 = 2, PD_CU2_STEP = 3, PD_CU2_DOUBLE = 4,
        PD_CU2_INIT = 5, PD_CU3 = 6, PD_CU4 = 7, PD_NSPECIES = 8 };
-/* collision channels, in the order their probabilities are summed:
- * elastic, Cu -> Cu+, Cu -> Cu2+ (double), Cu+ -> Cu2+ (these four must be
- * set before stepping), Cu2+ of any label -> Cu3+, Cu3+ -> Cu4+ (these two
- * take part only when set) */
-enum { PD_EL = 0, PD_SI = 1, PD_DI = 2, PD_SI2 = 3, PD_SI3 = 4, PD_SI4 = 5,
-       PD_NCHANNELS = 6 };
+/* collision channels.  Electron impact, in the order their probabilities
+ * are summed: elastic, Cu -> Cu+, Cu -> Cu2+ (double), Cu+ -> Cu2+ (these
+ * four must be set before stepping), Cu2+ of any label -> Cu3+, Cu3+ -> Cu4+.
+ * Heavy projectiles (Sec. 2.3), on heavy steps over the heavy step: Cu+ + Cu
+ * charge exchange (the charge passes to the atom: the two labels swap,
+ * positions and velocities stay), Cu + Cu elastic (isotropic in the
+ * centre-of-mass frame; each pair is tried from both sides at half weight).
+ * Every channel from PD_SI3 on takes part only when its table is set.  A
+ * particle takes part in at most one event per step: an electron event
+ * claims its target, a heavy event its target and its projectile, the
+ * lowest sorted projectile position wins a claim, and an event happens iff
+ * it wins all its claims. */
+enum { PD_EL = 0, PD_SI = 1, PD_DI = 2, PD_SI2 = 3, PD_SI3 = 4, PD_SI4 = 5, PD_CEX = 6,
+       PD_NN = 7, PD_NCHANNELS = 8 };
 /* absorbing boundaries */
 enum { PD_CATHODE = 0, PD_ANODE = 1, PD_OUTER = 2 };
 /* precision forms: FP64 deterministic (with PD_POISSON_DIRECT64 every result

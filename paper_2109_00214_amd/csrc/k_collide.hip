@@ -111,6 +111,12 @@ __device__ inline void binary(double v1[3], double v2[3], double two_dE_mr, doub
   }
 }
 
+// the heavy-projectile channels run on this step (a table is set and the
+// sort marked a heavy step)
+__device__ inline bool heavy_trials(const CollideParams& cp, const DevState* st) {
+  return cp.heavy && st->heavy_now != 0u;
+}
+
 // (T: precision of the particle record; the collision arithmetic is FP64)
 // (indices e, tc, t1 are sorted positions; the records are read in U
 // through perm)
@@ -148,7 +154,7 @@ __global__ void __launch_bounds__(256) k_decide(Flow<T> f, const uint32_t* off, 
     const uint32_t tc = b_cu + __umulhi(t[0], n_cu);
     const uint32_t t1 = b_c1 + __umulhi(t[1], n_c1);
     const double evr = ev.vr, evt = ev.vt, evz = ev.vz;
-    double x[kNC] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double x[kNEC] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     const double Vc = cp.Vcell[ci];
     // Cu target: EL, SI, DI share the pick and the relative speed
     if (n_cu > 0) {
@@ -199,12 +205,12 @@ __global__ void __launch_bounds__(256) k_decide(Flow<T> f, const uint32_t* off, 
       const double u = R2 * X;
       double c = 0.0;
 #pragma unroll
-      for (int k = 0; k < kNC; ++k) {
+      for (int k = 0; k < kNEC; ++k) {
         c = c + x[k];
         if (ch < 0 && u < c) ch = k;
       }
       if (ch < 0) {
-        for (int k = kNC - 1; k >= 0; --k)
+        for (int k = kNEC - 1; k >= 0; --k)
           if (x[k] > 0.0) {
             ch = k;
             break;
@@ -220,15 +226,55 @@ __global__ void __launch_bounds__(256) k_decide(Flow<T> f, const uint32_t* off, 
       choice[e] = 0;
     }
   }
+  // Heavy projectiles on heavy steps (Sec. 2.3's ion-neutral charge exchange
+  // and neutral-neutral elastic collisions): the Cu range [off[C], off[2C])
+  // tries NN against another Cu of its cell (half weight: every pair is tried
+  // from both sides), the Cu+ range [off[2C], off[3C]) tries CEX against a Cu;
+  // an event claims its target and its projectile.
+  if (!heavy_trials(cp, st)) return;
+  const uint32_t h0 = off[C], h1 = off[3 * C], h_mid = off[2 * C];
+  for (uint32_t p = h0 + blockIdx.x * blockDim.x + threadIdx.x; p < h1; p += ndec * blockDim.x) {
+    const bool nn = p < h_mid;
+    const int k = nn ? kNN : kCEX;
+    choice[p] = 0;
+    if (cp.tabn[k] == 0) continue;
+    const uint32_t cell = f.skey[p] - (nn ? C : 2 * C);
+    const int ci = (int)(cell % (uint32_t)g.nr);
+    const uint32_t b = off[C + cell], nt = off[C + cell + 1] - b;
+    const uint32_t partners = nn ? nt - 1u : nt;
+    if (nt == 0 || partners == 0) continue;
+    const RecT<T> pv = P.v[f.perm[p]];
+    uint32_t w[4], t[4];
+    philox(pv.id, 0u, step, 0u, cp.seed_lo, cp.seed_hi, w);
+    philox(pv.id, 0u, step, 1u << 24, cp.seed_lo, cp.seed_hi, t);
+    const double R1 = u53(w[0], w[1]);
+    uint32_t u = __umulhi(t[0], partners);
+    if (nn && b + u >= p) u += 1u;  // never the projectile itself
+    const uint32_t tp = b + u;
+    const RecT<T> tv = P.v[f.perm[tp]];
+    const double dvr = (double)pv.vr - (double)tv.vr, dvt = (double)pv.vt - (double)tv.vt,
+                 dvz = (double)pv.vz - (double)tv.vz;
+    const double gg = sqrt(((dvr * dvr) + (dvt * dvt)) + (dvz * dvz));
+    const double dens = ((double)partners * cp.W) / cp.Vcell[ci];
+    double x = ((cp.dt_heavy * gg) * dens) * sigma_of(cp, k, gg);
+    if (nn) x = 0.5 * x;
+    const double pc = 1.0 - exp(-x);
+    if (R1 < pc) {
+      choice[p] = (uint8_t)(k + 1);
+      target[p] = tp;
+      atomicMin(&claim[tp], p);
+      atomicMin(&claim[p], p);
+    }
+  }
 }
 
 // Claims are resolved per chunk of 256 electrons (one per thread): a
 // winner keeps its channel and counts the electrons it creates (0, 1 or 2);
 // the chunk's total goes to bsum for the scan of the created slots.
 __global__ void __launch_bounds__(256) k_resolve(const uint32_t* off, DevState* st, Grid g,
-                                                 uint8_t* choice, const uint32_t* target,
-                                                 const uint32_t* claim, uint32_t* ccount,
-                                                 uint32_t* bsum) {
+                                                 CollideParams cp, uint8_t* choice,
+                                                 const uint32_t* target, const uint32_t* claim,
+                                                 uint32_t* ccount, uint32_t* bsum) {
   __shared__ uint32_t sh[4];
   __shared__ uint32_t tally[1 + kNC];  // conflicts, events per channel: one atomic per block
   const uint32_t n_e = off[g.C];
@@ -264,6 +310,35 @@ __global__ void __launch_bounds__(256) k_resolve(const uint32_t* off, DevState* 
     uint32_t tot;
     block_scan256(cnt, &tot, sh);
     if (threadIdx.x == 0) bsum[b] = tot;
+  }
+  // heavy events: an event happens iff it holds both of its claims; the
+  // losers keep their channel with bit 7 set, so that the apply resets the
+  // claims they made
+  if (heavy_trials(cp, st)) {
+    const uint32_t h0 = off[g.C], h1 = off[3 * g.C];
+    for (uint32_t p0 = h0 + blockIdx.x * 256u; p0 < h1; p0 += gridDim.x * 256u) {
+      const uint32_t p = p0 + threadIdx.x;
+      int ch = -1;
+      bool lost = false;
+      if (p < h1) {
+        const uint32_t c = choice[p];
+        if (c) {
+          if (claim[target[p]] == p && claim[p] == p) {
+            ch = (int)c - 1;
+          } else {
+            lost = true;
+            choice[p] = (uint8_t)(c | 0x80u);
+          }
+        }
+      }
+      const uint64_t ml = __ballot(lost);
+      if (lane == 0 && ml) atomicAdd(&tally[0], (uint32_t)__popcll(ml));
+#pragma unroll
+      for (int k = kCEX; k <= kNN; ++k) {
+        const uint64_t m = __ballot(ch == k);
+        if (lane == 0 && m) atomicAdd(&tally[1 + k], (uint32_t)__popcll(m));
+      }
+    }
   }
   __syncthreads();
   if (threadIdx.x <= kNC && tally[threadIdx.x]) {
@@ -396,6 +471,53 @@ __global__ void __launch_bounds__(256) k_apply(Flow<T> f, const uint32_t* off, D
       P.v[pe] = v1;
     }
   }
+  // heavy events (disjoint from every other event); every heavy trial that
+  // claimed resets its two claims, won or lost
+  if (!heavy_trials(cp, st)) return;
+  const uint32_t h0 = off[g.C], h1 = off[3 * g.C];
+  for (uint32_t p = h0 + blockIdx.x * blockDim.x + threadIdx.x; p < h1;
+       p += gridDim.x * blockDim.x) {
+    const uint32_t c = choice[p];
+    if (!c) continue;
+    const uint32_t tp = target[p];
+    if (!(c & 0x80u)) {
+      const int ch = (int)c - 1;
+      const uint32_t pp = f.perm[p], pt = f.perm[tp];
+      RecT<T> a = P.v[pp], b = P.v[pt];
+      if (ch == kCEX) {
+        // the charge passes from the ion to the atom: the labels swap, the
+        // charge moves from the projectile's place to the target's
+        const uint32_t sa = a.sp;
+        a.sp = b.sp;
+        b.sp = sa;
+        if (Q) {
+          long long v[4];
+          const PosT<T> xa = P.x[pp], xb = P.x[pt];
+          const long long dzp = (long long)spp.Z[a.sp] - spp.Z[b.sp];
+          int bn = cic_fixed<T>(g, xa.r, xa.z, v);
+          cic_atomic(Q, bn, g.nr + 1, dzp, v);
+          bn = cic_fixed<T>(g, xb.r, xb.z, v);
+          cic_atomic(Q, bn, g.nr + 1, -dzp, v);
+        }
+      } else {
+        // elastic, equal masses, isotropic in the centre-of-mass frame
+        double A[3] = {a.vr, a.vt, a.vz}, B[3] = {b.vr, b.vt, b.vz};
+        double nh[3];
+        isotropic(cp, a.id, step, 2u, nh);
+        binary(A, B, 0.0, cp.f1[ch], cp.f2[ch], nh);
+        a.vr = (T)A[0];
+        a.vt = (T)A[1];
+        a.vz = (T)A[2];
+        b.vr = (T)B[0];
+        b.vt = (T)B[1];
+        b.vz = (T)B[2];
+      }
+      P.v[pp] = a;
+      P.v[pt] = b;
+    }
+    claim[tp] = 0xFFFFFFFFu;
+    claim[p] = 0xFFFFFFFFu;
+  }
 }
 
 template <typename T>
@@ -412,7 +534,7 @@ void collide(const Flow<T>& P, const uint32_t* off, DevState* st, const Grid& g,
   if (Q) nd = (int)((cap + 255) / 256) < 4096 ? (int)((cap + 255) / 256) : 4096;
   k_decide<T><<<gr + nd, 256, 0, s>>>(P, off, st, g, cp, w.choice, w.target, w.claim,
                                       sp, (unsigned long long*)Q, (uint32_t)gr);
-  k_resolve<<<nb, 256, 0, s>>>(off, st, g, w.choice, w.target, w.claim, w.ccount, bsum);
+  k_resolve<<<nb, 256, 0, s>>>(off, st, g, cp, w.choice, w.target, w.claim, w.ccount, bsum);
   // created-electron slots: each apply block adds up the chunk sums before
   // its chunk; the guard (in every block) flags an overflow and then nothing
   // is created, so every later launch touches only [0, n_alive)

@@ -495,16 +495,19 @@ pd_status solve_poisson(pd_ctx* c) {
 }
 
 void derive_pairs(pd_ctx* c) {
-  // projectile: electron; target: Cu (EL, SI, DI), Cu+ (SI2), Cu2+ of any
-  // label (SI3: the labels share the Cu2+ mass) or Cu3+ (SI4)
-  const int tgt[kNC] = {PD_CU, PD_CU, PD_CU, PD_CU1, PD_CU2_STEP, PD_CU3};
+  // projectile: electron, Cu+ (CEX) or Cu (NN); target: Cu (EL, SI, DI,
+  // CEX, NN), Cu+ (SI2), Cu2+ of any label (SI3: the labels share the Cu2+
+  // mass) or Cu3+ (SI4)
+  const int tgt[kNC] = {PD_CU, PD_CU, PD_CU, PD_CU1, PD_CU2_STEP, PD_CU3, PD_CU, PD_CU};
+  const int prj[kNC] = {PD_E, PD_E, PD_E, PD_E, PD_E, PD_E, PD_CU1, PD_CU};
   for (int k = 0; k < kNC; ++k) {
-    const double m1 = c->spp.m[PD_E], m2 = c->spp.m[tgt[k]];
+    const double m1 = c->spp.m[prj[k]], m2 = c->spp.m[tgt[k]];
     const double mr = (m1 * m2) / (m1 + m2);
     c->cpar.f1[k] = mr / m1;
     c->cpar.f2[k] = mr / m2;
     c->cpar.ck[k] = std::sqrt(mr / (2.0 * kQE));
-    c->cpar.two_dE_mr[k] = (k == PD_EL) ? 0.0 : (2.0 * (-(c->xs_thr[k] * kQE))) / mr;
+    c->cpar.two_dE_mr[k] =
+        (k == PD_EL || k >= kNEC) ? 0.0 : (2.0 * (-(c->xs_thr[k] * kQE))) / mr;
   }
 }
 
@@ -683,6 +686,7 @@ pd_status pd_create(const pd_domain* dom, const pd_opts* opts, pd_ctx** out) {
   c->g.dt = dom->dt;
   c->g.heavy_every = 1;
   c->g.dt_heavy = dom->dt;
+  c->cpar.dt_heavy = dom->dt;
   c->sw.heavy_every = 1;
   c->qunit = (kQE * dom->weight) * 0x1p-40;
   {
@@ -842,6 +846,7 @@ pd_status pd_set_cross_section(pd_ctx* c, int ch, double thr, int n, double dsq,
   c->xs_thr[ch] = thr;
   c->xs_set[ch] = true;
   c->cpar.chain = (c->xs_set[PD_SI3] || c->xs_set[PD_SI4]) ? 1 : 0;
+  c->cpar.heavy = (c->xs_set[PD_CEX] || c->xs_set[PD_NN]) ? 1 : 0;
   if (c->species_set) derive_pairs(c);
   return PD_OK;
 }
@@ -854,6 +859,7 @@ pd_status pd_set_heavy_subcycle(pd_ctx* c, int32_t every) {
   if (s) return s;
   c->g.heavy_every = every;
   c->g.dt_heavy = (double)every * c->dom.dt;
+  c->cpar.dt_heavy = c->g.dt_heavy;
   c->sw.heavy_every = every;
   for (int k = 0; k < kNS; ++k)
     c->spp.qmdt_heavy[k] = (((double)c->spp.Z[k] * kQE) / c->spp.m[k]) * c->g.dt_heavy;

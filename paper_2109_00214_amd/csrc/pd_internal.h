@@ -13,7 +13,9 @@ constexpr double kEPS0 = 8.8541878128e-12; // vacuum permittivity, F/m
 constexpr double kPI = 3.14159265358979323846;
 constexpr int kNS = 8;                     // species (the three Cu2+ labels apart)
 constexpr int kNK = 6;                     // sort-key classes (the Cu2+ labels together)
-constexpr int kNC = 6;                     // collision channels
+constexpr int kNC = 8;                     // collision channels
+constexpr int kNEC = 6;                    // of them electron-impact (the rest: heavy projectiles)
+constexpr int kCEX = 6, kNN = 7;           // Cu+ + Cu charge exchange, Cu + Cu elastic
 
 // sort-key class of a species: e, Cu, Cu+, Cu2+ (every label), Cu3+, Cu4+
 __host__ __device__ inline uint32_t key_class(uint32_t s) {
@@ -116,6 +118,8 @@ struct CollideParams {
   const double* tab[kNC];
   int tabn[kNC];         // 0: the channel takes no part (its table is not set)
   int chain;             // the Cu2+ -> Cu3+ or Cu3+ -> Cu4+ channel takes part
+  int heavy;             // a heavy-projectile channel (CEX, NN) takes part
+  double dt_heavy;       // their time step (the heavy step)
   const double* Vcell;   // cell volumes [nr]
 };
 

@@ -50,7 +50,7 @@ class pd_opts(C.Structure):
                 ("stream", C.c_void_p), ("poisson_rtol", C.c_double)]
 
 
-PD_NSPECIES, PD_NCHANNELS = 8, 6
+PD_NSPECIES, PD_NCHANNELS = 8, 8
 
 
 class pd_diag(C.Structure):

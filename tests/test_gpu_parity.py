@@ -170,6 +170,55 @@ def test_chain_tiny_config_200_steps_bit_exact():
     assert d["events"][W.SI3] > 0
 
 
+@pytest.mark.parametrize("every", [1, 3])
+def test_heavy_collisions_bit_exact(every):
+    """Cu+ + Cu charge exchange and Cu + Cu elastic collisions beside the
+    electron-impact channels (constant cross sections, dense heavy gas with
+    drifting atoms and ions), with heavy steps every step or every third:
+    every claim, label swap, scattered velocity and node charge identical."""
+    log("case: heavy-projectile collisions, heavy step every %d" % every)
+    cfg = W.config("tiny", nr=16, nz=32, weight=1e5)
+    sig = [3e-19, 2e-19, 1e-19, 2e-19, 0.0, 0.0, 5e-18, 3e-18]
+    tables = W.constant_tables(sig, thresholds=list(W.THRESHOLDS_EV), n=4096)
+    parts = W.initial_population(cfg, n=30000)
+    heavy = parts["sp"] != W.E
+    rng = np.random.default_rng(21)
+    parts["vz"] = np.where(heavy, parts["vz"] + rng.normal(0.0, 2e4, heavy.size), parts["vz"])
+    g, o = pair(cfg, parts=parts, steps=15, tables=tables)
+    if every > 1:
+        g.set_heavy_subcycle(every)
+        o.set_heavy_subcycle(every)
+    for s in range(1, 16):
+        g.step(1)
+        o.step(1)
+        assert_same_state(g, o, "heavy every %d step %d" % (every, s))
+    d = g.diag()
+    log("  events per channel %s, conflicts %d" % (list(d["events"]), d["conflicts"]))
+    assert d["events"][W.CEX] > 100 and d["events"][W.NN] > 100
+
+
+def test_all_channels_tiny_config_200_steps_bit_exact():
+    """The tiny configuration with every channel's table (the chain to Cu4+
+    and the heavy projectiles' stand-ins) and the paper's heavy step of ten
+    electron steps."""
+    log("case: tiny config, all channels, heavy step 10, 200 steps")
+    cfg = W.config("tiny")
+    tables = W.cross_section_tables(chain=True, heavy=True)
+    g, o = pair(cfg, parts=_chain_population(cfg, cfg.n_init, 1000, 13), steps=cfg.steps,
+                tables=tables)
+    g.set_heavy_subcycle(10)
+    o.set_heavy_subcycle(10)
+    done = 0
+    for target in (1, 11, 60, 200):
+        g.step(target - done)
+        o.step(target - done)
+        done = target
+        assert_same_state(g, o, "all channels step %d" % done)
+    d = g.diag()
+    log("  events per channel %s" % list(d["events"]))
+    assert d["events"][W.CEX] > 0 and d["events"][W.NN] > 0
+
+
 def test_di_disabled_and_seed_dependence():
     log("case: DI off, seed 7")
     cfg = W.config("tiny", seed=7, enable_di=False)
