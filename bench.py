@@ -203,7 +203,7 @@ def run_ensemble(a):
     cfgs = W.ensemble_configs(a.ensemble)
     cands = (1, 2, 4, 8)
     tune_steps, eager_steps = 6, 10
-    nsteps = len(cands) * tune_steps + a.warmup + a.steps + eager_steps
+    nsteps = len(cands) * tune_steps + (a.warmup + 1) + (a.steps + 1) + eager_steps + 2
     torch.cuda.init()
     t0 = time.time()
     sims = []
@@ -261,6 +261,24 @@ def run_ensemble(a):
     for s in sims:
         s.synchronize()
     eager = (pushed() - p0) / (time.perf_counter() - t)
+    # roofline of the push over the replicas: two more steps of each with the
+    # stage events on (its HIP-event time on each replica's stream)
+    push_ms, units = 0.0, 0
+    for s in sims:
+        s.set_timing(True)
+        s.timing(reset=True)
+        d0 = s.diag()["particle_steps"]
+        s.step(2)
+        s.synchronize()
+        stages, _ = s.timing()
+        push_ms += stages["push"]
+        units += s.diag()["particle_steps"] - d0
+        s.set_timing(False)
+    bpp = algo_bytes(4)["push"]
+    achieved = bpp * units / (push_ms / 1e3) / 1e9
+    roof = {"bound": "hbm", "kernel": "push", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "bytes_per_particle": bpp, "particles_per_launch": round(units / (2 * len(sims)))}
     n_particles = sum(c.n_init for c in cfgs)
     out = {
         "metric": "particle-steps/s incl. DSMC", "value": value, "unit": "particle-steps/s",
@@ -274,7 +292,7 @@ def run_ensemble(a):
                    "replicas_256x512": sum(c.nr == 256 for c in cfgs),
                    "worker_streams": best, "autotune": {str(k): v for k, v in tune.items()},
                    "eager_particle_steps_per_s": eager},
-        "roofline": None, "cpu_baseline": None,
+        "roofline": roof, "cpu_baseline": None,
     }
     for s in sims:
         s.close()
