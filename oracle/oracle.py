@@ -36,7 +36,8 @@ class _Diag(C.Structure):
                 ("charge_alive", C.c_int64), ("charge_absorbed", C.c_int64),
                 ("charge_injected", C.c_int64), ("ke_J", C.c_double * NSPECIES),
                 ("gamma", C.c_double), ("qbar", C.c_double),
-                ("spectrum", (C.c_int64 * 66) * 3)]
+                ("spectrum", (C.c_int64 * 66) * 3), ("V_gap", C.c_double),
+                ("emitted", C.c_int64 * 2)]
 
 
 _lib = None
@@ -68,6 +69,8 @@ def load_oracle(path):
     lib.or_schedule_injection.argtypes = [P, C.c_int, P, P, P, P, P, P, P]
     lib.or_step.argtypes = [P, C.c_int]
     lib.or_set_heavy_subcycle.argtypes = [P, C.c_int]
+    lib.or_set_emission.argtypes = [P] + [C.c_double] * 5
+    lib.or_set_circuit.argtypes = [P] + [C.c_double] * 3
     for nm in ("sort", "collide", "deposit", "poisson", "field", "push",
                "compact_inject", "end"):
         getattr(lib, "or_stage_" + nm).argtypes = [P]
@@ -161,6 +164,12 @@ class Oracle:
 
     def set_heavy_subcycle(self, every):
         self._chk(self.lib.or_set_heavy_subcycle(self.h, int(every)))
+
+    def set_emission(self, beta, r_tip, phi_w, neutral_ratio, T):
+        self._chk(self.lib.or_set_emission(self.h, beta, r_tip, phi_w, neutral_ratio, T))
+
+    def set_circuit(self, V0, R, C):
+        self._chk(self.lib.or_set_circuit(self.h, V0, R, C))
 
     def step(self, nsteps=1):
         self._chk(self.lib.or_step(self.h, nsteps))

@@ -31,6 +31,11 @@
 #define Q_E 1.602176634e-19
 #define EPS0 8.8541878128e-12
 #define PI_D 3.14159265358979323846
+#define K_B 1.380649e-23
+/* Fowler-Nordheim constants of the elementary form J = (A F^2 / phi)
+ * exp(-B phi^(3/2) / F): A in A eV V^-2, B in eV^(-3/2) V m^-1           */
+#define FN_A 1.541434e-6
+#define FN_B 6.830890e9
 
 static char g_err[256];
 static int fail(const char* msg) {
@@ -46,6 +51,13 @@ struct or_sim {
   uint64_t seed;
   int enable_di, deposit_off, collisions_off;
   int heavy_every;  /* heavy particles advance every heavy_every steps (1: every step) */
+  /* cathode emission (Sec. 2.3): off while em_beta == 0 */
+  double em_beta, em_rtip, em_phi, em_ratio, em_T;
+  double em_acc_e, em_acc_n; /* fractional super-particles carried to the next step */
+  int64_t emitted[2];        /* cumulative: electrons, neutrals */
+  /* external circuit (Sec. 2.3): off while circ_C == 0 */
+  double circ_V0, circ_R, circ_C;
+  int64_t circ_zanode; /* sum of Z absorbed at the anode at the last update */
 
   int Z[OR_NSPECIES];
   double m[OR_NSPECIES];
@@ -868,7 +880,10 @@ int or_set_heavy_subcycle(or_sim* s, int every) {
 /* 9. gather (the deposit's bilinear weights, unrounded) and leapfrog push
  *    in 2D3V: v += (q/m) E dt; straight move in the particle's local
  *    Cartesian frame; rotate back to the r-z plane                        */
+static void circuit_update(or_sim* s); /* boundary physics, below */
+
 void or_stage_push(or_sim* s) {
+  circuit_update(s);
   const int nr = s->nr, W = nr + 1;
   const int K = s->heavy_every;
   const int heavy_now = (K <= 1) || ((s->step % K) == 0);
@@ -923,6 +938,127 @@ void or_stage_push(or_sim* s) {
 
 /* 10. stable compaction of the absorbed particles, then this step's
  *     injected particles in the order given                              */
+/* ------------------------------------------------------------------ */
+/* Boundary physics of Sec. 2.3.
+ *
+ * Emission: a tip of radius r_tip at the centre of the cathode with field
+ * enhancement beta.  Each cathode node i with part of its annulus
+ * [(i - 1/2) dr, (i + 1/2) dr] (clipped to [0, r_tip]) inside the tip sees
+ * the surface field F_i = beta * (-E_z(r_i, 0)) (E_z of this step's field,
+ * the one-sided difference at the electrode) and emits the Fowler-Nordheim
+ * current density J_i = (A F_i^2 / phi) exp(-B phi^(3/2) / F_i) (F_i > 0)
+ * over the annulus area; I = sum_i J_i a_i in ascending i.  The step emits
+ * floor(I dt / (e W) + carry) electron super-particles and, with the
+ * neutral flux at the ratio rho of the electron flux, floor(rho I dt / (e W)
+ * + carry') Cu atoms; the fractions carry over.  Each emitted particle
+ * (id = the one it receives) draws (purpose 5) its annulus by u1 I against
+ * the running sums and its radius uniform in area in it; it starts on the
+ * cathode (z = 0), an electron at rest, an atom with the normal speed of
+ * a flux-Maxwellian at T (sqrt((2 k T / m)(-ln(1 - u3))), no tangential
+ * velocity).  They are appended after this step's scheduled particles,
+ * electrons first.
+ *
+ * Circuit: the anode sits at the gap voltage V of a capacitor C charged
+ * from V0 through R and discharged by the gap current.  Before each push
+ * V <- V + (dt / C)((V0 - V) / R - I), I = -(Delta sum Z absorbed at the
+ * anode since the last update) e W / dt (the charge the previous push
+ * delivered); the next step's Poisson solve uses the new V.            */
+int or_set_emission(or_sim* s, double beta, double r_tip, double phi_w, double ratio,
+                    double T) {
+  if (!(beta >= 0.0) || !(r_tip >= 0.0) || !(r_tip <= s->R) || !(phi_w > 0.0) ||
+      !(ratio >= 0.0) || !(T >= 0.0) || !isfinite(beta) || !isfinite(phi_w) || !isfinite(ratio) ||
+      !isfinite(T))
+    return fail("or_set_emission: bad parameters");
+  s->em_beta = beta; s->em_rtip = r_tip; s->em_phi = phi_w; s->em_ratio = ratio; s->em_T = T;
+  return 0;
+}
+
+int or_set_circuit(or_sim* s, double V0, double R, double C) {
+  if (!isfinite(V0) || !(R > 0.0) || !(C >= 0.0) || !isfinite(R) || !isfinite(C))
+    return fail("or_set_circuit: bad parameters");
+  s->circ_V0 = V0; s->circ_R = R; s->circ_C = C;
+  int64_t za = 0;
+  for (int sp = 0; sp < OR_NSPECIES; ++sp) za += (int64_t)s->Z[sp] * s->absorbed[OR_ANODE][sp];
+  s->circ_zanode = za;
+  return 0;
+}
+
+static void circuit_update(or_sim* s) {
+  if (!(s->circ_C > 0.0)) return;
+  int64_t za = 0;
+  for (int sp = 0; sp < OR_NSPECIES; ++sp) za += (int64_t)s->Z[sp] * s->absorbed[OR_ANODE][sp];
+  double I = ((-(double)(za - s->circ_zanode)) * (Q_E * s->W)) / s->dt;
+  s->V = s->V + ((s->dt / s->circ_C) * (((s->circ_V0 - s->V) / s->circ_R) - I));
+  s->circ_zanode = za;
+}
+
+static void emit(or_sim* s) {
+  if (!(s->em_beta > 0.0)) return;
+  const int nr = s->nr;
+  double* cum = (double*)xalloc(sizeof(double) * (nr + 1));
+  double I = 0.0;
+  for (int i = 0; i <= nr; ++i) {
+    double lo = ((double)i - 0.5) * s->dr, hi = ((double)i + 0.5) * s->dr;
+    if (lo < 0.0) lo = 0.0;
+    if (hi > s->em_rtip) hi = s->em_rtip;
+    double c = 0.0;
+    if (hi > lo) {
+      double F = (-s->Ez[i]) * s->em_beta;
+      if (F > 0.0) {
+        double J = ((FN_A * (F * F)) / s->em_phi) *
+                   exp(-((FN_B * (s->em_phi * sqrt(s->em_phi))) / F));
+        c = J * (PI_D * ((hi * hi) - (lo * lo)));
+      }
+    }
+    I = I + c;
+    cum[i] = I;
+  }
+  double xe = ((I * s->dt) / (Q_E * s->W)) + s->em_acc_e;
+  double xn = (((s->em_ratio * I) * s->dt) / (Q_E * s->W)) + s->em_acc_n;
+  double fe = floor(xe), fn = floor(xn);
+  s->em_acc_e = xe - fe;
+  s->em_acc_n = xn - fn;
+  int64_t ne = (int64_t)fe, nn = (int64_t)fn, tot = ne + nn;
+  if (tot > 0) {
+    double* a = (double*)xalloc(sizeof(double) * 5 * tot);
+    uint8_t* sp = (uint8_t*)xalloc(tot);
+    for (int64_t k = 0; k < tot; ++k) {
+      uint32_t id = (uint32_t)(s->next_id + k);
+      uint32_t w[4];
+      draw4(s, id, 5, 0, w);
+      double u1 = u53(w[0], w[1]), u2 = u53(w[2], w[3]);
+      double target = u1 * I;
+      int ring = -1;
+      for (int i = 0; i <= nr; ++i)
+        if (target < cum[i]) { ring = i; break; }
+      if (ring < 0) /* rounding at the top: the last annulus that emits */
+        for (int i = nr; i >= 0; --i)
+          if (cum[i] > (i > 0 ? cum[i - 1] : 0.0)) { ring = i; break; }
+      double lo = ((double)ring - 0.5) * s->dr, hi = ((double)ring + 0.5) * s->dr;
+      if (lo < 0.0) lo = 0.0;
+      if (hi > s->em_rtip) hi = s->em_rtip;
+      a[k] = sqrt((lo * lo) + (u2 * ((hi * hi) - (lo * lo))));
+      a[tot + k] = 0.0;
+      a[2 * tot + k] = 0.0;
+      a[3 * tot + k] = 0.0;
+      if (k < ne) {
+        a[4 * tot + k] = 0.0;
+        sp[k] = OR_E;
+      } else {
+        draw4(s, id, 5, 1, w);
+        double u3 = u53(w[0], w[1]);
+        a[4 * tot + k] = sqrt((((2.0 * K_B) * s->em_T) / s->m[OR_CU]) * (-log(1.0 - u3)));
+        sp[k] = OR_CU;
+      }
+    }
+    append(s, tot, a, a + tot, a + 2 * tot, a + 3 * tot, a + 4 * tot, sp);
+    free(a); free(sp);
+  }
+  s->emitted[0] += ne;
+  s->emitted[1] += nn;
+  free(cum);
+}
+
 void or_stage_compact_inject(or_sim* s) {
   int64_t w = 0;
   for (int64_t p = 0; p < s->n; ++p) {
@@ -939,6 +1075,7 @@ void or_stage_compact_inject(or_sim* s) {
            s->s_sp + a);
     s->sched_pos += 1;
   }
+  emit(s);
 }
 
 void or_stage_end(or_sim* s) { s->step += 1; }
@@ -1040,6 +1177,9 @@ void or_get_diag(const or_sim* s, or_diag* d) {
   int64_t qsum = N[1] + 2 * N[2] + 3 * N[3] + 4 * N[4];
   d->gamma = (ions + N[0]) > 0 ? (double)ions / (double)(ions + N[0]) : 0.0;
   d->qbar = ions > 0 ? (double)qsum / (double)ions : 0.0;
+  d->V_gap = s->V;
+  d->emitted[0] = s->emitted[0];
+  d->emitted[1] = s->emitted[1];
 }
 
 /* ------------------------------------------------------------------ */

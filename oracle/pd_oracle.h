@@ -53,6 +53,8 @@ typedef struct {
   double ke_J[OR_NSPECIES];
   double gamma, qbar; /* Eq. 21 over the charge states 0..4 */
   int64_t spectrum[3][66]; /* Cu2+ tags STEP, DOUBLE, INIT: 64 bins, <1 eV, >=1000 eV */
+  double V_gap;            /* the gap voltage the next Poisson solve uses */
+  int64_t emitted[2];      /* cumulative super-particles emitted: electrons, atoms */
 } or_diag;
 
 or_sim* or_create(int nr, int nz, double R, double L, double V, double dt,
@@ -74,6 +76,14 @@ int or_step(or_sim* s, int nsteps);
 /* heavy-particle subcycling: heavy species advance every `every` steps with
  * the step every*dt (1, the default: every step) */
 int or_set_heavy_subcycle(or_sim* s, int every);
+/* boundary physics (Sec. 2.3): Fowler-Nordheim emission from a tip of radius
+ * r_tip with field enhancement beta and work function phi_w (eV), with Cu
+ * atoms emitted at neutral_ratio times the electron flux at temperature T
+ * (beta = 0: off); the gap voltage of an RC circuit (source V0, resistance
+ * R, capacitance C; C = 0: off, the voltage stays fixed)                 */
+int or_set_emission(or_sim* s, double beta, double r_tip, double phi_w, double neutral_ratio,
+                    double T);
+int or_set_circuit(or_sim* s, double V0, double R, double C);
 
 /* stage-level entry points (a full step is these in this order) */
 void or_stage_sort(or_sim* s);
