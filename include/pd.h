@@ -155,6 +155,10 @@ typedef struct {
   double poisson_seconds;        /* device time of the solves made by pd_poisson
                                   * (HIP events around each solve; the steps'
                                   * solves are timed by pd_get_timing) */
+  double V_gap;                  /* gap voltage the next Poisson solve uses, V */
+  int64_t emitted[2];            /* cumulative super-particles emitted by the
+                                  * cathode: electrons, Cu atoms (also counted
+                                  * in injected) */
 } pd_diag;
 
 /* Create a context on the current HIP device.  dom and opts are copied.
@@ -185,6 +189,35 @@ pd_status pd_set_cross_section(pd_ctx* ctx, int channel, double threshold_eV, in
  * heavy particles are taken at the half step K dt / 2 before their first
  * push.  Errors: PD_EINVAL (K outside 1..1000), PD_ESTATE (ensemble member).*/
 pd_status pd_set_heavy_subcycle(pd_ctx* ctx, int32_t every);
+
+/* Cathode emission (Sec. 2.3): a tip of radius r_tip (m) at the centre of the
+ * cathode with field-enhancement factor beta emits electrons by the
+ * Fowler-Nordheim law J = (A F^2 / phi_w) exp(-B phi_w^(3/2) / F),
+ * A = 1.541434e-6 A eV V^-2, B = 6.830890e9 eV^(-3/2) V m^-1, phi_w the work
+ * function in eV, F = beta * (-E_z) at each cathode node whose annulus
+ * [(i - 1/2) dr, (i + 1/2) dr] reaches into the tip (E_z the field stage's
+ * one-sided difference at the electrode); the step emits the current's
+ * super-particles (floor of I dt / (e W) plus the carried fraction) at radii
+ * uniform in area over the annuli in proportion to their current, on the
+ * cathode (z = 0) and at rest, and Cu atoms at neutral_ratio times that
+ * flux (the paper's 3 %) with the normal speed of a flux-Maxwellian at T (K).
+ * They are appended after the step's scheduled particles with the next ids.
+ * beta = 0 (the default) switches emission off.  Errors: PD_EINVAL (negative
+ * or non-finite values, r_tip > R, a tip wider than 1023 radial nodes),
+ * PD_ESTATE (ensemble member).                                          */
+pd_status pd_set_emission(pd_ctx* ctx, double beta, double r_tip, double phi_w,
+                          double neutral_ratio, double T);
+
+/* External circuit (Sec. 2.3): the gap (cathode at -V_gap, anode at 0) is a
+ * capacitor C charged from the source V0 through the resistance R and
+ * discharged by the gap current.  Before each step's push
+ * V_gap <- V_gap + (dt / C)((V0 - V_gap) / R - I), I = -(the sum of Z of the
+ * particles the previous push absorbed at the anode) e W / dt; the next
+ * step's Poisson solve (and pd_poisson) uses the new V_gap.  V_gap starts at
+ * V_cathode.  C = 0 switches the updates off (V_gap stays where it is).
+ * Needs a direct Poisson solve.  Errors: PD_EINVAL (R <= 0, C < 0,
+ * non-finite), PD_ESTATE (iterative solver, ensemble member).          */
+pd_status pd_set_circuit(pd_ctx* ctx, double V0, double R, double C);
 
 /* Append n particles now: positions r, z (0 <= r < R, 0 <= z < L),
  * velocities vr, vt, vz at the half step before their first push

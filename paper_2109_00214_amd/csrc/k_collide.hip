@@ -31,35 +31,6 @@ static inline int grid_for(int64_t n, int block = 256) {
   return (int)g;
 }
 
-// Philox4x32-10 (Salmon et al., SC'11)
-__device__ inline void philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
-                              uint32_t k1, uint32_t out[4]) {
-#pragma unroll
-  for (int round = 0; round < 10; ++round) {
-    if (round > 0) {
-      k0 += 0x9E3779B9u;
-      k1 += 0xBB67AE85u;
-    }
-    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
-    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
-    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
-    c0 = n0;
-    c1 = lo1;
-    c2 = n2;
-    c3 = lo0;
-  }
-  out[0] = c0;
-  out[1] = c1;
-  out[2] = c2;
-  out[3] = c3;
-}
-
-// uniform in [0,1): the top 53 bits of (hi:lo) times 2^-53
-__device__ inline double u53(uint32_t hi, uint32_t lo) {
-  const uint64_t b = (((uint64_t)hi << 32) | (uint64_t)lo) >> 11;
-  return (double)b * 0x1p-53;
-}
-
 __device__ inline double sigma_of(const CollideParams& cp, int k, double g) {
   const double sq = g * cp.ck[k];
   const double eps = sq * sq;

@@ -108,39 +108,142 @@ __device__ inline void count_codes(int code, unsigned long long* ctr) {
 // ---------------------------------------------------------------------------
 // this step's scheduled particles, appended after the pushed ones (the slots
 // after alive + created, which the push does not touch), as extra blocks of
-// the field's launch; the push's first thread then rolls the step counters.
-// Both read the same counters (no launch between them changes them), so
-// they take the same decision; the roll leaves n_created to the next
-// collisions, which set it.
+// the field's launch, followed by the particles the cathode emits; the
+// push's first thread then rolls the step counters.  Both read the same
+// counters (no launch between them changes them; the emitted counts come
+// from the injection launch's first block), so they take the same decision;
+// the roll leaves n_created to the next collisions, which set it.
 struct InjectPlan {
   uint32_t pos, cnt, base, id0;
-  int64_t a;  // first schedule entry
+  uint32_t ne, nn;  // emitted electrons and atoms, after the cnt scheduled ones
+  int64_t a;        // first schedule entry
   bool have, fits;
 };
 
-__device__ inline InjectPlan inject_plan(const DevState* st, const Schedule& sc, uint32_t cap) {
+__device__ inline InjectPlan inject_plan(const DevState* st, const Schedule& sc, uint32_t cap,
+                                         uint32_t ne, uint32_t nn) {
   InjectPlan ip;
   ip.pos = st->sched_pos;
   ip.have = sc.off && ip.pos < st->sched_n;
   ip.a = ip.have ? sc.off[ip.pos] : 0;
   ip.cnt = ip.have ? (uint32_t)(sc.off[ip.pos + 1] - ip.a) : 0u;
+  ip.ne = ne;
+  ip.nn = nn;
   ip.base = st->n_alive + st->n_created;
   ip.id0 = st->next_id + st->n_created;
-  ip.fits = (uint64_t)ip.base + ip.cnt <= cap && (uint64_t)ip.id0 + ip.cnt <= 0xFFFFFFFFull;
-  if (!ip.fits) ip.cnt = 0;
+  const uint64_t tot = (uint64_t)ip.cnt + ne + nn;
+  ip.fits = (uint64_t)ip.base + tot <= cap && (uint64_t)ip.id0 + tot <= 0xFFFFFFFFull;
+  if (!ip.fits) ip.cnt = ip.ne = ip.nn = 0;
   return ip;
 }
 
+// Cathode emission (paper Sec. 2.3): the annuli of the cathode nodes inside
+// the tip, i = 0 .. nring-1 (part of [(i - 1/2) dr, (i + 1/2) dr] below
+// r_tip), each with the surface field F_i = beta (-E_z(r_i, 0)) from the
+// electrode's one-sided difference of phi (the field stage's expression)
+// and the Fowler-Nordheim current J(F_i) a_i, J = (A F^2 / phi_w)
+// exp(-B phi_w^(3/2) / F) for F > 0; cum[i] = running sum in ascending i.
+constexpr double kFnA = 1.541434e-6;  // A eV V^-2
+constexpr double kFnB = 6.830890e9;   // eV^(-3/2) V m^-1
+constexpr double kKB = 1.380649e-23;  // J/K
+constexpr int kMaxRings = 1024;
+
+__device__ inline void ring_bounds(const Grid& g, int i, double& lo, double& hi) {
+  lo = ((double)i - 0.5) * g.dr;
+  hi = ((double)i + 0.5) * g.dr;
+  if (lo < 0.0) lo = 0.0;
+  if (hi > g.em_rtip) hi = g.em_rtip;
+}
+
+__device__ inline double emission_rings(const double* phi, const Grid& g, int nring, double* cum) {
+  const int W = g.nr + 1;
+  const double tdz = 2.0 * g.dz;
+  double I = 0.0;
+  for (int i = 0; i < nring; ++i) {
+    double lo, hi;
+    ring_bounds(g, i, lo, hi);
+    double c = 0.0;
+    if (hi > lo) {
+      const double ez = (((3.0 * phi[i]) - (4.0 * phi[i + W])) + phi[i + 2 * W]) / tdz;
+      const double F = (-ez) * g.em_beta;
+      if (F > 0.0) {
+        const double J = ((kFnA * (F * F)) / g.em_phi) *
+                         exp(-((kFnB * (g.em_phi * sqrt(g.em_phi))) / F));
+        c = J * (kPI * ((hi * hi) - (lo * lo)));
+      }
+    }
+    I = I + c;
+    cum[i] = I;
+  }
+  return I;
+}
+
+// super-particles this step: floor(I dt / (e W) + carry) electrons and
+// floor(ratio I dt / (e W) + carry') atoms; the fractions carry over
+__device__ inline void emission_counts(const DevState* st, const Grid& g, double I, uint32_t n[2],
+                                       double acc[2]) {
+  const double x[2] = {((I * g.dt) / (kQE * g.W)) + st->em_acc[0],
+                       (((g.em_ratio * I) * g.dt) / (kQE * g.W)) + st->em_acc[1]};
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const double f = floor(x[k]);
+    acc[k] = x[k] - f;
+    n[k] = f < 4.0e9 ? (uint32_t)f : 0xF0000000u;  // beyond any capacity: the guard refuses it
+  }
+}
+
 template <typename T>
-__device__ inline void inject_records(const PartsT<T>& P, const Grid& g, const Schedule& sc,
-                                      const InjectPlan& ip, uint32_t blk, uint32_t nblk) {
-  for (uint32_t q = blk * blockDim.x + threadIdx.x; q < ip.cnt; q += nblk * blockDim.x) {
-    const int64_t src = ip.a + q;
-    const uint32_t d = ip.base + q;
-    const T r = (T)sc.r[src], z = (T)sc.z[src];
-    const uint32_t s = sc.sp[src];
+__device__ inline void inject_records(const PartsT<T>& P, const DevState* st, const Grid& g,
+                                      const Schedule& sc, const InjectPlan& ip, const double* cum,
+                                      int nring, double I, uint32_t blk, uint32_t nblk) {
+  const uint32_t tot = ip.cnt + ip.ne + ip.nn;
+  for (uint32_t q = blk * blockDim.x + threadIdx.x; q < tot; q += nblk * blockDim.x) {
+    const uint32_t d = ip.base + q, id = ip.id0 + q;
+    T r, z;
+    RecT<T> v;
+    uint32_t s;
+    if (q < ip.cnt) {
+      const int64_t src = ip.a + q;
+      r = (T)sc.r[src];
+      z = (T)sc.z[src];
+      s = sc.sp[src];
+      v = RecT<T>{(T)sc.vr[src], (T)sc.vt[src], (T)sc.vz[src], id, s};
+    } else {
+      // emitted: annulus by u1 I against the running sums, radius uniform in
+      // area in it, on the cathode; an electron at rest, an atom with the
+      // normal speed of a flux-Maxwellian at em_T (purpose 5 draws)
+      const bool electron = q < ip.cnt + ip.ne;
+      uint32_t w[4];
+      philox(id, 0u, st->step, 5u << 24, g.seed_lo, g.seed_hi, w);
+      const double u1 = u53(w[0], w[1]), u2 = u53(w[2], w[3]);
+      const double target = u1 * I;
+      int ring = -1;
+      for (int i = 0; i < nring; ++i)
+        if (target < cum[i]) {
+          ring = i;
+          break;
+        }
+      if (ring < 0)
+        for (int i = nring - 1; i >= 0; --i)
+          if (cum[i] > (i > 0 ? cum[i - 1] : 0.0)) {
+            ring = i;
+            break;
+          }
+      double lo, hi;
+      ring_bounds(g, ring, lo, hi);
+      r = (T)sqrt((lo * lo) + (u2 * ((hi * hi) - (lo * lo))));
+      z = (T)0.0;
+      double vz = 0.0;
+      if (!electron) {
+        philox(id, 0u, st->step, (5u << 24) | 1u, g.seed_lo, g.seed_hi, w);
+        const double u3 = u53(w[0], w[1]);
+        vz = sqrt((((2.0 * kKB) * g.em_T) / g.em_mass) * (-log(1.0 - u3)));
+      }
+      s = electron ? 0u : 1u;
+      v = RecT<T>{(T)0.0, (T)0.0, (T)vz, id, s};
+    }
     P.x[d] = PosT<T>{r, z};
-    P.v[d] = RecT<T>{(T)sc.vr[src], (T)sc.vt[src], (T)sc.vz[src], ip.id0 + q, s};
+    P.v[d] = v;
     int i, j;
     T fr, fz;
     cell_of<T>(g, r, z, i, j, fr, fz);
@@ -148,44 +251,91 @@ __device__ inline void inject_records(const PartsT<T>& P, const Grid& g, const S
   }
 }
 
-// (one thread) the arrays now hold alive + created + injected
+// (one thread) the arrays now hold alive + created + injected + emitted
 __device__ inline void roll_counters(DevState* st, const InjectPlan& ip) {
   if (!ip.fits) atomicOr(&st->err, 1u);
   if (ip.have) st->sched_pos = ip.pos + 1;
+  const uint32_t tot = ip.cnt + ip.ne + ip.nn;
+  if (ip.fits) {
+    st->em_acc[0] = st->em_acc_next[0];
+    st->em_acc[1] = st->em_acc_next[1];
+    st->emitted[0] += ip.ne;
+    st->emitted[1] += ip.nn;
+  }
   st->created += st->n_created;
   st->pushed += st->n_alive + st->n_created;
-  st->n_total = ip.base + ip.cnt;
-  st->next_id = ip.id0 + ip.cnt;
+  st->n_total = ip.base + tot;
+  st->next_id = ip.id0 + tot;
   st->step += 1;
+}
+
+// The external circuit (paper Sec. 2.3), one thread, before this step's
+// push: V <- V + (dt / C)((V0 - V) / R - I), I = -(Delta sum Z absorbed at
+// the anode since the last update) e W / dt; the next Poisson solve uses V.
+__device__ inline void circuit_update(DevState* st, const Grid& g, const SpeciesParams& spp) {
+  long long za = 0;
+  for (int s = 0; s < kNS; ++s) za += (long long)spp.Z[s] * (long long)st->absorbed[kNS + s];
+  const double I = ((-(double)(za - st->circ_zanode)) * (kQE * g.W)) / g.dt;
+  st->V_gap = st->V_gap + ((g.dt / g.circ_C) * (((g.circ_V0 - st->V_gap) / g.circ_R) - I));
+  st->circ_zanode = za;
 }
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_field_inject(const double* phi, int nr, int nz, double dr,
                                                       double dz, double* Er, double* Ez,
                                                       float* Erf, float* Ezf, PartsT<T> P,
-                                                      const DevState* st, Grid g, Schedule sc,
-                                                      uint32_t cap, uint32_t nf) {
+                                                      DevState* st, Grid g, SpeciesParams spp,
+                                                      Schedule sc, uint32_t cap, uint32_t nf,
+                                                      int nring) {
   if (blockIdx.x < nf) {
     field_nodes(phi, nr, nz, dr, dz, Er, Ez, Erf, Ezf, blockIdx.x, nf);
     return;
   }
-  const InjectPlan ip = inject_plan(st, sc, cap);
-  inject_records<T>(P, g, sc, ip, blockIdx.x - nf, gridDim.x - nf);
+  __shared__ double cum[kMaxRings];
+  __shared__ double Ish;
+  uint32_t n[2] = {0u, 0u};
+  double acc[2] = {0.0, 0.0};
+  double I = 0.0;
+  if (nring > 0) {
+    if (threadIdx.x == 0) Ish = emission_rings(phi, g, nring, cum);
+    __syncthreads();
+    I = Ish;
+    emission_counts(st, g, I, n, acc);
+  }
+  const InjectPlan ip = inject_plan(st, sc, cap, n[0], n[1]);
+  if (blockIdx.x == nf && threadIdx.x == 0) {
+    st->em_now[0] = n[0];
+    st->em_now[1] = n[1];
+    st->em_acc_next[0] = acc[0];
+    st->em_acc_next[1] = acc[1];
+    if (g.circ_C > 0.0) circuit_update(st, g, spp);
+  }
+  inject_records<T>(P, st, g, sc, ip, cum, nring, I, blockIdx.x - nf, gridDim.x - nf);
+}
+
+// emission annuli: those with part of their annulus inside the tip (0: off)
+inline int emission_ring_count(const Grid& g) {
+  if (!(g.em_beta > 0.0)) return 0;
+  int n = 0;
+  while (n <= g.nr && ((double)n - 0.5) * g.dr < g.em_rtip) ++n;
+  return n < kMaxRings ? n : kMaxRings;
 }
 
 template <typename T>
-void field_and_inject(const Grid& g, FieldWork& fw, const PartsT<T>& P, const DevState* st,
-                      const Schedule& sc, int64_t cap, hipStream_t s) {
+void field_and_inject(const Grid& g, FieldWork& fw, const PartsT<T>& P, DevState* st,
+                      const SpeciesParams& spp, const Schedule& sc, int64_t cap, hipStream_t s) {
   const int64_t n = (int64_t)(g.nr + 1) * (g.nz + 1);
   const int nf = grid_for(n), ni = grid_for(sc.off ? sc.max_count : 1);
   k_field_inject<T><<<nf + ni, 256, 0, s>>>(fw.phi, g.nr, g.nz, g.dr, g.dz, fw.Er, fw.Ez,
-                                            fw.Erf, fw.Ezf, P, st, g, sc, (uint32_t)cap,
-                                            (uint32_t)nf);
+                                            fw.Erf, fw.Ezf, P, st, g, spp, sc, (uint32_t)cap,
+                                            (uint32_t)nf, emission_ring_count(g));
 }
-template void field_and_inject<double>(const Grid&, FieldWork&, const Parts&, const DevState*,
-                                       const Schedule&, int64_t, hipStream_t);
-template void field_and_inject<float>(const Grid&, FieldWork&, const PartsF&, const DevState*,
-                                      const Schedule&, int64_t, hipStream_t);
+template void field_and_inject<double>(const Grid&, FieldWork&, const Parts&, DevState*,
+                                       const SpeciesParams&, const Schedule&, int64_t,
+                                       hipStream_t);
+template void field_and_inject<float>(const Grid&, FieldWork&, const PartsF&, DevState*,
+                                      const SpeciesParams&, const Schedule&, int64_t,
+                                      hipStream_t);
 
 // gather (bilinear, the deposit's weights) and leapfrog push in the record's
 // precision T: v += (q/m) E dt, Cartesian move, rotation back to the r-z
@@ -202,7 +352,8 @@ __global__ void __launch_bounds__(256) k_push(Flow<T> f, DevState* st, Grid g, S
   const uint32_t n_alive = st->n_alive;
   const uint32_t n = n_alive + st->n_created;
   const bool heavy_now = st->heavy_now != 0u;
-  if (blockIdx.x == 0 && threadIdx.x == 0) roll_counters(st, inject_plan(st, sc, cap));
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    roll_counters(st, inject_plan(st, sc, cap, st->em_now[0], st->em_now[1]));
   const int W = g.nr + 1;
   const bool sub = g.heavy_every > 1;
   const uint32_t stride = gridDim.x * blockDim.x;

@@ -21,12 +21,14 @@ namespace pd {
 // of the table are not prefetched and wait for every group of terms.
 __global__ void __launch_bounds__(256) k_rhs(const int64_t* __restrict__ Q,
                                              const double* __restrict__ Vnode, double qunit,
-                                             int nr, int nz, double V, double* __restrict__ f,
+                                             int nr, int nz, double V, const double* Vp,
+                                             double* __restrict__ f,
                                              double* __restrict__ phi,
                                              const double* __restrict__ Sm,
                                              double* __restrict__ sink) {
   const int W = nr + 1, M = nz - 1;
   const int n = M * W;
+  if (Vp) V = *Vp;  // the circuit's gap voltage
   {
     // slice blockIdx.x / 8 of gridDim.x / 8 slices: one word of every
     // 128-byte line of the slice
@@ -72,9 +74,10 @@ constexpr int kFoB = kFoWaves * kFoRb;  // b per block
 template <bool FWD>
 __global__ void __launch_bounds__(256, 1) k_sine_fo(const double* __restrict__ X,
                                                     const double* __restrict__ Sm, int nr,
-                                                    int nz, int ag, double V,
+                                                    int nz, int ag, double V, const double* Vp,
                                                     double* __restrict__ out) {
   const int W = nr + 1, M = nz - 1;
+  if (!FWD && Vp) V = *Vp;  // the circuit's gap voltage
   const int t = threadIdx.x, lane = t & 63;
   const int w = __builtin_amdgcn_readfirstlane(t >> 6);
   const int a = (int)blockIdx.x * ag + lane;
@@ -303,15 +306,16 @@ void poisson_direct(const Grid& g, FieldWork& fw, hipStream_t s) {
   const int nr = g.nr, nz = g.nz, M = nz - 1, W = nr + 1;
   int gr = (M * W + 255) / 256;
   if (gr > 4096) gr = 4096;
-  k_rhs<<<gr, 256, 0, s>>>(fw.Q, fw.Vnode, fw.qunit, nr, nz, g.V, fw.f, fw.phi, fw.Sm, fw.g);
+  k_rhs<<<gr, 256, 0, s>>>(fw.Q, fw.Vnode, fw.qunit, nr, nz, g.V, g.Vdev, fw.f, fw.phi, fw.Sm,
+                           fw.g);
   // the radial nodes in equal groups of at most 64 (one group per lane set)
   const int ngrp = (W + 63) / 64, ag = (W + ngrp - 1) / ngrp;
   const dim3 grid(ngrp, (M + kFoB - 1) / kFoB);
-  k_sine_fo<true><<<grid, 256, 0, s>>>(fw.f, fw.Sm, nr, nz, ag, g.V, fw.fh);
+  k_sine_fo<true><<<grid, 256, 0, s>>>(fw.f, fw.Sm, nr, nz, ag, g.V, nullptr, fw.fh);
   const int mpb = thomas_modes(nr);
   k_thomas_fo<<<(M + mpb - 1) / mpb, 256, sizeof(double) * ((size_t)3 * mpb + 1) * W, s>>>(
       fw.fh, fw.tinv, fw.tcp, fw.ra, nr, nz, mpb, fw.g);
-  k_sine_fo<false><<<grid, 256, 0, s>>>(fw.g, fw.Sm, nr, nz, ag, g.V, fw.phi);
+  k_sine_fo<false><<<grid, 256, 0, s>>>(fw.g, fw.Sm, nr, nz, ag, g.V, g.Vdev, fw.phi);
 }
 
 // the direct solve's limits: the full sine table (nz-1)^2 words; the

@@ -38,10 +38,11 @@ template <bool FWD>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 k_dst_mfma(const int64_t* __restrict__ Q, const double* __restrict__ coef,
            const double* __restrict__ G, const double* __restrict__ T, int nr, int nz, double V,
-           double* __restrict__ out) {
+           const double* Vp, double* __restrict__ out) {
   extern __shared__ double Ts[];  // the sine table, 2 nz entries (dynamic LDS)
   __shared__ double red[3][4][64];
   const int W = nr + 1, M = nz - 1, N2 = 2 * nz;
+  if (Vp) V = *Vp;  // the circuit's gap voltage
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   // the operand entries are scattered over the table: served from LDS, a
   // gather from the vector cache costs one tag lookup per lane
@@ -226,12 +227,14 @@ void poisson_spectral(const Grid& g, FieldWork& fw, hipStream_t s) {
   const int nr = g.nr, nz = g.nz, M = nz - 1, W = nr + 1;
   const dim3 grid((W + 15) / 16, (M + 15) / 16);
   const size_t lds = (size_t)2 * nz * sizeof(double);
-  k_dst_mfma<true><<<grid, 256, lds, s>>>(fw.Q, fw.coef, nullptr, fw.T, nr, nz, g.V, fw.fh);
+  k_dst_mfma<true><<<grid, 256, lds, s>>>(fw.Q, fw.coef, nullptr, fw.T, nr, nz, g.V, nullptr,
+                                           fw.fh);
   const int P = (W + 63) / 64;
   if (P <= 4) k_tri_scan<4><<<(M + 3) / 4, 256, 0, s>>>(fw.fh, fw.tinv, fw.tcp, fw.ra, nr, nz, fw.g);
   else if (P <= 8) k_tri_scan<8><<<(M + 3) / 4, 256, 0, s>>>(fw.fh, fw.tinv, fw.tcp, fw.ra, nr, nz, fw.g);
   else k_tri_scan<kTriMaxP><<<(M + 3) / 4, 256, 0, s>>>(fw.fh, fw.tinv, fw.tcp, fw.ra, nr, nz, fw.g);
-  k_dst_mfma<false><<<grid, 256, lds, s>>>(nullptr, nullptr, fw.g, fw.T, nr, nz, g.V, fw.phi);
+  k_dst_mfma<false><<<grid, 256, lds, s>>>(nullptr, nullptr, fw.g, fw.T, nr, nz, g.V, g.Vdev,
+                                            fw.phi);
 }
 
 // rows per lane of the scan; the sine table (2 nz doubles) within 64 KiB of LDS

@@ -620,7 +620,7 @@ pd_status enqueue_step(pd_ctx* c, PartsT<T>& A, PartsT<T>& B, int64_t nn, Mark& 
   pd_status ps = solve_poisson(c);
   if (ps) return ps;
   mark();
-  field_and_inject(c->g, c->fw, B, c->st, c->sched, c->cap, s);
+  field_and_inject(c->g, c->fw, B, c->st, c->spp, c->sched, c->cap, s);
   mark();
   push(f, c->st, c->g, c->spp, c->fw, c->sched, c->cap, s);
   mark();
@@ -684,6 +684,9 @@ pd_status pd_create(const pd_domain* dom, const pd_opts* opts, pd_ctx** out) {
   c->g.L = dom->L;
   c->g.V = dom->V_cathode;
   c->g.dt = dom->dt;
+  c->g.W = dom->weight;
+  c->g.seed_lo = (uint32_t)dom->seed;
+  c->g.seed_hi = (uint32_t)(dom->seed >> 32);
   c->g.heavy_every = 1;
   c->g.dt_heavy = dom->dt;
   c->cpar.dt_heavy = dom->dt;
@@ -782,6 +785,8 @@ pd_status pd_create(const pd_domain* dom, const pd_opts* opts, pd_ctx** out) {
   if ((s = build_mg(c, dVn))) return fail(s);
 
   DevState h{};
+  h.V_gap = dom->V_cathode;  // every Poisson solve reads the gap voltage here
+  c->g.Vdev = &c->st->V_gap;
   if (hipMemcpy(c->st, &h, sizeof h, hipMemcpyHostToDevice) != hipSuccess)
     return fail(set_err(c, PD_EDEVICE, "state upload failed"));
   fill_u32(c->cw.claim, 0xFFFFFFFFu, cap, c->stream);
@@ -812,6 +817,7 @@ pd_status pd_set_species(pd_ctx* c, int n, const int32_t* Z, const double* mass)
   for (int k = PD_CU2_DOUBLE; k <= PD_CU2_INIT; ++k)
     if (Z[k] != Z[PD_CU2_STEP] || mass[k] != mass[PD_CU2_STEP])
       return set_err(c, PD_EINVAL, "the Cu2+ labels must share one charge and mass");
+  c->g.em_mass = mass[PD_CU];
   for (int k = 0; k < n; ++k) {
     c->spp.Z[k] = Z[k];
     c->spp.Zk[key_class((uint32_t)k)] = Z[k];
@@ -863,6 +869,47 @@ pd_status pd_set_heavy_subcycle(pd_ctx* c, int32_t every) {
   c->sw.heavy_every = every;
   for (int k = 0; k < kNS; ++k)
     c->spp.qmdt_heavy[k] = (((double)c->spp.Z[k] * kQE) / c->spp.m[k]) * c->g.dt_heavy;
+  return PD_OK;
+}
+
+pd_status pd_set_emission(pd_ctx* c, double beta, double r_tip, double phi_w, double neutral_ratio,
+                          double T) {
+  if (!c) return PD_EINVAL;
+  if (c->in_ensemble) return set_err(c, PD_ESTATE, "the ensemble's graph holds the emission");
+  if (!(beta >= 0.0) || !std::isfinite(beta) || !(r_tip >= 0.0) || !(r_tip <= c->dom.R) ||
+      (beta > 0.0 && !(phi_w > 0.0)) || !std::isfinite(phi_w) || !(neutral_ratio >= 0.0) ||
+      !std::isfinite(neutral_ratio) || !(T >= 0.0) || !std::isfinite(T))
+    return set_err(c, PD_EINVAL, "bad emission parameters");
+  if (beta > 0.0 && (r_tip / c->g.dr) + 0.5 >= 1023.0)
+    return set_err(c, PD_EINVAL, "the tip spans more than 1023 radial nodes");
+  pd_status s = sync(c);
+  if (s) return s;
+  c->g.em_beta = beta;
+  c->g.em_rtip = r_tip;
+  c->g.em_phi = phi_w;
+  c->g.em_ratio = neutral_ratio;
+  c->g.em_T = T;
+  return PD_OK;
+}
+
+pd_status pd_set_circuit(pd_ctx* c, double V0, double R, double C) {
+  if (!c) return PD_EINVAL;
+  if (c->in_ensemble) return set_err(c, PD_ESTATE, "the ensemble's graph holds the circuit");
+  if (!std::isfinite(V0) || !(R > 0.0) || !std::isfinite(R) || !(C >= 0.0) || !std::isfinite(C))
+    return set_err(c, PD_EINVAL, "bad circuit parameters");
+  if (C > 0.0 && c->mg_on)
+    return set_err(c, PD_ESTATE, "the circuit needs a direct Poisson solve");
+  DevState h;
+  pd_status s = read_state(c, &h);
+  if (s) return s;
+  // the anode charge counted so far is not current of the circuit
+  long long za = 0;
+  for (int k = 0; k < kNS; ++k) za += (long long)c->spp.Z[k] * (long long)h.absorbed[kNS + k];
+  HIPCHK(c, hipMemcpy((char*)c->st + offsetof(DevState, circ_zanode), &za, sizeof za,
+                      hipMemcpyHostToDevice));
+  c->g.circ_V0 = V0;
+  c->g.circ_R = R;
+  c->g.circ_C = C;
   return PD_OK;
 }
 
@@ -1075,6 +1122,13 @@ pd_status pd_get_diagnostics(pd_ctx* c, pd_diag* out) {
   const int64_t qsum = N[1] + 2 * N[2] + 3 * N[3] + 4 * N[4];
   out->gamma = (ions + N[0]) > 0 ? (double)ions / (double)(ions + N[0]) : 0.0;
   out->qbar = ions > 0 ? (double)qsum / (double)ions : 0.0;
+  out->V_gap = h.V_gap;
+  out->emitted[0] = (int64_t)h.emitted[0];
+  out->emitted[1] = (int64_t)h.emitted[1];
+  // the emitted particles enter like injected ones (electrons, Cu atoms)
+  out->injected[PD_E] += out->emitted[0];
+  out->injected[PD_CU] += out->emitted[1];
+  out->charge_injected += out->emitted[0] * c->spp.Z[PD_E] + out->emitted[1] * c->spp.Z[PD_CU];
   return PD_OK;
 }
 
@@ -1100,7 +1154,7 @@ pd_status pd_get_count(pd_ctx* c, int64_t* n) {
   for (int k = 0; k < 3 * kNS; ++k) a += (int64_t)h.absorbed[k];
   int64_t inj = 0;
   for (int k = 0; k < kNS; ++k) inj += c->injected[k];
-  *n = inj + (int64_t)h.created - a;
+  *n = inj + (int64_t)h.emitted[0] + (int64_t)h.emitted[1] + (int64_t)h.created - a;
   return PD_OK;
 }
 
@@ -1193,13 +1247,17 @@ pd_status pd_poisson(pd_ctx* c, const int64_t* Q, double* phi, int32_t* iters, d
 // with its read position; the host-side counters; the solver's scalars; the
 // magic again.
 static const char kSaveMagic[8] = {'P', 'D', 'S', 'T', 'A', 'T', 'E', '1'};
-constexpr uint32_t kSaveVersion = 2;
+constexpr uint32_t kSaveVersion = 3;
 
 struct SaveHead {
   char magic[8];
   uint32_t version, sz_domain, sz_state, sz_mgscal;
   pd_domain dom;
   int32_t precision, poisson, enable_di, deposit_off, collisions_off, heavy_every;
+};
+
+struct SaveBoundary {
+  double em_beta, em_rtip, em_phi, em_ratio, em_T, circ_V0, circ_R, circ_C;
 };
 
 struct SaveHost {
@@ -1242,6 +1300,9 @@ pd_status pd_save(pd_ctx* c, const char* path) {
   h.collisions_off = c->opts.collisions_off;
   h.heavy_every = c->g.heavy_every;
   put(&h, sizeof h);
+  const SaveBoundary sb{c->g.em_beta, c->g.em_rtip, c->g.em_phi, c->g.em_ratio,
+                        c->g.em_T,    c->g.circ_V0, c->g.circ_R, c->g.circ_C};
+  put(&sb, sizeof sb);
   put(c->spp.Z, sizeof c->spp.Z);
   put(c->spp.m, sizeof c->spp.m);
   for (int k = 0; k < kNC; ++k) {
@@ -1349,6 +1410,8 @@ pd_status pd_load(pd_ctx* c, const char* path) {
       h.enable_di != c->opts.enable_di || h.deposit_off != c->opts.deposit_off ||
       h.collisions_off != c->opts.collisions_off || h.heavy_every < 1 || h.heavy_every > 1000)
     return set_err(c, PD_EINVAL, "%s: domain or options differ from the context's", path);
+  SaveBoundary sb{};
+  get(&sb, sizeof sb);
   int32_t Z[kNS];
   double m[kNS];
   get(Z, sizeof Z);
@@ -1425,6 +1488,13 @@ pd_status pd_load(pd_ctx* c, const char* path) {
   pd_status s = pd_set_species(c, kNS, Z, m);
   if (s) return s;
   if ((s = pd_set_heavy_subcycle(c, h.heavy_every))) return s;
+  if ((s = pd_set_emission(c, sb.em_beta, sb.em_rtip, sb.em_phi, sb.em_ratio, sb.em_T))) return s;
+  if (sb.circ_C > 0.0 && c->mg_on)
+    return set_err(c, PD_EINVAL, "%s: a circuit state for an iterative Poisson solve", path);
+  // (the saved device counters below carry the circuit's anode charge)
+  c->g.circ_V0 = sb.circ_V0;
+  c->g.circ_R = sb.circ_R;
+  c->g.circ_C = sb.circ_C;
   for (int k = 0; k < kNC; ++k)
     if (xset[k] && (s = pd_set_cross_section(c, k, xthr[k], xn[k], xdsq[k], xsig[k]))) return s;
   if (sn > 0) {

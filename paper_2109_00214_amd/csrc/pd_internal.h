@@ -27,6 +27,35 @@ __host__ __device__ inline uint32_t product_of(int ch, uint32_t sp) {
   return ch == 1 ? 2u : ch == 2 ? 4u : ch == 3 ? 3u : ch == 4 ? 6u : ch == 5 ? 7u : sp;
 }
 
+// Philox4x32-10 (Salmon et al., SC'11)
+__device__ inline void philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                              uint32_t k1, uint32_t out[4]) {
+#pragma unroll
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+  }
+  out[0] = c0;
+  out[1] = c1;
+  out[2] = c2;
+  out[3] = c3;
+}
+
+// uniform in [0,1): the top 53 bits of (hi:lo) times 2^-53
+__device__ inline double u53(uint32_t hi, uint32_t lo) {
+  const uint64_t b = (((uint64_t)hi << 32) | (uint64_t)lo) >> 11;
+  return (double)b * 0x1p-53;
+}
+
 // Device-resident counters: every launch reads the particle counts from
 // here, so a step needs no host round trip and can be replayed as a graph.
 struct DevState {
@@ -45,6 +74,17 @@ struct DevState {
   unsigned long long created;
   unsigned long long pushed;   // sum over steps of the particles pushed
   unsigned long long absorbed[3 * kNS];
+  // boundary physics: the gap voltage the next Poisson solve uses, the
+  // emission's carried fractions (electrons, atoms) and this step's emitted
+  // counts (written by the injection launch for the push's counter roll),
+  // cumulative emitted counts, and sum Z absorbed at the anode at the last
+  // circuit update
+  double V_gap;
+  double em_acc[2];
+  double em_acc_next[2];
+  uint32_t em_now[2];
+  unsigned long long emitted[2];
+  long long circ_zanode;
 };
 
 // Particle store in three arrays; T = double in the FP64 deterministic form,
@@ -96,6 +136,14 @@ struct Grid {
   double dr, dz, R, L, V, dt;
   int heavy_every;    // heavy species advance every heavy_every steps (1: every step)
   double dt_heavy;    // their step, heavy_every * dt
+  double W;           // particles per super-particle
+  // cathode emission (em_beta == 0: off): field enhancement, tip radius,
+  // work function (eV), atoms per emitted electron, their temperature, mass
+  double em_beta, em_rtip, em_phi, em_ratio, em_T, em_mass;
+  // external circuit (circ_C == 0: off): source, resistance, capacitance
+  double circ_V0, circ_R, circ_C;
+  const double* Vdev; // the gap voltage on the device when the circuit is on, else NULL
+  uint32_t seed_lo, seed_hi;  // Philox key (the emission's draws)
 };
 
 struct SpeciesParams {
@@ -420,8 +468,8 @@ void field(const Grid& g, FieldWork& fw, hipStream_t s);
 // the field, the same launch appending this step's scheduled particles to P
 // (after alive + created)
 template <typename T>
-void field_and_inject(const Grid& g, FieldWork& fw, const PartsT<T>& P, const DevState* st,
-                      const Schedule& sc, int64_t cap, hipStream_t s);
+void field_and_inject(const Grid& g, FieldWork& fw, const PartsT<T>& P, DevState* st,
+                      const SpeciesParams& spp, const Schedule& sc, int64_t cap, hipStream_t s);
 // gather + push into f.S; its first thread rolls the step counters (the
 // injection above included)
 template <typename T>

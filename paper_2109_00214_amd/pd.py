@@ -21,6 +21,7 @@ PD_POISSON_DIRECT64, PD_POISSON_MGPCG, PD_POISSON_LEARNED, PD_POISSON_SPECTRAL =
 TIMER_NAMES = ("radix", "permute", "offsets", "collide", "deposit", "poisson", "field", "push",
                "inject")
 EXPORTED = ("pd_create", "pd_set_species", "pd_set_cross_section", "pd_set_heavy_subcycle",
+            "pd_set_emission", "pd_set_circuit",
             "pd_inject",
             "pd_schedule_injection", "pd_step", "pd_synchronize", "pd_get_diagnostics",
             "pd_get_spectrum", "pd_get_count", "pd_get_particles", "pd_get_field",
@@ -64,7 +65,8 @@ class pd_diag(C.Structure):
                 ("particle_steps", C.c_int64), ("poisson_rel_res", C.c_double),
                 ("poisson_solves", C.c_int64), ("poisson_iters", C.c_int64),
                 ("poisson_refinements", C.c_int64), ("poisson_fallbacks", C.c_int64),
-                ("poisson_seconds", C.c_double)]
+                ("poisson_seconds", C.c_double), ("V_gap", C.c_double),
+                ("emitted", C.c_int64 * 2)]
 
 
 _lib = None
@@ -95,6 +97,8 @@ def load_library(path=LIB_PATH):
     lib.pd_poisson_noalloc.argtypes = [P, P, P, P]
     lib.pd_save.argtypes = [P, C.c_char_p]
     lib.pd_set_heavy_subcycle.argtypes = [P, C.c_int32]
+    lib.pd_set_emission.argtypes = [P] + [C.c_double] * 5
+    lib.pd_set_circuit.argtypes = [P] + [C.c_double] * 3
     lib.pd_load.argtypes = [P, C.c_char_p]
     lib.pd_get_timing.argtypes = [P, P, C.POINTER(C.c_int64), C.c_int]
     lib.pd_set_timing.argtypes = [P, C.c_int]
@@ -252,6 +256,14 @@ def pd_poisson_noalloc(ctx, q_dev, phi_dev, stream=None):
 
 def pd_set_heavy_subcycle(ctx, every):
     _check(ctx, load_library().pd_set_heavy_subcycle(ctx, int(every)))
+
+
+def pd_set_emission(ctx, beta, r_tip, phi_w, neutral_ratio, T):
+    _check(ctx, load_library().pd_set_emission(ctx, beta, r_tip, phi_w, neutral_ratio, T))
+
+
+def pd_set_circuit(ctx, V0, R, C_farad):
+    _check(ctx, load_library().pd_set_circuit(ctx, V0, R, C_farad))
 
 
 def pd_save(ctx, path):
@@ -420,6 +432,12 @@ class Simulation:
 
     def set_heavy_subcycle(self, every):
         pd_set_heavy_subcycle(self.h, every)
+
+    def set_emission(self, beta, r_tip, phi_w, neutral_ratio, T):
+        pd_set_emission(self.h, beta, r_tip, phi_w, neutral_ratio, T)
+
+    def set_circuit(self, V0, R, C_farad):
+        pd_set_circuit(self.h, V0, R, C_farad)
 
     def save(self, path):
         pd_save(self.h, path)
