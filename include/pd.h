@@ -219,6 +219,15 @@ pd_status pd_set_emission(pd_ctx* ctx, double beta, double r_tip, double phi_w,
  * non-finite), PD_ESTATE (iterative solver, ensemble member).          */
 pd_status pd_set_circuit(pd_ctx* ctx, double V0, double R, double C);
 
+/* The last stage of a double ionization (Sec. 2.2, Eq. 15) by the literal
+ * construction of Eqs. 16-20 (on != 0): v5 = R^-1(theta, phi) R^-1(chi, psi)
+ * R(theta, phi) (cos(chi) v3) with the rotation matrix of Eq. 20, theta and
+ * phi the polar angles of v3, cos(chi) uniform on [0, 1) and psi on
+ * [0, 2 pi); v6 = v3 - v5.  The default (on = 0) is the equivalent projection
+ * form v5 = (v3 . n) n with n uniform on the sphere, which needs no
+ * trigonometric function.  Errors: PD_ESTATE (ensemble member).        */
+pd_status pd_set_split_literal(pd_ctx* ctx, int32_t on);
+
 /* Append n particles now: positions r, z (0 <= r < R, 0 <= z < L),
  * velocities vr, vt, vz at the half step before their first push
  * (leapfrog), species sp[n].  They receive ids next_id, next_id+1, ...

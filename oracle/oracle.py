@@ -71,6 +71,7 @@ def load_oracle(path):
     lib.or_set_heavy_subcycle.argtypes = [P, C.c_int]
     lib.or_set_emission.argtypes = [P] + [C.c_double] * 5
     lib.or_set_circuit.argtypes = [P] + [C.c_double] * 3
+    lib.or_set_split_literal.argtypes = [P, C.c_int]
     for nm in ("sort", "collide", "deposit", "poisson", "field", "push",
                "compact_inject", "end"):
         getattr(lib, "or_stage_" + nm).argtypes = [P]
@@ -170,6 +171,9 @@ class Oracle:
 
     def set_circuit(self, V0, R, C):
         self._chk(self.lib.or_set_circuit(self.h, V0, R, C))
+
+    def set_split_literal(self, on):
+        self._chk(self.lib.or_set_split_literal(self.h, 1 if on else 0))
 
     def step(self, nsteps=1):
         self._chk(self.lib.or_step(self.h, nsteps))

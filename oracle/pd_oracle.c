@@ -51,6 +51,7 @@ struct or_sim {
   uint64_t seed;
   int enable_di, deposit_off, collisions_off;
   int heavy_every;  /* heavy particles advance every heavy_every steps (1: every step) */
+  int split_literal; /* 1: the double ionization's last stage by the literal Eqs. 16-20 */
   /* cathode emission (Sec. 2.3): off while em_beta == 0 */
   double em_beta, em_rtip, em_phi, em_ratio, em_T;
   double em_acc_e, em_acc_n; /* fractional super-particles carried to the next step */
@@ -673,10 +674,21 @@ void or_stage_collide(or_sim* s) {
     s->n += 1; s->next_id += 1; s->created += 1;
     if (ch == OR_DI) {
       /* stage 4: e3 splits into two orthogonal edges of the rectangle
-       * whose diagonal is v3: v5 = (v3.n)n stays, v6 = v3 - v5 is new  */
-      or_isotropic(s, s->id[p], 4, nh);
-      double d = ((e1[0] * nh[0]) + (e1[1] * nh[1])) + (e1[2] * nh[2]);
-      double v5[3] = {d * nh[0], d * nh[1], d * nh[2]};
+       * whose diagonal is v3: v5 = (v3.n)n stays, v6 = v3 - v5 is new;
+       * or, literally (Eqs. 16-20), v5 = cos(chi) |v3| turned by (chi, psi)
+       * about v3 with cos(chi) ~ U[0,1), psi ~ U[0,2pi) (purpose 4, draw 0) */
+      double v5[3];
+      if (s->split_literal) {
+        uint32_t w[4];
+        draw4(s, s->id[p], 4, 0, w);
+        double chi = acos(u53(w[0], w[1]));
+        double psi = (2.0 * PI_D) * u53(w[2], w[3]);
+        or_split_literal(e1, chi, psi, v5);
+      } else {
+        or_isotropic(s, s->id[p], 4, nh);
+        double d = ((e1[0] * nh[0]) + (e1[1] * nh[1])) + (e1[2] * nh[2]);
+        v5[0] = d * nh[0]; v5[1] = d * nh[1]; v5[2] = d * nh[2];
+      }
       double v6[3] = {e1[0] - v5[0], e1[1] - v5[1], e1[2] - v5[2]};
       e1[0] = v5[0]; e1[1] = v5[1]; e1[2] = v5[2];
       q = s->n;
@@ -871,6 +883,11 @@ void or_stage_field(or_sim* s) {
  * pushed every step with dt, the heavy species only on the steps whose
  * counter is a multiple of K, with the step K dt, and they stay where they
  * are in between (collisions still change their velocity and label).      */
+int or_set_split_literal(or_sim* s, int on) {
+  s->split_literal = on ? 1 : 0;
+  return 0;
+}
+
 int or_set_heavy_subcycle(or_sim* s, int every) {
   if (every < 1 || every > 1000) return fail("or_set_heavy_subcycle: every must be in 1..1000");
   s->heavy_every = every;

@@ -84,6 +84,9 @@ int or_set_heavy_subcycle(or_sim* s, int every);
 int or_set_emission(or_sim* s, double beta, double r_tip, double phi_w, double neutral_ratio,
                     double T);
 int or_set_circuit(or_sim* s, double V0, double R, double C);
+/* the double ionization's last stage by the literal construction of Eqs.
+ * 16-20 (cos chi ~ U[0,1), psi ~ U[0,2pi)) instead of the projection form */
+int or_set_split_literal(or_sim* s, int on);
 
 /* stage-level entry points (a full step is these in this order) */
 void or_stage_sort(or_sim* s);

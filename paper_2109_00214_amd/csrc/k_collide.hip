@@ -65,6 +65,44 @@ __device__ inline void isotropic(const CollideParams& cp, uint32_t id, uint32_t 
   n[2] = 1.0;
 }
 
+// The literal construction of Eqs. 16-20 for the last stage of a double
+// ionization: v5 = R^-1(theta, phi) R^-1(chi, psi) R(theta, phi) (cos(chi) v),
+// theta and phi the polar angles of v (phi = 0 on the z axis), with the
+// rotation matrix of Eq. 20; every product and sum as written, in order.
+__device__ inline void rotation(double theta, double phi, double Rm[9]) {
+  const double ct = cos(theta), st = sin(theta), cf = cos(phi), sf = sin(phi);
+  Rm[0] = ct * cf;
+  Rm[1] = ct * sf;
+  Rm[2] = -st;
+  Rm[3] = -sf;
+  Rm[4] = cf;
+  Rm[5] = 0.0;
+  Rm[6] = st * cf;
+  Rm[7] = st * sf;
+  Rm[8] = ct;
+}
+
+__device__ inline void split_literal(const double v[3], double chi, double psi, double v5[3]) {
+  const double vm = sqrt(((v[0] * v[0]) + (v[1] * v[1])) + (v[2] * v[2]));
+  const double theta = (vm > 0.0) ? acos(v[2] / vm) : 0.0;
+  const double vp = sqrt((v[0] * v[0]) + (v[1] * v[1]));
+  const double phi = (vp > 0.0) ? atan2(v[1], v[0]) : 0.0;
+  const double a = cos(chi);
+  const double sv[3] = {a * v[0], a * v[1], a * v[2]};
+  double Rt[9], Rc[9], t1[3], t2[3];
+  rotation(theta, phi, Rt);
+  rotation(chi, psi, Rc);
+#pragma unroll
+  for (int k = 0; k < 3; ++k)  // Eq. 17: into the local frame
+    t1[k] = ((Rt[3 * k] * sv[0]) + (Rt[3 * k + 1] * sv[1])) + (Rt[3 * k + 2] * sv[2]);
+#pragma unroll
+  for (int k = 0; k < 3; ++k)  // Eq. 18: scatter (the inverse is the transpose)
+    t2[k] = ((Rc[k] * t1[0]) + (Rc[3 + k] * t1[1])) + (Rc[6 + k] * t1[2]);
+#pragma unroll
+  for (int k = 0; k < 3; ++k)  // Eq. 19: back to the laboratory frame
+    v5[k] = ((Rt[k] * t2[0]) + (Rt[3 + k] * t2[1])) + (Rt[6 + k] * t2[2]);
+}
+
 // binary collision, Eqs. 5-6
 __device__ inline void binary(double v1[3], double v2[3], double two_dE_mr, double f1, double f2,
                               const double n[3]) {
@@ -424,9 +462,21 @@ __global__ void __launch_bounds__(256) k_apply(Flow<T> f, const uint32_t* off, D
       if (ch == 2) {
         // stage 4 (Eq. 15): e3 splits into the two orthogonal edges of the
         // rectangle whose diagonal is v3
-        isotropic(cp, id, step, 4u, nh);
-        const double d = ((e1[0] * nh[0]) + (e1[1] * nh[1])) + (e1[2] * nh[2]);
-        const double v5[3] = {d * nh[0], d * nh[1], d * nh[2]};
+        double v5[3];
+        if (cp.split_literal) {
+          // cos(chi) ~ U[0,1), psi ~ U[0,2 pi): purpose 4, draw 0
+          uint32_t w4[4];
+          philox(id, 0u, step, 4u << 24, cp.seed_lo, cp.seed_hi, w4);
+          const double chi = acos(u53(w4[0], w4[1]));
+          const double psi = (2.0 * kPI) * u53(w4[2], w4[3]);
+          split_literal(e1, chi, psi, v5);
+        } else {
+          isotropic(cp, id, step, 4u, nh);
+          const double d = ((e1[0] * nh[0]) + (e1[1] * nh[1])) + (e1[2] * nh[2]);
+          v5[0] = d * nh[0];
+          v5[1] = d * nh[1];
+          v5[2] = d * nh[2];
+        }
         const uint32_t s6 = slot + 1;
         S.x[s6] = P.x[pe];
         S.v[s6] = RecT<T>{(T)(e1[0] - v5[0]), (T)(e1[1] - v5[1]), (T)(e1[2] - v5[2]), nid + 1,

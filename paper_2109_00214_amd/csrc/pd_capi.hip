@@ -892,6 +892,15 @@ pd_status pd_set_emission(pd_ctx* c, double beta, double r_tip, double phi_w, do
   return PD_OK;
 }
 
+pd_status pd_set_split_literal(pd_ctx* c, int32_t on) {
+  if (!c) return PD_EINVAL;
+  if (c->in_ensemble) return set_err(c, PD_ESTATE, "the ensemble's graph holds the split");
+  pd_status s = sync(c);
+  if (s) return s;
+  c->cpar.split_literal = on ? 1 : 0;
+  return PD_OK;
+}
+
 pd_status pd_set_circuit(pd_ctx* c, double V0, double R, double C) {
   if (!c) return PD_EINVAL;
   if (c->in_ensemble) return set_err(c, PD_ESTATE, "the ensemble's graph holds the circuit");
@@ -1258,6 +1267,7 @@ struct SaveHead {
 
 struct SaveBoundary {
   double em_beta, em_rtip, em_phi, em_ratio, em_T, circ_V0, circ_R, circ_C;
+  int32_t split_literal, pad;
 };
 
 struct SaveHost {
@@ -1301,7 +1311,8 @@ pd_status pd_save(pd_ctx* c, const char* path) {
   h.heavy_every = c->g.heavy_every;
   put(&h, sizeof h);
   const SaveBoundary sb{c->g.em_beta, c->g.em_rtip, c->g.em_phi, c->g.em_ratio,
-                        c->g.em_T,    c->g.circ_V0, c->g.circ_R, c->g.circ_C};
+                        c->g.em_T,    c->g.circ_V0, c->g.circ_R, c->g.circ_C,
+                        c->cpar.split_literal, 0};
   put(&sb, sizeof sb);
   put(c->spp.Z, sizeof c->spp.Z);
   put(c->spp.m, sizeof c->spp.m);
@@ -1495,6 +1506,7 @@ pd_status pd_load(pd_ctx* c, const char* path) {
   c->g.circ_V0 = sb.circ_V0;
   c->g.circ_R = sb.circ_R;
   c->g.circ_C = sb.circ_C;
+  c->cpar.split_literal = sb.split_literal ? 1 : 0;
   for (int k = 0; k < kNC; ++k)
     if (xset[k] && (s = pd_set_cross_section(c, k, xthr[k], xn[k], xdsq[k], xsig[k]))) return s;
   if (sn > 0) {

@@ -167,6 +167,7 @@ struct CollideParams {
   int tabn[kNC];         // 0: the channel takes no part (its table is not set)
   int chain;             // the Cu2+ -> Cu3+ or Cu3+ -> Cu4+ channel takes part
   int heavy;             // a heavy-projectile channel (CEX, NN) takes part
+  int split_literal;     // the last stage of a double ionization by Eqs. 16-20
   double dt_heavy;       // their time step (the heavy step)
   const double* Vcell;   // cell volumes [nr]
 };

@@ -347,3 +347,38 @@ def test_chain_run_bookkeeping():
                             d["events"][W.SI3] + d["events"][W.SI4])
     assert d["charge_alive"] + d["charge_absorbed"] == d["charge_injected"]
     assert int(np.sum(d["count"])) == d["n_alive"] == o.count()
+
+
+def test_literal_split_run_mode():
+    """With the literal Eqs. 16-20 as the double ionization's last stage, the
+    two electrons it leaves are the edges of a rectangle whose diagonal is
+    the electron before it (v5 + v6 = v3, v5 . v6 = 0) and |v5| / |v3| =
+    cos(chi) is uniform on [0, 1)."""
+    cfg = W.config("tiny", nr=4, nz=8, weight=1e5)
+    sig = [0.0] * W.NCHANNELS
+    sig[W.DI] = 5e-19
+    tables = W.constant_tables(sig, thresholds=list(W.THRESHOLDS_EV), n=4096)
+    ratios = []
+    for trial in range(6):
+        c2 = W.config("tiny", nr=4, nz=8, weight=1e5, seed=300 + trial)
+        o = make_oracle(c2, tables=tables)
+        o.set_split_literal(True)
+        parts = _uniform_vapour(c2, 30, 0, 3, 6.0e6, trial)
+        o.inject(parts)
+        o.stage("sort")
+        n = o.count()
+        o.stage("collide")
+        a = o.particles()
+        ch, tg, wn = o.collisions(n)
+        win = np.nonzero(wn)[0]
+        # the stage-4 electron of winner k is the (2k+1)-th created particle
+        for k, p in enumerate(win):
+            q6 = n + 2 * k + 1
+            v5 = np.array([a["vr"][p], a["vt"][p], a["vz"][p]])
+            v6 = np.array([a["vr"][q6], a["vt"][q6], a["vz"][q6]])
+            v3 = v5 + v6
+            m = np.linalg.norm(v3)
+            assert abs(v5 @ v6) <= 1e-9 * m * m
+            ratios.append(np.linalg.norm(v5) / m)
+    assert len(ratios) > 200
+    assert stats.kstest(ratios, "uniform").pvalue > 1e-3
