@@ -37,7 +37,7 @@ class _Diag(C.Structure):
                 ("charge_injected", C.c_int64), ("ke_J", C.c_double * NSPECIES),
                 ("gamma", C.c_double), ("qbar", C.c_double),
                 ("spectrum", (C.c_int64 * 66) * 3), ("V_gap", C.c_double),
-                ("emitted", C.c_int64 * 2)]
+                ("emitted", C.c_int64 * 2), ("sputtered", C.c_int64)]
 
 
 _lib = None
@@ -72,6 +72,9 @@ def load_oracle(path):
     lib.or_set_emission.argtypes = [P] + [C.c_double] * 5
     lib.or_set_circuit.argtypes = [P] + [C.c_double] * 3
     lib.or_set_split_literal.argtypes = [P, C.c_int]
+    lib.or_set_sputtering.argtypes = [P, C.c_int]
+    lib.or_sputter_yield.restype = C.c_double
+    lib.or_sputter_yield.argtypes = [C.c_double]
     for nm in ("sort", "collide", "deposit", "poisson", "field", "push",
                "compact_inject", "end"):
         getattr(lib, "or_stage_" + nm).argtypes = [P]
@@ -174,6 +177,13 @@ class Oracle:
 
     def set_split_literal(self, on):
         self._chk(self.lib.or_set_split_literal(self.h, 1 if on else 0))
+
+    def set_sputtering(self, on):
+        self._chk(self.lib.or_set_sputtering(self.h, 1 if on else 0))
+
+    @staticmethod
+    def sputter_yield(E_eV):
+        return oracle_lib().or_sputter_yield(E_eV)
 
     def step(self, nsteps=1):
         self._chk(self.lib.or_step(self.h, nsteps))

@@ -59,6 +59,11 @@ struct or_sim {
   /* external circuit (Sec. 2.3): off while circ_C == 0 */
   double circ_V0, circ_R, circ_C;
   int64_t circ_zanode; /* sum of Z absorbed at the anode at the last update */
+  /* sputtering at the cathode (Sec. 2.3): off while sput_on == 0 */
+  int sput_on;
+  uint64_t* sput;      /* per cathode annulus: yields in units of 2^-32 */
+  int64_t* sput_now;   /* atoms to emit this step, per annulus */
+  int64_t sputtered;   /* cumulative */
 
   int Z[OR_NSPECIES];
   double m[OR_NSPECIES];
@@ -238,6 +243,7 @@ or_sim* or_create(int nr, int nz, double R, double L, double V, double dt,
 }
 
 void or_destroy(or_sim* s) {
+  if (s) { free(s->sput); free(s->sput_now); }
   if (!s) return;
   for (int k = 0; k < OR_NCHANNELS; ++k) free(s->xs_tab[k]);
   free(s->Vnode); free(s->Vcell); free(s->ra); free(s->rb); free(s->rc);
@@ -898,9 +904,12 @@ int or_set_heavy_subcycle(or_sim* s, int every) {
  *    in 2D3V: v += (q/m) E dt; straight move in the particle's local
  *    Cartesian frame; rotate back to the r-z plane                        */
 static void circuit_update(or_sim* s); /* boundary physics, below */
+static void sputter_yield(or_sim* s, int64_t p);
+static void sputter_take(or_sim* s);
 
 void or_stage_push(or_sim* s) {
   circuit_update(s);
+  sputter_take(s);
   const int nr = s->nr, W = nr + 1;
   const int K = s->heavy_every;
   const int heavy_now = (K <= 1) || ((s->step % K) == 0);
@@ -946,6 +955,7 @@ void or_stage_push(or_sim* s) {
       s->alive[p] = 0;
       s->absorbed[bnd][s->sp[p]] += 1;
       s->charge_absorbed += s->Z[s->sp[p]];
+      if (bnd == OR_CATHODE && s->sput_on && s->Z[s->sp[p]] > 0) sputter_yield(s, p);
     } else {
       s->alive[p] = 1;
       s->key[p] = key_of(s, rn, z, s->sp[p]);
@@ -1007,6 +1017,120 @@ static void circuit_update(or_sim* s) {
   double I = ((-(double)(za - s->circ_zanode)) * (Q_E * s->W)) / s->dt;
   s->V = s->V + ((s->dt / s->circ_C) * (((s->circ_V0 - s->V) / s->circ_R) - I));
   s->circ_zanode = za;
+}
+
+/* Sputtering (Sec. 2.3, yield of Yamamura and Tawara): an ion of the Cu
+ * family absorbed at the cathode with kinetic energy E (eV, from its velocity
+ * after the push) adds the yield Y(E) of Cu on Cu to the annulus of its
+ * nearest cathode node, i = (int)(r/dr + 1/2), in fixed point (floor of
+ * Y 2^32).  Before each push the whole atoms of every annulus are taken
+ * (integer part of its sum) and emitted at the end of the step: radius
+ * uniform in area over the annulus, on the cathode, normal to it, with an
+ * energy from the Thompson distribution E / (E + U_s)^3 truncated at 1 keV
+ * (purpose 6 draws).
+ *
+ * Y(E) = 0.042 (Q alpha* / U_s) S_n(E) / (1 + Gamma k_e eps^0.3)
+ *        (1 - sqrt(E_th / E))^s,                         E > E_th, else 0,
+ * the published fit with Z1 = Z2 = 29, M1 = M2 = 63.546 u (so alpha* and
+ * E_th take their equal-mass values, alpha* = 0.2525, E_th = 6.7 U_s), and
+ * the Cu parameters U_s = 3.49 eV, Q = 1.30, W = 0.73, s = 2.5 (stand-ins
+ * for the paper's ref. 32):
+ *   eps = 0.03255 / (Z1 Z2 sqrt(Z1^(2/3) + Z2^(2/3))) M2 / (M1 + M2) E,
+ *   S_n = 84.78 Z1 Z2 / sqrt(Z1^(2/3) + Z2^(2/3)) M1 / (M1 + M2) s_n(eps),
+ *   s_n(eps) = 0.5 ln(1 + 1.2288 eps) / (eps + 0.1728 sqrt(eps) + 0.008 eps^0.1504),
+ *   k_e = 0.079 (M1 + M2)^(3/2) / (M1^(3/2) M2^(1/2))
+ *         Z1^(2/3) Z2^(1/2) / (Z1^(2/3) + Z2^(2/3))^(3/4),
+ *   Gamma = W / (1 + (M1 / 7)^3).                                         */
+#define YT_US 3.49
+#define YT_Q 1.30
+#define YT_W 0.73
+#define YT_S 2.5
+#define YT_EMAX 1000.0
+
+double or_sputter_yield(double E) {
+  const double Z = 29.0, M = 63.546;
+  const double z23 = pow(Z, 2.0 / 3.0);
+  const double zs = z23 + z23;
+  const double eps = ((0.03255 / ((Z * Z) * sqrt(zs))) * (M / (M + M))) * E;
+  const double sn = (0.5 * log(1.0 + (1.2288 * eps))) /
+                    ((eps + (0.1728 * sqrt(eps))) + (0.008 * pow(eps, 0.1504)));
+  const double Sn = (((84.78 * (Z * Z)) / sqrt(zs)) * (M / (M + M))) * sn;
+  const double ke = ((0.079 * pow(M + M, 1.5)) / (pow(M, 1.5) * sqrt(M))) *
+                    ((z23 * sqrt(Z)) / pow(zs, 0.75));
+  const double gam = YT_W / (1.0 + pow(M / 7.0, 3.0));
+  const double alpha = (0.249 * pow(M / M, 0.56)) + (0.0035 * pow(M / M, 1.5));
+  const double Eth = 6.7 * YT_US;
+  if (!(E > Eth)) return 0.0;
+  return (((0.042 * ((YT_Q * alpha) / YT_US)) * Sn) / (1.0 + ((gam * ke) * pow(eps, 0.3)))) *
+         pow(1.0 - sqrt(Eth / E), YT_S);
+}
+
+static int ring_of(const or_sim* s, double r) {
+  int i = (int)((r / s->dr) + 0.5);
+  return i > s->nr ? s->nr : i;
+}
+
+static void sputter_yield(or_sim* s, int64_t p) {
+  const int sp = s->sp[p];
+  double v2 = ((s->vr[p] * s->vr[p]) + (s->vt[p] * s->vt[p])) + (s->vz[p] * s->vz[p]);
+  double E = ((0.5 * s->m[sp]) * v2) / Q_E;
+  double Y = or_sputter_yield(E);
+  s->sput[ring_of(s, s->r[p])] += (uint64_t)floor(Y * 4294967296.0);
+}
+
+int or_set_sputtering(or_sim* s, int on) {
+  if (on && !s->sput) {
+    s->sput = (uint64_t*)xalloc(sizeof(uint64_t) * (s->nr + 1));
+    s->sput_now = (int64_t*)xalloc(sizeof(int64_t) * (s->nr + 1));
+    memset(s->sput, 0, sizeof(uint64_t) * (s->nr + 1));
+    memset(s->sput_now, 0, sizeof(int64_t) * (s->nr + 1));
+  }
+  s->sput_on = on ? 1 : 0;
+  return 0;
+}
+
+/* before each push: the whole atoms of every annulus, taken for this step */
+static void sputter_take(or_sim* s) {
+  if (!s->sput_on) return;
+  for (int i = 0; i <= s->nr; ++i) {
+    s->sput_now[i] = (int64_t)(s->sput[i] >> 32);
+    s->sput[i] -= (uint64_t)s->sput_now[i] << 32;
+  }
+}
+
+static void sputter_emit(or_sim* s) {
+  if (!s->sput_on) return;
+  int64_t tot = 0;
+  for (int i = 0; i <= s->nr; ++i) tot += s->sput_now[i];
+  if (tot > 0) {
+    double* a = (double*)xalloc(sizeof(double) * 5 * tot);
+    uint8_t* sp = (uint8_t*)xalloc(tot);
+    const double Fmax = (YT_EMAX / (YT_EMAX + YT_US)) * (YT_EMAX / (YT_EMAX + YT_US));
+    int64_t k = 0;
+    for (int i = 0; i <= s->nr; ++i)
+      for (int64_t c = 0; c < s->sput_now[i]; ++c, ++k) {
+        uint32_t id = (uint32_t)(s->next_id + k);
+        uint32_t w[4];
+        draw4(s, id, 6, 0, w);
+        double u2 = u53(w[0], w[1]), u3 = u53(w[2], w[3]);
+        double lo = ((double)i - 0.5) * s->dr, hi = ((double)i + 0.5) * s->dr;
+        if (lo < 0.0) lo = 0.0;
+        if (hi > s->R) hi = s->R;
+        double r = sqrt((lo * lo) + (u2 * ((hi * hi) - (lo * lo))));
+        if (!(r < s->R)) r = lo; /* the outer annulus' rounding at the wall */
+        double q = sqrt(u3 * Fmax);
+        double E = (YT_US * q) / (1.0 - q);
+        a[k] = r;
+        a[tot + k] = 0.0;
+        a[2 * tot + k] = 0.0;
+        a[3 * tot + k] = 0.0;
+        a[4 * tot + k] = sqrt(((2.0 * E) * Q_E) / s->m[OR_CU]);
+        sp[k] = OR_CU;
+      }
+    append(s, tot, a, a + tot, a + 2 * tot, a + 3 * tot, a + 4 * tot, sp);
+    free(a); free(sp);
+  }
+  s->sputtered += tot;
 }
 
 static void emit(or_sim* s) {
@@ -1093,6 +1217,7 @@ void or_stage_compact_inject(or_sim* s) {
     s->sched_pos += 1;
   }
   emit(s);
+  sputter_emit(s);
 }
 
 void or_stage_end(or_sim* s) { s->step += 1; }
@@ -1197,6 +1322,7 @@ void or_get_diag(const or_sim* s, or_diag* d) {
   d->V_gap = s->V;
   d->emitted[0] = s->emitted[0];
   d->emitted[1] = s->emitted[1];
+  d->sputtered = s->sputtered;
 }
 
 /* ------------------------------------------------------------------ */

@@ -55,6 +55,7 @@ typedef struct {
   int64_t spectrum[3][66]; /* Cu2+ tags STEP, DOUBLE, INIT: 64 bins, <1 eV, >=1000 eV */
   double V_gap;            /* the gap voltage the next Poisson solve uses */
   int64_t emitted[2];      /* cumulative super-particles emitted: electrons, atoms */
+  int64_t sputtered;       /* cumulative Cu atoms sputtered from the cathode */
 } or_diag;
 
 or_sim* or_create(int nr, int nz, double R, double L, double V, double dt,
@@ -87,6 +88,10 @@ int or_set_circuit(or_sim* s, double V0, double R, double C);
 /* the double ionization's last stage by the literal construction of Eqs.
  * 16-20 (cos chi ~ U[0,1), psi ~ U[0,2pi)) instead of the projection form */
 int or_set_split_literal(or_sim* s, int on);
+/* sputtering of the cathode by the ions that reach it (Yamamura-Tawara
+ * yield of Cu on Cu), emitted the step after the impacts               */
+int or_set_sputtering(or_sim* s, int on);
+double or_sputter_yield(double E_eV);
 
 /* stage-level entry points (a full step is these in this order) */
 void or_stage_sort(or_sim* s);

@@ -151,3 +151,64 @@ def test_circuit_discharge_by_absorbed_electrons():
         assert abs(o.diag()["V_gap"] - V) <= 1e-12 * V0, (step, o.diag()["V_gap"], V)
     assert sum(per_push) > 100
     assert o.diag()["V_gap"] < V0 - 0.01
+
+
+def test_sputter_yield_threshold_and_magnitude():
+    """The Cu-on-Cu yield: zero up to the threshold 6.7 U_s = 23.383 eV, the
+    (1 - sqrt(E_th/E))^2.5 rise just above it (log-log slope 2.5), rising
+    with energy, and of the size measured for copper self-sputtering at
+    normal incidence (about 1.5-2.5 atoms per ion at 500 eV, 2-4 at 1 keV)."""
+    from oracle import Oracle
+    Eth = 6.7 * 3.49
+    assert Oracle.sputter_yield(Eth) == 0.0 and Oracle.sputter_yield(10.0) == 0.0
+    assert Oracle.sputter_yield(Eth * (1 + 1e-9)) > 0.0
+    f = lambda E: 1 - np.sqrt(Eth / E)
+    E1, E2 = Eth * 1.0001, Eth * 1.0002
+    slope = np.log(Oracle.sputter_yield(E2) / Oracle.sputter_yield(E1)) / np.log(f(E2) / f(E1))
+    assert abs(slope - 2.5) < 0.01
+    ys = [Oracle.sputter_yield(E) for E in (30, 50, 100, 300, 1000, 3000)]
+    assert all(b > a for a, b in zip(ys, ys[1:]))
+    assert 1.5 < Oracle.sputter_yield(500.0) < 2.5
+    assert 2.0 < Oracle.sputter_yield(1000.0) < 4.0
+
+
+def test_sputtered_atoms_follow_the_impacts():
+    """Cu+ ions driven into the cathode at known energies and radii: the
+    step after the impacts, each annulus emits the whole atoms of the summed
+    yields of the ions that hit nearest to its node, on the cathode, moving
+    off it along z with Thompson energies E/(E + U_s)^3 (truncated at 1 keV);
+    the fractions wait for the next impacts."""
+    from oracle import Oracle
+    cfg = W.config("tiny", V=0.0)
+    dr = cfg.R / cfg.nr
+    o = make_oracle(cfg, deposit_off=True, collisions_off=True)
+    o.set_sputtering(True)
+    rng = np.random.default_rng(7)
+    n = 3000
+    rings = rng.integers(0, 6, n)
+    r = np.clip((rings + rng.uniform(-0.45, 0.45, n)) * dr, 0.0, None)
+    E = rng.uniform(50.0, 900.0, n)
+    vz = -np.sqrt(2 * E * W.QE / W.M_CU)
+    z = rng.uniform(0.0, 0.5, n) * (-vz) * cfg.dt  # every ion crosses z = 0 in the first push
+    o.inject({"r": r, "z": z, "vr": np.zeros(n), "vt": np.zeros(n), "vz": vz,
+              "sp": np.full(n, W.CU1, np.uint8)})
+    o.step(1)
+    assert o.count() == 0 and o.diag()["absorbed"][0][W.CU1] == n
+    o.step(1)  # the atoms of the first impacts appear at the end of this step
+    p = o.particles()
+    fp = np.floor(np.array([Oracle.sputter_yield(e) for e in E]) * 2.0 ** 32).astype(np.uint64)
+    ring_of = np.minimum(np.floor(r / dr + 0.5).astype(int), cfg.nr)
+    expect = np.zeros(cfg.nr + 1, np.int64)
+    for i in range(cfg.nr + 1):
+        expect[i] = int(fp[ring_of == i].sum(dtype=np.uint64)) >> 32
+    got = np.bincount(np.minimum(np.floor(p["r"] / dr + 0.5).astype(int), cfg.nr),
+                      minlength=cfg.nr + 1)
+    assert expect.sum() > 1000
+    assert np.array_equal(got, expect)
+    assert o.diag()["sputtered"] == expect.sum()
+    assert np.all(p["sp"] == W.CU) and np.all(p["z"] == 0.0) and np.all(p["vz"] > 0.0)
+    Es = 0.5 * W.M_CU * p["vz"] ** 2 / W.QE
+    Us, Emax = 3.49, 1000.0
+    cdf = lambda e: (e / (e + Us)) ** 2 / (Emax / (Emax + Us)) ** 2
+    assert np.all(Es <= Emax * (1 + 1e-12))
+    assert stats.kstest(Es, cdf).pvalue > 1e-3
