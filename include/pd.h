@@ -159,6 +159,8 @@ typedef struct {
   int64_t emitted[2];            /* cumulative super-particles emitted by the
                                   * cathode: electrons, Cu atoms (also counted
                                   * in injected) */
+  int64_t sputtered;             /* cumulative Cu atoms sputtered from the
+                                  * cathode (also counted in injected) */
 } pd_diag;
 
 /* Create a context on the current HIP device.  dom and opts are copied.
@@ -227,6 +229,20 @@ pd_status pd_set_circuit(pd_ctx* ctx, double V0, double R, double C);
  * form v5 = (v3 . n) n with n uniform on the sphere, which needs no
  * trigonometric function.  Errors: PD_ESTATE (ensemble member).        */
 pd_status pd_set_split_literal(pd_ctx* ctx, int32_t on);
+
+/* Cathode sputtering (Sec. 2.3, yield of Yamamura and Tawara): an ion
+ * absorbed at the cathode with kinetic energy E (eV, from its velocity after
+ * the push) adds Y(E), the published fit for Cu on Cu at normal incidence
+ * with the Cu parameters U_s = 3.49 eV, Q = 1.30, W = 0.73, s = 2.5
+ * (threshold 6.7 U_s), to the annulus of its nearest cathode node, in fixed
+ * point (floor of Y 2^32, so the sums are exact and order-free); the next
+ * step emits the whole atoms of every annulus at radii uniform in area over
+ * it, on the cathode, moving normal to it with an energy from the Thompson
+ * distribution E / (E + U_s)^3 truncated at 1 keV, after the emitted
+ * particles, and carries the fractions.  on = 0 (the default) switches it
+ * off.  Errors: PD_EINVAL (more than 4096 cathode annuli), PD_ESTATE
+ * (ensemble member).                                                   */
+pd_status pd_set_sputtering(pd_ctx* ctx, int32_t on);
 
 /* Append n particles now: positions r, z (0 <= r < R, 0 <= z < L),
  * velocities vr, vt, vz at the half step before their first push

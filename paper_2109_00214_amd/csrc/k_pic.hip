@@ -116,12 +116,13 @@ __device__ inline void count_codes(int code, unsigned long long* ctr) {
 struct InjectPlan {
   uint32_t pos, cnt, base, id0;
   uint32_t ne, nn;  // emitted electrons and atoms, after the cnt scheduled ones
+  uint32_t ns;      // sputtered atoms, after those
   int64_t a;        // first schedule entry
   bool have, fits;
 };
 
 __device__ inline InjectPlan inject_plan(const DevState* st, const Schedule& sc, uint32_t cap,
-                                         uint32_t ne, uint32_t nn) {
+                                         uint32_t ne, uint32_t nn, uint32_t ns) {
   InjectPlan ip;
   ip.pos = st->sched_pos;
   ip.have = sc.off && ip.pos < st->sched_n;
@@ -129,11 +130,12 @@ __device__ inline InjectPlan inject_plan(const DevState* st, const Schedule& sc,
   ip.cnt = ip.have ? (uint32_t)(sc.off[ip.pos + 1] - ip.a) : 0u;
   ip.ne = ne;
   ip.nn = nn;
+  ip.ns = ns;
   ip.base = st->n_alive + st->n_created;
   ip.id0 = st->next_id + st->n_created;
-  const uint64_t tot = (uint64_t)ip.cnt + ne + nn;
+  const uint64_t tot = (uint64_t)ip.cnt + ne + nn + ns;
   ip.fits = (uint64_t)ip.base + tot <= cap && (uint64_t)ip.id0 + tot <= 0xFFFFFFFFull;
-  if (!ip.fits) ip.cnt = ip.ne = ip.nn = 0;
+  if (!ip.fits) ip.cnt = ip.ne = ip.nn = ip.ns = 0;
   return ip;
 }
 
@@ -147,6 +149,38 @@ constexpr double kFnA = 1.541434e-6;  // A eV V^-2
 constexpr double kFnB = 6.830890e9;   // eV^(-3/2) V m^-1
 constexpr double kKB = 1.380649e-23;  // J/K
 constexpr int kMaxRings = 1024;
+
+// Sputtering (paper Sec. 2.3, yield of Yamamura and Tawara): the published
+// fit for Cu on Cu at normal incidence (Z1 = Z2 = 29, M1 = M2 = 63.546 u,
+// so alpha* and E_th take their equal-mass values) with the Cu parameters
+// U_s = 3.49 eV, Q = 1.30, W = 0.73, s = 2.5:
+//   Y(E) = 0.042 (Q alpha* / U_s) S_n(E) / (1 + Gamma k_e eps^0.3)
+//          (1 - sqrt(E_th / E))^s for E > E_th = 6.7 U_s, else 0, with
+//   eps = 0.03255 / (Z1 Z2 sqrt(Z1^(2/3) + Z2^(2/3))) M2 / (M1 + M2) E,
+//   S_n = 84.78 Z1 Z2 / sqrt(Z1^(2/3) + Z2^(2/3)) M1 / (M1 + M2) s_n(eps),
+//   s_n(eps) = 0.5 ln(1 + 1.2288 eps) / (eps + 0.1728 sqrt(eps) + 0.008 eps^0.1504),
+//   k_e = 0.079 (M1 + M2)^(3/2) / (M1^(3/2) M2^(1/2)) Z1^(2/3) Z2^(1/2) / (Z1^(2/3) + Z2^(2/3))^(3/4),
+//   Gamma = W / (1 + (M1 / 7)^3).
+constexpr double kYtUs = 3.49, kYtQ = 1.30, kYtW = 0.73, kYtS = 2.5, kYtEmax = 1000.0;
+constexpr int kMaxSputRings = 4096;
+
+__device__ inline double sputter_yield(double E) {
+  const double Z = 29.0, M = 63.546;
+  const double z23 = pow(Z, 2.0 / 3.0);
+  const double zs = z23 + z23;
+  const double eps = ((0.03255 / ((Z * Z) * sqrt(zs))) * (M / (M + M))) * E;
+  const double sn = (0.5 * log(1.0 + (1.2288 * eps))) /
+                    ((eps + (0.1728 * sqrt(eps))) + (0.008 * pow(eps, 0.1504)));
+  const double Sn = (((84.78 * (Z * Z)) / sqrt(zs)) * (M / (M + M))) * sn;
+  const double ke = ((0.079 * pow(M + M, 1.5)) / (pow(M, 1.5) * sqrt(M))) *
+                    ((z23 * sqrt(Z)) / pow(zs, 0.75));
+  const double gam = kYtW / (1.0 + pow(M / 7.0, 3.0));
+  const double alpha = (0.249 * pow(M / M, 0.56)) + (0.0035 * pow(M / M, 1.5));
+  const double Eth = 6.7 * kYtUs;
+  if (!(E > Eth)) return 0.0;
+  return (((0.042 * ((kYtQ * alpha) / kYtUs)) * Sn) / (1.0 + ((gam * ke) * pow(eps, 0.3)))) *
+         pow(1.0 - sqrt(Eth / E), kYtS);
+}
 
 __device__ inline void ring_bounds(const Grid& g, int i, double& lo, double& hi) {
   lo = ((double)i - 0.5) * g.dr;
@@ -195,14 +229,42 @@ __device__ inline void emission_counts(const DevState* st, const Grid& g, double
 template <typename T>
 __device__ inline void inject_records(const PartsT<T>& P, const DevState* st, const Grid& g,
                                       const Schedule& sc, const InjectPlan& ip, const double* cum,
-                                      int nring, double I, uint32_t blk, uint32_t nblk) {
-  const uint32_t tot = ip.cnt + ip.ne + ip.nn;
+                                      int nring, double I, const uint32_t* spre, int nsr,
+                                      uint32_t blk, uint32_t nblk) {
+  const uint32_t tot = ip.cnt + ip.ne + ip.nn + ip.ns;
+  const uint32_t q_sput = ip.cnt + ip.ne + ip.nn;
   for (uint32_t q = blk * blockDim.x + threadIdx.x; q < tot; q += nblk * blockDim.x) {
     const uint32_t d = ip.base + q, id = ip.id0 + q;
     T r, z;
     RecT<T> v;
     uint32_t s;
-    if (q < ip.cnt) {
+    if (q >= q_sput) {
+      // sputtered: the annulus whose whole atoms this is (spre: inclusive
+      // running counts), radius uniform in area in it, on the cathode,
+      // normal to it with a Thompson energy truncated at kYtEmax (purpose 6)
+      const uint32_t k = q - q_sput;
+      int lo_i = 0, hi_i = nsr - 1;  // first annulus with k < spre[i]
+      while (lo_i < hi_i) {
+        const int mid = (lo_i + hi_i) >> 1;
+        if (k < spre[mid]) hi_i = mid;
+        else lo_i = mid + 1;
+      }
+      uint32_t w[4];
+      philox(id, 0u, st->step, 6u << 24, g.seed_lo, g.seed_hi, w);
+      const double u2 = u53(w[0], w[1]), u3 = u53(w[2], w[3]);
+      double lo = ((double)lo_i - 0.5) * g.dr, hi = ((double)lo_i + 0.5) * g.dr;
+      if (lo < 0.0) lo = 0.0;
+      if (hi > g.R) hi = g.R;
+      double rr = sqrt((lo * lo) + (u2 * ((hi * hi) - (lo * lo))));
+      if (!(rr < g.R)) rr = lo;
+      const double Fmax = (kYtEmax / (kYtEmax + kYtUs)) * (kYtEmax / (kYtEmax + kYtUs));
+      const double qq = sqrt(u3 * Fmax);
+      const double E = (kYtUs * qq) / (1.0 - qq);
+      r = (T)rr;
+      z = (T)0.0;
+      s = 1u;
+      v = RecT<T>{(T)0.0, (T)0.0, (T)sqrt(((2.0 * E) * kQE) / g.em_mass), id, s};
+    } else if (q < ip.cnt) {
       const int64_t src = ip.a + q;
       r = (T)sc.r[src];
       z = (T)sc.z[src];
@@ -255,12 +317,13 @@ __device__ inline void inject_records(const PartsT<T>& P, const DevState* st, co
 __device__ inline void roll_counters(DevState* st, const InjectPlan& ip) {
   if (!ip.fits) atomicOr(&st->err, 1u);
   if (ip.have) st->sched_pos = ip.pos + 1;
-  const uint32_t tot = ip.cnt + ip.ne + ip.nn;
+  const uint32_t tot = ip.cnt + ip.ne + ip.nn + ip.ns;
   if (ip.fits) {
     st->em_acc[0] = st->em_acc_next[0];
     st->em_acc[1] = st->em_acc_next[1];
     st->emitted[0] += ip.ne;
     st->emitted[1] += ip.nn;
+    st->sputtered += ip.ns;
   }
   st->created += st->n_created;
   st->pushed += st->n_alive + st->n_created;
@@ -293,6 +356,8 @@ __global__ void __launch_bounds__(256) k_field_inject(const double* phi, int nr,
   }
   __shared__ double cum[kMaxRings];
   __shared__ double Ish;
+  __shared__ uint32_t spre[kMaxSputRings];
+  __shared__ uint32_t wsum[4];
   uint32_t n[2] = {0u, 0u};
   double acc[2] = {0.0, 0.0};
   double I = 0.0;
@@ -302,15 +367,35 @@ __global__ void __launch_bounds__(256) k_field_inject(const double* phi, int nr,
     I = Ish;
     emission_counts(st, g, I, n, acc);
   }
-  const InjectPlan ip = inject_plan(st, sc, cap, n[0], n[1]);
-  if (blockIdx.x == nf && threadIdx.x == 0) {
-    st->em_now[0] = n[0];
-    st->em_now[1] = n[1];
-    st->em_acc_next[0] = acc[0];
-    st->em_acc_next[1] = acc[1];
-    if (g.circ_C > 0.0) circuit_update(st, g, spp);
+  // sputtered atoms: the whole atoms of every annulus, inclusive running
+  // counts in LDS (a block scan over chunks of 256 annuli)
+  const int nsr = g.sput_on ? g.nr + 1 : 0;
+  uint32_t ns = 0;
+  for (int i0 = 0; i0 < nsr; i0 += 256) {
+    const int i = i0 + (int)threadIdx.x;
+    const uint32_t c = (i < nsr) ? (uint32_t)(g.sput[i] >> 32) : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_scan256(c, &tot, wsum);
+    if (i < nsr) spre[i] = ns + ex + c;
+    ns += tot;
   }
-  inject_records<T>(P, st, g, sc, ip, cum, nring, I, blockIdx.x - nf, gridDim.x - nf);
+  __syncthreads();
+  const InjectPlan ip = inject_plan(st, sc, cap, n[0], n[1], ns);
+  if (blockIdx.x == nf) {
+    if (threadIdx.x == 0) {
+      st->em_now[0] = n[0];
+      st->em_now[1] = n[1];
+      st->em_now[2] = ns;
+      st->em_acc_next[0] = acc[0];
+      st->em_acc_next[1] = acc[1];
+      if (g.circ_C > 0.0) circuit_update(st, g, spp);
+    }
+    // the atoms taken from every annulus (the push subtracts them; none when
+    // the injection does not fit)
+    for (int i = (int)threadIdx.x; i < nsr; i += (int)blockDim.x)
+      g.sput_take[i] = ip.fits ? spre[i] - (i > 0 ? spre[i - 1] : 0u) : 0u;
+  }
+  inject_records<T>(P, st, g, sc, ip, cum, nring, I, spre, nsr, blockIdx.x - nf, gridDim.x - nf);
 }
 
 // emission annuli: those with part of their annulus inside the tip (0: off)
@@ -353,7 +438,12 @@ __global__ void __launch_bounds__(256) k_push(Flow<T> f, DevState* st, Grid g, S
   const uint32_t n = n_alive + st->n_created;
   const bool heavy_now = st->heavy_now != 0u;
   if (blockIdx.x == 0 && threadIdx.x == 0)
-    roll_counters(st, inject_plan(st, sc, cap, st->em_now[0], st->em_now[1]));
+    roll_counters(st, inject_plan(st, sc, cap, st->em_now[0], st->em_now[1], st->em_now[2]));
+  if (g.sput_on && blockIdx.x == 0)
+    for (int i = (int)threadIdx.x; i <= g.nr; i += (int)blockDim.x) {
+      const unsigned long long t = (unsigned long long)g.sput_take[i] << 32;
+      if (t) atomicAdd(&g.sput[i], ~t + 1ull);  // minus the atoms taken this step
+    }
   const int W = g.nr + 1;
   const bool sub = g.heavy_every > 1;
   const uint32_t stride = gridDim.x * blockDim.x;
@@ -407,6 +497,16 @@ __global__ void __launch_bounds__(256) k_push(Flow<T> f, DevState* st, Grid g, S
       if (bnd >= 0) {
         code = bnd * kNS + s;
         D.key[p] = g.sentinel;
+        if (bnd == 0 && g.sput_on && spp.Z[s] > 0) {
+          // an ion on the cathode: its yield to the annulus of its nearest node
+          const double vrd = (double)vr, vtd = (double)vt, vzd = (double)vz;
+          const double v2 = ((vrd * vrd) + (vtd * vtd)) + (vzd * vzd);
+          const double E = ((0.5 * spp.m[s]) * v2) / kQE;
+          int ring = (int)(((double)rn / g.dr) + 0.5);
+          if (ring > g.nr) ring = g.nr;
+          const double Y = sputter_yield(E);
+          if (Y > 0.0) atomicAdd(&g.sput[ring], (unsigned long long)floor(Y * 4294967296.0));
+        }
       } else {
         int i2, j2;
         T a, c;

@@ -56,6 +56,8 @@ struct pd_ctx {
   unsigned long long* d_dcount = nullptr;
   double* d_dke = nullptr;
   unsigned long long* d_spec = nullptr;
+  unsigned long long* sput = nullptr;  // cathode sputtering: yields per annulus (2^-32 units)
+  uint32_t* sput_take = nullptr;
 
   // injection schedule
   Schedule sched{};
@@ -732,8 +734,14 @@ pd_status pd_create(const pd_domain* dom, const pd_opts* opts, pd_ctx** out) {
       (s = dalloc(c, &c->off, (size_t)c->g.sentinel + 1)) || (s = dalloc(c, &c->d_edges, 65)) ||
       (s = dalloc(c, &c->d_dcount, (size_t)kDiagBlocks * kNS)) ||
       (s = dalloc(c, &c->d_dke, (size_t)kDiagBlocks * kNS)) ||
-      (s = dalloc(c, &c->d_spec, 3 * 66)))
+      (s = dalloc(c, &c->d_spec, 3 * 66)) || (s = dalloc(c, &c->sput, (size_t)nr + 1)) ||
+      (s = dalloc(c, &c->sput_take, (size_t)nr + 1)))
     return fail(s);
+  if (hipMemset(c->sput, 0, sizeof(unsigned long long) * ((size_t)nr + 1)) != hipSuccess ||
+      hipMemset(c->sput_take, 0, sizeof(uint32_t) * ((size_t)nr + 1)) != hipSuccess)
+    return fail(set_err(c, PD_EDEVICE, "clearing the sputtering counters failed"));
+  c->g.sput = c->sput;
+  c->g.sput_take = c->sput_take;
   c->sw.cap = cap;
   c->cw.cap = cap;
 
@@ -889,6 +897,16 @@ pd_status pd_set_emission(pd_ctx* c, double beta, double r_tip, double phi_w, do
   c->g.em_phi = phi_w;
   c->g.em_ratio = neutral_ratio;
   c->g.em_T = T;
+  return PD_OK;
+}
+
+pd_status pd_set_sputtering(pd_ctx* c, int32_t on) {
+  if (!c) return PD_EINVAL;
+  if (c->in_ensemble) return set_err(c, PD_ESTATE, "the ensemble's graph holds the sputtering");
+  if (on && c->g.nr + 1 > 4096) return set_err(c, PD_EINVAL, "more than 4096 cathode annuli");
+  pd_status s = sync(c);
+  if (s) return s;
+  c->g.sput_on = on ? 1 : 0;
   return PD_OK;
 }
 
@@ -1134,9 +1152,10 @@ pd_status pd_get_diagnostics(pd_ctx* c, pd_diag* out) {
   out->V_gap = h.V_gap;
   out->emitted[0] = (int64_t)h.emitted[0];
   out->emitted[1] = (int64_t)h.emitted[1];
-  // the emitted particles enter like injected ones (electrons, Cu atoms)
+  out->sputtered = (int64_t)h.sputtered;
+  // the emitted and sputtered particles enter like injected ones
   out->injected[PD_E] += out->emitted[0];
-  out->injected[PD_CU] += out->emitted[1];
+  out->injected[PD_CU] += out->emitted[1] + out->sputtered;
   out->charge_injected += out->emitted[0] * c->spp.Z[PD_E] + out->emitted[1] * c->spp.Z[PD_CU];
   return PD_OK;
 }
@@ -1163,7 +1182,8 @@ pd_status pd_get_count(pd_ctx* c, int64_t* n) {
   for (int k = 0; k < 3 * kNS; ++k) a += (int64_t)h.absorbed[k];
   int64_t inj = 0;
   for (int k = 0; k < kNS; ++k) inj += c->injected[k];
-  *n = inj + (int64_t)h.emitted[0] + (int64_t)h.emitted[1] + (int64_t)h.created - a;
+  *n = inj + (int64_t)h.emitted[0] + (int64_t)h.emitted[1] + (int64_t)h.sputtered +
+       (int64_t)h.created - a;
   return PD_OK;
 }
 
@@ -1256,7 +1276,7 @@ pd_status pd_poisson(pd_ctx* c, const int64_t* Q, double* phi, int32_t* iters, d
 // with its read position; the host-side counters; the solver's scalars; the
 // magic again.
 static const char kSaveMagic[8] = {'P', 'D', 'S', 'T', 'A', 'T', 'E', '1'};
-constexpr uint32_t kSaveVersion = 3;
+constexpr uint32_t kSaveVersion = 4;
 
 struct SaveHead {
   char magic[8];
@@ -1267,7 +1287,7 @@ struct SaveHead {
 
 struct SaveBoundary {
   double em_beta, em_rtip, em_phi, em_ratio, em_T, circ_V0, circ_R, circ_C;
-  int32_t split_literal, pad;
+  int32_t split_literal, sput_on;
 };
 
 struct SaveHost {
@@ -1312,7 +1332,7 @@ pd_status pd_save(pd_ctx* c, const char* path) {
   put(&h, sizeof h);
   const SaveBoundary sb{c->g.em_beta, c->g.em_rtip, c->g.em_phi, c->g.em_ratio,
                         c->g.em_T,    c->g.circ_V0, c->g.circ_R, c->g.circ_C,
-                        c->cpar.split_literal, 0};
+                        c->cpar.split_literal, c->g.sput_on};
   put(&sb, sizeof sb);
   put(c->spp.Z, sizeof c->spp.Z);
   put(c->spp.m, sizeof c->spp.m);
@@ -1341,7 +1361,8 @@ pd_status pd_save(pd_ctx* c, const char* path) {
   if ((s = putd(c->sw.skey, 4 * (size_t)st.n_alive)) ||
       (s = putd(c->off, 4 * ((size_t)c->g.sentinel + 1))) || (s = putd(c->fw.Q, 8 * nn)) ||
       (s = putd(c->fw.phi, 8 * nn)) || (s = putd(c->fw.Er, 8 * nn)) ||
-      (s = putd(c->fw.Ez, 8 * nn)))
+      (s = putd(c->fw.Ez, 8 * nn)) ||
+      (s = putd(c->sput, sizeof(unsigned long long) * ((size_t)c->g.nr + 1))))
     return s;
   const int64_t sn = c->sched_n;
   put(&sn, 8);
@@ -1461,6 +1482,7 @@ pd_status pd_load(pd_ctx* c, const char* path) {
   const unsigned char* phi = span(8 * nn);
   const unsigned char* Er = span(8 * nn);
   const unsigned char* Ez = span(8 * nn);
+  const unsigned char* sput = span(sizeof(unsigned long long) * ((size_t)c->g.nr + 1));
   int64_t sn = 0;
   get(&sn, 8);
   std::vector<int64_t> soff;
@@ -1507,6 +1529,7 @@ pd_status pd_load(pd_ctx* c, const char* path) {
   c->g.circ_R = sb.circ_R;
   c->g.circ_C = sb.circ_C;
   c->cpar.split_literal = sb.split_literal ? 1 : 0;
+  c->g.sput_on = sb.sput_on ? 1 : 0;
   for (int k = 0; k < kNC; ++k)
     if (xset[k] && (s = pd_set_cross_section(c, k, xthr[k], xn[k], xdsq[k], xsig[k]))) return s;
   if (sn > 0) {
@@ -1534,7 +1557,9 @@ pd_status pd_load(pd_ctx* c, const char* path) {
       (s = up(c->sw.skey, skey, 4 * (size_t)st.n_alive)) ||
       (s = up(c->off, off, 4 * ((size_t)c->g.sentinel + 1))) || (s = up(c->fw.Q, Q, 8 * nn)) ||
       (s = up(c->fw.phi, phi, 8 * nn)) || (s = up(c->fw.Er, Er, 8 * nn)) ||
-      (s = up(c->fw.Ez, Ez, 8 * nn)) || (s = up(c->st, &st, sizeof st)) ||
+      (s = up(c->fw.Ez, Ez, 8 * nn)) ||
+      (s = up(c->sput, sput, sizeof(unsigned long long) * ((size_t)c->g.nr + 1))) ||
+      (s = up(c->st, &st, sizeof st)) ||
       (s = up(c->mg.sc, sc, sizeof(MGScal))))
     return s;
   for (int k = 0; k < kNS; ++k) c->injected[k] = hh.injected[k];

@@ -82,8 +82,10 @@ struct DevState {
   double V_gap;
   double em_acc[2];
   double em_acc_next[2];
-  uint32_t em_now[2];
+  uint32_t em_now[3];   // emitted electrons, atoms, sputtered atoms this step
+  uint32_t pad2_;
   unsigned long long emitted[2];
+  unsigned long long sputtered;
   long long circ_zanode;
 };
 
@@ -143,6 +145,12 @@ struct Grid {
   // external circuit (circ_C == 0: off): source, resistance, capacitance
   double circ_V0, circ_R, circ_C;
   const double* Vdev; // the gap voltage on the device when the circuit is on, else NULL
+  // cathode sputtering (sput_on == 0: off): per cathode annulus the yields of
+  // the ions absorbed there in units of 2^-32, and the whole atoms the
+  // injection launch took this step (the push subtracts them)
+  int sput_on;
+  unsigned long long* sput;
+  uint32_t* sput_take;
   uint32_t seed_lo, seed_hi;  // Philox key (the emission's draws)
 };
 

@@ -21,7 +21,7 @@ PD_POISSON_DIRECT64, PD_POISSON_MGPCG, PD_POISSON_LEARNED, PD_POISSON_SPECTRAL =
 TIMER_NAMES = ("radix", "permute", "offsets", "collide", "deposit", "poisson", "field", "push",
                "inject")
 EXPORTED = ("pd_create", "pd_set_species", "pd_set_cross_section", "pd_set_heavy_subcycle",
-            "pd_set_emission", "pd_set_circuit", "pd_set_split_literal",
+            "pd_set_emission", "pd_set_circuit", "pd_set_split_literal", "pd_set_sputtering",
             "pd_inject",
             "pd_schedule_injection", "pd_step", "pd_synchronize", "pd_get_diagnostics",
             "pd_get_spectrum", "pd_get_count", "pd_get_particles", "pd_get_field",
@@ -66,7 +66,7 @@ class pd_diag(C.Structure):
                 ("poisson_solves", C.c_int64), ("poisson_iters", C.c_int64),
                 ("poisson_refinements", C.c_int64), ("poisson_fallbacks", C.c_int64),
                 ("poisson_seconds", C.c_double), ("V_gap", C.c_double),
-                ("emitted", C.c_int64 * 2)]
+                ("emitted", C.c_int64 * 2), ("sputtered", C.c_int64)]
 
 
 _lib = None
@@ -100,6 +100,7 @@ def load_library(path=LIB_PATH):
     lib.pd_set_emission.argtypes = [P] + [C.c_double] * 5
     lib.pd_set_circuit.argtypes = [P] + [C.c_double] * 3
     lib.pd_set_split_literal.argtypes = [P, C.c_int32]
+    lib.pd_set_sputtering.argtypes = [P, C.c_int32]
     lib.pd_load.argtypes = [P, C.c_char_p]
     lib.pd_get_timing.argtypes = [P, P, C.POINTER(C.c_int64), C.c_int]
     lib.pd_set_timing.argtypes = [P, C.c_int]
@@ -269,6 +270,10 @@ def pd_set_circuit(ctx, V0, R, C_farad):
 
 def pd_set_split_literal(ctx, on):
     _check(ctx, load_library().pd_set_split_literal(ctx, 1 if on else 0))
+
+
+def pd_set_sputtering(ctx, on):
+    _check(ctx, load_library().pd_set_sputtering(ctx, 1 if on else 0))
 
 
 def pd_save(ctx, path):
@@ -446,6 +451,9 @@ class Simulation:
 
     def set_split_literal(self, on):
         pd_set_split_literal(self.h, on)
+
+    def set_sputtering(self, on):
+        pd_set_sputtering(self.h, on)
 
     def save(self, path):
         pd_save(self.h, path)

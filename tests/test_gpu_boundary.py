@@ -68,3 +68,93 @@ def test_circuit_only_is_bit_exact():
         assert_same_state(g, o, "circuit step %d" % target)
         assert g.diag()["V_gap"] == o.diag()["V_gap"]
     assert g.diag()["V_gap"] != cfg.V
+
+
+def test_sputtering_matches_the_oracle():
+    """Cu+ ions driven into the cathode at known energies, then the workload's
+    own ions: the yields go into the annuli of the impacts (exact fixed-point
+    sums; the yield's pow and log on the device may differ by an ulp, which
+    moves a sum by at most one unit of 2^-32 per ion) and the next steps
+    emit the same atoms."""
+    log("case: cathode sputtering")
+    cfg = W.config("tiny", V=0.0)
+    dr = cfg.R / cfg.nr
+    rng = np.random.default_rng(7)
+    n = 3000
+    rings = rng.integers(0, 6, n)
+    r = np.clip((rings + rng.uniform(-0.45, 0.45, n)) * dr, 0.0, None)
+    E = rng.uniform(50.0, 900.0, n)
+    vz = -np.sqrt(2 * E * W.QE / W.M_CU)
+    z = rng.uniform(0.0, 0.5, n) * (-vz) * cfg.dt
+    parts = {"r": r, "z": z, "vr": np.zeros(n), "vt": np.zeros(n), "vz": vz,
+             "sp": np.full(n, W.CU1, np.uint8)}
+    g, o = pair(cfg, parts=parts, capacity=20000, sched=False, deposit_off=True,
+                collisions_off=True)
+    for s in (g, o):
+        s.set_sputtering(True)
+    for step in range(1, 5):
+        g.step(1)
+        o.step(1)
+        _check(g, o, "sputter step %d" % step)
+        assert g.diag()["sputtered"] == o.diag()["sputtered"]
+    log("  sputtered %d atoms" % g.diag()["sputtered"])
+    assert g.diag()["sputtered"] > 1000
+
+
+def test_all_boundary_physics_on_the_workload():
+    """Emission, neutral flux, circuit and sputtering together on the 32x64
+    workload with collisions, 60 steps beside the oracle."""
+    log("case: emission, circuit and sputtering, 32x64 workload")
+    cfg = W.config("tiny")
+    g, o = pair(cfg, n_init=5000, steps=60)
+    for s in (g, o):
+        s.set_emission(BETA, RTIP, PHI_W, RATIO, T_N)
+        s.set_circuit(V0, R_OHM, C_F)
+        s.set_sputtering(True)
+    done = 0
+    for target in (1, 20, 60):
+        g.step(target - done)
+        o.step(target - done)
+        done = target
+        _check(g, o, "step %d" % done)
+        assert g.diag()["sputtered"] == o.diag()["sputtered"]
+    d = g.diag()
+    log("  emitted %s, sputtered %d, gap voltage %.6f V" % (list(d["emitted"]), d["sputtered"],
+                                                          d["V_gap"]))
+    assert d["charge_alive"] + d["charge_absorbed"] == d["charge_injected"]
+
+
+def test_resume_with_boundary_physics_is_bit_exact(tmp_path):
+    """The checkpoint carries the emission, circuit and sputtering settings,
+    the carried fractions, the gap voltage and the sputtering sums: 40 steps
+    equal 20 + save + load into a fresh context + 20, bit for bit."""
+    from gpu_common import gpu_sim
+    log("case: checkpoint resume with emission, circuit and sputtering")
+    cfg = W.config("tiny")
+    parts = W.initial_population(cfg, n=5000)
+    off, inj = W.injection_schedule(cfg, 40)
+
+    def make():
+        s = gpu_sim(cfg, 100_000)
+        return s
+
+    ref = make()
+    ref.inject(parts)
+    ref.schedule_injection(off, inj)
+    ref.set_emission(BETA, RTIP, PHI_W, RATIO, T_N)
+    ref.set_circuit(V0, R_OHM, C_F)
+    ref.set_sputtering(True)
+    ref.step(20)
+    path = str(tmp_path / "b.pd")
+    ref.save(path)
+    ref.step(20)
+    fresh = make()
+    fresh.load(path)
+    fresh.step(20)
+    pa, pb = ref.particles(), fresh.particles()
+    for k in pa:
+        assert np.array_equal(pa[k], pb[k]), k
+    da, db = ref.diag(), fresh.diag()
+    for k in ("V_gap", "emitted", "sputtered", "count", "events", "injected", "absorbed"):
+        assert np.array_equal(np.asarray(da[k]), np.asarray(db[k])), k
+    assert da["emitted"][0] > 0 and da["V_gap"] != cfg.V
