@@ -366,7 +366,9 @@ __device__ inline void cic_atomic(unsigned long long* Q, int b, int W, long long
 
 // The winners' outcomes; the created slots of a chunk start at its scanned
 // block sum, in electron order inside the block.
-template <typename T>
+// (LIT: the literal Eqs. 16-20 split; a separate instantiation keeps its
+// trigonometric registers out of the default apply)
+template <typename T, bool LIT>
 __global__ void __launch_bounds__(256) k_apply(Flow<T> f, const uint32_t* off, DevState* st, Grid g,
                                                CollideParams cp, SpeciesParams spp,
                                                unsigned long long* Q, const uint8_t* choice,
@@ -463,7 +465,7 @@ __global__ void __launch_bounds__(256) k_apply(Flow<T> f, const uint32_t* off, D
         // stage 4 (Eq. 15): e3 splits into the two orthogonal edges of the
         // rectangle whose diagonal is v3
         double v5[3];
-        if (cp.split_literal) {
+        if (LIT) {
           // cos(chi) ~ U[0,1), psi ~ U[0,2 pi): purpose 4, draw 0
           uint32_t w4[4];
           philox(id, 0u, step, 4u << 24, cp.seed_lo, cp.seed_hi, w4);
@@ -559,8 +561,12 @@ void collide(const Flow<T>& P, const uint32_t* off, DevState* st, const Grid& g,
   // created-electron slots: each apply block adds up the chunk sums before
   // its chunk; the guard (in every block) flags an overflow and then nothing
   // is created, so every later launch touches only [0, n_alive)
-  k_apply<T><<<nb, 256, 0, s>>>(P, off, st, g, cp, sp, (unsigned long long*)Q, w.choice, w.target,
-                                w.ccount, bsum, w.claim, (uint32_t)cap);
+  if (cp.split_literal)
+    k_apply<T, true><<<nb, 256, 0, s>>>(P, off, st, g, cp, sp, (unsigned long long*)Q, w.choice,
+                                        w.target, w.ccount, bsum, w.claim, (uint32_t)cap);
+  else
+    k_apply<T, false><<<nb, 256, 0, s>>>(P, off, st, g, cp, sp, (unsigned long long*)Q, w.choice,
+                                         w.target, w.ccount, bsum, w.claim, (uint32_t)cap);
 }
 template void collide<double>(const Flow<double>&, const uint32_t*, DevState*, const Grid&,
                               const CollideParams&, const SpeciesParams&, int64_t*, CollideWork&,

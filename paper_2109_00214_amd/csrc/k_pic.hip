@@ -226,7 +226,7 @@ __device__ inline void emission_counts(const DevState* st, const Grid& g, double
   }
 }
 
-template <typename T>
+template <typename T, bool BND>
 __device__ inline void inject_records(const PartsT<T>& P, const DevState* st, const Grid& g,
                                       const Schedule& sc, const InjectPlan& ip, const double* cum,
                                       int nring, double I, const uint32_t* spre, int nsr,
@@ -238,7 +238,7 @@ __device__ inline void inject_records(const PartsT<T>& P, const DevState* st, co
     T r, z;
     RecT<T> v;
     uint32_t s;
-    if (q >= q_sput) {
+    if (BND && q >= q_sput) {
       // sputtered: the annulus whose whole atoms this is (spre: inclusive
       // running counts), radius uniform in area in it, on the cathode,
       // normal to it with a Thompson energy truncated at kYtEmax (purpose 6)
@@ -264,7 +264,7 @@ __device__ inline void inject_records(const PartsT<T>& P, const DevState* st, co
       z = (T)0.0;
       s = 1u;
       v = RecT<T>{(T)0.0, (T)0.0, (T)sqrt(((2.0 * E) * kQE) / g.em_mass), id, s};
-    } else if (q < ip.cnt) {
+    } else if (!BND || q < ip.cnt) {
       const int64_t src = ip.a + q;
       r = (T)sc.r[src];
       z = (T)sc.z[src];
@@ -343,7 +343,9 @@ __device__ inline void circuit_update(DevState* st, const Grid& g, const Species
   st->circ_zanode = za;
 }
 
-template <typename T>
+// (BND: emission or sputtering on: their annuli's sums in dynamic LDS, cum
+// then spre; a separate instantiation keeps them out of the plain launch)
+template <typename T, bool BND>
 __global__ void __launch_bounds__(256) k_field_inject(const double* phi, int nr, int nz, double dr,
                                                       double dz, double* Er, double* Ez,
                                                       float* Erf, float* Ezf, PartsT<T> P,
@@ -354,9 +356,22 @@ __global__ void __launch_bounds__(256) k_field_inject(const double* phi, int nr,
     field_nodes(phi, nr, nz, dr, dz, Er, Ez, Erf, Ezf, blockIdx.x, nf);
     return;
   }
-  __shared__ double cum[kMaxRings];
+  if (!BND) {
+    const InjectPlan ip = inject_plan(st, sc, cap, 0u, 0u, 0u);
+    if (blockIdx.x == nf && threadIdx.x == 0) {
+      st->em_now[0] = st->em_now[1] = st->em_now[2] = 0u;
+      st->em_acc_next[0] = st->em_acc[0];
+      st->em_acc_next[1] = st->em_acc[1];
+      if (g.circ_C > 0.0) circuit_update(st, g, spp);
+    }
+    inject_records<T, false>(P, st, g, sc, ip, nullptr, 0, 0.0, nullptr, 0, blockIdx.x - nf,
+                             gridDim.x - nf);
+    return;
+  }
+  extern __shared__ double dyn[];
+  double* cum = dyn;                                         // [nring]
+  uint32_t* spre = (uint32_t*)(dyn + (nring > 0 ? nring : 1));  // [nr + 1] when sputtering
   __shared__ double Ish;
-  __shared__ uint32_t spre[kMaxSputRings];
   __shared__ uint32_t wsum[4];
   uint32_t n[2] = {0u, 0u};
   double acc[2] = {0.0, 0.0};
@@ -395,7 +410,8 @@ __global__ void __launch_bounds__(256) k_field_inject(const double* phi, int nr,
     for (int i = (int)threadIdx.x; i < nsr; i += (int)blockDim.x)
       g.sput_take[i] = ip.fits ? spre[i] - (i > 0 ? spre[i - 1] : 0u) : 0u;
   }
-  inject_records<T>(P, st, g, sc, ip, cum, nring, I, spre, nsr, blockIdx.x - nf, gridDim.x - nf);
+  inject_records<T, true>(P, st, g, sc, ip, cum, nring, I, spre, nsr, blockIdx.x - nf,
+                          gridDim.x - nf);
 }
 
 // emission annuli: those with part of their annulus inside the tip (0: off)
@@ -411,9 +427,18 @@ void field_and_inject(const Grid& g, FieldWork& fw, const PartsT<T>& P, DevState
                       const SpeciesParams& spp, const Schedule& sc, int64_t cap, hipStream_t s) {
   const int64_t n = (int64_t)(g.nr + 1) * (g.nz + 1);
   const int nf = grid_for(n), ni = grid_for(sc.off ? sc.max_count : 1);
-  k_field_inject<T><<<nf + ni, 256, 0, s>>>(fw.phi, g.nr, g.nz, g.dr, g.dz, fw.Er, fw.Ez,
-                                            fw.Erf, fw.Ezf, P, st, g, spp, sc, (uint32_t)cap,
-                                            (uint32_t)nf, emission_ring_count(g));
+  const int nring = emission_ring_count(g);
+  if (nring > 0 || g.sput_on) {
+    const size_t lds = sizeof(double) * (size_t)(nring > 0 ? nring : 1) +
+                       (g.sput_on ? sizeof(uint32_t) * (size_t)(g.nr + 1) : 0);
+    k_field_inject<T, true><<<nf + ni, 256, lds, s>>>(fw.phi, g.nr, g.nz, g.dr, g.dz, fw.Er,
+                                                      fw.Ez, fw.Erf, fw.Ezf, P, st, g, spp, sc,
+                                                      (uint32_t)cap, (uint32_t)nf, nring);
+  } else {
+    k_field_inject<T, false><<<nf + ni, 256, 0, s>>>(fw.phi, g.nr, g.nz, g.dr, g.dz, fw.Er,
+                                                     fw.Ez, fw.Erf, fw.Ezf, P, st, g, spp, sc,
+                                                     (uint32_t)cap, (uint32_t)nf, 0);
+  }
 }
 template void field_and_inject<double>(const Grid&, FieldWork&, const Parts&, DevState*,
                                        const SpeciesParams&, const Schedule&, int64_t,
@@ -430,7 +455,9 @@ template void field_and_inject<float>(const Grid&, FieldWork&, const PartsF&, De
 // With heavy subcycling the heavy species advance only on heavy steps, with
 // their own step; on the other steps their record is moved unchanged and its
 // key recomputed (a collision may have changed the label).
-template <typename T>
+// (SPUT: cathode sputtering on; a separate instantiation keeps the yield's
+// registers out of the plain push)
+template <typename T, bool SPUT>
 __global__ void __launch_bounds__(256) k_push(Flow<T> f, DevState* st, Grid g, SpeciesParams spp,
                                               const T* Er, const T* Ez, Schedule sc,
                                               uint32_t cap) {
@@ -439,7 +466,7 @@ __global__ void __launch_bounds__(256) k_push(Flow<T> f, DevState* st, Grid g, S
   const bool heavy_now = st->heavy_now != 0u;
   if (blockIdx.x == 0 && threadIdx.x == 0)
     roll_counters(st, inject_plan(st, sc, cap, st->em_now[0], st->em_now[1], st->em_now[2]));
-  if (g.sput_on && blockIdx.x == 0)
+  if (SPUT && blockIdx.x == 0)
     for (int i = (int)threadIdx.x; i <= g.nr; i += (int)blockDim.x) {
       const unsigned long long t = (unsigned long long)g.sput_take[i] << 32;
       if (t) atomicAdd(&g.sput[i], ~t + 1ull);  // minus the atoms taken this step
@@ -497,7 +524,7 @@ __global__ void __launch_bounds__(256) k_push(Flow<T> f, DevState* st, Grid g, S
       if (bnd >= 0) {
         code = bnd * kNS + s;
         D.key[p] = g.sentinel;
-        if (bnd == 0 && g.sput_on && spp.Z[s] > 0) {
+        if (SPUT && bnd == 0 && spp.Z[s] > 0) {
           // an ion on the cathode: its yield to the annulus of its nearest node
           const double vrd = (double)vr, vtd = (double)vt, vzd = (double)vz;
           const double v2 = ((vrd * vrd) + (vtd * vtd)) + (vzd * vzd);
@@ -521,12 +548,22 @@ __global__ void __launch_bounds__(256) k_push(Flow<T> f, DevState* st, Grid g, S
 template <>
 void push<double>(const Flow<double>& f, DevState* st, const Grid& g, const SpeciesParams& sp,
                   const FieldWork& fw, const Schedule& sc, int64_t cap, hipStream_t s) {
-  k_push<double><<<grid_for(cap), 256, 0, s>>>(f, st, g, sp, fw.Er, fw.Ez, sc, (uint32_t)cap);
+  if (g.sput_on)
+    k_push<double, true><<<grid_for(cap), 256, 0, s>>>(f, st, g, sp, fw.Er, fw.Ez, sc,
+                                                       (uint32_t)cap);
+  else
+    k_push<double, false><<<grid_for(cap), 256, 0, s>>>(f, st, g, sp, fw.Er, fw.Ez, sc,
+                                                        (uint32_t)cap);
 }
 template <>
 void push<float>(const Flow<float>& f, DevState* st, const Grid& g, const SpeciesParams& sp,
                  const FieldWork& fw, const Schedule& sc, int64_t cap, hipStream_t s) {
-  k_push<float><<<grid_for(cap), 256, 0, s>>>(f, st, g, sp, fw.Erf, fw.Ezf, sc, (uint32_t)cap);
+  if (g.sput_on)
+    k_push<float, true><<<grid_for(cap), 256, 0, s>>>(f, st, g, sp, fw.Erf, fw.Ezf, sc,
+                                                      (uint32_t)cap);
+  else
+    k_push<float, false><<<grid_for(cap), 256, 0, s>>>(f, st, g, sp, fw.Erf, fw.Ezf, sc,
+                                                       (uint32_t)cap);
 }
 
 // host-initiated append of n particles already copied to src
