@@ -15,7 +15,7 @@ _LIB = os.path.join(_HERE, "libpd_oracle.so")
 
 NSPECIES = 8
 NKEYS = 6
-NCHANNELS = 8
+NCHANNELS = 10
 
 
 def build_oracle(force=True):

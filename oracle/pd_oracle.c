@@ -260,10 +260,16 @@ void or_destroy(or_sim* s) {
 /* the species each channel's target is drawn from (any Cu2+ tag for SI3:
  * all tags have the Cu2+ mass) and the label the target takes             */
 static const int TARGET_OF[OR_NCHANNELS] = {OR_CU, OR_CU, OR_CU, OR_CU1, OR_CU2_STEP, OR_CU3,
-                                            OR_CU, OR_CU};
-static const int PROJECTILE_OF[OR_NCHANNELS] = {OR_E, OR_E, OR_E, OR_E, OR_E, OR_E, OR_CU1, OR_CU};
-static const int PRODUCT_OF[OR_NCHANNELS] = {OR_CU, OR_CU1, OR_CU2_DOUBLE, OR_CU2_STEP,
-                                             OR_CU3, OR_CU4, OR_CU1, OR_CU};
+                                            OR_CU, OR_CU, OR_CU1, OR_E};
+static const int PROJECTILE_OF[OR_NCHANNELS] = {OR_E, OR_E, OR_E, OR_E,   OR_E,
+                                                OR_E, OR_CU1, OR_CU, OR_E, OR_E};
+static const int PRODUCT_OF[OR_NCHANNELS] = {OR_CU, OR_CU1, OR_CU2_DOUBLE, OR_CU2_STEP, OR_CU3,
+                                             OR_CU4, OR_CU1, OR_CU, OR_CU1, OR_E};
+/* the electron channels in cumulative-sum order, and the key class their
+ * target is drawn from (0: another electron)                             */
+static const int ECH[OR_NELECTRON_CHANNELS] = {OR_EL, OR_SI, OR_DI, OR_SI2, OR_SI3, OR_SI4,
+                                               OR_CEI, OR_CEE};
+static const int ECLS[OR_NELECTRON_CHANNELS] = {1, 1, 1, 2, 3, 4, 2, 0};
 
 static void derive_pairs(or_sim* s) {
   /* projectile PROJECTILE_OF[channel], target TARGET_OF[channel] */
@@ -535,9 +541,13 @@ void or_stage_collide(or_sim* s) {
 
   /* decide: reads the pre-collision state only (Eq. 4).  Each electron
    * draws one target of each target class in its cell (Cu, Cu+, Cu2+ of any
-   * tag, Cu3+): the channels of one target class share the draw and the
-   * relative speed.  SI3 and SI4 take part only when their tables are set. */
-  const int cls_of[OR_NCHANNELS] = {1, 1, 1, 2, 3, 4}; /* key class of the target */
+   * tag, Cu3+, and with electron-electron Coulomb collisions one of the
+   * other electrons): the channels of one target class share the draw and
+   * the relative speed.  Channels from SI3 on take part only when their
+   * tables are set.  The electron-electron channel tries every pair from
+   * both sides, so its x carries a factor 1/2 and its density counts the
+   * other N - 1 electrons.                                                */
+  const int cee = s->xs_set[OR_CEE];
   for (int64_t p = 0; p < n_e; ++p) {
     int64_t cell = s->key[p]; /* key class 0 */
     int ci = (int)(cell % s->nr);
@@ -553,10 +563,22 @@ void or_stage_collide(or_sim* s) {
       /* uniform pick: floor(u32 * n / 2^32), word c-1 of the second draw */
       tp[c] = b[c] + (int64_t)(((uint64_t)t[c - 1] * (uint64_t)nt[c]) >> 32);
     }
-    double x[OR_NELECTRON_CHANNELS] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int k = 0; k < OR_NELECTRON_CHANNELS; ++k) {
-      int c = cls_of[k];
-      if (nt[c] == 0 || !s->xs_set[k]) continue;
+    /* another electron of the cell (word 0 of the draw (purpose 1, 1)),
+     * never the projectile itself */
+    b[0] = s->off[cell];
+    nt[0] = s->off[cell + 1] - b[0] - 1; /* the others */
+    tp[0] = 0;
+    if (cee && nt[0] > 0) {
+      uint32_t t2[4];
+      draw4(s, s->id[p], 1, 1, t2);
+      int64_t u = (int64_t)(((uint64_t)t2[0] * (uint64_t)nt[0]) >> 32);
+      if (b[0] + u >= p) u += 1;
+      tp[0] = b[0] + u;
+    }
+    double x[OR_NELECTRON_CHANNELS] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int e = 0; e < OR_NELECTRON_CHANNELS; ++e) {
+      int k = ECH[e], c = ECLS[e];
+      if (nt[c] <= 0 || !s->xs_set[k]) continue;
       if (k == OR_DI && !s->enable_di) continue;
       double dvr = s->vr[p] - s->vr[tp[c]];
       double dvt = s->vt[p] - s->vt[tp[c]];
@@ -564,22 +586,23 @@ void or_stage_collide(or_sim* s) {
       double g = sqrt(((dvr * dvr) + (dvt * dvt)) + (dvz * dvz));
       double sig = sigma_of(s, k, g);
       double dens = ((double)nt[c] * s->W) / s->Vcell[ci];
-      x[k] = ((s->dt * g) * dens) * sig;
+      x[e] = ((s->dt * g) * dens) * sig;
+      if (k == OR_CEE) x[e] = 0.5 * x[e];
     }
-    double X = ((((x[0] + x[1]) + x[2]) + x[3]) + x[4]) + x[5];
+    double X = ((((((x[0] + x[1]) + x[2]) + x[3]) + x[4]) + x[5]) + x[6]) + x[7];
     double pc = 1.0 - exp(-X);
     if (!(R1 < pc)) continue;
     double u = R2 * X, c = 0.0;
-    int ch = -1;
-    for (int k = 0; k < OR_NELECTRON_CHANNELS; ++k) {
-      c = c + x[k];
-      if (u < c) { ch = k; break; }
+    int ce = -1;
+    for (int e = 0; e < OR_NELECTRON_CHANNELS; ++e) {
+      c = c + x[e];
+      if (u < c) { ce = e; break; }
     }
-    if (ch < 0)
-      for (int k = OR_NELECTRON_CHANNELS - 1; k >= 0; --k)
-        if (x[k] > 0.0) { ch = k; break; }
-    s->choice[p] = (uint8_t)(ch + 1);
-    s->target[p] = (uint32_t)tp[cls_of[ch]];
+    if (ce < 0)
+      for (int e = OR_NELECTRON_CHANNELS - 1; e >= 0; --e)
+        if (x[e] > 0.0) { ce = e; break; }
+    s->choice[p] = (uint8_t)(ECH[ce] + 1);
+    s->target[p] = (uint32_t)tp[ECLS[ce]];
   }
 
   /* heavy projectiles (Sec. 2.3 lists ion-neutral charge exchange and
@@ -629,16 +652,18 @@ void or_stage_collide(or_sim* s) {
    * electron event touches its target, a heavy event its target and its
    * projectile), and an event happens iff it wins everything it touches */
   for (int64_t p = 0; p < n; ++p) s->claim[p] = UINT32_MAX;
+  /* (with electron-electron collisions an electron can be a target, so
+   * every electron event then claims its projectile as well)            */
   for (int64_t p = 0; p < n; ++p) {
     if (!s->choice[p]) continue;
     uint32_t t = s->target[p];
     if (s->claim[t] == UINT32_MAX) s->claim[t] = (uint32_t)p;
-    if (p >= n_e && s->claim[p] == UINT32_MAX) s->claim[p] = (uint32_t)p;
+    if ((p >= n_e || cee) && s->claim[p] == UINT32_MAX) s->claim[p] = (uint32_t)p;
   }
   for (int64_t p = 0; p < n; ++p)
     if (s->choice[p]) {
       int won = s->claim[s->target[p]] == (uint32_t)p;
-      if (p >= n_e) won = won && s->claim[p] == (uint32_t)p;
+      if (p >= n_e || cee) won = won && s->claim[p] == (uint32_t)p;
       if (won) s->win[p] = 1;
       else s->conflicts += 1;
     }
@@ -647,7 +672,8 @@ void or_stage_collide(or_sim* s) {
    * ids next_id++ (the stage-2 electron first, then the stage-4 one)   */
   int64_t n_new = 0;
   for (int64_t p = 0; p < n_e; ++p)
-    if (s->win[p]) n_new += (s->choice[p] == OR_EL + 1) ? 0 : (s->choice[p] == OR_DI + 1 ? 2 : 1);
+    if (s->win[p]) n_new += (s->choice[p] == OR_EL + 1 || s->choice[p] == OR_CEI + 1 ||
+                        s->choice[p] == OR_CEE + 1) ? 0 : (s->choice[p] == OR_DI + 1 ? 2 : 1);
   reserve(s, n + n_new);
   for (int64_t p = 0; p < n_e; ++p) {
     if (!s->win[p]) continue;
@@ -661,7 +687,7 @@ void or_stage_collide(or_sim* s) {
     or_isotropic(s, s->id[p], 2, nh);
     binary(e1, A, s->two_dE_mr[ch], s->f1[ch], s->f2[ch], nh);
     s->vr[tp] = A[0]; s->vt[tp] = A[1]; s->vz[tp] = A[2];
-    if (ch == OR_EL) {
+    if (ch == OR_EL || ch == OR_CEI || ch == OR_CEE) { /* elastic */
       s->vr[p] = e1[0]; s->vt[p] = e1[1]; s->vz[p] = e1[2];
       continue;
     }

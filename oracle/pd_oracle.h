@@ -31,11 +31,15 @@ enum { OR_E = 0, OR_CU = 1, OR_CU1 = 2, OR_CU2_STEP = 3, OR_CU2_DOUBLE = 4,
 enum { OR_NKEYS = 6 };
 /* collision channels.  Electron impact, in cumulative-sum order: elastic,
  * Cu -> Cu+, Cu -> Cu2+ (double), Cu+ -> Cu2+, Cu2+ -> Cu3+, Cu3+ -> Cu4+.
- * Heavy projectiles: Cu+ + Cu charge exchange, Cu + Cu elastic.  Channels
- * from SI3 on take part only when their cross sections are set. */
+ * Heavy projectiles: Cu+ + Cu charge exchange, Cu + Cu elastic.  Coulomb
+ * collisions of electrons with Cu+ and with other electrons, as elastic
+ * channels with a tabulated momentum-transfer cross section.  Channels from
+ * SI3 on take part only when their cross sections are set. */
 enum { OR_EL = 0, OR_SI = 1, OR_DI = 2, OR_SI2 = 3, OR_SI3 = 4, OR_SI4 = 5,
-       OR_CEX = 6, OR_NN = 7, OR_NCHANNELS = 8 };
-enum { OR_NELECTRON_CHANNELS = 6 };
+       OR_CEX = 6, OR_NN = 7, OR_CEI = 8, OR_CEE = 9, OR_NCHANNELS = 10 };
+/* the electron-impact channels, in cumulative-sum order: the six above, then
+ * the Coulomb channels electron-Cu+ and electron-electron */
+enum { OR_NELECTRON_CHANNELS = 8 };
 /* absorbing boundaries */
 enum { OR_CATHODE = 0, OR_ANODE = 1, OR_OUTER = 2 };
 

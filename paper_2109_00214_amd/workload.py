@@ -38,17 +38,18 @@ M_CU = 63.546 * AMU
 E, CU, CU1, CU2_STEP, CU2_DOUBLE, CU2_INIT, CU3, CU4 = range(8)
 NSPECIES = 8
 SPECIES_NAMES = ("e", "Cu", "Cu+", "Cu2+(step)", "Cu2+(double)", "Cu2+(init)", "Cu3+", "Cu4+")
-# channels: electron impact in cumulative order, then the heavy projectiles'
-# charge exchange (Cu+ + Cu) and neutral-neutral elastic (Cu + Cu); SI3 and
-# SI4 (the step-wise chain on to Cu4+), CEX and NN take part only when their
-# tables are given
-EL, SI, DI, SI2, SI3, SI4, CEX, NN = range(8)
-NCHANNELS = 8
+# channels: electron impact (six), the heavy projectiles' charge exchange
+# (Cu+ + Cu) and neutral-neutral elastic (Cu + Cu), the Coulomb collisions of
+# electrons with Cu+ and with electrons; every channel from SI3 on takes part
+# only when its table is given
+EL, SI, DI, SI2, SI3, SI4, CEX, NN, CEI, CEE = range(10)
+NCHANNELS = 10
 CHANNEL_NAMES = ("elastic", "Cu->Cu+", "Cu->Cu2+ (double)", "Cu+->Cu2+", "Cu2+->Cu3+",
-                 "Cu3+->Cu4+", "Cu+ + Cu charge exchange", "Cu + Cu elastic")
+                 "Cu3+->Cu4+", "Cu+ + Cu charge exchange", "Cu + Cu elastic", "e + Cu+ Coulomb",
+                 "e + e Coulomb")
 # ionization energies (eV) of Cu, Cu+, Cu2+, Cu3+ and the paper's double-
-# ionization threshold; the heavy channels lose no energy
-THRESHOLDS_EV = (0.0, 7.73, 28.0, 20.29, 36.84, 57.38, 0.0, 0.0)
+# ionization threshold; the other channels lose no energy
+THRESHOLDS_EV = (0.0, 7.73, 28.0, 20.29, 36.84, 57.38, 0.0, 0.0, 0.0, 0.0)
 
 
 def species_table():
@@ -66,13 +67,23 @@ def lotz(E, P, q, a_cm2=4.5e-14):
     return np.where(E >= P, s, 0.0) * 1e-4
 
 
-def cross_section_tables(dsqrtE=2.0 ** -4, n=1025, chain=False, heavy=False):
+def coulomb_sigma(E, ln_lambda=10.0, E_min=0.1):
+    """Momentum-transfer cross section of a Coulomb pair of unit charges,
+    4 pi lnL b^2 with b = e^2 / (8 pi eps0 E) (E the energy of relative motion
+    in eV, held at E_min below it), in m^2."""
+    E = np.maximum(np.asarray(E, dtype=np.float64), E_min)
+    b = QE / (8.0 * np.pi * EPS0 * E)
+    return 4.0 * np.pi * ln_lambda * b * b
+
+
+def cross_section_tables(dsqrtE=2.0 ** -4, n=1025, chain=False, heavy=False, coulomb=False):
     """(channel, threshold_eV, dsqrtE, sigma[n]) for EL, SI, DI, SI2, with
     chain=True also SI3 and SI4 (Lotz forms with 9 and 8 d electrons), with
     heavy=True also CEX and NN (stand-ins: a resonant charge-exchange form
     (a - b ln E)^2, a = 7.5 A, b = 0.4 A, E >= 0.01 eV; hard spheres of
     diameter 2.6 A).
 
+    With coulomb=True also CEI and CEE (coulomb_sigma, ln Lambda = 10).
     Tables are uniform in sqrt(E/eV) with spacing dsqrtE (a power of 2); E is
     the energy of relative motion of the pair.
     """
@@ -90,6 +101,8 @@ def cross_section_tables(dsqrtE=2.0 ** -4, n=1025, chain=False, heavy=False):
         cex = (7.5 - 0.4 * np.log(np.maximum(En, 0.01))) ** 2 * 1e-20
         nn = np.full(n, np.pi * 2.6e-10 ** 2)
         out += [(CEX, 0.0, dsqrtE, cex), (NN, 0.0, dsqrtE, nn)]
+    if coulomb:
+        out += [(CEI, 0.0, dsqrtE, coulomb_sigma(En)), (CEE, 0.0, dsqrtE, coulomb_sigma(En))]
     return out
 
 

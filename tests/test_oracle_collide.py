@@ -338,7 +338,11 @@ def test_chain_run_bookkeeping():
     cfg = W.config("tiny", nr=8, nz=16, weight=1e5)
     tables = W.constant_tables([3e-19] * W.NCHANNELS, thresholds=list(W.THRESHOLDS_EV), n=4096)
     o = make_oracle(cfg, tables=tables)
-    o.inject(_uniform_vapour(cfg, 20, 10, 4, 6.0e6, 3, n_cu2_per_tag=4, n_cu3_per_cell=8))
+    parts = _uniform_vapour(cfg, 20, 10, 4, 6.0e6, 3, n_cu2_per_tag=4, n_cu3_per_cell=8)
+    rng = np.random.default_rng(8)
+    e = parts["sp"] == W.E
+    parts["vr"] = np.where(e, rng.normal(0.0, 1e6, e.size), parts["vr"])  # electron pairs move apart
+    o.inject(parts)
     o.step(6)
     d = o.diag()
     assert np.all(d["events"] > 0), d["events"]
