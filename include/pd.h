@@ -72,13 +72,18 @@ enum { PD_E = 0, PD_CU = 1, PD_CU1 = 2, PD_CU2_STEP = 3, PD_CU2_DOUBLE = 4,
  * charge exchange (the charge passes to the atom: the two labels swap,
  * positions and velocities stay), Cu + Cu elastic (isotropic in the
  * centre-of-mass frame; each pair is tried from both sides at half weight).
- * Every channel from PD_SI3 on takes part only when its table is set.  A
- * particle takes part in at most one event per step: an electron event
- * claims its target, a heavy event its target and its projectile, the
- * lowest sorted projectile position wins a claim, and an event happens iff
- * it wins all its claims. */
+ * Coulomb collisions (Sec. 2.3) of electrons with Cu+ (PD_CEI) and with other
+ * electrons (PD_CEE): elastic, isotropic, with the table holding the
+ * momentum-transfer cross section 4 pi lnL b90^2 (b90 = e^2 / (8 pi eps0
+ * E_rel)); they follow PD_SI4 in the electrons' cumulative sum, and the
+ * electron pairs are tried from both sides at half weight.  Every channel
+ * from PD_SI3 on takes part only when its table is set.  A particle takes
+ * part in at most one event per step: an electron event claims its target
+ * (and, when PD_CEE is set, its projectile), a heavy event its target and its
+ * projectile, the lowest sorted projectile position wins a claim, and an
+ * event happens iff it wins all its claims. */
 enum { PD_EL = 0, PD_SI = 1, PD_DI = 2, PD_SI2 = 3, PD_SI3 = 4, PD_SI4 = 5, PD_CEX = 6,
-       PD_NN = 7, PD_NCHANNELS = 8 };
+       PD_NN = 7, PD_CEI = 8, PD_CEE = 9, PD_NCHANNELS = 10 };
 /* absorbing boundaries */
 enum { PD_CATHODE = 0, PD_ANODE = 1, PD_OUTER = 2 };
 /* precision forms: FP64 deterministic (with PD_POISSON_DIRECT64 every result

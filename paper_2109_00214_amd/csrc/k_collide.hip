@@ -163,7 +163,7 @@ __global__ void __launch_bounds__(256) k_decide(Flow<T> f, const uint32_t* off, 
     const uint32_t tc = b_cu + __umulhi(t[0], n_cu);
     const uint32_t t1 = b_c1 + __umulhi(t[1], n_c1);
     const double evr = ev.vr, evt = ev.vt, evz = ev.vz;
-    double x[kNEC] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double x[kNEC] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     const double Vc = cp.Vcell[ci];
     // Cu target: EL, SI, DI share the pick and the relative speed
     if (n_cu > 0) {
@@ -185,6 +185,8 @@ __global__ void __launch_bounds__(256) k_decide(Flow<T> f, const uint32_t* off, 
       const double gg = sqrt(((dvr * dvr) + (dvt * dvt)) + (dvz * dvz));
       const double dens = ((double)n_c1 * cp.W) / Vc;
       x[3] = ((cp.dt * gg) * dens) * sigma_of(cp, 3, gg);
+      // Coulomb with the same Cu+ (position 6)
+      if (cp.coulomb && cp.tabn[kCEI] > 0) x[6] = ((cp.dt * gg) * dens) * sigma_of(cp, kCEI, gg);
     }
     // the step-wise chain on: a Cu2+ target of any label (the labels share
     // one key class) and a Cu3+ target, words 2 and 3 of the same draw
@@ -207,30 +209,56 @@ __global__ void __launch_bounds__(256) k_decide(Flow<T> f, const uint32_t* off, 
         }
       }
     }
-    const double X = ((((x[0] + x[1]) + x[2]) + x[3]) + x[4]) + x[5];
+    // electron-electron Coulomb (position 7): one of the other electrons of
+    // the cell (word 0 of the draw (purpose 1, 1)), never the projectile;
+    // every pair is tried from both sides, so half weight
+    uint32_t te = 0;
+    if (cp.cee) {
+      const uint32_t b0 = off[cell], n0 = off[cell + 1] - b0 - 1u;
+      if (n0 > 0 && cp.tabn[kCEE] > 0) {
+        uint32_t t2w[4];
+        philox(id, 0u, step, (1u << 24) | 1u, cp.seed_lo, cp.seed_hi, t2w);
+        uint32_t u = __umulhi(t2w[0], n0);
+        if (b0 + u >= e) u += 1u;
+        te = b0 + u;
+        const RecT<T> tv = P.v[f.perm[te]];
+        const double dvr = evr - (double)tv.vr, dvt = evt - (double)tv.vt,
+                     dvz = evz - (double)tv.vz;
+        const double gg = sqrt(((dvr * dvr) + (dvt * dvt)) + (dvz * dvz));
+        const double dens = ((double)n0 * cp.W) / Vc;
+        x[7] = 0.5 * (((cp.dt * gg) * dens) * sigma_of(cp, kCEE, gg));
+      }
+    }
+    const double X = ((((((x[0] + x[1]) + x[2]) + x[3]) + x[4]) + x[5]) + x[6]) + x[7];
     const double pc = 1.0 - exp(-X);
-    int ch = -1;
+    int q = -1;
     if (R1 < pc) {
       const double u = R2 * X;
       double c = 0.0;
 #pragma unroll
       for (int k = 0; k < kNEC; ++k) {
         c = c + x[k];
-        if (ch < 0 && u < c) ch = k;
+        if (q < 0 && u < c) q = k;
       }
-      if (ch < 0) {
+      if (q < 0) {
         for (int k = kNEC - 1; k >= 0; --k)
           if (x[k] > 0.0) {
-            ch = k;
+            q = k;
             break;
           }
       }
     }
-    if (ch >= 0) {
-      const uint32_t tp = (ch == 3) ? t1 : (ch == 4) ? t2 : (ch == 5) ? t3 : tc;
+    if (q >= 0) {
+      const int ch = echannel(q);
+      const uint32_t tp = (ch == 3 || ch == kCEI) ? t1
+                        : (ch == 4)              ? t2
+                        : (ch == 5)              ? t3
+                        : (ch == kCEE)           ? te
+                                                 : tc;
       choice[e] = (uint8_t)(ch + 1);
       target[e] = tp;
       atomicMin(&claim[tp], e);
+      if (cp.cee) atomicMin(&claim[e], e);
     } else {
       choice[e] = 0;
     }
@@ -299,12 +327,14 @@ __global__ void __launch_bounds__(256) k_resolve(const uint32_t* off, DevState* 
     if (e < n_e) {
       const uint32_t c = choice[e];
       if (c) {
-        if (claim[target[e]] == e) {
+        if (claim[target[e]] == e && (!cp.cee || claim[e] == e)) {
           ch = (int)c - 1;
-          cnt = (ch == 0) ? 0u : (ch == 2 ? 2u : 1u);
+          cnt = (ch == 0 || ch == kCEI || ch == kCEE) ? 0u : (ch == 2 ? 2u : 1u);
         } else {
           lost = true;
-          choice[e] = 0;
+          // with electron-electron collisions the apply resets the claims
+          // of the losers too (bit 7 marks them)
+          choice[e] = cp.cee ? (uint8_t)(c | 0x80u) : (uint8_t)0;
         }
       }
       ccount[e] = cnt;
@@ -406,8 +436,14 @@ __global__ void __launch_bounds__(256) k_apply(Flow<T> f, const uint32_t* off, D
       if (e >= n_e) continue;
       const uint32_t c = choice[e];
       if (!c) continue;
-      const int ch = (int)c - 1;
       const uint32_t tp = target[e];
+      if (c & 0x80u) {  // lost, with projectile claims: reset both
+        claim[tp] = 0xFFFFFFFFu;
+        claim[e] = 0xFFFFFFFFu;
+        continue;
+      }
+      if (cp.cee) claim[e] = 0xFFFFFFFFu;
+      const int ch = (int)c - 1;
       const uint32_t pe = f.perm[e], pt = f.perm[tp];
       const RecT<T> ve = P.v[pe];
       RecT<T> vt = P.v[pt];
@@ -422,7 +458,7 @@ __global__ void __launch_bounds__(256) k_apply(Flow<T> f, const uint32_t* off, D
       vt.vr = (T)A[0];
       vt.vt = (T)A[1];
       vt.vz = (T)A[2];
-      if (ch == 0) {
+      if (ch == 0 || ch == kCEI || ch == kCEE) {  // elastic
         P.v[pt] = vt;
         RecT<T> v1 = ve;
         v1.vr = (T)e1[0];

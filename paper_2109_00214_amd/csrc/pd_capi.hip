@@ -500,16 +500,18 @@ void derive_pairs(pd_ctx* c) {
   // projectile: electron, Cu+ (CEX) or Cu (NN); target: Cu (EL, SI, DI,
   // CEX, NN), Cu+ (SI2), Cu2+ of any label (SI3: the labels share the Cu2+
   // mass) or Cu3+ (SI4)
-  const int tgt[kNC] = {PD_CU, PD_CU, PD_CU, PD_CU1, PD_CU2_STEP, PD_CU3, PD_CU, PD_CU};
-  const int prj[kNC] = {PD_E, PD_E, PD_E, PD_E, PD_E, PD_E, PD_CU1, PD_CU};
+  const int tgt[kNC] = {PD_CU, PD_CU, PD_CU, PD_CU1, PD_CU2_STEP, PD_CU3, PD_CU, PD_CU,
+                        PD_CU1, PD_E};
+  const int prj[kNC] = {PD_E, PD_E, PD_E, PD_E, PD_E, PD_E, PD_CU1, PD_CU, PD_E, PD_E};
   for (int k = 0; k < kNC; ++k) {
     const double m1 = c->spp.m[prj[k]], m2 = c->spp.m[tgt[k]];
     const double mr = (m1 * m2) / (m1 + m2);
     c->cpar.f1[k] = mr / m1;
     c->cpar.f2[k] = mr / m2;
     c->cpar.ck[k] = std::sqrt(mr / (2.0 * kQE));
+    // energy lost: the ionization thresholds; the other channels are elastic
     c->cpar.two_dE_mr[k] =
-        (k == PD_EL || k >= kNEC) ? 0.0 : (2.0 * (-(c->xs_thr[k] * kQE))) / mr;
+        (k >= PD_SI && k <= PD_SI4) ? (2.0 * (-(c->xs_thr[k] * kQE))) / mr : 0.0;
   }
 }
 
@@ -861,6 +863,8 @@ pd_status pd_set_cross_section(pd_ctx* c, int ch, double thr, int n, double dsq,
   c->xs_set[ch] = true;
   c->cpar.chain = (c->xs_set[PD_SI3] || c->xs_set[PD_SI4]) ? 1 : 0;
   c->cpar.heavy = (c->xs_set[PD_CEX] || c->xs_set[PD_NN]) ? 1 : 0;
+  c->cpar.coulomb = (c->xs_set[PD_CEI] || c->xs_set[PD_CEE]) ? 1 : 0;
+  c->cpar.cee = c->xs_set[PD_CEE] ? 1 : 0;
   if (c->species_set) derive_pairs(c);
   return PD_OK;
 }

@@ -13,9 +13,13 @@ constexpr double kEPS0 = 8.8541878128e-12; // vacuum permittivity, F/m
 constexpr double kPI = 3.14159265358979323846;
 constexpr int kNS = 8;                     // species (the three Cu2+ labels apart)
 constexpr int kNK = 6;                     // sort-key classes (the Cu2+ labels together)
-constexpr int kNC = 8;                     // collision channels
-constexpr int kNEC = 6;                    // of them electron-impact (the rest: heavy projectiles)
+constexpr int kNC = 10;                    // collision channels
 constexpr int kCEX = 6, kNN = 7;           // Cu+ + Cu charge exchange, Cu + Cu elastic
+constexpr int kCEI = 8, kCEE = 9;          // Coulomb: electron with Cu+, with an electron
+// the electron channels in cumulative-sum order: EL, SI, DI, SI2, SI3, SI4,
+// CEI, CEE (position q is channel q below 6, q + 2 from 6 on)
+constexpr int kNEC = 8;
+__host__ __device__ inline int echannel(int q) { return q < 6 ? q : q + 2; }
 
 // sort-key class of a species: e, Cu, Cu+, Cu2+ (every label), Cu3+, Cu4+
 __host__ __device__ inline uint32_t key_class(uint32_t s) {
@@ -176,6 +180,9 @@ struct CollideParams {
   int chain;             // the Cu2+ -> Cu3+ or Cu3+ -> Cu4+ channel takes part
   int heavy;             // a heavy-projectile channel (CEX, NN) takes part
   int split_literal;     // the last stage of a double ionization by Eqs. 16-20
+  int coulomb;           // an electron Coulomb channel (CEI, CEE) takes part
+  int cee;               // the electron-electron channel takes part: every electron
+                         // event then claims its projectile too
   double dt_heavy;       // their time step (the heavy step)
   const double* Vcell;   // cell volumes [nr]
 };

@@ -51,7 +51,7 @@ class pd_opts(C.Structure):
                 ("stream", C.c_void_p), ("poisson_rtol", C.c_double)]
 
 
-PD_NSPECIES, PD_NCHANNELS = 8, 8
+PD_NSPECIES, PD_NCHANNELS = 8, 10
 
 
 class pd_diag(C.Structure):

@@ -198,12 +198,12 @@ def test_heavy_collisions_bit_exact(every):
 
 
 def test_all_channels_tiny_config_200_steps_bit_exact():
-    """The tiny configuration with every channel's table (the chain to Cu4+
-    and the heavy projectiles' stand-ins) and the paper's heavy step of ten
-    electron steps."""
+    """The tiny configuration with every channel's table (the chain to Cu4+,
+    the heavy projectiles' stand-ins, the Coulomb channels) and the paper's
+    heavy step of ten electron steps."""
     log("case: tiny config, all channels, heavy step 10, 200 steps")
     cfg = W.config("tiny")
-    tables = W.cross_section_tables(chain=True, heavy=True)
+    tables = W.cross_section_tables(chain=True, heavy=True, coulomb=True)
     g, o = pair(cfg, parts=_chain_population(cfg, cfg.n_init, 1000, 13), steps=cfg.steps,
                 tables=tables)
     g.set_heavy_subcycle(10)
@@ -217,6 +217,25 @@ def test_all_channels_tiny_config_200_steps_bit_exact():
     d = g.diag()
     log("  events per channel %s" % list(d["events"]))
     assert d["events"][W.CEX] > 0 and d["events"][W.NN] > 0
+    assert d["events"][W.CEI] > 0 and d["events"][W.CEE] > 0
+
+
+def test_coulomb_collisions_bit_exact():
+    """Electron-Cu+ and electron-electron Coulomb channels beside the
+    electron-impact ones on a dense population: electrons are targets too,
+    so every electron event claims its projectile; the whole state stays
+    bit-identical."""
+    log("case: Coulomb collisions, dense")
+    cfg = W.config("tiny", nr=16, nz=32, weight=1e4)
+    tables = W.cross_section_tables(coulomb=True)
+    g, o = pair(cfg, n_init=40000, steps=10, tables=tables)
+    for s in range(1, 11):
+        g.step(1)
+        o.step(1)
+        assert_same_state(g, o, "coulomb step %d" % s)
+    d = g.diag()
+    log("  events per channel %s, conflicts %d" % (list(d["events"]), d["conflicts"]))
+    assert d["events"][W.CEI] > 100 and d["events"][W.CEE] > 100
 
 
 def test_di_disabled_and_seed_dependence():
