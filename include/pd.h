@@ -168,14 +168,19 @@ typedef struct {
                                   * cathode (also counted in injected) */
 } pd_diag;
 
-/* Create a context on the current HIP device.  dom and opts are copied.
+/* Create a context on the current HIP device for the r-z domain of the
+ * 2D3V cylindrical PIC-DSMC model (Sec. 2.1: cells of nr x nz, cathode
+ * at z = 0, anode at z = L, axis at r = 0).  dom and opts are copied.
  * Device memory for dom->capacity particles is allocated here.
  * PD_POISSON_SPECTRAL needs nr <= 1023 and nz <= 4096.
  * Errors: PD_EINVAL (sizes, NaN), PD_ENOMEM, PD_EDEVICE.            */
 pd_status pd_create(const pd_domain* dom, const pd_opts* opts, pd_ctx** out);
 
-/* Charge numbers Z[n] and masses mass[n] (kg) in the species order above;
- * n must be PD_NSPECIES.  Must be called before the first step.       */
+/* Charge numbers Z[n] and masses mass[n] (kg) in the species order above
+ * (the tracked species of Sec. 2.3 with the three Cu2+ labels of Sec. 3);
+ * n must be PD_NSPECIES.  Must be called before the first step.
+ * Errors: PD_EINVAL (n, a mass not positive or a charge outside -8..8,
+ * Cu2+ labels of different charge or mass).                          */
 pd_status pd_set_species(pd_ctx* ctx, int n, const int32_t* Z, const double* mass);
 
 /* Integrated cross section of one channel (Eq. 4's sigma) as a table
@@ -249,16 +254,18 @@ pd_status pd_set_split_literal(pd_ctx* ctx, int32_t on);
  * (ensemble member).                                                   */
 pd_status pd_set_sputtering(pd_ctx* ctx, int32_t on);
 
-/* Append n particles now: positions r, z (0 <= r < R, 0 <= z < L),
- * velocities vr, vt, vz at the half step before their first push
- * (leapfrog), species sp[n].  They receive ids next_id, next_id+1, ...
+/* Append n super-particles now (Sec. 2.1: each stands for weight real
+ * particles): positions r, z (0 <= r < R, 0 <= z < L), velocities vr, vt,
+ * vz at the half step before their first push (leapfrog), species sp[n].
+ * All arrays are caller host memory of length n, read during the call.  They receive ids next_id, next_id+1, ...
  * Errors: PD_EINVAL (non-finite, outside the domain, species >= 8) and
  * PD_ECAPACITY; the context is unchanged on error.                   */
 pd_status pd_inject(pd_ctx* ctx, int64_t n, const double* r, const double* z,
                     const double* vr, const double* vt, const double* vz,
                     const uint8_t* sp);
 
-/* Upload an injection schedule for the next nsteps steps: step k appends
+/* Upload an injection schedule (the cathode spot's particle source of
+ * Sec. 2.3, given as explicit records) for the next nsteps steps: step k appends
  * particles offsets[k] .. offsets[k+1]-1 (offsets[0] = 0) at the end of
  * the step, after absorption, in the order given, with fresh ids.  The
  * whole schedule is copied to device memory now.  Replaces any earlier
@@ -267,9 +274,12 @@ pd_status pd_schedule_injection(pd_ctx* ctx, int nsteps, const int64_t* offsets,
                                 const double* r, const double* z, const double* vr,
                                 const double* vt, const double* vz, const uint8_t* sp);
 
-/* Enqueue nsteps full steps on the context's stream and return.  Step n:
- * sort -> collide -> deposit -> Poisson -> field -> gather+push ->
- * absorb -> inject.  Capacity overflow found on the device is reported
+/* Enqueue nsteps full steps on the context's stream and return.  Step n
+ * (the PIC-DSMC cycle of Sec. 2.1 with the collisions of Secs. 2.2-2.3):
+ * sort -> collide (Eqs. 4-7, 11-15) -> deposit (Eqs. 9-10) -> Poisson
+ * (Eq. 8) -> field -> gather+push -> absorb -> inject.  Needs the species
+ * and, unless collisions are off, the tables of channels PD_EL..PD_SI2
+ * (PD_ESTATE otherwise).  Capacity overflow found on the device is reported
  * by the next call that synchronises (PD_ECAPACITY); the context is then
  * unusable (PD_ESTATE).                                               */
 pd_status pd_step(pd_ctx* ctx, int nsteps);
@@ -277,10 +287,12 @@ pd_status pd_step(pd_ctx* ctx, int nsteps);
 /* Wait for all enqueued work; reports device-side errors.            */
 pd_status pd_synchronize(pd_ctx* ctx);
 
-/* Counts, cumulative events and the snapshot reductions.            */
+/* Counts, cumulative events and the snapshot reductions, among them the
+ * ionization degree and mean ion charge of Eq. 21 (Sec. 3).  out is
+ * caller host memory.                                                 */
 pd_status pd_get_diagnostics(pd_ctx* ctx, pd_diag* out);
 
-/* Kinetic-energy spectrum of one Cu2+ label (tag 0 = step-wise, 1 =
+/* Kinetic-energy spectrum (Sec. 3.3, Figs. 8-9) of one Cu2+ label (tag 0 = step-wise, 1 =
  * direct double ionization, 2 = initial): out[0..63] count particles
  * with 10^(3b/64) <= E/eV < 10^(3(b+1)/64); out[64] counts E < 1 eV,
  * out[65] counts E >= 1000 eV.  E = M |v|^2 / 2 at v(n+1/2).          */
@@ -290,16 +302,19 @@ pd_status pd_get_spectrum(pd_ctx* ctx, int tag, int64_t out[66]);
 pd_status pd_get_count(pd_ctx* ctx, int64_t* n);
 
 /* Copy the alive particles, in the order the next sort receives them,
- * into caller arrays of length >= cap (cap >= count, else PD_EINVAL).
- * key = species * nr * nz + j * nr + i of the particle's cell.  Any
- * pointer may be NULL.                                                */
+ * into caller host arrays of length >= cap (cap >= count, else PD_EINVAL).
+ * key = c * nr * nz + j * nr + i for the particle's cell (i, j) and key
+ * class c (0 electrons, 1 Cu, 2 Cu+, 3 Cu2+ of every label, 4 Cu3+,
+ * 5 Cu4+): the order of the per-cell lists the pairing of Sec. 2.1 draws
+ * from.  Any pointer may be NULL.                                     */
 pd_status pd_get_particles(pd_ctx* ctx, int64_t cap, double* r, double* z, double* vr,
                            double* vt, double* vz, uint8_t* sp, uint32_t* id,
                            uint32_t* key);
 
-/* Potential, field and integer node charge of the last step ((nr+1) *
- * (nz+1) nodes each; Q in units of e * weight * 2^-40).  Any pointer may
- * be NULL.                                                            */
+/* Potential (Eq. 8), field E = -grad(phi) and integer node charge
+ * (Eqs. 9-10) of the last step ((nr+1) * (nz+1) nodes each, node-major
+ * with r fastest, caller host memory; Q in units of e * weight * 2^-40).
+ * Any pointer may be NULL.                                            */
 pd_status pd_get_field(pd_ctx* ctx, double* phi, double* Er, double* Ez, int64_t* Q);
 
 /* Solve the field equation for the node charge Q ((nr+1)*(nz+1) values,
