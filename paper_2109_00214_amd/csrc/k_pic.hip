@@ -473,10 +473,9 @@ __global__ void __launch_bounds__(256) k_push(Flow<T> f, DevState* st, Grid g, S
     }
   const int W = g.nr + 1;
   const bool sub = g.heavy_every > 1;
-  const uint32_t stride = gridDim.x * blockDim.x;
   const PartsT<T>& D = f.S;
-  for (uint32_t p0 = blockIdx.x * blockDim.x; p0 < n; p0 += stride) {
-    const uint32_t p = p0 + threadIdx.x;
+  for (ChunkWalk<64> cw((n + blockDim.x - 1) / blockDim.x); cw.more(); cw.next()) {
+    const uint32_t p = cw.chunk() * blockDim.x + threadIdx.x;
     int code = -1;
     if (p < n) {
       const bool old = p < n_alive;

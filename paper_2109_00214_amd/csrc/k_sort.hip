@@ -235,7 +235,7 @@ __global__ void __launch_bounds__(256) k_radix_down(const uint32_t* __restrict__
   constexpr int R = 1 << DB;
   constexpr uint32_t mask = (uint32_t)R - 1u;
   constexpr int PER = (R + 255) / 256;
-  constexpr int kStage = 256 * kMoverItems;  // short tiles are reordered in LDS
+  constexpr int kStage = 256 * ITM;  // every tile is reordered in LDS
   __shared__ uint32_t wh[4][R];
   __shared__ uint32_t gofs[R];
   __shared__ uint32_t dbase[R];
@@ -246,14 +246,16 @@ __global__ void __launch_bounds__(256) k_radix_down(const uint32_t* __restrict__
   const uint32_t n = *np;
   const int itn = mover_items(n);
   const uint32_t tsz = 256u * (uint32_t)itn;
-  const bool staged = itn == kMoverItems;
   const uint32_t ntiles = (n + tsz - 1) / tsz;
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const bool last = mp.skey != nullptr;
   const uint32_t n_prev = last ? mp.st->n_alive : 0u;
   bool have_base = false;
-  for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  // tiles in runs of eight per XCD: the digit runs of neighbouring tiles
+  // are neighbours in the output, and their partial lines meet in one L2
+  for (ChunkWalk<8> cw(ntiles); cw.more(); cw.next()) {
+    const uint32_t tile = cw.chunk();
     const uint32_t tile0 = tile * tsz;
     const uint32_t base = tile0 + w * (tsz / 4);
     // everything the tile reads from memory is requested first: its keys
@@ -346,12 +348,12 @@ __global__ void __launch_bounds__(256) k_radix_down(const uint32_t* __restrict__
       }
     }
     __syncthreads();
-    if (staged) {
-      // short tile: reordered in LDS so that the stores of a digit run are
+    {
+      // the tile reordered in LDS, so that the stores of a digit run are
       // contiguous
 #pragma unroll
-      for (int it = 0; it < kMoverItems; ++it) {
-        if (base + it * 64 + lane < n) {
+      for (int it = 0; it < ITM; ++it) {
+        if (it < itn && base + it * 64 + lane < n) {
           const uint32_t lp = wh[w][(kk[it] >> shift) & mask] + rk[it];
           tkey[lp] = kk[it];
           tval[lp] = vv[it];
@@ -378,23 +380,6 @@ __global__ void __launch_bounds__(256) k_radix_down(const uint32_t* __restrict__
           mp.ins[p] = ins;
           mp.skey[ins + p] = k;
           mp.perm[ins + p] = i;
-        }
-      }
-    } else {
-      // long tile: each key straight to its place
-#pragma unroll
-      for (int it = 0; it < ITM; ++it) {
-        if (it < itn && base + it * 64 + lane < n) {
-          const uint32_t d = (kk[it] >> shift) & mask;
-          const uint32_t p = gofs[d] + wh[w][d] + rk[it];
-          kout[p] = kk[it];
-          if (!last) {
-            vout[p] = vv[it];
-          } else {
-            mp.ins[p] = in[it];
-            mp.skey[in[it] + p] = kk[it];
-            mp.perm[in[it] + p] = vv[it];
-          }
         }
       }
     }

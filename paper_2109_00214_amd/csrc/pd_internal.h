@@ -54,6 +54,43 @@ __device__ inline void philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3
   out[3] = c3;
 }
 
+// Chunks of a grid-stride loop in XCD order.  The dispatcher hands
+// consecutive workgroups to the eight XCDs in turn, so block b runs on XCD
+// b % 8 and shares that XCD's L2 with the blocks of the same residue.  The
+// chunks are grouped into runs of S, and run g belongs to residue g % 8:
+// blocks that share an L2 work on neighbouring chunks (the particles of a
+// few rows of cells, whose records the movers read across chunks), while
+// every XCD still gets runs from the whole array.  The t-th chunk of a
+// residue is chunk ((t / S) * 8 + x) * S + t % S, increasing in t; every
+// chunk is taken exactly once whatever the placement (with fewer than eight
+// blocks, the plain order).
+template <uint32_t S>
+struct ChunkWalk {
+  uint32_t t, step, x, n;
+  // blocks blk = 0 .. nblk-1 walk the chunks; walk block blk is the
+  // launch's block blk + first, whose index decides its XCD
+  __device__ ChunkWalk(uint32_t nchunks, uint32_t blk, uint32_t nblk, uint32_t first)
+      : n(nchunks) {
+    if (nblk < 8u) {
+      t = blk;
+      step = nblk;
+      x = 8u;  // plain order
+      return;
+    }
+    x = (blk + first) & 7u;
+    const uint32_t r0 = (x - first) & 7u;  // the first walk block of this residue
+    t = (blk - r0) >> 3;
+    step = (nblk - r0 + 7u) >> 3;  // walk blocks of this residue
+  }
+  __device__ explicit ChunkWalk(uint32_t nchunks)
+      : ChunkWalk(nchunks, blockIdx.x, gridDim.x, 0u) {}
+  __device__ uint32_t chunk() const {
+    return x == 8u ? t : ((t / S) * 8u + x) * S + (t % S);
+  }
+  __device__ bool more() const { return chunk() < n; }
+  __device__ void next() { t += step; }
+};
+
 // uniform in [0,1): the top 53 bits of (hi:lo) times 2^-53
 __device__ inline double u53(uint32_t hi, uint32_t lo) {
   const uint64_t b = (((uint64_t)hi << 32) | (uint64_t)lo) >> 11;
