@@ -37,7 +37,7 @@ from collections import defaultdict
 HERE = os.path.dirname(os.path.abspath(__file__))
 # stage -> (kernel name, sources that define it)
 STAGE_KERNELS = {
-    "push": ("pd::k_push<double>", ("csrc/k_pic.hip", "csrc/pd_internal.h")),
+    "push": ("pd::k_push<double, false>", ("csrc/k_pic.hip", "csrc/pd_internal.h")),
     "deposit": ("pd::k_deposit<double>", ("csrc/k_pic.hip", "csrc/pd_internal.h")),
 }
 
@@ -53,7 +53,7 @@ def stage_line(stage, fetch_b, write_b, particles):
     """The summary line of one roofline stage (read back by read_traffic)."""
     k, files = STAGE_KERNELS[stage]
     return "stage %s %s %.0f %.0f %.0f %.0f %.2f %s %s" % (
-        stage, k, fetch_b, write_b, fetch_b + write_b, particles, (fetch_b + write_b) / particles,
+        stage, k.replace(" ", ""), fetch_b, write_b, fetch_b + write_b, particles, (fetch_b + write_b) / particles,
         "+".join(os.path.basename(x) for x in files), source_digest(files))
 
 
