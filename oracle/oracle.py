@@ -37,7 +37,8 @@ class _Diag(C.Structure):
                 ("charge_injected", C.c_int64), ("ke_J", C.c_double * NSPECIES),
                 ("gamma", C.c_double), ("qbar", C.c_double),
                 ("spectrum", (C.c_int64 * 66) * 3), ("V_gap", C.c_double),
-                ("emitted", C.c_int64 * 2), ("sputtered", C.c_int64)]
+                ("emitted", C.c_int64 * 2), ("sputtered", C.c_int64),
+                ("real", C.c_int64 * NSPECIES)]
 
 
 _lib = None
@@ -66,6 +67,8 @@ def load_oracle(path):
     lib.or_set_species.argtypes = [P, C.c_int, P, P]
     lib.or_set_cross_section.argtypes = [P, C.c_int, C.c_double, C.c_int, C.c_double, P]
     lib.or_inject.argtypes = [P, C.c_int64, P, P, P, P, P, P]
+    lib.or_inject_weighted.argtypes = [P, C.c_int64, P, P, P, P, P, P, P]
+    lib.or_get_weights.argtypes = [P, P]
     lib.or_schedule_injection.argtypes = [P, C.c_int, P, P, P, P, P, P, P]
     lib.or_step.argtypes = [P, C.c_int]
     lib.or_set_heavy_subcycle.argtypes = [P, C.c_int]
@@ -156,9 +159,23 @@ class Oracle:
                 for k in ("r", "z", "vr", "vt", "vz")] + [
             np.ascontiguousarray(parts["sp"], dtype=np.uint8)]
 
-    def inject(self, parts):
+    def inject(self, parts, mult=None):
+        """append particles; mult (optional): each one's multiplicity, the
+        number of W-weight units it stands for (unequal weights)"""
         a = self._arrs(parts)
-        self._chk(self.lib.or_inject(self.h, len(a[0]), *[_p(x) for x in a]))
+        if mult is None:
+            self._chk(self.lib.or_inject(self.h, len(a[0]), *[_p(x) for x in a]))
+        else:
+            m = np.ascontiguousarray(mult, dtype=np.uint16)
+            assert len(m) == len(a[0])
+            self._chk(self.lib.or_inject_weighted(self.h, len(a[0]), *[_p(x) for x in a],
+                                                  _p(m)))
+
+    def weights(self):
+        """the multiplicities, in the order of particles()"""
+        out = np.zeros(self.count(), np.uint16)
+        self.lib.or_get_weights(self.h, _p(out))
+        return out
 
     def schedule_injection(self, offsets, parts):
         off = np.ascontiguousarray(offsets, dtype=np.int64)

@@ -89,6 +89,7 @@ struct or_sim {
   int64_t n, cap;
   double *r, *z, *vr, *vt, *vz;
   uint8_t* sp;
+  uint16_t* mult; /* multiplicity: the super-particle stands for mult * W */
   uint32_t *id, *key;
   uint8_t* alive;
   int64_t n_sorted; /* particles present at the sort (before creation) */
@@ -249,7 +250,7 @@ void or_destroy(or_sim* s) {
   free(s->Vnode); free(s->Vcell); free(s->ra); free(s->rb); free(s->rc);
   free(s->S); free(s->mu);
   free(s->r); free(s->z); free(s->vr); free(s->vt); free(s->vz);
-  free(s->sp); free(s->id); free(s->key); free(s->alive);
+  free(s->sp); free(s->mult); free(s->id); free(s->key); free(s->alive);
   free(s->choice); free(s->target); free(s->win); free(s->claim);
   free(s->Q); free(s->phi); free(s->Er); free(s->Ez); free(s->off);
   free(s->sched_off); free(s->s_r); free(s->s_z); free(s->s_vr); free(s->s_vt);
@@ -326,10 +327,11 @@ static void reserve(or_sim* s, int64_t need) {
   s->vt = (double*)realloc(s->vt, sizeof(double) * c);
   s->vz = (double*)realloc(s->vz, sizeof(double) * c);
   s->sp = (uint8_t*)realloc(s->sp, c);
+  s->mult = (uint16_t*)realloc(s->mult, sizeof(uint16_t) * c);
   s->id = (uint32_t*)realloc(s->id, sizeof(uint32_t) * c);
   s->key = (uint32_t*)realloc(s->key, sizeof(uint32_t) * c);
   s->alive = (uint8_t*)realloc(s->alive, c);
-  if (!s->r || !s->z || !s->vr || !s->vt || !s->vz || !s->sp || !s->id ||
+  if (!s->r || !s->z || !s->vr || !s->vt || !s->vz || !s->sp || !s->mult || !s->id ||
       !s->key || !s->alive) { fprintf(stderr, "oracle: out of memory\n"); abort(); }
   s->cap = c;
 }
@@ -372,12 +374,13 @@ static int check_particles(const or_sim* s, int64_t n, const double* r,
 
 static void append(or_sim* s, int64_t n, const double* r, const double* z,
                    const double* vr, const double* vt, const double* vz,
-                   const uint8_t* sp) {
+                   const uint8_t* sp, const uint16_t* mult) {
   reserve(s, s->n + n);
   for (int64_t p = 0; p < n; ++p) {
     int64_t q = s->n + p;
     s->r[q] = r[p]; s->z[q] = z[p]; s->vr[q] = vr[p]; s->vt[q] = vt[p];
     s->vz[q] = vz[p]; s->sp[q] = sp[p];
+    s->mult[q] = mult ? mult[p] : 1;
     s->id[q] = (uint32_t)(s->next_id + p);
     s->key[q] = key_of(s, r[p], z[p], sp[p]);
     s->alive[q] = 1;
@@ -394,7 +397,21 @@ int or_inject(or_sim* s, int64_t n, const double* r, const double* z,
   if (n < 0) return fail("inject: n < 0");
   if (s->next_id + n > (int64_t)UINT32_MAX) return fail("inject: id overflow");
   if (check_particles(s, n, r, z, vr, vt, vz, sp)) return -1;
-  append(s, n, r, z, vr, vt, vz, sp);
+  append(s, n, r, z, vr, vt, vz, sp, NULL);
+  return 0;
+}
+
+/* injection with multiplicities (unequal weights): particle p stands for
+ * mult[p] * W real particles, 1 <= mult[p] <= 65535                      */
+int or_inject_weighted(or_sim* s, int64_t n, const double* r, const double* z,
+                       const double* vr, const double* vt, const double* vz,
+                       const uint8_t* sp, const uint16_t* mult) {
+  if (n < 0) return fail("inject: n < 0");
+  if (s->next_id + n > (int64_t)UINT32_MAX) return fail("inject: id overflow");
+  if (check_particles(s, n, r, z, vr, vt, vz, sp)) return -1;
+  for (int64_t p = 0; p < n; ++p)
+    if (mult[p] < 1) return fail("inject: multiplicity below 1");
+  append(s, n, r, z, vr, vt, vz, sp, mult);
   return 0;
 }
 
@@ -452,6 +469,9 @@ void or_stage_sort(or_sim* s) {
   uint8_t* t8 = (uint8_t*)tmp;
   for (int64_t p = 0; p < n; ++p) t8[p] = s->sp[kv[p] & 0xffffffffu];
   memcpy(s->sp, t8, n);
+  uint16_t* t16 = (uint16_t*)tmp;
+  for (int64_t p = 0; p < n; ++p) t16[p] = s->mult[kv[p] & 0xffffffffu];
+  memcpy(s->mult, t16, sizeof(uint16_t) * n);
   free(tmp);
   free(kv);
   /* CSR offsets over the flattened (key class, cell) key space */
@@ -530,6 +550,28 @@ static void coll_reserve(or_sim* s, int64_t n) {
   s->coll_cap = n;
 }
 
+/* Unequal weights (Sec. 2.2 leaves them to the rejection or the merging
+ * method): an event between super-particles of multiplicities mp and mt
+ * stands for min(mp, mt) real collisions.  The side with the smaller
+ * multiplicity always takes the outcome, the other with probability
+ * min/its own, decided by one draw (purpose 7, draw 0) per event; with
+ * equal multiplicities both sides take it and nothing is drawn.  A target
+ * that takes an ionizing outcome is relabelled as a whole and the electrons
+ * it emits carry its multiplicity, so every ionizing event conserves
+ * charge exactly; charge exchange between unequal multiplicities conserves
+ * it on average only.                                                      */
+static void take_sides(const or_sim* s, uint32_t id, uint32_t mp, uint32_t mt, int* up,
+                       int* ut) {
+  *up = 1;
+  *ut = 1;
+  if (mp == mt) return;
+  uint32_t w[4];
+  draw4(s, id, 7, 0, w);
+  double u = u53(w[0], w[1]);
+  if (mp > mt) *up = u < ((double)mt / (double)mp);
+  else *ut = u < ((double)mp / (double)mt);
+}
+
 void or_stage_collide(or_sim* s) {
   int64_t n = s->n;
   coll_reserve(s, n ? n : 1);
@@ -585,7 +627,8 @@ void or_stage_collide(or_sim* s) {
       double dvz = s->vz[p] - s->vz[tp[c]];
       double g = sqrt(((dvr * dvr) + (dvt * dvt)) + (dvz * dvz));
       double sig = sigma_of(s, k, g);
-      double dens = ((double)nt[c] * s->W) / s->Vcell[ci];
+      /* the cell's count times the picked target's weight */
+      double dens = ((double)nt[c] * ((double)s->mult[tp[c]] * s->W)) / s->Vcell[ci];
       x[e] = ((s->dt * g) * dens) * sig;
       if (k == OR_CEE) x[e] = 0.5 * x[e];
     }
@@ -637,7 +680,7 @@ void or_stage_collide(or_sim* s) {
       double dvt = s->vt[p] - s->vt[tp];
       double dvz = s->vz[p] - s->vz[tp];
       double g = sqrt(((dvr * dvr) + (dvt * dvt)) + (dvz * dvz));
-      double dens = ((double)partners * s->W) / s->Vcell[ci];
+      double dens = ((double)partners * ((double)s->mult[tp] * s->W)) / s->Vcell[ci];
       double x = ((dth * g) * dens) * sigma_of(s, k, g);
       if (hc == 1) x = 0.5 * x;
       double pc = 1.0 - exp(-x);
@@ -679,6 +722,9 @@ void or_stage_collide(or_sim* s) {
     if (!s->win[p]) continue;
     int ch = s->choice[p] - 1;
     uint32_t tp = s->target[p];
+    const uint16_t mt = s->mult[tp];
+    int up, ut;
+    take_sides(s, s->id[p], s->mult[p], mt, &up, &ut);
     double e1[3] = {s->vr[p], s->vt[p], s->vz[p]};
     double A[3] = {s->vr[tp], s->vt[tp], s->vz[tp]};
     double nh[3];
@@ -686,24 +732,27 @@ void or_stage_collide(or_sim* s) {
     /* stage 1: elastic (dE = 0) or inelastic with the channel threshold */
     or_isotropic(s, s->id[p], 2, nh);
     binary(e1, A, s->two_dE_mr[ch], s->f1[ch], s->f2[ch], nh);
-    s->vr[tp] = A[0]; s->vt[tp] = A[1]; s->vz[tp] = A[2];
+    if (ut) { s->vr[tp] = A[0]; s->vt[tp] = A[1]; s->vz[tp] = A[2]; }
     if (ch == OR_EL || ch == OR_CEI || ch == OR_CEE) { /* elastic */
-      s->vr[p] = e1[0]; s->vt[p] = e1[1]; s->vz[p] = e1[2];
+      if (up) { s->vr[p] = e1[0]; s->vt[p] = e1[1]; s->vz[p] = e1[2]; }
       continue;
     }
     /* stage 2: the excited target emits e2, which inherits its position
      * and post-stage-1 velocity; the target keeps its slot and id        */
-    s->sp[tp] = (uint8_t)PRODUCT_OF[ch];
+    if (ut) s->sp[tp] = (uint8_t)PRODUCT_OF[ch];
     double e2[3] = {A[0], A[1], A[2]};
     /* stage 3: e1-e2 elastic, equal masses (m_r/m = 1/2), isotropic    */
     or_isotropic(s, s->id[p], 3, nh);
     binary(e1, e2, 0.0, 0.5, 0.5, nh);
     int64_t q = s->n;
-    s->r[q] = s->r[tp]; s->z[q] = s->z[tp];
-    s->vr[q] = e2[0]; s->vt[q] = e2[1]; s->vz[q] = e2[2];
-    s->sp[q] = OR_E; s->id[q] = (uint32_t)s->next_id; s->alive[q] = 1;
-    s->key[q] = key_of(s, s->r[q], s->z[q], OR_E);
-    s->n += 1; s->next_id += 1; s->created += 1;
+    if (ut) {
+      s->r[q] = s->r[tp]; s->z[q] = s->z[tp];
+      s->vr[q] = e2[0]; s->vt[q] = e2[1]; s->vz[q] = e2[2];
+      s->sp[q] = OR_E; s->mult[q] = mt;
+      s->id[q] = (uint32_t)s->next_id; s->alive[q] = 1;
+      s->key[q] = key_of(s, s->r[q], s->z[q], OR_E);
+      s->n += 1; s->next_id += 1; s->created += 1;
+    }
     if (ch == OR_DI) {
       /* stage 4: e3 splits into two orthogonal edges of the rectangle
        * whose diagonal is v3: v5 = (v3.n)n stays, v6 = v3 - v5 is new;
@@ -723,14 +772,17 @@ void or_stage_collide(or_sim* s) {
       }
       double v6[3] = {e1[0] - v5[0], e1[1] - v5[1], e1[2] - v5[2]};
       e1[0] = v5[0]; e1[1] = v5[1]; e1[2] = v5[2];
-      q = s->n;
-      s->r[q] = s->r[p]; s->z[q] = s->z[p];
-      s->vr[q] = v6[0]; s->vt[q] = v6[1]; s->vz[q] = v6[2];
-      s->sp[q] = OR_E; s->id[q] = (uint32_t)s->next_id; s->alive[q] = 1;
-      s->key[q] = key_of(s, s->r[q], s->z[q], OR_E);
-      s->n += 1; s->next_id += 1; s->created += 1;
+      if (ut) {
+        q = s->n;
+        s->r[q] = s->r[p]; s->z[q] = s->z[p];
+        s->vr[q] = v6[0]; s->vt[q] = v6[1]; s->vz[q] = v6[2];
+        s->sp[q] = OR_E; s->mult[q] = mt;
+        s->id[q] = (uint32_t)s->next_id; s->alive[q] = 1;
+        s->key[q] = key_of(s, s->r[q], s->z[q], OR_E);
+        s->n += 1; s->next_id += 1; s->created += 1;
+      }
     }
-    s->vr[p] = e1[0]; s->vt[p] = e1[1]; s->vz[p] = e1[2];
+    if (up) { s->vr[p] = e1[0]; s->vt[p] = e1[1]; s->vz[p] = e1[2]; }
   }
 
   /* heavy events: charge exchange passes the charge from the ion to the
@@ -741,11 +793,13 @@ void or_stage_collide(or_sim* s) {
     if (!s->win[p]) continue;
     int ch = s->choice[p] - 1;
     uint32_t tp = s->target[p];
+    int up, ut;
+    take_sides(s, s->id[p], s->mult[p], s->mult[tp], &up, &ut);
     s->events[ch] += 1;
     if (ch == OR_CEX) {
-      uint8_t a = s->sp[p];
-      s->sp[p] = s->sp[tp];
-      s->sp[tp] = a;
+      uint8_t a = s->sp[p], b = s->sp[tp];
+      if (up) s->sp[p] = b;
+      if (ut) s->sp[tp] = a;
       continue;
     }
     double A[3] = {s->vr[p], s->vt[p], s->vz[p]};
@@ -753,8 +807,8 @@ void or_stage_collide(or_sim* s) {
     double nh[3];
     or_isotropic(s, s->id[p], 2, nh);
     binary(A, B, 0.0, s->f1[ch], s->f2[ch], nh);
-    s->vr[p] = A[0]; s->vt[p] = A[1]; s->vz[p] = A[2];
-    s->vr[tp] = B[0]; s->vt[tp] = B[1]; s->vz[tp] = B[2];
+    if (up) { s->vr[p] = A[0]; s->vt[p] = A[1]; s->vz[p] = A[2]; }
+    if (ut) { s->vr[tp] = B[0]; s->vt[tp] = B[1]; s->vz[tp] = B[2]; }
   }
 }
 
@@ -772,7 +826,7 @@ void or_stage_deposit(or_sim* s) {
     cell_of(s, s->r[p], s->z[p], &i, &j, &fr, &fz);
     int64_t ar = (int64_t)floor((fr * 1048576.0) + 0.5), br = 1048576 - ar;
     int64_t az = (int64_t)floor((fz * 1048576.0) + 0.5), bz = 1048576 - az;
-    int64_t Zp = s->Z[s->sp[p]];
+    int64_t Zp = s->Z[s->sp[p]] * (int64_t)s->mult[p]; /* W_alpha of Eq. 9 */
     int64_t b = (int64_t)j * (nr + 1) + i;
     s->Q[b] += Zp * (br * bz);
     s->Q[b + 1] += Zp * (ar * bz);
@@ -1153,7 +1207,7 @@ static void sputter_emit(or_sim* s) {
         a[4 * tot + k] = sqrt(((2.0 * E) * Q_E) / s->m[OR_CU]);
         sp[k] = OR_CU;
       }
-    append(s, tot, a, a + tot, a + 2 * tot, a + 3 * tot, a + 4 * tot, sp);
+    append(s, tot, a, a + tot, a + 2 * tot, a + 3 * tot, a + 4 * tot, sp, NULL);
     free(a); free(sp);
   }
   s->sputtered += tot;
@@ -1218,7 +1272,7 @@ static void emit(or_sim* s) {
         sp[k] = OR_CU;
       }
     }
-    append(s, tot, a, a + tot, a + 2 * tot, a + 3 * tot, a + 4 * tot, sp);
+    append(s, tot, a, a + tot, a + 2 * tot, a + 3 * tot, a + 4 * tot, sp, NULL);
     free(a); free(sp);
   }
   s->emitted[0] += ne;
@@ -1232,6 +1286,7 @@ void or_stage_compact_inject(or_sim* s) {
     if (!s->alive[p]) continue;
     s->r[w] = s->r[p]; s->z[w] = s->z[p]; s->vr[w] = s->vr[p];
     s->vt[w] = s->vt[p]; s->vz[w] = s->vz[p]; s->sp[w] = s->sp[p];
+    s->mult[w] = s->mult[p];
     s->id[w] = s->id[p]; s->key[w] = s->key[p]; s->alive[w] = 1;
     ++w;
   }
@@ -1239,7 +1294,7 @@ void or_stage_compact_inject(or_sim* s) {
   if (s->sched_pos < s->sched_n) {
     int64_t a = s->sched_off[s->sched_pos], b = s->sched_off[s->sched_pos + 1];
     append(s, b - a, s->s_r + a, s->s_z + a, s->s_vr + a, s->s_vt + a, s->s_vz + a,
-           s->s_sp + a);
+           s->s_sp + a, NULL);
     s->sched_pos += 1;
   }
   emit(s);
@@ -1278,6 +1333,10 @@ void or_get_particles(const or_sim* s, double* r, double* z, double* vr,
   memcpy(vr, s->vr, sizeof(double) * n); memcpy(vt, s->vt, sizeof(double) * n);
   memcpy(vz, s->vz, sizeof(double) * n); memcpy(sp, s->sp, n);
   memcpy(id, s->id, sizeof(uint32_t) * n); memcpy(key, s->key, sizeof(uint32_t) * n);
+}
+
+void or_get_weights(const or_sim* s, uint16_t* mult) {
+  memcpy(mult, s->mult, sizeof(uint16_t) * s->n);
 }
 
 void or_set_velocities(or_sim* s, const double* vr, const double* vt, const double* vz) {
@@ -1323,6 +1382,7 @@ void or_get_diag(const or_sim* s, or_diag* d) {
   for (int64_t p = 0; p < s->n; ++p) {
     int sp = s->sp[p];
     d->count[sp] += 1;
+    d->real[sp] += s->mult[p];
     d->charge_alive += s->Z[sp];
     double v2 = ((s->vr[p] * s->vr[p]) + (s->vt[p] * s->vt[p])) + (s->vz[p] * s->vz[p]);
     d->ke_J[sp] += (0.5 * s->m[sp]) * v2;
@@ -1338,9 +1398,9 @@ void or_get_diag(const or_sim* s, or_diag* d) {
   /* Eq. 21 over the charge states q = 0..4 (N_2 counts every Cu2+ tag):
    * gamma = sum_{q>=1} N_q / sum_q N_q, qbar = sum_q q N_q / sum_{q>=1} N_q;
    * the counts are summed as integers, each ratio is one division        */
-  int64_t N[5] = {d->count[OR_CU], d->count[OR_CU1],
-                  d->count[OR_CU2_STEP] + d->count[OR_CU2_DOUBLE] + d->count[OR_CU2_INIT],
-                  d->count[OR_CU3], d->count[OR_CU4]};
+  int64_t N[5] = {d->real[OR_CU], d->real[OR_CU1],
+                  d->real[OR_CU2_STEP] + d->real[OR_CU2_DOUBLE] + d->real[OR_CU2_INIT],
+                  d->real[OR_CU3], d->real[OR_CU4]};
   int64_t ions = N[1] + N[2] + N[3] + N[4];
   int64_t qsum = N[1] + 2 * N[2] + 3 * N[3] + 4 * N[4];
   d->gamma = (ions + N[0]) > 0 ? (double)ions / (double)(ions + N[0]) : 0.0;

@@ -60,6 +60,8 @@ typedef struct {
   double V_gap;            /* the gap voltage the next Poisson solve uses */
   int64_t emitted[2];      /* cumulative super-particles emitted: electrons, atoms */
   int64_t sputtered;       /* cumulative Cu atoms sputtered from the cathode */
+  int64_t real[OR_NSPECIES]; /* sum of the multiplicities (real particles / W);
+                              * Eq. 21 is taken over these */
 } or_diag;
 
 or_sim* or_create(int nr, int nz, double R, double L, double V, double dt,
@@ -74,6 +76,13 @@ int or_set_cross_section(or_sim* s, int channel, double threshold_eV, int n,
 int or_inject(or_sim* s, int64_t n, const double* r, const double* z,
               const double* vr, const double* vt, const double* vz,
               const uint8_t* sp);
+/* unequal weights: particle p stands for mult[p] * W real particles
+ * (1 <= mult <= 65535); or_inject gives every particle multiplicity 1, as
+ * do the schedule, the emission and the sputtering                        */
+int or_inject_weighted(or_sim* s, int64_t n, const double* r, const double* z,
+                       const double* vr, const double* vt, const double* vz,
+                       const uint8_t* sp, const uint16_t* mult);
+void or_get_weights(const or_sim* s, uint16_t* mult);
 int or_schedule_injection(or_sim* s, int nsteps, const int64_t* offsets,
                           const double* r, const double* z, const double* vr,
                           const double* vt, const double* vz, const uint8_t* sp);
