@@ -166,6 +166,10 @@ typedef struct {
                                   * in injected) */
   int64_t sputtered;             /* cumulative Cu atoms sputtered from the
                                   * cathode (also counted in injected) */
+  int64_t real[PD_NSPECIES];     /* sums of the multiplicities per species:
+                                  * real particles in units of weight (equal
+                                  * to count without multiplicities); gamma
+                                  * and qbar are taken over these */
 } pd_diag;
 
 /* Create a context on the current HIP device for the r-z domain of the
@@ -263,6 +267,42 @@ pd_status pd_set_sputtering(pd_ctx* ctx, int32_t on);
 pd_status pd_inject(pd_ctx* ctx, int64_t n, const double* r, const double* z,
                     const double* vr, const double* vt, const double* vz,
                     const uint8_t* sp);
+
+/* Unequal weights (Sec. 2.2 names the rejection and the merging method for
+ * super-particles of different weights; this is the rejection reading).
+ * pd_set_weighted(ctx, 1) gives every record a multiplicity mu (1 for the
+ * particles present; the records then stand for mu * weight real
+ * particles); it cannot be turned off.  With multiplicities:
+ *   - the deposit weights each particle's charge by mu (Eq. 9's W_alpha);
+ *   - Eq. 4's target density is the cell's count times the picked target's
+ *     weight mu_t * weight;
+ *   - an event stands for min(mu_p, mu_t) real collisions: the side with
+ *     the smaller multiplicity always takes the outcome, the other with
+ *     probability min/its own (one Philox draw of the projectile, purpose
+ *     7, draw 0); a target that takes an ionizing outcome is relabelled
+ *     whole and the electrons it emits carry its multiplicity, so ionizing
+ *     events conserve charge exactly (charge exchange between unequal
+ *     multiplicities conserves it on average only);
+ *   - scheduled, emitted and sputtered particles have multiplicity 1;
+ *   - the counters of pd_diag stay counts of records (super-particles),
+ *     real[] sums the multiplicities and Eq. 21 is taken over real[].
+ * FP64 record only; not with the circuit (its current counts records).
+ * With every mu = 1 the results are bit-identical to a context without
+ * multiplicities.  Errors: PD_EINVAL (FP32, circuit on, on = 0 after on),
+ * PD_ENOMEM, PD_ESTATE (in an ensemble).                                 */
+pd_status pd_set_weighted(pd_ctx* ctx, int32_t on);
+
+/* pd_inject with multiplicities mu[n] (1 <= mu <= 65535), caller host
+ * memory; needs pd_set_weighted.  Errors as pd_inject, and PD_EINVAL for a
+ * multiplicity of 0, PD_ESTATE without multiplicities.                   */
+pd_status pd_inject_weighted(pd_ctx* ctx, int64_t n, const double* r, const double* z,
+                             const double* vr, const double* vt, const double* vz,
+                             const uint8_t* sp, const uint16_t* mu);
+
+/* The multiplicities of the alive particles, in the order of
+ * pd_get_particles, into a caller host array of length >= cap (all 1
+ * without multiplicities).  Errors: PD_EINVAL (NULL, cap too small).     */
+pd_status pd_get_weights(pd_ctx* ctx, int64_t cap, uint16_t* mu);
 
 /* Upload an injection schedule (the cathode spot's particle source of
  * Sec. 2.3, given as explicit records) for the next nsteps steps: step k appends

@@ -120,6 +120,27 @@ __device__ inline void binary(double v1[3], double v2[3], double two_dE_mr, doub
   }
 }
 
+// Unequal weights (Sec. 2.2 leaves them to the rejection or the merging
+// method; this is the rejection reading): an event between records of
+// multiplicities mp (projectile) and mt (target) stands for min(mp, mt) real
+// collisions.  The side with the smaller multiplicity always takes the
+// outcome, the other with probability min/its own, from one draw of the
+// projectile (purpose 7, draw 0).  The decision leaves the answer in the
+// choice byte: kNoProjectile / kNoTarget mark a side that keeps its state
+// (equal multiplicities draw nothing and mark nothing).  A target that takes
+// an ionizing outcome is relabelled whole and its electrons carry its
+// multiplicity.
+constexpr uint32_t kChannelBits = 0x1Fu, kNoProjectile = 0x20u, kNoTarget = 0x40u;
+__device__ inline uint32_t side_bits(const CollideParams& cp, uint32_t id, uint32_t step,
+                                     uint32_t mp, uint32_t mt) {
+  if (mp == mt) return 0u;
+  uint32_t w[4];
+  philox(id, 0u, step, 7u << 24, cp.seed_lo, cp.seed_hi, w);
+  const double u = u53(w[0], w[1]);
+  if (mp > mt) return (u < ((double)mt / (double)mp)) ? 0u : kNoProjectile;
+  return (u < ((double)mp / (double)mt)) ? 0u : kNoTarget;
+}
+
 // the heavy-projectile channels run on this step (a table is set and the
 // sort marked a heavy step)
 __device__ inline bool heavy_trials(const CollideParams& cp, const DevState* st) {
@@ -165,13 +186,17 @@ __global__ void __launch_bounds__(256) k_decide(Flow<T> f, const uint32_t* off, 
     const double evr = ev.vr, evt = ev.vt, evz = ev.vz;
     double x[kNEC] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     const double Vc = cp.Vcell[ci];
+    // the weight the density counts per candidate: the picked target's
+    auto wt = [&](uint32_t tpos) {
+      return P.mu ? (double)P.mu[f.perm[tpos]] * cp.W : cp.W;
+    };
     // Cu target: EL, SI, DI share the pick and the relative speed
     if (n_cu > 0) {
       const RecT<T> tv = P.v[f.perm[tc]];
       const double dvr = evr - (double)tv.vr, dvt = evt - (double)tv.vt,
                    dvz = evz - (double)tv.vz;
       const double gg = sqrt(((dvr * dvr) + (dvt * dvt)) + (dvz * dvz));
-      const double dens = ((double)n_cu * cp.W) / Vc;
+      const double dens = ((double)n_cu * wt(tc)) / Vc;
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         if (k == 2 && !cp.enable_di) continue;
@@ -183,7 +208,7 @@ __global__ void __launch_bounds__(256) k_decide(Flow<T> f, const uint32_t* off, 
       const double dvr = evr - (double)tv.vr, dvt = evt - (double)tv.vt,
                    dvz = evz - (double)tv.vz;
       const double gg = sqrt(((dvr * dvr) + (dvt * dvt)) + (dvz * dvz));
-      const double dens = ((double)n_c1 * cp.W) / Vc;
+      const double dens = ((double)n_c1 * wt(t1)) / Vc;
       x[3] = ((cp.dt * gg) * dens) * sigma_of(cp, 3, gg);
       // Coulomb with the same Cu+ (position 6)
       if (cp.coulomb && cp.tabn[kCEI] > 0) x[6] = ((cp.dt * gg) * dens) * sigma_of(cp, kCEI, gg);
@@ -204,7 +229,7 @@ __global__ void __launch_bounds__(256) k_decide(Flow<T> f, const uint32_t* off, 
           const double dvr = evr - (double)tv.vr, dvt = evt - (double)tv.vt,
                        dvz = evz - (double)tv.vz;
           const double gg = sqrt(((dvr * dvr) + (dvt * dvt)) + (dvz * dvz));
-          const double dens = ((double)nt * cp.W) / Vc;
+          const double dens = ((double)nt * wt(tp)) / Vc;
           x[k] = ((cp.dt * gg) * dens) * sigma_of(cp, k, gg);
         }
       }
@@ -225,7 +250,7 @@ __global__ void __launch_bounds__(256) k_decide(Flow<T> f, const uint32_t* off, 
         const double dvr = evr - (double)tv.vr, dvt = evt - (double)tv.vt,
                      dvz = evz - (double)tv.vz;
         const double gg = sqrt(((dvr * dvr) + (dvt * dvt)) + (dvz * dvz));
-        const double dens = ((double)n0 * cp.W) / Vc;
+        const double dens = ((double)n0 * wt(te)) / Vc;
         x[7] = 0.5 * (((cp.dt * gg) * dens) * sigma_of(cp, kCEE, gg));
       }
     }
@@ -255,7 +280,8 @@ __global__ void __launch_bounds__(256) k_decide(Flow<T> f, const uint32_t* off, 
                         : (ch == 5)              ? t3
                         : (ch == kCEE)           ? te
                                                  : tc;
-      choice[e] = (uint8_t)(ch + 1);
+      const uint32_t side = P.mu ? side_bits(cp, id, step, P.mu[pe], P.mu[f.perm[tp]]) : 0u;
+      choice[e] = (uint8_t)((uint32_t)(ch + 1) | side);
       target[e] = tp;
       atomicMin(&claim[tp], e);
       if (cp.cee) atomicMin(&claim[e], e);
@@ -292,12 +318,15 @@ __global__ void __launch_bounds__(256) k_decide(Flow<T> f, const uint32_t* off, 
     const double dvr = (double)pv.vr - (double)tv.vr, dvt = (double)pv.vt - (double)tv.vt,
                  dvz = (double)pv.vz - (double)tv.vz;
     const double gg = sqrt(((dvr * dvr) + (dvt * dvt)) + (dvz * dvz));
-    const double dens = ((double)partners * cp.W) / cp.Vcell[ci];
+    const double wgt = P.mu ? (double)P.mu[f.perm[tp]] * cp.W : cp.W;
+    const double dens = ((double)partners * wgt) / cp.Vcell[ci];
     double x = ((cp.dt_heavy * gg) * dens) * sigma_of(cp, k, gg);
     if (nn) x = 0.5 * x;
     const double pc = 1.0 - exp(-x);
     if (R1 < pc) {
-      choice[p] = (uint8_t)(k + 1);
+      const uint32_t side =
+          P.mu ? side_bits(cp, pv.id, step, P.mu[f.perm[p]], P.mu[f.perm[tp]]) : 0u;
+      choice[p] = (uint8_t)((uint32_t)(k + 1) | side);
       target[p] = tp;
       atomicMin(&claim[tp], p);
       atomicMin(&claim[p], p);
@@ -328,8 +357,10 @@ __global__ void __launch_bounds__(256) k_resolve(const uint32_t* off, DevState* 
       const uint32_t c = choice[e];
       if (c) {
         if (claim[target[e]] == e && (!cp.cee || claim[e] == e)) {
-          ch = (int)c - 1;
-          cnt = (ch == 0 || ch == kCEI || ch == kCEE) ? 0u : (ch == 2 ? 2u : 1u);
+          ch = (int)(c & kChannelBits) - 1;
+          // a target that keeps its state emits nothing
+          cnt = (ch == 0 || ch == kCEI || ch == kCEE || (c & kNoTarget)) ? 0u
+                                                                          : (ch == 2 ? 2u : 1u);
         } else {
           lost = true;
           // with electron-electron collisions the apply resets the claims
@@ -363,7 +394,7 @@ __global__ void __launch_bounds__(256) k_resolve(const uint32_t* off, DevState* 
         const uint32_t c = choice[p];
         if (c) {
           if (claim[target[p]] == p && claim[p] == p) {
-            ch = (int)c - 1;
+            ch = (int)(c & kChannelBits) - 1;
           } else {
             lost = true;
             choice[p] = (uint8_t)(c | 0x80u);
@@ -443,7 +474,8 @@ __global__ void __launch_bounds__(256) k_apply(Flow<T> f, const uint32_t* off, D
         continue;
       }
       if (cp.cee) claim[e] = 0xFFFFFFFFu;
-      const int ch = (int)c - 1;
+      const int ch = (int)(c & kChannelBits) - 1;
+      const bool up = !(c & kNoProjectile), ut = !(c & kNoTarget);  // the sides that take it
       const uint32_t pe = f.perm[e], pt = f.perm[tp];
       const RecT<T> ve = P.v[pe];
       RecT<T> vt = P.v[pt];
@@ -459,25 +491,26 @@ __global__ void __launch_bounds__(256) k_apply(Flow<T> f, const uint32_t* off, D
       vt.vt = (T)A[1];
       vt.vz = (T)A[2];
       if (ch == 0 || ch == kCEI || ch == kCEE) {  // elastic
-        P.v[pt] = vt;
+        if (ut) P.v[pt] = vt;
         RecT<T> v1 = ve;
         v1.vr = (T)e1[0];
         v1.vt = (T)e1[1];
         v1.vz = (T)e1[2];
-        P.v[pe] = v1;
+        if (up) P.v[pe] = v1;
         continue;
       }
       // stage 2 (Eq. 13): the target keeps its slot and id, changes label;
       // the new electron e2 takes the target's position and velocity
       const int sp_old = (int)vt.sp, sp_new = (int)product_of(ch, vt.sp);
       vt.sp = (uint32_t)sp_new;
-      P.v[pt] = vt;
+      const long long mt = P.mu ? (long long)P.mu[pt] : 1ll;  // the target's multiplicity
+      if (ut) P.v[pt] = vt;
       const PosT<T> xt = P.x[pt];
-      if (Q) {
+      if (Q && ut) {
         // the deposit counted the target with its old charge and none of
         // the new electrons: add the target's change with e2 (at the target)
         // and, for e6, one electron at the primary's place
-        const long long zt = (long long)spp.Z[sp_new] - spp.Z[sp_old] + spp.Z[0];
+        const long long zt = ((long long)spp.Z[sp_new] - spp.Z[sp_old] + spp.Z[0]) * mt;
         long long v[4];
         if (zt) {
           const int b = cic_fixed<T>(g, xt.r, xt.z, v);
@@ -486,7 +519,7 @@ __global__ void __launch_bounds__(256) k_apply(Flow<T> f, const uint32_t* off, D
         if (ch == 2) {
           const PosT<T> xe = P.x[pe];
           const int b = cic_fixed<T>(g, xe.r, xe.z, v);
-          cic_atomic(Q, b, g.nr + 1, (long long)spp.Z[0], v);
+          cic_atomic(Q, b, g.nr + 1, (long long)spp.Z[0] * mt, v);
         }
       }
       double e2[3] = {A[0], A[1], A[2]};
@@ -495,8 +528,11 @@ __global__ void __launch_bounds__(256) k_apply(Flow<T> f, const uint32_t* off, D
       binary(e1, e2, 0.0, 0.5, 0.5, nh);
       const uint32_t slot = n_alive + cbase;
       const uint32_t nid = next_id + cbase;
-      S.x[slot] = xt;
-      S.v[slot] = RecT<T>{(T)e2[0], (T)e2[1], (T)e2[2], nid, 0u};
+      if (ut) {
+        S.x[slot] = xt;
+        S.v[slot] = RecT<T>{(T)e2[0], (T)e2[1], (T)e2[2], nid, 0u};
+        if (S.mu) S.mu[slot] = (uint16_t)mt;
+      }
       if (ch == 2) {
         // stage 4 (Eq. 15): e3 splits into the two orthogonal edges of the
         // rectangle whose diagonal is v3
@@ -515,10 +551,13 @@ __global__ void __launch_bounds__(256) k_apply(Flow<T> f, const uint32_t* off, D
           v5[1] = d * nh[1];
           v5[2] = d * nh[2];
         }
-        const uint32_t s6 = slot + 1;
-        S.x[s6] = P.x[pe];
-        S.v[s6] = RecT<T>{(T)(e1[0] - v5[0]), (T)(e1[1] - v5[1]), (T)(e1[2] - v5[2]), nid + 1,
-                          0u};
+        if (ut) {
+          const uint32_t s6 = slot + 1;
+          S.x[s6] = P.x[pe];
+          S.v[s6] = RecT<T>{(T)(e1[0] - v5[0]), (T)(e1[1] - v5[1]), (T)(e1[2] - v5[2]),
+                            nid + 1, 0u};
+          if (S.mu) S.mu[s6] = (uint16_t)mt;
+        }
         e1[0] = v5[0];
         e1[1] = v5[1];
         e1[2] = v5[2];
@@ -527,7 +566,7 @@ __global__ void __launch_bounds__(256) k_apply(Flow<T> f, const uint32_t* off, D
       v1.vr = (T)e1[0];
       v1.vt = (T)e1[1];
       v1.vz = (T)e1[2];
-      P.v[pe] = v1;
+      if (up) P.v[pe] = v1;
     }
   }
   // heavy events (disjoint from every other event); every heavy trial that
@@ -540,23 +579,32 @@ __global__ void __launch_bounds__(256) k_apply(Flow<T> f, const uint32_t* off, D
     if (!c) continue;
     const uint32_t tp = target[p];
     if (!(c & 0x80u)) {
-      const int ch = (int)c - 1;
+      const int ch = (int)(c & kChannelBits) - 1;
+      const bool up = !(c & kNoProjectile), ut = !(c & kNoTarget);
       const uint32_t pp = f.perm[p], pt = f.perm[tp];
       RecT<T> a = P.v[pp], b = P.v[pt];
       if (ch == kCEX) {
         // the charge passes from the ion to the atom: the labels swap, the
-        // charge moves from the projectile's place to the target's
-        const uint32_t sa = a.sp;
-        a.sp = b.sp;
-        b.sp = sa;
+        // charge moves from the projectile's place to the target's (each
+        // side that takes the outcome with its own multiplicity)
+        const uint32_t sa = a.sp, sb = b.sp;
+        if (up) a.sp = sb;
+        if (ut) b.sp = sa;
         if (Q) {
           long long v[4];
           const PosT<T> xa = P.x[pp], xb = P.x[pt];
-          const long long dzp = (long long)spp.Z[a.sp] - spp.Z[b.sp];
-          int bn = cic_fixed<T>(g, xa.r, xa.z, v);
-          cic_atomic(Q, bn, g.nr + 1, dzp, v);
-          bn = cic_fixed<T>(g, xb.r, xb.z, v);
-          cic_atomic(Q, bn, g.nr + 1, -dzp, v);
+          const long long dzp = (long long)spp.Z[sb] - spp.Z[sa];
+          const long long ma = P.mu ? (long long)P.mu[pp] : 1ll;
+          const long long mb = P.mu ? (long long)P.mu[pt] : 1ll;
+          int bn;
+          if (up) {
+            bn = cic_fixed<T>(g, xa.r, xa.z, v);
+            cic_atomic(Q, bn, g.nr + 1, dzp * ma, v);
+          }
+          if (ut) {
+            bn = cic_fixed<T>(g, xb.r, xb.z, v);
+            cic_atomic(Q, bn, g.nr + 1, -dzp * mb, v);
+          }
         }
       } else {
         // elastic, equal masses, isotropic in the centre-of-mass frame
@@ -571,8 +619,8 @@ __global__ void __launch_bounds__(256) k_apply(Flow<T> f, const uint32_t* off, D
         b.vt = (T)B[1];
         b.vz = (T)B[2];
       }
-      P.v[pp] = a;
-      P.v[pt] = b;
+      if (up) P.v[pp] = a;
+      if (ut) P.v[pt] = b;
     }
     claim[tp] = 0xFFFFFFFFu;
     claim[p] = 0xFFFFFFFFu;

@@ -306,6 +306,7 @@ __device__ inline void inject_records(const PartsT<T>& P, const DevState* st, co
     }
     P.x[d] = PosT<T>{r, z};
     P.v[d] = v;
+    if (P.mu) P.mu[d] = 1u;  // scheduled, emitted and sputtered particles stand for W
     int i, j;
     T fr, fz;
     cell_of<T>(g, r, z, i, j, fr, fz);
@@ -516,6 +517,7 @@ __global__ void __launch_bounds__(256) k_push(Flow<T> f, DevState* st, Grid g, S
       }
       D.x[p] = PosT<T>{rn, z};
       D.v[p] = RecT<T>{vr, vt, vz, v0.id, v0.sp};
+      if (D.mu) D.mu[p] = P.mu[q];
       int bnd = -1;
       if (z < (T)0) bnd = 0;
       else if (!(z < (T)g.L)) bnd = 1;
@@ -580,6 +582,7 @@ __global__ void __launch_bounds__(256) k_append(PartsT<T> P, const DevState* st,
     v.id = id0 + q;
     P.x[d] = x;
     P.v[d] = v;
+    if (P.mu) P.mu[d] = src.mu ? src.mu[q] : (uint16_t)1u;
     int i, j;
     T fr, fz;
     cell_of<T>(g, r, z, i, j, fr, fz);
@@ -612,11 +615,12 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_diag(PartsT<T> P, const DevState* st, Grid g,
                                               SpeciesParams spp, const double* edges,
                                               unsigned long long* counts, double* ke,
-                                              unsigned long long* spec) {
-  __shared__ unsigned long long sc[kNS];
+                                              unsigned long long* spec,
+                                              unsigned long long* real) {
+  __shared__ unsigned long long sc[kNS], sm[kNS];
   __shared__ double sk[256][kNS];
   const uint32_t n = st->n_total;
-  if (threadIdx.x < kNS) sc[threadIdx.x] = 0;
+  if (threadIdx.x < kNS) sc[threadIdx.x] = sm[threadIdx.x] = 0;
   double acc[kNS] = {0, 0, 0, 0, 0, 0, 0, 0};
   __syncthreads();
   for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
@@ -624,6 +628,7 @@ __global__ void __launch_bounds__(256) k_diag(PartsT<T> P, const DevState* st, G
     const RecT<T> v = P.v[p];
     const int s = (int)v.sp;
     atomicAdd(&sc[s], 1ull);
+    atomicAdd(&sm[s], P.mu ? (unsigned long long)P.mu[p] : 1ull);  // real particles / W
     const double vr = v.vr, vt = v.vt, vz = v.vz;
     const double v2 = ((vr * vr) + (vt * vt)) + (vz * vz);
     acc[s] += (0.5 * spp.m[s]) * v2;
@@ -651,20 +656,23 @@ __global__ void __launch_bounds__(256) k_diag(PartsT<T> P, const DevState* st, G
     for (int q = 0; q < 256; ++q) t += sk[q][threadIdx.x];
     ke[blockIdx.x * kNS + threadIdx.x] = t;
     counts[blockIdx.x * kNS + threadIdx.x] = sc[threadIdx.x];
+    real[blockIdx.x * kNS + threadIdx.x] = sm[threadIdx.x];
   }
 }
 
 template <typename T>
 void diag_snapshot(const PartsT<T>& P, const DevState* st, const Grid& g, const SpeciesParams& sp,
                    const double* edges, unsigned long long* counts, double* ke,
-                   unsigned long long* spec, hipStream_t s) {
-  k_diag<T><<<kDiagBlocks, 256, 0, s>>>(P, st, g, sp, edges, counts, ke, spec);
+                   unsigned long long* spec, unsigned long long* real, hipStream_t s) {
+  k_diag<T><<<kDiagBlocks, 256, 0, s>>>(P, st, g, sp, edges, counts, ke, spec, real);
 }
 template void diag_snapshot<double>(const Parts&, const DevState*, const Grid&,
                                     const SpeciesParams&, const double*, unsigned long long*,
-                                    double*, unsigned long long*, hipStream_t);
+                                    double*, unsigned long long*, unsigned long long*,
+                                    hipStream_t);
 template void diag_snapshot<float>(const PartsF&, const DevState*, const Grid&,
                                    const SpeciesParams&, const double*, unsigned long long*,
-                                   double*, unsigned long long*, hipStream_t);
+                                   double*, unsigned long long*, unsigned long long*,
+                                   hipStream_t);
 
 }  // namespace pd

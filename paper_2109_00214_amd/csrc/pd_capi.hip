@@ -30,6 +30,7 @@ struct pd_ctx {
   bool own_stream = false;
   std::string err;
   bool poisoned = false;
+  bool weighted = false;  // the records carry multiplicities (A.mu, B.mu)
 
   Grid g{};
   SpeciesParams spp{};
@@ -54,6 +55,7 @@ struct pd_ctx {
   double* d_xs[kNC] = {};
   double* d_edges = nullptr;
   unsigned long long* d_dcount = nullptr;
+  unsigned long long* d_dreal = nullptr;  // per-block sums of multiplicities
   double* d_dke = nullptr;
   unsigned long long* d_spec = nullptr;
   unsigned long long* sput = nullptr;  // cathode sputtering: yields per annulus (2^-32 units)
@@ -578,7 +580,8 @@ void host_after_step(pd_ctx* c) {
 template <class T>
 pd_status stage_append(pd_ctx* c, const PartsT<T>& A, const PartsT<T>& B, int64_t n,
                               const double* r, const double* z, const double* vr,
-                              const double* vt, const double* vz, const uint8_t* sp) {
+                              const double* vt, const double* vz, const uint8_t* sp,
+                              const uint16_t* mu) {
   std::vector<PosT<T>> x((size_t)n);
   std::vector<RecT<T>> v((size_t)n);
   for (int64_t p = 0; p < n; ++p) {
@@ -587,6 +590,11 @@ pd_status stage_append(pd_ctx* c, const PartsT<T>& A, const PartsT<T>& B, int64_
   }
   HIPCHK(c, hipMemcpy(B.x, x.data(), sizeof(PosT<T>) * n, hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(B.v, v.data(), sizeof(RecT<T>) * n, hipMemcpyHostToDevice));
+  if (B.mu) {
+    std::vector<uint16_t> m((size_t)n, (uint16_t)1);
+    if (mu) std::memcpy(m.data(), mu, sizeof(uint16_t) * (size_t)n);
+    HIPCHK(c, hipMemcpy(B.mu, m.data(), sizeof(uint16_t) * n, hipMemcpyHostToDevice));
+  }
   append(A, c->st, c->g, B, (uint32_t)n, c->stream);
   HIPCHK(c, hipGetLastError());
   return PD_OK;
@@ -735,6 +743,7 @@ pd_status pd_create(const pd_domain* dom, const pd_opts* opts, pd_ctx** out) {
       (s = dalloc(c, &c->fw.g, (size_t)M * (nr + 1))) || (s = dalloc(c, &c->st, 1)) ||
       (s = dalloc(c, &c->off, (size_t)c->g.sentinel + 1)) || (s = dalloc(c, &c->d_edges, 65)) ||
       (s = dalloc(c, &c->d_dcount, (size_t)kDiagBlocks * kNS)) ||
+      (s = dalloc(c, &c->d_dreal, (size_t)kDiagBlocks * kNS)) ||
       (s = dalloc(c, &c->d_dke, (size_t)kDiagBlocks * kNS)) ||
       (s = dalloc(c, &c->d_spec, 3 * 66)) || (s = dalloc(c, &c->sput, (size_t)nr + 1)) ||
       (s = dalloc(c, &c->sput_take, (size_t)nr + 1)))
@@ -930,6 +939,8 @@ pd_status pd_set_circuit(pd_ctx* c, double V0, double R, double C) {
     return set_err(c, PD_EINVAL, "bad circuit parameters");
   if (C > 0.0 && c->mg_on)
     return set_err(c, PD_ESTATE, "the circuit needs a direct Poisson solve");
+  if (C > 0.0 && c->weighted)
+    return set_err(c, PD_EINVAL, "the circuit counts super-particles; no multiplicities with it");
   DevState h;
   pd_status s = read_state(c, &h);
   if (s) return s;
@@ -957,9 +968,52 @@ pd_status pd_inject(pd_ctx* c, int64_t n, const double* r, const double* z, cons
   if ((int64_t)h.n_total + n > c->cap) return set_err(c, PD_ECAPACITY, "capacity %lld", (long long)c->cap);
   if ((int64_t)h.next_id + n > (int64_t)0xFFFFFFFFLL) return set_err(c, PD_ECAPACITY, "id space");
   // stage through the sort's destination buffers (scratch between steps)
-  if (c->fp32) s = stage_append(c, c->Af, c->Bf, n, r, z, vr, vt, vz, sp);
-  else s = stage_append(c, c->A, c->B, n, r, z, vr, vt, vz, sp);
+  if (c->fp32) s = stage_append(c, c->Af, c->Bf, n, r, z, vr, vt, vz, sp, nullptr);
+  else s = stage_append(c, c->A, c->B, n, r, z, vr, vt, vz, sp, nullptr);
   if (s) return s;
+  if ((s = sync(c))) return s;
+  for (int64_t p = 0; p < n; ++p) c->injected[sp[p]] += 1;
+  return PD_OK;
+}
+
+pd_status pd_set_weighted(pd_ctx* c, int32_t on) {
+  if (!c) return PD_EINVAL;
+  if (!on) return c->weighted ? set_err(c, PD_EINVAL, "multiplicities cannot be turned off")
+                              : PD_OK;
+  if (c->weighted) return PD_OK;
+  if (c->poisoned) return set_err(c, PD_ESTATE, "context unusable after an earlier error");
+  if (c->in_ensemble) return set_err(c, PD_ESTATE, "context is in an ensemble");
+  if (c->fp32) return set_err(c, PD_EINVAL, "multiplicities need the FP64 record");
+  if (c->g.circ_C > 0.0)
+    return set_err(c, PD_EINVAL, "the circuit counts super-particles; no multiplicities with it");
+  pd_status s;
+  if ((s = sync(c))) return s;
+  if ((s = dalloc(c, &c->A.mu, c->cap)) || (s = dalloc(c, &c->B.mu, c->cap))) return s;
+  std::vector<uint16_t> one((size_t)c->cap, (uint16_t)1);
+  HIPCHK(c, hipMemcpy(c->A.mu, one.data(), sizeof(uint16_t) * c->cap, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->B.mu, one.data(), sizeof(uint16_t) * c->cap, hipMemcpyHostToDevice));
+  c->weighted = true;
+  return PD_OK;
+}
+
+pd_status pd_inject_weighted(pd_ctx* c, int64_t n, const double* r, const double* z,
+                             const double* vr, const double* vt, const double* vz,
+                             const uint8_t* sp, const uint16_t* mu) {
+  if (!c) return PD_EINVAL;
+  if (c->poisoned) return set_err(c, PD_ESTATE, "context unusable after an earlier error");
+  if (!c->weighted) return set_err(c, PD_ESTATE, "multiplicities not enabled (pd_set_weighted)");
+  if (n < 0) return set_err(c, PD_EINVAL, "n < 0");
+  if (n > 0 && !mu) return set_err(c, PD_EINVAL, "mu is NULL");
+  for (int64_t p = 0; p < n; ++p)
+    if (mu[p] < 1) return set_err(c, PD_EINVAL, "multiplicity of particle %lld below 1", (long long)p);
+  pd_status s = check_particles(c, n, r, z, vr, vt, vz, sp);
+  if (s) return s;
+  if (n == 0) return PD_OK;
+  DevState h;
+  if ((s = read_state(c, &h))) return s;
+  if ((int64_t)h.n_total + n > c->cap) return set_err(c, PD_ECAPACITY, "capacity %lld", (long long)c->cap);
+  if ((int64_t)h.next_id + n > (int64_t)0xFFFFFFFFLL) return set_err(c, PD_ECAPACITY, "id space");
+  if ((s = stage_append(c, c->A, c->B, n, r, z, vr, vt, vz, sp, mu))) return s;
   if ((s = sync(c))) return s;
   for (int64_t p = 0; p < n; ++p) c->injected[sp[p]] += 1;
   return PD_OK;
@@ -1075,30 +1129,34 @@ pd_status pd_synchronize(pd_ctx* c) {
 }
 
 static pd_status snapshot(pd_ctx* c, DevState& h, int64_t counts[kNS], double ke[kNS],
-                          int64_t spec[3][66]) {
+                          int64_t spec[3][66], int64_t real[kNS]) {
   pd_status s = read_state(c, &h);
   if (s) return s;
   HIPCHK(c, hipMemsetAsync(c->d_spec, 0, sizeof(unsigned long long) * 3 * 66, c->stream));
   if (c->fp32)
     diag_snapshot(c->Af, c->st, c->g, c->spp, c->d_edges, c->d_dcount, c->d_dke, c->d_spec,
-                  c->stream);
+                  c->d_dreal, c->stream);
   else
     diag_snapshot(c->A, c->st, c->g, c->spp, c->d_edges, c->d_dcount, c->d_dke, c->d_spec,
-                  c->stream);
+                  c->d_dreal, c->stream);
   HIPCHK(c, hipGetLastError());
   if ((s = sync(c))) return s;
-  std::vector<unsigned long long> hc((size_t)kDiagBlocks * kNS), hs(3 * 66);
+  std::vector<unsigned long long> hc((size_t)kDiagBlocks * kNS), hs(3 * 66),
+      hr((size_t)kDiagBlocks * kNS);
   std::vector<double> hk((size_t)kDiagBlocks * kNS);
   HIPCHK(c, hipMemcpy(hc.data(), c->d_dcount, hc.size() * 8, hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(hr.data(), c->d_dreal, hr.size() * 8, hipMemcpyDeviceToHost));
   HIPCHK(c, hipMemcpy(hk.data(), c->d_dke, hk.size() * 8, hipMemcpyDeviceToHost));
   HIPCHK(c, hipMemcpy(hs.data(), c->d_spec, hs.size() * 8, hipMemcpyDeviceToHost));
   for (int k = 0; k < kNS; ++k) {
     counts[k] = 0;
+    real[k] = 0;
     ke[k] = 0.0;
   }
   for (int b = 0; b < kDiagBlocks; ++b)
     for (int k = 0; k < kNS; ++k) {
       counts[k] += (int64_t)hc[(size_t)b * kNS + k];
+      real[k] += (int64_t)hr[(size_t)b * kNS + k];
       ke[k] += hk[(size_t)b * kNS + k];
     }
   for (int t = 0; t < 3; ++t)
@@ -1109,12 +1167,13 @@ static pd_status snapshot(pd_ctx* c, DevState& h, int64_t counts[kNS], double ke
 pd_status pd_get_diagnostics(pd_ctx* c, pd_diag* out) {
   if (!c || !out) return PD_EINVAL;
   DevState h;
-  int64_t counts[kNS];
+  int64_t counts[kNS], real[kNS];
   double ke[kNS];
   int64_t spec[3][66];
-  pd_status s = snapshot(c, h, counts, ke, spec);
+  pd_status s = snapshot(c, h, counts, ke, spec, real);
   if (s) return s;
   std::memset(out, 0, sizeof *out);
+  for (int k = 0; k < kNS; ++k) out->real[k] = real[k];
   out->step = c->host_step;
   out->next_id = h.next_id;
   int64_t n = 0;
@@ -1144,11 +1203,11 @@ pd_status pd_get_diagnostics(pd_ctx* c, pd_diag* out) {
   out->poisson_refinements = c->h_sc->outer;
   out->poisson_fallbacks = c->p_fallbacks;
   out->poisson_seconds = c->p_call_ms * 1e-3;
-  // Eq. 21 over the charge states 0..4 (N_2: every Cu2+ label), integer
-  // sums, one division each
-  const int64_t N[5] = {counts[PD_CU], counts[PD_CU1],
-                        counts[PD_CU2_STEP] + counts[PD_CU2_DOUBLE] + counts[PD_CU2_INIT],
-                        counts[PD_CU3], counts[PD_CU4]};
+  // Eq. 21 over the charge states 0..4 (N_2: every Cu2+ label) of the real
+  // particle numbers (in units of W), integer sums, one division each
+  const int64_t N[5] = {real[PD_CU], real[PD_CU1],
+                        real[PD_CU2_STEP] + real[PD_CU2_DOUBLE] + real[PD_CU2_INIT],
+                        real[PD_CU3], real[PD_CU4]};
   const int64_t ions = N[1] + N[2] + N[3] + N[4];
   const int64_t qsum = N[1] + 2 * N[2] + 3 * N[3] + 4 * N[4];
   out->gamma = (ions + N[0]) > 0 ? (double)ions / (double)(ions + N[0]) : 0.0;
@@ -1168,10 +1227,10 @@ pd_status pd_get_spectrum(pd_ctx* c, int tag, int64_t out[66]) {
   if (!c || !out) return PD_EINVAL;
   if (tag < 0 || tag > 2) return set_err(c, PD_EINVAL, "tag %d", tag);
   DevState h;
-  int64_t counts[kNS];
+  int64_t counts[kNS], real[kNS];
   double ke[kNS];
   int64_t spec[3][66];
-  pd_status s = snapshot(c, h, counts, ke, spec);
+  pd_status s = snapshot(c, h, counts, ke, spec, real);
   if (s) return s;
   for (int b = 0; b < 66; ++b) out[b] = spec[tag][b];
   return PD_OK;
@@ -1228,6 +1287,29 @@ pd_status pd_get_particles(pd_ctx* c, int64_t cap, double* r, double* z, double*
   return c->fp32 ? out(c->Af) : out(c->A);
 }
 
+pd_status pd_get_weights(pd_ctx* c, int64_t cap, uint16_t* mu) {
+  if (!c || !mu) return PD_EINVAL;
+  DevState h;
+  pd_status s = read_state(c, &h);
+  if (s) return s;
+  const size_t n = h.n_total;
+  std::vector<uint32_t> k(n);
+  std::vector<uint16_t> m(n, (uint16_t)1);
+  const uint32_t* dkey = c->fp32 ? c->Af.key : c->A.key;
+  if (n) {
+    HIPCHK(c, hipMemcpy(k.data(), dkey, 4 * n, hipMemcpyDeviceToHost));
+    if (c->weighted) HIPCHK(c, hipMemcpy(m.data(), c->A.mu, 2 * n, hipMemcpyDeviceToHost));
+  }
+  int64_t alive = 0;
+  for (size_t p = 0; p < n; ++p) alive += (k[p] != c->g.sentinel);
+  if (cap < alive)
+    return set_err(c, PD_EINVAL, "cap %lld < %lld particles", (long long)cap, (long long)alive);
+  int64_t w = 0;
+  for (size_t p = 0; p < n; ++p)
+    if (k[p] != c->g.sentinel) mu[w++] = m[p];
+  return PD_OK;
+}
+
 pd_status pd_get_field(pd_ctx* c, double* phi, double* Er, double* Ez, int64_t* Q) {
   if (!c) return PD_EINVAL;
   pd_status s = sync(c);
@@ -1280,7 +1362,7 @@ pd_status pd_poisson(pd_ctx* c, const int64_t* Q, double* phi, int32_t* iters, d
 // with its read position; the host-side counters; the solver's scalars; the
 // magic again.
 static const char kSaveMagic[8] = {'P', 'D', 'S', 'T', 'A', 'T', 'E', '1'};
-constexpr uint32_t kSaveVersion = 4;
+constexpr uint32_t kSaveVersion = 5;
 
 struct SaveHead {
   char magic[8];
@@ -1291,7 +1373,7 @@ struct SaveHead {
 
 struct SaveBoundary {
   double em_beta, em_rtip, em_phi, em_ratio, em_T, circ_V0, circ_R, circ_C;
-  int32_t split_literal, sput_on;
+  int32_t split_literal, sput_on, weighted, pad;
 };
 
 struct SaveHost {
@@ -1336,7 +1418,7 @@ pd_status pd_save(pd_ctx* c, const char* path) {
   put(&h, sizeof h);
   const SaveBoundary sb{c->g.em_beta, c->g.em_rtip, c->g.em_phi, c->g.em_ratio,
                         c->g.em_T,    c->g.circ_V0, c->g.circ_R, c->g.circ_C,
-                        c->cpar.split_literal, c->g.sput_on};
+                        c->cpar.split_literal, c->g.sput_on, c->weighted ? 1 : 0, 0};
   put(&sb, sizeof sb);
   put(c->spp.Z, sizeof c->spp.Z);
   put(c->spp.m, sizeof c->spp.m);
@@ -1361,6 +1443,7 @@ pd_status pd_save(pd_ctx* c, const char* path) {
     if ((s = putd(c->A.x, sizeof(PosT<double>) * n)) ||
         (s = putd(c->A.v, sizeof(RecT<double>) * n)) || (s = putd(c->A.key, 4 * n)))
       return s;
+    if (c->weighted && (s = putd(c->A.mu, sizeof(uint16_t) * n))) return s;
   }
   if ((s = putd(c->sw.skey, 4 * (size_t)st.n_alive)) ||
       (s = putd(c->off, 4 * ((size_t)c->g.sentinel + 1))) || (s = putd(c->fw.Q, 8 * nn)) ||
@@ -1480,6 +1563,8 @@ pd_status pd_load(pd_ctx* c, const char* path) {
   const unsigned char* xrec = span(xsz * n);
   const unsigned char* vrec = span(vsz * n);
   const unsigned char* key = span(4 * n);
+  if (ok && sb.weighted && c->fp32) ok = false;
+  const unsigned char* mu = sb.weighted ? span(sizeof(uint16_t) * n) : nullptr;
   const unsigned char* skey = span(4 * (size_t)st.n_alive);
   const unsigned char* off = span(4 * ((size_t)c->g.sentinel + 1));
   const unsigned char* Q = span(8 * nn);
@@ -1521,6 +1606,13 @@ pd_status pd_load(pd_ctx* c, const char* path) {
   }
   for (int64_t p = 0; p < (sn > 0 ? soff[sn] : 0); ++p)
     if (sarr[5][p] >= kNS) return set_err(c, PD_EINVAL, "%s: schedule species out of range", path);
+  for (size_t p = 0; mu && p < n; ++p) {
+    uint16_t m;
+    std::memcpy(&m, mu + 2 * p, 2);
+    if (m < 1) return set_err(c, PD_EINVAL, "%s: multiplicity below 1", path);
+  }
+  if (sb.weighted && sb.circ_C > 0.0)
+    return set_err(c, PD_EINVAL, "%s: multiplicities with the circuit", path);
   // apply: tables, then the device state
   pd_status s = pd_set_species(c, kNS, Z, m);
   if (s) return s;
@@ -1549,6 +1641,7 @@ pd_status pd_load(pd_ctx* c, const char* path) {
                                         nullptr, nullptr))) {
     return s;
   }
+  if (sb.weighted && (s = pd_set_weighted(c, 1))) return s;
   if ((s = sync(c))) return s;
   void* dx = c->fp32 ? (void*)c->Af.x : (void*)c->A.x;
   void* dv = c->fp32 ? (void*)c->Af.v : (void*)c->A.v;
@@ -1566,6 +1659,12 @@ pd_status pd_load(pd_ctx* c, const char* path) {
       (s = up(c->st, &st, sizeof st)) ||
       (s = up(c->mg.sc, sc, sizeof(MGScal))))
     return s;
+  if (c->weighted) {
+    // a file without multiplicities: every record stands for W
+    std::vector<uint16_t> m(n, (uint16_t)1);
+    if (mu) std::memcpy(m.data(), mu, 2 * n);
+    if ((s = up(c->A.mu, m.data(), 2 * n))) return s;
+  }
   for (int k = 0; k < kNS; ++k) c->injected[k] = hh.injected[k];
   c->host_step = hh.host_step;
   c->host_sched_pos = hh.host_sched_pos;

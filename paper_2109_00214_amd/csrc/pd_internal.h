@@ -157,6 +157,9 @@ struct PartsT {
   PosT<T>* x;
   RecT<T>* v;
   uint32_t* key;
+  // multiplicities (unequal weights: a record stands for mu W real
+  // particles), or null when every record stands for W
+  uint16_t* mu = nullptr;
 };
 using Parts = PartsT<double>;
 using PartsF = PartsT<float>;
@@ -311,7 +314,9 @@ __device__ inline void deposit_blocks(const Flow<T>& f, const uint32_t* __restri
           p = lo[s] + (q - cum[s]);
           Zp = spp.Zk[s];
         }
-      const PosT<T> x = f.U.x[f.perm[p]];
+      const uint32_t ip = f.perm[p];
+      if (f.U.mu) Zp *= (long long)f.U.mu[ip];  // W_alpha of Eq. 9
+      const PosT<T> x = f.U.x[ip];
       b = cic_fixed<T>(g, x.r, x.z, v);
 #pragma unroll
       for (int k = 0; k < 4; ++k) v[k] *= Zp;
@@ -538,8 +543,9 @@ void append(const PartsT<T>& P, DevState* st, const Grid& g, const PartsT<T>& sr
 constexpr int kDiagBlocks = 512;
 template <typename T>
 void diag_snapshot(const PartsT<T>& P, const DevState* st, const Grid& g, const SpeciesParams& sp,
-                   const double* edges, unsigned long long* counts /*[kDiagBlocks*6]*/,
-                   double* ke /*[kDiagBlocks*6]*/, unsigned long long* spec /*[3*66]*/,
+                   const double* edges, unsigned long long* counts /*[kDiagBlocks*kNS]*/,
+                   double* ke /*[kDiagBlocks*kNS]*/, unsigned long long* spec /*[3*66]*/,
+                   unsigned long long* real /*[kDiagBlocks*kNS]: sums of multiplicities*/,
                    hipStream_t s);
 // ---- learned Poisson part: U-Net on the BF16 matrix cores (k_unet.hip) ----
 struct Unet;

@@ -22,7 +22,7 @@ TIMER_NAMES = ("radix", "permute", "offsets", "collide", "deposit", "poisson", "
                "inject")
 EXPORTED = ("pd_create", "pd_set_species", "pd_set_cross_section", "pd_set_heavy_subcycle",
             "pd_set_emission", "pd_set_circuit", "pd_set_split_literal", "pd_set_sputtering",
-            "pd_inject",
+            "pd_set_weighted", "pd_inject", "pd_inject_weighted", "pd_get_weights",
             "pd_schedule_injection", "pd_step", "pd_synchronize", "pd_get_diagnostics",
             "pd_get_spectrum", "pd_get_count", "pd_get_particles", "pd_get_field",
             "pd_poisson", "pd_poisson_noalloc", "pd_save", "pd_load", "pd_get_timing", "pd_set_timing", "pd_last_error", "pd_destroy",
@@ -66,7 +66,8 @@ class pd_diag(C.Structure):
                 ("poisson_solves", C.c_int64), ("poisson_iters", C.c_int64),
                 ("poisson_refinements", C.c_int64), ("poisson_fallbacks", C.c_int64),
                 ("poisson_seconds", C.c_double), ("V_gap", C.c_double),
-                ("emitted", C.c_int64 * 2), ("sputtered", C.c_int64)]
+                ("emitted", C.c_int64 * 2), ("sputtered", C.c_int64),
+                ("real", C.c_int64 * PD_NSPECIES)]
 
 
 _lib = None
@@ -85,6 +86,9 @@ def load_library(path=LIB_PATH):
     lib.pd_set_species.argtypes = [P, C.c_int, P, P]
     lib.pd_set_cross_section.argtypes = [P, C.c_int, C.c_double, C.c_int, C.c_double, P]
     lib.pd_inject.argtypes = [P, C.c_int64] + [P] * 6
+    lib.pd_inject_weighted.argtypes = [P, C.c_int64] + [P] * 7
+    lib.pd_set_weighted.argtypes = [P, C.c_int32]
+    lib.pd_get_weights.argtypes = [P, C.c_int64, P]
     lib.pd_schedule_injection.argtypes = [P, C.c_int, P] + [P] * 6
     lib.pd_step.argtypes = [P, C.c_int]
     lib.pd_synchronize.argtypes = [P]
@@ -276,6 +280,26 @@ def pd_set_sputtering(ctx, on):
     _check(ctx, load_library().pd_set_sputtering(ctx, 1 if on else 0))
 
 
+def pd_set_weighted(ctx, on):
+    _check(ctx, load_library().pd_set_weighted(ctx, 1 if on else 0))
+
+
+def pd_inject_weighted(ctx, parts, mu):
+    a = _parts(parts)
+    m = np.ascontiguousarray(mu, dtype=np.uint16)
+    if len(m) != len(a[0]):
+        raise ValueError("one multiplicity per particle")
+    _check(ctx, load_library().pd_inject_weighted(ctx, len(a[0]), *[_ptr(x) for x in a],
+                                                  _ptr(m)))
+
+
+def pd_get_weights(ctx):
+    n = pd_get_count(ctx)
+    out = np.zeros(n, np.uint16)
+    _check(ctx, load_library().pd_get_weights(ctx, n, _ptr(out)))
+    return out
+
+
 def pd_save(ctx, path):
     _check(ctx, load_library().pd_save(ctx, os.fsencode(path)))
 
@@ -425,8 +449,17 @@ class Simulation:
         for ch, thr, dsq, sig in tables:
             pd_set_cross_section(self.h, ch, thr, dsq, sig)
 
-    def inject(self, parts):
-        pd_inject(self.h, parts)
+    def inject(self, parts, mult=None):
+        if mult is None:
+            pd_inject(self.h, parts)
+        else:
+            pd_inject_weighted(self.h, parts, mult)
+
+    def set_weighted(self, on=True):
+        pd_set_weighted(self.h, on)
+
+    def weights(self):
+        return pd_get_weights(self.h)
 
     def schedule_injection(self, offsets, parts):
         pd_schedule_injection(self.h, offsets, parts)

@@ -66,7 +66,7 @@ def assert_same_state(g, o, where=""):
     for k in ("n_alive", "next_id", "conflicts", "created", "charge_alive", "charge_absorbed",
               "charge_injected"):
         assert dg[k] == do[k], (where, k, dg[k], do[k])
-    for k in ("count", "events", "absorbed", "injected"):
+    for k in ("count", "events", "absorbed", "injected", "real"):
         assert np.array_equal(np.asarray(dg[k]), np.asarray(do[k])), (where, k, dg[k], do[k])
     np.testing.assert_allclose(dg["ke_J"], do["ke_J"], rtol=1e-12, atol=0)
     for t in range(3):
@@ -111,7 +111,7 @@ def assert_close_state(g, o, where="", rel=1e-10):
     for k in ("n_alive", "next_id", "conflicts", "created", "charge_alive", "charge_absorbed",
               "charge_injected"):
         assert dg[k] == do[k], (where, k, dg[k], do[k])
-    for k in ("count", "events", "absorbed", "injected"):
+    for k in ("count", "events", "absorbed", "injected", "real"):
         assert np.array_equal(np.asarray(dg[k]), np.asarray(do[k])), (where, k, dg[k], do[k])
     np.testing.assert_allclose(dg["ke_J"], do["ke_J"], rtol=rel, atol=0)
     for t in range(3):
