@@ -156,147 +156,150 @@ __global__ void __launch_bounds__(256, 1) k_sine_fo(const double* __restrict__ X
 // Tridiagonal solve per sine mode with the host-factored reciprocals (tinv)
 // and upper factors (tcp), both [mode][i]: dp_0 = f_0 inv_0,
 // dp_i = (f_i - a_i dp_{i-1}) inv_i; x_nr = dp_nr, x_i = dp_i - cp_i x_{i+1}.
-// Each mode is one chain of dependent operations, so one lane per mode.  The
-// block first stages every input of its modes in LDS with all loads in
-// flight at once (one memory latency), then each lane runs its two sweeps
-// from LDS with the next kThomasAhead rows read ahead into registers (dp
-// and then x overwrite the right-hand side in place).  The result is
-// written [mode][i], the layout the inverse transform reads.
+// Each mode is one chain of dependent operations, so one lane per mode, and
+// the time is the chain's: a single wave per SIMD waits out every dependent
+// FP64 operation, so what matters is that nothing else is on the chain.  The
+// block stages its modes' inputs in LDS mode by mode (a mode's rows
+// contiguous, pitch kThomasPitch rows apart with 2*kThomasAhead padding rows
+// at each end), all loads in flight at once; each lane then sweeps its own
+// rows at fixed offsets from one address, kThomasAhead rows read ahead into
+// registers with no bounds checks (the reads past either end land in the
+// padding and are never used).  The forward sweep leaves dp in LDS; the
+// backward sweep writes x straight to G[mode][i], the layout the inverse
+// transform reads.
 constexpr int kThomasAhead = 8;
 constexpr int kThomasStage = 12;  // staged words per thread and input array
+constexpr int kThomasPad = 2 * kThomasAhead;
+
+static int thomas_pitch(int nr) {
+  int P = nr + 1 + 2 * kThomasPad;
+  return (P & 1) ? P : P + 1;  // odd: the lanes' rows fall in different banks
+}
 
 __global__ void __launch_bounds__(256) k_thomas_fo(const double* __restrict__ fh,
                                                   const double* __restrict__ tinv,
                                                   const double* __restrict__ tcp,
                                                   const double* __restrict__ ra, int nr, int nz,
-                                                  int mpb, double* __restrict__ G) {
+                                                  int mpb, int P, double* __restrict__ G) {
   extern __shared__ double sh[];
+  constexpr int K = kThomasAhead, H = kThomasPad;
   const int M = nz - 1, W = nr + 1;
-  const int nL = W * mpb;
-  double* fL = sh;            // [W][mpb] rhs, then dp
-  double* iL = sh + nL;       // reciprocals
-  double* cL = sh + 2 * nL;   // upper factors
-  double* aL = sh + 3 * nL;   // [W] lower coefficients
+  double* fL = sh;                         // [mode][P]: rhs, then dp
+  double* iL = sh + (size_t)mpb * P;       // reciprocals
+  double* cL = sh + (size_t)2 * mpb * P;   // upper factors
+  double* aL = sh + (size_t)3 * mpb * P;   // [P] lower coefficients
   const int t = threadIdx.x;
   const int k0 = (int)blockIdx.x * mpb;
-  for (int i = t; i < W; i += 256) aL[i] = ra[i];
+  const int nm = (M - k0 < mpb) ? M - k0 : mpb;  // modes of this block
+  const int nL = nm * W;
+  const size_t g0 = (size_t)k0 * W;  // the block's modes are contiguous in fh, tinv, tcp, G
+  for (int i = t; i < W; i += 256) aL[H + i] = ra[i];
   // every load in flight at once (mpb * W <= kThomasStage * 256 by the
-  // choice of mpb), then the stores; element e = (mode kk, row i), i fastest
+  // choice of mpb), then the stores
   double fv[kThomasStage], iv[kThomasStage], cv[kThomasStage];
 #pragma unroll
   for (int u = 0; u < kThomasStage; ++u) {
     int e = 256 * u + t;
     e = (e < nL) ? e : nL - 1;
-    const int kk = e / W, i = e % W;
-    const int k = (k0 + kk < M) ? k0 + kk : M - 1;
-    const size_t q = (size_t)k * W + i;
-    fv[u] = fh[q];
-    iv[u] = tinv[q];
-    cv[u] = tcp[q];
+    fv[u] = fh[g0 + e];
+    iv[u] = tinv[g0 + e];
+    cv[u] = tcp[g0 + e];
   }
 #pragma unroll
   for (int u = 0; u < kThomasStage; ++u) {
     const int e = 256 * u + t;
     if (e < nL) {
-      const int kk = e / W, i = e % W;
-      fL[i * mpb + kk] = fv[u];
-      iL[i * mpb + kk] = iv[u];
-      cL[i * mpb + kk] = cv[u];
+      const int kk = e / W, i = e - kk * W;
+      const int o = kk * P + H + i;
+      fL[o] = fv[u];
+      iL[o] = iv[u];
+      cL[o] = cv[u];
     }
   }
   __syncthreads();
-  // the two sweeps, one lane per mode: full runs of kThomasAhead rows with no
-  // bounds checks (the rows of the next run are read while this one is
-  // computed), then the remaining rows one at a time
-  if (t < mpb) {
-    double dp = fL[t] * iL[t];
-    fL[t] = dp;
-    {
-      double fa[kThomasAhead], ia[kThomasAhead], aa[kThomasAhead];
-      double fb[kThomasAhead], ib[kThomasAhead], ab[kThomasAhead];
-      auto rd = [&](double* f, double* iv, double* a, int i0) {
+  if (t >= nm) return;
+  double* fr = fL + t * P + H;  // row i of this lane's mode at fr[i]
+  const double* ir = iL + t * P + H;
+  const double* cr = cL + t * P + H;
+  const double* ar = aL + H;
+  double* gr = G + g0 + (size_t)t * W;
+  // forward sweep: runs of K rows, the next run read while this one is
+  // computed; the last two runs are checked against nr
+  double dp = fr[0] * ir[0];
+  fr[0] = dp;
+  {
+    double fa[K], ia[K], aa[K], fb[K], ib[K], ab[K];
+    auto rd = [&](double* f, double* iv, double* a, int i0) {
 #pragma unroll
-        for (int u = 0; u < kThomasAhead; ++u) {
-          const int i = (i0 + u <= nr) ? i0 + u : nr;
-          f[u] = fL[i * mpb + t];
-          iv[u] = iL[i * mpb + t];
-          a[u] = aL[i];
-        }
-      };
-      auto run = [&](const double* f, const double* iv, const double* a, int i0) {
+      for (int u = 0; u < K; ++u) {
+        f[u] = fr[i0 + u];
+        iv[u] = ir[i0 + u];
+        a[u] = ar[i0 + u];
+      }
+    };
+    auto run = [&](const double* f, const double* iv, const double* a, int i0, bool check) {
 #pragma unroll
-        for (int u = 0; u < kThomasAhead; ++u) {
+      for (int u = 0; u < K; ++u) {
+        if (!check || i0 + u <= nr) {
           dp = (f[u] - (a[u] * dp)) * iv[u];
-          fL[(i0 + u) * mpb + t] = dp;
+          fr[i0 + u] = dp;
         }
-      };
-      int i = 1;
-      rd(fa, ia, aa, 1);
-      for (; i + 2 * kThomasAhead - 1 <= nr; i += 2 * kThomasAhead) {
-        rd(fb, ib, ab, i + kThomasAhead);
-        run(fa, ia, aa, i);
-        rd(fa, ia, aa, i + 2 * kThomasAhead);
-        run(fb, ib, ab, i + kThomasAhead);
       }
-      if (i + kThomasAhead - 1 <= nr) {
-        run(fa, ia, aa, i);
-        i += kThomasAhead;
-      }
-      for (; i <= nr; ++i) {
-        dp = (fL[i * mpb + t] - (aL[i] * dp)) * iL[i * mpb + t];
-        fL[i * mpb + t] = dp;
-      }
+    };
+    int i = 1;
+    rd(fa, ia, aa, 1);
+    for (; i + 2 * K - 1 <= nr; i += 2 * K) {
+      rd(fb, ib, ab, i + K);
+      run(fa, ia, aa, i, false);
+      rd(fa, ia, aa, i + 2 * K);  // rows up to nr + K
+      run(fb, ib, ab, i + K, false);
     }
-    // backward sweep from x_nr = dp_nr; x overwrites dp in LDS
-    double x = dp;
-    {
-      double da[kThomasAhead], ca[kThomasAhead], db[kThomasAhead], cb[kThomasAhead];
-      auto rd = [&](double* d, double* c, int i0) {
-#pragma unroll
-        for (int u = 0; u < kThomasAhead; ++u) {
-          const int i = (i0 - u >= 0) ? i0 - u : 0;
-          d[u] = fL[i * mpb + t];
-          c[u] = cL[i * mpb + t];
-        }
-      };
-      auto run = [&](const double* d, const double* c, int i0) {
-#pragma unroll
-        for (int u = 0; u < kThomasAhead; ++u) {
-          x = d[u] - (c[u] * x);
-          fL[(i0 - u) * mpb + t] = x;
-        }
-      };
-      int i = nr - 1;
-      rd(da, ca, nr - 1);
-      for (; i - 2 * kThomasAhead + 1 >= 0; i -= 2 * kThomasAhead) {
-        rd(db, cb, i - kThomasAhead);
-        run(da, ca, i);
-        rd(da, ca, i - 2 * kThomasAhead);
-        run(db, cb, i - kThomasAhead);
-      }
-      if (i - kThomasAhead + 1 >= 0) {
-        run(da, ca, i);
-        i -= kThomasAhead;
-      }
-      for (; i >= 0; --i) {
-        x = fL[i * mpb + t] - (cL[i * mpb + t] * x);
-        fL[i * mpb + t] = x;
-      }
-    }
+    rd(fb, ib, ab, i + K);  // i <= nr + 1: rows up to nr + 2K
+    run(fa, ia, aa, i, true);
+    run(fb, ib, ab, i + K, true);
   }
-  __syncthreads();
-  // the block's solutions to G[mode][i], coalesced over the rows
-  for (int e = t; e < nL; e += 256) {
-    const int kk = e / W, i = e % W, k = k0 + kk;
-    if (k < M) G[(size_t)k * W + i] = fL[i * mpb + kk];
+  // backward sweep from x_nr = dp_nr, the same way down to row 0
+  double x = dp;
+  gr[nr] = x;
+  {
+    double da[K], ca[K], db[K], cb[K];
+    auto rd = [&](double* d, double* c, int i0) {
+#pragma unroll
+      for (int u = 0; u < K; ++u) {
+        d[u] = fr[i0 - u];
+        c[u] = cr[i0 - u];
+      }
+    };
+    auto run = [&](const double* d, const double* c, int i0, bool check) {
+#pragma unroll
+      for (int u = 0; u < K; ++u) {
+        if (!check || i0 - u >= 0) {
+          x = d[u] - (c[u] * x);
+          gr[i0 - u] = x;
+        }
+      }
+    };
+    int i = nr - 1;
+    rd(da, ca, nr - 1);
+    for (; i - 2 * K + 1 >= 0; i -= 2 * K) {
+      rd(db, cb, i - K);
+      run(da, ca, i, false);
+      rd(da, ca, i - 2 * K);  // rows down to -K
+      run(db, cb, i - K, false);
+    }
+    rd(db, cb, i - K);  // i >= -1: rows down to -2K
+    run(da, ca, i, true);
+    run(db, cb, i - K, true);
   }
 }
 
-// modes per Thomas block: the block's three input columns per mode and the
-// lower coefficients in 64 KB of LDS
+// modes per Thomas block: two (the sweeps take the same time for any number
+// of lanes, and a small block stages its inputs sooner), one where two do not
+// fit in 64 KB of LDS or the staging registers
 static int thomas_modes(int nr) {
-  int mpb = 64;
-  while (mpb > 1 && (((size_t)3 * mpb + 1) * (size_t)(nr + 1) * sizeof(double) > 65536 ||
+  const size_t P = (size_t)thomas_pitch(nr);
+  int mpb = 2;
+  while (mpb > 1 && (((size_t)3 * mpb + 1) * P * sizeof(double) > 65536 ||
                      (size_t)mpb * (size_t)(nr + 1) > (size_t)kThomasStage * 256))
     mpb >>= 1;
   return mpb;
@@ -312,16 +315,17 @@ void poisson_direct(const Grid& g, FieldWork& fw, hipStream_t s) {
   const int ngrp = (W + 63) / 64, ag = (W + ngrp - 1) / ngrp;
   const dim3 grid(ngrp, (M + kFoB - 1) / kFoB);
   k_sine_fo<true><<<grid, 256, 0, s>>>(fw.f, fw.Sm, nr, nz, ag, g.V, nullptr, fw.fh);
-  const int mpb = thomas_modes(nr);
-  k_thomas_fo<<<(M + mpb - 1) / mpb, 256, sizeof(double) * ((size_t)3 * mpb + 1) * W, s>>>(
-      fw.fh, fw.tinv, fw.tcp, fw.ra, nr, nz, mpb, fw.g);
+  const int mpb = thomas_modes(nr), P = thomas_pitch(nr);
+  k_thomas_fo<<<(M + mpb - 1) / mpb, 256, sizeof(double) * ((size_t)3 * mpb + 1) * P, s>>>(
+      fw.fh, fw.tinv, fw.tcp, fw.ra, nr, nz, mpb, P, fw.g);
   k_sine_fo<false><<<grid, 256, 0, s>>>(fw.g, fw.Sm, nr, nz, ag, g.V, g.Vdev, fw.phi);
 }
 
 // the direct solve's limits: the full sine table (nz-1)^2 words; the
-// tridiagonal inputs of at least one mode in 64 KB of LDS
+// tridiagonal inputs of at least one mode, with the padding rows, in 64 KB
+// of LDS
 bool direct_fits(int nr, int nz) {
-  return nz - 1 <= 2048 && (size_t)4 * (size_t)(nr + 1) * sizeof(double) <= 65536 &&
+  return nz - 1 <= 2048 && (size_t)4 * (size_t)thomas_pitch(nr) * sizeof(double) <= 65536 &&
          (size_t)(nr + 1) <= (size_t)kThomasStage * 256;
 }
 
