@@ -61,13 +61,17 @@ __global__ void __launch_bounds__(256) k_rhs(const int64_t* __restrict__ Q,
 //        phi_vac added and the factor 2/nz.
 // Each output is one chain of dependent additions.  A wave's lanes take
 // consecutive radial nodes a (the radial extent split into equal groups of at
-// most 64) and two b, the same for every lane: a term costs one vector load
+// most 64) and three b, the same for every lane: a term costs one vector load
 // of a row of X (coalesced; the four waves of a block read the same rows) and
-// the two sine entries come as scalar operands, eight consecutive c of a
+// the three sine entries come as scalar operands, eight consecutive c of a
 // table row per scalar load.  No LDS: with one wave per SIMD every
 // instruction takes an issue slot, and the operands need no staging.  The
-// row loads are requested kFoAhead terms ahead; no contraction: each term is
-// the product rounded, then the sum rounded, as written.
+// row loads are requested kFoAhead terms ahead, as buffer loads from the
+// lane's byte offset of each of the kFoAhead rows (fixed for the kernel) and
+// one scalar offset per block of rows, so that a term costs no address
+// arithmetic; a half block's eight rows are requested after its eight terms,
+// and one wait at the start of a half covers them all.  No contraction: each
+// term is the product rounded, then the sum rounded, as written.
 constexpr int kFoWaves = 4, kFoRb = 3, kFoAhead = 16;
 constexpr int kFoB = kFoWaves * kFoRb;  // b per block
 
@@ -98,42 +102,63 @@ __global__ void __launch_bounds__(256, 1) k_sine_fo(const double* __restrict__ X
     const uint32_t o = (uint32_t)u * (uint32_t)W + (uint32_t)ac;
     xr[u] = X[(o < last) ? o : last];
   }
-  const double* __restrict__ xp = X + (size_t)kFoAhead * W + ac;
   const int mfull = (M / kFoAhead) * kFoAhead;
   int c0 = 0;
-  // a block of kFoAhead terms in two halves; each half's sine entries (three
-  // table rows, eight words each) are loaded just before it, which keeps
-  // them within the scalar registers
-  auto block = [&](bool clamp) {
+  // the terms of a half block (its sine entries, three table rows of eight
+  // words, are loaded just before it, which keeps them within the scalar
+  // registers)
+  auto half = [&](int h) {
+    double sv[kFoRb][8];
+#pragma unroll
+    for (int q = 0; q < kFoRb; ++q)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) sv[q][u] = sr[q][c0 + h + u];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      double p[kFoRb];
+#pragma unroll
+      for (int q = 0; q < kFoRb; ++q) p[q] = xr[h + u] * sv[q][u];
+#pragma unroll
+      for (int q = 0; q < kFoRb; ++q) acc[q] = acc[q] + p[q];
+    }
+  };
+  // the blocks whose look-ahead rows all exist: the byte offsets of a block's
+  // rows from its first row's, per lane, and the buffer over X
+  __amdgpu_buffer_rsrc_t rx =
+      __builtin_amdgcn_make_buffer_rsrc((void*)X, (short)0, (int)((size_t)M * W * 8), 0x00020000);
+  int voff[kFoAhead];
+#pragma unroll
+  for (int u = 0; u < kFoAhead; ++u) voff[u] = (ac + u * W) * 8;
+  for (; c0 + 2 * kFoAhead <= M; c0 += kFoAhead) {
+    const int sob = (c0 + kFoAhead) * W * 8;  // the next block's first row
 #pragma unroll
     for (int h = 0; h < kFoAhead; h += 8) {
-      double sv[kFoRb][8];
-#pragma unroll
-      for (int q = 0; q < kFoRb; ++q)
-#pragma unroll
-        for (int u = 0; u < 8; ++u) sv[q][u] = sr[q][c0 + h + u];
+      // this half's rows were requested before the other half's: at most the
+      // other half's eight loads are still in flight
+      __builtin_amdgcn_s_waitcnt(0xF78);  // vmcnt(8)
+      half(h);
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        double p[kFoRb];
-#pragma unroll
-        for (int q = 0; q < kFoRb; ++q) p[q] = xr[h + u] * sv[q][u];
-        if (clamp) {
-          const uint32_t o = (uint32_t)(c0 + kFoAhead + h + u) * (uint32_t)W + (uint32_t)ac;
-          xr[h + u] = X[(o < last) ? o : last];
-        } else {
-          xr[h + u] = xp[(size_t)(h + u) * W];
-        }
-#pragma unroll
-        for (int q = 0; q < kFoRb; ++q) acc[q] = acc[q] + p[q];
+        const auto v = __builtin_amdgcn_raw_buffer_load_b64(rx, voff[h + u], sob, 0);
+        __builtin_memcpy(&xr[h + u], &v, sizeof(double));
       }
       __builtin_amdgcn_sched_barrier(0);
     }
-    xp += (size_t)kFoAhead * W;
-  };
-  // the blocks whose look-ahead rows all exist, then the last full block,
-  // then the remaining rows (already in the ring)
-  for (; c0 + 2 * kFoAhead <= M; c0 += kFoAhead) block(false);
-  for (; c0 < mfull; c0 += kFoAhead) block(true);
+  }
+  // then the last full block, whose look-ahead rows are clamped to the last
+  // row, then the remaining rows (already in the ring)
+  for (; c0 < mfull; c0 += kFoAhead) {
+#pragma unroll
+    for (int h = 0; h < kFoAhead; h += 8) {
+      half(h);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const uint32_t o = (uint32_t)(c0 + kFoAhead + h + u) * (uint32_t)W + (uint32_t)ac;
+        xr[h + u] = X[(o < last) ? o : last];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
   for (int u = 0; c0 + u < M; ++u) {
 #pragma unroll
     for (int q = 0; q < kFoRb; ++q) acc[q] = acc[q] + (xr[u] * sr[q][c0 + u]);
