@@ -141,6 +141,15 @@ __device__ inline uint32_t side_bits(const CollideParams& cp, uint32_t id, uint3
   return (u < ((double)mp / (double)mt)) ? 0u : kNoTarget;
 }
 
+// electrons a resolved electron event creates, from its choice byte: none
+// for no event, a lost one (bit 7) or a target that keeps its state; the
+// elastic and Coulomb channels none, double ionization two, the others one
+__device__ inline uint32_t created_by(uint32_t c) {
+  if (!c || (c & 0x80u) || (c & kNoTarget)) return 0u;
+  const int ch = (int)(c & kChannelBits) - 1;
+  return (ch == 0 || ch == kCEI || ch == kCEE) ? 0u : (ch == 2 ? 2u : 1u);
+}
+
 // the heavy-projectile channels run on this step (a table is set and the
 // sort marked a heavy step)
 __device__ inline bool heavy_trials(const CollideParams& cp, const DevState* st) {
@@ -158,7 +167,7 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_decide(Flow<T> f, const uint32_t* off, const DevState* st,
                                                 Grid g, CollideParams cp, uint8_t* choice,
                                                 uint32_t* target, uint32_t* claim,
-                                                SpeciesParams spp,
+                                                uint32_t* csum, SpeciesParams spp,
                                                 unsigned long long* Q, uint32_t ndec) {
   if (blockIdx.x >= ndec) {
     deposit_blocks<T>(f, off, g, spp, Q, blockIdx.x - ndec, gridDim.x - ndec);
@@ -168,6 +177,13 @@ __global__ void __launch_bounds__(256) k_decide(Flow<T> f, const uint32_t* off, 
   const uint32_t C = g.C;
   const uint32_t n_e = off[C];
   const uint32_t step = st->step;
+  // the resolution adds the created electrons of every chunk of 256 electrons
+  // into the sum of its group of 32 chunks: clear those sums
+  {
+    const uint32_t ncs = ((n_e + 255) / 256 + 31) / 32;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < ncs; i += ndec * blockDim.x)
+      csum[i] = 0u;
+  }
   for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < n_e; e += ndec * blockDim.x) {
     const uint32_t cell = f.skey[e];
     const uint32_t pe = f.perm[e];
@@ -336,11 +352,13 @@ __global__ void __launch_bounds__(256) k_decide(Flow<T> f, const uint32_t* off, 
 
 // Claims are resolved per chunk of 256 electrons (one per thread): a
 // winner keeps its channel and counts the electrons it creates (0, 1 or 2);
-// the chunk's total goes to bsum for the scan of the created slots.
+// the chunk's total goes to bsum[chunk] and is added to csum[chunk / 32]
+// (integer sums: the same in any order), from which the apply takes the
+// created electrons before any chunk with one round of loads.
 __global__ void __launch_bounds__(256) k_resolve(const uint32_t* off, DevState* st, Grid g,
                                                  CollideParams cp, uint8_t* choice,
                                                  const uint32_t* target, const uint32_t* claim,
-                                                 uint32_t* ccount, uint32_t* bsum) {
+                                                 uint32_t* bsum, uint32_t* csum) {
   __shared__ uint32_t sh[4];
   __shared__ uint32_t tally[1 + kNC];  // conflicts, events per channel: one atomic per block
   const uint32_t n_e = off[g.C];
@@ -358,9 +376,7 @@ __global__ void __launch_bounds__(256) k_resolve(const uint32_t* off, DevState* 
       if (c) {
         if (claim[target[e]] == e && (!cp.cee || claim[e] == e)) {
           ch = (int)(c & kChannelBits) - 1;
-          // a target that keeps its state emits nothing
-          cnt = (ch == 0 || ch == kCEI || ch == kCEE || (c & kNoTarget)) ? 0u
-                                                                          : (ch == 2 ? 2u : 1u);
+          cnt = created_by(c);
         } else {
           lost = true;
           // with electron-electron collisions the apply resets the claims
@@ -368,7 +384,6 @@ __global__ void __launch_bounds__(256) k_resolve(const uint32_t* off, DevState* 
           choice[e] = cp.cee ? (uint8_t)(c | 0x80u) : (uint8_t)0;
         }
       }
-      ccount[e] = cnt;
     }
     const uint64_t ml = __ballot(lost);
     if (lane == 0 && ml) atomicAdd(&tally[0], (uint32_t)__popcll(ml));
@@ -379,7 +394,10 @@ __global__ void __launch_bounds__(256) k_resolve(const uint32_t* off, DevState* 
     }
     uint32_t tot;
     block_scan256(cnt, &tot, sh);
-    if (threadIdx.x == 0) bsum[b] = tot;
+    if (threadIdx.x == 0) {
+      bsum[b] = tot;
+      if (tot) atomicAdd(&csum[b >> 5], tot);
+    }
   }
   // heavy events: an event happens iff it holds both of its claims; the
   // losers keep their channel with bit 7 set, so that the apply resets the
@@ -425,16 +443,20 @@ __device__ inline void cic_atomic(unsigned long long* Q, int b, int W, long long
   atomicAdd(&Q[b + W + 1], (unsigned long long)(Z * v[3]));
 }
 
-// The winners' outcomes; the created slots of a chunk start at its scanned
-// block sum, in electron order inside the block.
+// The winners' outcomes; the created slots of a chunk start at the created
+// electrons of the chunks before it, in electron order inside the chunk.
+// The chunks before chunk b are the whole groups of 32 before its group
+// (csum) and the chunks of its group before it (bsum): one round of loads,
+// taken only by a chunk that creates electrons; the electrons' own counts
+// come again from their choice bytes.
 // (LIT: the literal Eqs. 16-20 split; a separate instantiation keeps its
 // trigonometric registers out of the default apply)
 template <typename T, bool LIT>
 __global__ void __launch_bounds__(256) k_apply(Flow<T> f, const uint32_t* off, DevState* st, Grid g,
                                                CollideParams cp, SpeciesParams spp,
                                                unsigned long long* Q, const uint8_t* choice,
-                                               const uint32_t* target, const uint32_t* ccount,
-                                               const uint32_t* bsum, uint32_t* claim,
+                                               const uint32_t* target, const uint32_t* bsum,
+                                               const uint32_t* csum, uint32_t* claim,
                                                uint32_t cap) {
   __shared__ uint32_t sh[4];
   const PartsT<T>& P = f.U;
@@ -448,7 +470,7 @@ __global__ void __launch_bounds__(256) k_apply(Flow<T> f, const uint32_t* off, D
   // the created electrons of every chunk: their total must fit (capacity,
   // id space), else the step creates nothing and flags the error; every
   // block decides the same from the same sums
-  const uint32_t all = block_range_sum(bsum, 0, nb, sh);
+  const uint32_t all = block_range_sum(csum, 0, (nb + 31) / 32, sh);
   const bool fits = !err0 && (uint64_t)n_alive + all <= cap &&
                     (uint64_t)next_id + all <= 0xFFFFFFFFull;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -456,16 +478,20 @@ __global__ void __launch_bounds__(256) k_apply(Flow<T> f, const uint32_t* off, D
     if (!fits) atomicOr(&st->err, 1u);
   }
   if (!fits) return;
-  uint32_t before = block_range_sum(bsum, 0, (blockIdx.x < nb) ? blockIdx.x : nb, sh);
   for (uint32_t b = blockIdx.x; b < nb; b += gridDim.x) {
-    if (b != blockIdx.x) before += block_range_sum(bsum, b - gridDim.x, b, sh);
     const uint32_t e = b * 256 + threadIdx.x;
-    const uint32_t cnt = (e < n_e) ? ccount[e] : 0u;
-    uint32_t tot;
-    const uint32_t cbase = before + block_scan256(cnt, &tot, sh);
+    const uint32_t c = (e < n_e) ? choice[e] : 0u;
+    uint32_t cbase = 0;
+    if (bsum[b]) {  // the same for the whole block
+      const uint32_t grp = b >> 5;
+      uint32_t s = 0;
+      for (uint32_t i = threadIdx.x; i < grp; i += 256) s += csum[i];
+      if (threadIdx.x < (b & 31u)) s += bsum[(grp << 5) + threadIdx.x];
+      uint32_t before, tot;
+      block_scan256(s, &before, sh);
+      cbase = before + block_scan256(created_by(c), &tot, sh);
+    }
     {
-      if (e >= n_e) continue;
-      const uint32_t c = choice[e];
       if (!c) continue;
       const uint32_t tp = target[e];
       if (c & 0x80u) {  // lost, with projectile claims: reset both
@@ -635,22 +661,22 @@ void collide(const Flow<T>& P, const uint32_t* off, DevState* st, const Grid& g,
   // state); the launches loop over whatever there is
   const int gr = grid_for(cap) < 1024 ? grid_for(cap) : 1024;
   int nb = (int)((cap + 255) / 256);
-  if (nb > 1024) nb = 1024;
+  if (nb > 4096) nb = 4096;
   // deposit blocks after the decision blocks (dispatched in order)
   int nd = 0;
   if (Q) nd = (int)((cap + 255) / 256) < 4096 ? (int)((cap + 255) / 256) : 4096;
-  k_decide<T><<<gr + nd, 256, 0, s>>>(P, off, st, g, cp, w.choice, w.target, w.claim,
+  k_decide<T><<<gr + nd, 256, 0, s>>>(P, off, st, g, cp, w.choice, w.target, w.claim, w.csum,
                                       sp, (unsigned long long*)Q, (uint32_t)gr);
-  k_resolve<<<nb, 256, 0, s>>>(off, st, g, cp, w.choice, w.target, w.claim, w.ccount, bsum);
+  k_resolve<<<nb, 256, 0, s>>>(off, st, g, cp, w.choice, w.target, w.claim, bsum, w.csum);
   // created-electron slots: each apply block adds up the chunk sums before
   // its chunk; the guard (in every block) flags an overflow and then nothing
   // is created, so every later launch touches only [0, n_alive)
   if (cp.split_literal)
     k_apply<T, true><<<nb, 256, 0, s>>>(P, off, st, g, cp, sp, (unsigned long long*)Q, w.choice,
-                                        w.target, w.ccount, bsum, w.claim, (uint32_t)cap);
+                                        w.target, bsum, w.csum, w.claim, (uint32_t)cap);
   else
     k_apply<T, false><<<nb, 256, 0, s>>>(P, off, st, g, cp, sp, (unsigned long long*)Q, w.choice,
-                                         w.target, w.ccount, bsum, w.claim, (uint32_t)cap);
+                                         w.target, bsum, w.csum, w.claim, (uint32_t)cap);
 }
 template void collide<double>(const Flow<double>&, const uint32_t*, DevState*, const Grid&,
                               const CollideParams&, const SpeciesParams&, int64_t*, CollideWork&,

@@ -191,7 +191,9 @@ __global__ void __launch_bounds__(256, 1) k_sine_fo(const double* __restrict__ X
 // registers with no bounds checks (the reads past either end land in the
 // padding and are never used).  The forward sweep leaves dp in LDS; the
 // backward sweep writes x straight to G[mode][i], the layout the inverse
-// transform reads.
+// transform reads.  Meanwhile the block's other three waves read the sine
+// table once per XCD, as the right-hand side does for the forward transform,
+// so that the inverse transform finds it in its XCD's L2.
 constexpr int kThomasAhead = 8;
 constexpr int kThomasStage = 12;  // staged words per thread and input array
 constexpr int kThomasPad = 2 * kThomasAhead;
@@ -205,7 +207,9 @@ __global__ void __launch_bounds__(256) k_thomas_fo(const double* __restrict__ fh
                                                   const double* __restrict__ tinv,
                                                   const double* __restrict__ tcp,
                                                   const double* __restrict__ ra, int nr, int nz,
-                                                  int mpb, int P, double* __restrict__ G) {
+                                                  int mpb, int P, double* __restrict__ G,
+                                                  const double* __restrict__ Sm,
+                                                  double* __restrict__ sink) {
   extern __shared__ double sh[];
   constexpr int K = kThomasAhead, H = kThomasPad;
   const int M = nz - 1, W = nr + 1;
@@ -242,7 +246,21 @@ __global__ void __launch_bounds__(256) k_thomas_fo(const double* __restrict__ fh
     }
   }
   __syncthreads();
-  if (t >= nm) return;
+  if (t >= nm) {
+    if (t >= 64) {
+      // slice blockIdx.x / 8 of gridDim.x / 8 slices: one word of every
+      // 128-byte line of the slice
+      const size_t words = (size_t)M * (size_t)M;
+      const uint32_t nsl = gridDim.x / 8u > 0u ? gridDim.x / 8u : 1u;
+      const size_t per = (words + nsl - 1) / nsl;
+      const size_t lo = (size_t)(blockIdx.x / 8u) * per;
+      const size_t hi = (lo + per < words) ? lo + per : words;
+      double acc = 0.0;
+      for (size_t i = lo + 16 * (size_t)(t - 64); i < hi; i += 16 * 192) acc += Sm[i];
+      if (acc == 1.0e300) sink[0] = acc;  // keeps the reads
+    }
+    return;
+  }
   double* fr = fL + t * P + H;  // row i of this lane's mode at fr[i]
   const double* ir = iL + t * P + H;
   const double* cr = cL + t * P + H;
@@ -342,7 +360,7 @@ void poisson_direct(const Grid& g, FieldWork& fw, hipStream_t s) {
   k_sine_fo<true><<<grid, 256, 0, s>>>(fw.f, fw.Sm, nr, nz, ag, g.V, nullptr, fw.fh);
   const int mpb = thomas_modes(nr), P = thomas_pitch(nr);
   k_thomas_fo<<<(M + mpb - 1) / mpb, 256, sizeof(double) * ((size_t)3 * mpb + 1) * P, s>>>(
-      fw.fh, fw.tinv, fw.tcp, fw.ra, nr, nz, mpb, P, fw.g);
+      fw.fh, fw.tinv, fw.tcp, fw.ra, nr, nz, mpb, P, fw.g, fw.Sm, fw.f);
   k_sine_fo<false><<<grid, 256, 0, s>>>(fw.g, fw.Sm, nr, nz, ag, g.V, g.Vdev, fw.phi);
 }
 

@@ -735,7 +735,7 @@ pd_status pd_create(const pd_domain* dom, const pd_opts* opts, pd_ctx** out) {
       (s = dalloc(c, &c->sw.n_mov, 2)) || (s = dalloc(c, &c->sw.perm, cap)) ||
       (s = dalloc(c, &c->sw.ins, cap)) ||
       (s = dalloc(c, &c->cw.choice, cap)) || (s = dalloc(c, &c->cw.target, cap)) ||
-      (s = dalloc(c, &c->cw.claim, cap)) || (s = dalloc(c, &c->cw.ccount, cap)) ||
+      (s = dalloc(c, &c->cw.claim, cap)) || (s = dalloc(c, &c->cw.csum, (cap / 256 + 1) / 32 + 2)) ||
       (s = dalloc(c, &c->fw.Q, nn)) || (s = dalloc(c, &c->fw.phi, nn)) ||
       (s = dalloc(c, &c->fw.Er, nn)) || (s = dalloc(c, &c->fw.Ez, nn)) ||
       (s = dalloc(c, &c->fw.fh, (size_t)M * (nr + 1))) ||

@@ -438,7 +438,8 @@ void place_and_offsets(const uint32_t* key, const SortWork& w, DevState* st, uin
 // ---- collisions (k_collide.hip) ----
 struct CollideWork {
   uint8_t* choice;
-  uint32_t *target, *claim, *ccount;
+  uint32_t *target, *claim;
+  uint32_t* csum;  // created electrons per group of 32 chunks of 256 electrons
   int64_t cap;
 };
 // Q: the node charge the deposit of the sorted state goes to (NULL when
