@@ -83,43 +83,39 @@ __device__ inline int mover_items(uint32_t n) {
   return (n > (1u << 20)) ? 16 : ((n > (1u << 18)) ? 8 : kMoverItems);
 }
 
-// per-tile digit histogram: each wave ranks its contiguous quarter of the tile 64 keys at a
-// time (all rankings first, so their ballot chains overlap), then adds
-// one count per distinct digit to its LDS row (no atomics)
+// per-tile digit histogram: every key adds one to its digit's count in LDS
+// (integer counts, the same in any order; keys of one digit in one wave
+// instruction are added one after another by the LDS, which the near order
+// of the movers makes common but still cheaper than ranking every key)
 template <int DB, int ITM>
 __global__ void __launch_bounds__(256) k_radix_up(const uint32_t* __restrict__ keys,
                                                   const uint32_t* np, int shift,
                                                   uint32_t* __restrict__ hist) {
   constexpr int R = 1 << DB;
-  __shared__ uint32_t wh[4][R];
+  __shared__ uint32_t wh[R];
   const uint32_t n = *np;
   const int itn = mover_items(n);
   const uint32_t tsz = 256u * (uint32_t)itn;
   const uint32_t ntiles = (n + tsz - 1) / tsz;
   constexpr uint32_t mask = (uint32_t)R - 1u;
-  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
-  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const int t = threadIdx.x;
   for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    for (int d = t; d < R; d += 256) wh[0][d] = wh[1][d] = wh[2][d] = wh[3][d] = 0;
-    const uint32_t base = tile * tsz + w * (tsz / 4);
-    uint32_t dd[ITM], rr[ITM], cc[ITM];
+    for (int d = t; d < R; d += 256) wh[d] = 0;
+    const uint32_t base = tile * tsz;
+    uint32_t dd[ITM];
 #pragma unroll
     for (int it = 0; it < ITM; ++it) {
       if (it < itn) {
-        const uint32_t idx = base + it * 64 + lane;
+        const uint32_t idx = base + it * 256 + t;
         dd[it] = (keys[(idx < n) ? idx : n - 1] >> shift) & mask;  // clamped, unconditional
       }
     }
-#pragma unroll
-    for (int it = 0; it < ITM; ++it)
-      if (it < itn) rr[it] = match_rank<DB>(dd[it], base + it * 64 + lane < n, lt, &cc[it]);
     __syncthreads();
 #pragma unroll
     for (int it = 0; it < ITM; ++it)
-      if (it < itn && base + it * 64 + lane < n && rr[it] == 0) wh[w][dd[it]] += cc[it];
+      if (it < itn && base + it * 256 + t < n) atomicAdd(&wh[dd[it]], 1u);
     __syncthreads();
-    for (int d = t; d < R; d += 256)
-      hist[(size_t)tile * R + d] = wh[0][d] + wh[1][d] + wh[2][d] + wh[3][d];
+    for (int d = t; d < R; d += 256) hist[(size_t)tile * R + d] = wh[d];
     __syncthreads();
   }
 }
