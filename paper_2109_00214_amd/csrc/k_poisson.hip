@@ -74,6 +74,7 @@ __global__ void __launch_bounds__(256) k_rhs(const int64_t* __restrict__ Q,
 // term is the product rounded, then the sum rounded, as written.
 constexpr int kFoWaves = 4, kFoRb = 3, kFoAhead = 16;
 constexpr int kFoB = kFoWaves * kFoRb;  // b per block
+constexpr int kFoWait = ((kFoAhead - 8) & 0xF) | (((kFoAhead - 8) >> 4) << 14) | 0x70 | 0xF00;
 
 template <bool FWD>
 __global__ void __launch_bounds__(256, 1) k_sine_fo(const double* __restrict__ X,
@@ -133,9 +134,10 @@ __global__ void __launch_bounds__(256, 1) k_sine_fo(const double* __restrict__ X
     const int sob = (c0 + kFoAhead) * W * 8;  // the next block's first row
 #pragma unroll
     for (int h = 0; h < kFoAhead; h += 8) {
-      // this half's rows were requested before the other half's: at most the
-      // other half's eight loads are still in flight
-      __builtin_amdgcn_s_waitcnt(0xF78);  // vmcnt(8)
+      // this group's rows were requested before the other groups': at most
+      // their kFoAhead - 8 loads are still in flight (s_waitcnt vmcnt, split
+      // into bits 3:0 and 15:14; the other counters at their maximum)
+      __builtin_amdgcn_s_waitcnt(kFoWait);
       half(h);
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
@@ -159,9 +161,12 @@ __global__ void __launch_bounds__(256, 1) k_sine_fo(const double* __restrict__ X
       __builtin_amdgcn_sched_barrier(0);
     }
   }
-  for (int u = 0; c0 + u < M; ++u) {
 #pragma unroll
-    for (int q = 0; q < kFoRb; ++q) acc[q] = acc[q] + (xr[u] * sr[q][c0 + u]);
+  for (int u = 0; u < kFoAhead; ++u) {  // unrolled: the ring stays in registers
+    if (c0 + u < M) {
+#pragma unroll
+      for (int q = 0; q < kFoRb; ++q) acc[q] = acc[q] + (xr[u] * sr[q][c0 + u]);
+    }
   }
   if (!live) return;
 #pragma unroll
