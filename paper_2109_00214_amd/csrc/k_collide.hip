@@ -350,53 +350,65 @@ __global__ void __launch_bounds__(256) k_decide(Flow<T> f, const uint32_t* off, 
   }
 }
 
-// Claims are resolved per chunk of 256 electrons (one per thread): a
-// winner keeps its channel and counts the electrons it creates (0, 1 or 2);
-// the chunk's total goes to bsum[chunk] and is added to csum[chunk / 32]
-// (integer sums: the same in any order), from which the apply takes the
-// created electrons before any chunk with one round of loads.
+// Claims are resolved per chunk of 256 electrons: a winner keeps its channel
+// and counts the electrons it creates (0, 1 or 2); the chunk's total goes to
+// bsum[chunk] and is added to csum[chunk / 32] (integer sums: the same in
+// any order), from which the apply takes the created electrons before any
+// chunk with one round of loads.  A wave takes one chunk, four consecutive
+// electrons per lane: one 32-bit load of their choice bytes and the loads
+// of their events issued together, so that a wave keeps four electrons'
+// chains of dependent loads in flight; the chunk's total is the wave's sum.
 __global__ void __launch_bounds__(256) k_resolve(const uint32_t* off, DevState* st, Grid g,
                                                  CollideParams cp, uint8_t* choice,
                                                  const uint32_t* target, const uint32_t* claim,
                                                  uint32_t* bsum, uint32_t* csum) {
-  __shared__ uint32_t sh[4];
   __shared__ uint32_t tally[1 + kNC];  // conflicts, events per channel: one atomic per block
   const uint32_t n_e = off[g.C];
   const uint32_t nb = (n_e + 255) / 256;
   const int lane = threadIdx.x & 63;
   if (threadIdx.x <= kNC) tally[threadIdx.x] = 0;
   __syncthreads();
-  for (uint32_t b = blockIdx.x; b < nb; b += gridDim.x) {
-    const uint32_t e = b * 256 + threadIdx.x;
-    int ch = -1;
-    bool lost = false;
+  const uint32_t nw = gridDim.x * (blockDim.x / 64);  // waves of the launch
+  for (uint32_t b = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); b < nb; b += nw) {
+    const uint32_t e0 = b * 256 + 4 * (uint32_t)lane;
+    uint32_t cw = 0;
+    if (e0 + 4 <= n_e) {
+      cw = *(const uint32_t*)(choice + e0);  // e0 is a multiple of 4
+    } else {
+      for (uint32_t k = 0; k < 4; ++k)
+        if (e0 + k < n_e) cw |= (uint32_t)choice[e0 + k] << (8 * k);
+    }
     uint32_t cnt = 0;
-    if (e < n_e) {
-      const uint32_t c = choice[e];
-      if (c) {
-        if (claim[target[e]] == e && (!cp.cee || claim[e] == e)) {
-          ch = (int)(c & kChannelBits) - 1;
-          cnt = created_by(c);
+    if (cw) {
+      uint32_t tp[4], ct[4], cs[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) tp[k] = ((cw >> (8 * k)) & 0xFFu) ? target[e0 + k] : 0u;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const bool ev = ((cw >> (8 * k)) & 0xFFu) != 0u;
+        ct[k] = ev ? claim[tp[k]] : 0u;
+        cs[k] = (ev && cp.cee) ? claim[e0 + k] : 0u;
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t c = (cw >> (8 * k)) & 0xFFu, e = e0 + k;
+        if (!c) continue;
+        if (ct[k] == e && (!cp.cee || cs[k] == e)) {
+          atomicAdd(&tally[1 + ((int)(c & kChannelBits) - 1)], 1u);
+          cnt += created_by(c);
         } else {
-          lost = true;
+          atomicAdd(&tally[0], 1u);
           // with electron-electron collisions the apply resets the claims
           // of the losers too (bit 7 marks them)
           choice[e] = cp.cee ? (uint8_t)(c | 0x80u) : (uint8_t)0;
         }
       }
     }
-    const uint64_t ml = __ballot(lost);
-    if (lane == 0 && ml) atomicAdd(&tally[0], (uint32_t)__popcll(ml));
 #pragma unroll
-    for (int k = 0; k < kNC; ++k) {
-      const uint64_t m = __ballot(ch == k);
-      if (lane == 0 && m) atomicAdd(&tally[1 + k], (uint32_t)__popcll(m));
-    }
-    uint32_t tot;
-    block_scan256(cnt, &tot, sh);
-    if (threadIdx.x == 0) {
-      bsum[b] = tot;
-      if (tot) atomicAdd(&csum[b >> 5], tot);
+    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+    if (lane == 0) {
+      bsum[b] = cnt;
+      if (cnt) atomicAdd(&csum[b >> 5], cnt);
     }
   }
   // heavy events: an event happens iff it holds both of its claims; the
@@ -667,7 +679,10 @@ void collide(const Flow<T>& P, const uint32_t* off, DevState* st, const Grid& g,
   if (Q) nd = (int)((cap + 255) / 256) < 4096 ? (int)((cap + 255) / 256) : 4096;
   k_decide<T><<<gr + nd, 256, 0, s>>>(P, off, st, g, cp, w.choice, w.target, w.claim, w.csum,
                                       sp, (unsigned long long*)Q, (uint32_t)gr);
-  k_resolve<<<nb, 256, 0, s>>>(off, st, g, cp, w.choice, w.target, w.claim, bsum, w.csum);
+  // the resolution: one wave per chunk
+  int nr = (int)((cap + 1023) / 1024);
+  if (nr > 4096) nr = 4096;
+  k_resolve<<<nr, 256, 0, s>>>(off, st, g, cp, w.choice, w.target, w.claim, bsum, w.csum);
   // created-electron slots: each apply block adds up the chunk sums before
   // its chunk; the guard (in every block) flags an overflow and then nothing
   // is created, so every later launch touches only [0, n_alive)
