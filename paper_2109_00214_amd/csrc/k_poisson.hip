@@ -190,8 +190,8 @@ __global__ void __launch_bounds__(256, 1) k_sine_fo(const double* __restrict__ X
 // the time is the chain's: a single wave per SIMD waits out every dependent
 // FP64 operation, so what matters is that nothing else is on the chain.  The
 // block stages its modes' inputs in LDS mode by mode (a mode's rows
-// contiguous, pitch kThomasPitch rows apart with 2*kThomasAhead padding rows
-// at each end), all loads in flight at once; each lane then sweeps its own
+// contiguous, modes thomas_pitch(nr) words apart, with kThomasPad padding
+// rows at each end), all loads in flight at once; each lane then sweeps its own
 // rows at fixed offsets from one address, kThomasAhead rows read ahead into
 // registers with no bounds checks (the reads past either end land in the
 // padding and are never used).  The forward sweep leaves dp in LDS; the
