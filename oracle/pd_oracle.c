@@ -848,14 +848,20 @@ void or_set_potential(or_sim* s, const double* phi) {
 /* 7. Poisson, Eq. 8 read as lap(phi) = -rho/eps0 in r-z, finite volume:
  *    Dirichlet at z = 0, L; zero flux at r = 0 and r = R.
  *    phi = phi_vac + phi_p; phi_p by a sine transform in z (DST-I over
- *    the interior z nodes), a tridiagonal (Thomas) solve per mode in r,
- *    and the inverse transform.                                         */
+ *    the interior z nodes), a tridiagonal solve per mode in r, and the
+ *    inverse transform.  The tridiagonal solve eliminates from both ends:
+ *    rows 0 .. m-1 downwards from the axis and rows nr .. m+1 upwards from
+ *    the wall (m = nr / 2), each pivot's reciprocal multiplying its row;
+ *    row m takes both neighbours' eliminated rows, then the back
+ *    substitution runs from m outwards both ways.                       */
 int or_poisson_solve(const or_sim* s, const double* f, double* phi_p) {
   const int nr = s->nr, nz = s->nz, W = nr + 1;
   double* fh = (double*)xalloc(sizeof(double) * (size_t)(nz + 1) * W);
   double* g = (double*)xalloc(sizeof(double) * (size_t)(nz + 1) * W);
   double* cp = (double*)xalloc(sizeof(double) * W);
   double* dp = (double*)xalloc(sizeof(double) * W);
+  double* cq = (double*)xalloc(sizeof(double) * W);
+  double* dq = (double*)xalloc(sizeof(double) * W);
   for (int k = 1; k < nz; ++k)
     for (int i = 0; i <= nr; ++i) {
       double acc = 0.0;
@@ -863,20 +869,47 @@ int or_poisson_solve(const or_sim* s, const double* f, double* phi_p) {
         acc = acc + (f[(size_t)j * W + i] * s->S[(size_t)k * (nz + 1) + j]);
       fh[(size_t)k * W + i] = acc;
     }
+  const int m = nr / 2;
   for (int k = 1; k < nz; ++k) {
     const double* rhs = fh + (size_t)k * W;
-    double inv = 1.0 / (s->rb[0] + s->mu[k]);
-    cp[0] = s->rc[0] * inv;
-    dp[0] = rhs[0] * inv;
-    for (int i = 1; i <= nr; ++i) {
-      double den = (s->rb[i] + s->mu[k]) - (s->ra[i] * cp[i - 1]);
-      inv = 1.0 / den;
+    const double mu = s->mu[k];
+    /* rows 0 .. m-1: row i less ra[i] times the eliminated row i-1 */
+    for (int i = 0; i < m; ++i) {
+      double den = s->rb[i] + mu, num = rhs[i];
+      if (i > 0) {
+        den = den - (s->ra[i] * cp[i - 1]);
+        num = num - (s->ra[i] * dp[i - 1]);
+      }
+      const double inv = 1.0 / den;
       cp[i] = s->rc[i] * inv;
-      dp[i] = (rhs[i] - (s->ra[i] * dp[i - 1])) * inv;
+      dp[i] = num * inv;
+    }
+    /* rows nr .. m+1: row i less rc[i] times the eliminated row i+1 */
+    for (int i = nr; i > m; --i) {
+      double den = s->rb[i] + mu, num = rhs[i];
+      if (i < nr) {
+        den = den - (s->rc[i] * cq[i + 1]);
+        num = num - (s->rc[i] * dq[i + 1]);
+      }
+      const double inv = 1.0 / den;
+      cq[i] = s->ra[i] * inv;
+      dq[i] = num * inv;
     }
     double* x = g + (size_t)k * W;
-    x[nr] = dp[nr];
-    for (int i = nr - 1; i >= 0; --i) x[i] = dp[i] - (cp[i] * x[i + 1]);
+    {
+      double den = s->rb[m] + mu, num = rhs[m];
+      if (m > 0) {
+        den = den - (s->ra[m] * cp[m - 1]);
+        num = num - (s->ra[m] * dp[m - 1]);
+      }
+      if (m < nr) {
+        den = den - (s->rc[m] * cq[m + 1]);
+        num = num - (s->rc[m] * dq[m + 1]);
+      }
+      x[m] = num * (1.0 / den);
+    }
+    for (int i = m - 1; i >= 0; --i) x[i] = dp[i] - (cp[i] * x[i + 1]);
+    for (int i = m + 1; i <= nr; ++i) x[i] = dq[i] - (cq[i] * x[i - 1]);
   }
   const double scale = 2.0 / (double)nz;
   for (int j = 0; j <= nz; ++j)
@@ -887,7 +920,7 @@ int or_poisson_solve(const or_sim* s, const double* f, double* phi_p) {
         acc = acc + (g[(size_t)k * W + i] * s->S[(size_t)k * (nz + 1) + j]);
       phi_p[(size_t)j * W + i] = acc * scale;
     }
-  free(fh); free(g); free(cp); free(dp);
+  free(fh); free(g); free(cp); free(dp); free(cq); free(dq);
   return 0;
 }
 

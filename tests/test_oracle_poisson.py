@@ -109,7 +109,9 @@ def _dense_operator(nr, nz, R, L):
 
 
 def test_dense_lu_brute_force():
-    for nr, nz in ((6, 10), (12, 24)):
+    # odd and even radial cell counts down to the smallest domain: the
+    # two-sided elimination meets at row nr // 2 (one row above it for nr = 2)
+    for nr, nz in ((2, 4), (3, 5), (4, 6), (6, 10), (7, 9), (12, 24)):
         cfg = W.config("tiny", nr=nr, nz=nz)
         o = make_oracle(cfg, collisions_off=True)
         rng = np.random.default_rng(nr)
