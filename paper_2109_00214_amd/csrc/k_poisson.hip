@@ -183,53 +183,65 @@ __global__ void __launch_bounds__(256, 1) k_sine_fo(const double* __restrict__ X
   }
 }
 
-// Tridiagonal solve per sine mode with the host-factored reciprocals (tinv)
-// and upper factors (tcp), both [mode][i]: dp_0 = f_0 inv_0,
-// dp_i = (f_i - a_i dp_{i-1}) inv_i; x_nr = dp_nr, x_i = dp_i - cp_i x_{i+1}.
-// Each mode is one chain of dependent operations, so one lane per mode, and
-// the time is the chain's: a single wave per SIMD waits out every dependent
-// FP64 operation, so what matters is that nothing else is on the chain.  The
-// block stages its modes' inputs in LDS mode by mode (a mode's rows
-// contiguous, modes thomas_pitch(nr) words apart, with kThomasPad padding
-// rows at each end), all loads in flight at once; each lane then sweeps its own
-// rows at fixed offsets from one address, kThomasAhead rows read ahead into
-// registers with no bounds checks (the reads past either end land in the
-// padding and are never used).  The forward sweep leaves dp in LDS; the
-// backward sweep writes x straight to G[mode][i], the layout the inverse
-// transform reads.  Meanwhile the block's other three waves read the sine
-// table once per XCD, as the right-hand side does for the forward transform,
-// so that the inverse transform finds it in its XCD's L2.
+// Tridiagonal solve per sine mode, eliminated from both ends with the
+// host-factored pivot reciprocals (tinv) and factors toward the middle row
+// m = nr / 2 (tcp), both [mode][i]:
+//   rows s = 0 .. m-1 from the axis:  d_s = (f_s - a_s d_{s-1}) inv_s,
+//   rows i = nr .. m+1 from the wall: d_i = (f_i - c_i d_{i+1}) inv_i,
+//   x_m = ((f_m - a_m d_{m-1}) - c_m d_{m+1}) inv_m,
+//   x_s = d_s - cp_s x_{s+1} above m, x_i = d_i - cp_i x_{i-1} below.
+// Each half is one chain of dependent operations, so two lanes per mode,
+// each with half the chain; the time is the chain's: a single wave per SIMD
+// waits out every dependent FP64 operation, so what matters is that nothing
+// else is on the chain.  The block stages its modes' inputs in LDS half by
+// half, the wall's half reversed, so that both lanes of a mode run the same
+// instructions on ascending rows (s = i above, s = nr - i below; each half
+// thomas_pitch(nr) words apart with kThomasPad padding rows at each end),
+// all loads in flight at once; each lane then sweeps its own rows at fixed
+// offsets from one address, kThomasAhead rows read ahead into registers
+// with no bounds checks (the reads past either end land in the padding and
+// are never used).  The two lanes meet in row m through a lane exchange and
+// compute it alike; the back substitution writes x straight to G[mode][i],
+// the layout the inverse transform reads.  Meanwhile the block's other
+// three waves read the sine table once per XCD, as the right-hand side does
+// for the forward transform, so that the inverse transform finds it in its
+// XCD's L2.
 constexpr int kThomasAhead = 8;
 constexpr int kThomasStage = 12;  // staged words per thread and input array
 constexpr int kThomasPad = 2 * kThomasAhead;
 
 static int thomas_pitch(int nr) {
-  int P = nr + 1 + 2 * kThomasPad;
+  int P = (nr - nr / 2 + 1) + 2 * kThomasPad;  // rows of the longer half, middle included
   return (P & 1) ? P : P + 1;  // odd: the lanes' rows fall in different banks
 }
 
 __global__ void __launch_bounds__(256) k_thomas_fo(const double* __restrict__ fh,
                                                   const double* __restrict__ tinv,
                                                   const double* __restrict__ tcp,
-                                                  const double* __restrict__ ra, int nr, int nz,
+                                                  const double* __restrict__ ra,
+                                                  const double* __restrict__ rc, int nr, int nz,
                                                   int mpb, int P, double* __restrict__ G,
                                                   const double* __restrict__ Sm,
                                                   double* __restrict__ sink) {
   extern __shared__ double sh[];
   constexpr int K = kThomasAhead, H = kThomasPad;
-  const int M = nz - 1, W = nr + 1;
-  double* fL = sh;                         // [mode][P]: rhs, then dp
-  double* iL = sh + (size_t)mpb * P;       // reciprocals
-  double* cL = sh + (size_t)2 * mpb * P;   // upper factors
-  double* aL = sh + (size_t)3 * mpb * P;   // [P] lower coefficients
+  const int M = nz - 1, W = nr + 1, m = nr / 2;
+  const int L = 2 * mpb;                  // lanes: a mode's two halves
+  double* fL = sh;                        // [lane][P]: rhs, then d
+  double* iL = sh + (size_t)L * P;        // pivot reciprocals
+  double* cL = sh + (size_t)2 * L * P;    // factors toward the middle
+  double* oL = sh + (size_t)3 * L * P;    // [half][P] a (axis half), c (wall half)
   const int t = threadIdx.x;
   const int k0 = (int)blockIdx.x * mpb;
   const int nm = (M - k0 < mpb) ? M - k0 : mpb;  // modes of this block
   const int nL = nm * W;
   const size_t g0 = (size_t)k0 * W;  // the block's modes are contiguous in fh, tinv, tcp, G
-  for (int i = t; i < W; i += 256) aL[H + i] = ra[i];
+  for (int i = t; i < W; i += 256) {
+    if (i <= m) oL[H + i] = ra[i];
+    if (i >= m) oL[P + H + (nr - i)] = rc[i];
+  }
   // every load in flight at once (mpb * W <= kThomasStage * 256 by the
-  // choice of mpb), then the stores
+  // choice of mpb), then the stores; row m goes to both halves
   double fv[kThomasStage], iv[kThomasStage], cv[kThomasStage];
 #pragma unroll
   for (int u = 0; u < kThomasStage; ++u) {
@@ -244,14 +256,22 @@ __global__ void __launch_bounds__(256) k_thomas_fo(const double* __restrict__ fh
     const int e = 256 * u + t;
     if (e < nL) {
       const int kk = e / W, i = e - kk * W;
-      const int o = kk * P + H + i;
-      fL[o] = fv[u];
-      iL[o] = iv[u];
-      cL[o] = cv[u];
+      if (i <= m) {
+        const int o = (2 * kk) * P + H + i;
+        fL[o] = fv[u];
+        iL[o] = iv[u];
+        cL[o] = cv[u];
+      }
+      if (i >= m) {
+        const int o = (2 * kk + 1) * P + H + (nr - i);
+        fL[o] = fv[u];
+        iL[o] = iv[u];
+        cL[o] = cv[u];
+      }
     }
   }
   __syncthreads();
-  if (t >= nm) {
+  if (t >= 2 * nm) {
     if (t >= 64) {
       // slice blockIdx.x / 8 of gridDim.x / 8 slices: one word of every
       // 128-byte line of the slice
@@ -266,15 +286,21 @@ __global__ void __launch_bounds__(256) k_thomas_fo(const double* __restrict__ fh
     }
     return;
   }
-  double* fr = fL + t * P + H;  // row i of this lane's mode at fr[i]
+  const int half = t & 1, kk = t >> 1;
+  const int len = half ? nr - m : m;  // rows this lane eliminates: s = 0 .. len-1
+  double* fr = fL + t * P + H;        // row s of this lane's half at fr[s]
   const double* ir = iL + t * P + H;
   const double* cr = cL + t * P + H;
-  const double* ar = aL + H;
-  double* gr = G + g0 + (size_t)t * W;
-  // forward sweep: runs of K rows, the next run read while this one is
-  // computed; the last two runs are checked against nr
-  double dp = fr[0] * ir[0];
-  fr[0] = dp;
+  const double* ar = oL + half * P + H;
+  double* gr = G + g0 + (size_t)kk * W;
+  // elimination toward the middle: runs of K rows, the next run read while
+  // this one is computed; the last two runs are checked against len - 1
+  const int last = len - 1;
+  double dp = 0.0;
+  if (len > 0) {
+    dp = fr[0] * ir[0];
+    fr[0] = dp;
+  }
   {
     double fa[K], ia[K], aa[K], fb[K], ib[K], ab[K];
     auto rd = [&](double* f, double* iv, double* a, int i0) {
@@ -288,7 +314,7 @@ __global__ void __launch_bounds__(256) k_thomas_fo(const double* __restrict__ fh
     auto run = [&](const double* f, const double* iv, const double* a, int i0, bool check) {
 #pragma unroll
       for (int u = 0; u < K; ++u) {
-        if (!check || i0 + u <= nr) {
+        if (!check || i0 + u <= last) {
           dp = (f[u] - (a[u] * dp)) * iv[u];
           fr[i0 + u] = dp;
         }
@@ -296,21 +322,31 @@ __global__ void __launch_bounds__(256) k_thomas_fo(const double* __restrict__ fh
     };
     int i = 1;
     rd(fa, ia, aa, 1);
-    for (; i + 2 * K - 1 <= nr; i += 2 * K) {
+    for (; i + 2 * K - 1 <= last; i += 2 * K) {
       rd(fb, ib, ab, i + K);
       run(fa, ia, aa, i, false);
-      rd(fa, ia, aa, i + 2 * K);  // rows up to nr + K
+      rd(fa, ia, aa, i + 2 * K);  // rows up to last + K
       run(fb, ib, ab, i + K, false);
     }
-    rd(fb, ib, ab, i + K);  // i <= nr + 1: rows up to nr + 2K
+    rd(fb, ib, ab, i + K);  // i <= last + 1: rows up to last + 2K
     run(fa, ia, aa, i, true);
     run(fb, ib, ab, i + K, true);
   }
-  // backward sweep from x_nr = dp_nr, the same way down to row 0
-  double x = dp;
-  gr[nr] = x;
+  // row m from both halves' last eliminated rows, the same arithmetic on
+  // both lanes (the axis half's first, as in the elimination order)
+  const int ta = t & ~1;
+  const double da = __shfl(dp, ta, 64), dw = __shfl(dp, ta | 1, 64);
+  double num = fL[ta * P + H + m];
+  if (m > 0) num = num - (oL[H + m] * da);
+  if (m < nr) num = num - (oL[P + H + (nr - m)] * dw);
+  double x = num * iL[ta * P + H + m];
+  if (half == 0) gr[m] = x;
+  // back substitution from row m outwards: x_s = d_s - cp_s x_{s+1}, s from
+  // len - 1 down to 0; G at i = s (axis half) or i = nr - s (wall half)
+  double* gx = half ? gr + nr : gr;
+  const int gs = half ? -1 : 1;
   {
-    double da[K], ca[K], db[K], cb[K];
+    double da_[K], ca[K], db[K], cb[K];
     auto rd = [&](double* d, double* c, int i0) {
 #pragma unroll
       for (int u = 0; u < K; ++u) {
@@ -323,31 +359,31 @@ __global__ void __launch_bounds__(256) k_thomas_fo(const double* __restrict__ fh
       for (int u = 0; u < K; ++u) {
         if (!check || i0 - u >= 0) {
           x = d[u] - (c[u] * x);
-          gr[i0 - u] = x;
+          gx[gs * (i0 - u)] = x;
         }
       }
     };
-    int i = nr - 1;
-    rd(da, ca, nr - 1);
+    int i = len - 1;
+    rd(da_, ca, len - 1);
     for (; i - 2 * K + 1 >= 0; i -= 2 * K) {
       rd(db, cb, i - K);
-      run(da, ca, i, false);
-      rd(da, ca, i - 2 * K);  // rows down to -K
+      run(da_, ca, i, false);
+      rd(da_, ca, i - 2 * K);  // rows down to -K
       run(db, cb, i - K, false);
     }
     rd(db, cb, i - K);  // i >= -1: rows down to -2K
-    run(da, ca, i, true);
+    run(da_, ca, i, true);
     run(db, cb, i - K, true);
   }
 }
 
-// modes per Thomas block: two (the sweeps take the same time for any number
-// of lanes, and a small block stages its inputs sooner), one where two do not
-// fit in 64 KB of LDS or the staging registers
+// modes per tridiagonal block: two (the sweeps take the same time for any
+// number of lanes, and a small block stages its inputs sooner), one where
+// two do not fit in 64 KB of LDS or the staging registers
 static int thomas_modes(int nr) {
   const size_t P = (size_t)thomas_pitch(nr);
   int mpb = 2;
-  while (mpb > 1 && (((size_t)3 * mpb + 1) * P * sizeof(double) > 65536 ||
+  while (mpb > 1 && (((size_t)6 * mpb + 2) * P * sizeof(double) > 65536 ||
                      (size_t)mpb * (size_t)(nr + 1) > (size_t)kThomasStage * 256))
     mpb >>= 1;
   return mpb;
@@ -364,8 +400,8 @@ void poisson_direct(const Grid& g, FieldWork& fw, hipStream_t s) {
   const dim3 grid(ngrp, (M + kFoB - 1) / kFoB);
   k_sine_fo<true><<<grid, 256, 0, s>>>(fw.f, fw.Sm, nr, nz, ag, g.V, nullptr, fw.fh);
   const int mpb = thomas_modes(nr), P = thomas_pitch(nr);
-  k_thomas_fo<<<(M + mpb - 1) / mpb, 256, sizeof(double) * ((size_t)3 * mpb + 1) * P, s>>>(
-      fw.fh, fw.tinv, fw.tcp, fw.ra, nr, nz, mpb, P, fw.g, fw.Sm, fw.f);
+  k_thomas_fo<<<(M + mpb - 1) / mpb, 256, sizeof(double) * ((size_t)6 * mpb + 2) * P, s>>>(
+      fw.fh, fw.twinv, fw.twcp, fw.ra, fw.rc, nr, nz, mpb, P, fw.g, fw.Sm, fw.f);
   k_sine_fo<false><<<grid, 256, 0, s>>>(fw.g, fw.Sm, nr, nz, ag, g.V, g.Vdev, fw.phi);
 }
 
@@ -373,7 +409,7 @@ void poisson_direct(const Grid& g, FieldWork& fw, hipStream_t s) {
 // tridiagonal inputs of at least one mode, with the padding rows, in 64 KB
 // of LDS
 bool direct_fits(int nr, int nz) {
-  return nz - 1 <= 2048 && (size_t)4 * (size_t)thomas_pitch(nr) * sizeof(double) <= 65536 &&
+  return nz - 1 <= 2048 && (size_t)8 * (size_t)thomas_pitch(nr) * sizeof(double) <= 65536 &&
          (size_t)(nr + 1) <= (size_t)kThomasStage * 256;
 }
 

@@ -227,7 +227,8 @@ pd_status check_particles(pd_ctx* c, int64_t n, const double* r, const double* z
 // formula as parenthesised (compiled without contraction).
 void build_tables(pd_ctx* c, std::vector<double>& Vnode, std::vector<double>& Vcell,
                   std::vector<double>& ra, std::vector<double>& S, std::vector<double>& tinv,
-                  std::vector<double>& tcp, std::vector<double>& edges) {
+                  std::vector<double>& tcp, std::vector<double>& edges, std::vector<double>& rcv,
+                  std::vector<double>& twinv, std::vector<double>& twcp) {
   const int nr = c->dom.nr, nz = c->dom.nz, M = nz - 1;
   const double R = c->dom.R, dr = c->g.dr, dz = c->g.dz;
   Vnode.assign(nr + 1, 0.0);
@@ -289,6 +290,36 @@ void build_tables(pd_ctx* c, std::vector<double>& Vnode, std::vector<double>& Vc
       tcp[(size_t)(k - 1) * (nr + 1) + i] = cp;
     }
   }
+  // the same systems eliminated from both ends (rows 0 .. m-1 from the axis,
+  // nr .. m+1 from the wall, m = nr / 2): each row's pivot reciprocal and
+  // its factor toward the middle ([mode][i]; row m: the middle pivot's
+  // reciprocal and no factor), in the order the direct solve uses them
+  const int m = nr / 2;
+  twinv.assign((size_t)(nr + 1) * M, 0.0);
+  twcp.assign((size_t)(nr + 1) * M, 0.0);
+  for (int k = 1; k <= M; ++k) {
+    const double h = std::sin((kPI * (double)k) / (2.0 * (double)nz));
+    const double mu = -(4.0 * (h * h)) / (dz * dz);
+    double* iv = &twinv[(size_t)(k - 1) * (nr + 1)];
+    double* cv = &twcp[(size_t)(k - 1) * (nr + 1)];
+    for (int i = 0; i < m; ++i) {
+      double den = rb[i] + mu;
+      if (i > 0) den = den - (ra[i] * cv[i - 1]);
+      iv[i] = 1.0 / den;
+      cv[i] = rc[i] * iv[i];
+    }
+    for (int i = nr; i > m; --i) {
+      double den = rb[i] + mu;
+      if (i < nr) den = den - (rc[i] * cv[i + 1]);
+      iv[i] = 1.0 / den;
+      cv[i] = ra[i] * iv[i];
+    }
+    double den = rb[m] + mu;
+    if (m > 0) den = den - (ra[m] * cv[m - 1]);
+    if (m < nr) den = den - (rc[m] * cv[m + 1]);
+    iv[m] = 1.0 / den;
+  }
+  rcv = rc;
   edges.assign(65, 0.0);
   for (int b = 0; b <= 64; ++b) edges[b] = std::pow(10.0, (3.0 * (double)b) / 64.0);
 }
@@ -756,12 +787,14 @@ pd_status pd_create(const pd_domain* dom, const pd_opts* opts, pd_ctx** out) {
   c->sw.cap = cap;
   c->cw.cap = cap;
 
-  std::vector<double> Vnode, Vcell, ra, S, tinv, tcp, edges;
-  build_tables(c, Vnode, Vcell, ra, S, tinv, tcp, edges);
-  double *dVn, *dVc, *dra, *dS, *dti, *dtc;
+  std::vector<double> Vnode, Vcell, ra, S, tinv, tcp, edges, rcv, twinv, twcp;
+  build_tables(c, Vnode, Vcell, ra, S, tinv, tcp, edges, rcv, twinv, twcp);
+  double *dVn, *dVc, *dra, *dS, *dti, *dtc, *drc, *dwi, *dwc;
   if ((s = dalloc(c, &dVn, Vnode.size())) || (s = dalloc(c, &dVc, Vcell.size())) ||
       (s = dalloc(c, &dra, ra.size())) || (s = dalloc(c, &dS, S.size())) ||
-      (s = dalloc(c, &dti, tinv.size())) || (s = dalloc(c, &dtc, tcp.size())))
+      (s = dalloc(c, &dti, tinv.size())) || (s = dalloc(c, &dtc, tcp.size())) ||
+      (s = dalloc(c, &drc, rcv.size())) || (s = dalloc(c, &dwi, twinv.size())) ||
+      (s = dalloc(c, &dwc, twcp.size())))
     return fail(s);
   auto up = [&](void* d, const void* h, size_t b) {
     return hipMemcpy(d, h, b, hipMemcpyHostToDevice) == hipSuccess;
@@ -769,6 +802,8 @@ pd_status pd_create(const pd_domain* dom, const pd_opts* opts, pd_ctx** out) {
   if (!up(dVn, Vnode.data(), Vnode.size() * 8) || !up(dVc, Vcell.data(), Vcell.size() * 8) ||
       !up(dra, ra.data(), ra.size() * 8) || !up(dS, S.data(), S.size() * 8) ||
       !up(dti, tinv.data(), tinv.size() * 8) || !up(dtc, tcp.data(), tcp.size() * 8) ||
+      !up(drc, rcv.data(), rcv.size() * 8) || !up(dwi, twinv.data(), twinv.size() * 8) ||
+      !up(dwc, twcp.data(), twcp.size() * 8) ||
       !up(c->d_edges, edges.data(), 65 * 8))
     return fail(set_err(c, PD_EDEVICE, "table upload failed"));
   c->fw.Vnode = dVn;
@@ -776,6 +811,9 @@ pd_status pd_create(const pd_domain* dom, const pd_opts* opts, pd_ctx** out) {
   c->fw.T = dS;
   c->fw.tinv = dti;
   c->fw.tcp = dtc;
+  c->fw.rc = drc;
+  c->fw.twinv = dwi;
+  c->fw.twcp = dwc;
   c->fw.qunit = c->qunit;
   if (!c->spectral) {
     // the whole DST-I matrix for the fixed-order transforms (its entries are

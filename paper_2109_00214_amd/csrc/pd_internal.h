@@ -462,6 +462,9 @@ struct FieldWork {
   const double* tinv;   // [(nz-1) * (nr+1)] Thomas reciprocals, per mode, r fastest
   const double* tcp;    // [(nz-1) * (nr+1)] Thomas upper factors, per mode, r fastest
   const double* ra;     // [nr+1] radial lower coefficients
+  const double* rc;     // [nr+1] radial upper coefficients
+  const double* twinv;  // [(nz-1) * (nr+1)] the same systems eliminated from both ends:
+  const double* twcp;   //   pivot reciprocals and factors toward the middle row nr / 2
   const double* Vnode;  // [nr+1]
   double qunit;
   // the right-hand-side scale of the matrix-core form of the direct solve
