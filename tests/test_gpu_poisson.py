@@ -95,11 +95,12 @@ def test_direct_pd_poisson_is_bit_exact():
 
 # grids: the paper's, the tiny one, ragged (radial nodes not a multiple of the
 # eight per transform block, rows not a multiple of 64 or of the 32-row
-# staging chunks), one interior row, wide radial extents (rows of 701 and 1024
-# nodes per tridiagonal lane, past the read-ahead runs) and a tall one
+# staging chunks), one interior row, wide radial extents (halves of 351 and
+# 512 rows per tridiagonal lane, past the read-ahead runs), a tall one, and
+# the smallest radial extents (one and two rows on each side of the middle)
 @pytest.mark.parametrize("grid,n", [((32, 64), 50_000), ((30, 50), 20_000), ((3, 2), 2_000),
                                     ((700, 40), 100_000), ((1023, 20), 50_000),
-                                    ((5, 300), 20_000)])
+                                    ((5, 300), 20_000), ((2, 4), 1_000), ((4, 6), 2_000)])
 def test_direct_solve_bit_exact_on_ragged_grids(grid, n):
     nr, nz = grid
     log("case: fixed-order direct solve, %dx%d, %d particles" % (nr, nz, n))
