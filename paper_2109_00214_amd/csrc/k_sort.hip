@@ -477,6 +477,7 @@ __global__ void __launch_bounds__(256) k_cls_compact(const uint32_t* __restrict_
                                                      int heavy_every,
                                                      uint32_t* __restrict__ heavy_now) {
   __shared__ uint32_t sh[4];
+  __shared__ uint32_t sk[kScanChunk], si[kScanChunk];
   const uint32_t n = st->n_total, n_prev = st->n_alive;
   const uint32_t nb = n / kScanChunk + 1;
   if (blockIdx.x == 0) {
@@ -505,15 +506,23 @@ __global__ void __launch_bounds__(256) k_cls_compact(const uint32_t* __restrict_
   }
   const uint32_t before = block_range_sum(bsum, 0, blockIdx.x, sh);
   uint32_t tot;
-  uint32_t run = before + block_scan256(__popc(m), &tot, sh);
-  if ((threadIdx.x & 3) == 0) mword[base >> 5] = run;
+  uint32_t run = block_scan256(__popc(m), &tot, sh);
+  if ((threadIdx.x & 3) == 0) mword[base >> 5] = before + run;
+  // the chunk's movers are the run [before, before + tot) of the output:
+  // gathered in LDS in order, then written with consecutive lanes on
+  // consecutive words
 #pragma unroll
   for (int k = 0; k < kScanPer; ++k) {
     if ((m >> k) & 1u) {
-      mk[run] = kv[k];
-      mi[run] = base + k;
+      sk[run] = kv[k];
+      si[run] = base + k;
       ++run;
     }
+  }
+  __syncthreads();
+  for (uint32_t j = threadIdx.x; j < tot; j += 256) {
+    mk[before + j] = sk[j];
+    mi[before + j] = si[j];
   }
 }
 
