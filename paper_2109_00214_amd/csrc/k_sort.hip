@@ -87,11 +87,12 @@ __device__ inline int mover_items(uint32_t n) {
 // (integer counts, the same in any order; keys of one digit in one wave
 // instruction are added one after another by the LDS, which the near order
 // of the movers makes common but still cheaper than ranking every key)
-template <int DB, int ITM>
-__global__ void __launch_bounds__(256) k_radix_up(const uint32_t* __restrict__ keys,
-                                                  const uint32_t* np, int shift,
-                                                  uint32_t* __restrict__ hist) {
+template <int DB, int ITM, int NT>  // NT threads per block, a multiple of 256
+__global__ void __launch_bounds__(NT) k_radix_up(const uint32_t* __restrict__ keys,
+                                                 const uint32_t* np, int shift,
+                                                 uint32_t* __restrict__ hist) {
   constexpr int R = 1 << DB;
+  constexpr int IT = (256 * ITM + NT - 1) / NT;  // keys per thread in the longest tile
   __shared__ uint32_t wh[R];
   const uint32_t n = *np;
   const int itn = mover_items(n);
@@ -100,22 +101,22 @@ __global__ void __launch_bounds__(256) k_radix_up(const uint32_t* __restrict__ k
   constexpr uint32_t mask = (uint32_t)R - 1u;
   const int t = threadIdx.x;
   for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    for (int d = t; d < R; d += 256) wh[d] = 0;
+    for (int d = t; d < R; d += NT) wh[d] = 0;
     const uint32_t base = tile * tsz;
-    uint32_t dd[ITM];
+    uint32_t dd[IT];
 #pragma unroll
-    for (int it = 0; it < ITM; ++it) {
-      if (it < itn) {
-        const uint32_t idx = base + it * 256 + t;
+    for (int it = 0; it < IT; ++it) {
+      if ((uint32_t)(it * NT + t) < tsz) {
+        const uint32_t idx = base + it * NT + t;
         dd[it] = (keys[(idx < n) ? idx : n - 1] >> shift) & mask;  // clamped, unconditional
       }
     }
     __syncthreads();
 #pragma unroll
-    for (int it = 0; it < ITM; ++it)
-      if (it < itn && base + it * 256 + t < n) atomicAdd(&wh[dd[it]], 1u);
+    for (int it = 0; it < IT; ++it)
+      if ((uint32_t)(it * NT + t) < tsz && base + it * NT + t < n) atomicAdd(&wh[dd[it]], 1u);
     __syncthreads();
-    for (int d = t; d < R; d += 256) hist[(size_t)tile * R + d] = wh[d];
+    for (int d = t; d < R; d += NT) hist[(size_t)tile * R + d] = wh[d];
     __syncthreads();
   }
 }
@@ -392,7 +393,9 @@ static void radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout,
   constexpr int R = 1 << DB;
   constexpr int ITM = kMoverItemsMax;
   const int grid = tile_grid(w.cap, 2, 256 * kMoverItems);
-  k_radix_up<DB, ITM><<<grid, 256, 0, s>>>(kin, np, shift, w.hist);
+  // the histograms with four times the threads per tile: more loads in
+  // flight per CU (the tiles are few)
+  k_radix_up<DB, ITM, 1024><<<grid, 1024, 0, s>>>(kin, np, shift, w.hist);
   k_radix_colscan<R><<<R / 64, 64 * kColWaves, 0, s>>>(w.hist, w.bsum, np);
   if (!vin)
     k_radix_down<DB, ITM, true><<<grid, 256, 0, s>>>(kin, vin, kout, vout, np, shift, w.hist,
