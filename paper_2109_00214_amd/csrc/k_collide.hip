@@ -459,8 +459,11 @@ __device__ inline void cic_atomic(unsigned long long* Q, int b, int W, long long
 // electrons of the chunks before it, in electron order inside the chunk.
 // The chunks before chunk b are the whole groups of 32 before its group
 // (csum) and the chunks of its group before it (bsum): one round of loads,
-// taken only by a chunk that creates electrons; the electrons' own counts
-// come again from their choice bytes.
+// taken only by a block whose electrons create some; the electrons' own
+// counts come again from their choice bytes.  A thread reads the choices
+// of kApplyPer electrons at once, so that one round of blocks covers them
+// (rather than rounds of one chunk each, every one waiting for its loads).
+constexpr int kApplyPer = 8;
 // (LIT: the literal Eqs. 16-20 split; a separate instantiation keeps its
 // trigonometric registers out of the default apply)
 template <typename T, bool LIT>
@@ -471,6 +474,8 @@ __global__ void __launch_bounds__(256) k_apply(Flow<T> f, const uint32_t* off, D
                                                const uint32_t* csum, uint32_t* claim,
                                                uint32_t cap) {
   __shared__ uint32_t sh[4];
+  __shared__ uint32_t lev[256 * kApplyPer], lcb[256 * kApplyPer];
+  __shared__ uint8_t lch[256 * kApplyPer];
   const PartsT<T>& P = f.U;
   const PartsT<T>& S = f.S;
   const uint32_t n_e = off[g.C];
@@ -490,21 +495,55 @@ __global__ void __launch_bounds__(256) k_apply(Flow<T> f, const uint32_t* off, D
     if (!fits) atomicOr(&st->err, 1u);
   }
   if (!fits) return;
-  for (uint32_t b = blockIdx.x; b < nb; b += gridDim.x) {
-    const uint32_t e = b * 256 + threadIdx.x;
-    const uint32_t c = (e < n_e) ? choice[e] : 0u;
-    uint32_t cbase = 0;
-    if (bsum[b]) {  // the same for the whole block
+  // kApplyPer consecutive electrons per thread, their choice bytes in one
+  // load: a block takes kApplyPer chunks of 256 at a time
+  const uint32_t nbk = (n_e + 256 * kApplyPer - 1) / (256 * kApplyPer);
+  for (uint32_t bk = blockIdx.x; bk < nbk; bk += gridDim.x) {
+    const uint32_t e0 = bk * (256 * kApplyPer) + threadIdx.x * kApplyPer;
+    uint32_t ck[kApplyPer];
+    if (e0 + kApplyPer <= n_e) {
+      const uint2 cw = *(const uint2*)(choice + e0);
+#pragma unroll
+      for (int k = 0; k < kApplyPer; ++k) ck[k] = ((k < 4 ? cw.x : cw.y) >> (8 * (k & 3))) & 0xFFu;
+    } else {
+#pragma unroll
+      for (int k = 0; k < kApplyPer; ++k) ck[k] = (e0 + k < n_e) ? choice[e0 + k] : 0u;
+    }
+    uint32_t mine = 0, nev = 0;
+#pragma unroll
+    for (int k = 0; k < kApplyPer; ++k) {
+      mine += created_by(ck[k]);
+      nev += ck[k] ? 1u : 0u;
+    }
+    uint32_t run = 0;  // created electrons before the thread's next electron
+    if (__syncthreads_or(mine != 0u)) {  // the same for the whole block
+      const uint32_t b = bk * kApplyPer;  // its first chunk (kApplyPer divides 32)
       const uint32_t grp = b >> 5;
       uint32_t s = 0;
       for (uint32_t i = threadIdx.x; i < grp; i += 256) s += csum[i];
       if (threadIdx.x < (b & 31u)) s += bsum[(grp << 5) + threadIdx.x];
       uint32_t before, tot;
       block_scan256(s, &before, sh);
-      cbase = before + block_scan256(created_by(c), &tot, sh);
+      run = before + block_scan256(mine, &tot, sh);
     }
-    {
-      if (!c) continue;
+    // the block's events listed in electron order with their first created
+    // slots, then taken one per thread (a thread's own electrons would run
+    // the outcome code once per electron with an event in any lane)
+    uint32_t evtot;
+    uint32_t ev = block_scan256(nev, &evtot, sh);
+#pragma unroll
+    for (int k = 0; k < kApplyPer; ++k) {
+      if (ck[k]) {
+        lev[ev] = e0 + k;
+        lcb[ev] = run;
+        lch[ev] = (uint8_t)ck[k];
+        ++ev;
+      }
+      run += created_by(ck[k]);
+    }
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < evtot; j += 256) {
+      const uint32_t e = lev[j], cbase = lcb[j], c = lch[j];
       const uint32_t tp = target[e];
       if (c & 0x80u) {  // lost, with projectile claims: reset both
         claim[tp] = 0xFFFFFFFFu;
@@ -606,6 +645,7 @@ __global__ void __launch_bounds__(256) k_apply(Flow<T> f, const uint32_t* off, D
       v1.vz = (T)e1[2];
       if (up) P.v[pe] = v1;
     }
+    __syncthreads();  // the next round rewrites the lists
   }
   // heavy events (disjoint from every other event); every heavy trial that
   // claimed resets its two claims, won or lost
@@ -672,8 +712,8 @@ void collide(const Flow<T>& P, const uint32_t* off, DevState* st, const Grid& g,
   // grids for the electrons (a few percent of the capacity in a steady
   // state); the launches loop over whatever there is
   const int gr = grid_for(cap) < 1024 ? grid_for(cap) : 1024;
-  int nb = (int)((cap + 255) / 256);
-  if (nb > 4096) nb = 4096;
+  int nb = (int)((cap + 256 * kApplyPer - 1) / (256 * kApplyPer));
+  if (nb > 2048) nb = 2048;
   // deposit blocks after the decision blocks (dispatched in order)
   int nd = 0;
   if (Q) nd = (int)((cap + 255) / 256) < 4096 ? (int)((cap + 255) / 256) : 4096;
