@@ -464,6 +464,32 @@ __device__ inline void cic_atomic(unsigned long long* Q, int b, int W, long long
 // of kApplyPer electrons at once, so that one round of blocks covers them
 // (rather than rounds of one chunk each, every one waiting for its loads).
 constexpr int kApplyPer = 8;
+static_assert(32 % kApplyPer == 0, "a block's chunks lie in one group of 32");
+
+// the choice bytes of electrons e0 .. e0 + kApplyPer - 1 (0 past n_e)
+__device__ inline void apply_choices(const uint8_t* __restrict__ choice, uint32_t e0,
+                                     uint32_t n_e, uint32_t* ck) {
+  static_assert(kApplyPer == 8, "one 64-bit load");
+  if (e0 + kApplyPer <= n_e) {
+    const uint2 cw = *(const uint2*)(choice + e0);
+#pragma unroll
+    for (int k = 0; k < kApplyPer; ++k) ck[k] = ((k < 4 ? cw.x : cw.y) >> (8 * (k & 3))) & 0xFFu;
+  } else {
+#pragma unroll
+    for (int k = 0; k < kApplyPer; ++k) ck[k] = (e0 + k < n_e) ? choice[e0 + k] : 0u;
+  }
+}
+// this thread's share of the created electrons of the chunks before chunk b
+// (the whole groups of 32 before its group, then its group's chunks before
+// it); the block's sum of the shares is the count
+__device__ inline uint32_t created_before_part(const uint32_t* __restrict__ csum,
+                                               const uint32_t* __restrict__ bsum, uint32_t b) {
+  const uint32_t grp = b >> 5;
+  uint32_t s = 0;
+  for (uint32_t i = threadIdx.x; i < grp; i += 256) s += csum[i];
+  if (threadIdx.x < (b & 31u)) s += bsum[(grp << 5) + threadIdx.x];
+  return s;
+}
 // (LIT: the literal Eqs. 16-20 split; a separate instantiation keeps its
 // trigonometric registers out of the default apply)
 template <typename T, bool LIT>
@@ -484,6 +510,15 @@ __global__ void __launch_bounds__(256) k_apply(Flow<T> f, const uint32_t* off, D
   const uint32_t next_id = st->next_id;
   const uint32_t step = st->step;
   const uint32_t err0 = st->err;
+  // kApplyPer consecutive electrons per thread, their choice bytes in one
+  // load: a block takes kApplyPer chunks of 256 at a time.  The first
+  // round's choices and its share of the created electrons before it are
+  // requested before the total below, so that the three wait together.
+  const uint32_t nbk = (n_e + 256 * kApplyPer - 1) / (256 * kApplyPer);
+  uint32_t bk = blockIdx.x;
+  uint32_t ck[kApplyPer];
+  apply_choices(choice, bk * (256 * kApplyPer) + threadIdx.x * kApplyPer, n_e, ck);
+  uint32_t pre = bk < nbk ? created_before_part(csum, bsum, bk * kApplyPer) : 0u;
   // the created electrons of every chunk: their total must fit (capacity,
   // id space), else the step creates nothing and flags the error; every
   // block decides the same from the same sums
@@ -495,19 +530,11 @@ __global__ void __launch_bounds__(256) k_apply(Flow<T> f, const uint32_t* off, D
     if (!fits) atomicOr(&st->err, 1u);
   }
   if (!fits) return;
-  // kApplyPer consecutive electrons per thread, their choice bytes in one
-  // load: a block takes kApplyPer chunks of 256 at a time
-  const uint32_t nbk = (n_e + 256 * kApplyPer - 1) / (256 * kApplyPer);
-  for (uint32_t bk = blockIdx.x; bk < nbk; bk += gridDim.x) {
+  for (; bk < nbk; bk += gridDim.x) {
     const uint32_t e0 = bk * (256 * kApplyPer) + threadIdx.x * kApplyPer;
-    uint32_t ck[kApplyPer];
-    if (e0 + kApplyPer <= n_e) {
-      const uint2 cw = *(const uint2*)(choice + e0);
-#pragma unroll
-      for (int k = 0; k < kApplyPer; ++k) ck[k] = ((k < 4 ? cw.x : cw.y) >> (8 * (k & 3))) & 0xFFu;
-    } else {
-#pragma unroll
-      for (int k = 0; k < kApplyPer; ++k) ck[k] = (e0 + k < n_e) ? choice[e0 + k] : 0u;
+    if (bk != blockIdx.x) {
+      apply_choices(choice, e0, n_e, ck);
+      pre = created_before_part(csum, bsum, bk * kApplyPer);
     }
     uint32_t mine = 0, nev = 0;
 #pragma unroll
@@ -517,13 +544,8 @@ __global__ void __launch_bounds__(256) k_apply(Flow<T> f, const uint32_t* off, D
     }
     uint32_t run = 0;  // created electrons before the thread's next electron
     if (__syncthreads_or(mine != 0u)) {  // the same for the whole block
-      const uint32_t b = bk * kApplyPer;  // its first chunk (kApplyPer divides 32)
-      const uint32_t grp = b >> 5;
-      uint32_t s = 0;
-      for (uint32_t i = threadIdx.x; i < grp; i += 256) s += csum[i];
-      if (threadIdx.x < (b & 31u)) s += bsum[(grp << 5) + threadIdx.x];
       uint32_t before, tot;
-      block_scan256(s, &before, sh);
+      block_scan256(pre, &before, sh);
       run = before + block_scan256(mine, &tot, sh);
     }
     // the block's events listed in electron order with their first created
