@@ -511,14 +511,16 @@ __global__ void __launch_bounds__(256) k_apply(Flow<T> f, const uint32_t* off, D
   const uint32_t step = st->step;
   const uint32_t err0 = st->err;
   // kApplyPer consecutive electrons per thread, their choice bytes in one
-  // load: a block takes kApplyPer chunks of 256 at a time.  The first
-  // round's choices and its share of the created electrons before it are
-  // requested before the total below, so that the three wait together.
+  // load: block bk takes the kApplyPer chunks of 256 from chunk bk kApplyPer
+  // (the grid covers the capacity).  Its choices and its share of the
+  // created electrons before it are requested before the total below, so
+  // that the three wait together.
   const uint32_t nbk = (n_e + 256 * kApplyPer - 1) / (256 * kApplyPer);
-  uint32_t bk = blockIdx.x;
+  const uint32_t bk = blockIdx.x;
+  const uint32_t e0 = bk * (256 * kApplyPer) + threadIdx.x * kApplyPer;
   uint32_t ck[kApplyPer];
-  apply_choices(choice, bk * (256 * kApplyPer) + threadIdx.x * kApplyPer, n_e, ck);
-  uint32_t pre = bk < nbk ? created_before_part(csum, bsum, bk * kApplyPer) : 0u;
+  apply_choices(choice, e0, n_e, ck);
+  const uint32_t pre = bk < nbk ? created_before_part(csum, bsum, bk * kApplyPer) : 0u;
   // the created electrons of every chunk: their total must fit (capacity,
   // id space), else the step creates nothing and flags the error; every
   // block decides the same from the same sums
@@ -530,12 +532,7 @@ __global__ void __launch_bounds__(256) k_apply(Flow<T> f, const uint32_t* off, D
     if (!fits) atomicOr(&st->err, 1u);
   }
   if (!fits) return;
-  for (; bk < nbk; bk += gridDim.x) {
-    const uint32_t e0 = bk * (256 * kApplyPer) + threadIdx.x * kApplyPer;
-    if (bk != blockIdx.x) {
-      apply_choices(choice, e0, n_e, ck);
-      pre = created_before_part(csum, bsum, bk * kApplyPer);
-    }
+  if (bk < nbk) {
     uint32_t mine = 0, nev = 0;
 #pragma unroll
     for (int k = 0; k < kApplyPer; ++k) {
@@ -667,7 +664,6 @@ __global__ void __launch_bounds__(256) k_apply(Flow<T> f, const uint32_t* off, D
       v1.vz = (T)e1[2];
       if (up) P.v[pe] = v1;
     }
-    __syncthreads();  // the next round rewrites the lists
   }
   // heavy events (disjoint from every other event); every heavy trial that
   // claimed resets its two claims, won or lost
@@ -734,8 +730,8 @@ void collide(const Flow<T>& P, const uint32_t* off, DevState* st, const Grid& g,
   // grids for the electrons (a few percent of the capacity in a steady
   // state); the launches loop over whatever there is
   const int gr = grid_for(cap) < 1024 ? grid_for(cap) : 1024;
-  int nb = (int)((cap + 256 * kApplyPer - 1) / (256 * kApplyPer));
-  if (nb > 2048) nb = 2048;
+  // one block per kApplyPer chunks of the capacity (the electrons are fewer)
+  const int nb = (int)((cap + 256 * kApplyPer - 1) / (256 * kApplyPer));
   // deposit blocks after the decision blocks (dispatched in order)
   int nd = 0;
   if (Q) nd = (int)((cap + 255) / 256) < 4096 ? (int)((cap + 255) / 256) : 4096;
