@@ -121,67 +121,72 @@ __global__ void __launch_bounds__(NT) k_radix_up(const uint32_t* __restrict__ ke
   }
 }
 
-// Per digit (one lane each, 64 digits per block): hist[t][d] <- sum of
-// hist[t'][d] over t' < t, and tot[d] <- the sum over all tiles.  The 16
-// waves of a block take consecutive runs of tiles; their run sums are
-// combined in LDS, then each wave rewrites its run.
+// Per digit (32 digits per block): hist[t][d] <- sum of hist[t'][d] over
+// t' < t, and tot[d] <- the sum over all tiles.  The 16 waves of a block
+// take consecutive runs of tiles, and a wave's two halves (lanes 0-31 and
+// 32-63, the same 32 digits) the two halves of its run; the half sums meet
+// through a lane exchange, the wave sums in LDS, then each half rewrites
+// its part of the run.
 constexpr int kColWaves = 16;
-constexpr uint32_t kColHeld = 32;  // tiles per wave held in registers
+constexpr uint32_t kColHeld = 16;  // tiles per lane held in registers
 template <int R>
 __global__ void __launch_bounds__(64 * kColWaves) k_radix_colscan(uint32_t* __restrict__ hist,
                                                                   uint32_t* __restrict__ tot,
                                                                   const uint32_t* np) {
-  __shared__ uint32_t part[kColWaves][64];
+  __shared__ uint32_t part[kColWaves][32];
   const uint32_t n = *np;
   const uint32_t tsz = 256u * (uint32_t)mover_items(n);
   const uint32_t ntiles = (n + tsz - 1) / tsz;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int d = blockIdx.x * 64 + lane;
+  const int dl = lane & 31, hf = lane >> 5;
+  const int d = blockIdx.x * 32 + dl;
   const uint32_t ch = (ntiles + kColWaves - 1) / kColWaves;
   const uint32_t t0 = (uint32_t)w * ch;
   const uint32_t t1 = (t0 + ch < ntiles) ? t0 + ch : ntiles;
+  const uint32_t hc = (ch + 1) / 2;  // the first half's tiles
+  const uint32_t tm = (t0 + hc < t1) ? t0 + hc : t1;
+  const uint32_t a0 = hf ? tm : t0, a1 = hf ? t1 : tm;  // this lane's tiles
+  const bool held = hc <= kColHeld;  // the usual case: the part loaded once
+  uint32_t v[kColHeld];
   uint32_t s = 0;
-  if (ch <= kColHeld) {
-    // the usual case (few movers): the run is loaded once, all at once, and
-    // rewritten from registers
-    uint32_t v[kColHeld];
+  if (held) {
 #pragma unroll
     for (int u = 0; u < kColHeld; ++u)
-      v[u] = (t0 + u < t1) ? hist[(size_t)(t0 + u) * R + d] : 0u;
+      v[u] = (a0 + u < a1) ? hist[(size_t)(a0 + u) * R + d] : 0u;
 #pragma unroll
     for (int u = 0; u < kColHeld; ++u) s += v[u];
-    part[w][lane] = s;
-    __syncthreads();
-    uint32_t run = 0;
-    for (int q = 0; q < w; ++q) run += part[q][lane];
-    if (w == kColWaves - 1) tot[d] = run + s;
+  } else {
+    for (uint32_t tb = a0; tb < a1; tb += 8) {
+      uint32_t x[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) x[u] = (tb + u < a1) ? hist[(size_t)(tb + u) * R + d] : 0u;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += x[u];
+    }
+  }
+  const uint32_t so = __shfl_xor(s, 32, 64);  // the other half's sum
+  if (hf == 0) part[w][dl] = s + so;
+  __syncthreads();
+  uint32_t run = 0;
+  for (int q = 0; q < w; ++q) run += part[q][dl];
+  if (w == kColWaves - 1 && hf == 0) tot[d] = run + s + so;
+  if (hf) run += so;  // the first half's tiles come before
+  if (held) {
 #pragma unroll
     for (int u = 0; u < kColHeld; ++u) {
-      if (t0 + u < t1) hist[(size_t)(t0 + u) * R + d] = run;
+      if (a0 + u < a1) hist[(size_t)(a0 + u) * R + d] = run;
       run += v[u];
     }
     return;
   }
-  for (uint32_t tb = t0; tb < t1; tb += 8) {
-    uint32_t v[8];
+  for (uint32_t tb = a0; tb < a1; tb += 8) {
+    uint32_t x[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = (tb + u < t1) ? hist[(size_t)(tb + u) * R + d] : 0u;
-#pragma unroll
-    for (int u = 0; u < 8; ++u) s += v[u];
-  }
-  part[w][lane] = s;
-  __syncthreads();
-  uint32_t run = 0;
-  for (int q = 0; q < w; ++q) run += part[q][lane];
-  if (w == kColWaves - 1) tot[d] = run + s;
-  for (uint32_t tb = t0; tb < t1; tb += 8) {
-    uint32_t v[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = (tb + u < t1) ? hist[(size_t)(tb + u) * R + d] : 0u;
+    for (int u = 0; u < 8; ++u) x[u] = (tb + u < a1) ? hist[(size_t)(tb + u) * R + d] : 0u;
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      if (tb + u < t1) hist[(size_t)(tb + u) * R + d] = run;
-      run += v[u];
+      if (tb + u < a1) hist[(size_t)(tb + u) * R + d] = run;
+      run += x[u];
     }
   }
 }
@@ -396,7 +401,7 @@ static void radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout,
   // the histograms with four times the threads per tile: more loads in
   // flight per CU (the tiles are few)
   k_radix_up<DB, ITM, 1024><<<grid, 1024, 0, s>>>(kin, np, shift, w.hist);
-  k_radix_colscan<R><<<R / 64, 64 * kColWaves, 0, s>>>(w.hist, w.bsum, np);
+  k_radix_colscan<R><<<R / 32, 64 * kColWaves, 0, s>>>(w.hist, w.bsum, np);
   if (!vin)
     k_radix_down<DB, ITM, true><<<grid, 256, 0, s>>>(kin, vin, kout, vout, np, shift, w.hist,
                                                      w.bsum, mp);
